@@ -1,0 +1,412 @@
+"""Newton step, FGMRES and geometric multigrid with point-block Jacobi.
+
+Oracle (test infrastructure only; see the package docstring).
+
+What the method computes (Sec. 3.4, Eqs. FinalRes and linAlgEq): at each Newton
+iteration the increment Delta solves K Delta = -R, then U <- U + Delta.  The
+plain definition of that increment is a direct sparse solve (``direct_solve``);
+GMRES with a geometric-multigrid preconditioner reaches it approximately.  The
+preconditioner (Sec. 3.4): operators rebuilt on every level by reassembly (not
+Galerkin projection), V-cycle of pre-smoothing, coarse correction, direct
+solve on the coarsest level, prolongation and post-smoothing, with point-block
+Jacobi relaxation whose 9x9 blocks gather all unknowns of a node and are
+inverted by LU with partial pivoting.
+
+Readings where the paper is silent (all listed in the design doc):
+* Dirichlet conditions: symmetric elimination (constrained rows and columns of
+  K replaced by the identity); a prescribed increment g enters the first
+  Newton system by lifting: b_free = -R_free - (K g)_free, b_con = g.
+* Coarse-level state is the injection (coincident-node values) of the fine
+  state; a coarse dof is constrained iff its coincident fine dof is.
+* Prolongation P = trilinear interpolation, restriction = P^T; restricted
+  residuals are zeroed at constrained coarse dofs, prolongated corrections are
+  not added at constrained fine dofs; the preconditioner is the identity on
+  the constrained dofs of the finest level.
+* Smoother: x <- x + omega D^-1 (b - A x), omega = 1/2, nu1 = nu2 = 2, zero
+  initial guess on every level.  (The spectral radius of D^-1 A measured on
+  these operators is about 3.37 on every level, so the damped-Jacobi
+  stability limit 2/lambda_max is about 0.59 and the textbook 2/3 diverges.)
+* Outer Krylov method: flexible GMRES(m), right preconditioned, x0 = 0,
+  classical Gram-Schmidt applied twice, Givens rotations, stop when the
+  recurrence residual drops to rtol * ||b||, then a true-residual check.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import scipy.linalg
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .fem import NDOF, NETA, Discretisation, Mesh
+from .material import Card
+
+
+# ---------------------------------------------------------------------------
+# boundary conditions
+# ---------------------------------------------------------------------------
+
+def dirichlet(mesh: Mesh, kind: str = "patch", patch: int = 2, radius: float = 0.2,
+              depth: float = 0.0, depth_prev: float = 0.0):
+    """Constrained-dof mask (n_nodes, 9) bool and prescribed increments (n_nodes, 9).
+
+    Bottom face z = 0: all three displacement components fixed.  Top face:
+    kind 'patch' -- nodes of the centred patch x patch element square get
+    u_z increment -(depth - depth_prev); kind 'cap' -- nodes under a rigid
+    sphere of radius R at total depth d (r^2 < 2 R d - d^2) get
+    u_z(d) = -(d - (R - sqrt(R^2 - r^2))), increment u_z(d) - u_z(d_prev).
+    Order parameters are never constrained (natural boundary conditions).
+    """
+    nn = mesh.n_nodes
+    mask = np.zeros((nn, NDOF), dtype=bool)
+    g = np.zeros((nn, NDOF))
+    i, j, k = mesh.node_ijk(np.arange(nn))
+    mask[k == 0, 0:3] = True
+    top = k == mesh.nz
+    if kind == "patch":
+        if patch % 2 or mesh.nx % 2 or mesh.ny % 2:
+            raise ValueError("patch and mesh must be even to centre the patch on a node")
+        cx, cy, hp = mesh.nx // 2, mesh.ny // 2, patch // 2
+        sel = top & (np.abs(i - cx) <= hp) & (np.abs(j - cy) <= hp)
+        mask[sel, 2] = True
+        g[sel, 2] = -(depth - depth_prev)
+    elif kind == "cap":
+        x = i * mesh.h - 0.5 * mesh.nx * mesh.h
+        y = j * mesh.h - 0.5 * mesh.ny * mesh.h
+        r2 = x * x + y * y
+
+        def uz(d):
+            inside = r2 < 2.0 * radius * d - d * d
+            val = -(d - (radius - np.sqrt(np.maximum(radius * radius - r2, 0.0))))
+            return inside, np.where(inside, val, 0.0)
+
+        in1, u1 = uz(depth)
+        _, u0 = uz(depth_prev)
+        sel = top & in1
+        mask[sel, 2] = True
+        g[sel, 2] = (u1 - u0)[sel]
+    else:
+        raise ValueError(kind)
+    return mask, g
+
+
+def coarse_mask(fine_mesh: Mesh, fine_mask: np.ndarray, coarse_mesh: Mesh) -> np.ndarray:
+    """A coarse dof is constrained iff the coincident fine dof is."""
+    I, J, K = coarse_mesh.node_ijk(np.arange(coarse_mesh.n_nodes))
+    return fine_mask[fine_mesh.node_id(2 * I, 2 * J, 2 * K)]
+
+
+def inject(fine_mesh: Mesh, fine_nodal: np.ndarray, coarse_mesh: Mesh) -> np.ndarray:
+    """Coarse nodal values = fine values at coincident nodes."""
+    I, J, K = coarse_mesh.node_ijk(np.arange(coarse_mesh.n_nodes))
+    return fine_nodal.reshape(fine_mesh.n_nodes, -1)[fine_mesh.node_id(2 * I, 2 * J, 2 * K)]
+
+
+# ---------------------------------------------------------------------------
+# operators
+# ---------------------------------------------------------------------------
+
+def assemble(disc: Discretisation, U: np.ndarray, Eta_n: np.ndarray) -> sp.csr_matrix:
+    """Unconstrained tangent K as CSR (duplicates summed by scipy)."""
+    n = disc.mesh.n_nodes * NDOF
+    r, c, v = disc.tangent_coo(U, Eta_n)
+    return sp.coo_matrix((v, (r, c)), shape=(n, n)).tocsr()
+
+
+def eliminate(K: sp.csr_matrix, mask: np.ndarray) -> sp.csr_matrix:
+    """Replace constrained rows and columns by those of the identity."""
+    m = mask.ravel()
+    keep = sp.diags((~m).astype(float))
+    return (keep @ K @ keep + sp.diags(m.astype(float))).tocsr()
+
+
+def prolongation(coarse: Mesh, fine: Mesh, bs: int = NDOF) -> sp.csr_matrix:
+    """Trilinear interpolation, node-interleaved with bs components:
+    P = P_node (x) I_bs.  Fine node (i,j,k) takes weight prod_d w_d from coarse
+    node (I,J,K), w_d = 1 if i_d = 2 I_d and 1/2 if |i_d - 2 I_d| = 1."""
+    rows, cols, vals = [], [], []
+    fi, fj, fk = fine.node_ijk(np.arange(fine.n_nodes))
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                # candidate coarse parent of each fine node
+                ci, cj, ck = (fi + dx), (fj + dy), (fk + dz)
+                ok = (ci % 2 == 0) & (cj % 2 == 0) & (ck % 2 == 0)
+                ci, cj, ck = ci // 2, cj // 2, ck // 2
+                ok &= (ci >= 0) & (ci <= coarse.nx) & (cj >= 0) & (cj <= coarse.ny) \
+                    & (ck >= 0) & (ck <= coarse.nz)
+                w = (0.5 ** abs(dx)) * (0.5 ** abs(dy)) * (0.5 ** abs(dz))
+                rows.append(np.nonzero(ok)[0])
+                cols.append(coarse.node_id(ci[ok], cj[ok], ck[ok]))
+                vals.append(np.full(ok.sum(), w))
+    Pn = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                       shape=(fine.n_nodes, coarse.n_nodes)).tocsr()
+    return sp.kron(Pn, sp.eye(bs), format="csr")
+
+
+def block_diagonal_inverse(A: sp.csr_matrix, bs: int = NDOF) -> np.ndarray:
+    """Inverses of the bs x bs diagonal blocks, (n_nodes, bs, bs).
+    numpy.linalg.inv factors each block by LU with partial pivoting (LAPACK
+    getrf/getri)."""
+    n = A.shape[0] // bs
+    Ab = A.tobsr(blocksize=(bs, bs))
+    D = np.zeros((n, bs, bs))
+    for row in range(n):
+        for p in range(Ab.indptr[row], Ab.indptr[row + 1]):
+            if Ab.indices[p] == row:
+                D[row] = Ab.data[p]
+    return np.linalg.inv(D)
+
+
+@dataclass
+class Level:
+    mesh: Mesh
+    mask: np.ndarray           # (n_nodes, 9) bool
+    A: sp.csr_matrix           # eliminated operator
+    Dinv: Optional[np.ndarray] = None
+    P: Optional[sp.csr_matrix] = None     # prolongation from the next coarser level
+    lu: Optional[tuple] = None            # dense LU of the coarsest operator
+
+
+@dataclass
+class MGOptions:
+    nu1: int = 2
+    nu2: int = 2
+    omega: float = 0.5
+
+
+class Multigrid:
+    """Geometric multigrid hierarchy rebuilt by reassembly at injected states."""
+
+    def __init__(self, problem, card: Card, U: np.ndarray, Eta_n: np.ndarray,
+                 fine_mask: np.ndarray, n_levels: Optional[int] = None,
+                 opts: MGOptions = MGOptions(), K_fine: Optional[sp.csr_matrix] = None):
+        self.opts = opts
+        self.bs = NDOF
+        L = problem.n_levels if n_levels is None else n_levels
+        self.levels: List[Level] = []
+        mesh = Mesh.from_problem(problem, 0)
+        Ul, En, mask = U.reshape(-1, NDOF), Eta_n.reshape(-1, NETA), fine_mask
+        for l in range(L):
+            if l > 0:
+                cm = Mesh.from_problem(problem, l)
+                Ul = inject(mesh, Ul, cm)
+                En = inject(mesh, En, cm)
+                mask = coarse_mask(mesh, mask, cm)
+                self.levels[-1].P = prolongation(cm, mesh)
+                mesh = cm
+            disc = Discretisation(mesh, card)
+            K = K_fine if (l == 0 and K_fine is not None) else assemble(disc, Ul.ravel(), En.ravel())
+            A = eliminate(K, mask)
+            self.levels.append(Level(mesh=mesh, mask=mask, A=A))
+        self._finish()
+
+    @classmethod
+    def from_levels(cls, levels: List[Level], bs: int, opts: MGOptions = MGOptions()):
+        """Hierarchy from given operators/masks/prolongations (finest first)."""
+        mg = cls.__new__(cls)
+        mg.opts, mg.bs, mg.levels = opts, bs, levels
+        mg._finish()
+        return mg
+
+    def _finish(self):
+        for lev in self.levels[:-1]:
+            lev.Dinv = block_diagonal_inverse(lev.A, self.bs)
+        self.levels[-1].lu = scipy.linalg.lu_factor(self.levels[-1].A.toarray())
+
+    def smooth(self, lev: Level, x: np.ndarray, b: np.ndarray, sweeps: int) -> np.ndarray:
+        """Damped point-block Jacobi: x <- x + omega D^-1 (b - A x)."""
+        for _ in range(sweeps):
+            r = (b - lev.A @ x).reshape(-1, self.bs)
+            x = x + self.opts.omega * np.einsum("nij,nj->ni", lev.Dinv, r).ravel()
+        return x
+
+    def vcycle(self, l: int, b: np.ndarray) -> np.ndarray:
+        lev = self.levels[l]
+        if l == len(self.levels) - 1:
+            return scipy.linalg.lu_solve(lev.lu, b)
+        x = self.smooth(lev, np.zeros_like(b), b, self.opts.nu1)
+        r = b - lev.A @ x
+        nxt = self.levels[l + 1]
+        bc = lev.P.T @ r
+        bc[nxt.mask.ravel()] = 0.0
+        e = self.vcycle(l + 1, bc)
+        corr = lev.P @ e
+        corr[lev.mask.ravel()] = 0.0
+        x = x + corr
+        return self.smooth(lev, x, b, self.opts.nu2)
+
+    def precondition(self, v: np.ndarray) -> np.ndarray:
+        m = self.levels[0].mask.ravel()
+        b = v.copy()
+        b[m] = 0.0
+        z = self.vcycle(0, b)
+        z[m] = v[m]
+        return z
+
+
+# ---------------------------------------------------------------------------
+# Krylov solver
+# ---------------------------------------------------------------------------
+
+@dataclass
+class SolveStats:
+    iterations: int = 0
+    restarts: int = 0
+    rel_residual: float = 0.0       # true ||b - A x|| / ||b||
+    history: list = field(default_factory=list)   # recurrence residual / ||b||
+    converged: bool = False
+
+
+def fgmres(A, b: np.ndarray, precond, rtol: float = 1e-8, restart: int = 30,
+           max_it: int = 500):
+    """Flexible GMRES(m), right preconditioning, x0 = 0 (Saad 1993)."""
+    n = b.shape[0]
+    st = SolveStats()
+    bnorm = float(np.linalg.norm(b))
+    x = np.zeros(n)
+    if bnorm == 0.0:
+        st.converged = True
+        return x, st
+    r = b.copy()
+    beta = bnorm
+    while True:
+        V = np.zeros((restart + 1, n))
+        Z = np.zeros((restart, n))
+        H = np.zeros((restart + 1, restart))
+        cs = np.zeros(restart)
+        sn = np.zeros(restart)
+        g = np.zeros(restart + 1)
+        V[0] = r / beta
+        g[0] = beta
+        k = 0
+        for j in range(restart):
+            Z[j] = precond(V[j])
+            w = A @ Z[j]
+            h = V[:j + 1] @ w
+            w = w - V[:j + 1].T @ h
+            h2 = V[:j + 1] @ w
+            w = w - V[:j + 1].T @ h2
+            H[:j + 1, j] = h + h2
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] > 0.0:
+                V[j + 1] = w / H[j + 1, j]
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = H[j, j] / den, H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            st.iterations += 1
+            k = j + 1
+            st.history.append(abs(g[j + 1]) / bnorm)
+            if abs(g[j + 1]) <= rtol * bnorm or st.iterations >= max_it:
+                break
+        y = scipy.linalg.solve_triangular(H[:k, :k], g[:k])
+        x = x + Z[:k].T @ y
+        r = b - A @ x
+        beta = float(np.linalg.norm(r))
+        st.rel_residual = beta / bnorm
+        if st.rel_residual <= rtol:
+            st.converged = True
+            return x, st
+        if st.iterations >= max_it:
+            return x, st
+        st.restarts += 1
+
+
+def poisson_levels(n: int, n_levels: int) -> List[Level]:
+    """Scalar (block size 1) Q1 Laplacian on the unit cube with u = 0 on z = 0,
+    rediscretised on n, n/2, ... (textbook tensor-product element matrix
+    K_e = Km(x)Mm(x)Mm + Mm(x)Km(x)Mm + Mm(x)Mm(x)Km with the 1D forms
+    Km = [[1,-1],[-1,1]]/h and Mm = h/6 [[2,1],[1,2]]).  Used to check the
+    h-independence of the V-cycle."""
+    levels = []
+    prev = None
+    for l in range(n_levels):
+        m = Mesh(n >> l, n >> l, n >> l, 1.0 / (n >> l))
+        h = m.h
+        Km = np.array([[1.0, -1.0], [-1.0, 1.0]]) / h
+        Mm = h / 6.0 * np.array([[2.0, 1.0], [1.0, 2.0]])
+        # local node a = ax + 2 ay + 4 az  <->  kron order (az, ay, ax)
+        Ke = np.kron(np.kron(Mm, Mm), Km) + np.kron(np.kron(Mm, Km), Mm) \
+            + np.kron(np.kron(Km, Mm), Mm)
+        en = m.element_nodes()
+        r = np.repeat(en, 8, axis=1).ravel()
+        c = np.tile(en, (1, 8)).ravel()
+        v = np.tile(Ke.ravel(), m.n_elem)
+        K = sp.coo_matrix((v, (r, c)), shape=(m.n_nodes, m.n_nodes)).tocsr()
+        _, _, k = m.node_ijk(np.arange(m.n_nodes))
+        mask = (k == 0)[:, None]
+        lev = Level(mesh=m, mask=mask, A=eliminate(K, mask))
+        if prev is not None:
+            levels[-1].P = prolongation(m, prev, bs=1)
+        levels.append(lev)
+        prev = m
+    return levels
+
+
+def direct_solve(A: sp.csr_matrix, b: np.ndarray) -> np.ndarray:
+    """The plain definition of the Newton increment: x = A^-1 b (SuperLU)."""
+    return spla.spsolve(A.tocsc(), b)
+
+
+# ---------------------------------------------------------------------------
+# Newton
+# ---------------------------------------------------------------------------
+
+class NewtonSystem:
+    """Linear system of one Newton iteration (Eq. linAlgEq) with Dirichlet
+    lifting: A = K with constrained rows/cols eliminated, b as described in the
+    module docstring."""
+
+    def __init__(self, problem, card: Card, U: np.ndarray, Eta_n: np.ndarray,
+                 mask: np.ndarray, g: np.ndarray):
+        self.mesh = Mesh.from_problem(problem, 0)
+        self.disc = Discretisation(self.mesh, card)
+        self.R = self.disc.residual(U, Eta_n)
+        self.K = assemble(self.disc, U, Eta_n)
+        m = mask.ravel()
+        gv = np.where(m, g.ravel(), 0.0)
+        b = -self.R - self.K @ gv
+        b[m] = gv[m]
+        self.b = b
+        self.A = eliminate(self.K, mask)
+        self.mask = mask
+
+
+def newton_step(problem, card: Card, U: np.ndarray, Eta_n: np.ndarray, mask: np.ndarray,
+                g: np.ndarray, rtol: float = 1e-9, max_iter: int = 12, linear: str = "direct",
+                lin_rtol: float = 1e-12, log: Optional[list] = None):
+    """Newton iterations of one implicit step.  The first system carries the
+    prescribed increment g; later ones are homogeneous on constrained dofs.
+    Converged when ||R_free|| <= rtol * ||b_0|| (b_0 = first right-hand side).
+    Returns (U, iterations, converged)."""
+    U = U.copy()
+    b0 = None
+    gk = g
+    for it in range(max_iter):
+        sysk = NewtonSystem(problem, card, U, Eta_n, mask, gk)
+        if b0 is None:
+            b0 = float(np.linalg.norm(sysk.b))
+        rfree = float(np.linalg.norm(np.where(mask.ravel(), 0.0, sysk.R)))
+        if log is not None:
+            log.append(rfree)
+        if it > 0 and rfree <= rtol * b0:
+            return U, it, True
+        if linear == "direct":
+            dx = direct_solve(sysk.A, sysk.b)
+        else:
+            mg = Multigrid(problem, card, U, Eta_n, mask, K_fine=sysk.K)
+            dx, _ = fgmres(sysk.A, sysk.b, mg.precondition, rtol=lin_rtol)
+        U = U + dx
+        gk = np.zeros_like(g)
+    sysk = NewtonSystem(problem, card, U, Eta_n, mask, gk)
+    rfree = float(np.linalg.norm(np.where(mask.ravel(), 0.0, sysk.R)))
+    return U, max_iter, rfree <= rtol * b0

@@ -1,0 +1,128 @@
+"""Pins of the oracle's linear and nonlinear solvers (Sec. 3.4)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import solver as S
+from oracle.fem import Mesh, NDOF
+from oracle.material import Card
+
+
+def _tiny(n=4, levels=2, patch=2, depth=0.02, eta_offset=0.0):
+    p = synth.Problem(n, n, n, n_levels=levels, patch=patch, depth_increment=depth)
+    card = Card(p.material)
+    m = Mesh.from_problem(p)
+    U = np.zeros((m.n_nodes, NDOF))
+    U[:, 3:] = eta_offset + p.eta0()
+    En = U[:, 3:].ravel().copy()
+    mask, g = S.dirichlet(m, "patch", p.patch, depth=p.depth_increment)
+    return p, card, m, U.ravel(), En, mask, g
+
+
+def test_dirichlet_sets():
+    m = Mesh(8, 8, 8, 0.125)
+    mask, g = S.dirichlet(m, "patch", 2, depth=0.02)
+    i, j, k = m.node_ijk(np.arange(m.n_nodes))
+    assert mask[k == 0][:, :3].all() and not mask[k == 0][:, 3:].any()
+    top = np.nonzero(mask[:, 2] & (k == 8))[0]
+    assert len(top) == 9 and set(i[top]) == {3, 4, 5} and set(j[top]) == {3, 4, 5}
+    assert np.all(g[top, 2] == -0.02) and np.count_nonzero(g) == 9
+    cm = Mesh(4, 4, 4, 0.25)
+    cmask = S.coarse_mask(m, mask, cm)
+    ci, cj, ck = cm.node_ijk(np.arange(cm.n_nodes))
+    assert np.nonzero(cmask[:, 2] & (ck == 4))[0].tolist() == [cm.node_id(2, 2, 4)]
+
+
+def test_prolongation_exact_on_trilinear_fields():
+    fine, coarse = Mesh(4, 6, 2, 0.1), Mesh(2, 3, 1, 0.2)
+    P = S.prolongation(coarse, fine, bs=1)
+
+    def f(m):
+        i, j, k = m.node_ijk(np.arange(m.n_nodes))
+        x, y, z = i * m.h, j * m.h, k * m.h
+        return 1.5 - 2 * x + 0.5 * y + 3 * z + x * y - 2 * x * z + 0.7 * y * z + 4 * x * y * z
+
+    assert np.allclose(P @ f(coarse), f(fine), atol=1e-14)
+    assert np.allclose(np.asarray(P.sum(1)).ravel(), 1.0)
+
+
+def test_direct_solve_matches_dense_library_solve():
+    p, card, m, U, En, mask, g = _tiny(4)
+    sysk = S.NewtonSystem(p, card, U, En, mask, g)
+    x = S.direct_solve(sysk.A, sysk.b)
+    y = np.linalg.solve(sysk.A.toarray(), sysk.b)
+    # both are backward stable: forward error <= ~ cond(A) * eps
+    kappa = np.linalg.cond(sysk.A.toarray())
+    assert np.linalg.norm(x - y) <= 10 * kappa * 2.2e-16 * np.linalg.norm(y)
+    assert np.allclose(x[mask.ravel()], g.ravel()[mask.ravel()], rtol=0, atol=1e-15)
+    A = sysk.A.toarray()
+    assert np.allclose(A, A.T, atol=1e-12 * np.abs(A).max())
+
+
+def test_lifting_equals_constrained_solve():
+    """Lifting + elimination gives the same increment as solving the full
+    system with the constrained rows replaced by Delta_c = g."""
+    p, card, m, U, En, mask, g = _tiny(4)
+    sysk = S.NewtonSystem(p, card, U, En, mask, g)
+    x = S.direct_solve(sysk.A, sysk.b)
+    K = sysk.K.toarray()
+    mv = mask.ravel()
+    rhs = -sysk.R.copy()
+    K[mv, :] = 0.0
+    K[mv, mv] = 1.0
+    rhs[mv] = g.ravel()[mv]
+    y = np.linalg.solve(K, rhs)
+    assert np.linalg.norm(x - y) <= 1e-11 * np.linalg.norm(y)
+
+
+@pytest.mark.slow
+def test_fgmres_multigrid_reaches_direct_solution():
+    p, card, m, U, En, mask, g = _tiny(8, levels=3)
+    sysk = S.NewtonSystem(p, card, U, En, mask, g)
+    x = S.direct_solve(sysk.A, sysk.b)
+    mg = S.Multigrid(p, card, U, En, mask, K_fine=sysk.K)
+    y, st = S.fgmres(sysk.A, sysk.b, mg.precondition, rtol=1e-12)
+    assert st.converged and st.rel_residual <= 1e-12
+    assert np.linalg.norm(y - x) <= 1e-9 * np.linalg.norm(x)
+    y8, st8 = S.fgmres(sysk.A, sysk.b, mg.precondition, rtol=1e-8)
+    assert st8.converged and st8.iterations < 40
+
+
+def test_fgmres_without_preconditioner_is_gmres_on_spd_system():
+    rng = np.random.default_rng(0)
+    B = rng.standard_normal((40, 40))
+    A = sp.csr_matrix(B @ B.T + 40 * np.eye(40))
+    b = rng.standard_normal(40)
+    x, st = S.fgmres(A, b, lambda v: v, rtol=1e-13, restart=10)
+    assert np.linalg.norm(x - np.linalg.solve(A.toarray(), b)) < 1e-11 * np.linalg.norm(x)
+    assert st.restarts >= 1
+
+
+@pytest.mark.slow
+def test_poisson_vcycle_h_independent():
+    its = []
+    for n in (8, 16, 32):
+        levs = S.poisson_levels(n, int(np.log2(n)) - 1)
+        mg = S.Multigrid.from_levels(levs, 1)
+        A = levs[0].A
+        b = np.ones(A.shape[0])
+        b[levs[0].mask.ravel()] = 0
+        _, st = S.fgmres(A, b, mg.precondition, rtol=1e-8)
+        assert st.converged
+        its.append(st.iterations)
+    assert max(its) - min(its) <= 2 and max(its) <= 12
+
+
+def test_newton_converges_quadratically():
+    """Order parameters away from zero (no penalty switching): the residual
+    decreases quadratically once small.  Above the round-off floor,
+    r_{k+1} <= C r_k^2 with a moderate C."""
+    p, card, m, U, En, mask, g = _tiny(4, depth=0.02, eta_offset=0.1)
+    log = []
+    U1, it, ok = S.newton_step(p, card, U, En, mask, g, rtol=1e-12, log=log)
+    assert ok and it <= 8
+    r = log[1:]
+    ratios = [r[k + 1] / r[k] ** 2 for k in range(len(r) - 1) if r[k] < 1e-2 and r[k + 1] > 1e-12]
+    assert ratios and max(ratios) < 1e2
+    assert np.allclose(U1.reshape(-1, NDOF)[mask], (U.reshape(-1, NDOF) + g)[mask])
