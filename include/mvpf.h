@@ -1,0 +1,243 @@
+/*
+ * mvpf -- Newton-step solver for the finite-strain multivariant martensite
+ * phase-field model on one AMD Instinct MI355X (gfx950).
+ *
+ * Model: Tuma, Rezaee-Hajidehi, Hron, Farrell, Stupkiewicz, "Phase-field
+ * modeling of multivariant martensitic transformation at finite-strain:
+ * computational aspects and large-scale finite-element simulations",
+ * CMAME 2021 (cited below by section / equation / table).
+ *
+ * Unknowns: 9 per node, node-interleaved [u_x, u_y, u_z, eta_1 .. eta_6]:
+ * displacement u = phi - X and the condensed order parameters eta_hat with
+ * eta_0 = 1 - sum eta_i (Sec. 3.1).  Nodes are numbered lexicographically,
+ * x fastest: node(i,j,k) = i + (nx+1)*(j + (ny+1)*k).  The mesh is a uniform
+ * grid of nx*ny*nz cubes of side h (trilinear Q1 elements, 2x2x2 Gauss).
+ *
+ * Conventions for every call:
+ *  - return 0 on success; negative on error (MVPF_EINVAL, MVPF_ENOMEM,
+ *    MVPF_EDEVICE, MVPF_ESINGULAR, MVPF_ESTATE); MVPF_ENOTCONV (> 0) when a
+ *    solve or Newton loop stopped without converging -- outputs and stats are
+ *    still valid.  mvpf_last_error() gives a message.
+ *  - every "device" array argument is a device pointer (e.g. a torch CUDA
+ *    tensor's data_ptr) to FP64 data, node-interleaved, length 9*n_nodes of
+ *    the addressed level unless stated otherwise; the caller owns it; the
+ *    library reads/writes it in stream order on the problem's stream and does
+ *    not retain it after the call returns.
+ *  - the library owns all of its internal device memory (operators, Krylov
+ *    bases, work vectors); it is allocated in mvpf_create / on first use and
+ *    released by mvpf_destroy.
+ *  - one HIP stream per problem (given at creation; NULL = the default
+ *    stream).  Calls on one handle are not thread-safe; separate handles are
+ *    independent.
+ */
+#ifndef MVPF_H
+#define MVPF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MVPF_OK = 0,
+  MVPF_ENOTCONV = 1,
+  MVPF_EINVAL = -1,
+  MVPF_ENOMEM = -2,
+  MVPF_EDEVICE = -3,
+  MVPF_ESINGULAR = -4,
+  MVPF_ESTATE = -5
+};
+
+enum { MVPF_FP64 = 0, MVPF_MIXED = 1 };          /* mvpf_opts.precision */
+enum { MVPF_LOAD_PATCH = 0, MVPF_LOAD_CAP = 1 };  /* mvpf_loading.kind */
+
+typedef struct mvpf_problem mvpf_problem;
+
+/* Structured mesh of nx*ny*nz cubes of side h, and the number of geometric
+ * multigrid levels.  Level l has nx/2^l x ny/2^l x nz/2^l elements, so nx, ny,
+ * nz must be divisible by 2^(n_levels-1); n_levels >= 2 (the coarsest level is
+ * solved directly and must have at most MVPF_MAX_COARSE_DOF unknowns). */
+typedef struct {
+  int nx, ny, nz;
+  double h;
+  int n_levels;
+} mvpf_mesh;
+
+#define MVPF_MAX_COARSE_DOF 8192
+
+/* Material card (Sec. 2.2, 2.3, 3.1, 4.1; Table 1).  Stresses and energy
+ * densities in GPa, lengths in units of the mesh coordinates.
+ *  cubic   austenite c11, c12, c44 in the cubic crystal axes
+ *  ortho   martensite c11, c22, c33, c44, c55, c66, c12, c13, c23 in the
+ *          orthorhombic axes; variant k's axes 1,2,3 are the principal axes of
+ *          its stretch tensor U_k for the eigenvalues alpha, beta, gamma
+ *  alpha, beta, gamma   transformation stretch parameters (Sec. 4.1)
+ *  Q       rotation, row-major; rows are the sample axes in crystal axes
+ *  F0      chemical energy densities of phases 0..6 (austenite first)
+ *  w_am, w_mm  double-obstacle coefficients 4 gamma_ij / (pi l_ij) of the
+ *          austenite-martensite and martensite-martensite pairs (Eq. IntEnergy)
+ *  ell     interface thickness parameter l_ij (all pairs)
+ *  rho     viscous coefficient 1/(m tau) (all phases, Sec. 2.3)
+ *  eps_eta penalty parameter of eta_i >= 0 (Eq. PenPot)
+ *  pade    Pade order of the Hencky strain: 22 ((2,2), Eq. pade22) */
+typedef struct {
+  double cubic[3];
+  double ortho[9];
+  double alpha, beta, gamma;
+  double Q[9];
+  double F0[7];
+  double w_am, w_mm;
+  double ell;
+  double rho;
+  double eps_eta;
+  int pade;
+} mvpf_material;
+
+/* Indentation loading (Sec. 4.1, replaced by prescribed displacements).
+ * Bottom face z = 0: u = 0.  Top face z = nz*h:
+ *  MVPF_LOAD_PATCH  nodes of the centred patch x patch element square have
+ *                   u_z = -depth (patch, nx and ny even);
+ *  MVPF_LOAD_CAP    nodes with r^2 < 2 R d - d^2 (r from the top-face centre,
+ *                   R = radius, d = depth) have u_z = -(d - (R - sqrt(R^2-r^2))).
+ * All other dofs are free; order parameters have natural conditions. */
+typedef struct {
+  int kind;
+  int patch;
+  double radius;
+} mvpf_loading;
+
+/* Solver options.  precision MVPF_FP64: every multigrid level in FP64;
+ * MVPF_MIXED: multigrid operators, smoother and transfers in FP32 inside the
+ * FP64 outer FGMRES (finest operator kept in FP64 for the outer product; the
+ * coarsest level always solved in FP64).  rtol: FGMRES stops when the true
+ * FP64 residual satisfies ||b - A x|| <= rtol ||b||.  restart: Krylov space
+ * size m (<= 64).  max_it: total FGMRES iterations.  nu_pre, nu_post, omega:
+ * damped point-block Jacobi sweeps and damping.  newton_max, newton_rtol:
+ * Newton iterations of a time step (Sec. 3.4: 12) and its tolerance on the
+ * free-dof residual relative to the first right-hand side. */
+typedef struct {
+  int precision;
+  double rtol;
+  int restart;
+  int max_it;
+  int nu_pre, nu_post;
+  double omega;
+  int newton_max;
+  double newton_rtol;
+} mvpf_opts;
+
+typedef struct {
+  int iterations;        /* FGMRES iterations (preconditioner applications) */
+  int restarts;
+  int converged;
+  double rel_residual;   /* true FP64 ||b - A x|| / ||b|| at exit */
+  double solve_ms;       /* wall time of the FGMRES solve (stream-synchronised) */
+} mvpf_solve_stats;
+
+typedef struct {
+  int newton_iterations;
+  int linear_iterations; /* summed over the Newton iterations */
+  int halvings;          /* depth-increment halvings after Newton failures */
+  int converged;
+  double residual0;      /* ||b|| of the first Newton system */
+  double residual;       /* final free-dof residual norm */
+  double assemble_ms;    /* residual + tangent assembly on all levels */
+  double setup_ms;       /* block inverses + coarse factorisation */
+  double solve_ms;       /* all FGMRES solves */
+} mvpf_step_stats;
+
+typedef struct {
+  int n_levels;
+  int nx[8], ny[8], nz[8];
+  int64_t n_nodes[8];
+  int64_t bytes_device;  /* device memory held by the problem */
+} mvpf_info;
+
+/* Fill opts with the defaults (FP64, rtol 1e-8, restart 30, max_it 500,
+ * V(2,2), omega 0.5, newton_max 12, newton_rtol 1e-9). */
+void mvpf_default_opts(mvpf_opts* opts);
+
+/* Create a problem: validates the inputs, builds the material card in the
+ * sample frame, allocates every level's operators and vectors, zeroes the
+ * state (u = 0, eta_hat = eta_hat_n = 0, depth 0).  stream: hipStream_t or
+ * NULL.  On error *out is NULL and mvpf_last_error(NULL) explains. */
+int mvpf_create(const mvpf_mesh* mesh, const mvpf_material* mat, const mvpf_loading* load,
+                const mvpf_opts* opts, void* stream, mvpf_problem** out);
+void mvpf_destroy(mvpf_problem* p);
+/* Last error message of p, or of the last failed mvpf_create if p is NULL. */
+const char* mvpf_last_error(const mvpf_problem* p);
+int mvpf_get_info(const mvpf_problem* p, mvpf_info* info);
+/* Change options that do not change memory layout (rtol, max_it, restart <=
+ * the value at creation, sweeps, omega, Newton limits); precision is fixed. */
+int mvpf_set_opts(mvpf_problem* p, const mvpf_opts* opts);
+
+/* State transfer.  u: device n_nodes x 3, eta, eta_prev: device n_nodes x 6
+ * (node-major); NULL leaves that field unchanged / unread.  depth: the
+ * indenter depth the state corresponds to. */
+int mvpf_set_state(mvpf_problem* p, const double* u, const double* eta, const double* eta_prev,
+                   double depth);
+int mvpf_get_state(mvpf_problem* p, double* u, double* eta, double* eta_prev, double* depth);
+/* u = 0, depth 0, eta_hat = eta_hat_n with eta_hat(a, i) =
+ * 0.05 * (splitmix64(seed ^ (9a + 3 + i)) >> 11) * 2^-53, i = 0..5. */
+int mvpf_init_random(mvpf_problem* p, uint64_t seed);
+
+/* Residual R = dPi/dU of the discrete penalised incremental potential at the
+ * current state (Eqs. PenPot, FinalRes; Sec. 3.4), contact term excluded,
+ * Dirichlet rows NOT zeroed.  R: device (nullable).  norm_free: host
+ * (nullable), Euclidean norm of R over the free dofs of the loading at the
+ * current depth. */
+int mvpf_residual(mvpf_problem* p, double* R, double* norm_free);
+
+/* Build the Newton system of Eq. linAlgEq at the current state for the
+ * loading at total depth `depth`: tangent K = d^2 Pi / dU^2 reassembled on
+ * every level at the injected state (Sec. 3.4), Dirichlet rows/columns
+ * replaced by the identity, right-hand side b_free = -R_free - (K g)_free,
+ * b_con = g with g = target - current on constrained dofs (lifting); inverts
+ * the 9x9 diagonal blocks (LU, partial pivoting) and factors the coarsest
+ * level.  Returns MVPF_ESINGULAR if a block or the coarse matrix is singular. */
+int mvpf_newton_system(mvpf_problem* p, double depth);
+/* Copy the right-hand side b of the last mvpf_newton_system (device). */
+int mvpf_get_rhs(mvpf_problem* p, double* b);
+
+/* y = A_level x with the eliminated operator of the last mvpf_newton_system
+ * (Dirichlet rows/columns = identity).  level 0 = finest.  precision
+ * MVPF_FP64 uses the FP64 copy (finest level, or every level in FP64 mode),
+ * MVPF_MIXED the FP32 copy (mixed mode, levels above the coarsest).  x, y:
+ * device, length 9*n_nodes(level). */
+int mvpf_jacobian_apply(mvpf_problem* p, int level, int precision, const double* x, double* y);
+
+/* z = M^-1 v: one application of the preconditioner (V-cycle; identity on the
+ * constrained dofs of the finest level).  v, z: device, finest level. */
+int mvpf_precondition(mvpf_problem* p, const double* v, double* z);
+
+/* FGMRES(m) with the V-cycle as right preconditioner, x0 = 0 (Sec. 3.4).
+ * b: device right-hand side or NULL for the one built by mvpf_newton_system;
+ * x: device solution or NULL to keep it internally for mvpf_newton_update.
+ * Returns MVPF_ENOTCONV if max_it was reached. */
+int mvpf_solve(mvpf_problem* p, const double* b, double* x, mvpf_solve_stats* stats);
+
+/* U <- U + Delta with the internally kept solution of the last mvpf_solve;
+ * constrained dofs are set to their targets. */
+int mvpf_newton_update(mvpf_problem* p);
+
+/* One implicit time step to total depth `depth` (Sec. 3.4): Newton
+ * iterations (newton_system, solve, update) until the free-dof residual is
+ * <= newton_rtol * ||b_0||; if not within newton_max iterations, the state is
+ * restored and the depth increment halved (at most 8 times).  On success
+ * eta_hat_n <- eta_hat and the depth is advanced. */
+int mvpf_time_step(mvpf_problem* p, double depth, mvpf_step_stats* stats);
+
+/* Per-kernel device timing with HIP events on the problem's stream.  name:
+ * "pbj_sweep" (finest-level smoother sweep), "spmv_outer" (finest FP64
+ * operator product), "residual" (finest defect).  enable != 0 starts
+ * recording (and clears totals); stats: launches, summed ms, algorithmic
+ * bytes moved per launch. */
+int mvpf_kernel_timing(mvpf_problem* p, int enable);
+int mvpf_kernel_stats(mvpf_problem* p, const char* name, int* launches, double* total_ms,
+                      double* bytes_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MVPF_H */

@@ -49,19 +49,19 @@ from .material import Card
 # ---------------------------------------------------------------------------
 
 def dirichlet(mesh: Mesh, kind: str = "patch", patch: int = 2, radius: float = 0.2,
-              depth: float = 0.0, depth_prev: float = 0.0):
-    """Constrained-dof mask (n_nodes, 9) bool and prescribed increments (n_nodes, 9).
+              depth: float = 0.0):
+    """Constrained-dof mask (n_nodes, 9) bool and target values (n_nodes, 9).
 
-    Bottom face z = 0: all three displacement components fixed.  Top face:
-    kind 'patch' -- nodes of the centred patch x patch element square get
-    u_z increment -(depth - depth_prev); kind 'cap' -- nodes under a rigid
-    sphere of radius R at total depth d (r^2 < 2 R d - d^2) get
-    u_z(d) = -(d - (R - sqrt(R^2 - r^2))), increment u_z(d) - u_z(d_prev).
-    Order parameters are never constrained (natural boundary conditions).
+    Bottom face z = 0: all three displacement components fixed at 0.  Top
+    face: kind 'patch' -- nodes of the centred patch x patch element square
+    have u_z = -depth; kind 'cap' -- nodes under a rigid sphere of radius R
+    at total depth d, r^2 < 2 R d - d^2 (r measured from the top-face
+    centre), have u_z = -(d - (R - sqrt(R^2 - r^2))).  Order parameters are
+    never constrained (natural boundary conditions).
     """
     nn = mesh.n_nodes
     mask = np.zeros((nn, NDOF), dtype=bool)
-    g = np.zeros((nn, NDOF))
+    target = np.zeros((nn, NDOF))
     i, j, k = mesh.node_ijk(np.arange(nn))
     mask[k == 0, 0:3] = True
     top = k == mesh.nz
@@ -71,25 +71,22 @@ def dirichlet(mesh: Mesh, kind: str = "patch", patch: int = 2, radius: float = 0
         cx, cy, hp = mesh.nx // 2, mesh.ny // 2, patch // 2
         sel = top & (np.abs(i - cx) <= hp) & (np.abs(j - cy) <= hp)
         mask[sel, 2] = True
-        g[sel, 2] = -(depth - depth_prev)
+        target[sel, 2] = -depth
     elif kind == "cap":
         x = i * mesh.h - 0.5 * mesh.nx * mesh.h
         y = j * mesh.h - 0.5 * mesh.ny * mesh.h
         r2 = x * x + y * y
-
-        def uz(d):
-            inside = r2 < 2.0 * radius * d - d * d
-            val = -(d - (radius - np.sqrt(np.maximum(radius * radius - r2, 0.0))))
-            return inside, np.where(inside, val, 0.0)
-
-        in1, u1 = uz(depth)
-        _, u0 = uz(depth_prev)
-        sel = top & in1
+        sel = top & (r2 < 2.0 * radius * depth - depth * depth)
         mask[sel, 2] = True
-        g[sel, 2] = (u1 - u0)[sel]
+        target[sel, 2] = -(depth - (radius - np.sqrt(radius * radius - r2[sel])))
     else:
         raise ValueError(kind)
-    return mask, g
+    return mask, target
+
+
+def increment(mask: np.ndarray, target: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """Prescribed Newton increment g = target - current on constrained dofs."""
+    return np.where(mask, target - U.reshape(mask.shape), 0.0)
 
 
 def coarse_mask(fine_mesh: Mesh, fine_mask: np.ndarray, coarse_mesh: Mesh) -> np.ndarray:

@@ -1,0 +1,967 @@
+// C-ABI implementation: problem setup, Newton system assembly on all levels,
+// the multigrid V-cycle, FGMRES and the Newton / time-step drivers.  Host code
+// only orchestrates; every arithmetic step on the solve path runs in the HIP
+// kernels of this library.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "common.h"
+
+using namespace mvpf;
+
+static thread_local std::string g_create_err;
+
+namespace mvpf {
+
+Grid make_grid(int nx, int ny, int nz, double h) {
+  Grid g;
+  g.nx = nx; g.ny = ny; g.nz = nz;
+  g.nnx = nx + 1; g.nny = ny + 1; g.nnz = nz + 1;
+  g.N = g.nnx * g.nny * g.nnz;
+  g.Npad = (g.N + TILE - 1) / TILE * TILE;
+  g.ntiles = g.Npad / TILE;
+  g.NE = nx * ny * nz;
+  g.NEpad = (g.NE + TILE - 1) / TILE * TILE;
+  g.h = h;
+  return g;
+}
+
+}  // namespace mvpf
+
+namespace {
+
+#define HIPCHK(call)                                                             \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      p->err = std::string(#call) + " failed: " + hipGetErrorString(e_);         \
+      return MVPF_EDEVICE;                                                       \
+    }                                                                            \
+  } while (0)
+
+#define TRY(expr)              \
+  do {                         \
+    int rc_ = (expr);          \
+    if (rc_ < 0) return rc_;   \
+  } while (0)
+
+int launch_check(mvpf_problem* p, const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    p->err = std::string(where) + ": " + hipGetErrorString(e);
+    return MVPF_EDEVICE;
+  }
+  return 0;
+}
+
+template <typename T>
+int dalloc(mvpf_problem* p, T** ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) return 0;
+  const size_t bytes = count * sizeof(T);
+  hipError_t e = hipMalloc((void**)ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    p->err = "hipMalloc(" + std::to_string(bytes) + " bytes) failed: " + hipGetErrorString(e);
+    return MVPF_ENOMEM;
+  }
+  p->bytes += (int64_t)bytes;
+  e = hipMemsetAsync(*ptr, 0, bytes, p->stream);
+  if (e != hipSuccess) {
+    p->err = std::string("hipMemsetAsync failed: ") + hipGetErrorString(e);
+    return MVPF_EDEVICE;
+  }
+  return 0;
+}
+
+template <typename T>
+void dfree(T*& ptr) {
+  if (ptr) (void)hipFree((void*)ptr);
+  ptr = nullptr;
+}
+
+// ---- material card (Sec. 4.1, Table 1), rotated into the sample frame ----
+using T4 = double[3][3][3][3];
+
+void voigt_to_t4(const double C[6][6], T4 L) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) L[i][j][k][l] = C[SI(i, j)][SI(k, l)];
+}
+
+void t4_to_voigt(const T4 L, double C[6][6]) {
+  const int ia[6] = {0, 1, 2, 1, 0, 0}, ib[6] = {0, 1, 2, 2, 2, 1};
+  for (int v = 0; v < 6; ++v)
+    for (int u = 0; u < 6; ++u) C[v][u] = L[ia[v]][ib[v]][ia[u]][ib[u]];
+}
+
+// L'_ijkl = R_ia R_jb R_kc R_ld L_abcd
+void rotate_t4(const T4 L, const double R[3][3], T4 out) {
+  double t1[3][3][3][3], t2[3][3][3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) {
+          double s = 0;
+          for (int a = 0; a < 3; ++a) s += R[i][a] * L[a][b][c][d];
+          t1[i][b][c][d] = s;
+        }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) {
+          double s = 0;
+          for (int b = 0; b < 3; ++b) s += R[j][b] * t1[i][b][c][d];
+          t2[i][j][c][d] = s;
+        }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k)
+        for (int d = 0; d < 3; ++d) {
+          double s = 0;
+          for (int c = 0; c < 3; ++c) s += R[k][c] * t2[i][j][c][d];
+          t1[i][j][k][d] = s;
+        }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+          double s = 0;
+          for (int d = 0; d < 3; ++d) s += R[l][d] * t1[i][j][k][d];
+          out[i][j][k][l] = s;
+        }
+}
+
+void build_card(const mvpf_material& m, DevCard& cd) {
+  std::memset(&cd, 0, sizeof(cd));
+  double Q[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Q[i][j] = m.Q[3 * i + j];
+  // austenite
+  double C0[6][6] = {};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) C0[a][b] = (a == b) ? m.cubic[0] : m.cubic[1];
+  C0[3][3] = C0[4][4] = C0[5][5] = m.cubic[2];
+  T4 L0c, L0s;
+  voigt_to_t4(C0, L0c);
+  rotate_t4(L0c, Q, L0s);
+  double L0v[6][6];
+  t4_to_voigt(L0s, L0v);
+  // martensite in its orthorhombic axes: c11,c22,c33,c44,c55,c66,c12,c13,c23
+  const double* o = m.ortho;
+  double Cm[6][6] = {};
+  Cm[0][0] = o[0]; Cm[1][1] = o[1]; Cm[2][2] = o[2];
+  Cm[3][3] = o[3]; Cm[4][4] = o[4]; Cm[5][5] = o[5];
+  Cm[0][1] = Cm[1][0] = o[6];
+  Cm[0][2] = Cm[2][0] = o[7];
+  Cm[1][2] = Cm[2][1] = o[8];
+  T4 Lmo;
+  voigt_to_t4(Cm, Lmo);
+  // variant k = 2*pair + sign: stretch tensor p(e_a e_a + e_b e_b) +- q (e_a e_b + e_b e_a)
+  // + beta e_c e_c with p = (alpha+gamma)/2, q = (alpha-gamma)/2 (Sec. 4.1);
+  // its alpha-, beta-, gamma-axes are (e_a +- e_b)/sqrt2, e_c, (e_a -+ e_b)/sqrt2.
+  const int pa[3] = {0, 0, 1}, pb[3] = {2, 1, 2}, pc[3] = {1, 2, 0};
+  const double pp = 0.5 * (m.alpha + m.gamma), qq = 0.5 * (m.alpha - m.gamma);
+  const double r2 = 1.0 / std::sqrt(2.0);
+  for (int v = 0; v < 6; ++v) {
+    const int pr = v / 2;
+    const double sg = (v % 2 == 0) ? 1.0 : -1.0;
+    const int a = pa[pr], b = pb[pr], c = pc[pr];
+    double U[3][3] = {};
+    U[a][a] = U[b][b] = pp;
+    U[a][b] = U[b][a] = sg * qq;
+    U[c][c] = m.beta;
+    double R[3][3] = {};  // columns: alpha-, beta-, gamma-axis in crystal coordinates
+    R[a][0] = r2; R[b][0] = sg * r2;
+    R[c][1] = 1.0;
+    R[a][2] = r2; R[b][2] = -sg * r2;
+    // U in the sample frame: Q U Q^T
+    double Us[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0;
+        for (int k = 0; k < 3; ++k)
+          for (int l = 0; l < 3; ++l) s += Q[i][k] * U[k][l] * Q[j][l];
+        Us[i][j] = s;
+      }
+    for (int i = 0; i < 3; ++i)
+      for (int j = i; j < 3; ++j) cd.dU[v][SI(i, j)] = Us[i][j] - (i == j ? 1.0 : 0.0);
+    T4 Lc, Ls;
+    rotate_t4(Lmo, R, Lc);
+    rotate_t4(Lc, Q, Ls);
+    double Lv[6][6];
+    t4_to_voigt(Ls, Lv);
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) cd.dL[v][i][j] = Lv[i][j] - L0v[i][j];
+  }
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) cd.L0[i][j] = L0v[i][j];
+  for (int k = 0; k < 6; ++k) cd.dF0[k] = m.F0[k + 1] - m.F0[0];
+  for (int i = 0; i < 7; ++i)
+    for (int j = 0; j < 7; ++j) cd.W[i][j] = (i == j) ? 0.0 : ((i == 0 || j == 0) ? m.w_am : m.w_mm);
+  // condensation eta_0 = 1 - sum eta_k: Hessian of 1/2 eta^T W eta w.r.t. eta_hat
+  for (int k = 0; k < 6; ++k)
+    for (int l = 0; l < 6; ++l) cd.Sw[k][l] = cd.W[k + 1][l + 1] - cd.W[k + 1][0] - cd.W[0][l + 1] + cd.W[0][0];
+  // gradient energy -sum_{i<j} w_ij l^2 grad eta_i . grad eta_j in eta_hat
+  const double l2 = m.ell * m.ell;
+  for (int k = 0; k < 6; ++k)
+    for (int l = 0; l < 6; ++l) cd.Mg[k][l] = -l2 * cd.Sw[k][l];
+  cd.rho = m.rho;
+  cd.eps = m.eps_eta;
+  cd.pade = m.pade;
+}
+
+// ---- typed accessors for the two precision modes --------------------------
+template <typename T> const T* opA(const Level& L);
+template <> const float* opA<float>(const Level& L) { return L.A32; }
+template <> const double* opA<double>(const Level& L) { return L.A64; }
+template <typename T> const T* opD(const Level& L);
+template <> const float* opD<float>(const Level& L) { return L.Dinv32; }
+template <> const double* opD<double>(const Level& L) { return L.Dinv64; }
+
+int64_t nvec(const Grid& g) { return (int64_t)NDOF * g.Npad; }
+
+void timer_begin(mvpf_problem* p, KernelTimer& t) {
+  if (!p->timing) return;
+  if ((int)t.ev.size() < 2 * (t.used + 1)) {
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    t.ev.push_back(a);
+    t.ev.push_back(b);
+  }
+  (void)hipEventRecord(t.ev[2 * t.used], p->stream);
+}
+
+void timer_end(mvpf_problem* p, KernelTimer& t, double bytes) {
+  if (!p->timing) return;
+  (void)hipEventRecord(t.ev[2 * t.used + 1], p->stream);
+  t.used++;
+  t.bytes = bytes;
+}
+
+void timer_collect(mvpf_problem* p, KernelTimer& t) {
+  if (t.used == 0) return;
+  (void)hipStreamSynchronize(p->stream);
+  for (int i = 0; i < t.used; ++i) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]);
+    t.total_ms += ms;
+    t.launches++;
+  }
+  t.used = 0;
+}
+
+// Exact count of in-grid (node, neighbour) pairs of the 27-point stencil.
+double stencil_blocks(const Grid& g) {
+  return (3.0 * g.nx + 1.0) * (3.0 * g.ny + 1.0) * (3.0 * g.nz + 1.0);
+}
+
+// Algorithmic bytes of one damped point-block Jacobi sweep on level g.
+template <typename T>
+double sweep_bytes(const Grid& g) {
+  return sizeof(T) * (stencil_blocks(g) * NBLK + (double)g.N * (NBLK + 3 * NDOF));
+}
+
+// ---- V-cycle ------------------------------------------------------------------
+template <typename T>
+void sweep(mvpf_problem* p, int l, bool zero) {
+  Level& L = p->lev[l];
+  const T om = (T)p->opts.omega;
+  const bool timed = (l == 0 && !zero);
+  if (timed) timer_begin(p, p->t_sweep);
+  launch_pbj<T>(L.g, opA<T>(L), opD<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.x2, om, zero, p->stream);
+  if (timed) timer_end(p, p->t_sweep, sweep_bytes<T>(L.g));
+  std::swap(L.x, L.x2);
+}
+
+template <typename T>
+void vcycle(mvpf_problem* p, int l) {
+  Level& L = p->lev[l];
+  hipStream_t s = p->stream;
+  if (l == p->L - 1) {
+    launch_coarse_solve<T>(L.g, L.Ainv, (const T*)L.b, (T*)L.x, s);
+    return;
+  }
+  if (p->opts.nu_pre > 0) {
+    sweep<T>(p, l, true);
+    for (int k = 1; k < p->opts.nu_pre; ++k) sweep<T>(p, l, false);
+  } else {
+    launch_zero<T>(nvec(L.g), (T*)L.x, s);
+  }
+  if (l == 0 && p->timing) timer_begin(p, p->t_resid);
+  launch_defect<T>(L.g, opA<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.r, s);
+  if (l == 0 && p->timing)
+    timer_end(p, p->t_resid, sizeof(T) * (stencil_blocks(L.g) * NBLK + (double)L.g.N * 3 * NDOF));
+  Level& C = p->lev[l + 1];
+  launch_restrict<T>(L.g, C.g, (const T*)L.r, C.mask, (T*)C.b, s);
+  vcycle<T>(p, l + 1);
+  launch_prolong_add<T>(L.g, C.g, (const T*)C.x, L.mask, (T*)L.x, s);
+  for (int k = 0; k < p->opts.nu_post; ++k) sweep<T>(p, l, false);
+}
+
+template <typename T, typename TZ>
+void precondition(mvpf_problem* p, const double* v, TZ* z) {
+  Level& L0 = p->lev[0];
+  launch_convert_masked<double, T>(L0.g, v, L0.mask, (T*)L0.b, p->stream);
+  vcycle<T>(p, 0);
+  launch_precond_finish<T, TZ>(L0.g, (const T*)L0.x, v, L0.mask, z, p->stream);
+}
+
+// ---- FGMRES ---------------------------------------------------------------------
+int fetch(mvpf_problem* p, const double* dsrc, int count) {
+  HIPCHK(hipMemcpyAsync(p->hhost, dsrc, sizeof(double) * count, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return 0;
+}
+
+int norm_device(mvpf_problem* p, int64_t n, const double* v, double* out_host) {
+  const int nb = red_blocks(n);
+  launch_multidot(n, v, n, 1, v, p->red, p->stream);
+  launch_reduce(1, nb, p->red, p->hcol, 0, p->stream);
+  TRY(launch_check(p, "norm"));
+  TRY(fetch(p, p->hcol, 1));
+  *out_host = std::sqrt(p->hhost[0]);
+  return 0;
+}
+
+// Flexible GMRES(m), right preconditioned, x0 = 0, classical Gram-Schmidt
+// twice, Givens rotations; convergence on the recurrence residual, then a
+// true FP64 residual check (restart if it is not met).
+template <typename T, typename TZ>
+int fgmres(mvpf_problem* p, const double* b, double* x, mvpf_solve_stats* st) {
+  const Grid& g = p->lev[0].g;
+  const int64_t n = nvec(g);
+  const int m = std::min(p->opts.restart, p->restart_cap);
+  const int nb = red_blocks(n);
+  hipStream_t s = p->stream;
+  TZ* Z = (TZ*)p->Z;
+  double* V = p->V;
+  st->iterations = st->restarts = st->converged = 0;
+  st->rel_residual = 0.0;
+  launch_zero<double>(n, x, s);
+  double bnorm;
+  TRY(norm_device(p, n, b, &bnorm));
+  if (bnorm == 0.0) {
+    st->converged = 1;
+    return 0;
+  }
+  const double rtol = p->opts.rtol;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gg(m + 1), y(m);
+  auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  double beta = bnorm;
+  const double* r0 = b;
+  double* h1 = p->hcol;
+  double* h2 = p->hcol + (MAX_RESTART + 2);
+  double* hn = p->hcol + 2 * (MAX_RESTART + 2);
+  while (true) {
+    launch_axpby(n, 1.0 / beta, r0, 0.0, nullptr, V, s);
+    std::fill(gg.begin(), gg.end(), 0.0);
+    gg[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = V + (int64_t)j * n;
+      double* w = V + (int64_t)(j + 1) * n;
+      TZ* zj = Z + (int64_t)j * n;
+      precondition<T, TZ>(p, vj, zj);
+      if (p->timing) timer_begin(p, p->t_outer);
+      launch_spmv<double, TZ, double>(g, p->lev[0].A64, zj, w, s);
+      if (p->timing)
+        timer_end(p, p->t_outer,
+                  8.0 * stencil_blocks(g) * NBLK + (double)g.N * NDOF * (sizeof(TZ) + sizeof(double)));
+      launch_multidot(n, V, n, j + 1, w, p->red, s);
+      launch_reduce(j + 1, nb, p->red, h1, 0, s);
+      launch_multiaxpy(n, V, n, j + 1, h1, w, nullptr, s);
+      launch_multidot(n, V, n, j + 1, w, p->red, s);
+      launch_reduce(j + 1, nb, p->red, h2, 0, s);
+      launch_multiaxpy(n, V, n, j + 1, h2, w, p->red, s);
+      launch_reduce(1, nb, p->red, hn, 0, s);
+      TRY(launch_check(p, "fgmres arnoldi"));
+      TRY(fetch(p, p->hcol, 3 * (MAX_RESTART + 2)));
+      for (int i = 0; i <= j; ++i) Hij(i, j) = p->hhost[i] + p->hhost[(MAX_RESTART + 2) + i];
+      const double hnext = std::sqrt(p->hhost[2 * (MAX_RESTART + 2)]);
+      Hij(j + 1, j) = hnext;
+      if (hnext > 0.0) launch_axpby(n, 1.0 / hnext, w, 0.0, nullptr, w, s);
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
+        Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
+        Hij(i, j) = t;
+      }
+      const double den = std::hypot(Hij(j, j), Hij(j + 1, j));
+      cs[j] = Hij(j, j) / den;
+      sn[j] = Hij(j + 1, j) / den;
+      Hij(j, j) = den;
+      Hij(j + 1, j) = 0.0;
+      gg[j + 1] = -sn[j] * gg[j];
+      gg[j] = cs[j] * gg[j];
+      st->iterations++;
+      k = j + 1;
+      if (std::fabs(gg[j + 1]) <= rtol * bnorm || st->iterations >= p->opts.max_it) break;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double sacc = gg[i];
+      for (int c = i + 1; c < k; ++c) sacc -= Hij(i, c) * y[c];
+      y[i] = sacc / Hij(i, i);
+    }
+    HIPCHK(hipMemcpyAsync(h1, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+    launch_combine<TZ>(n, Z, n, k, h1, x, s);
+    // true residual r = b - A x
+    launch_spmv<double, double, double>(g, p->lev[0].A64, x, p->tmp, s);
+    launch_axpby(n, 1.0, b, -1.0, p->tmp, p->tmp, s);
+    TRY(norm_device(p, n, p->tmp, &beta));  // synchronises (y upload complete)
+    st->rel_residual = beta / bnorm;
+    if (st->rel_residual <= rtol) {
+      st->converged = 1;
+      return 0;
+    }
+    if (st->iterations >= p->opts.max_it) return MVPF_ENOTCONV;
+    st->restarts++;
+    r0 = p->tmp;
+    // the next restart overwrites V[0] from tmp before tmp is reused
+  }
+}
+
+int validate(const mvpf_mesh* mesh, const mvpf_material* mat, const mvpf_loading* load, const mvpf_opts* o,
+             std::string& err) {
+  if (!mesh || !mat || !load || !o) { err = "null argument"; return MVPF_EINVAL; }
+  if (mesh->nx < 2 || mesh->ny < 2 || mesh->nz < 2 || !(mesh->h > 0)) { err = "bad mesh sizes"; return MVPF_EINVAL; }
+  if (mesh->n_levels < 2 || mesh->n_levels > MAX_LEVELS) { err = "n_levels must be in [2, 8]"; return MVPF_EINVAL; }
+  const int f = 1 << (mesh->n_levels - 1);
+  if (mesh->nx % f || mesh->ny % f || mesh->nz % f) {
+    err = "nx, ny, nz must be divisible by 2^(n_levels-1)";
+    return MVPF_EINVAL;
+  }
+  const int64_t nc = (int64_t)(mesh->nx / f + 1) * (mesh->ny / f + 1) * (mesh->nz / f + 1) * NDOF;
+  if (nc > MVPF_MAX_COARSE_DOF) { err = "coarsest level too large for the dense direct solve"; return MVPF_EINVAL; }
+  const int64_t nn = (int64_t)(mesh->nx + 1) * (mesh->ny + 1) * (mesh->nz + 1);
+  if (nn * NDOF * 27 * 9 > ((int64_t)1 << 62) || nn >= ((int64_t)1 << 31) - 64) {
+    err = "mesh too large";
+    return MVPF_EINVAL;
+  }
+  if (mat->pade != 22) { err = "only the Pade (2,2) Hencky approximation is implemented"; return MVPF_EINVAL; }
+  if (load->kind == MVPF_LOAD_PATCH) {
+    if (load->patch < 0 || load->patch % 2 || mesh->nx % 2 || mesh->ny % 2) {
+      err = "patch loading needs even patch, nx and ny";
+      return MVPF_EINVAL;
+    }
+  } else if (load->kind == MVPF_LOAD_CAP) {
+    if (!(load->radius > 0)) { err = "cap radius must be positive"; return MVPF_EINVAL; }
+  } else {
+    err = "unknown loading kind";
+    return MVPF_EINVAL;
+  }
+  if (o->precision != MVPF_FP64 && o->precision != MVPF_MIXED) { err = "bad precision"; return MVPF_EINVAL; }
+  if (o->restart < 1 || o->restart > MAX_RESTART || o->max_it < 1 || !(o->rtol > 0)) {
+    err = "bad Krylov options";
+    return MVPF_EINVAL;
+  }
+  if (o->nu_pre < 0 || o->nu_post < 0 || !(o->omega > 0) || o->newton_max < 1) {
+    err = "bad smoother/Newton options";
+    return MVPF_EINVAL;
+  }
+  return 0;
+}
+
+void destroy_all(mvpf_problem* p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  for (int l = 0; l < MAX_LEVELS; ++l) {
+    Level& L = p->lev[l];
+    dfree(L.state); dfree(L.mask); dfree(L.target); dfree(L.A64); dfree(L.A32); dfree(L.diag64);
+    dfree(L.Dinv64); dfree(L.Dinv32); dfree(L.x); dfree(L.x2); dfree(L.b); dfree(L.r); dfree(L.Ainv);
+  }
+  dfree(p->card); dfree(p->qp); dfree(p->R); dfree(p->rhs); dfree(p->gvec); dfree(p->dx); dfree(p->tmp);
+  dfree(p->tmp2); dfree(p->V); dfree(p->Z); dfree(p->red); dfree(p->hcol); dfree(p->save_state);
+  if (p->hhost) (void)hipHostFree(p->hhost);
+  p->hhost = nullptr;
+  for (KernelTimer* t : {&p->t_sweep, &p->t_outer, &p->t_resid})
+    for (hipEvent_t e : t->ev) (void)hipEventDestroy(e);
+}
+
+int allocate(mvpf_problem* p) {
+  const mvpf_mesh& M = p->mesh;
+  p->L = M.n_levels;
+  p->mixed = p->opts.precision == MVPF_MIXED;
+  for (int l = 0; l < p->L; ++l) {
+    const int f = 1 << l;
+    Level& L = p->lev[l];
+    L.g = make_grid(M.nx / f, M.ny / f, M.nz / f, M.h * f);
+    const bool coarsest = (l == p->L - 1);
+    const int64_t nv = nvec(L.g);
+    const int64_t nA = (int64_t)L.g.ntiles * NSTEN * NBLK * TILE;
+    const int64_t nD = (int64_t)L.g.ntiles * NBLK * TILE;
+    TRY(dalloc(p, &L.state, (size_t)NSTATE * L.g.Npad));
+    TRY(dalloc(p, &L.mask, (size_t)L.g.Npad));
+    if (l == 0) TRY(dalloc(p, &L.target, (size_t)L.g.Npad));
+    if (l == 0 || !p->mixed || coarsest) TRY(dalloc(p, &L.A64, (size_t)nA));
+    if (p->mixed && !coarsest) TRY(dalloc(p, &L.A32, (size_t)nA));
+    if (!coarsest) {
+      TRY(dalloc(p, &L.diag64, (size_t)nD));
+      if (p->mixed)
+        TRY(dalloc(p, &L.Dinv32, (size_t)nD));
+      else
+        TRY(dalloc(p, &L.Dinv64, (size_t)nD));
+    }
+    const size_t es = p->mixed ? sizeof(float) : sizeof(double);
+    for (void** v : {&L.x, &L.x2, &L.b, &L.r}) {
+      char* c = nullptr;
+      TRY(dalloc(p, &c, (size_t)nv * es));
+      *v = c;
+    }
+    if (coarsest) {
+      L.ndense = NDOF * L.g.N;
+      TRY(dalloc(p, &L.Ainv, (size_t)L.ndense * L.ndense));
+    }
+  }
+  const Grid& g0 = p->lev[0].g;
+  const int64_t n = nvec(g0);
+  TRY(dalloc(p, &p->card, 1));
+  TRY(dalloc(p, &p->qp, (size_t)QP_HESS * 8 * g0.NEpad));
+  for (double** v : {&p->R, &p->rhs, &p->gvec, &p->dx, &p->tmp, &p->tmp2}) TRY(dalloc(p, v, (size_t)n));
+  p->restart_cap = p->opts.restart;
+  TRY(dalloc(p, &p->V, (size_t)(p->restart_cap + 1) * n));
+  {
+    char* z = nullptr;
+    TRY(dalloc(p, &z, (size_t)p->restart_cap * n * (p->mixed ? sizeof(float) : sizeof(double))));
+    p->Z = z;
+  }
+  TRY(dalloc(p, &p->red, (size_t)(MAX_RESTART + 2) * 1024));
+  TRY(dalloc(p, &p->hcol, (size_t)3 * (MAX_RESTART + 2)));
+  TRY(dalloc(p, &p->save_state, (size_t)NSTATE * g0.Npad));
+  hipError_t e = hipHostMalloc((void**)&p->hhost, sizeof(double) * 3 * (MAX_RESTART + 2));
+  if (e != hipSuccess) {
+    p->err = "hipHostMalloc failed";
+    return MVPF_ENOMEM;
+  }
+  DevCard hc;
+  build_card(p->mat, hc);
+  HIPCHK(hipMemcpyAsync(p->card, &hc, sizeof(DevCard), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return 0;
+}
+
+int free_norm(mvpf_problem* p, const double* v, double* out) {
+  const Grid& g = p->lev[0].g;
+  const int nb = red_blocks((int64_t)g.N * 9);
+  launch_free_norm_partial(g, v, p->lev[0].mask, p->red, p->stream);
+  launch_reduce(1, nb, p->red, p->hcol, 0, p->stream);
+  TRY(launch_check(p, "free norm"));
+  TRY(fetch(p, p->hcol, 1));
+  *out = std::sqrt(p->hhost[0]);
+  return 0;
+}
+
+// residual at the current state into p->R (masks of `depth` for the norm)
+int compute_residual(mvpf_problem* p, double depth, double* norm_free) {
+  Level& L0 = p->lev[0];
+  launch_dirichlet_masks(L0.g, p->load, depth, L0.mask, L0.target, p->stream);
+  launch_qp(L0.g, L0.state, p->card, p->qp, false, p->stream);
+  launch_residual_gather(L0.g, L0.state, p->qp, p->card, p->R, p->stream);
+  TRY(launch_check(p, "residual"));
+  if (norm_free) TRY(free_norm(p, p->R, norm_free));
+  return 0;
+}
+
+int build_system(mvpf_problem* p, double depth) {
+  hipStream_t s = p->stream;
+  Level& L0 = p->lev[0];
+  launch_dirichlet_masks(L0.g, p->load, depth, L0.mask, L0.target, s);
+  for (int l = 1; l < p->L; ++l) launch_inject_mask(p->lev[l - 1].g, p->lev[l].g, p->lev[l - 1].mask, p->lev[l].mask, s);
+  // finest: residual and unconstrained tangent
+  launch_qp(L0.g, L0.state, p->card, p->qp, true, s);
+  launch_residual_gather(L0.g, L0.state, p->qp, p->card, p->R, s);
+  launch_jacobian_gather(L0.g, p->qp, p->card, L0.A64, L0.A32, L0.diag64, s);
+  // lifting of the prescribed increment, then symmetric elimination
+  launch_increment(L0.g, L0.mask, L0.target, L0.state, p->gvec, s);
+  launch_spmv<double, double, double>(L0.g, L0.A64, p->gvec, p->tmp, s);
+  launch_newton_rhs(L0.g, L0.mask, p->R, p->tmp, p->gvec, p->rhs, s);
+  launch_apply_dirichlet(L0.g, L0.mask, L0.A64, L0.A32, L0.diag64, s);
+  // coarse levels: reassembly at the injected state
+  for (int l = 1; l < p->L; ++l) {
+    Level& F = p->lev[l - 1];
+    Level& C = p->lev[l];
+    launch_inject(F.g, C.g, F.state, C.state, s);
+    launch_qp(C.g, C.state, p->card, p->qp, true, s);
+    launch_jacobian_gather(C.g, p->qp, p->card, C.A64, C.A32, C.diag64, s);
+    launch_apply_dirichlet(C.g, C.mask, C.A64, C.A32, C.diag64, s);
+  }
+  TRY(launch_check(p, "assembly"));
+  return 0;
+}
+
+int setup_solver(mvpf_problem* p) {
+  hipStream_t s = p->stream;
+  int* status = (int*)p->red;  // first word of the reduction scratch
+  HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
+  for (int l = 0; l < p->L - 1; ++l) {
+    Level& L = p->lev[l];
+    launch_block_inverse(L.g, L.diag64, L.Dinv64, L.Dinv32, status, s);
+  }
+  Level& C = p->lev[p->L - 1];
+  const int nd = C.ndense;
+  // dense operator in tmp-sized scratch: use V (>= (m+1) * 9 * Npad doubles)
+  const int64_t need = (int64_t)nd * nd + 2 * (int64_t)nd * nd + nd;
+  const int64_t have = (int64_t)(p->restart_cap + 1) * nvec(p->lev[0].g);
+  double* work = nullptr;
+  bool own = false;
+  if (need <= have) {
+    work = p->V;
+  } else {
+    HIPCHK(hipMalloc((void**)&work, sizeof(double) * need));
+    own = true;
+  }
+  launch_dense_from_bsr(C.g, C.A64, work, s);
+  dense_invert(nd, work, C.Ainv, work + (int64_t)nd * nd, status, s);
+  TRY(launch_check(p, "solver setup"));
+  int hs = 0;
+  HIPCHK(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (own) (void)hipFree(work);
+  if (hs) {
+    p->err = "singular 9x9 diagonal block or coarse operator";
+    return MVPF_ESINGULAR;
+  }
+  return 0;
+}
+
+double elapsed_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  return ms;
+}
+
+int solve_internal(mvpf_problem* p, const double* b, double* x, mvpf_solve_stats* st) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, p->stream));
+  int rc = p->mixed ? fgmres<float, float>(p, b, x, st) : fgmres<double, double>(p, b, x, st);
+  (void)hipEventRecord(e1, p->stream);
+  (void)hipEventSynchronize(e1);
+  st->solve_ms = elapsed_ms(e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+}  // namespace
+
+// =============================================================================
+// C ABI
+// =============================================================================
+extern "C" {
+
+void mvpf_default_opts(mvpf_opts* o) {
+  if (!o) return;
+  o->precision = MVPF_FP64;
+  o->rtol = 1e-8;
+  o->restart = 30;
+  o->max_it = 500;
+  o->nu_pre = 2;
+  o->nu_post = 2;
+  o->omega = 0.5;
+  o->newton_max = 12;
+  o->newton_rtol = 1e-9;
+}
+
+int mvpf_create(const mvpf_mesh* mesh, const mvpf_material* mat, const mvpf_loading* load, const mvpf_opts* opts,
+                void* stream, mvpf_problem** out) {
+  if (!out) return MVPF_EINVAL;
+  *out = nullptr;
+  std::string err;
+  int rc = validate(mesh, mat, load, opts, err);
+  if (rc) {
+    g_create_err = err;
+    return rc;
+  }
+  mvpf_problem* p = new mvpf_problem();
+  p->mesh = *mesh;
+  p->mat = *mat;
+  p->load = *load;
+  p->opts = *opts;
+  p->stream = (hipStream_t)stream;
+  rc = allocate(p);
+  if (rc) {
+    g_create_err = p->err;
+    destroy_all(p);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return 0;
+}
+
+void mvpf_destroy(mvpf_problem* p) {
+  if (!p) return;
+  destroy_all(p);
+  delete p;
+}
+
+const char* mvpf_last_error(const mvpf_problem* p) { return p ? p->err.c_str() : g_create_err.c_str(); }
+
+int mvpf_get_info(const mvpf_problem* p, mvpf_info* info) {
+  if (!p || !info) return MVPF_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  info->n_levels = p->L;
+  for (int l = 0; l < p->L; ++l) {
+    info->nx[l] = p->lev[l].g.nx;
+    info->ny[l] = p->lev[l].g.ny;
+    info->nz[l] = p->lev[l].g.nz;
+    info->n_nodes[l] = p->lev[l].g.N;
+  }
+  info->bytes_device = p->bytes;
+  return 0;
+}
+
+int mvpf_set_opts(mvpf_problem* p, const mvpf_opts* o) {
+  if (!p || !o) return MVPF_EINVAL;
+  std::string err;
+  int rc = validate(&p->mesh, &p->mat, &p->load, o, err);
+  if (rc) { p->err = err; return rc; }
+  if (o->precision != p->opts.precision || o->restart > p->restart_cap) {
+    p->err = "precision and a larger restart need a new problem";
+    return MVPF_EINVAL;
+  }
+  p->opts = *o;
+  return 0;
+}
+
+int mvpf_set_state(mvpf_problem* p, const double* u, const double* eta, const double* eta_prev, double depth) {
+  if (!p) return MVPF_EINVAL;
+  const Grid& g = p->lev[0].g;
+  if (u) launch_interleaved_to_soa(g, u, 3, 0, 3, p->lev[0].state, p->stream);
+  if (eta) launch_interleaved_to_soa(g, eta, 6, 3, 6, p->lev[0].state, p->stream);
+  if (eta_prev) launch_interleaved_to_soa(g, eta_prev, 6, 9, 6, p->lev[0].state, p->stream);
+  p->depth = depth;
+  p->have_system = p->have_solution = false;
+  TRY(launch_check(p, "set_state"));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return 0;
+}
+
+int mvpf_get_state(mvpf_problem* p, double* u, double* eta, double* eta_prev, double* depth) {
+  if (!p) return MVPF_EINVAL;
+  const Grid& g = p->lev[0].g;
+  if (u) launch_soa_to_interleaved(g, p->lev[0].state, 3, 0, 3, u, p->stream);
+  if (eta) launch_soa_to_interleaved(g, p->lev[0].state, 6, 3, 6, eta, p->stream);
+  if (eta_prev) launch_soa_to_interleaved(g, p->lev[0].state, 6, 9, 6, eta_prev, p->stream);
+  if (depth) *depth = p->depth;
+  TRY(launch_check(p, "get_state"));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return 0;
+}
+
+int mvpf_init_random(mvpf_problem* p, uint64_t seed) {
+  if (!p) return MVPF_EINVAL;
+  launch_init_random(p->lev[0].g, seed, p->lev[0].state, p->stream);
+  p->depth = 0.0;
+  p->have_system = p->have_solution = false;
+  TRY(launch_check(p, "init_random"));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return 0;
+}
+
+int mvpf_residual(mvpf_problem* p, double* R, double* norm_free) {
+  if (!p) return MVPF_EINVAL;
+  TRY(compute_residual(p, p->have_system ? p->sys_depth : p->depth, norm_free));
+  if (R) launch_soa_to_interleaved(p->lev[0].g, p->R, 9, 0, 9, R, p->stream);
+  TRY(launch_check(p, "residual"));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return 0;
+}
+
+int mvpf_newton_system(mvpf_problem* p, double depth) {
+  if (!p) return MVPF_EINVAL;
+  p->have_system = p->have_solution = false;
+  TRY(build_system(p, depth));
+  TRY(setup_solver(p));
+  p->sys_depth = depth;
+  p->have_system = true;
+  return 0;
+}
+
+int mvpf_get_rhs(mvpf_problem* p, double* b) {
+  if (!p || !b) return MVPF_EINVAL;
+  if (!p->have_system) { p->err = "no Newton system"; return MVPF_ESTATE; }
+  launch_soa_to_interleaved(p->lev[0].g, p->rhs, 9, 0, 9, b, p->stream);
+  TRY(launch_check(p, "get_rhs"));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return 0;
+}
+
+int mvpf_jacobian_apply(mvpf_problem* p, int level, int precision, const double* x, double* y) {
+  if (!p || !x || !y || level < 0 || level >= p->L) return MVPF_EINVAL;
+  if (!p->have_system) { p->err = "no Newton system"; return MVPF_ESTATE; }
+  Level& L = p->lev[level];
+  const Grid& g = L.g;
+  hipStream_t s = p->stream;
+  launch_interleaved_to_soa(g, x, 9, 0, 9, p->tmp, s);
+  if (precision == MVPF_FP64) {
+    if (!L.A64) { p->err = "no FP64 operator on this level"; return MVPF_EINVAL; }
+    launch_spmv<double, double, double>(g, L.A64, p->tmp, p->tmp2, s);
+  } else if (precision == MVPF_MIXED) {
+    if (!L.A32) { p->err = "no FP32 operator on this level"; return MVPF_EINVAL; }
+    launch_convert<double, float>(nvec(g), p->tmp, (float*)L.x, s);
+    launch_spmv<float, float, float>(g, L.A32, (const float*)L.x, (float*)L.r, s);
+    launch_convert<float, double>(nvec(g), (const float*)L.r, p->tmp2, s);
+  } else {
+    return MVPF_EINVAL;
+  }
+  launch_soa_to_interleaved(g, p->tmp2, 9, 0, 9, y, s);
+  TRY(launch_check(p, "jacobian_apply"));
+  HIPCHK(hipStreamSynchronize(s));
+  return 0;
+}
+
+int mvpf_precondition(mvpf_problem* p, const double* v, double* z) {
+  if (!p || !v || !z) return MVPF_EINVAL;
+  if (!p->have_system) { p->err = "no Newton system"; return MVPF_ESTATE; }
+  const Grid& g = p->lev[0].g;
+  launch_interleaved_to_soa(g, v, 9, 0, 9, p->tmp, p->stream);
+  if (p->mixed)
+    precondition<float, double>(p, p->tmp, p->tmp2);
+  else
+    precondition<double, double>(p, p->tmp, p->tmp2);
+  launch_soa_to_interleaved(g, p->tmp2, 9, 0, 9, z, p->stream);
+  TRY(launch_check(p, "precondition"));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return 0;
+}
+
+int mvpf_solve(mvpf_problem* p, const double* b, double* x, mvpf_solve_stats* stats) {
+  if (!p) return MVPF_EINVAL;
+  if (!p->have_system) { p->err = "no Newton system"; return MVPF_ESTATE; }
+  mvpf_solve_stats local;
+  mvpf_solve_stats* st = stats ? stats : &local;
+  const Grid& g = p->lev[0].g;
+  const double* bb = p->rhs;
+  if (b) {
+    launch_interleaved_to_soa(g, b, 9, 0, 9, p->tmp2, p->stream);
+    bb = p->tmp2;
+  }
+  int rc = solve_internal(p, bb, p->dx, st);
+  if (rc < 0) return rc;
+  if (x) {
+    launch_soa_to_interleaved(g, p->dx, 9, 0, 9, x, p->stream);
+    TRY(launch_check(p, "solve output"));
+    HIPCHK(hipStreamSynchronize(p->stream));
+  }
+  p->have_solution = (b == nullptr);
+  if (rc == MVPF_ENOTCONV) p->err = "FGMRES reached max_it";
+  return rc;
+}
+
+int mvpf_newton_update(mvpf_problem* p) {
+  if (!p) return MVPF_EINVAL;
+  if (!p->have_solution) { p->err = "no Newton increment"; return MVPF_ESTATE; }
+  Level& L0 = p->lev[0];
+  launch_state_update(L0.g, L0.mask, L0.target, p->dx, L0.state, p->stream);
+  TRY(launch_check(p, "newton_update"));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->depth = p->sys_depth;
+  p->have_solution = false;
+  p->have_system = false;
+  return 0;
+}
+
+int mvpf_time_step(mvpf_problem* p, double depth, mvpf_step_stats* stats) {
+  if (!p) return MVPF_EINVAL;
+  mvpf_step_stats local;
+  mvpf_step_stats* st = stats ? stats : &local;
+  std::memset(st, 0, sizeof(*st));
+  Level& L0 = p->lev[0];
+  const size_t sbytes = sizeof(double) * NSTATE * L0.g.Npad;
+  const double goal = depth;
+  double trial = depth;
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  int rc = 0;
+  while (true) {
+    const double cur = p->depth;
+    HIPCHK(hipMemcpyAsync(p->save_state, L0.state, sbytes, hipMemcpyDeviceToDevice, p->stream));
+    bool ok = false;
+    double b0 = 0.0;
+    for (int it = 0; it <= p->opts.newton_max; ++it) {
+      double rfree = 0.0;
+      TRY(compute_residual(p, trial, &rfree));
+      st->residual = rfree;
+      if (it > 0 && rfree <= p->opts.newton_rtol * b0) { ok = true; break; }
+      if (it == p->opts.newton_max) break;
+      (void)hipEventRecord(a, p->stream);
+      TRY(build_system(p, trial));
+      (void)hipEventRecord(b, p->stream);
+      (void)hipEventSynchronize(b);
+      st->assemble_ms += elapsed_ms(a, b);
+      (void)hipEventRecord(a, p->stream);
+      TRY(setup_solver(p));
+      (void)hipEventRecord(b, p->stream);
+      (void)hipEventSynchronize(b);
+      st->setup_ms += elapsed_ms(a, b);
+      p->sys_depth = trial;
+      p->have_system = true;
+      if (it == 0) {
+        TRY(norm_device(p, nvec(L0.g), p->rhs, &b0));
+        st->residual0 = b0;
+      }
+      mvpf_solve_stats ss;
+      int src = solve_internal(p, p->rhs, p->dx, &ss);
+      if (src < 0) return src;
+      st->linear_iterations += ss.iterations;
+      st->solve_ms += ss.solve_ms;
+      st->newton_iterations++;
+      p->have_solution = true;
+      TRY(mvpf_newton_update(p));
+    }
+    if (ok) {
+      // eta_n <- eta
+      HIPCHK(hipMemcpyAsync(L0.state + (int64_t)9 * L0.g.Npad, L0.state + (int64_t)3 * L0.g.Npad,
+                            sizeof(double) * 6 * L0.g.Npad, hipMemcpyDeviceToDevice, p->stream));
+      HIPCHK(hipStreamSynchronize(p->stream));
+      p->depth = trial;
+      if (trial == goal) { st->converged = 1; break; }
+      trial = goal;
+      continue;
+    }
+    HIPCHK(hipMemcpyAsync(L0.state, p->save_state, sbytes, hipMemcpyDeviceToDevice, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->depth = cur;
+    if (++st->halvings > 8) { rc = MVPF_ENOTCONV; p->err = "Newton failed after 8 halvings"; break; }
+    trial = cur + 0.5 * (trial - cur);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  p->have_system = p->have_solution = false;
+  return rc;
+}
+
+int mvpf_kernel_timing(mvpf_problem* p, int enable) {
+  if (!p) return MVPF_EINVAL;
+  (void)hipStreamSynchronize(p->stream);
+  for (KernelTimer* t : {&p->t_sweep, &p->t_outer, &p->t_resid}) {
+    t->used = 0;
+    t->launches = 0;
+    t->total_ms = 0.0;
+  }
+  p->timing = enable != 0;
+  return 0;
+}
+
+int mvpf_kernel_stats(mvpf_problem* p, const char* name, int* launches, double* total_ms, double* bytes_per_launch) {
+  if (!p || !name) return MVPF_EINVAL;
+  KernelTimer* t = nullptr;
+  if (!std::strcmp(name, "pbj_sweep")) t = &p->t_sweep;
+  else if (!std::strcmp(name, "spmv_outer")) t = &p->t_outer;
+  else if (!std::strcmp(name, "residual")) t = &p->t_resid;
+  else { p->err = "unknown kernel name"; return MVPF_EINVAL; }
+  timer_collect(p, *t);
+  if (launches) *launches = t->launches;
+  if (total_ms) *total_ms = t->total_ms;
+  if (bytes_per_launch) *bytes_per_launch = t->bytes;
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,190 @@
+// Internal declarations of the mvpf library (not part of the C ABI).
+//
+// Data layout in HBM:
+//  * vectors: structure-of-arrays, component-major: v[c * Npad + n] for the
+//    9 unknowns c of node n; Npad = N rounded up to 64; padding is kept 0.
+//  * state:   15 FP64 components [u_x,u_y,u_z, eta_1..6, eta_n_1..6] in the
+//    same SoA layout.
+//  * 9x9 block operators on the structured 27-point stencil, tiled SoA:
+//    A[((t * 27 + s) * 81 + e) * 64 + l] is entry e = 9*row + col of the block
+//    coupling node n = 64 t + l with its neighbour n + off(s),
+//    s = (dz+1)*9 + (dy+1)*3 + (dx+1).  Blocks of out-of-grid neighbours and of
+//    padding rows are zero.  One wavefront reads one (tile, s, e) slice of 64
+//    consecutive values per load.
+//  * block inverses D^-1: Dinv[(t * 81 + e) * 64 + l].
+//  * per-Gauss-point scratch: qp[(comp * 8 + g) * NEpad + e].
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mvpf.h"
+#include "local.h"
+
+namespace mvpf {
+
+constexpr int NDOF = 9;
+constexpr int NSTATE = 15;
+constexpr int NSTEN = 27;
+constexpr int NBLK = 81;
+constexpr int TILE = 64;
+constexpr int QP_GRAD = 15;          // gradient components per Gauss point
+constexpr int QP_HESS = 15 + 120;    // gradient + packed Hessian
+constexpr int MAX_LEVELS = 8;
+constexpr int MAX_RESTART = 64;
+
+struct Grid {
+  int nx, ny, nz;      // elements
+  int nnx, nny, nnz;   // nodes per direction
+  int N;               // nodes
+  int Npad;            // nodes rounded up to TILE
+  int ntiles;
+  int NE, NEpad;       // elements, rounded up to TILE
+  double h;
+};
+
+Grid make_grid(int nx, int ny, int nz, double h);
+
+struct Level {
+  Grid g;
+  double* state = nullptr;    // [15][Npad]
+  uint16_t* mask = nullptr;   // [Npad] constrained-dof bits (bit c = dof c)
+  double* target = nullptr;   // [Npad] prescribed u_z on the top face (finest only)
+  double* A64 = nullptr;      // FP64 operator (finest; every level in FP64 mode)
+  float* A32 = nullptr;       // FP32 operator (mixed mode, all but coarsest)
+  double* diag64 = nullptr;   // FP64 diagonal blocks [ntiles][81][64]
+  double* Dinv64 = nullptr;   // FP64 block inverses (FP64 mode)
+  float* Dinv32 = nullptr;    // FP32 block inverses (mixed mode)
+  // work vectors of the V-cycle (type per precision mode), [9][Npad]
+  void* x = nullptr;
+  void* x2 = nullptr;
+  void* b = nullptr;
+  void* r = nullptr;
+  // coarsest level: dense inverse in SoA dof order (9 * N)^2
+  double* Ainv = nullptr;
+  int ndense = 0;
+};
+
+struct KernelTimer {
+  std::vector<hipEvent_t> ev;  // start/stop pairs
+  int used = 0;
+  int launches = 0;
+  double total_ms = 0.0;
+  double bytes = 0.0;
+};
+
+}  // namespace mvpf
+
+struct mvpf_problem {
+  mvpf_mesh mesh;
+  mvpf_material mat;
+  mvpf_loading load;
+  mvpf_opts opts;
+  int restart_cap = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int L = 0;
+  bool mixed = false;
+  mvpf::Level lev[mvpf::MAX_LEVELS];
+  mvpf::DevCard* card = nullptr;     // device copy
+  double* qp = nullptr;              // per-Gauss-point scratch (finest size)
+  double depth = 0.0;                // depth of the current state
+  double sys_depth = 0.0;            // depth used by the last Newton system
+  bool have_system = false;
+  bool have_solution = false;
+  // Newton / Krylov vectors (finest level, FP64 unless noted), [9][Npad]
+  double* R = nullptr;       // residual
+  double* rhs = nullptr;     // Newton right-hand side
+  double* gvec = nullptr;    // prescribed increment (lifting)
+  double* dx = nullptr;      // solution of the last solve
+  double* tmp = nullptr;     // work
+  double* tmp2 = nullptr;
+  double* V = nullptr;       // (m+1) basis vectors
+  void* Z = nullptr;         // m preconditioned vectors (FP32 in mixed mode)
+  double* red = nullptr;     // reduction partials
+  double* hcol = nullptr;    // device column of H (m+2)
+  double* hhost = nullptr;   // pinned host mirror
+  double* save_state = nullptr;  // backup for step rejection
+  int64_t bytes = 0;
+  bool timing = false;
+  mvpf::KernelTimer t_sweep, t_outer, t_resid;
+};
+
+namespace mvpf {
+
+// ---- launchers (all asynchronous on `s`) ----------------------------------
+// quadrature / assembly
+void launch_qp(const Grid& g, const double* state, const DevCard* cd, double* qp, bool hess, hipStream_t s);
+void launch_residual_gather(const Grid& g, const double* state, const double* qp, const DevCard* cd,
+                            double* R, hipStream_t s);
+void launch_jacobian_gather(const Grid& g, const double* qp, const DevCard* cd, double* A64, float* A32,
+                            double* diag64, hipStream_t s);
+void launch_apply_dirichlet(const Grid& g, const uint16_t* mask, double* A64, float* A32, double* diag64,
+                            hipStream_t s);
+void launch_block_inverse(const Grid& g, const double* diag64, double* Dinv64, float* Dinv32, int* status,
+                          hipStream_t s);
+// BSR products (TA = operator type, TX = vector type)
+template <typename TA, typename TX, typename TY>
+void launch_spmv(const Grid& g, const TA* A, const TX* x, TY* y, hipStream_t s);
+template <typename T>
+void launch_defect(const Grid& g, const T* A, const T* x, const T* b, T* r, hipStream_t s);
+template <typename T>
+void launch_pbj(const Grid& g, const T* A, const T* Dinv, const T* x, const T* b, T* xo, T omega,
+                bool zero_guess, hipStream_t s);
+// transfers
+template <typename T>
+void launch_restrict(const Grid& fine, const Grid& coarse, const T* rf, const uint16_t* cmask, T* bc,
+                     hipStream_t s);
+template <typename T>
+void launch_prolong_add(const Grid& fine, const Grid& coarse, const T* ec, const uint16_t* fmask, T* xf,
+                        hipStream_t s);
+void launch_inject(const Grid& fine, const Grid& coarse, const double* sf, double* sc, hipStream_t s);
+void launch_inject_mask(const Grid& fine, const Grid& coarse, const uint16_t* mf, uint16_t* mc,
+                        hipStream_t s);
+// coarse direct solve
+void launch_dense_from_bsr(const Grid& g, const double* A64, double* dense, hipStream_t s);
+int dense_invert(int n, double* a, double* inv, double* work, int* piv_status, hipStream_t s);
+template <typename T>
+void launch_coarse_solve(const Grid& g, const double* Ainv, const T* b, T* x, hipStream_t s);
+// vectors
+void launch_interleaved_to_soa(const Grid& g, const double* in, int ncomp, int comp0, int ldc,
+                               double* out, hipStream_t s);
+void launch_soa_to_interleaved(const Grid& g, const double* in, int ncomp, int comp0, int ldc,
+                               double* out, hipStream_t s);
+template <typename TI, typename TO>
+void launch_convert_masked(const Grid& g, const TI* in, const uint16_t* mask, TO* out, hipStream_t s);
+void launch_set_constrained(const Grid& g, const uint16_t* mask, const double* src, double* dst,
+                            hipStream_t s);
+void launch_dirichlet_masks(const Grid& g, const mvpf_loading& ld, double depth, uint16_t* mask,
+                            double* target, hipStream_t s);
+void launch_increment(const Grid& g, const uint16_t* mask, const double* target, const double* state,
+                      double* gvec, hipStream_t s);
+void launch_newton_rhs(const Grid& g, const uint16_t* mask, const double* R, const double* Kg,
+                       const double* gvec, double* rhs, hipStream_t s);
+void launch_state_update(const Grid& g, const uint16_t* mask, const double* target, const double* dx,
+                         double* state, hipStream_t s);
+void launch_init_random(const Grid& g, uint64_t seed, double* state, hipStream_t s);
+void launch_free_norm_partial(const Grid& g, const double* v, const uint16_t* mask, double* part,
+                              hipStream_t s);
+// Krylov (n = 9 * Npad)
+int red_blocks(int64_t n);
+void launch_multidot(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part,
+                     hipStream_t s);
+void launch_reduce(int k, int nblk, const double* part, double* out, int accumulate, hipStream_t s);
+void launch_multiaxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w,
+                      double* part_norm, hipStream_t s);
+void launch_scale(int64_t n, const double* w, const double* beta, double* v, hipStream_t s);
+template <typename TZ>
+void launch_combine(int64_t n, const TZ* Z, int64_t ldz, int k, const double* y, double* x, hipStream_t s);
+void launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* z,
+                  hipStream_t s);
+template <typename T>
+void launch_zero(int64_t n, T* p, hipStream_t s);
+template <typename TI, typename TO>
+void launch_convert(int64_t n, const TI* in, TO* out, hipStream_t s);
+template <typename T, typename TZ>
+void launch_precond_finish(const Grid& g, const T* x, const double* v, const uint16_t* mask, TZ* z, hipStream_t s);
+
+}  // namespace mvpf

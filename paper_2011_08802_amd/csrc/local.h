@@ -1,0 +1,561 @@
+// Local (quadrature-point) derivatives of the penalised incremental potential
+// density with respect to q = (F_00..F_22 row-major, eta_1..eta_6).
+//
+// Density (Sec. 2.2-2.3, 3.1-3.2; gradient-energy part handled separately by
+// the element kernels since it is a constant quadratic form):
+//   psi = sum_i eta_i F_i + 1/2 J_t H : L(eta) H + sum_{i<j} w_ij eta_i eta_j
+//         + sum_i rho/2 (eta_i - eta_in)^2 + sum_i eps/2 <eta_i>_-^2
+//   F^t = I + sum_k eta_k dU_k  (Eq. LinMix with U_0 = I, condensed),
+//   J_t = det F^t, G = (F^t)^-1, C = G F^T F G  (C^e of Eq. elasticEn),
+//   H = 3/2 (C^2 - I)(C^2 + 4C + I)^-1  (Eq. pade22), L = L_0 + sum eta_k dL_k.
+//
+// Derivatives are closed-form:
+//  * in C-space along the symmetric basis E_v (xx,yy,zz,yz,xz,xy; the shear
+//    ones are e_a e_b^T + e_b e_a^T):  with A = C^2 - I, B = C^2 + 4C + I,
+//    dH = (3/2 dA - H dB) B^-1,
+//    d2H = (3/2 d2A - dH_u dB_v - dH_v dB_u - H d2B) B^-1, d2A = d2B = E_u E_v + E_v E_u;
+//  * chain rule through C(F, G(eta)), J_t(eta), L(eta):
+//    dC/dF_ij = a_i (x) G_j + G_j (x) a_i  (a_i = row i of F G),
+//    dC/deta_k = -(Q_k C + C Q_k^T), Q_k = G dU_k,  dJ_t/deta_k = J_t tr Q_k,
+//    d2C/dF_ij dF_kl = delta_ik (G_j (x) G_l + G_l (x) G_j),
+//    d2C/dF deta_k = -(Q_k dC_F + dC_F Q_k^T),
+//    d2C/deta_k deta_l = sym2(Q_k Q_l C + Q_l Q_k C + Q_k C Q_l^T),
+//    d2J_t/deta_k deta_l = J_t (tr Q_k tr Q_l - tr(Q_k Q_l)).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mvpf {
+
+// Material card on the device, in the sample frame.
+struct DevCard {
+  double dU[6][6];     // U_k - I (k = 1..6) as symmetric components
+  double L0[6][6];     // austenite stiffness, Voigt (engineering shear strain)
+  double dL[6][6][6];  // L_k - L_0
+  double dF0[6];       // F_k - F_0
+  double W[7][7];      // double-obstacle coefficients, zero diagonal
+  double Sw[6][6];     // condensed Hessian of 1/2 eta^T W eta w.r.t. eta_hat
+  double Mg[6][6];     // gradient-energy species matrix: psi_g = 1/2 Mg_kl grad eta_k . grad eta_l
+  double rho;
+  double eps;
+  int pade;
+};
+
+// symmetric index map (xx,yy,zz,yz,xz,xy)
+__host__ __device__ constexpr int SI(int a, int b) {
+  return a == b ? a : (a + b == 3 ? 3 : (a + b == 2 ? 4 : 5));
+}
+
+__device__ __forceinline__ void full_from_sym(const double s[6], double m[9]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) m[3 * a + b] = s[SI(a, b)];
+}
+
+// symmetric part components of a full matrix
+__device__ __forceinline__ void sym_of(const double m[9], double s[6]) {
+  s[0] = m[0];
+  s[1] = m[4];
+  s[2] = m[8];
+  s[3] = 0.5 * (m[5] + m[7]);
+  s[4] = 0.5 * (m[2] + m[6]);
+  s[5] = 0.5 * (m[1] + m[3]);
+}
+
+__device__ __forceinline__ void mm(const double a[9], const double b[9], double c[9]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      c[3 * i + j] = a[3 * i] * b[j] + a[3 * i + 1] * b[3 + j] + a[3 * i + 2] * b[6 + j];
+}
+
+__device__ __forceinline__ double ddot9(const double a[9], const double b[9]) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) s += a[i] * b[i];
+  return s;
+}
+
+// sum_ab a_ab b_ba
+__device__ __forceinline__ double trprod(const double a[9], const double b[9]) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) s += a[3 * i + j] * b[3 * j + i];
+  return s;
+}
+
+// Contraction X : E_v of a full matrix with the symmetric basis element E_v.
+__device__ __forceinline__ double contract_basis(const double x[9], int v) {
+  switch (v) {
+    case 0: return x[0];
+    case 1: return x[4];
+    case 2: return x[8];
+    case 3: return x[5] + x[7];
+    case 4: return x[2] + x[6];
+    default: return x[1] + x[3];
+  }
+}
+
+// engineering (Voigt strain) form of symmetric components
+__device__ __forceinline__ void eng(const double s[6], double e[6]) {
+  e[0] = s[0]; e[1] = s[1]; e[2] = s[2];
+  e[3] = 2.0 * s[3]; e[4] = 2.0 * s[4]; e[5] = 2.0 * s[5];
+}
+
+// inverse and determinant of a symmetric 3x3 (components)
+__device__ __forceinline__ double sym_inv(const double s[6], double r[6]) {
+  const double xx = s[0], yy = s[1], zz = s[2], yz = s[3], xz = s[4], xy = s[5];
+  const double c0 = yy * zz - yz * yz;
+  const double c5 = xz * yz - xy * zz;  // cofactor (0,1)
+  const double c4 = xy * yz - xz * yy;  // cofactor (0,2)
+  const double det = xx * c0 + xy * c5 + xz * c4;
+  const double id = 1.0 / det;
+  r[0] = c0 * id;
+  r[5] = c5 * id;
+  r[4] = c4 * id;
+  r[1] = (xx * zz - xz * xz) * id;
+  r[3] = (xy * xz - xx * yz) * id;
+  r[2] = (xx * yy - xy * xy) * id;
+  return det;
+}
+
+// Symmetric basis element E_v as a full matrix.
+__device__ __forceinline__ void basis(int v, double e[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) e[i] = 0.0;
+  switch (v) {
+    case 0: e[0] = 1.0; break;
+    case 1: e[4] = 1.0; break;
+    case 2: e[8] = 1.0; break;
+    case 3: e[5] = e[7] = 1.0; break;
+    case 4: e[2] = e[6] = 1.0; break;
+    default: e[1] = e[3] = 1.0; break;
+  }
+}
+
+__host__ __device__ constexpr int hidx(int p, int q) {  // packed upper triangle, p <= q < 15
+  return p * 15 - (p * (p - 1)) / 2 + (q - p);
+}
+
+// Quantities shared by the gradient and the Hessian.
+struct LocalBase {
+  double Jt;
+  double G[9];    // (F^t)^-1, full
+  double Fe[9];   // F G
+  double C[9];    // full symmetric
+  double w;       // 1/2 H : L H
+  double wC[6];   // dw/dC along E_v
+  double wEta[6]; // partial dw/deta_k at fixed C
+  double dh[6][6];  // engineering components of dH_v
+  double h[6];      // engineering H
+  double T[6];      // L H (tensor components)
+  double Binv[9];
+  double H[9];
+};
+
+// Padé (2,2) Hencky energy and its first C-derivatives.
+__device__ __forceinline__ void local_base(const double F[9], const double eh[6], const DevCard& cd,
+                                           LocalBase& b) {
+  double Ft[6];
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    double s = (v < 3) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s += eh[k] * cd.dU[k][v];
+    Ft[v] = s;
+  }
+  double Gs[6];
+  b.Jt = sym_inv(Ft, Gs);
+  full_from_sym(Gs, b.G);
+  mm(F, b.G, b.Fe);
+  // C = Fe^T Fe
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      b.C[3 * a + c] = b.Fe[a] * b.Fe[c] + b.Fe[3 + a] * b.Fe[3 + c] + b.Fe[6 + a] * b.Fe[6 + c];
+  double C2[9];
+  mm(b.C, b.C, C2);
+  double Bs[6], Bi[6];
+  {
+    double Bf[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Bf[i] = C2[i] + 4.0 * b.C[i] + ((i % 4 == 0) ? 1.0 : 0.0);
+    sym_of(Bf, Bs);
+  }
+  sym_inv(Bs, Bi);
+  full_from_sym(Bi, b.Binv);
+  double Am[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Am[i] = C2[i] - ((i % 4 == 0) ? 1.0 : 0.0);
+  double Hf[9];
+  mm(Am, b.Binv, Hf);
+  double Hs[6];
+  sym_of(Hf, Hs);
+#pragma unroll
+  for (int v = 0; v < 6; ++v) Hs[v] *= 1.5;
+  full_from_sym(Hs, b.H);
+  eng(Hs, b.h);
+  // mixed stiffness and Hencky stress
+  double Lm[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      double s = cd.L0[i][j];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) s += eh[k] * cd.dL[k][i][j];
+      Lm[i][j] = s;
+    }
+  double w = 0.0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) s += Lm[i][j] * b.h[j];
+    b.T[i] = s;
+    w += b.h[i] * s;
+  }
+  b.w = 0.5 * w;
+  // partial derivative w.r.t. eta at fixed C: 1/2 h^T dL_k h
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) t += cd.dL[k][i][j] * b.h[j];
+      s += b.h[i] * t;
+    }
+    b.wEta[k] = 0.5 * s;
+  }
+  // dH along the C basis and dw/dC
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    double E[9], P[9], dA[9], dB[9], HdB[9], X[9], dHf[9], dHs[6];
+    basis(v, E);
+    mm(b.C, E, P);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dA[3 * a + c] = P[3 * a + c] + P[3 * c + a];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dB[i] = dA[i] + 4.0 * E[i];
+    mm(b.H, dB, HdB);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) X[i] = 1.5 * dA[i] - HdB[i];
+    mm(X, b.Binv, dHf);
+    sym_of(dHf, dHs);
+    eng(dHs, b.dh[v]);
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) s += b.T[i] * b.dh[v][i];
+    b.wC[v] = s;
+  }
+}
+
+// Symmetric components of dC along variable q (0..8: F_ij row-major; 9..14: eta).
+__device__ __forceinline__ void dC_of(const LocalBase& b, const DevCard& cd, int q, double dc[6],
+                                      double dcf[9]) {
+  if (q < 9) {
+    const int i = q / 3, j = q % 3;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        dcf[3 * a + c] = b.Fe[3 * i + a] * b.G[3 * c + j] + b.G[3 * a + j] * b.Fe[3 * i + c];
+  } else {
+    const int k = q - 9;
+    double dU[9], Q[9], X[9];
+    full_from_sym(cd.dU[k], dU);
+    mm(b.G, dU, Q);
+    mm(Q, b.C, X);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dcf[3 * a + c] = -(X[3 * a + c] + X[3 * c + a]);
+  }
+  dc[0] = dcf[0]; dc[1] = dcf[4]; dc[2] = dcf[8];
+  dc[3] = dcf[5]; dc[4] = dcf[2]; dc[5] = dcf[1];
+}
+
+__device__ __forceinline__ double neg_part(double x) { return x < 0.0 ? x : 0.0; }
+
+// Gradient of the local density: g[15].
+__device__ __forceinline__ void local_gradient(const double F[9], const double eh[6], const double ehn[6],
+                                               const DevCard& cd, double g[15]) {
+  LocalBase b;
+  local_base(F, eh, cd, b);
+#pragma unroll
+  for (int q = 0; q < 15; ++q) {
+    double dc[6], dcf[9];
+    dC_of(b, cd, q, dc, dcf);
+    double wq = 0.0;
+#pragma unroll
+    for (int v = 0; v < 6; ++v) wq += b.wC[v] * dc[v];
+    if (q < 9) {
+      g[q] = b.Jt * wq;
+    } else {
+      const int k = q - 9;
+      double dU[9], Q[9];
+      full_from_sym(cd.dU[k], dU);
+      mm(b.G, dU, Q);
+      const double trQ = Q[0] + Q[4] + Q[8];
+      g[q] = b.Jt * (wq + b.wEta[k]) + b.Jt * trQ * b.w;
+    }
+  }
+  // order-parameter terms: chemical, double obstacle, viscous, penalty
+  double eta[7], etan[7];
+  double s = 0.0, sn = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) { eta[k + 1] = eh[k]; etan[k + 1] = ehn[k]; s += eh[k]; sn += ehn[k]; }
+  eta[0] = 1.0 - s;
+  etan[0] = 1.0 - sn;
+  double We[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) t += cd.W[i][j] * eta[j];
+    We[i] = t;
+  }
+  const double d0 = eta[0] - etan[0];
+  const double n0 = neg_part(eta[0]);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    g[9 + k] += cd.dF0[k] + (We[k + 1] - We[0]) + cd.rho * ((eta[k + 1] - etan[k + 1]) - d0)
+                + cd.eps * (neg_part(eta[k + 1]) - n0);
+  }
+}
+
+// Gradient and packed upper-triangular Hessian D[120] of the local density.
+__device__ __forceinline__ void local_hessian(const double F[9], const double eh[6], const double ehn[6],
+                                              const DevCard& cd, double g[15], double D[120]) {
+  LocalBase b;
+  local_base(F, eh, cd, b);
+  // ---- second derivatives in C-space -------------------------------------
+  double wCC[6][6];
+  double wCeta[6][6];  // [v][k]
+  {
+    double Lm[6][6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        double s = cd.L0[i][j];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s += eh[k] * cd.dL[k][i][j];
+        Lm[i][j] = s;
+      }
+    // Y = T B^-1, Z = (3/2 I - H) Y
+    double Tf[9], Ts[6] = {b.T[0], b.T[1], b.T[2], b.T[3], b.T[4], b.T[5]};
+    full_from_sym(Ts, Tf);
+    double Y[9], HY[9], Z[9];
+    mm(Tf, b.Binv, Y);
+    mm(b.H, Y, HY);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Z[i] = 1.5 * Y[i] - HY[i];
+    // vt[u][v] = (C V_u + V_u C + 4 V_u) : E_v with V_u = dH_u Y
+    double vt[6][6];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      double dHs[6] = {b.dh[u][0], b.dh[u][1], b.dh[u][2],
+                       0.5 * b.dh[u][3], 0.5 * b.dh[u][4], 0.5 * b.dh[u][5]};
+      double dHf[9], V[9], CV[9], VC[9], Vt[9];
+      full_from_sym(dHs, dHf);
+      mm(dHf, Y, V);
+      mm(b.C, V, CV);
+      mm(V, b.C, VC);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Vt[i] = CV[i] + VC[i] + 4.0 * V[i];
+#pragma unroll
+      for (int v = 0; v < 6; ++v) vt[u][v] = contract_basis(Vt, v);
+    }
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      double LdH[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) s += Lm[i][j] * b.dh[u][j];
+        LdH[i] = s;
+      }
+#pragma unroll
+      for (int v = 0; v <= u; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) s += b.dh[v][i] * LdH[i];
+        // Z : (E_u E_v + E_v E_u)
+        double Eu[9], Ev[9], P1[9], P2[9];
+        basis(u, Eu);
+        basis(v, Ev);
+        mm(Eu, Ev, P1);
+        mm(Ev, Eu, P2);
+        double zd = 0.0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) zd += Z[i] * (P1[i] + P2[i]);
+        const double val = s + zd - vt[u][v] - vt[v][u];
+        wCC[u][v] = val;
+        wCC[v][u] = val;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      double dLh[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) s += cd.dL[k][i][j] * b.h[j];
+        dLh[i] = s;
+      }
+#pragma unroll
+      for (int v = 0; v < 6; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) s += dLh[i] * b.dh[v][i];
+        wCeta[v][k] = s;
+      }
+    }
+  }
+  // ---- chain rule ---------------------------------------------------------
+  // S: symmetric tensor with S : dC = sum_v wC_v dc_v
+  double Sf[9];
+  {
+    double Ss[6] = {b.wC[0], b.wC[1], b.wC[2], 0.5 * b.wC[3], 0.5 * b.wC[4], 0.5 * b.wC[5]};
+    full_from_sym(Ss, Sf);
+  }
+  double GS[9], GSG[9];
+  mm(b.G, Sf, GS);
+  mm(GS, b.G, GSG);
+  double dc[15][6];
+  double wq[15];
+  double Jq[6];
+#pragma unroll
+  for (int q = 0; q < 15; ++q) {
+    double dcf[9];
+    dC_of(b, cd, q, dc[q], dcf);
+    double s = 0.0;
+#pragma unroll
+    for (int v = 0; v < 6; ++v) s += b.wC[v] * dc[q][v];
+    wq[q] = s + (q >= 9 ? b.wEta[q - 9] : 0.0);
+  }
+  double Qk[6][9];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    double dU[9];
+    full_from_sym(cd.dU[k], dU);
+    mm(b.G, dU, Qk[k]);
+    Jq[k] = b.Jt * (Qk[k][0] + Qk[k][4] + Qk[k][8]);
+  }
+#pragma unroll
+  for (int q = 0; q < 15; ++q) g[q] = b.Jt * wq[q] + (q >= 9 ? Jq[q - 9] * b.w : 0.0);
+
+  // F-F and F-eta blocks
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    double WCq[6];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      double s = 0.0;
+#pragma unroll
+      for (int v = 0; v < 6; ++v) s += wCC[u][v] * dc[q][v];
+      WCq[u] = s;
+    }
+    const int i = q / 3, j = q % 3;
+#pragma unroll
+    for (int r = q; r < 9; ++r) {
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < 6; ++u) s += WCq[u] * dc[r][u];
+      const int k = r / 3, l = r % 3;
+      if (i == k) s += 2.0 * GSG[3 * j + l];
+      D[hidx(q, r)] = b.Jt * s;
+    }
+    // dC_q as a full matrix for the S : d2C term
+    double dcq[6] = {dc[q][0], dc[q][1], dc[q][2], dc[q][3], dc[q][4], dc[q][5]};
+    double dcqf[9];
+    full_from_sym(dcq, dcqf);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      double P[9];
+      mm(Sf, Qk[k], P);  // S G dU_k
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < 6; ++u) s += WCq[u] * dc[9 + k][u];
+      s += -2.0 * ddot9(P, dcqf);
+#pragma unroll
+      for (int v = 0; v < 6; ++v) s += wCeta[v][k] * dc[q][v];
+      D[hidx(q, 9 + k)] = b.Jt * s + Jq[k] * wq[q];
+    }
+  }
+  // eta-eta block
+  double Rk[6][9], Uk[6][9];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    double SQ[9];
+    mm(Sf, Qk[k], SQ);
+    mm(b.C, SQ, Rk[k]);   // C S Q_k
+    mm(SQ, b.C, Uk[k]);   // S Q_k C
+  }
+  double eta[7], etan[7];
+  {
+    double s = 0.0, sn = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) { eta[k + 1] = eh[k]; etan[k + 1] = ehn[k]; s += eh[k]; sn += ehn[k]; }
+    eta[0] = 1.0 - s;
+    etan[0] = 1.0 - sn;
+  }
+  const double pen0 = (eta[0] < 0.0) ? cd.eps : 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    double WCk[6];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      double s = 0.0;
+#pragma unroll
+      for (int v = 0; v < 6; ++v) s += wCC[u][v] * dc[9 + k][v];
+      WCk[u] = s;
+    }
+    const double trk = Qk[k][0] + Qk[k][4] + Qk[k][8];
+#pragma unroll
+    for (int l = k; l < 6; ++l) {
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < 6; ++u) s += WCk[u] * dc[9 + l][u];
+      s += 2.0 * (trprod(Rk[k], Qk[l]) + trprod(Rk[l], Qk[k]) + ddot9(Uk[k], Qk[l]));
+#pragma unroll
+      for (int v = 0; v < 6; ++v) s += wCeta[v][l] * dc[9 + k][v] + wCeta[v][k] * dc[9 + l][v];
+      const double trl = Qk[l][0] + Qk[l][4] + Qk[l][8];
+      const double Jkl = b.Jt * (trk * trl - trprod(Qk[k], Qk[l]));
+      double val = b.Jt * s + Jq[k] * wq[9 + l] + Jq[l] * wq[9 + k] + Jkl * b.w;
+      // order-parameter terms
+      val += cd.Sw[k][l] + cd.rho * ((k == l ? 1.0 : 0.0) + 1.0) + pen0;
+      if (k == l && eta[k + 1] < 0.0) val += cd.eps;
+      D[hidx(9 + k, 9 + l)] = val;
+    }
+  }
+  // order-parameter gradient terms
+  double We[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) t += cd.W[i][j] * eta[j];
+    We[i] = t;
+  }
+  const double d0 = eta[0] - etan[0];
+  const double n0 = neg_part(eta[0]);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    g[9 + k] += cd.dF0[k] + (We[k + 1] - We[0]) + cd.rho * ((eta[k + 1] - etan[k + 1]) - d0)
+                + cd.eps * (neg_part(eta[k + 1]) - n0);
+  }
+}
+
+}  // namespace mvpf

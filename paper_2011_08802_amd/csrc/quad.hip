@@ -1,0 +1,371 @@
+// Quadrature and assembly kernels (Sec. 3.3-3.4): residual R = dPi/dU and
+// tangent K = d^2 Pi / dU^2 of the discrete potential on Q1 hexahedra with
+// 2x2x2 Gauss points, assembled without atomics:
+//   1. qp_kernel: one thread per (Gauss point, element) evaluates the local
+//      gradient (and Hessian) of the density and stores it (SoA, coalesced);
+//   2. residual_gather: one thread per node sums its <= 8 elements;
+//   3. jacobian_gather: one thread per (node row, stencil neighbour) sums the
+//      <= 8 elements that contain both nodes and writes the 9x9 block into the
+//      tiled BSR layout (64 consecutive rows per wavefront -> coalesced).
+// Summation order is fixed, so results are bitwise reproducible.
+#include "common.h"
+
+namespace mvpf {
+
+// Gauss abscissae on [0,1]: (1 -+ 1/sqrt(3)) / 2
+constexpr double GQ0 = 0.21132486540518711775;
+constexpr double GQ1 = 0.78867513459481288225;
+
+struct Shape {
+  double N;
+  double dN[3];  // reference-cube derivatives (divide by h for physical)
+};
+
+__device__ __forceinline__ Shape shape(int g, int a) {
+  const double x[3] = {(g & 1) ? GQ1 : GQ0, (g & 2) ? GQ1 : GQ0, (g & 4) ? GQ1 : GQ0};
+  double f[3], df[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const bool bit = (a >> d) & 1;
+    f[d] = bit ? x[d] : 1.0 - x[d];
+    df[d] = bit ? 1.0 : -1.0;
+  }
+  Shape s;
+  s.N = f[0] * f[1] * f[2];
+  s.dN[0] = df[0] * f[1] * f[2];
+  s.dN[1] = f[0] * df[1] * f[2];
+  s.dN[2] = f[0] * f[1] * df[2];
+  return s;
+}
+
+// reference Laplacian 1/8 sum_g dN_a(g) . dN_b(g)  (element matrix = h * this)
+__device__ __forceinline__ double lap_ref(int a, int b) {
+  double s = 0.0;
+#pragma unroll
+  for (int g = 0; g < 8; ++g) {
+    const Shape sa = shape(g, a), sb = shape(g, b);
+    s += sa.dN[0] * sb.dN[0] + sa.dN[1] * sb.dN[1] + sa.dN[2] * sb.dN[2];
+  }
+  return 0.125 * s;
+}
+
+template <bool HESS>
+__global__ void __launch_bounds__(128) qp_kernel(Grid g, const double* __restrict__ state,
+                                                 const DevCard* __restrict__ cd, double* __restrict__ qp) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int gp = (int)(tid / g.NEpad);
+  const int e = (int)(tid - (int64_t)gp * g.NEpad);
+  if (gp >= 8 || e >= g.NE) return;
+  const int ex = e % g.nx, ey = (e / g.nx) % g.ny, ez = e / (g.nx * g.ny);
+  const double ih = 1.0 / g.h;
+  double F[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  double eh[6] = {0, 0, 0, 0, 0, 0}, ehn[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int node = (ex + (a & 1)) + g.nnx * ((ey + ((a >> 1) & 1)) + g.nny * (ez + ((a >> 2) & 1)));
+    const Shape s = shape(gp, a);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double u = state[(int64_t)i * g.Npad + node];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) F[3 * i + j] += u * s.dN[j] * ih;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      eh[k] += s.N * state[(int64_t)(3 + k) * g.Npad + node];
+      ehn[k] += s.N * state[(int64_t)(9 + k) * g.Npad + node];
+    }
+  }
+  const int64_t stride = (int64_t)8 * g.NEpad;
+  double* out = qp + (int64_t)gp * g.NEpad + e;
+  double gr[15];
+  if (HESS) {
+    double D[120];
+    local_hessian(F, eh, ehn, *cd, gr, D);
+#pragma unroll
+    for (int c = 0; c < 120; ++c) out[(int64_t)(15 + c) * stride] = D[c];
+  } else {
+    local_gradient(F, eh, ehn, *cd, gr);
+  }
+#pragma unroll
+  for (int c = 0; c < 15; ++c) out[(int64_t)c * stride] = gr[c];
+}
+
+void launch_qp(const Grid& g, const double* state, const DevCard* cd, double* qp, bool hess, hipStream_t s) {
+  const int64_t n = (int64_t)8 * g.NEpad;
+  const int bs = 128;
+  const int nb = (int)((n + bs - 1) / bs);
+  if (hess)
+    qp_kernel<true><<<nb, bs, 0, s>>>(g, state, cd, qp);
+  else
+    qp_kernel<false><<<nb, bs, 0, s>>>(g, state, cd, qp);
+}
+
+__global__ void __launch_bounds__(256) residual_gather_kernel(Grid g, const double* __restrict__ state,
+                                                              const double* __restrict__ qp,
+                                                              const DevCard* __restrict__ cd,
+                                                              double* __restrict__ R) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.Npad) return;
+  double r[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (n < g.N) {
+    const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
+    const double cu = g.h * g.h * 0.125, ce = g.h * g.h * g.h * 0.125;
+    const int64_t stride = (int64_t)8 * g.NEpad;
+    for (int a = 0; a < 8; ++a) {
+      const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+      const int ex = i - ax, ey = j - ay, ez = k - az;
+      if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || ez < 0 || ez >= g.nz) continue;
+      const int e = ex + g.nx * (ey + g.ny * ez);
+#pragma unroll
+      for (int gp = 0; gp < 8; ++gp) {
+        const Shape s = shape(gp, a);
+        const double* q = qp + (int64_t)gp * g.NEpad + e;
+#pragma unroll
+        for (int i3 = 0; i3 < 3; ++i3)
+          r[i3] += cu * (s.dN[0] * q[(3 * i3 + 0) * stride] + s.dN[1] * q[(3 * i3 + 1) * stride] +
+                         s.dN[2] * q[(3 * i3 + 2) * stride]);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) r[3 + m] += ce * s.N * q[(9 + m) * stride];
+      }
+      // gradient energy 1/2 Mg_kl grad eta_k . grad eta_l: h * Lap_ab * Mg * eta_b
+      for (int b = 0; b < 8; ++b) {
+        const int nb = (ex + (b & 1)) + g.nnx * ((ey + ((b >> 1) & 1)) + g.nny * (ez + ((b >> 2) & 1)));
+        const double lap = g.h * lap_ref(a, b);
+        double eb[6];
+#pragma unroll
+        for (int l = 0; l < 6; ++l) eb[l] = state[(int64_t)(3 + l) * g.Npad + nb];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          double s2 = 0.0;
+#pragma unroll
+          for (int l = 0; l < 6; ++l) s2 += cd->Mg[m][l] * eb[l];
+          r[3 + m] += lap * s2;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 9; ++c) R[(int64_t)c * g.Npad + n] = r[c];
+}
+
+void launch_residual_gather(const Grid& g, const double* state, const double* qp, const DevCard* cd, double* R,
+                            hipStream_t s) {
+  residual_gather_kernel<<<(g.Npad + 255) / 256, 256, 0, s>>>(g, state, qp, cd, R);
+}
+
+// Logical block index with the 8 XCDs of the chip in mind: hardware places
+// workgroup b on XCD b % 8; consecutive logical ids (the 27 stencil blocks of
+// one 64-node tile) are kept on one XCD so they share its L2.
+__device__ __forceinline__ int xcd_logical(int b, int nb_pad) {
+  const int per = nb_pad >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+__global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, const double* __restrict__ qp,
+                                                             const DevCard* __restrict__ cd,
+                                                             double* __restrict__ A64, float* __restrict__ A32,
+                                                             double* __restrict__ diag64, int nblocks) {
+  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  if (L >= nblocks) return;
+  const int t = L / NSTEN, sten = L - t * NSTEN;
+  const int l = threadIdx.x;
+  const int n = t * TILE + l;
+  const int dx = sten % 3 - 1, dy = (sten / 3) % 3 - 1, dz = sten / 9 - 1;
+  double K[81];
+#pragma unroll
+  for (int e = 0; e < 81; ++e) K[e] = 0.0;
+  if (n < g.N) {
+    const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
+    const bool valid = (i + dx >= 0) && (i + dx < g.nnx) && (j + dy >= 0) && (j + dy < g.nny) &&
+                       (k + dz >= 0) && (k + dz < g.nnz);
+    if (valid) {
+      const double cuu = g.h * 0.125, cue = g.h * g.h * 0.125, cee = g.h * g.h * g.h * 0.125;
+      const int64_t stride = (int64_t)8 * g.NEpad;
+      for (int a = 0; a < 8; ++a) {
+        const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+        const int bx = ax + dx, by = ay + dy, bz = az + dz;
+        if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;  // wave-uniform
+        const int ex = i - ax, ey = j - ay, ez = k - az;
+        if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || ez < 0 || ez >= g.nz) continue;
+        const int b = bx + 2 * by + 4 * bz;
+        const int e = ex + g.nx * (ey + g.ny * ez);
+        for (int gp = 0; gp < 8; ++gp) {
+          const Shape sa = shape(gp, a), sb = shape(gp, b);
+          const double* q = qp + (int64_t)gp * g.NEpad + e + (int64_t)15 * stride;
+          // u-u block: K[i3][k3] += h/8 sum_jl dNa_j dNb_l D(3i3+j, 3k3+l)
+          {
+            double P[9];
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+              for (int ll = 0; ll < 3; ++ll) P[3 * jj + ll] = cuu * sa.dN[jj] * sb.dN[ll];
+#pragma unroll
+            for (int i3 = 0; i3 < 3; ++i3)
+#pragma unroll
+              for (int k3 = 0; k3 < 3; ++k3) {
+                double s = 0.0;
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+                  for (int ll = 0; ll < 3; ++ll) {
+                    const int p = 3 * i3 + jj, r = 3 * k3 + ll;
+                    const int pq = p <= r ? hidx(p, r) : hidx(r, p);
+                    s += P[3 * jj + ll] * q[(int64_t)pq * stride];
+                  }
+                K[9 * i3 + k3] += s;
+              }
+          }
+          // u-eta and eta-u blocks
+#pragma unroll
+          for (int m = 0; m < 6; ++m) {
+            double Dm[9];
+#pragma unroll
+            for (int p = 0; p < 9; ++p) Dm[p] = q[(int64_t)hidx(p, 9 + m) * stride];
+#pragma unroll
+            for (int i3 = 0; i3 < 3; ++i3) {
+              K[9 * i3 + 3 + m] += cue * sb.N *
+                                   (sa.dN[0] * Dm[3 * i3] + sa.dN[1] * Dm[3 * i3 + 1] + sa.dN[2] * Dm[3 * i3 + 2]);
+              K[9 * (3 + m) + i3] += cue * sa.N *
+                                     (sb.dN[0] * Dm[3 * i3] + sb.dN[1] * Dm[3 * i3 + 1] + sb.dN[2] * Dm[3 * i3 + 2]);
+            }
+          }
+          // eta-eta block
+          const double nn = cee * sa.N * sb.N;
+#pragma unroll
+          for (int m = 0; m < 6; ++m)
+#pragma unroll
+            for (int m2 = 0; m2 < 6; ++m2) {
+              const int p = 9 + m, r = 9 + m2;
+              const int pq = p <= r ? hidx(p, r) : hidx(r, p);
+              K[9 * (3 + m) + 3 + m2] += nn * q[(int64_t)pq * stride];
+            }
+        }
+        // gradient energy: h * Lap_ab * Mg
+        const double lap = g.h * lap_ref(a, b);
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+#pragma unroll
+          for (int m2 = 0; m2 < 6; ++m2) K[9 * (3 + m) + 3 + m2] += lap * cd->Mg[m][m2];
+      }
+    }
+  }
+  const int64_t base = ((int64_t)(t * NSTEN + sten) * NBLK) * TILE + l;
+  if (A64) {
+#pragma unroll
+    for (int e = 0; e < 81; ++e) A64[base + (int64_t)e * TILE] = K[e];
+  }
+  if (A32) {
+#pragma unroll
+    for (int e = 0; e < 81; ++e) A32[base + (int64_t)e * TILE] = (float)K[e];
+  }
+  if (sten == 13 && diag64) {
+    const int64_t db = (int64_t)t * NBLK * TILE + l;
+#pragma unroll
+    for (int e = 0; e < 81; ++e) diag64[db + (int64_t)e * TILE] = K[e];
+  }
+}
+
+void launch_jacobian_gather(const Grid& g, const double* qp, const DevCard* cd, double* A64, float* A32,
+                            double* diag64, hipStream_t s) {
+  const int nblocks = g.ntiles * NSTEN;
+  const int nb_pad = (nblocks + 7) / 8 * 8;
+  jacobian_gather_kernel<<<nb_pad, TILE, 0, s>>>(g, qp, cd, A64, A32, diag64, nblocks);
+}
+
+__global__ void __launch_bounds__(64) apply_dirichlet_kernel(Grid g, const uint16_t* __restrict__ mask,
+                                                             double* __restrict__ A64, float* __restrict__ A32,
+                                                             double* __restrict__ diag64, int nblocks) {
+  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  if (L >= nblocks) return;
+  const int t = L / NSTEN, sten = L - t * NSTEN;
+  const int l = threadIdx.x;
+  const int n = t * TILE + l;
+  if (n >= g.N) return;
+  const int dx = sten % 3 - 1, dy = (sten / 3) % 3 - 1, dz = sten / 9 - 1;
+  const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
+  if (i + dx < 0 || i + dx >= g.nnx || j + dy < 0 || j + dy >= g.nny || k + dz < 0 || k + dz >= g.nnz) return;
+  const int m = n + dx + g.nnx * (dy + g.nny * dz);
+  const unsigned mr = mask[n], mc = mask[m];
+  if ((mr | mc) == 0) return;
+  const int64_t base = ((int64_t)(t * NSTEN + sten) * NBLK) * TILE + l;
+  const int64_t db = (int64_t)t * NBLK * TILE + l;
+  for (int e = 0; e < 81; ++e) {
+    const int r = e / 9, c = e % 9;
+    if (((mr >> r) & 1) || ((mc >> c) & 1)) {
+      const double v = (sten == 13 && r == c) ? 1.0 : 0.0;
+      if (A64) A64[base + (int64_t)e * TILE] = v;
+      if (A32) A32[base + (int64_t)e * TILE] = (float)v;
+      if (sten == 13 && diag64) diag64[db + (int64_t)e * TILE] = v;
+    }
+  }
+}
+
+void launch_apply_dirichlet(const Grid& g, const uint16_t* mask, double* A64, float* A32, double* diag64,
+                            hipStream_t s) {
+  const int nblocks = g.ntiles * NSTEN;
+  const int nb_pad = (nblocks + 7) / 8 * 8;
+  apply_dirichlet_kernel<<<nb_pad, TILE, 0, s>>>(g, mask, A64, A32, diag64, nblocks);
+}
+
+// 9x9 inverse by Gauss-Jordan elimination with partial pivoting (the paper's
+// point-block Jacobi inverts each block by LU with partial pivoting).  Each
+// thread keeps its augmented [A | I] in LDS, lane-interleaved.
+constexpr int BI_THREADS = 32;  // 32 x 9 x 18 doubles = 41 KB of LDS per block
+
+__global__ void __launch_bounds__(BI_THREADS) block_inverse_kernel(Grid g, const double* __restrict__ diag64,
+                                                                   double* __restrict__ Dinv64,
+                                                                   float* __restrict__ Dinv32, int* status) {
+  __shared__ double M[9 * 18 * BI_THREADS];
+  const int n = blockIdx.x * BI_THREADS + threadIdx.x;
+  const int t = n / TILE, l = n % TILE, lt = threadIdx.x;
+  if (n >= g.Npad) return;
+  const int64_t db = (int64_t)t * NBLK * TILE + l;
+#define MM(r, c) M[((r) * 18 + (c)) * BI_THREADS + lt]
+  bool ok = n < g.N;
+  if (ok) {
+    for (int r = 0; r < 9; ++r)
+      for (int c = 0; c < 9; ++c) {
+        MM(r, c) = diag64[db + (int64_t)(9 * r + c) * TILE];
+        MM(r, 9 + c) = (r == c) ? 1.0 : 0.0;
+      }
+    for (int c = 0; c < 9; ++c) {
+      int p = c;
+      double best = fabs(MM(c, c));
+      for (int r = c + 1; r < 9; ++r) {
+        const double v = fabs(MM(r, c));
+        if (v > best) { best = v; p = r; }
+      }
+      if (!(best > 0.0)) { ok = false; break; }
+      if (p != c)
+        for (int cc = 0; cc < 18; ++cc) {
+          const double tmp = MM(c, cc);
+          MM(c, cc) = MM(p, cc);
+          MM(p, cc) = tmp;
+        }
+      const double ip = 1.0 / MM(c, c);
+      for (int cc = 0; cc < 18; ++cc) MM(c, cc) *= ip;
+      for (int r = 0; r < 9; ++r) {
+        if (r == c) continue;
+        const double f = MM(r, c);
+        if (f != 0.0)
+          for (int cc = 0; cc < 18; ++cc) MM(r, cc) -= f * MM(c, cc);
+      }
+    }
+    if (!ok) atomicOr(status, 1);
+  }
+  for (int e = 0; e < 81; ++e) {
+    const double v = ok ? MM(e / 9, 9 + e % 9) : 0.0;
+    if (Dinv64) Dinv64[db + (int64_t)e * TILE] = v;
+    if (Dinv32) Dinv32[db + (int64_t)e * TILE] = (float)v;
+  }
+#undef MM
+}
+
+void launch_block_inverse(const Grid& g, const double* diag64, double* Dinv64, float* Dinv32, int* status,
+                          hipStream_t s) {
+  block_inverse_kernel<<<(g.Npad + BI_THREADS - 1) / BI_THREADS, BI_THREADS, 0, s>>>(g, diag64, Dinv64, Dinv32,
+                                                                                      status);
+}
+
+}  // namespace mvpf

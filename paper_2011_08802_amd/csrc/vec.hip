@@ -1,0 +1,390 @@
+// Vector kernels: FGMRES reductions (wavefront shuffles + LDS, two-stage,
+// deterministic), layout conversions, boundary conditions, state updates.
+#include "common.h"
+
+namespace mvpf {
+
+constexpr int RB = 256;  // reduction block size
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
+  __syncthreads();
+  return r;  // valid in thread 0
+}
+
+int red_blocks(int64_t n) {
+  const int64_t b = (n + 4095) / 4096;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 1024));
+}
+
+// part[j * nblk + blk] = sum over the block's chunk of V_j . w, j < k
+__global__ void __launch_bounds__(RB) multidot_kernel(int64_t n, const double* __restrict__ V, int64_t ldv, int k,
+                                                      const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double sh[RB / 64];
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = std::min<int64_t>(n, lo + chunk);
+  for (int j = 0; j < k; ++j) {
+    const double* vj = V + (int64_t)j * ldv;
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += RB) s += vj[i] * w[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+void launch_multidot(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part, hipStream_t s) {
+  multidot_kernel<<<red_blocks(n), RB, 0, s>>>(n, V, ldv, k, w, part);
+}
+
+// out[j] (+)= sum_b part[j * nblk + b]
+__global__ void __launch_bounds__(RB) reduce_kernel(int nblk, const double* __restrict__ part, double* __restrict__ out,
+                                                    int accumulate) {
+  __shared__ double sh[RB / 64];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += RB) s += part[(int64_t)j * nblk + b];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[j] = accumulate ? out[j] + s : s;
+}
+
+void launch_reduce(int k, int nblk, const double* part, double* out, int accumulate, hipStream_t s) {
+  reduce_kernel<<<k, RB, 0, s>>>(nblk, part, out, accumulate);
+}
+
+// w -= sum_j h_j V_j ; optional part_norm[blk] = sum of w^2 over the chunk
+__global__ void __launch_bounds__(RB) multiaxpy_kernel(int64_t n, const double* __restrict__ V, int64_t ldv, int k,
+                                                       const double* __restrict__ h, double* __restrict__ w,
+                                                       double* __restrict__ part_norm) {
+  __shared__ double sh[RB / 64];
+  __shared__ double hs[MAX_RESTART + 2];
+  for (int j = threadIdx.x; j < k; j += RB) hs[j] = h[j];
+  __syncthreads();
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = std::min<int64_t>(n, lo + chunk);
+  double nrm = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += RB) {
+    double s = w[i];
+    for (int j = 0; j < k; ++j) s -= hs[j] * V[(int64_t)j * ldv + i];
+    w[i] = s;
+    nrm += s * s;
+  }
+  if (part_norm) {
+    nrm = block_sum(nrm, sh);
+    if (threadIdx.x == 0) part_norm[blockIdx.x] = nrm;
+  }
+}
+
+void launch_multiaxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w, double* part_norm,
+                      hipStream_t s) {
+  multiaxpy_kernel<<<red_blocks(n), RB, 0, s>>>(n, V, ldv, k, h, w, part_norm);
+}
+
+__global__ void __launch_bounds__(RB) scale_kernel(int64_t n, const double* __restrict__ w, const double* beta,
+                                                   double* __restrict__ v) {
+  const double ib = 1.0 / beta[0];
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) v[i] = w[i] * ib;
+}
+
+void launch_scale(int64_t n, const double* w, const double* beta, double* v, hipStream_t s) {
+  scale_kernel<<<1024, RB, 0, s>>>(n, w, beta, v);
+}
+
+// x += sum_j y_j Z_j
+template <typename TZ>
+__global__ void __launch_bounds__(RB) combine_kernel(int64_t n, const TZ* __restrict__ Z, int64_t ldz, int k,
+                                                     const double* __restrict__ y, double* __restrict__ x) {
+  __shared__ double ys[MAX_RESTART + 2];
+  for (int j = threadIdx.x; j < k; j += RB) ys[j] = y[j];
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
+    double s = x[i];
+    for (int j = 0; j < k; ++j) s += ys[j] * (double)Z[(int64_t)j * ldz + i];
+    x[i] = s;
+  }
+}
+
+template <typename TZ>
+void launch_combine(int64_t n, const TZ* Z, int64_t ldz, int k, const double* y, double* x, hipStream_t s) {
+  combine_kernel<TZ><<<1024, RB, 0, s>>>(n, Z, ldz, k, y, x);
+}
+template void launch_combine<float>(int64_t, const float*, int64_t, int, const double*, double*, hipStream_t);
+template void launch_combine<double>(int64_t, const double*, int64_t, int, const double*, double*, hipStream_t);
+
+// z = a x + b y (y may be null when b == 0)
+__global__ void __launch_bounds__(RB) axpby_kernel(int64_t n, double a, const double* __restrict__ x, double b,
+                                                   const double* __restrict__ y, double* __restrict__ z) {
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB)
+    z[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+
+void launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* z, hipStream_t s) {
+  axpby_kernel<<<1024, RB, 0, s>>>(n, a, x, b, y, z);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RB) zero_kernel(int64_t n, T* p) {
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) p[i] = (T)0;
+}
+
+template <typename T>
+void launch_zero(int64_t n, T* p, hipStream_t s) {
+  zero_kernel<T><<<1024, RB, 0, s>>>(n, p);
+}
+template void launch_zero<float>(int64_t, float*, hipStream_t);
+template void launch_zero<double>(int64_t, double*, hipStream_t);
+
+// ---- layout conversions ---------------------------------------------------
+// out[(comp0 + c) * Npad + n] = in[n * ldc + c], c < ncomp  (out is SoA)
+__global__ void __launch_bounds__(RB) i2s_kernel(Grid g, const double* __restrict__ in, int ncomp, int comp0,
+                                                 int ldc, double* __restrict__ out) {
+  const int n = blockIdx.x * RB + threadIdx.x;
+  if (n >= g.Npad) return;
+  for (int c = 0; c < ncomp; ++c)
+    out[(int64_t)(comp0 + c) * g.Npad + n] = (n < g.N) ? in[(int64_t)n * ldc + c] : 0.0;
+}
+
+void launch_interleaved_to_soa(const Grid& g, const double* in, int ncomp, int comp0, int ldc, double* out,
+                               hipStream_t s) {
+  i2s_kernel<<<(g.Npad + RB - 1) / RB, RB, 0, s>>>(g, in, ncomp, comp0, ldc, out);
+}
+
+__global__ void __launch_bounds__(RB) s2i_kernel(Grid g, const double* __restrict__ in, int ncomp, int comp0,
+                                                 int ldc, double* __restrict__ out) {
+  const int n = blockIdx.x * RB + threadIdx.x;
+  if (n >= g.N) return;
+  for (int c = 0; c < ncomp; ++c) out[(int64_t)n * ldc + c] = in[(int64_t)(comp0 + c) * g.Npad + n];
+}
+
+void launch_soa_to_interleaved(const Grid& g, const double* in, int ncomp, int comp0, int ldc, double* out,
+                               hipStream_t s) {
+  s2i_kernel<<<(g.Npad + RB - 1) / RB, RB, 0, s>>>(g, in, ncomp, comp0, ldc, out);
+}
+
+// out = in with constrained dofs (and padding) zeroed, converted to TO
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(RB) convert_masked_kernel(Grid g, const TI* __restrict__ in,
+                                                            const uint16_t* __restrict__ mask, TO* __restrict__ out) {
+  const int n = blockIdx.x * RB + threadIdx.x;
+  if (n >= g.Npad) return;
+  const unsigned m = (n < g.N) ? mask[n] : 0x1ff;
+#pragma unroll
+  for (int c = 0; c < 9; ++c)
+    out[(int64_t)c * g.Npad + n] = ((m >> c) & 1) ? (TO)0 : (TO)in[(int64_t)c * g.Npad + n];
+}
+
+template <typename TI, typename TO>
+void launch_convert_masked(const Grid& g, const TI* in, const uint16_t* mask, TO* out, hipStream_t s) {
+  convert_masked_kernel<TI, TO><<<(g.Npad + RB - 1) / RB, RB, 0, s>>>(g, in, mask, out);
+}
+template void launch_convert_masked<double, float>(const Grid&, const double*, const uint16_t*, float*, hipStream_t);
+template void launch_convert_masked<double, double>(const Grid&, const double*, const uint16_t*, double*,
+                                                    hipStream_t);
+template void launch_convert_masked<float, float>(const Grid&, const float*, const uint16_t*, float*, hipStream_t);
+template void launch_convert_masked<float, double>(const Grid&, const float*, const uint16_t*, double*, hipStream_t);
+
+// dst[c][n] = src[c][n] on constrained dofs (the preconditioner is the
+// identity there); src FP64, dst FP64
+__global__ void __launch_bounds__(RB) set_constrained_kernel(Grid g, const uint16_t* __restrict__ mask,
+                                                             const double* __restrict__ src, double* __restrict__ dst) {
+  const int n = blockIdx.x * RB + threadIdx.x;
+  if (n >= g.N) return;
+  const unsigned m = mask[n];
+  if (!m) return;
+#pragma unroll
+  for (int c = 0; c < 9; ++c)
+    if ((m >> c) & 1) dst[(int64_t)c * g.Npad + n] = src[(int64_t)c * g.Npad + n];
+}
+
+void launch_set_constrained(const Grid& g, const uint16_t* mask, const double* src, double* dst, hipStream_t s) {
+  set_constrained_kernel<<<(g.Npad + RB - 1) / RB, RB, 0, s>>>(g, mask, src, dst);
+}
+
+// ---- boundary conditions and Newton updates ---------------------------------
+__global__ void __launch_bounds__(RB) dirichlet_masks_kernel(Grid g, int kind, int patch, double radius, double depth,
+                                                             uint16_t* __restrict__ mask, double* __restrict__ target) {
+  const int n = blockIdx.x * RB + threadIdx.x;
+  if (n >= g.Npad) return;
+  unsigned m = 0;
+  double t = 0.0;
+  if (n < g.N) {
+    const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
+    if (k == 0) m |= 7u;                 // bottom face: u = 0
+    if (k == g.nz) {                     // top face
+      if (kind == MVPF_LOAD_PATCH) {
+        const int hp = patch / 2;
+        if (abs(i - g.nx / 2) <= hp && abs(j - g.ny / 2) <= hp) {
+          m |= 4u;
+          t = -depth;
+        }
+      } else {
+        const double x = i * g.h - 0.5 * g.nx * g.h, y = j * g.h - 0.5 * g.ny * g.h;
+        const double r2 = x * x + y * y;
+        if (r2 < 2.0 * radius * depth - depth * depth) {
+          m |= 4u;
+          t = -(depth - (radius - sqrt(radius * radius - r2)));
+        }
+      }
+    }
+  }
+  mask[n] = (uint16_t)m;
+  target[n] = t;
+}
+
+void launch_dirichlet_masks(const Grid& g, const mvpf_loading& ld, double depth, uint16_t* mask, double* target,
+                            hipStream_t s) {
+  dirichlet_masks_kernel<<<(g.Npad + RB - 1) / RB, RB, 0, s>>>(g, ld.kind, ld.patch, ld.radius, depth, mask, target);
+}
+
+// g = target - current on constrained displacement dofs, 0 elsewhere
+__global__ void __launch_bounds__(RB) increment_kernel(Grid g, const uint16_t* __restrict__ mask,
+                                                       const double* __restrict__ target,
+                                                       const double* __restrict__ state, double* __restrict__ gv) {
+  const int n = blockIdx.x * RB + threadIdx.x;
+  if (n >= g.Npad) return;
+  const unsigned m = (n < g.N) ? mask[n] : 0;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    double v = 0.0;
+    if ((m >> c) & 1) v = (c == 2 ? target[n] : 0.0) - state[(int64_t)c * g.Npad + n];
+    gv[(int64_t)c * g.Npad + n] = v;
+  }
+}
+
+void launch_increment(const Grid& g, const uint16_t* mask, const double* target, const double* state, double* gvec,
+                      hipStream_t s) {
+  increment_kernel<<<(g.Npad + RB - 1) / RB, RB, 0, s>>>(g, mask, target, state, gvec);
+}
+
+// rhs = g on constrained dofs, -R - K g elsewhere
+__global__ void __launch_bounds__(RB) newton_rhs_kernel(Grid g, const uint16_t* __restrict__ mask,
+                                                        const double* __restrict__ R, const double* __restrict__ Kg,
+                                                        const double* __restrict__ gv, double* __restrict__ rhs) {
+  const int n = blockIdx.x * RB + threadIdx.x;
+  if (n >= g.Npad) return;
+  const unsigned m = (n < g.N) ? mask[n] : 0;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    const int64_t q = (int64_t)c * g.Npad + n;
+    rhs[q] = (n >= g.N) ? 0.0 : (((m >> c) & 1) ? gv[q] : -R[q] - Kg[q]);
+  }
+}
+
+void launch_newton_rhs(const Grid& g, const uint16_t* mask, const double* R, const double* Kg, const double* gvec,
+                       double* rhs, hipStream_t s) {
+  newton_rhs_kernel<<<(g.Npad + RB - 1) / RB, RB, 0, s>>>(g, mask, R, Kg, gvec, rhs);
+}
+
+// U <- U + dx on free dofs; constrained dofs set to their targets
+__global__ void __launch_bounds__(RB) state_update_kernel(Grid g, const uint16_t* __restrict__ mask,
+                                                          const double* __restrict__ target,
+                                                          const double* __restrict__ dx, double* __restrict__ st) {
+  const int n = blockIdx.x * RB + threadIdx.x;
+  if (n >= g.N) return;
+  const unsigned m = mask[n];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    const int64_t q = (int64_t)c * g.Npad + n;
+    st[q] = ((m >> c) & 1) ? (c == 2 ? target[n] : 0.0) : st[q] + dx[q];
+  }
+}
+
+void launch_state_update(const Grid& g, const uint16_t* mask, const double* target, const double* dx, double* state,
+                         hipStream_t s) {
+  state_update_kernel<<<(g.Npad + RB - 1) / RB, RB, 0, s>>>(g, mask, target, dx, state);
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(RB) init_random_kernel(Grid g, uint64_t seed, double* __restrict__ st) {
+  const int n = blockIdx.x * RB + threadIdx.x;
+  if (n >= g.Npad) return;
+  for (int c = 0; c < 3; ++c) st[(int64_t)c * g.Npad + n] = 0.0;
+  for (int i = 0; i < 6; ++i) {
+    double v = 0.0;
+    if (n < g.N) {
+      const uint64_t r = splitmix64(seed ^ (uint64_t)(9ull * (uint64_t)n + 3ull + (uint64_t)i));
+      v = 0.05 * ((double)(r >> 11) * 0x1.0p-53);
+    }
+    st[(int64_t)(3 + i) * g.Npad + n] = v;
+    st[(int64_t)(9 + i) * g.Npad + n] = v;
+  }
+}
+
+void launch_init_random(const Grid& g, uint64_t seed, double* state, hipStream_t s) {
+  init_random_kernel<<<(g.Npad + RB - 1) / RB, RB, 0, s>>>(g, seed, state);
+}
+
+__global__ void __launch_bounds__(RB) free_norm_kernel(Grid g, const double* __restrict__ v,
+                                                       const uint16_t* __restrict__ mask, double* __restrict__ part) {
+  __shared__ double sh[RB / 64];
+  double s = 0.0;
+  for (int n = blockIdx.x * RB + threadIdx.x; n < g.N; n += gridDim.x * RB) {
+    const unsigned m = mask[n];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      const double x = v[(int64_t)c * g.Npad + n];
+      if (!((m >> c) & 1)) s += x * x;
+    }
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_free_norm_partial(const Grid& g, const double* v, const uint16_t* mask, double* part, hipStream_t s) {
+  free_norm_kernel<<<red_blocks((int64_t)g.N * 9), RB, 0, s>>>(g, v, mask, part);
+}
+
+// flat type conversion out[i] = (TO) in[i]
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(RB) convert_kernel(int64_t n, const TI* __restrict__ in, TO* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) out[i] = (TO)in[i];
+}
+
+template <typename TI, typename TO>
+void launch_convert(int64_t n, const TI* in, TO* out, hipStream_t s) {
+  convert_kernel<TI, TO><<<1024, RB, 0, s>>>(n, in, out);
+}
+template void launch_convert<float, double>(int64_t, const float*, double*, hipStream_t);
+template void launch_convert<double, float>(int64_t, const double*, float*, hipStream_t);
+
+// Preconditioner output: z = V-cycle result on free dofs, z = v on
+// constrained dofs of the finest level (identity there).
+template <typename T, typename TZ>
+__global__ void __launch_bounds__(RB) precond_finish_kernel(Grid g, const T* __restrict__ x,
+                                                            const double* __restrict__ v,
+                                                            const uint16_t* __restrict__ mask, TZ* __restrict__ z) {
+  const int n = blockIdx.x * RB + threadIdx.x;
+  if (n >= g.Npad) return;
+  const unsigned m = (n < g.N) ? mask[n] : 0;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    const int64_t q = (int64_t)c * g.Npad + n;
+    z[q] = ((m >> c) & 1) ? (TZ)v[q] : (TZ)x[q];
+  }
+}
+
+template <typename T, typename TZ>
+void launch_precond_finish(const Grid& g, const T* x, const double* v, const uint16_t* mask, TZ* z, hipStream_t s) {
+  precond_finish_kernel<T, TZ><<<(g.Npad + RB - 1) / RB, RB, 0, s>>>(g, x, v, mask, z);
+}
+template void launch_precond_finish<float, float>(const Grid&, const float*, const double*, const uint16_t*, float*,
+                                                  hipStream_t);
+template void launch_precond_finish<float, double>(const Grid&, const float*, const double*, const uint16_t*,
+                                                   double*, hipStream_t);
+template void launch_precond_finish<double, double>(const Grid&, const double*, const double*, const uint16_t*,
+                                                    double*, hipStream_t);
+
+}  // namespace mvpf

@@ -1,0 +1,260 @@
+"""ctypes binding of libmvpf (include/mvpf.h): argument marshalling only.
+
+Every computation runs in the HIP library; PyTorch supplies device memory
+(CUDA/HIP tensors) and the stream.  ``Problem`` methods map one-to-one onto the
+C calls: ``Problem.X(...)`` calls ``mvpf_X`` on the handle.  If the library is
+not built, ``load()`` raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmvpf.so")
+
+FP64, MIXED = 0, 1
+LOAD_PATCH, LOAD_CAP = 0, 1
+OK, ENOTCONV = 0, 1
+MAX_COARSE_DOF = 8192
+
+_ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESINGULAR", -5: "ESTATE", 1: "ENOTCONV"}
+
+
+class MvpfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mvpf error {_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Mesh(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("h", C.c_double), ("n_levels", C.c_int)]
+
+
+class Material(C.Structure):
+    _fields_ = [("cubic", C.c_double * 3), ("ortho", C.c_double * 9), ("alpha", C.c_double),
+                ("beta", C.c_double), ("gamma", C.c_double), ("Q", C.c_double * 9), ("F0", C.c_double * 7),
+                ("w_am", C.c_double), ("w_mm", C.c_double), ("ell", C.c_double), ("rho", C.c_double),
+                ("eps_eta", C.c_double), ("pade", C.c_int)]
+
+
+class Loading(C.Structure):
+    _fields_ = [("kind", C.c_int), ("patch", C.c_int), ("radius", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("rtol", C.c_double), ("restart", C.c_int), ("max_it", C.c_int),
+                ("nu_pre", C.c_int), ("nu_post", C.c_int), ("omega", C.c_double), ("newton_max", C.c_int),
+                ("newton_rtol", C.c_double)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("rel_residual", C.c_double), ("solve_ms", C.c_double)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("newton_iterations", C.c_int), ("linear_iterations", C.c_int), ("halvings", C.c_int),
+                ("converged", C.c_int), ("residual0", C.c_double), ("residual", C.c_double),
+                ("assemble_ms", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_levels", C.c_int), ("nx", C.c_int * 8), ("ny", C.c_int * 8), ("nz", C.c_int * 8),
+                ("n_nodes", C.c_int64 * 8), ("bytes_device", C.c_int64)]
+
+
+# exported symbols: name -> (restype, argtypes)
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+SIGNATURES = {
+    "mvpf_default_opts": (None, [C.POINTER(Opts)]),
+    "mvpf_create": (C.c_int, [C.POINTER(Mesh), C.POINTER(Material), C.POINTER(Loading), C.POINTER(Opts), _P,
+                              C.POINTER(_P)]),
+    "mvpf_destroy": (None, [_P]),
+    "mvpf_last_error": (C.c_char_p, [_P]),
+    "mvpf_get_info": (C.c_int, [_P, C.POINTER(Info)]),
+    "mvpf_set_opts": (C.c_int, [_P, C.POINTER(Opts)]),
+    "mvpf_set_state": (C.c_int, [_P, _P, _P, _P, C.c_double]),
+    "mvpf_get_state": (C.c_int, [_P, _P, _P, _P, _D]),
+    "mvpf_init_random": (C.c_int, [_P, C.c_uint64]),
+    "mvpf_residual": (C.c_int, [_P, _P, _D]),
+    "mvpf_newton_system": (C.c_int, [_P, C.c_double]),
+    "mvpf_get_rhs": (C.c_int, [_P, _P]),
+    "mvpf_jacobian_apply": (C.c_int, [_P, C.c_int, C.c_int, _P, _P]),
+    "mvpf_precondition": (C.c_int, [_P, _P, _P]),
+    "mvpf_solve": (C.c_int, [_P, _P, _P, C.POINTER(SolveStats)]),
+    "mvpf_newton_update": (C.c_int, [_P]),
+    "mvpf_time_step": (C.c_int, [_P, C.c_double, C.POINTER(StepStats)]),
+    "mvpf_kernel_timing": (C.c_int, [_P, C.c_int]),
+    "mvpf_kernel_stats": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int), _D, _D]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libmvpf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise MvpfError(-3, f"{path} not found: build it with __graft_entry__.build()")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def material_struct(mp) -> Material:
+    m = Material()
+    m.cubic[:] = list(mp.cubic)
+    m.ortho[:] = list(mp.ortho)
+    m.alpha, m.beta, m.gamma = mp.alpha, mp.beta, mp.gamma
+    m.Q[:] = list(mp.Q)
+    m.F0[:] = list(mp.F0)
+    m.w_am, m.w_mm, m.ell, m.rho, m.eps_eta, m.pade = mp.w_am, mp.w_mm, mp.ell, mp.rho, mp.eps_eta, mp.pade
+    return m
+
+
+def default_opts() -> Opts:
+    o = Opts()
+    load().mvpf_default_opts(C.byref(o))
+    return o
+
+
+class Problem:
+    """One indentation problem on the GPU (handle of mvpf_create)."""
+
+    def __init__(self, prob, precision: str = "fp64", device: int = 0, **opts):
+        lib = load()
+        self.lib = lib
+        self.prob = prob
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.current_stream(self.device)
+        mesh = Mesh(prob.nx, prob.ny, prob.nz, prob.lx / prob.nx, prob.n_levels)
+        ld = Loading(LOAD_PATCH if prob.kind == "patch" else LOAD_CAP, prob.patch, prob.radius)
+        o = default_opts()
+        o.precision = MIXED if precision == "mixed" else FP64
+        for k, v in opts.items():
+            setattr(o, k, v)
+        self.opts = o
+        self.mat = material_struct(prob.material)
+        h = C.c_void_p()
+        rc = lib.mvpf_create(C.byref(mesh), C.byref(self.mat), C.byref(ld), C.byref(o),
+                             C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != 0:
+            raise MvpfError(rc, lib.mvpf_last_error(None).decode())
+        self.h = h
+        self.n_nodes = prob.n_nodes
+
+    def _check(self, rc, allow=(OK,)):
+        if rc not in allow:
+            raise MvpfError(rc, self.lib.mvpf_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mvpf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, n_nodes=None, comps=9):
+        return torch.zeros((n_nodes or self.n_nodes) * comps, dtype=torch.float64, device=self.device)
+
+    def info(self) -> Info:
+        i = Info()
+        self._check(self.lib.mvpf_get_info(self.h, C.byref(i)))
+        return i
+
+    def set_opts(self, **kw):
+        for k, v in kw.items():
+            setattr(self.opts, k, v)
+        self._check(self.lib.mvpf_set_opts(self.h, C.byref(self.opts)))
+
+    def set_state(self, u=None, eta=None, eta_prev=None, depth=0.0):
+        def dev(a):
+            if a is None:
+                return None
+            return torch.as_tensor(a, dtype=torch.float64).to(self.device).contiguous().reshape(-1)
+        u, eta, eta_prev = dev(u), dev(eta), dev(eta_prev)
+        self._check(self.lib.mvpf_set_state(self.h, _ptr(u), _ptr(eta), _ptr(eta_prev), depth))
+
+    def get_state(self):
+        u, e, en = self._vec(comps=3), self._vec(comps=6), self._vec(comps=6)
+        d = C.c_double()
+        self._check(self.lib.mvpf_get_state(self.h, _ptr(u), _ptr(e), _ptr(en), C.byref(d)))
+        return u.view(-1, 3), e.view(-1, 6), en.view(-1, 6), d.value
+
+    def init_random(self, seed: int):
+        self._check(self.lib.mvpf_init_random(self.h, C.c_uint64(seed)))
+
+    def residual(self):
+        R = self._vec()
+        nf = C.c_double()
+        self._check(self.lib.mvpf_residual(self.h, _ptr(R), C.byref(nf)))
+        return R, nf.value
+
+    def newton_system(self, depth: float):
+        self._check(self.lib.mvpf_newton_system(self.h, depth))
+
+    def get_rhs(self):
+        b = self._vec()
+        self._check(self.lib.mvpf_get_rhs(self.h, _ptr(b)))
+        return b
+
+    def jacobian_apply(self, level: int, x: torch.Tensor, precision: int = FP64):
+        y = torch.zeros_like(x)
+        self._check(self.lib.mvpf_jacobian_apply(self.h, level, precision, _ptr(x), _ptr(y)))
+        return y
+
+    def precondition(self, v: torch.Tensor):
+        z = torch.zeros_like(v)
+        self._check(self.lib.mvpf_precondition(self.h, _ptr(v), _ptr(z)))
+        return z
+
+    def solve(self, b: Optional[torch.Tensor] = None, want_x: bool = True):
+        x = self._vec() if want_x else None
+        st = SolveStats()
+        self._check(self.lib.mvpf_solve(self.h, _ptr(b), _ptr(x), C.byref(st)), allow=(OK, ENOTCONV))
+        return x, st
+
+    def newton_update(self):
+        self._check(self.lib.mvpf_newton_update(self.h))
+
+    def time_step(self, depth: float):
+        st = StepStats()
+        self._check(self.lib.mvpf_time_step(self.h, depth, C.byref(st)), allow=(OK, ENOTCONV))
+        return st
+
+    def kernel_timing(self, enable: bool):
+        self._check(self.lib.mvpf_kernel_timing(self.h, int(enable)))
+
+    def kernel_stats(self, name: str):
+        n, ms, by = C.c_int(), C.c_double(), C.c_double()
+        self._check(self.lib.mvpf_kernel_stats(self.h, name.encode(), C.byref(n), C.byref(ms), C.byref(by)))
+        return n.value, ms.value, by.value
+
+
+def stats_dict(st) -> dict:
+    return {f: getattr(st, f) for f, _ in st._fields_}

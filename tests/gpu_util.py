@@ -1,0 +1,63 @@
+"""Shared setup for the GPU parity tests: seeded states and the oracle's
+counterparts (oracle = CPU reference, test infrastructure only)."""
+import os
+import sys
+
+import numpy as np
+
+import synth
+from oracle import solver as S
+from oracle.fem import Discretisation, Mesh, NDOF
+from oracle.material import Card
+
+
+def say(msg):
+    """Progress line naming the case, flushed before the GPU work starts."""
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def seeded_state(p, u_amp=0.0, seed=7):
+    """(U (n,9), Eta_n (n,6)): eta_hat from the problem seed (splitmix64),
+    optional small random displacement field (numpy PCG64 with ``seed``)."""
+    m = Mesh.from_problem(p)
+    U = np.zeros((m.n_nodes, NDOF))
+    U[:, 3:] = p.eta0()
+    if u_amp:
+        U[:, :3] = u_amp * np.random.default_rng(seed).standard_normal((m.n_nodes, 3))
+    return U, U[:, 3:].copy()
+
+
+class OracleCase:
+    """Oracle Newton system + multigrid for one problem/state/depth."""
+
+    def __init__(self, p, U, En, depth, build_mg=True, direct=True):
+        self.p = p
+        self.card = Card(p.material)
+        self.mesh = Mesh.from_problem(p)
+        self.U, self.En = U, En
+        self.mask, self.target = S.dirichlet(self.mesh, p.kind, p.patch, p.radius, depth=depth)
+        self.g = S.increment(self.mask, self.target, U)
+        self.sys = S.NewtonSystem(p, self.card, U.ravel(), En.ravel(), self.mask, self.g)
+        self.mg = S.Multigrid(p, self.card, U.ravel(), En.ravel(), self.mask, K_fine=self.sys.K) if build_mg else None
+        self.x = S.direct_solve(self.sys.A, self.sys.b) if direct else None
+
+
+def gpu_problem(p, U, En, precision="fp64", depth=0.0, **opts):
+    from paper_2011_08802_amd import mvpf
+    gp = mvpf.Problem(p, precision, **opts)
+    gp.set_state(U[:, :3], U[:, 3:], En, depth)
+    return gp
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=float).ravel()
+    b = np.asarray(b, dtype=float).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def rel_blocks(a, b):
+    """Relative errors of the displacement and order-parameter parts."""
+    a = np.asarray(a).reshape(-1, NDOF)
+    b = np.asarray(b).reshape(-1, NDOF)
+    return rel(a[:, :3], b[:, :3]), rel(a[:, 3:], b[:, 3:])

@@ -1,0 +1,76 @@
+"""The C-ABI library loads and exports every symbol declared in include/mvpf.h;
+argument validation errors come back without touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mvpf.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mvpf_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2011_08802_amd import mvpf
+    return mvpf.load()
+
+
+def test_every_declared_symbol_is_exported_and_bound(lib):
+    from paper_2011_08802_amd import mvpf
+    names = declared()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(mvpf.SIGNATURES)
+
+
+def test_default_opts(lib):
+    from paper_2011_08802_amd import mvpf
+    o = mvpf.default_opts()
+    assert o.precision == mvpf.FP64 and o.rtol == 1e-8 and o.restart == 30 and o.omega == 0.5
+    assert o.nu_pre == 2 and o.nu_post == 2 and o.newton_max == 12
+
+
+def _create(lib, mesh, mat=None, load=None, opts=None):
+    from paper_2011_08802_amd import mvpf
+    mat = mat or mvpf.material_struct(synth.config_material())
+    load = load or mvpf.Loading(mvpf.LOAD_PATCH, 2, 0.2)
+    opts = opts or mvpf.default_opts()
+    h = C.c_void_p()
+    rc = lib.mvpf_create(C.byref(mesh), C.byref(mat), C.byref(load), C.byref(opts), None, C.byref(h))
+    return rc, h, lib.mvpf_last_error(None).decode()
+
+
+@pytest.mark.parametrize("mesh,msg", [
+    ((8, 8, 6, 0.125, 3), "divisible"),      # 6 not divisible by 4
+    ((8, 8, 8, 0.125, 1), "n_levels"),
+    ((8, 8, 8, -1.0, 3), "mesh"),
+    ((64, 64, 64, 1 / 64, 2), "coarsest"),   # 33^3 * 9 unknowns on the coarsest level
+])
+def test_create_rejects_bad_mesh(lib, mesh, msg):
+    from paper_2011_08802_amd import mvpf
+    rc, h, err = _create(lib, mvpf.Mesh(*mesh))
+    assert rc == -1 and not h.value and msg in err
+
+
+def test_create_rejects_bad_options(lib):
+    from paper_2011_08802_amd import mvpf
+    o = mvpf.default_opts()
+    o.restart = 100
+    rc, h, err = _create(lib, mvpf.Mesh(8, 8, 8, 0.125, 3), opts=o)
+    assert rc == -1 and "Krylov" in err
+    mat = mvpf.material_struct(synth.config_material())
+    mat.pade = 33
+    rc, h, err = _create(lib, mvpf.Mesh(8, 8, 8, 0.125, 3), mat=mat)
+    assert rc == -1 and "Pade" in err
+    rc, h, err = _create(lib, mvpf.Mesh(8, 8, 8, 0.125, 3), load=mvpf.Loading(mvpf.LOAD_PATCH, 3, 0.2))
+    assert rc == -1 and "patch" in err

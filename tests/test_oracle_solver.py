@@ -16,13 +16,15 @@ def _tiny(n=4, levels=2, patch=2, depth=0.02, eta_offset=0.0):
     U = np.zeros((m.n_nodes, NDOF))
     U[:, 3:] = eta_offset + p.eta0()
     En = U[:, 3:].ravel().copy()
-    mask, g = S.dirichlet(m, "patch", p.patch, depth=p.depth_increment)
+    mask, target = S.dirichlet(m, "patch", p.patch, depth=p.depth_increment)
+    g = S.increment(mask, target, U)
     return p, card, m, U.ravel(), En, mask, g
 
 
 def test_dirichlet_sets():
     m = Mesh(8, 8, 8, 0.125)
     mask, g = S.dirichlet(m, "patch", 2, depth=0.02)
+    assert np.array_equal(S.increment(mask, g, np.zeros((m.n_nodes, NDOF))), g)
     i, j, k = m.node_ijk(np.arange(m.n_nodes))
     assert mask[k == 0][:, :3].all() and not mask[k == 0][:, 3:].any()
     top = np.nonzero(mask[:, 2] & (k == 8))[0]
@@ -32,6 +34,23 @@ def test_dirichlet_sets():
     cmask = S.coarse_mask(m, mask, cm)
     ci, cj, ck = cm.node_ijk(np.arange(cm.n_nodes))
     assert np.nonzero(cmask[:, 2] & (ck == 4))[0].tolist() == [cm.node_id(2, 2, 4)]
+
+
+def test_cap_profile():
+    """Spherical cap: contact radius sqrt(2Rd - d^2); the centre node sits at
+    -d and the profile follows the sphere R - sqrt(R^2 - r^2) - d."""
+    m = Mesh(16, 16, 8, 1.0 / 16)
+    R, d = 0.2, 0.02
+    mask, t = S.dirichlet(m, "cap", radius=R, depth=d)
+    i, j, k = m.node_ijk(np.arange(m.n_nodes))
+    top = np.nonzero(mask[:, 2] & (k == 8))[0]
+    r = np.hypot(i[top] / 16 - 0.5, j[top] / 16 - 0.5)
+    assert r.max() < np.sqrt(2 * R * d - d * d)
+    assert np.isclose(t[m.node_id(8, 8, 8), 2], -d)
+    x, z = r, t[top, 2] + d            # indenter surface height above its tip
+    assert np.allclose((R - z) ** 2 + x ** 2, R * R)
+    # contact radius 0.0872 > h = 0.0625 but < h*sqrt2: centre + 4 edge neighbours
+    assert len(top) == 5
 
 
 def test_prolongation_exact_on_trilinear_fields():
