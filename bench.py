@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Newton-step benchmark on one MI355X.
+
+A step is one full Newton iteration of the indentation problem: residual and
+tangent reassembled on every multigrid level at the injected state, block
+inverses and coarse factorisation, FGMRES + geometric-multigrid solve to a
+1e-8 relative FP64 residual, state update.  The state is restored from a
+device-resident copy before every step, so each step solves the same (first,
+lifted) Newton system of the first load step.
+
+Default workload: 64^3 hex elements (274,625 nodes, 2,471,625 dof), 5 levels,
+8x8-element patch pushed 0.01, initial eta from seed 20110880.  The headline
+value is the FP32-multigrid (mixed) path; the all-FP64 multigrid path is timed
+on the same system and reported beside it.
+
+Prints one JSON line (see the README/DESIGN for the fields).
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+import synth  # noqa: E402
+
+METRIC = "Newton-step solve time & DOF/s at 1e-8 rel. residual, FP32-GMG vs FP64 GMG"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "tiny": synth.tiny,
+    "medium": synth.medium,
+    "large": synth.large,
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_precision(prob, precision, steps, warmup, timing):
+    from paper_2011_08802_amd import mvpf
+    gp = mvpf.Problem(prob, precision, rtol=1e-8)
+    gp.init_random(prob.seed)
+    u0, e0, en0, _ = gp.get_state()
+    u0, e0, en0 = u0.clone(), e0.clone(), en0.clone()
+    depth = prob.depth_increment
+
+    def step(rec):
+        gp.set_state(u0, e0, en0, 0.0)
+        t0 = time.perf_counter()
+        gp.newton_system(depth)
+        t1 = time.perf_counter()
+        x, st = gp.solve(want_x=False)
+        t2 = time.perf_counter()
+        gp.newton_update()
+        if rec is not None:
+            rec.append(dict(system_ms=1e3 * (t1 - t0), solve_ms=st.solve_ms, its=st.iterations,
+                            rel_res=st.rel_residual, converged=st.converged))
+
+    for _ in range(warmup):
+        step(None)
+    recs = []
+    if timing:
+        gp.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(recs)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    kstats = {}
+    if timing:
+        for name in ("pbj_sweep", "residual", "spmv_outer"):
+            n, ms, by = gp.kernel_stats(name)
+            if n:
+                kstats[name] = dict(launches=n, avg_ms=ms / n, bytes=by, gbs=by / (ms / n) / 1e6)
+        gp.kernel_timing(False)
+    # solution of the (same) Newton system for the error statement
+    gp.set_state(u0, e0, en0, 0.0)
+    gp.newton_system(depth)
+    x, st = gp.solve()
+    gp.close()
+    return dict(total_s=total, recs=recs, kernels=kstats, x=x.cpu().numpy())
+
+
+def cpu_baseline(n=16, levels=4):
+    """The oracle (test infrastructure) on a bounded sample of the workload:
+    one Newton iteration (autodiff assembly of the tangent, multigrid setup,
+    FGMRES+GMG to 1e-8) of the same indentation problem at n^3 elements."""
+    from oracle import solver as S
+    from oracle.fem import Mesh, NDOF
+    from oracle.material import Card
+    threads = min(16, os.cpu_count() or 1)
+    torch.set_num_threads(threads)
+    p = synth.Problem(n, n, n, n_levels=levels, patch=max(2, n // 8), depth_increment=0.01)
+    card = Card(p.material)
+    m = Mesh.from_problem(p)
+    U = np.zeros((m.n_nodes, NDOF))
+    U[:, 3:] = p.eta0()
+    mask, target = S.dirichlet(m, "patch", p.patch, depth=p.depth_increment)
+    t0 = time.perf_counter()
+    sysk = S.NewtonSystem(p, card, U.ravel(), U[:, 3:].ravel().copy(), mask, S.increment(mask, target, U))
+    mg = S.Multigrid(p, card, U.ravel(), U[:, 3:].ravel().copy(), mask, K_fine=sysk.K)
+    t1 = time.perf_counter()
+    x, st = S.fgmres(sysk.A, sysk.b, mg.precondition, rtol=1e-8)
+    t2 = time.perf_counter()
+    return dict(value=p.n_dof / (t2 - t0), unit="DOF/s", cores=threads, kind="oracle",
+                sample=f"one Newton iteration of the patch-indentation workload at {n}^3 elements "
+                       f"({p.n_dof} dof, {levels} levels): autodiff assembly + MG setup {t1 - t0:.1f} s, "
+                       f"FGMRES+GMG {st.iterations} its {t2 - t1:.1f} s",
+                solve_dof_per_s=p.n_dof / (t2 - t1), iterations=st.iterations)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="medium", choices=list(WORKLOADS))
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-multigrid comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    a = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the solve would shard)", file=sys.stderr)
+        sys.exit(2)
+    prob = WORKLOADS[a.workload]()
+    ndof = prob.n_dof
+    log(f"[bench] workload {a.workload}: {prob.nx}x{prob.ny}x{prob.nz}, {ndof} dof, {prob.n_levels} levels")
+    log("[bench] mixed (FP32 multigrid) ...")
+    mixed = run_precision(prob, "mixed", a.steps, a.warmup, not a.no_timing)
+    fp64 = None
+    if not a.no_fp64:
+        log("[bench] fp64 multigrid ...")
+        fp64 = run_precision(prob, "fp64", a.steps, a.warmup, False)
+
+    def summary(r):
+        recs = r["recs"]
+        solve_ms = statistics.median(x["solve_ms"] for x in recs)
+        return dict(ms_per_step=1e3 * r["total_s"] / len(recs), solve_ms_median=solve_ms,
+                    solve_dof_per_s=ndof / (solve_ms / 1e3),
+                    system_ms_median=statistics.median(x["system_ms"] for x in recs),
+                    fgmres_iterations=[x["its"] for x in recs],
+                    rel_residual_max=max(x["rel_res"] for x in recs),
+                    converged=all(x["converged"] for x in recs))
+
+    ms = summary(mixed)
+    out = {
+        "metric": METRIC,
+        "value": ndof * a.steps / mixed["total_s"],
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"patch indentation {prob.nx}x{prob.ny}x{prob.nz} Q1 hex, "
+                               f"{ndof} dof, {prob.n_levels}-level GMG V(2,2), FGMRES(30) rtol 1e-8",
+                   "nx": prob.nx, "ny": prob.ny, "nz": prob.nz, "levels": prob.n_levels,
+                   "depth": prob.depth_increment, "seed": prob.seed, "precision": "mixed"},
+        "mixed": ms,
+    }
+    if fp64 is not None:
+        fs = summary(fp64)
+        out["fp64_gmg"] = fs
+        out["fp64_gmg"]["value"] = ndof * a.steps / fp64["total_s"]
+        out["speedup_solve_mixed_vs_fp64"] = fs["solve_ms_median"] / ms["solve_ms_median"]
+        out["speedup_step_mixed_vs_fp64"] = fs["ms_per_step"] / ms["ms_per_step"]
+        out["mixed_vs_fp64_solution_rel_diff"] = float(
+            np.linalg.norm(mixed["x"] - fp64["x"]) / np.linalg.norm(fp64["x"]))
+    k = mixed["kernels"].get("pbj_sweep")
+    if k:
+        out["roofline"] = {"bound": "hbm", "achieved": k["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": k["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "pbj_kernel<float,false> (finest level)",
+                           "bytes_per_launch": k["bytes"], "avg_ms": k["avg_ms"], "launches": k["launches"]}
+        out["kernels"] = mixed["kernels"]
+    if not a.no_cpu_baseline:
+        log("[bench] oracle cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
