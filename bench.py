@@ -44,13 +44,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_precision(prob, precision, steps, warmup, timing):
+def run_precision(prob, precision, steps, warmup, timing, tune=True):
     from paper_2011_08802_amd import mvpf
     gp = mvpf.Problem(prob, precision, rtol=1e-8)
     gp.init_random(prob.seed)
     u0, e0, en0, _ = gp.get_state()
     u0, e0, en0 = u0.clone(), e0.clone(), en0.clone()
     depth = prob.depth_increment
+    shapes = None
+    if tune:  # untimed setup: pick launch shapes on this Newton system
+        gp.newton_system(depth)
+        shapes = gp.autotune()
 
     def step(rec):
         gp.set_state(u0, e0, en0, 0.0)
@@ -87,7 +91,7 @@ def run_precision(prob, precision, steps, warmup, timing):
     gp.newton_system(depth)
     x, st = gp.solve()
     gp.close()
-    return dict(total_s=total, recs=recs, kernels=kstats, x=x.cpu().numpy())
+    return dict(total_s=total, recs=recs, kernels=kstats, x=x.cpu().numpy(), shapes=shapes)
 
 
 def cpu_baseline(n=16, levels=4):
@@ -127,21 +131,30 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-multigrid comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    ap.add_argument("--no-tune", action="store_true", help="default launch shapes (no autotuning)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first run an elementwise copy of this many MiB (counter calibration)")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the solve would shard)", file=sys.stderr)
         sys.exit(2)
+    if a.calib_copy_mb:
+        x = torch.ones(a.calib_copy_mb << 18, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        del x, y
     prob = WORKLOADS[a.workload]()
     ndof = prob.n_dof
     log(f"[bench] workload {a.workload}: {prob.nx}x{prob.ny}x{prob.nz}, {ndof} dof, {prob.n_levels} levels")
     log("[bench] mixed (FP32 multigrid) ...")
-    mixed = run_precision(prob, "mixed", a.steps, a.warmup, not a.no_timing)
+    mixed = run_precision(prob, "mixed", a.steps, a.warmup, not a.no_timing, not a.no_tune)
     fp64 = None
     if not a.no_fp64:
         log("[bench] fp64 multigrid ...")
-        fp64 = run_precision(prob, "fp64", a.steps, a.warmup, False)
+        fp64 = run_precision(prob, "fp64", a.steps, a.warmup, False, not a.no_tune)
 
     def summary(r):
         recs = r["recs"]
@@ -154,6 +167,7 @@ def main():
                     converged=all(x["converged"] for x in recs))
 
     ms = summary(mixed)
+    ms["launch_shapes"] = mixed["shapes"]
     out = {
         "metric": METRIC,
         "value": ndof * a.steps / mixed["total_s"],
@@ -175,6 +189,7 @@ def main():
     }
     if fp64 is not None:
         fs = summary(fp64)
+        fs["launch_shapes"] = fp64["shapes"]
         out["fp64_gmg"] = fs
         out["fp64_gmg"]["value"] = ndof * a.steps / fp64["total_s"]
         out["speedup_solve_mixed_vs_fp64"] = fs["solve_ms_median"] / ms["solve_ms_median"]

@@ -228,6 +228,24 @@ int mvpf_newton_update(mvpf_problem* p);
  * eta_hat_n <- eta_hat and the depth is advanced. */
 int mvpf_time_step(mvpf_problem* p, double depth, mvpf_step_stats* stats);
 
+/* Launch-shape tuning (results are bitwise independent of it).  key
+ * "row_blocks": number of 256-thread workgroups of the smoother and defect
+ * kernels on `level` (0 = one workgroup per 256 rows; fewer makes each
+ * workgroup loop over rows in rounds, which keeps the rows in flight within
+ * cache reach of each other); "outer_blocks": the same for the outer FP64
+ * operator product (level ignored); "small_grid_nodes": levels with at most
+ * this many nodes use the latency-oriented small-grid smoother and defect
+ * kernels (27 threads per row; default 40000; level ignored).  The two kernel
+ * families sum the 27 block products in different orders, so this key alone
+ * changes results at rounding level; the others never do. */
+int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value);
+int mvpf_get_tuning(const mvpf_problem* p, const char* key, int level, int* value);
+/* Time candidate launch shapes of the smoother (every level but the coarsest)
+ * and of the outer product on the operators of the last mvpf_newton_system,
+ * and keep the fastest.  row_blocks_out (nullable, n_levels ints): chosen
+ * values per level, the last entry being the outer product's. */
+int mvpf_autotune(mvpf_problem* p, int* row_blocks_out);
+
 /* Per-kernel device timing with HIP events on the problem's stream.  name:
  * "pbj_sweep" (finest-level smoother sweep), "spmv_outer" (finest FP64
  * operator product), "residual" (finest defect).  enable != 0 starts

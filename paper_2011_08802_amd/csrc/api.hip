@@ -255,15 +255,18 @@ void timer_collect(mvpf_problem* p, KernelTimer& t) {
   t.used = 0;
 }
 
-// Exact count of in-grid (node, neighbour) pairs of the 27-point stencil.
+// Exact count of in-grid (node, neighbour) pairs of the 27-point stencil, and
+// of the stored half (diagonal + upper blocks) that the symmetric operator
+// must read from memory.
 double stencil_blocks(const Grid& g) {
   return (3.0 * g.nx + 1.0) * (3.0 * g.ny + 1.0) * (3.0 * g.nz + 1.0);
 }
+double stored_blocks(const Grid& g) { return 0.5 * (stencil_blocks(g) + g.N); }
 
 // Algorithmic bytes of one damped point-block Jacobi sweep on level g.
 template <typename T>
 double sweep_bytes(const Grid& g) {
-  return sizeof(T) * (stencil_blocks(g) * NBLK + (double)g.N * (NBLK + 3 * NDOF));
+  return sizeof(T) * (stored_blocks(g) * NBLK + (double)g.N * (NBLK + 3 * NDOF));
 }
 
 // ---- V-cycle ------------------------------------------------------------------
@@ -273,7 +276,11 @@ void sweep(mvpf_problem* p, int l, bool zero) {
   const T om = (T)p->opts.omega;
   const bool timed = (l == 0 && !zero);
   if (timed) timer_begin(p, p->t_sweep);
-  launch_pbj<T>(L.g, opA<T>(L), opD<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.x2, om, zero, p->stream);
+  if (!zero && L.g.N <= p->small_nodes)
+    launch_row_small<T>(L.g, opA<T>(L), opD<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.x2, om, true, p->stream);
+  else
+    launch_pbj<T>(L.g, opA<T>(L), opD<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.x2, om, zero, p->Cbuf, p->stream,
+                  p->row_G[l]);
   if (timed) timer_end(p, p->t_sweep, sweep_bytes<T>(L.g));
   std::swap(L.x, L.x2);
 }
@@ -293,9 +300,12 @@ void vcycle(mvpf_problem* p, int l) {
     launch_zero<T>(nvec(L.g), (T*)L.x, s);
   }
   if (l == 0 && p->timing) timer_begin(p, p->t_resid);
-  launch_defect<T>(L.g, opA<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.r, s);
+  if (L.g.N <= p->small_nodes)
+    launch_row_small<T>(L.g, opA<T>(L), opD<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.r, (T)0, false, s);
+  else
+    launch_defect<T>(L.g, opA<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.r, p->Cbuf, s, p->row_G[l]);
   if (l == 0 && p->timing)
-    timer_end(p, p->t_resid, sizeof(T) * (stencil_blocks(L.g) * NBLK + (double)L.g.N * 3 * NDOF));
+    timer_end(p, p->t_resid, sizeof(T) * (stored_blocks(L.g) * NBLK + (double)L.g.N * 3 * NDOF));
   Level& C = p->lev[l + 1];
   launch_restrict<T>(L.g, C.g, (const T*)L.r, C.mask, (T*)C.b, s);
   vcycle<T>(p, l + 1);
@@ -368,10 +378,10 @@ int fgmres(mvpf_problem* p, const double* b, double* x, mvpf_solve_stats* st) {
       TZ* zj = Z + (int64_t)j * n;
       precondition<T, TZ>(p, vj, zj);
       if (p->timing) timer_begin(p, p->t_outer);
-      launch_spmv<double, TZ, double>(g, p->lev[0].A64, zj, w, s);
+      launch_spmv<double, TZ, double>(g, p->lev[0].A64, zj, w, p->Cbuf, s, p->outer_G);
       if (p->timing)
         timer_end(p, p->t_outer,
-                  8.0 * stencil_blocks(g) * NBLK + (double)g.N * NDOF * (sizeof(TZ) + sizeof(double)));
+                  8.0 * stored_blocks(g) * NBLK + (double)g.N * NDOF * (sizeof(TZ) + sizeof(double)));
       launch_multidot(n, V, n, j + 1, w, p->red, s);
       launch_reduce(j + 1, nb, p->red, h1, 0, s);
       launch_multiaxpy(n, V, n, j + 1, h1, w, nullptr, s);
@@ -409,7 +419,7 @@ int fgmres(mvpf_problem* p, const double* b, double* x, mvpf_solve_stats* st) {
     HIPCHK(hipMemcpyAsync(h1, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
     launch_combine<TZ>(n, Z, n, k, h1, x, s);
     // true residual r = b - A x
-    launch_spmv<double, double, double>(g, p->lev[0].A64, x, p->tmp, s);
+    launch_spmv<double, double, double>(g, p->lev[0].A64, x, p->tmp, p->Cbuf, s, p->outer_G);
     launch_axpby(n, 1.0, b, -1.0, p->tmp, p->tmp, s);
     TRY(norm_device(p, n, p->tmp, &beta));  // synchronises (y upload complete)
     st->rel_residual = beta / bnorm;
@@ -473,7 +483,7 @@ void destroy_all(mvpf_problem* p) {
     dfree(L.state); dfree(L.mask); dfree(L.target); dfree(L.A64); dfree(L.A32); dfree(L.diag64);
     dfree(L.Dinv64); dfree(L.Dinv32); dfree(L.x); dfree(L.x2); dfree(L.b); dfree(L.r); dfree(L.Ainv);
   }
-  dfree(p->card); dfree(p->qp); dfree(p->R); dfree(p->rhs); dfree(p->gvec); dfree(p->dx); dfree(p->tmp);
+  dfree(p->card); dfree(p->qp); dfree(p->elem); dfree(p->Cbuf); dfree(p->R); dfree(p->rhs); dfree(p->gvec); dfree(p->dx); dfree(p->tmp);
   dfree(p->tmp2); dfree(p->V); dfree(p->Z); dfree(p->red); dfree(p->hcol); dfree(p->save_state);
   if (p->hhost) (void)hipHostFree(p->hhost);
   p->hhost = nullptr;
@@ -491,7 +501,7 @@ int allocate(mvpf_problem* p) {
     L.g = make_grid(M.nx / f, M.ny / f, M.nz / f, M.h * f);
     const bool coarsest = (l == p->L - 1);
     const int64_t nv = nvec(L.g);
-    const int64_t nA = (int64_t)L.g.ntiles * NSTEN * NBLK * TILE;
+    const int64_t nA = (int64_t)L.g.ntiles * NUP * NBLK * TILE;
     const int64_t nD = (int64_t)L.g.ntiles * NBLK * TILE;
     TRY(dalloc(p, &L.state, (size_t)NSTATE * L.g.Npad));
     TRY(dalloc(p, &L.mask, (size_t)L.g.Npad));
@@ -520,6 +530,12 @@ int allocate(mvpf_problem* p) {
   const int64_t n = nvec(g0);
   TRY(dalloc(p, &p->card, 1));
   TRY(dalloc(p, &p->qp, (size_t)QP_HESS * 8 * g0.NEpad));
+  TRY(dalloc(p, &p->elem, (size_t)NPAIR * NBLK * g0.NEpad));
+  {
+    double* cb = nullptr;
+    TRY(dalloc(p, &cb, (size_t)(NUP - 1) * NDOF * g0.Npad));
+    p->Cbuf = cb;
+  }
   for (double** v : {&p->R, &p->rhs, &p->gvec, &p->dx, &p->tmp, &p->tmp2}) TRY(dalloc(p, v, (size_t)n));
   p->restart_cap = p->opts.restart;
   TRY(dalloc(p, &p->V, (size_t)(p->restart_cap + 1) * n));
@@ -573,10 +589,11 @@ int build_system(mvpf_problem* p, double depth) {
   // finest: residual and unconstrained tangent
   launch_qp(L0.g, L0.state, p->card, p->qp, true, s);
   launch_residual_gather(L0.g, L0.state, p->qp, p->card, p->R, s);
-  launch_jacobian_gather(L0.g, p->qp, p->card, L0.A64, L0.A32, L0.diag64, s);
+  launch_element_matrices(L0.g, p->qp, p->card, p->elem, s);
+  launch_jacobian_gather(L0.g, p->elem, L0.A64, L0.A32, L0.diag64, s);
   // lifting of the prescribed increment, then symmetric elimination
   launch_increment(L0.g, L0.mask, L0.target, L0.state, p->gvec, s);
-  launch_spmv<double, double, double>(L0.g, L0.A64, p->gvec, p->tmp, s);
+  launch_spmv<double, double, double>(L0.g, L0.A64, p->gvec, p->tmp, p->Cbuf, s);
   launch_newton_rhs(L0.g, L0.mask, p->R, p->tmp, p->gvec, p->rhs, s);
   launch_apply_dirichlet(L0.g, L0.mask, L0.A64, L0.A32, L0.diag64, s);
   // coarse levels: reassembly at the injected state
@@ -585,7 +602,8 @@ int build_system(mvpf_problem* p, double depth) {
     Level& C = p->lev[l];
     launch_inject(F.g, C.g, F.state, C.state, s);
     launch_qp(C.g, C.state, p->card, p->qp, true, s);
-    launch_jacobian_gather(C.g, p->qp, p->card, C.A64, C.A32, C.diag64, s);
+    launch_element_matrices(C.g, p->qp, p->card, p->elem, s);
+    launch_jacobian_gather(C.g, p->elem, C.A64, C.A32, C.diag64, s);
     launch_apply_dirichlet(C.g, C.mask, C.A64, C.A32, C.diag64, s);
   }
   TRY(launch_check(p, "assembly"));
@@ -603,7 +621,7 @@ int setup_solver(mvpf_problem* p) {
   Level& C = p->lev[p->L - 1];
   const int nd = C.ndense;
   // dense operator in tmp-sized scratch: use V (>= (m+1) * 9 * Npad doubles)
-  const int64_t need = (int64_t)nd * nd + 2 * (int64_t)nd * nd + nd;
+  const int64_t need = (int64_t)nd * nd + (int64_t)(dense_invert_work(nd) / sizeof(double)) + 1;
   const int64_t have = (int64_t)(p->restart_cap + 1) * nvec(p->lev[0].g);
   double* work = nullptr;
   bool own = false;
@@ -647,6 +665,59 @@ int solve_internal(mvpf_problem* p, const double* b, double* x, mvpf_solve_stats
   return rc;
 }
 
+}  // namespace
+
+namespace {
+// time `reps` launches of f on the problem's stream (ms per launch)
+template <typename Fn>
+double time_launches(mvpf_problem* p, int reps, Fn f) {
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  f();  // warm-up
+  (void)hipEventRecord(a, p->stream);
+  for (int i = 0; i < reps; ++i) f();
+  (void)hipEventRecord(b, p->stream);
+  (void)hipEventSynchronize(b);
+  const double ms = elapsed_ms(a, b) / reps;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms;
+}
+
+template <typename T>
+void autotune_levels(mvpf_problem* p, int* tuned) {
+  const int cands[] = {0, 4096, 2048, 1536, 1024, 768, 512, 384, 256, 192, 128, 96, 64};
+  for (int l = 0; l < p->L - 1; ++l) {
+    Level& L = p->lev[l];
+    if (L.g.N <= p->small_nodes) continue;  // small-grid kernels have a fixed shape
+    double best = 1e30;
+    int bestG = 0;
+    for (int G : cands) {
+      const double ms = time_launches(p, 5, [&] {
+        launch_pbj<T>(L.g, opA<T>(L), opD<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.x2, (T)p->opts.omega, false,
+                      p->Cbuf, p->stream, G);
+      });
+      if (ms < best * 0.98) { best = ms; bestG = G; }
+    }
+    p->row_G[l] = bestG;
+    tuned[l] = bestG;
+  }
+  const Grid& g = p->lev[0].g;
+  double best = 1e30;
+  int bestG = 0;
+  for (int G : cands) {
+    const double ms = time_launches(p, 5, [&] {
+      if (p->mixed)
+        launch_spmv<double, float, double>(g, p->lev[0].A64, (const float*)p->Z, p->tmp, p->Cbuf, p->stream, G);
+      else
+        launch_spmv<double, double, double>(g, p->lev[0].A64, p->tmp2, p->tmp, p->Cbuf, p->stream, G);
+    });
+    if (ms < best * 0.98) { best = ms; bestG = G; }
+  }
+  p->outer_G = bestG;
+  tuned[p->L - 1] = bestG;
+}
 }  // namespace
 
 // =============================================================================
@@ -801,11 +872,11 @@ int mvpf_jacobian_apply(mvpf_problem* p, int level, int precision, const double*
   launch_interleaved_to_soa(g, x, 9, 0, 9, p->tmp, s);
   if (precision == MVPF_FP64) {
     if (!L.A64) { p->err = "no FP64 operator on this level"; return MVPF_EINVAL; }
-    launch_spmv<double, double, double>(g, L.A64, p->tmp, p->tmp2, s);
+    launch_spmv<double, double, double>(g, L.A64, p->tmp, p->tmp2, p->Cbuf, s);
   } else if (precision == MVPF_MIXED) {
     if (!L.A32) { p->err = "no FP32 operator on this level"; return MVPF_EINVAL; }
     launch_convert<double, float>(nvec(g), p->tmp, (float*)L.x, s);
-    launch_spmv<float, float, float>(g, L.A32, (const float*)L.x, (float*)L.r, s);
+    launch_spmv<float, float, float>(g, L.A32, (const float*)L.x, (float*)L.r, p->Cbuf, s);
     launch_convert<float, double>(nvec(g), (const float*)L.r, p->tmp2, s);
   } else {
     return MVPF_EINVAL;
@@ -936,6 +1007,52 @@ int mvpf_time_step(mvpf_problem* p, double depth, mvpf_step_stats* stats) {
   (void)hipEventDestroy(b);
   p->have_system = p->have_solution = false;
   return rc;
+}
+
+int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value) {
+  if (!p || !key || value < 0) return MVPF_EINVAL;
+  if (!std::strcmp(key, "row_blocks")) {
+    if (level < 0 || level >= p->L) return MVPF_EINVAL;
+    p->row_G[level] = value;
+  } else if (!std::strcmp(key, "outer_blocks")) {
+    p->outer_G = value;
+  } else if (!std::strcmp(key, "small_grid_nodes")) {
+    p->small_nodes = value;
+  } else {
+    p->err = "unknown tuning key";
+    return MVPF_EINVAL;
+  }
+  return 0;
+}
+
+int mvpf_get_tuning(const mvpf_problem* p, const char* key, int level, int* value) {
+  if (!p || !key || !value) return MVPF_EINVAL;
+  if (!std::strcmp(key, "row_blocks")) {
+    if (level < 0 || level >= p->L) return MVPF_EINVAL;
+    *value = p->row_G[level];
+  } else if (!std::strcmp(key, "outer_blocks")) {
+    *value = p->outer_G;
+  } else if (!std::strcmp(key, "small_grid_nodes")) {
+    *value = p->small_nodes;
+  } else {
+    return MVPF_EINVAL;
+  }
+  return 0;
+}
+
+
+int mvpf_autotune(mvpf_problem* p, int* row_blocks_out) {
+  if (!p) return MVPF_EINVAL;
+  if (!p->have_system) { p->err = "autotune needs a Newton system"; return MVPF_ESTATE; }
+  int tuned[MAX_LEVELS] = {0};
+  if (p->mixed)
+    autotune_levels<float>(p, tuned);
+  else
+    autotune_levels<double>(p, tuned);
+  TRY(launch_check(p, "autotune"));
+  if (row_blocks_out)
+    for (int l = 0; l < p->L; ++l) row_blocks_out[l] = tuned[l];
+  return 0;
 }
 
 int mvpf_kernel_timing(mvpf_problem* p, int enable) {

@@ -1,12 +1,12 @@
 // 9x9-block operator kernels on the structured 27-point stencil.
 //
-// One thread per node row.  The operator is stored tiled structure-of-arrays
-// (64 rows per tile, see common.h), so each of the 27*81 loads of a row is a
-// fully coalesced 64-lane access (256 B in FP32, 512 B in FP64); the vector
-// is stored component-major, so the 9 neighbour values of each stencil point
-// are also coalesced 64-lane loads and largely L1/L2 hits (neighbouring rows
-// share them).  These kernels are HBM-bandwidth bound: per row they move
-// 27*81*sizeof(TA) bytes of operator plus ~10 vector values.
+// One thread per node row.  The operator is stored as symmetric half stencil,
+// tiled structure-of-arrays (64 rows per tile, see common.h), so each operator
+// load of a row is a fully coalesced 64-lane access (256 B in FP32, 512 B in
+// FP64); vectors are component-major, so the 9 values of each neighbour are
+// coalesced loads as well.  These kernels are HBM-bandwidth bound: per row
+// they move 14*81*sizeof(TA) bytes of operator plus ~10 vector values, and
+// 2*13*9 accumulation values for the transposed lower half.
 #include "common.h"
 
 namespace mvpf {
@@ -18,119 +18,315 @@ struct Acc<float> { using type = float; };
 template <>
 struct Acc<double> { using type = double; };
 
-// acc[r] -= sum_s sum_c A(n, s)[r][c] * x[c][n + off(s)]   (SUB) or +=
+// Launch shape of the row kernels.  nb = ceil(Npad / 256) logical blocks of
+// 256 rows.  With G = gridDim.x workgroups (a multiple of 8), workgroup b
+// (which the hardware places on XCD b % 8) handles logical blocks
+// L = r*G + (b % 8)*(G/8) + b/8 for rounds r = 0, 1, ...: within a round each
+// XCD walks a contiguous range of rows, and only G*256 rows are in flight, so
+// the transposed lower-half reads of neighbouring rows hit L2 / the infinity
+// cache.  G >= nb is the plain one-block-per-256-rows launch.
+__host__ __device__ inline int row_blocks(const Grid& g) { return (g.Npad + 255) / 256; }
+inline int row_grid(const Grid& g, int G) {
+  const int nb_pad = (row_blocks(g) + 7) / 8 * 8;
+  if (G <= 0 || G >= nb_pad) return nb_pad;
+  return std::max(8, G / 8 * 8);
+}
+
+#define ROW_LOOP(g)                                                                    \
+  const int nb_ = row_blocks(g);                                                      \
+  const int per_ = gridDim.x >> 3;                                                     \
+  for (int L_ = (blockIdx.x & 7) * per_ + (blockIdx.x >> 3); L_ < nb_; L_ += gridDim.x) \
+    for (int n = L_ * 256 + threadIdx.x, once_ = 1; once_; once_ = 0)
+
+// Symmetric product in two passes, so that every stored block is read from
+// memory exactly once whatever the cache does:
+//  pass 1 (row n): acc_n (-)= sum_u A_u(n) x(n + off_u) over the 14 stored
+//    blocks, and for the 13 off-diagonal ones the transposed contribution
+//    A_u(n)^T x(n) to row m = n + off_u is written to C[u-1][.][m] (each
+//    (u, m) has exactly one writer; lanes write consecutive m);
+//  pass 2 (row m): acc_m (-)= sum_u C[u-1][.][m] over the in-grid lower
+//    neighbours, then the kernel's epilogue (defect, Jacobi update, product).
+// C holds 13 * 9 * Npad values of the accumulation type.
 template <bool SUB, typename TA, typename TX, typename TC>
-__device__ __forceinline__ void row_product(const Grid& g, const TA* __restrict__ A, const TX* __restrict__ x,
-                                            int n, TC acc[9]) {
+__device__ __forceinline__ void upper_pass(const Grid& g, const TA* __restrict__ A, const TX* __restrict__ x, int n,
+                                           TC acc[9], TC* __restrict__ C) {
   const int t = n >> 6, l = n & 63;
   const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
-  const TA* Arow = A + (int64_t)t * NSTEN * NBLK * TILE + l;
+  const int64_t slice = (int64_t)NBLK * TILE;
+  TC xn[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) xn[c] = (TC)x[(int64_t)c * g.Npad + n];
 #pragma unroll 1
-  for (int s = 0; s < NSTEN; ++s) {
+  for (int u = 0; u < NUP; ++u) {
+    const int s = 13 + u;
     const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
-    const bool valid = (i + dx >= 0) && (i + dx < g.nnx) && (j + dy >= 0) && (j + dy < g.nny) &&
-                       (k + dz >= 0) && (k + dz < g.nnz);
-    if (!valid) continue;
+    if (!((i + dx >= 0) && (i + dx < g.nnx) && (j + dy >= 0) && (j + dy < g.nny) && (k + dz < g.nnz))) continue;
     const int m = n + dx + g.nnx * (dy + g.nny * dz);
     TC xv[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) xv[c] = (TC)x[(int64_t)c * g.Npad + m];
-    const TA* Ab = Arow + (int64_t)s * NBLK * TILE;
+    const TA* Ab = A + ((int64_t)t * NUP + u) * slice + l;
+    TC ct[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
       TC sum = 0;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) sum += (TC)Ab[(r * 9 + c) * TILE] * xv[c];
-      if (SUB)
-        acc[r] -= sum;
-      else
-        acc[r] += sum;
+      for (int c = 0; c < 9; ++c) {
+        const TC a = (TC)Ab[(r * 9 + c) * TILE];
+        sum += a * xv[c];
+        ct[c] += a * xn[r];
+      }
+      if (SUB) acc[r] -= sum; else acc[r] += sum;
+    }
+    if (u > 0) {
+      TC* Cu = C + (int64_t)(u - 1) * 9 * g.Npad + m;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) Cu[(int64_t)c * g.Npad] = ct[c];
     }
   }
 }
 
-template <typename TA, typename TX, typename TY>
-__global__ void __launch_bounds__(256) spmv_kernel(Grid g, const TA* __restrict__ A, const TX* __restrict__ x,
-                                                   TY* __restrict__ y) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= g.Npad) return;
-  using TC = typename Acc<TY>::type;
-  TC acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  if (n < g.N) row_product<false>(g, A, x, n, acc);
+template <bool SUB, typename TC>
+__device__ __forceinline__ void lower_pass(const Grid& g, int m, TC acc[9], const TC* __restrict__ C) {
+  const int i = m % g.nnx, j = (m / g.nnx) % g.nny, k = m / (g.nnx * g.nny);
 #pragma unroll
-  for (int r = 0; r < 9; ++r) y[(int64_t)r * g.Npad + n] = (TY)acc[r];
+  for (int u = 1; u < NUP; ++u) {
+    const int s = 13 + u;
+    const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+    if (!((i - dx >= 0) && (i - dx < g.nnx) && (j - dy >= 0) && (j - dy < g.nny) && (k - dz >= 0))) continue;
+    const TC* Cu = C + (int64_t)(u - 1) * 9 * g.Npad + m;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      if (SUB) acc[c] -= Cu[(int64_t)c * g.Npad]; else acc[c] += Cu[(int64_t)c * g.Npad];
+    }
+  }
+}
+
+// y = A x: pass 1 writes the upper part into y, pass 2 adds the lower part.
+template <typename TA, typename TX, typename TY>
+__global__ void __launch_bounds__(256) spmv_upper_kernel(Grid g, const TA* __restrict__ A, const TX* __restrict__ x,
+                                                         TY* __restrict__ y, TY* __restrict__ C) {
+  ROW_LOOP(g) {
+    if (n >= g.Npad) continue;
+    TY acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (n < g.N) upper_pass<false>(g, A, x, n, acc, C);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) y[(int64_t)r * g.Npad + n] = acc[r];
+  }
+}
+
+template <typename TY>
+__global__ void __launch_bounds__(256) spmv_lower_kernel(Grid g, TY* __restrict__ y, const TY* __restrict__ C) {
+  ROW_LOOP(g) {
+    if (n >= g.N) continue;
+    TY acc[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) acc[r] = y[(int64_t)r * g.Npad + n];
+    lower_pass<false>(g, n, acc, C);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) y[(int64_t)r * g.Npad + n] = acc[r];
+  }
 }
 
 template <typename TA, typename TX, typename TY>
-void launch_spmv(const Grid& g, const TA* A, const TX* x, TY* y, hipStream_t s) {
-  spmv_kernel<TA, TX, TY><<<(g.Npad + 255) / 256, 256, 0, s>>>(g, A, x, y);
+void launch_spmv(const Grid& g, const TA* A, const TX* x, TY* y, void* C, hipStream_t s, int G) {
+  const int nb = row_grid(g, G);
+  spmv_upper_kernel<TA, TX, TY><<<nb, 256, 0, s>>>(g, A, x, y, (TY*)C);
+  spmv_lower_kernel<TY><<<nb, 256, 0, s>>>(g, y, (const TY*)C);
 }
-template void launch_spmv<double, double, double>(const Grid&, const double*, const double*, double*, hipStream_t);
-template void launch_spmv<double, float, double>(const Grid&, const double*, const float*, double*, hipStream_t);
-template void launch_spmv<float, float, float>(const Grid&, const float*, const float*, float*, hipStream_t);
+template void launch_spmv<double, double, double>(const Grid&, const double*, const double*, double*, void*,
+                                                  hipStream_t, int);
+template void launch_spmv<double, float, double>(const Grid&, const double*, const float*, double*, void*,
+                                                 hipStream_t, int);
+template void launch_spmv<float, float, float>(const Grid&, const float*, const float*, float*, void*, hipStream_t,
+                                               int);
 
 // r = b - A x
 template <typename T>
-__global__ void __launch_bounds__(256) defect_kernel(Grid g, const T* __restrict__ A, const T* __restrict__ x,
-                                                     const T* __restrict__ b, T* __restrict__ r) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= g.Npad) return;
-  T acc[9];
+__global__ void __launch_bounds__(256) defect_upper_kernel(Grid g, const T* __restrict__ A, const T* __restrict__ x,
+                                                           const T* __restrict__ b, T* __restrict__ r,
+                                                           T* __restrict__ C) {
+  ROW_LOOP(g) {
+    if (n >= g.Npad) continue;
+    T acc[9];
 #pragma unroll
-  for (int c = 0; c < 9; ++c) acc[c] = b[(int64_t)c * g.Npad + n];
-  if (n < g.N) row_product<true>(g, A, x, n, acc);
+    for (int c = 0; c < 9; ++c) acc[c] = b[(int64_t)c * g.Npad + n];
+    if (n < g.N) upper_pass<true>(g, A, x, n, acc, C);
 #pragma unroll
-  for (int c = 0; c < 9; ++c) r[(int64_t)c * g.Npad + n] = (n < g.N) ? acc[c] : (T)0;
+    for (int c = 0; c < 9; ++c) r[(int64_t)c * g.Npad + n] = (n < g.N) ? acc[c] : (T)0;
+  }
 }
 
 template <typename T>
-void launch_defect(const Grid& g, const T* A, const T* x, const T* b, T* r, hipStream_t s) {
-  defect_kernel<T><<<(g.Npad + 255) / 256, 256, 0, s>>>(g, A, x, b, r);
-}
-template void launch_defect<float>(const Grid&, const float*, const float*, const float*, float*, hipStream_t);
-template void launch_defect<double>(const Grid&, const double*, const double*, const double*, double*, hipStream_t);
-
-// Damped point-block Jacobi sweep (Sec. 3.4): xo = x + omega D^-1 (b - A x);
-// with a zero initial guess the product with A vanishes: xo = omega D^-1 b.
-template <typename T, bool ZERO>
-__global__ void __launch_bounds__(256) pbj_kernel(Grid g, const T* __restrict__ A, const T* __restrict__ Dinv,
-                                                  const T* __restrict__ x, const T* __restrict__ b,
-                                                  T* __restrict__ xo, T omega) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= g.Npad) return;
-  if (n >= g.N) {
+__global__ void __launch_bounds__(256) defect_lower_kernel(Grid g, T* __restrict__ r, const T* __restrict__ C) {
+  ROW_LOOP(g) {
+    if (n >= g.N) continue;
+    T acc[9];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) xo[(int64_t)c * g.Npad + n] = (T)0;
+    for (int c = 0; c < 9; ++c) acc[c] = r[(int64_t)c * g.Npad + n];
+    lower_pass<true>(g, n, acc, C);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) r[(int64_t)c * g.Npad + n] = acc[c];
+  }
+}
+
+template <typename T>
+void launch_defect(const Grid& g, const T* A, const T* x, const T* b, T* r, void* C, hipStream_t s, int G) {
+  const int nb = row_grid(g, G);
+  defect_upper_kernel<T><<<nb, 256, 0, s>>>(g, A, x, b, r, (T*)C);
+  defect_lower_kernel<T><<<nb, 256, 0, s>>>(g, r, (const T*)C);
+}
+template void launch_defect<float>(const Grid&, const float*, const float*, const float*, float*, void*, hipStream_t,
+                                   int);
+template void launch_defect<double>(const Grid&, const double*, const double*, const double*, double*, void*,
+                                    hipStream_t, int);
+
+// Damped point-block Jacobi sweep (Sec. 3.4): xo = x + omega D^-1 (b - A x).
+// Pass 1 leaves the partial residual in xo; pass 2 completes it and updates.
+// With a zero initial guess the product with A vanishes: xo = omega D^-1 b.
+template <typename T>
+__global__ void __launch_bounds__(256) pbj_zero_kernel(Grid g, const T* __restrict__ Dinv, const T* __restrict__ b,
+                                                       T* __restrict__ xo, T omega) {
+  ROW_LOOP(g) {
+    if (n >= g.Npad) continue;
+    const int t = n >> 6, l = n & 63;
+    const T* Db = Dinv + (int64_t)t * NBLK * TILE + l;
+    T bv[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) bv[c] = b[(int64_t)c * g.Npad + n];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) s += Db[(r * 9 + c) * TILE] * bv[c];
+      xo[(int64_t)r * g.Npad + n] = (n < g.N) ? omega * s : (T)0;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) pbj_lower_kernel(Grid g, const T* __restrict__ Dinv, const T* __restrict__ x,
+                                                        T* __restrict__ xo, const T* __restrict__ C, T omega) {
+  ROW_LOOP(g) {
+    if (n >= g.N) continue;
+    T res[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) res[c] = xo[(int64_t)c * g.Npad + n];
+    lower_pass<true>(g, n, res, C);
+    const int t = n >> 6, l = n & 63;
+    const T* Db = Dinv + (int64_t)t * NBLK * TILE + l;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) s += Db[(r * 9 + c) * TILE] * res[c];
+      xo[(int64_t)r * g.Npad + n] = x[(int64_t)r * g.Npad + n] + omega * s;
+    }
+  }
+}
+
+template <typename T>
+void launch_pbj(const Grid& g, const T* A, const T* Dinv, const T* x, const T* b, T* xo, T omega, bool zero_guess,
+                void* C, hipStream_t s, int G) {
+  const int nb = row_grid(g, G);
+  if (zero_guess) {
+    pbj_zero_kernel<T><<<nb, 256, 0, s>>>(g, Dinv, b, xo, omega);
     return;
   }
-  T res[9];
+  defect_upper_kernel<T><<<nb, 256, 0, s>>>(g, A, x, b, xo, (T*)C);
+  pbj_lower_kernel<T><<<nb, 256, 0, s>>>(g, Dinv, x, xo, (const T*)C, omega);
+}
+template void launch_pbj<float>(const Grid&, const float*, const float*, const float*, const float*, float*, float,
+                                bool, void*, hipStream_t, int);
+template void launch_pbj<double>(const Grid&, const double*, const double*, const double*, const double*, double*,
+                                 double, bool, void*, hipStream_t, int);
+
+// ---- small grids --------------------------------------------------------------
+// On coarse levels the one-thread-per-row kernels are latency bound (27 rounds
+// of dependent loads per thread).  Here 27 threads share a row, one per
+// stencil block; each does one round of loads and the 27 partial products are
+// summed through LDS in a fixed order.  9 rows per 256-thread workgroup,
+// thread index = s * 9 + local row.
+constexpr int SMALL_ROWS = 9;
+
+template <typename T, bool PBJ>
+__global__ void __launch_bounds__(256) row_small_kernel(Grid g, const T* __restrict__ A, const T* __restrict__ Dinv,
+                                                        const T* __restrict__ x, const T* __restrict__ b,
+                                                        T* __restrict__ out, T omega) {
+  __shared__ T part[SMALL_ROWS][NSTEN][9];
+  __shared__ T res[SMALL_ROWS][9];
+  const int tid = threadIdx.x;
+  const int s = tid / SMALL_ROWS, ln = tid % SMALL_ROWS;
+  const int n = blockIdx.x * SMALL_ROWS + ln;
+  T pr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (tid < SMALL_ROWS * NSTEN && n < g.N) {
+    const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
+    const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+    if (i + dx >= 0 && i + dx < g.nnx && j + dy >= 0 && j + dy < g.nny && k + dz >= 0 && k + dz < g.nnz) {
+      const int m = n + dx + g.nnx * (dy + g.nny * dz);
+      T xv[9];
 #pragma unroll
-  for (int c = 0; c < 9; ++c) res[c] = b[(int64_t)c * g.Npad + n];
-  if (!ZERO) row_product<true>(g, A, x, n, res);
-  const int t = n >> 6, l = n & 63;
-  const T* Db = Dinv + (int64_t)t * NBLK * TILE + l;
+      for (int c = 0; c < 9; ++c) xv[c] = x[(int64_t)c * g.Npad + m];
+      const int64_t slice = (int64_t)NBLK * TILE;
+      if (s >= 13) {
+        const T* Ab = A + ((int64_t)(n >> 6) * NUP + (s - 13)) * slice + (n & 63);
 #pragma unroll
-  for (int r = 0; r < 9; ++r) {
-    T s = 0;
+        for (int r = 0; r < 9; ++r) {
+          T acc = 0;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) s += Db[(r * 9 + c) * TILE] * res[c];
-    const T x0 = ZERO ? (T)0 : x[(int64_t)r * g.Npad + n];
-    xo[(int64_t)r * g.Npad + n] = x0 + omega * s;
+          for (int c = 0; c < 9; ++c) acc += Ab[(r * 9 + c) * TILE] * xv[c];
+          pr[r] = acc;
+        }
+      } else {
+        const T* Ab = A + ((int64_t)(m >> 6) * NUP + (13 - s)) * slice + (m & 63);
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+          T acc = 0;
+#pragma unroll
+          for (int c = 0; c < 9; ++c) acc += Ab[(c * 9 + r) * TILE] * xv[c];
+          pr[r] = acc;
+        }
+      }
+    }
+  }
+  if (tid < SMALL_ROWS * NSTEN)
+#pragma unroll
+    for (int r = 0; r < 9; ++r) part[ln][s][r] = pr[r];
+  __syncthreads();
+  const int ln2 = tid / 9, r2 = tid % 9;
+  const int n2 = blockIdx.x * SMALL_ROWS + ln2;
+  const bool own = tid < SMALL_ROWS * 9 && n2 < g.N;
+  if (own) {
+    T acc = b[(int64_t)r2 * g.Npad + n2];
+    for (int ss = 0; ss < NSTEN; ++ss) acc -= part[ln2][ss][r2];
+    res[ln2][r2] = acc;
+  }
+  __syncthreads();
+  if (own) {
+    if (!PBJ) {
+      out[(int64_t)r2 * g.Npad + n2] = res[ln2][r2];
+    } else {
+      const T* Db = Dinv + (int64_t)(n2 >> 6) * NBLK * TILE + (n2 & 63);
+      T acc = 0;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc += Db[(r2 * 9 + c) * TILE] * res[ln2][c];
+      out[(int64_t)r2 * g.Npad + n2] = x[(int64_t)r2 * g.Npad + n2] + omega * acc;
+    }
   }
 }
 
 template <typename T>
-void launch_pbj(const Grid& g, const T* A, const T* Dinv, const T* x, const T* b, T* xo, T omega,
-                bool zero_guess, hipStream_t s) {
-  const int nb = (g.Npad + 255) / 256;
-  if (zero_guess)
-    pbj_kernel<T, true><<<nb, 256, 0, s>>>(g, A, Dinv, x, b, xo, omega);
+void launch_row_small(const Grid& g, const T* A, const T* Dinv, const T* x, const T* b, T* out, T omega, bool pbj,
+                      hipStream_t s) {
+  const int nb = (g.N + SMALL_ROWS - 1) / SMALL_ROWS;
+  if (pbj)
+    row_small_kernel<T, true><<<nb, 256, 0, s>>>(g, A, Dinv, x, b, out, omega);
   else
-    pbj_kernel<T, false><<<nb, 256, 0, s>>>(g, A, Dinv, x, b, xo, omega);
+    row_small_kernel<T, false><<<nb, 256, 0, s>>>(g, A, Dinv, x, b, out, omega);
 }
-template void launch_pbj<float>(const Grid&, const float*, const float*, const float*, const float*, float*, float,
-                                bool, hipStream_t);
-template void launch_pbj<double>(const Grid&, const double*, const double*, const double*, const double*, double*,
-                                 double, bool, hipStream_t);
+template void launch_row_small<float>(const Grid&, const float*, const float*, const float*, const float*, float*,
+                                      float, bool, hipStream_t);
+template void launch_row_small<double>(const Grid&, const double*, const double*, const double*, const double*,
+                                       double*, double, bool, hipStream_t);
 
 }  // namespace mvpf

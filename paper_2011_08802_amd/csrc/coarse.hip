@@ -1,7 +1,7 @@
 // Coarsest-level direct solve (Sec. 3.4: the V-cycle bottoms out in a sparse
 // LU factorisation).  The coarsest operator (at most 8192 unknowns) is
 // gathered into a dense FP64 matrix and inverted once per Newton system by
-// Gauss-Jordan elimination with partial pivoting; each V-cycle then applies
+// blocked Gauss-Jordan elimination with partial pivoting; each V-cycle then applies
 // the inverse with one dense matrix-vector product (fully parallel, instead
 // of two latency-bound triangular solves).
 //
@@ -17,14 +17,18 @@ __global__ void __launch_bounds__(256) dense_from_bsr_kernel(Grid g, const doubl
   const int64_t nd = (int64_t)NDOF * g.N;
   const int t = n >> 6, l = n & 63;
   const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
-  for (int s = 0; s < NSTEN; ++s) {
+  for (int u = 0; u < NUP; ++u) {
+    const int s = 13 + u;
     const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
     if (i + dx < 0 || i + dx >= g.nnx || j + dy < 0 || j + dy >= g.nny || k + dz < 0 || k + dz >= g.nnz) continue;
     const int m = n + dx + g.nnx * (dy + g.nny * dz);
-    const double* Ab = A + ((int64_t)(t * NSTEN + s) * NBLK) * TILE + l;
+    const double* Ab = A + ((int64_t)(t * NUP + u) * NBLK) * TILE + l;
     for (int r = 0; r < 9; ++r)
-      for (int c = 0; c < 9; ++c)
-        D[((int64_t)r * g.N + n) * nd + (int64_t)c * g.N + m] = Ab[(r * 9 + c) * TILE];
+      for (int c = 0; c < 9; ++c) {
+        const double v = Ab[(r * 9 + c) * TILE];
+        D[((int64_t)r * g.N + n) * nd + (int64_t)c * g.N + m] = v;
+        if (u > 0) D[((int64_t)c * g.N + m) * nd + (int64_t)r * g.N + n] = v;  // lower half by symmetry
+      }
   }
 }
 
@@ -39,94 +43,276 @@ void launch_dense_from_bsr(const Grid& g, const double* A64, double* dense, hipS
   dense_from_bsr_kernel<<<(g.N + 255) / 256, 256, 0, s>>>(g, A64, dense);
 }
 
-// Augmented matrix M = [A | I], n x 2n, row-major.  Step j: pick the pivot
-// row (largest |M(i,j)|, i >= j), swap it into row j, scale row j, record the
-// elimination factors of column j.
-__global__ void __launch_bounds__(1024) gj_pivot_kernel(int n, int j, double* __restrict__ M,
-                                                        double* __restrict__ fac, int* status) {
-  __shared__ double sv[1024];
-  __shared__ int si[1024];
+// Blocked Gauss-Jordan inversion with partial pivoting on the augmented
+// matrix M = [A | I] (n x 2n, row-major), panels of GJB columns.  For panel
+// columns c0..c0+B-1:
+//   1. gj_panel: one workgroup snapshots the panel F = M[:, panel] (kept in
+//      registers), chooses the pivot rows P by Gauss-Jordan with partial
+//      pivoting restricted to the panel (rows pivoted earlier are excluded),
+//      and inverts the B x B pivot block Mp = F[P, :] (Gauss-Jordan with
+//      partial pivoting in LDS);
+//   2. gj_rows: R = Mp^-1 M[P, :] (the new pivot rows);
+//   3. gj_update: rows in P become R, every other row i becomes
+//      M[i, :] - F[i, :] R, which zeroes its panel columns.
+// After the last panel the left half is a permutation (row prow[c] holds the
+// unit entry of column c) and A^-1 row c = right half of row prow[c].
+constexpr int GJB = 32;
+constexpr int GJ_THREADS = 512;
+
+// argmax of v (ties: lowest index; idx < 0 = no candidate) over the block
+__device__ __forceinline__ void block_argmax(double& v, int& idx, double* sv, int* si) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_down(v, off, 64);
+    const int oi = __shfl_down(idx, off, 64);
+    if (oi >= 0 && (ov > v || (ov == v && (idx < 0 || oi < idx)))) { v = ov; idx = oi; }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) { sv[wid] = v; si[wid] = idx; }
+  __syncthreads();
+  if (wid == 0) {
+    v = (lane < (int)(blockDim.x >> 6)) ? sv[lane] : -1.0;
+    idx = (lane < (int)(blockDim.x >> 6)) ? si[lane] : -1;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_down(v, off, 64);
+      const int oi = __shfl_down(idx, off, 64);
+      if (oi >= 0 && (ov > v || (ov == v && (idx < 0 || oi < idx)))) { v = ov; idx = oi; }
+    }
+    if (lane == 0) { sv[0] = v; si[0] = idx; }
+  }
+  __syncthreads();
+  v = sv[0];
+  idx = si[0];
+}
+
+// Panel factorisation.  Thread t owns rows t, t + GJ_THREADS, ... (RPT of
+// them) and keeps their panel entries in registers; the pivot row is broadcast
+// through LDS.  n <= GJ_THREADS * RPT.
+template <int RPT>
+__global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int B, const double* __restrict__ M,
+                                                              double* __restrict__ F, int* __restrict__ done,
+                                                              int* __restrict__ prow, int* __restrict__ pos,
+                                                              double* __restrict__ Pinv, int* status) {
+  __shared__ double sv[GJ_THREADS / 64];
+  __shared__ int si[GJ_THREADS / 64];
+  __shared__ double prowv[GJB];
+  __shared__ double Mp[GJB][2 * GJB];
+  __shared__ double fr[GJB];
+  __shared__ int pr[GJB];
   const int tid = threadIdx.x;
   const int64_t w = 2 * (int64_t)n;
-  double best = -1.0;
-  int bi = j;
-  for (int i = j + tid; i < n; i += blockDim.x) {
-    const double v = fabs(M[(int64_t)i * w + j]);
-    if (v > best) { best = v; bi = i; }
+  double W[RPT][GJB];
+  bool act[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = tid + q * GJ_THREADS;
+    act[q] = i < n && !done[i];
+#pragma unroll
+    for (int b = 0; b < GJB; ++b) {
+      const double v = (i < n && b < B) ? M[(int64_t)i * w + c0 + b] : 0.0;
+      W[q][b] = v;
+      if (i < n && b < B) F[(int64_t)i * B + b] = v;
+    }
   }
-  sv[tid] = best;
-  si[tid] = bi;
-  __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if (tid < off) {
-      const double o = sv[tid + off];
-      const int oi = si[tid + off];
-      if (o > sv[tid] || (o == sv[tid] && oi < si[tid])) { sv[tid] = o; si[tid] = oi; }
+#pragma unroll 1
+  for (int jj = 0; jj < B; ++jj) {
+    double v = -1.0;
+    int idx = -1;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      double cand = -1.0;
+#pragma unroll
+      for (int b = 0; b < GJB; ++b)
+        if (b == jj) cand = fabs(W[q][b]);
+      if (act[q] && cand > v) { v = cand; idx = tid + q * GJ_THREADS; }
+    }
+    block_argmax(v, idx, sv, si);
+    if (!(v > 0.0) || idx < 0) {
+      if (tid == 0) atomicOr(status, 1);
+      return;  // uniform
+    }
+    const int p = idx;
+    if (p % GJ_THREADS == tid) {
+      const int q = p / GJ_THREADS;
+#pragma unroll
+      for (int qq = 0; qq < RPT; ++qq)
+        if (qq == q) {
+          act[qq] = false;
+#pragma unroll
+          for (int b = 0; b < GJB; ++b) prowv[b] = W[qq][b];
+        }
+      done[p] = 1;
+      prow[c0 + jj] = p;
+      pos[p] = c0 + jj;
+      pr[jj] = p;
+    }
+    __syncthreads();
+    double pvj = 0.0;
+#pragma unroll
+    for (int b = 0; b < GJB; ++b)
+      if (b == jj) pvj = prowv[b];
+    const double ip = 1.0 / pvj;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      if (!act[q]) continue;
+      double f = 0.0;
+#pragma unroll
+      for (int b = 0; b < GJB; ++b)
+        if (b == jj) f = W[q][b] * ip;
+#pragma unroll
+      for (int b = 0; b < GJB; ++b)
+        if (b > jj) W[q][b] -= f * prowv[b];
     }
     __syncthreads();
   }
-  const int p = si[0];
-  const double pv = sv[0];
-  if (!(pv > 0.0)) {
-    if (tid == 0) atomicOr(status, 1);
-    // leave the matrix untouched; host reports the singular pivot
-    for (int i = tid; i < n; i += blockDim.x) fac[i] = 0.0;
-    return;
+  // invert the pivot block Mp = F[P, :] (B x B) with partial pivoting, [Mp | I] in LDS
+  for (int idx = tid; idx < B * B; idx += blockDim.x) {
+    const int a = idx / B, b = idx % B;
+    Mp[a][b] = F[(int64_t)pr[a] * B + b];
+    Mp[a][B + b] = (a == b) ? 1.0 : 0.0;
   }
-  if (p != j)
-    for (int64_t c = tid; c < w; c += blockDim.x) {
-      const double a = M[(int64_t)j * w + c];
-      M[(int64_t)j * w + c] = M[(int64_t)p * w + c];
-      M[(int64_t)p * w + c] = a;
+  __syncthreads();
+  for (int c = 0; c < B; ++c) {
+    if (tid == 0) {
+      int q = c;
+      double bv = fabs(Mp[c][c]);
+      for (int r = c + 1; r < B; ++r)
+        if (fabs(Mp[r][c]) > bv) { bv = fabs(Mp[r][c]); q = r; }
+      si[0] = q;
+      sv[0] = bv;
     }
-  __syncthreads();
-  const double ip = 1.0 / M[(int64_t)j * w + j];
-  __syncthreads();
-  for (int64_t c = tid; c < w; c += blockDim.x) M[(int64_t)j * w + c] *= ip;
-  __syncthreads();
-  for (int i = tid; i < n; i += blockDim.x) fac[i] = (i == j) ? 0.0 : M[(int64_t)i * w + j];
+    __syncthreads();
+    const int q = si[0];
+    if (!(sv[0] > 0.0)) {
+      if (tid == 0) atomicOr(status, 1);
+      return;
+    }
+    if (q != c && tid < 2 * B) {
+      const double tmp = Mp[c][tid];
+      Mp[c][tid] = Mp[q][tid];
+      Mp[q][tid] = tmp;
+    }
+    __syncthreads();
+    const double ipc = 1.0 / Mp[c][c];
+    __syncthreads();
+    if (tid < 2 * B) Mp[c][tid] *= ipc;
+    if (tid < B) fr[tid] = (tid == c) ? 0.0 : Mp[tid][c];
+    __syncthreads();
+    for (int idx = tid; idx < B * 2 * B; idx += blockDim.x) {
+      const int r = idx / (2 * B), cc = idx % (2 * B);
+      if (r != c) Mp[r][cc] -= fr[r] * Mp[c][cc];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < B * B; idx += blockDim.x) Pinv[idx] = Mp[idx / B][B + idx % B];
 }
 
-__global__ void __launch_bounds__(256) gj_eliminate_kernel(int n, int j, double* __restrict__ M,
-                                                           const double* __restrict__ fac) {
+// R[a][c] = sum_b Pinv[a][b] M[prow[c0 + b]][c]
+__global__ void __launch_bounds__(256) gj_rows_kernel(int n, int c0, int B, const double* __restrict__ M,
+                                                      const int* __restrict__ prow, const double* __restrict__ Pinv,
+                                                      double* __restrict__ R) {
   const int64_t w = 2 * (int64_t)n;
-  const int i = blockIdx.y;
-  if (i == j) return;
-  const double f = fac[i];
-  if (f == 0.0) return;
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < w; c += (int64_t)gridDim.x * blockDim.x)
-    M[(int64_t)i * w + c] -= f * M[(int64_t)j * w + c];
+  const int a = blockIdx.y;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < w; c += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < B; ++b) s += Pinv[a * B + b] * M[(int64_t)prow[c0 + b] * w + c];
+    R[(int64_t)a * w + c] = s;
+  }
 }
 
-__global__ void __launch_bounds__(256) gj_init_kernel(int n, const double* __restrict__ a, double* __restrict__ M) {
+// M[i][c] = R[pos(i)][c] for pivot rows of this panel, else M[i][c] - F[i,:] R[:, c].
+// Block: 32 rows x 256 columns; R column strip kept in registers.
+__global__ void __launch_bounds__(256) gj_update_kernel(int n, int c0, int B, double* __restrict__ M,
+                                                        const double* __restrict__ F, const double* __restrict__ R,
+                                                        const int* __restrict__ pos) {
+  __shared__ double Fs[32][GJB];
+  const int64_t w = 2 * (int64_t)n;
+  const int r0 = blockIdx.y * 32;
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int idx = threadIdx.x; idx < 32 * GJB; idx += 256) {
+    const int rr = idx / GJB, b = idx % GJB;
+    Fs[rr][b] = (r0 + rr < n && b < B) ? F[(int64_t)(r0 + rr) * B + b] : 0.0;
+  }
+  __syncthreads();
+  if (c >= w) return;
+  double Rc[GJB];
+#pragma unroll
+  for (int b = 0; b < GJB; ++b) Rc[b] = (b < B) ? R[(int64_t)b * w + c] : 0.0;
+  for (int rr = 0; rr < 32; ++rr) {
+    const int i = r0 + rr;
+    if (i >= n) break;
+    const int pi = pos[i];
+    double v;
+    if (pi >= c0 && pi < c0 + B) {
+      v = Rc[0];
+#pragma unroll
+      for (int b = 1; b < GJB; ++b)
+        if (b == pi - c0) v = Rc[b];
+    } else {
+      v = M[(int64_t)i * w + c];
+#pragma unroll
+      for (int b = 0; b < GJB; ++b) v -= Fs[rr][b] * Rc[b];
+    }
+    M[(int64_t)i * w + c] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) gj_init_kernel(int n, const double* __restrict__ a, double* __restrict__ M,
+                                                      int* __restrict__ done, int* __restrict__ pos) {
   const int64_t w = 2 * (int64_t)n;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)n * w;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx / w, c = idx - i * w;
     M[idx] = (c < n) ? a[i * n + c] : ((c - n == i) ? 1.0 : 0.0);
+    if (c == 0) { done[i] = 0; pos[i] = -1; }
   }
 }
 
-__global__ void __launch_bounds__(256) gj_extract_kernel(int n, const double* __restrict__ M, double* __restrict__ inv) {
+__global__ void __launch_bounds__(256) gj_extract_kernel(int n, const double* __restrict__ M,
+                                                         const int* __restrict__ prow, double* __restrict__ inv) {
   const int64_t w = 2 * (int64_t)n;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)n * n;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx / n, c = idx - i * n;
-    inv[idx] = M[i * w + n + c];
+    inv[idx] = M[(int64_t)prow[i] * w + n + c];
   }
 }
 
-// a: n x n input (not modified); inv: n x n output; work: >= 2 n^2 + n doubles.
+size_t dense_invert_work(int n) {
+  // M (2n^2) + F, W (n*GJB each) + R (GJB*2n) + Pinv (GJB^2) doubles, then 3n ints
+  return (size_t)(2 * (int64_t)n * n + 2 * (int64_t)n * GJB + 2 * (int64_t)GJB * n + GJB * GJB) * sizeof(double) +
+         (size_t)3 * n * sizeof(int);
+}
+
+// a: n x n input (not modified); inv: n x n output; work: dense_invert_work(n) bytes.
 int dense_invert(int n, double* a, double* inv, double* work, int* status, hipStream_t s) {
   double* M = work;
-  double* fac = work + 2 * (int64_t)n * n;
-  gj_init_kernel<<<1024, 256, 0, s>>>(n, a, M);
-  const int gx = (int)std::min<int64_t>((2 * (int64_t)n + 255) / 256, 16);
-  for (int j = 0; j < n; ++j) {
-    gj_pivot_kernel<<<1, 1024, 0, s>>>(n, j, M, fac, status);
-    gj_eliminate_kernel<<<dim3(gx, n), 256, 0, s>>>(n, j, M, fac);
+  double* F = M + 2 * (int64_t)n * n;
+  double* W = F + (int64_t)n * GJB;
+  double* R = W + (int64_t)n * GJB;
+  double* Pinv = R + 2 * (int64_t)GJB * n;
+  int* done = (int*)(Pinv + GJB * GJB);
+  int* prow = done + n;
+  int* pos = prow + n;
+  gj_init_kernel<<<1024, 256, 0, s>>>(n, a, M, done, pos);
+  const int64_t w = 2 * (int64_t)n;
+  for (int c0 = 0; c0 < n; c0 += GJB) {
+    const int B = std::min(GJB, n - c0);
+    if (n <= GJ_THREADS)
+      gj_panel_kernel<1><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
+    else if (n <= 2 * GJ_THREADS)
+      gj_panel_kernel<2><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
+    else if (n <= 3 * GJ_THREADS)
+      gj_panel_kernel<3><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
+    else if (n <= 4 * GJ_THREADS)
+      gj_panel_kernel<4><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
+    else if (n <= 8 * GJ_THREADS)
+      gj_panel_kernel<8><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
+    else
+      gj_panel_kernel<16><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
+    gj_rows_kernel<<<dim3((int)std::min<int64_t>((w + 255) / 256, 64), B), 256, 0, s>>>(n, c0, B, M, prow, Pinv, R);
+    gj_update_kernel<<<dim3((int)((w + 255) / 256), (n + 31) / 32), 256, 0, s>>>(n, c0, B, M, F, R, pos);
   }
-  gj_extract_kernel<<<1024, 256, 0, s>>>(n, M, inv);
+  gj_extract_kernel<<<1024, 256, 0, s>>>(n, M, prow, inv);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

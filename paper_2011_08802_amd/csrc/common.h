@@ -5,12 +5,18 @@
 //    9 unknowns c of node n; Npad = N rounded up to 64; padding is kept 0.
 //  * state:   15 FP64 components [u_x,u_y,u_z, eta_1..6, eta_n_1..6] in the
 //    same SoA layout.
-//  * 9x9 block operators on the structured 27-point stencil, tiled SoA:
-//    A[((t * 27 + s) * 81 + e) * 64 + l] is entry e = 9*row + col of the block
-//    coupling node n = 64 t + l with its neighbour n + off(s),
-//    s = (dz+1)*9 + (dy+1)*3 + (dx+1).  Blocks of out-of-grid neighbours and of
-//    padding rows are zero.  One wavefront reads one (tile, s, e) slice of 64
-//    consecutive values per load.
+//  * 9x9 block operators on the structured 27-point stencil, symmetric half
+//    storage, tiled SoA: A[((t * 14 + u) * 81 + e) * 64 + l] is entry
+//    e = 9*row + col of the block coupling node n = 64 t + l with its neighbour
+//    n + off(13 + u), where s = (dz+1)*9 + (dy+1)*3 + (dx+1) numbers the 27
+//    offsets and s >= 13 are the diagonal and the 13 offsets with a positive
+//    node-index difference.  The operator is symmetric (a Hessian, with
+//    symmetric Dirichlet elimination), so the block for offset s < 13 is the
+//    transpose of the stored block (n + off(s), 26 - s).  Blocks of
+//    out-of-grid neighbours and of padding rows are zero.  One wavefront reads
+//    one (tile, u, e) slice of 64 consecutive values per load.
+//  * element matrices during assembly: E[(p * 81 + e) * NEpad + el] for the
+//    36 node pairs p = (a <= b) of element el.
 //  * block inverses D^-1: Dinv[(t * 81 + e) * 64 + l].
 //  * per-Gauss-point scratch: qp[(comp * 8 + g) * NEpad + e].
 #pragma once
@@ -28,12 +34,15 @@ namespace mvpf {
 constexpr int NDOF = 9;
 constexpr int NSTATE = 15;
 constexpr int NSTEN = 27;
+constexpr int NUP = 14;              // stored stencil blocks per row (diagonal + 13 upper)
+constexpr int NPAIR = 36;            // element node pairs a <= b
 constexpr int NBLK = 81;
 constexpr int TILE = 64;
 constexpr int QP_GRAD = 15;          // gradient components per Gauss point
 constexpr int QP_HESS = 15 + 120;    // gradient + packed Hessian
 constexpr int MAX_LEVELS = 8;
 constexpr int MAX_RESTART = 64;
+constexpr int SMALL_GRID_NODES = 10000;  // default size limit of the small-grid kernels
 
 struct Grid {
   int nx, ny, nz;      // elements
@@ -90,6 +99,8 @@ struct mvpf_problem {
   mvpf::Level lev[mvpf::MAX_LEVELS];
   mvpf::DevCard* card = nullptr;     // device copy
   double* qp = nullptr;              // per-Gauss-point scratch (finest size)
+  double* elem = nullptr;            // element matrices, upper node pairs (finest size)
+  void* Cbuf = nullptr;              // lower-half contributions, 13 * 9 * Npad doubles (finest size)
   double depth = 0.0;                // depth of the current state
   double sys_depth = 0.0;            // depth used by the last Newton system
   bool have_system = false;
@@ -109,6 +120,9 @@ struct mvpf_problem {
   double* save_state = nullptr;  // backup for step rejection
   int64_t bytes = 0;
   bool timing = false;
+  int row_G[mvpf::MAX_LEVELS] = {0};  // launch shape of the smoother/defect kernels per level
+  int outer_G = 0;                     // launch shape of the outer FP64 operator product
+  int small_nodes = mvpf::SMALL_GRID_NODES;  // levels up to this size use the small-grid kernels
   mvpf::KernelTimer t_sweep, t_outer, t_resid;
 };
 
@@ -119,20 +133,30 @@ namespace mvpf {
 void launch_qp(const Grid& g, const double* state, const DevCard* cd, double* qp, bool hess, hipStream_t s);
 void launch_residual_gather(const Grid& g, const double* state, const double* qp, const DevCard* cd,
                             double* R, hipStream_t s);
-void launch_jacobian_gather(const Grid& g, const double* qp, const DevCard* cd, double* A64, float* A32,
-                            double* diag64, hipStream_t s);
+void launch_element_matrices(const Grid& g, const double* qp, const DevCard* cd, double* elem, hipStream_t s);
+void launch_jacobian_gather(const Grid& g, const double* elem, double* A64, float* A32, double* diag64,
+                            hipStream_t s);
 void launch_apply_dirichlet(const Grid& g, const uint16_t* mask, double* A64, float* A32, double* diag64,
                             hipStream_t s);
 void launch_block_inverse(const Grid& g, const double* diag64, double* Dinv64, float* Dinv32, int* status,
                           hipStream_t s);
 // BSR products (TA = operator type, TX = vector type)
+// G: number of workgroups (0 = one per 256 rows; smaller = persistent rounds).
+// C: scratch for the transposed lower-half contributions, >= 13 * 9 * Npad
+// values of the accumulation type (TY for spmv, T otherwise).
 template <typename TA, typename TX, typename TY>
-void launch_spmv(const Grid& g, const TA* A, const TX* x, TY* y, hipStream_t s);
+void launch_spmv(const Grid& g, const TA* A, const TX* x, TY* y, void* C, hipStream_t s, int G = 0);
 template <typename T>
-void launch_defect(const Grid& g, const T* A, const T* x, const T* b, T* r, hipStream_t s);
+void launch_defect(const Grid& g, const T* A, const T* x, const T* b, T* r, void* C, hipStream_t s, int G = 0);
 template <typename T>
 void launch_pbj(const Grid& g, const T* A, const T* Dinv, const T* x, const T* b, T* xo, T omega,
-                bool zero_guess, hipStream_t s);
+                bool zero_guess, void* C, hipStream_t s, int G = 0);
+// coarse-level variant (27 threads per row); out = b - A x, or the damped
+// point-block Jacobi update when pbj is set.  Used on levels with at most
+// small_grid_nodes nodes (default SMALL_GRID_NODES, a tuning key).
+template <typename T>
+void launch_row_small(const Grid& g, const T* A, const T* Dinv, const T* x, const T* b, T* out, T omega, bool pbj,
+                      hipStream_t s);
 // transfers
 template <typename T>
 void launch_restrict(const Grid& fine, const Grid& coarse, const T* rf, const uint16_t* cmask, T* bc,
@@ -145,6 +169,7 @@ void launch_inject_mask(const Grid& fine, const Grid& coarse, const uint16_t* mf
                         hipStream_t s);
 // coarse direct solve
 void launch_dense_from_bsr(const Grid& g, const double* A64, double* dense, hipStream_t s);
+size_t dense_invert_work(int n);  // bytes of scratch needed by dense_invert
 int dense_invert(int n, double* a, double* inv, double* work, int* piv_status, hipStream_t s);
 template <typename T>
 void launch_coarse_solve(const Grid& g, const double* Ainv, const T* b, T* x, hipStream_t s);

@@ -4,9 +4,11 @@
 //   1. qp_kernel: one thread per (Gauss point, element) evaluates the local
 //      gradient (and Hessian) of the density and stores it (SoA, coalesced);
 //   2. residual_gather: one thread per node sums its <= 8 elements;
-//   3. jacobian_gather: one thread per (node row, stencil neighbour) sums the
-//      <= 8 elements that contain both nodes and writes the 9x9 block into the
-//      tiled BSR layout (64 consecutive rows per wavefront -> coalesced).
+//   3. element_matrix: element blocks for the 36 node pairs a <= b, with the
+//      Gauss-point Hessians shared through LDS;
+//   4. jacobian_gather: one thread per (node row, stored stencil block) sums
+//      the <= 8 element blocks of the elements containing both nodes and
+//      writes the 9x9 block into the tiled half-stencil layout.
 // Summation order is fixed, so results are bitwise reproducible.
 #include "common.h"
 
@@ -155,33 +157,130 @@ void launch_residual_gather(const Grid& g, const double* state, const double* qp
 }
 
 // Logical block index with the 8 XCDs of the chip in mind: hardware places
-// workgroup b on XCD b % 8; consecutive logical ids (the 27 stencil blocks of
-// one 64-node tile) are kept on one XCD so they share its L2.
+// workgroup b on XCD b % 8; consecutive logical ids are kept on one XCD so
+// that neighbouring tiles share its L2.
 __device__ __forceinline__ int xcd_logical(int b, int nb_pad) {
   const int per = nb_pad >> 3;
   return (b & 7) * per + (b >> 3);
 }
 
-__global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, const double* __restrict__ qp,
-                                                             const DevCard* __restrict__ cd,
+__host__ __device__ constexpr int pair_index(int a, int b) {  // a <= b < 8
+  return a * 8 - (a * (a - 1)) / 2 + (b - a);
+}
+
+// Element matrices K_e = sum_g w_g B_g^T D_g B_g + h Lap (x) Mg for the 36
+// node pairs a <= b.  A workgroup of EM_WAVES wavefronts covers 64
+// consecutive elements and EM_WAVES pairs; the Gauss-point Hessians of those
+// elements are staged once per Gauss point in LDS and shared by the
+// wavefronts (wave = pair, lane = element), so each Hessian is read from L2
+// 36 / EM_WAVES times in total.  Four waves leave room for the 81 FP64
+// accumulators in registers (no spills).
+constexpr int EM_WAVES = 4;
+
+__global__ void __launch_bounds__(EM_WAVES * 64) element_matrix_kernel(Grid g, const double* __restrict__ qp,
+                                                                       const DevCard* __restrict__ cd,
+                                                                       double* __restrict__ E) {
+  __shared__ double Ds[120 * 64];
+  const int groups = g.NEpad / 64;
+  const int eg = blockIdx.x % groups;
+  const int pc = blockIdx.x / groups;  // pair chunk
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int p = pc * EM_WAVES + w;     // pair 0..35
+  int a = 0, rem = p;
+  while (rem >= 8 - a) { rem -= 8 - a; ++a; }
+  const int b = a + rem;
+  const int e = eg * 64 + l;
+  const double cuu = g.h * 0.125, cue = g.h * g.h * 0.125, cee = g.h * g.h * g.h * 0.125;
+  const int64_t stride = (int64_t)8 * g.NEpad;
+  double K[81];
+#pragma unroll
+  for (int q = 0; q < 81; ++q) K[q] = 0.0;
+  for (int gp = 0; gp < 8; ++gp) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 120 * 64; idx += EM_WAVES * 64) {
+      const int comp = idx >> 6, el = idx & 63;
+      Ds[idx] = qp[(int64_t)(15 + comp) * stride + (int64_t)gp * g.NEpad + eg * 64 + el];
+    }
+    __syncthreads();
+    const Shape sa = shape(gp, a), sb = shape(gp, b);
+#define DV(pq) Ds[(pq) * 64 + l]
+    // u-u: K[i3][k3] += h/8 sum_jl dNa_j dNb_l D(3 i3 + j, 3 k3 + l)
+#pragma unroll
+    for (int i3 = 0; i3 < 3; ++i3)
+#pragma unroll
+      for (int k3 = 0; k3 < 3; ++k3) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+          for (int ll = 0; ll < 3; ++ll) {
+            const int pp = 3 * i3 + jj, rr = 3 * k3 + ll;
+            const int pq = pp <= rr ? hidx(pp, rr) : hidx(rr, pp);
+            sacc += sa.dN[jj] * sb.dN[ll] * DV(pq);
+          }
+        K[9 * i3 + k3] += cuu * sacc;
+      }
+    // u-eta and eta-u
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+      for (int i3 = 0; i3 < 3; ++i3) {
+        const double d0 = DV(hidx(3 * i3, 9 + m)), d1 = DV(hidx(3 * i3 + 1, 9 + m)), d2 = DV(hidx(3 * i3 + 2, 9 + m));
+        K[9 * i3 + 3 + m] += cue * sb.N * (sa.dN[0] * d0 + sa.dN[1] * d1 + sa.dN[2] * d2);
+        K[9 * (3 + m) + i3] += cue * sa.N * (sb.dN[0] * d0 + sb.dN[1] * d1 + sb.dN[2] * d2);
+      }
+    // eta-eta
+    const double nn = cee * sa.N * sb.N;
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+      for (int m2 = 0; m2 < 6; ++m2) {
+        const int pq = m <= m2 ? hidx(9 + m, 9 + m2) : hidx(9 + m2, 9 + m);
+        K[9 * (3 + m) + 3 + m2] += nn * DV(pq);
+      }
+#undef DV
+  }
+  // gradient energy: h * Lap_ab * Mg (exact under 2x2x2 Gauss)
+  const double lap = g.h * lap_ref(a, b);
+#pragma unroll
+  for (int m = 0; m < 6; ++m)
+#pragma unroll
+    for (int m2 = 0; m2 < 6; ++m2) K[9 * (3 + m) + 3 + m2] += lap * cd->Mg[m][m2];
+  if (e < g.NE) {
+#pragma unroll
+    for (int q = 0; q < 81; ++q) E[((int64_t)p * NBLK + q) * g.NEpad + e] = K[q];
+  }
+}
+
+void launch_element_matrices(const Grid& g, const double* qp, const DevCard* cd, double* elem, hipStream_t s) {
+  const int groups = g.NEpad / 64;
+  element_matrix_kernel<<<groups * (NPAIR / EM_WAVES), EM_WAVES * 64, 0, s>>>(g, qp, cd, elem);
+}
+
+// Stored block (n, n + off(13 + u)) = sum over the <= 8 elements containing
+// both nodes of their element blocks, in a fixed order (bitwise reproducible).
+// One wavefront per (tile, u): 64 consecutive rows, coalesced element reads
+// and coalesced tiled writes.
+__global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, const double* __restrict__ E,
                                                              double* __restrict__ A64, float* __restrict__ A32,
                                                              double* __restrict__ diag64, int nblocks) {
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= nblocks) return;
-  const int t = L / NSTEN, sten = L - t * NSTEN;
+  const int t = L / NUP, u = L - t * NUP;
+  const int sten = 13 + u;
   const int l = threadIdx.x;
   const int n = t * TILE + l;
   const int dx = sten % 3 - 1, dy = (sten / 3) % 3 - 1, dz = sten / 9 - 1;
-  double K[81];
+  const bool inside = n < g.N;
+  const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
+  const int64_t base = ((int64_t)(t * NUP + u) * NBLK) * TILE + l;
+  const int64_t db = (int64_t)t * NBLK * TILE + l;
+  // three chunks of three block rows keep 27 accumulators live
+  for (int r0 = 0; r0 < 9; r0 += 3) {
+    double K[27];
 #pragma unroll
-  for (int e = 0; e < 81; ++e) K[e] = 0.0;
-  if (n < g.N) {
-    const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
-    const bool valid = (i + dx >= 0) && (i + dx < g.nnx) && (j + dy >= 0) && (j + dy < g.nny) &&
-                       (k + dz >= 0) && (k + dz < g.nnz);
-    if (valid) {
-      const double cuu = g.h * 0.125, cue = g.h * g.h * 0.125, cee = g.h * g.h * g.h * 0.125;
-      const int64_t stride = (int64_t)8 * g.NEpad;
+    for (int q = 0; q < 27; ++q) K[q] = 0.0;
+    if (inside) {
       for (int a = 0; a < 8; ++a) {
         const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
         const int bx = ax + dx, by = ay + dy, bz = az + dz;
@@ -190,95 +289,51 @@ __global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, const doubl
         if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || ez < 0 || ez >= g.nz) continue;
         const int b = bx + 2 * by + 4 * bz;
         const int e = ex + g.nx * (ey + g.ny * ez);
-        for (int gp = 0; gp < 8; ++gp) {
-          const Shape sa = shape(gp, a), sb = shape(gp, b);
-          const double* q = qp + (int64_t)gp * g.NEpad + e + (int64_t)15 * stride;
-          // u-u block: K[i3][k3] += h/8 sum_jl dNa_j dNb_l D(3i3+j, 3k3+l)
-          {
-            double P[9];
+        if (a <= b) {
+          const double* src = E + (int64_t)pair_index(a, b) * NBLK * g.NEpad + e;
 #pragma unroll
-            for (int jj = 0; jj < 3; ++jj)
+          for (int q = 0; q < 27; ++q) K[q] += src[(int64_t)(9 * r0 + q) * g.NEpad];
+        } else {
+          const double* src = E + (int64_t)pair_index(b, a) * NBLK * g.NEpad + e;
 #pragma unroll
-              for (int ll = 0; ll < 3; ++ll) P[3 * jj + ll] = cuu * sa.dN[jj] * sb.dN[ll];
+          for (int rr = 0; rr < 3; ++rr)
 #pragma unroll
-            for (int i3 = 0; i3 < 3; ++i3)
-#pragma unroll
-              for (int k3 = 0; k3 < 3; ++k3) {
-                double s = 0.0;
-#pragma unroll
-                for (int jj = 0; jj < 3; ++jj)
-#pragma unroll
-                  for (int ll = 0; ll < 3; ++ll) {
-                    const int p = 3 * i3 + jj, r = 3 * k3 + ll;
-                    const int pq = p <= r ? hidx(p, r) : hidx(r, p);
-                    s += P[3 * jj + ll] * q[(int64_t)pq * stride];
-                  }
-                K[9 * i3 + k3] += s;
-              }
-          }
-          // u-eta and eta-u blocks
-#pragma unroll
-          for (int m = 0; m < 6; ++m) {
-            double Dm[9];
-#pragma unroll
-            for (int p = 0; p < 9; ++p) Dm[p] = q[(int64_t)hidx(p, 9 + m) * stride];
-#pragma unroll
-            for (int i3 = 0; i3 < 3; ++i3) {
-              K[9 * i3 + 3 + m] += cue * sb.N *
-                                   (sa.dN[0] * Dm[3 * i3] + sa.dN[1] * Dm[3 * i3 + 1] + sa.dN[2] * Dm[3 * i3 + 2]);
-              K[9 * (3 + m) + i3] += cue * sa.N *
-                                     (sb.dN[0] * Dm[3 * i3] + sb.dN[1] * Dm[3 * i3 + 1] + sb.dN[2] * Dm[3 * i3 + 2]);
-            }
-          }
-          // eta-eta block
-          const double nn = cee * sa.N * sb.N;
-#pragma unroll
-          for (int m = 0; m < 6; ++m)
-#pragma unroll
-            for (int m2 = 0; m2 < 6; ++m2) {
-              const int p = 9 + m, r = 9 + m2;
-              const int pq = p <= r ? hidx(p, r) : hidx(r, p);
-              K[9 * (3 + m) + 3 + m2] += nn * q[(int64_t)pq * stride];
-            }
+            for (int c = 0; c < 9; ++c) K[9 * rr + c] += src[(int64_t)(9 * c + r0 + rr) * g.NEpad];
         }
-        // gradient energy: h * Lap_ab * Mg
-        const double lap = g.h * lap_ref(a, b);
-#pragma unroll
-        for (int m = 0; m < 6; ++m)
-#pragma unroll
-          for (int m2 = 0; m2 < 6; ++m2) K[9 * (3 + m) + 3 + m2] += lap * cd->Mg[m][m2];
       }
     }
-  }
-  const int64_t base = ((int64_t)(t * NSTEN + sten) * NBLK) * TILE + l;
-  if (A64) {
+    if (A64) {
 #pragma unroll
-    for (int e = 0; e < 81; ++e) A64[base + (int64_t)e * TILE] = K[e];
-  }
-  if (A32) {
+      for (int q = 0; q < 27; ++q) A64[base + (int64_t)(9 * r0 + q) * TILE] = K[q];
+    }
+    if (A32) {
 #pragma unroll
-    for (int e = 0; e < 81; ++e) A32[base + (int64_t)e * TILE] = (float)K[e];
-  }
-  if (sten == 13 && diag64) {
-    const int64_t db = (int64_t)t * NBLK * TILE + l;
+      for (int q = 0; q < 27; ++q) A32[base + (int64_t)(9 * r0 + q) * TILE] = (float)K[q];
+    }
+    if (u == 0 && diag64) {
 #pragma unroll
-    for (int e = 0; e < 81; ++e) diag64[db + (int64_t)e * TILE] = K[e];
+      for (int q = 0; q < 27; ++q) diag64[db + (int64_t)(9 * r0 + q) * TILE] = K[q];
+    }
   }
 }
 
-void launch_jacobian_gather(const Grid& g, const double* qp, const DevCard* cd, double* A64, float* A32,
-                            double* diag64, hipStream_t s) {
-  const int nblocks = g.ntiles * NSTEN;
+void launch_jacobian_gather(const Grid& g, const double* elem, double* A64, float* A32, double* diag64,
+                            hipStream_t s) {
+  const int nblocks = g.ntiles * NUP;
   const int nb_pad = (nblocks + 7) / 8 * 8;
-  jacobian_gather_kernel<<<nb_pad, TILE, 0, s>>>(g, qp, cd, A64, A32, diag64, nblocks);
+  jacobian_gather_kernel<<<nb_pad, TILE, 0, s>>>(g, elem, A64, A32, diag64, nblocks);
 }
 
+// Symmetric elimination on the stored blocks: entries in constrained rows of
+// node n or constrained columns of node m are zeroed, the diagonal of a
+// constrained dof is 1.
 __global__ void __launch_bounds__(64) apply_dirichlet_kernel(Grid g, const uint16_t* __restrict__ mask,
                                                              double* __restrict__ A64, float* __restrict__ A32,
                                                              double* __restrict__ diag64, int nblocks) {
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= nblocks) return;
-  const int t = L / NSTEN, sten = L - t * NSTEN;
+  const int t = L / NUP, u = L - t * NUP;
+  const int sten = 13 + u;
   const int l = threadIdx.x;
   const int n = t * TILE + l;
   if (n >= g.N) return;
@@ -288,22 +343,22 @@ __global__ void __launch_bounds__(64) apply_dirichlet_kernel(Grid g, const uint1
   const int m = n + dx + g.nnx * (dy + g.nny * dz);
   const unsigned mr = mask[n], mc = mask[m];
   if ((mr | mc) == 0) return;
-  const int64_t base = ((int64_t)(t * NSTEN + sten) * NBLK) * TILE + l;
+  const int64_t base = ((int64_t)(t * NUP + u) * NBLK) * TILE + l;
   const int64_t db = (int64_t)t * NBLK * TILE + l;
   for (int e = 0; e < 81; ++e) {
     const int r = e / 9, c = e % 9;
     if (((mr >> r) & 1) || ((mc >> c) & 1)) {
-      const double v = (sten == 13 && r == c) ? 1.0 : 0.0;
+      const double v = (u == 0 && r == c) ? 1.0 : 0.0;
       if (A64) A64[base + (int64_t)e * TILE] = v;
       if (A32) A32[base + (int64_t)e * TILE] = (float)v;
-      if (sten == 13 && diag64) diag64[db + (int64_t)e * TILE] = v;
+      if (u == 0 && diag64) diag64[db + (int64_t)e * TILE] = v;
     }
   }
 }
 
 void launch_apply_dirichlet(const Grid& g, const uint16_t* mask, double* A64, float* A32, double* diag64,
                             hipStream_t s) {
-  const int nblocks = g.ntiles * NSTEN;
+  const int nblocks = g.ntiles * NUP;
   const int nb_pad = (nblocks + 7) / 8 * 8;
   apply_dirichlet_kernel<<<nb_pad, TILE, 0, s>>>(g, mask, A64, A32, diag64, nblocks);
 }

@@ -90,6 +90,9 @@ SIGNATURES = {
     "mvpf_solve": (C.c_int, [_P, _P, _P, C.POINTER(SolveStats)]),
     "mvpf_newton_update": (C.c_int, [_P]),
     "mvpf_time_step": (C.c_int, [_P, C.c_double, C.POINTER(StepStats)]),
+    "mvpf_set_tuning": (C.c_int, [_P, C.c_char_p, C.c_int, C.c_int]),
+    "mvpf_get_tuning": (C.c_int, [_P, C.c_char_p, C.c_int, C.POINTER(C.c_int)]),
+    "mvpf_autotune": (C.c_int, [_P, C.POINTER(C.c_int)]),
     "mvpf_kernel_timing": (C.c_int, [_P, C.c_int]),
     "mvpf_kernel_stats": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int), _D, _D]),
 }
@@ -246,6 +249,19 @@ class Problem:
         st = StepStats()
         self._check(self.lib.mvpf_time_step(self.h, depth, C.byref(st)), allow=(OK, ENOTCONV))
         return st
+
+    def set_tuning(self, key: str, level: int, value: int):
+        self._check(self.lib.mvpf_set_tuning(self.h, key.encode(), level, value))
+
+    def get_tuning(self, key: str, level: int = 0) -> int:
+        v = C.c_int()
+        self._check(self.lib.mvpf_get_tuning(self.h, key.encode(), level, C.byref(v)))
+        return v.value
+
+    def autotune(self):
+        out = (C.c_int * 8)()
+        self._check(self.lib.mvpf_autotune(self.h, out))
+        return list(out[: self.prob.n_levels])
 
     def kernel_timing(self, enable: bool):
         self._check(self.lib.mvpf_kernel_timing(self.h, int(enable)))

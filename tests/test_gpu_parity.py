@@ -34,6 +34,9 @@ def case(request):
     oc = OracleCase(p, U, En, p.depth_increment)
     say(f"[case {request.param}] GPU setup")
     gp = gpu_problem(p, U, En, "fp64")
+    # this handle exercises the large-grid row kernels on every level; the
+    # mixed-precision handles below use the default small-grid kernels
+    gp.set_tuning("small_grid_nodes", 0, 0)
     gp.newton_system(p.depth_increment)
     yield request.param, p, U, En, oc, gp
     gp.close()
@@ -186,4 +189,59 @@ def test_newton_time_step_matches_oracle():
         Ug = np.concatenate([u.cpu().numpy(), e.cpu().numpy()], 1)
         assert rel(Ug, Uo) <= 1e-9, rel(Ug, Uo)
         assert np.array_equal(e.cpu().numpy(), en.cpu().numpy()) and d == p.depth_increment
+        gp.close()
+
+
+def test_launch_shape_does_not_change_results():
+    """Persistent launch shapes of the operator kernels (tuning knobs and the
+    autotuner) leave every result bitwise unchanged."""
+    p = synth.tiny()
+    U, En = seeded_state(p, 1e-3)
+    say("[launch shape] default vs minimal grids vs autotuned")
+    outs = []
+    for mode in ("default", "minimal", "autotune"):
+        gp = gpu_problem(p, U, En, "mixed")
+        gp.newton_system(p.depth_increment)
+        if mode == "minimal":
+            for l in range(p.n_levels):
+                gp.set_tuning("row_blocks", l, 8)
+            gp.set_tuning("outer_blocks", 0, 8)
+            assert gp.get_tuning("row_blocks", 0) == 8
+        elif mode == "autotune":
+            shapes = gp.autotune()
+            assert len(shapes) == p.n_levels
+        x, st = gp.solve()
+        outs.append((x.cpu().numpy(), st.iterations))
+        gp.close()
+    for x, its in outs[1:]:
+        assert np.array_equal(x, outs[0][0]) and its == outs[0][1]
+
+
+def test_sixteen_cubed_coarse_1125():
+    """16^3 with 3 levels: the coarsest level has 1125 unknowns, as in the
+    64^3 workload (panel factorisation with 3 rows per thread).  Operators on
+    every level, V-cycle (both row-kernel families) and FGMRES."""
+    p = synth.Problem(16, 16, 16, n_levels=3, patch=4, depth_increment=0.01)
+    U, En = seeded_state(p, 5e-4)
+    say("[16^3] oracle")
+    oc = OracleCase(p, U, En, p.depth_increment, direct=False)
+    rng = np.random.default_rng(6)
+    v = rng.standard_normal(oc.sys.b.shape[0])
+    zo = oc.mg.precondition(v)
+    xo, sto = S.fgmres(oc.sys.A, oc.sys.b, oc.mg.precondition, rtol=1e-12)
+    for small in (0, 40000):
+        say(f"[16^3] GPU small_grid_nodes={small}")
+        gp = gpu_problem(p, U, En, "fp64", rtol=1e-12)
+        gp.set_tuning("small_grid_nodes", 0, small)
+        gp.newton_system(p.depth_increment)
+        b = gp.get_rhs().cpu().numpy()
+        assert max(rel_blocks(b, oc.sys.b)) < 1e-12
+        for l, lev in enumerate(oc.mg.levels):
+            x = rng.standard_normal(lev.A.shape[0])
+            assert max(rel_blocks(gp.jacobian_apply(l, _dev(x)).cpu().numpy(), lev.A @ x)) < 1e-12
+        z = gp.precondition(_dev(v)).cpu().numpy()
+        assert rel(z, zo) < 1e-10, rel(z, zo)
+        x, st = gp.solve()
+        assert st.converged and abs(st.iterations - sto.iterations) <= 1, (st.iterations, sto.iterations)
+        assert rel(x.cpu().numpy(), xo) < 1e-9
         gp.close()
