@@ -485,8 +485,15 @@ void destroy_all(mvpf_problem* p) {
   }
   dfree(p->card); dfree(p->qp); dfree(p->elem); dfree(p->Cbuf); dfree(p->R); dfree(p->rhs); dfree(p->gvec); dfree(p->dx); dfree(p->tmp);
   dfree(p->tmp2); dfree(p->V); dfree(p->Z); dfree(p->red); dfree(p->hcol); dfree(p->save_state);
+  if (p->side) (void)hipStreamSynchronize(p->side);
+  dfree(p->coarse_work);
   if (p->hhost) (void)hipHostFree(p->hhost);
   p->hhost = nullptr;
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  if (p->side) (void)hipStreamDestroy(p->side);
+  p->ev_fork = p->ev_join = nullptr;
+  p->side = nullptr;
   for (KernelTimer* t : {&p->t_sweep, &p->t_outer, &p->t_resid})
     for (hipEvent_t e : t->ev) (void)hipEventDestroy(e);
 }
@@ -501,19 +508,21 @@ int allocate(mvpf_problem* p) {
     L.g = make_grid(M.nx / f, M.ny / f, M.nz / f, M.h * f);
     const bool coarsest = (l == p->L - 1);
     const int64_t nv = nvec(L.g);
-    const int64_t nA = (int64_t)L.g.ntiles * NUP * NBLK * TILE;
-    const int64_t nD = (int64_t)L.g.ntiles * NBLK * TILE;
+    const int64_t nA64 = (int64_t)L.g.ntiles * NUP * Lay<double>::SLICE;
+    const int64_t nA32 = (int64_t)L.g.ntiles * NUP * Lay<float>::SLICE;
+    const int64_t nD64 = (int64_t)L.g.ntiles * Lay<double>::SLICE;
+    const int64_t nD32 = (int64_t)L.g.ntiles * Lay<float>::SLICE;
     TRY(dalloc(p, &L.state, (size_t)NSTATE * L.g.Npad));
     TRY(dalloc(p, &L.mask, (size_t)L.g.Npad));
     if (l == 0) TRY(dalloc(p, &L.target, (size_t)L.g.Npad));
-    if (l == 0 || !p->mixed || coarsest) TRY(dalloc(p, &L.A64, (size_t)nA));
-    if (p->mixed && !coarsest) TRY(dalloc(p, &L.A32, (size_t)nA));
+    if (l == 0 || !p->mixed || coarsest) TRY(dalloc(p, &L.A64, (size_t)nA64));
+    if (p->mixed && !coarsest) TRY(dalloc(p, &L.A32, (size_t)nA32));
     if (!coarsest) {
-      TRY(dalloc(p, &L.diag64, (size_t)nD));
+      TRY(dalloc(p, &L.diag64, (size_t)nD64));
       if (p->mixed)
-        TRY(dalloc(p, &L.Dinv32, (size_t)nD));
+        TRY(dalloc(p, &L.Dinv32, (size_t)nD32));
       else
-        TRY(dalloc(p, &L.Dinv64, (size_t)nD));
+        TRY(dalloc(p, &L.Dinv64, (size_t)nD64));
     }
     const size_t es = p->mixed ? sizeof(float) : sizeof(double);
     for (void** v : {&L.x, &L.x2, &L.b, &L.r}) {
@@ -552,6 +561,17 @@ int allocate(mvpf_problem* p) {
     p->err = "hipHostMalloc failed";
     return MVPF_ENOMEM;
   }
+  HIPCHK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+  {
+    // dense coarse operator + inversion workspace; reuses the Krylov basis V
+    // (idle during assembly) when it is large enough
+    const int nd = p->lev[p->L - 1].ndense;
+    const int64_t need = (int64_t)nd * nd + (int64_t)(dense_invert_work(nd) / sizeof(double)) + 1;
+    const int64_t have = (int64_t)(p->restart_cap + 1) * n;
+    if (need > have) TRY(dalloc(p, &p->coarse_work, (size_t)need));
+  }
   DevCard hc;
   build_card(p->mat, hc);
   HIPCHK(hipMemcpyAsync(p->card, &hc, sizeof(DevCard), hipMemcpyHostToDevice, p->stream));
@@ -581,11 +601,47 @@ int compute_residual(mvpf_problem* p, double depth, double* norm_free) {
   return 0;
 }
 
+// reassembly of level l >= 1 at its injected state (Sec. 3.4: rediscretised
+// coarse operators); the state must already be injected
+void assemble_coarse_level(mvpf_problem* p, int l) {
+  Level& C = p->lev[l];
+  launch_qp(C.g, C.state, p->card, p->qp, true, p->stream);
+  launch_element_matrices(C.g, p->qp, p->card, p->elem, p->stream);
+  launch_jacobian_gather(C.g, p->elem, C.A64, C.A32, C.diag64, p->stream);
+  launch_apply_dirichlet(C.g, C.mask, C.A64, C.A32, C.diag64, p->stream);
+}
+
+int* setup_status(mvpf_problem* p) { return (int*)p->red; }  // first word of the reduction scratch
+
+// The coarsest operator is assembled first; its dense gather and inversion
+// then run on the side stream while the main stream assembles the finer
+// levels.  setup_solver joins the two streams.
 int build_system(mvpf_problem* p, double depth) {
   hipStream_t s = p->stream;
   Level& L0 = p->lev[0];
+  const int Lc = p->L - 1;
+  HIPCHK(hipMemsetAsync(setup_status(p), 0, sizeof(int), s));
   launch_dirichlet_masks(L0.g, p->load, depth, L0.mask, L0.target, s);
-  for (int l = 1; l < p->L; ++l) launch_inject_mask(p->lev[l - 1].g, p->lev[l].g, p->lev[l - 1].mask, p->lev[l].mask, s);
+  for (int l = 1; l < p->L; ++l) {
+    launch_inject_mask(p->lev[l - 1].g, p->lev[l].g, p->lev[l - 1].mask, p->lev[l].mask, s);
+    launch_inject(p->lev[l - 1].g, p->lev[l].g, p->lev[l - 1].state, p->lev[l].state, s);
+  }
+  // coarsest level, then its inversion on the side stream
+  assemble_coarse_level(p, Lc);
+  TRY(launch_check(p, "coarse assembly"));
+  {
+    Level& C = p->lev[Lc];
+    const int nd = C.ndense;
+    double* work = p->coarse_work ? p->coarse_work : p->V;
+    HIPCHK(hipEventRecord(p->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+    launch_dense_from_bsr(C.g, C.A64, work, p->side);
+    dense_invert(nd, work, C.Ainv, work + (int64_t)nd * nd, setup_status(p), p->side);
+    HIPCHK(hipEventRecord(p->ev_join, p->side));
+    p->coarse_pending = true;
+    TRY(launch_check(p, "coarse inversion"));
+  }
+  for (int l = Lc - 1; l >= 1; --l) assemble_coarse_level(p, l);
   // finest: residual and unconstrained tangent
   launch_qp(L0.g, L0.state, p->card, p->qp, true, s);
   launch_residual_gather(L0.g, L0.state, p->qp, p->card, p->R, s);
@@ -596,48 +652,26 @@ int build_system(mvpf_problem* p, double depth) {
   launch_spmv<double, double, double>(L0.g, L0.A64, p->gvec, p->tmp, p->Cbuf, s);
   launch_newton_rhs(L0.g, L0.mask, p->R, p->tmp, p->gvec, p->rhs, s);
   launch_apply_dirichlet(L0.g, L0.mask, L0.A64, L0.A32, L0.diag64, s);
-  // coarse levels: reassembly at the injected state
-  for (int l = 1; l < p->L; ++l) {
-    Level& F = p->lev[l - 1];
-    Level& C = p->lev[l];
-    launch_inject(F.g, C.g, F.state, C.state, s);
-    launch_qp(C.g, C.state, p->card, p->qp, true, s);
-    launch_element_matrices(C.g, p->qp, p->card, p->elem, s);
-    launch_jacobian_gather(C.g, p->elem, C.A64, C.A32, C.diag64, s);
-    launch_apply_dirichlet(C.g, C.mask, C.A64, C.A32, C.diag64, s);
-  }
   TRY(launch_check(p, "assembly"));
   return 0;
 }
 
+// block inverses of the smoother; joins the coarse inversion
 int setup_solver(mvpf_problem* p) {
   hipStream_t s = p->stream;
-  int* status = (int*)p->red;  // first word of the reduction scratch
-  HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
+  int* status = setup_status(p);
   for (int l = 0; l < p->L - 1; ++l) {
     Level& L = p->lev[l];
     launch_block_inverse(L.g, L.diag64, L.Dinv64, L.Dinv32, status, s);
   }
-  Level& C = p->lev[p->L - 1];
-  const int nd = C.ndense;
-  // dense operator in tmp-sized scratch: use V (>= (m+1) * 9 * Npad doubles)
-  const int64_t need = (int64_t)nd * nd + (int64_t)(dense_invert_work(nd) / sizeof(double)) + 1;
-  const int64_t have = (int64_t)(p->restart_cap + 1) * nvec(p->lev[0].g);
-  double* work = nullptr;
-  bool own = false;
-  if (need <= have) {
-    work = p->V;
-  } else {
-    HIPCHK(hipMalloc((void**)&work, sizeof(double) * need));
-    own = true;
+  if (p->coarse_pending) {
+    HIPCHK(hipStreamWaitEvent(s, p->ev_join, 0));
+    p->coarse_pending = false;
   }
-  launch_dense_from_bsr(C.g, C.A64, work, s);
-  dense_invert(nd, work, C.Ainv, work + (int64_t)nd * nd, status, s);
   TRY(launch_check(p, "solver setup"));
   int hs = 0;
   HIPCHK(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (own) (void)hipFree(work);
   if (hs) {
     p->err = "singular 9x9 diagonal block or coarse operator";
     return MVPF_ESINGULAR;

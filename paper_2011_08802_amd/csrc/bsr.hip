@@ -52,7 +52,6 @@ __device__ __forceinline__ void upper_pass(const Grid& g, const TA* __restrict__
                                            TC acc[9], TC* __restrict__ C) {
   const int t = n >> 6, l = n & 63;
   const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
-  const int64_t slice = (int64_t)NBLK * TILE;
   TC xn[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) xn[c] = (TC)x[(int64_t)c * g.Npad + n];
@@ -65,18 +64,30 @@ __device__ __forceinline__ void upper_pass(const Grid& g, const TA* __restrict__
     TC xv[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) xv[c] = (TC)x[(int64_t)c * g.Npad + m];
-    const TA* Ab = A + ((int64_t)t * NUP + u) * slice + l;
+    using VT = typename Vec16<TA>::type;
+    constexpr int V = Lay<TA>::V;
+    const VT* Ab = reinterpret_cast<const VT*>(A + ((int64_t)t * NUP + u) * Lay<TA>::SLICE) + l;
     TC ct[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    TC sum[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < Lay<TA>::NQ; ++q) {
+      const VT vq = Ab[q * TILE];
+      TA av[V];
+      __builtin_memcpy(av, &vq, sizeof(VT));
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int e = q * V + v;
+        if (e < NBLK) {
+          const int r = e / 9, c = e % 9;
+          const TC a = (TC)av[v];
+          sum[r] += a * xv[c];
+          ct[c] += a * xn[r];
+        }
+      }
+    }
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
-      TC sum = 0;
-#pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        const TC a = (TC)Ab[(r * 9 + c) * TILE];
-        sum += a * xv[c];
-        ct[c] += a * xn[r];
-      }
-      if (SUB) acc[r] -= sum; else acc[r] += sum;
+      if (SUB) acc[r] -= sum[r]; else acc[r] += sum[r];
     }
     if (u > 0) {
       TC* Cu = C + (int64_t)(u - 1) * 9 * g.Npad + m;
@@ -190,7 +201,7 @@ __global__ void __launch_bounds__(256) pbj_zero_kernel(Grid g, const T* __restri
   ROW_LOOP(g) {
     if (n >= g.Npad) continue;
     const int t = n >> 6, l = n & 63;
-    const T* Db = Dinv + (int64_t)t * NBLK * TILE + l;
+    const T* Db = Dinv + (int64_t)t * Lay<T>::SLICE;
     T bv[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) bv[c] = b[(int64_t)c * g.Npad + n];
@@ -198,7 +209,7 @@ __global__ void __launch_bounds__(256) pbj_zero_kernel(Grid g, const T* __restri
     for (int r = 0; r < 9; ++r) {
       T s = 0;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) s += Db[(r * 9 + c) * TILE] * bv[c];
+      for (int c = 0; c < 9; ++c) s += Db[Lay<T>::off(r * 9 + c, l)] * bv[c];
       xo[(int64_t)r * g.Npad + n] = (n < g.N) ? omega * s : (T)0;
     }
   }
@@ -214,12 +225,12 @@ __global__ void __launch_bounds__(256) pbj_lower_kernel(Grid g, const T* __restr
     for (int c = 0; c < 9; ++c) res[c] = xo[(int64_t)c * g.Npad + n];
     lower_pass<true>(g, n, res, C);
     const int t = n >> 6, l = n & 63;
-    const T* Db = Dinv + (int64_t)t * NBLK * TILE + l;
+    const T* Db = Dinv + (int64_t)t * Lay<T>::SLICE;
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
       T s = 0;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) s += Db[(r * 9 + c) * TILE] * res[c];
+      for (int c = 0; c < 9; ++c) s += Db[Lay<T>::off(r * 9 + c, l)] * res[c];
       xo[(int64_t)r * g.Npad + n] = x[(int64_t)r * g.Npad + n] + omega * s;
     }
   }
@@ -267,23 +278,24 @@ __global__ void __launch_bounds__(256) row_small_kernel(Grid g, const T* __restr
       T xv[9];
 #pragma unroll
       for (int c = 0; c < 9; ++c) xv[c] = x[(int64_t)c * g.Npad + m];
-      const int64_t slice = (int64_t)NBLK * TILE;
       if (s >= 13) {
-        const T* Ab = A + ((int64_t)(n >> 6) * NUP + (s - 13)) * slice + (n & 63);
+        const T* Ab = A + ((int64_t)(n >> 6) * NUP + (s - 13)) * Lay<T>::SLICE;
+        const int ll = n & 63;
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
           T acc = 0;
 #pragma unroll
-          for (int c = 0; c < 9; ++c) acc += Ab[(r * 9 + c) * TILE] * xv[c];
+          for (int c = 0; c < 9; ++c) acc += Ab[Lay<T>::off(r * 9 + c, ll)] * xv[c];
           pr[r] = acc;
         }
       } else {
-        const T* Ab = A + ((int64_t)(m >> 6) * NUP + (13 - s)) * slice + (m & 63);
+        const T* Ab = A + ((int64_t)(m >> 6) * NUP + (13 - s)) * Lay<T>::SLICE;
+        const int ll = m & 63;
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
           T acc = 0;
 #pragma unroll
-          for (int c = 0; c < 9; ++c) acc += Ab[(c * 9 + r) * TILE] * xv[c];
+          for (int c = 0; c < 9; ++c) acc += Ab[Lay<T>::off(c * 9 + r, ll)] * xv[c];
           pr[r] = acc;
         }
       }
@@ -306,10 +318,10 @@ __global__ void __launch_bounds__(256) row_small_kernel(Grid g, const T* __restr
     if (!PBJ) {
       out[(int64_t)r2 * g.Npad + n2] = res[ln2][r2];
     } else {
-      const T* Db = Dinv + (int64_t)(n2 >> 6) * NBLK * TILE + (n2 & 63);
+      const T* Db = Dinv + (int64_t)(n2 >> 6) * Lay<T>::SLICE;
       T acc = 0;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) acc += Db[(r2 * 9 + c) * TILE] * res[ln2][c];
+      for (int c = 0; c < 9; ++c) acc += Db[Lay<T>::off(r2 * 9 + c, n2 & 63)] * res[ln2][c];
       out[(int64_t)r2 * g.Npad + n2] = x[(int64_t)r2 * g.Npad + n2] + omega * acc;
     }
   }

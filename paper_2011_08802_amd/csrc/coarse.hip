@@ -22,10 +22,10 @@ __global__ void __launch_bounds__(256) dense_from_bsr_kernel(Grid g, const doubl
     const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
     if (i + dx < 0 || i + dx >= g.nnx || j + dy < 0 || j + dy >= g.nny || k + dz < 0 || k + dz >= g.nnz) continue;
     const int m = n + dx + g.nnx * (dy + g.nny * dz);
-    const double* Ab = A + ((int64_t)(t * NUP + u) * NBLK) * TILE + l;
+    const double* Ab = A + (int64_t)(t * NUP + u) * Lay<double>::SLICE;
     for (int r = 0; r < 9; ++r)
       for (int c = 0; c < 9; ++c) {
-        const double v = Ab[(r * 9 + c) * TILE];
+        const double v = Ab[Lay<double>::off(r * 9 + c, l)];
         D[((int64_t)r * g.N + n) * nd + (int64_t)c * g.N + m] = v;
         if (u > 0) D[((int64_t)c * g.N + m) * nd + (int64_t)r * g.N + n] = v;  // lower half by symmetry
       }
@@ -85,44 +85,43 @@ __device__ __forceinline__ void block_argmax(double& v, int& idx, double* sv, in
 }
 
 // Panel factorisation.  Thread t owns rows t, t + GJ_THREADS, ... (RPT of
-// them) and keeps their panel entries in registers; the pivot row is broadcast
-// through LDS.  n <= GJ_THREADS * RPT.
-template <int RPT>
+// them) and keeps their panel entries (PB <= GJB columns) in registers; the
+// pivot row is broadcast through LDS.  n <= GJ_THREADS * RPT, B <= PB.
+template <int RPT, int PB>
 __global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int B, const double* __restrict__ M,
                                                               double* __restrict__ F, int* __restrict__ done,
                                                               int* __restrict__ prow, int* __restrict__ pos,
                                                               double* __restrict__ Pinv, int* status) {
   __shared__ double sv[GJ_THREADS / 64];
   __shared__ int si[GJ_THREADS / 64];
-  __shared__ double prowv[GJB];
-  __shared__ double Mp[GJB][2 * GJB];
-  __shared__ double fr[GJB];
-  __shared__ int pr[GJB];
+  __shared__ double prowv[PB];
+  __shared__ double Mp[PB][2 * PB];
+  __shared__ double fr[PB];
+  __shared__ int pr[PB];
   const int tid = threadIdx.x;
   const int64_t w = 2 * (int64_t)n;
-  double W[RPT][GJB];
+  double W[RPT][PB];
   bool act[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int i = tid + q * GJ_THREADS;
     act[q] = i < n && !done[i];
 #pragma unroll
-    for (int b = 0; b < GJB; ++b) {
+    for (int b = 0; b < PB; ++b) {
       const double v = (i < n && b < B) ? M[(int64_t)i * w + c0 + b] : 0.0;
       W[q][b] = v;
       if (i < n && b < B) F[(int64_t)i * B + b] = v;
     }
   }
+  // Register window: after each step the rows' entries shift left by one, so
+  // the active panel column is always W[q][0] (all register indices static).
 #pragma unroll 1
   for (int jj = 0; jj < B; ++jj) {
     double v = -1.0;
     int idx = -1;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      double cand = -1.0;
-#pragma unroll
-      for (int b = 0; b < GJB; ++b)
-        if (b == jj) cand = fabs(W[q][b]);
+      const double cand = fabs(W[q][0]);
       if (act[q] && cand > v) { v = cand; idx = tid + q * GJ_THREADS; }
     }
     block_argmax(v, idx, sv, si);
@@ -138,7 +137,7 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int
         if (qq == q) {
           act[qq] = false;
 #pragma unroll
-          for (int b = 0; b < GJB; ++b) prowv[b] = W[qq][b];
+          for (int b = 0; b < PB; ++b) prowv[b] = W[qq][b];
         }
       done[p] = 1;
       prow[c0 + jj] = p;
@@ -146,21 +145,13 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int
       pr[jj] = p;
     }
     __syncthreads();
-    double pvj = 0.0;
-#pragma unroll
-    for (int b = 0; b < GJB; ++b)
-      if (b == jj) pvj = prowv[b];
-    const double ip = 1.0 / pvj;
+    const double ip = 1.0 / prowv[0];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      if (!act[q]) continue;
-      double f = 0.0;
+      const double f = act[q] ? W[q][0] * ip : 0.0;
 #pragma unroll
-      for (int b = 0; b < GJB; ++b)
-        if (b == jj) f = W[q][b] * ip;
-#pragma unroll
-      for (int b = 0; b < GJB; ++b)
-        if (b > jj) W[q][b] -= f * prowv[b];
+      for (int b = 1; b < PB; ++b) W[q][b - 1] = W[q][b] - f * prowv[b];
+      W[q][PB - 1] = 0.0;
     }
     __syncthreads();
   }
@@ -295,20 +286,22 @@ int dense_invert(int n, double* a, double* inv, double* work, int* status, hipSt
   int* pos = prow + n;
   gj_init_kernel<<<1024, 256, 0, s>>>(n, a, M, done, pos);
   const int64_t w = 2 * (int64_t)n;
-  for (int c0 = 0; c0 < n; c0 += GJB) {
-    const int B = std::min(GJB, n - c0);
+  // panel width: the rows' panel entries must fit in registers
+  const int PBW = n <= 2 * GJ_THREADS ? 32 : n <= 4 * GJ_THREADS ? 16 : n <= 8 * GJ_THREADS ? 8 : 4;
+  for (int c0 = 0; c0 < n; c0 += PBW) {
+    const int B = std::min(PBW, n - c0);
     if (n <= GJ_THREADS)
-      gj_panel_kernel<1><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
+      gj_panel_kernel<1, 32><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
     else if (n <= 2 * GJ_THREADS)
-      gj_panel_kernel<2><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
+      gj_panel_kernel<2, 32><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
     else if (n <= 3 * GJ_THREADS)
-      gj_panel_kernel<3><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
+      gj_panel_kernel<3, 16><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
     else if (n <= 4 * GJ_THREADS)
-      gj_panel_kernel<4><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
+      gj_panel_kernel<4, 16><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
     else if (n <= 8 * GJ_THREADS)
-      gj_panel_kernel<8><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
+      gj_panel_kernel<8, 8><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
     else
-      gj_panel_kernel<16><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
+      gj_panel_kernel<16, 4><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
     gj_rows_kernel<<<dim3((int)std::min<int64_t>((w + 255) / 256, 64), B), 256, 0, s>>>(n, c0, B, M, prow, Pinv, R);
     gj_update_kernel<<<dim3((int)((w + 255) / 256), (n + 31) / 32), 256, 0, s>>>(n, c0, B, M, F, R, pos);
   }

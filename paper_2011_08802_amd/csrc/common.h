@@ -6,18 +6,21 @@
 //  * state:   15 FP64 components [u_x,u_y,u_z, eta_1..6, eta_n_1..6] in the
 //    same SoA layout.
 //  * 9x9 block operators on the structured 27-point stencil, symmetric half
-//    storage, tiled SoA: A[((t * 14 + u) * 81 + e) * 64 + l] is entry
-//    e = 9*row + col of the block coupling node n = 64 t + l with its neighbour
-//    n + off(13 + u), where s = (dz+1)*9 + (dy+1)*3 + (dx+1) numbers the 27
+//    storage, tiled: slice (t, u) = A + (t * 14 + u) * Lay<T>::SLICE holds the
+//    block coupling node n = 64 t + l with its neighbour n + off(13 + u); entry
+//    e = 9*row + col of lane l sits at Lay<T>::off(e, l), i.e. each lane's
+//    entries come in groups of V = 16 / sizeof(T) (one 16-byte load), and the
+//    64 lanes' groups are contiguous (one 1 KB coalesced wavefront load).
+//    s = (dz+1)*9 + (dy+1)*3 + (dx+1) numbers the 27
 //    offsets and s >= 13 are the diagonal and the 13 offsets with a positive
 //    node-index difference.  The operator is symmetric (a Hessian, with
 //    symmetric Dirichlet elimination), so the block for offset s < 13 is the
 //    transpose of the stored block (n + off(s), 26 - s).  Blocks of
-//    out-of-grid neighbours and of padding rows are zero.  One wavefront reads
-//    one (tile, u, e) slice of 64 consecutive values per load.
+//    out-of-grid neighbours and of padding rows are zero.
 //  * element matrices during assembly: E[(p * 81 + e) * NEpad + el] for the
 //    36 node pairs p = (a <= b) of element el.
-//  * block inverses D^-1: Dinv[(t * 81 + e) * 64 + l].
+//  * diagonal blocks and their inverses: slice t = D + t * Lay<T>::SLICE, same
+//    entry layout.
 //  * per-Gauss-point scratch: qp[(comp * 8 + g) * NEpad + e].
 #pragma once
 #include <hip/hip_runtime.h>
@@ -55,6 +58,23 @@ struct Grid {
 };
 
 Grid make_grid(int nx, int ny, int nz, double h);
+
+// Entry layout inside a 64-lane block slice (see the file comment).
+template <typename T>
+struct Lay {
+  static constexpr int V = 16 / (int)sizeof(T);                 // entries per 16-byte load
+  static constexpr int NE = (NBLK + V - 1) / V * V;             // padded entries per lane
+  static constexpr int NQ = NE / V;                             // 16-byte loads per block
+  static constexpr int64_t SLICE = (int64_t)NE * TILE;
+  __host__ __device__ static constexpr int64_t off(int e, int l) { return ((int64_t)(e / V) * TILE + l) * V + e % V; }
+};
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> { typedef float4 type; };
+template <>
+struct Vec16<double> { typedef double2 type; };
 
 struct Level {
   Grid g;
@@ -124,6 +144,12 @@ struct mvpf_problem {
   int outer_G = 0;                     // launch shape of the outer FP64 operator product
   int small_nodes = mvpf::SMALL_GRID_NODES;  // levels up to this size use the small-grid kernels
   mvpf::KernelTimer t_sweep, t_outer, t_resid;
+  // the coarsest-level inversion runs on a second stream (default priority),
+  // overlapping the assembly of the finer levels
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  double* coarse_work = nullptr;     // dense scratch when V is too small
+  bool coarse_pending = false;
 };
 
 namespace mvpf {

@@ -181,9 +181,14 @@ __global__ void __launch_bounds__(EM_WAVES * 64) element_matrix_kernel(Grid g, c
                                                                        const DevCard* __restrict__ cd,
                                                                        double* __restrict__ E) {
   __shared__ double Ds[120 * 64];
+  // the NPAIR / EM_WAVES pair chunks of one element group are consecutive
+  // logical blocks on one XCD, so the group's Hessians are read from HBM once
+  // and then hit that XCD's L2
   const int groups = g.NEpad / 64;
-  const int eg = blockIdx.x % groups;
-  const int pc = blockIdx.x / groups;  // pair chunk
+  const int Lb = xcd_logical(blockIdx.x, gridDim.x);
+  if (Lb >= groups * (NPAIR / EM_WAVES)) return;  // uniform; before any barrier
+  const int eg = Lb / (NPAIR / EM_WAVES);
+  const int pc = Lb % (NPAIR / EM_WAVES);  // pair chunk
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int p = pc * EM_WAVES + w;     // pair 0..35
   int a = 0, rem = p;
@@ -254,7 +259,8 @@ __global__ void __launch_bounds__(EM_WAVES * 64) element_matrix_kernel(Grid g, c
 
 void launch_element_matrices(const Grid& g, const double* qp, const DevCard* cd, double* elem, hipStream_t s) {
   const int groups = g.NEpad / 64;
-  element_matrix_kernel<<<groups * (NPAIR / EM_WAVES), EM_WAVES * 64, 0, s>>>(g, qp, cd, elem);
+  const int nb = groups * (NPAIR / EM_WAVES);
+  element_matrix_kernel<<<(nb + 7) / 8 * 8, EM_WAVES * 64, 0, s>>>(g, qp, cd, elem);
 }
 
 // Stored block (n, n + off(13 + u)) = sum over the <= 8 elements containing
@@ -273,8 +279,9 @@ __global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, const doubl
   const int dx = sten % 3 - 1, dy = (sten / 3) % 3 - 1, dz = sten / 9 - 1;
   const bool inside = n < g.N;
   const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
-  const int64_t base = ((int64_t)(t * NUP + u) * NBLK) * TILE + l;
-  const int64_t db = (int64_t)t * NBLK * TILE + l;
+  const int64_t base64 = (int64_t)(t * NUP + u) * Lay<double>::SLICE;
+  const int64_t base32 = (int64_t)(t * NUP + u) * Lay<float>::SLICE;
+  const int64_t db = (int64_t)t * Lay<double>::SLICE;
   // three chunks of three block rows keep 27 accumulators live
   for (int r0 = 0; r0 < 9; r0 += 3) {
     double K[27];
@@ -304,15 +311,15 @@ __global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, const doubl
     }
     if (A64) {
 #pragma unroll
-      for (int q = 0; q < 27; ++q) A64[base + (int64_t)(9 * r0 + q) * TILE] = K[q];
+      for (int q = 0; q < 27; ++q) A64[base64 + Lay<double>::off(9 * r0 + q, l)] = K[q];
     }
     if (A32) {
 #pragma unroll
-      for (int q = 0; q < 27; ++q) A32[base + (int64_t)(9 * r0 + q) * TILE] = (float)K[q];
+      for (int q = 0; q < 27; ++q) A32[base32 + Lay<float>::off(9 * r0 + q, l)] = (float)K[q];
     }
     if (u == 0 && diag64) {
 #pragma unroll
-      for (int q = 0; q < 27; ++q) diag64[db + (int64_t)(9 * r0 + q) * TILE] = K[q];
+      for (int q = 0; q < 27; ++q) diag64[db + Lay<double>::off(9 * r0 + q, l)] = K[q];
     }
   }
 }
@@ -343,15 +350,16 @@ __global__ void __launch_bounds__(64) apply_dirichlet_kernel(Grid g, const uint1
   const int m = n + dx + g.nnx * (dy + g.nny * dz);
   const unsigned mr = mask[n], mc = mask[m];
   if ((mr | mc) == 0) return;
-  const int64_t base = ((int64_t)(t * NUP + u) * NBLK) * TILE + l;
-  const int64_t db = (int64_t)t * NBLK * TILE + l;
+  const int64_t base64 = (int64_t)(t * NUP + u) * Lay<double>::SLICE;
+  const int64_t base32 = (int64_t)(t * NUP + u) * Lay<float>::SLICE;
+  const int64_t db = (int64_t)t * Lay<double>::SLICE;
   for (int e = 0; e < 81; ++e) {
     const int r = e / 9, c = e % 9;
     if (((mr >> r) & 1) || ((mc >> c) & 1)) {
       const double v = (u == 0 && r == c) ? 1.0 : 0.0;
-      if (A64) A64[base + (int64_t)e * TILE] = v;
-      if (A32) A32[base + (int64_t)e * TILE] = (float)v;
-      if (u == 0 && diag64) diag64[db + (int64_t)e * TILE] = v;
+      if (A64) A64[base64 + Lay<double>::off(e, l)] = v;
+      if (A32) A32[base32 + Lay<float>::off(e, l)] = (float)v;
+      if (u == 0 && diag64) diag64[db + Lay<double>::off(e, l)] = v;
     }
   }
 }
@@ -375,13 +383,14 @@ __global__ void __launch_bounds__(BI_THREADS) block_inverse_kernel(Grid g, const
   const int n = blockIdx.x * BI_THREADS + threadIdx.x;
   const int t = n / TILE, l = n % TILE, lt = threadIdx.x;
   if (n >= g.Npad) return;
-  const int64_t db = (int64_t)t * NBLK * TILE + l;
+  const int64_t db = (int64_t)t * Lay<double>::SLICE;
+  const int64_t db32 = (int64_t)t * Lay<float>::SLICE;
 #define MM(r, c) M[((r) * 18 + (c)) * BI_THREADS + lt]
   bool ok = n < g.N;
   if (ok) {
     for (int r = 0; r < 9; ++r)
       for (int c = 0; c < 9; ++c) {
-        MM(r, c) = diag64[db + (int64_t)(9 * r + c) * TILE];
+        MM(r, c) = diag64[db + Lay<double>::off(9 * r + c, l)];
         MM(r, 9 + c) = (r == c) ? 1.0 : 0.0;
       }
     for (int c = 0; c < 9; ++c) {
@@ -411,8 +420,8 @@ __global__ void __launch_bounds__(BI_THREADS) block_inverse_kernel(Grid g, const
   }
   for (int e = 0; e < 81; ++e) {
     const double v = ok ? MM(e / 9, 9 + e % 9) : 0.0;
-    if (Dinv64) Dinv64[db + (int64_t)e * TILE] = v;
-    if (Dinv32) Dinv32[db + (int64_t)e * TILE] = (float)v;
+    if (Dinv64) Dinv64[db + Lay<double>::off(e, l)] = v;
+    if (Dinv32) Dinv32[db32 + Lay<float>::off(e, l)] = (float)v;
   }
 #undef MM
 }
