@@ -43,20 +43,35 @@ void launch_dense_from_bsr(const Grid& g, const double* A64, double* dense, hipS
   dense_from_bsr_kernel<<<(g.N + 255) / 256, 256, 0, s>>>(g, A64, dense);
 }
 
-// Blocked Gauss-Jordan inversion with partial pivoting on the augmented
-// matrix M = [A | I] (n x 2n, row-major), panels of GJB columns.  For panel
-// columns c0..c0+B-1:
-//   1. gj_panel: one workgroup snapshots the panel F = M[:, panel] (kept in
-//      registers), chooses the pivot rows P by Gauss-Jordan with partial
-//      pivoting restricted to the panel (rows pivoted earlier are excluded),
-//      and inverts the B x B pivot block Mp = F[P, :] (Gauss-Jordan with
-//      partial pivoting in LDS);
-//   2. gj_rows: R = Mp^-1 M[P, :] (the new pivot rows);
+// Two-level blocked Gauss-Jordan inversion with partial pivoting.
+//
+// M = [A | Y] is n x 2n, row-major.  Y starts at zero; the k-th pivot row
+// p_k (the row chosen for column k) gets its unit vector e_{p_k} placed in
+// column n + k at the moment it is chosen, so the right half ends up holding
+// T e_{p_k}, where T is the product of all elimination steps.  Since
+// T A = E with E[p_k][k] = 1, row k of A^-1 is row p_k of T, i.e.
+// A^-1[k][p_m] = M[p_k][n + m].
+//
+// Outer panels of NB columns c0 .. c0 + nbw - 1.  Inside a panel, sub-panels
+// of PB columns are eliminated with partial pivoting by
+//   1. gj_panel: one workgroup snapshots the sub-panel F = M[:, sub-panel]
+//      in registers, chooses the pivot rows by Gauss-Jordan with partial
+//      pivoting restricted to the sub-panel (rows pivoted earlier are
+//      excluded), places the unit columns and inverts the pivot block
+//      Mp = F[P, :] (Gauss-Jordan with partial pivoting in LDS);
+//   2. gj_rows: R = Mp^-1 M[P, active] (the new pivot rows);
 //   3. gj_update: rows in P become R, every other row i becomes
-//      M[i, :] - F[i, :] R, which zeroes its panel columns.
-// After the last panel the left half is a permutation (row prow[c] holds the
-// unit entry of column c) and A^-1 row c = right half of row prow[c].
-constexpr int GJB = 32;
+//      M[i, active] - F[i, :] R,
+// where "active" is only the outer panel's 2 nbw columns [c0, c0 + nbw) and
+// [n + c0, n + c0 + nbw).  Columns outside the active set are either
+// untouched by these steps (eliminated unit columns, zero columns of Y) or
+// are updated once per outer panel: with T_o the panel's accumulated
+// transformation, T_o - I is non-zero only in the columns p_k, whose values
+// T_o e_{p_k} - e_{p_k} =: Yo[:, k] sit in the right half, so
+//   M[:, rest] += Yo * M_old[P, rest],   rest = [c0 + nbw, n + c0)
+// (gj_gather copies Yo and the old pivot rows; gj_gemm does the product).
+constexpr int GJB = 32;   // widest sub-panel
+constexpr int GJ_NB = 128;  // outer panel width
 constexpr int GJ_THREADS = 512;
 
 // argmax of v (ties: lowest index; idx < 0 = no candidate) over the block
@@ -84,14 +99,15 @@ __device__ __forceinline__ void block_argmax(double& v, int& idx, double* sv, in
   idx = si[0];
 }
 
-// Panel factorisation.  Thread t owns rows t, t + GJ_THREADS, ... (RPT of
-// them) and keeps their panel entries (PB <= GJB columns) in registers; the
-// pivot row is broadcast through LDS.  n <= GJ_THREADS * RPT, B <= PB.
+// Sub-panel factorisation (columns c0 .. c0 + B - 1).  Thread t owns rows t,
+// t + GJ_THREADS, ... (RPT of them) and keeps their sub-panel entries (PB >= B
+// columns) in registers; the pivot row is broadcast through LDS.
+// n <= GJ_THREADS * RPT.
 template <int RPT, int PB>
-__global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int B, const double* __restrict__ M,
+__global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int B, double* __restrict__ M,
                                                               double* __restrict__ F, int* __restrict__ done,
-                                                              int* __restrict__ prow, int* __restrict__ pos,
-                                                              double* __restrict__ Pinv, int* status) {
+                                                              int* __restrict__ prow, double* __restrict__ Pinv,
+                                                              int* status) {
   __shared__ double sv[GJ_THREADS / 64];
   __shared__ int si[GJ_THREADS / 64];
   __shared__ double prowv[PB];
@@ -114,7 +130,7 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int
     }
   }
   // Register window: after each step the rows' entries shift left by one, so
-  // the active panel column is always W[q][0] (all register indices static).
+  // the active column is always W[q][0] (all register indices static).
 #pragma unroll 1
   for (int jj = 0; jj < B; ++jj) {
     double v = -1.0;
@@ -141,8 +157,8 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int
         }
       done[p] = 1;
       prow[c0 + jj] = p;
-      pos[p] = c0 + jj;
       pr[jj] = p;
+      M[(int64_t)p * w + n + c0 + jj] = 1.0;  // unit column of the new pivot
     }
     __syncthreads();
     const double ip = 1.0 / prowv[0];
@@ -197,47 +213,61 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int
   for (int idx = tid; idx < B * B; idx += blockDim.x) Pinv[idx] = Mp[idx / B][B + idx % B];
 }
 
-// R[a][c] = sum_b Pinv[a][b] M[prow[c0 + b]][c]
-__global__ void __launch_bounds__(256) gj_rows_kernel(int n, int c0, int B, const double* __restrict__ M,
-                                                      const int* __restrict__ prow, const double* __restrict__ Pinv,
-                                                      double* __restrict__ R) {
-  const int64_t w = 2 * (int64_t)n;
-  const int a = blockIdx.y;
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < w; c += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < B; ++b) s += Pinv[a * B + b] * M[(int64_t)prow[c0 + b] * w + c];
-    R[(int64_t)a * w + c] = s;
-  }
+// active column j (0 .. 2 nbw - 1) of the outer panel at c0
+__device__ __forceinline__ int64_t gj_col(int n, int c0, int nbw, int j) {
+  return j < nbw ? (int64_t)c0 + j : (int64_t)n + c0 + (j - nbw);
 }
 
-// M[i][c] = R[pos(i)][c] for pivot rows of this panel, else M[i][c] - F[i,:] R[:, c].
-// Block: 32 rows x 256 columns; R column strip kept in registers.
-__global__ void __launch_bounds__(256) gj_update_kernel(int n, int c0, int B, double* __restrict__ M,
-                                                        const double* __restrict__ F, const double* __restrict__ R,
-                                                        const int* __restrict__ pos) {
+// R[a][j] = sum_b Pinv[a][b] M[prow[s0 + b]][col(j)] over the active columns
+__global__ void __launch_bounds__(256) gj_rows_kernel(int n, int c0, int nbw, int s0, int B,
+                                                      const double* __restrict__ M, const int* __restrict__ prow,
+                                                      const double* __restrict__ Pinv, double* __restrict__ R) {
+  const int64_t w = 2 * (int64_t)n;
+  const int a = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= 2 * nbw) return;
+  const int64_t c = gj_col(n, c0, nbw, j);
+  double s = 0.0;
+  for (int b = 0; b < B; ++b) s += Pinv[a * B + b] * M[(int64_t)prow[s0 + b] * w + c];
+  R[(int64_t)a * 2 * nbw + j] = s;
+}
+
+// Over the active columns: rows pivoted in this sub-panel become R, every
+// other row i becomes M[i] - F[i, :] R.  Block: 32 rows x 256 columns.
+__global__ void __launch_bounds__(256) gj_update_kernel(int n, int c0, int nbw, int s0, int B,
+                                                        double* __restrict__ M, const double* __restrict__ F,
+                                                        const double* __restrict__ R, const int* __restrict__ prow) {
   __shared__ double Fs[32][GJB];
+  __shared__ int sub[32];  // sub-panel position of each row, or -1
   const int64_t w = 2 * (int64_t)n;
   const int r0 = blockIdx.y * 32;
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.x * 256 + threadIdx.x;
   for (int idx = threadIdx.x; idx < 32 * GJB; idx += 256) {
     const int rr = idx / GJB, b = idx % GJB;
     Fs[rr][b] = (r0 + rr < n && b < B) ? F[(int64_t)(r0 + rr) * B + b] : 0.0;
   }
+  if (threadIdx.x < 32) sub[threadIdx.x] = -1;
   __syncthreads();
-  if (c >= w) return;
+  if (threadIdx.x < B) {
+    const int pr = prow[s0 + threadIdx.x];
+    if (pr >= r0 && pr < r0 + 32) sub[pr - r0] = threadIdx.x;
+  }
+  __syncthreads();
+  if (j >= 2 * nbw) return;
+  const int64_t c = gj_col(n, c0, nbw, j);
   double Rc[GJB];
 #pragma unroll
-  for (int b = 0; b < GJB; ++b) Rc[b] = (b < B) ? R[(int64_t)b * w + c] : 0.0;
+  for (int b = 0; b < GJB; ++b) Rc[b] = (b < B) ? R[(int64_t)b * 2 * nbw + j] : 0.0;
   for (int rr = 0; rr < 32; ++rr) {
     const int i = r0 + rr;
     if (i >= n) break;
-    const int pi = pos[i];
+    const int pi = sub[rr];
     double v;
-    if (pi >= c0 && pi < c0 + B) {
+    if (pi >= 0) {
       v = Rc[0];
 #pragma unroll
       for (int b = 1; b < GJB; ++b)
-        if (b == pi - c0) v = Rc[b];
+        if (b == pi) v = Rc[b];
     } else {
       v = M[(int64_t)i * w + c];
 #pragma unroll
@@ -247,63 +277,144 @@ __global__ void __launch_bounds__(256) gj_update_kernel(int n, int c0, int B, do
   }
 }
 
+// Yo[i][k] = M[i][n + c0 + k] - [i == p_{c0+k}];  Rb[k][j] = M[p_{c0+k}][c0 + nbw + j]
+__global__ void __launch_bounds__(256) gj_gather_kernel(int n, int c0, int nbw, const double* __restrict__ M,
+                                                        const int* __restrict__ prow, double* __restrict__ Yo,
+                                                        double* __restrict__ Rb) {
+  const int64_t w = 2 * (int64_t)n;
+  const int64_t nr = n - nbw;
+  const int64_t ny = (int64_t)n * nbw, nrb = (int64_t)nbw * nr;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ny + nrb;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    if (idx < ny) {
+      const int64_t i = idx / nbw;
+      const int k = (int)(idx - i * nbw);
+      Yo[idx] = M[i * w + n + c0 + k] - ((int)i == prow[c0 + k] ? 1.0 : 0.0);
+    } else {
+      const int64_t t = idx - ny;
+      const int k = (int)(t / nr);
+      const int64_t jj = t - (int64_t)k * nr;
+      Rb[t] = M[(int64_t)prow[c0 + k] * w + c0 + nbw + jj];
+    }
+  }
+}
+
+// M[i][c0 + nbw + j] += sum_k Yo[i][k] Rb[k][j]  (i < n, j < n - nbw).
+// 64 x 64 output tile per workgroup, 4 x 4 per thread, K staged in LDS by 16.
+constexpr int GT = 64, GK = 16;
+__global__ void __launch_bounds__(256) gj_gemm_kernel(int n, int c0, int nbw, const double* __restrict__ Yo,
+                                                      const double* __restrict__ Rb, double* __restrict__ M) {
+  __shared__ double Ys[GK][GT + 1];
+  __shared__ double Rs[GK][GT + 1];
+  const int64_t w = 2 * (int64_t)n;
+  const int nr = n - nbw;
+  const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int k0 = 0; k0 < nbw; k0 += GK) {
+    for (int idx = threadIdx.x; idx < GK * GT; idx += 256) {
+      const int kk = idx % GK, ii = idx / GK;   // Yo: consecutive threads walk k
+      const int i = i0 + ii, k = k0 + kk;
+      Ys[kk][ii] = (i < n && k < nbw) ? Yo[(int64_t)i * nbw + k] : 0.0;
+      const int jj = idx % GT, kr = idx / GT;   // Rb: consecutive threads walk j
+      const int jc = j0 + jj, k2 = k0 + kr;
+      Rs[kr][jj] = (jc < nr && k2 < nbw) ? Rb[(int64_t)k2 * nr + jc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { a[q] = Ys[kk][ty + 16 * q]; b[q] = Rs[kk][tx + 16 * q]; }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int i = i0 + ty + 16 * x;
+    if (i >= n) continue;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int jc = j0 + tx + 16 * y;
+      if (jc < nr) M[(int64_t)i * w + c0 + nbw + jc] += acc[x][y];
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) gj_init_kernel(int n, const double* __restrict__ a, double* __restrict__ M,
-                                                      int* __restrict__ done, int* __restrict__ pos) {
+                                                      int* __restrict__ done) {
   const int64_t w = 2 * (int64_t)n;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)n * w;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx / w, c = idx - i * w;
-    M[idx] = (c < n) ? a[i * n + c] : ((c - n == i) ? 1.0 : 0.0);
-    if (c == 0) { done[i] = 0; pos[i] = -1; }
+    M[idx] = (c < n) ? a[i * n + c] : 0.0;
+    if (c == 0) done[i] = 0;
   }
 }
 
+// A^-1[k][p_m] = M[p_k][n + m]
 __global__ void __launch_bounds__(256) gj_extract_kernel(int n, const double* __restrict__ M,
                                                          const int* __restrict__ prow, double* __restrict__ inv) {
   const int64_t w = 2 * (int64_t)n;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)n * n;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = idx / n, c = idx - i * n;
-    inv[idx] = M[(int64_t)prow[i] * w + n + c];
+    const int64_t k = idx / n, m = idx - k * n;
+    inv[k * n + prow[m]] = M[(int64_t)prow[k] * w + n + m];
   }
 }
 
 size_t dense_invert_work(int n) {
-  // M (2n^2) + F, W (n*GJB each) + R (GJB*2n) + Pinv (GJB^2) doubles, then 3n ints
-  return (size_t)(2 * (int64_t)n * n + 2 * (int64_t)n * GJB + 2 * (int64_t)GJB * n + GJB * GJB) * sizeof(double) +
-         (size_t)3 * n * sizeof(int);
+  // M (2n^2) + F (n*GJB) + R (GJB*2*GJ_NB) + Pinv (GJB^2) + Yo (n*GJ_NB) + Rb (GJ_NB*n) doubles, then 2n ints
+  return (size_t)(2 * (int64_t)n * n + (int64_t)n * GJB + 2 * (int64_t)GJB * GJ_NB + GJB * GJB +
+                  2 * (int64_t)n * GJ_NB) * sizeof(double) +
+         (size_t)2 * n * sizeof(int);
 }
 
 // a: n x n input (not modified); inv: n x n output; work: dense_invert_work(n) bytes.
 int dense_invert(int n, double* a, double* inv, double* work, int* status, hipStream_t s) {
   double* M = work;
   double* F = M + 2 * (int64_t)n * n;
-  double* W = F + (int64_t)n * GJB;
-  double* R = W + (int64_t)n * GJB;
-  double* Pinv = R + 2 * (int64_t)GJB * n;
-  int* done = (int*)(Pinv + GJB * GJB);
+  double* R = F + (int64_t)n * GJB;
+  double* Pinv = R + 2 * (int64_t)GJB * GJ_NB;
+  double* Yo = Pinv + GJB * GJB;
+  double* Rb = Yo + (int64_t)n * GJ_NB;
+  int* done = (int*)(Rb + (int64_t)GJ_NB * n);
   int* prow = done + n;
-  int* pos = prow + n;
-  gj_init_kernel<<<1024, 256, 0, s>>>(n, a, M, done, pos);
-  const int64_t w = 2 * (int64_t)n;
-  // panel width: the rows' panel entries must fit in registers
+  gj_init_kernel<<<1024, 256, 0, s>>>(n, a, M, done);
+  // sub-panel width: the rows' sub-panel entries must fit in registers
   const int PBW = n <= 2 * GJ_THREADS ? 32 : n <= 4 * GJ_THREADS ? 16 : n <= 8 * GJ_THREADS ? 8 : 4;
-  for (int c0 = 0; c0 < n; c0 += PBW) {
-    const int B = std::min(PBW, n - c0);
-    if (n <= GJ_THREADS)
-      gj_panel_kernel<1, 32><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
-    else if (n <= 2 * GJ_THREADS)
-      gj_panel_kernel<2, 32><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
-    else if (n <= 3 * GJ_THREADS)
-      gj_panel_kernel<3, 16><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
-    else if (n <= 4 * GJ_THREADS)
-      gj_panel_kernel<4, 16><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
-    else if (n <= 8 * GJ_THREADS)
-      gj_panel_kernel<8, 8><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
-    else
-      gj_panel_kernel<16, 4><<<1, GJ_THREADS, 0, s>>>(n, c0, B, M, F, done, prow, pos, Pinv, status);
-    gj_rows_kernel<<<dim3((int)std::min<int64_t>((w + 255) / 256, 64), B), 256, 0, s>>>(n, c0, B, M, prow, Pinv, R);
-    gj_update_kernel<<<dim3((int)((w + 255) / 256), (n + 31) / 32), 256, 0, s>>>(n, c0, B, M, F, R, pos);
+  for (int c0 = 0; c0 < n; c0 += GJ_NB) {
+    const int nbw = std::min(GJ_NB, n - c0);
+    for (int s0 = c0; s0 < c0 + nbw; s0 += PBW) {
+      const int B = std::min(PBW, c0 + nbw - s0);
+      if (n <= GJ_THREADS)
+        gj_panel_kernel<1, 32><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
+      else if (n <= 2 * GJ_THREADS)
+        gj_panel_kernel<2, 32><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
+      else if (n <= 3 * GJ_THREADS)
+        gj_panel_kernel<3, 16><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
+      else if (n <= 4 * GJ_THREADS)
+        gj_panel_kernel<4, 16><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
+      else if (n <= 8 * GJ_THREADS)
+        gj_panel_kernel<8, 8><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
+      else
+        gj_panel_kernel<16, 4><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
+      gj_rows_kernel<<<dim3((2 * nbw + 255) / 256, B), 256, 0, s>>>(n, c0, nbw, s0, B, M, prow, Pinv, R);
+      gj_update_kernel<<<dim3((2 * nbw + 255) / 256, (n + 31) / 32), 256, 0, s>>>(n, c0, nbw, s0, B, M, F, R,
+                                                                                   prow);
+    }
+    if (n - nbw > 0) {
+      gj_gather_kernel<<<1024, 256, 0, s>>>(n, c0, nbw, M, prow, Yo, Rb);
+      gj_gemm_kernel<<<dim3((n - nbw + GT - 1) / GT, (n + GT - 1) / GT), 256, 0, s>>>(n, c0, nbw, Yo, Rb, M);
+    }
   }
   gj_extract_kernel<<<1024, 256, 0, s>>>(n, M, prow, inv);
   return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -245,3 +245,32 @@ def test_sixteen_cubed_coarse_1125():
         assert st.converged and abs(st.iterations - sto.iterations) <= 1, (st.iterations, sto.iterations)
         assert rel(x.cpu().numpy(), xo) < 1e-9
         gp.close()
+
+
+@pytest.mark.parametrize("n,levels,coarse_dof", [(12, 2, 3087), (16, 2, 6561)])
+def test_large_coarse_inverse(n, levels, coarse_dof):
+    """Two-level hierarchies whose coarsest level is large (6^3 and 8^3
+    elements, the latter the size of the 128^3 workload's coarsest level):
+    blocked Gauss-Jordan with several outer panels and narrow sub-panels.
+    Coarse operator, V-cycle and FGMRES solve vs the oracle."""
+    p = synth.Problem(n, n, n, n_levels=levels, patch=4, depth_increment=0.01)
+    U, En = seeded_state(p, 5e-4)
+    say(f"[{n}^3 L{levels}] oracle (coarse {coarse_dof} dof)")
+    oc = OracleCase(p, U, En, p.depth_increment, direct=False)
+    assert oc.mg.levels[-1].A.shape[0] == coarse_dof
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal(oc.sys.b.shape[0])
+    zo = oc.mg.precondition(v)
+    xo, sto = S.fgmres(oc.sys.A, oc.sys.b, oc.mg.precondition, rtol=1e-12)
+    say(f"[{n}^3 L{levels}] GPU")
+    gp = gpu_problem(p, U, En, "fp64", rtol=1e-12)
+    gp.newton_system(p.depth_increment)
+    x = rng.standard_normal(coarse_dof)
+    yc = gp.jacobian_apply(levels - 1, _dev(x)).cpu().numpy()
+    assert max(rel_blocks(yc, oc.mg.levels[-1].A @ x)) < 1e-12
+    z = gp.precondition(_dev(v)).cpu().numpy()
+    assert rel(z, zo) < 1e-10, rel(z, zo)
+    xs, st = gp.solve()
+    assert st.converged and abs(st.iterations - sto.iterations) <= 1, (st.iterations, sto.iterations)
+    assert rel(xs.cpu().numpy(), xo) < 1e-9
+    gp.close()
