@@ -235,9 +235,13 @@ int mvpf_time_step(mvpf_problem* p, double depth, mvpf_step_stats* stats);
  * cache reach of each other); "outer_blocks": the same for the outer FP64
  * operator product (level ignored); "small_grid_nodes": levels with at most
  * this many nodes use the latency-oriented small-grid smoother and defect
- * kernels (27 threads per row; default 40000; level ignored).  The two kernel
+ * kernels (27 threads per row; default 10000; level ignored).  The two kernel
  * families sum the 27 block products in different orders, so this key alone
- * changes results at rounding level; the others never do. */
+ * changes results at rounding level; the others never do.  "coarse_overlap":
+ * 1 = the coarsest level's dense inversion runs on a second (default
+ * priority) stream, overlapping the assembly of the finer levels; 0 = in
+ * order on the problem's stream before them (default: 1 up to 2048 coarse
+ * unknowns, else 0; level ignored; results unchanged). */
 int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value);
 int mvpf_get_tuning(const mvpf_problem* p, const char* key, int level, int* value);
 /* Time candidate launch shapes of the smoother (every level but the coarsest)

@@ -633,12 +633,24 @@ int build_system(mvpf_problem* p, double depth) {
     Level& C = p->lev[Lc];
     const int nd = C.ndense;
     double* work = p->coarse_work ? p->coarse_work : p->V;
-    HIPCHK(hipEventRecord(p->ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
-    launch_dense_from_bsr(C.g, C.A64, work, p->side);
-    dense_invert(nd, work, C.Ainv, work + (int64_t)nd * nd, setup_status(p), p->side);
-    HIPCHK(hipEventRecord(p->ev_join, p->side));
-    p->coarse_pending = true;
+    // The overlap pays while the inversion is a few hundred launches; for
+    // large coarsest levels its thousands of small launches starve behind
+    // the assembly kernels, and running it first, alone, is faster.
+    const bool overlap = p->coarse_overlap < 0 ? nd <= COARSE_OVERLAP_MAX : p->coarse_overlap != 0;
+    hipStream_t cs = overlap ? p->side : s;
+    if (overlap) {
+      HIPCHK(hipEventRecord(p->ev_fork, s));
+      HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+    }
+    launch_dense_from_bsr(C.g, C.A64, work, cs);
+    if (dense_invert(nd, work, C.Ainv, work + (int64_t)nd * nd, setup_status(p), cs) != 0) {
+      p->err = "coarse inversion launch failed";
+      return MVPF_EDEVICE;
+    }
+    if (overlap) {
+      HIPCHK(hipEventRecord(p->ev_join, p->side));
+      p->coarse_pending = true;
+    }
     TRY(launch_check(p, "coarse inversion"));
   }
   for (int l = Lc - 1; l >= 1; --l) assemble_coarse_level(p, l);
@@ -1052,6 +1064,8 @@ int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value) {
     p->outer_G = value;
   } else if (!std::strcmp(key, "small_grid_nodes")) {
     p->small_nodes = value;
+  } else if (!std::strcmp(key, "coarse_overlap")) {
+    p->coarse_overlap = value;
   } else {
     p->err = "unknown tuning key";
     return MVPF_EINVAL;
@@ -1068,6 +1082,9 @@ int mvpf_get_tuning(const mvpf_problem* p, const char* key, int level, int* valu
     *value = p->outer_G;
   } else if (!std::strcmp(key, "small_grid_nodes")) {
     *value = p->small_nodes;
+  } else if (!std::strcmp(key, "coarse_overlap")) {
+    const int nd = p->lev[p->L - 1].ndense;
+    *value = p->coarse_overlap < 0 ? (nd <= COARSE_OVERLAP_MAX ? 1 : 0) : (p->coarse_overlap != 0);
   } else {
     return MVPF_EINVAL;
   }

@@ -99,6 +99,58 @@ __device__ __forceinline__ void block_argmax(double& v, int& idx, double* sv, in
   idx = si[0];
 }
 
+// Inverse of the pivot block Mp = F[pr[a], b] (B x B, B <= PB) by Gauss-Jordan
+// with partial pivoting, [Mp | I] in LDS; needs blockDim.x >= 2 B.
+template <int PB>
+__device__ void pivot_block_inverse(int B, const double* __restrict__ F, const int* pr, double* __restrict__ Pinv,
+                                    int* status, double (*Mp)[2 * PB], double* fr, double* sv, int* si) {
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < B * B; idx += blockDim.x) {
+    const int a = idx / B, b = idx % B;
+    Mp[a][b] = F[(int64_t)pr[a] * B + b];
+    Mp[a][B + b] = (a == b) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < B; ++c) {
+    if (tid < 64) {  // pivot search over rows c .. B - 1 (B <= 64) in the first wavefront
+      double bv = (tid >= c && tid < B) ? fabs(Mp[tid][c]) : -1.0;
+      int q = (tid >= c && tid < B) ? tid : -1;
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_down(bv, off, 64);
+        const int oq = __shfl_down(q, off, 64);
+        if (oq >= 0 && (ov > bv || (ov == bv && (q < 0 || oq < q)))) { bv = ov; q = oq; }
+      }
+      if (tid == 0) {
+        si[0] = q;
+        sv[0] = bv;
+      }
+    }
+    __syncthreads();
+    const int q = si[0];
+    if (!(sv[0] > 0.0)) {
+      if (tid == 0) atomicOr(status, 1);
+      return;  // uniform
+    }
+    if (q != c && tid < 2 * B) {
+      const double tmp = Mp[c][tid];
+      Mp[c][tid] = Mp[q][tid];
+      Mp[q][tid] = tmp;
+    }
+    __syncthreads();
+    const double ipc = 1.0 / Mp[c][c];
+    __syncthreads();
+    if (tid < 2 * B) Mp[c][tid] *= ipc;
+    if (tid < B) fr[tid] = (tid == c) ? 0.0 : Mp[tid][c];
+    __syncthreads();
+    for (int idx = tid; idx < B * 2 * B; idx += blockDim.x) {
+      const int r = idx / (2 * B), cc = idx % (2 * B);
+      if (r != c) Mp[r][cc] -= fr[r] * Mp[c][cc];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < B * B; idx += blockDim.x) Pinv[idx] = Mp[idx / B][B + idx % B];
+}
+
 // Sub-panel factorisation (columns c0 .. c0 + B - 1).  Thread t owns rows t,
 // t + GJ_THREADS, ... (RPT of them) and keeps their sub-panel entries (PB >= B
 // columns) in registers; the pivot row is broadcast through LDS.
@@ -171,46 +223,7 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int
     }
     __syncthreads();
   }
-  // invert the pivot block Mp = F[P, :] (B x B) with partial pivoting, [Mp | I] in LDS
-  for (int idx = tid; idx < B * B; idx += blockDim.x) {
-    const int a = idx / B, b = idx % B;
-    Mp[a][b] = F[(int64_t)pr[a] * B + b];
-    Mp[a][B + b] = (a == b) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int c = 0; c < B; ++c) {
-    if (tid == 0) {
-      int q = c;
-      double bv = fabs(Mp[c][c]);
-      for (int r = c + 1; r < B; ++r)
-        if (fabs(Mp[r][c]) > bv) { bv = fabs(Mp[r][c]); q = r; }
-      si[0] = q;
-      sv[0] = bv;
-    }
-    __syncthreads();
-    const int q = si[0];
-    if (!(sv[0] > 0.0)) {
-      if (tid == 0) atomicOr(status, 1);
-      return;
-    }
-    if (q != c && tid < 2 * B) {
-      const double tmp = Mp[c][tid];
-      Mp[c][tid] = Mp[q][tid];
-      Mp[q][tid] = tmp;
-    }
-    __syncthreads();
-    const double ipc = 1.0 / Mp[c][c];
-    __syncthreads();
-    if (tid < 2 * B) Mp[c][tid] *= ipc;
-    if (tid < B) fr[tid] = (tid == c) ? 0.0 : Mp[tid][c];
-    __syncthreads();
-    for (int idx = tid; idx < B * 2 * B; idx += blockDim.x) {
-      const int r = idx / (2 * B), cc = idx % (2 * B);
-      if (r != c) Mp[r][cc] -= fr[r] * Mp[c][cc];
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < B * B; idx += blockDim.x) Pinv[idx] = Mp[idx / B][B + idx % B];
+  pivot_block_inverse<PB>(B, F, pr, Pinv, status, Mp, fr, sv, si);
 }
 
 // active column j (0 .. 2 nbw - 1) of the outer panel at c0
@@ -233,24 +246,25 @@ __global__ void __launch_bounds__(256) gj_rows_kernel(int n, int c0, int nbw, in
 }
 
 // Over the active columns: rows pivoted in this sub-panel become R, every
-// other row i becomes M[i] - F[i, :] R.  Block: 32 rows x 256 columns.
+// other row i becomes M[i] - F[i, :] R.  Block: UPR rows x 256 columns.
+constexpr int UPR = 8;
 __global__ void __launch_bounds__(256) gj_update_kernel(int n, int c0, int nbw, int s0, int B,
                                                         double* __restrict__ M, const double* __restrict__ F,
                                                         const double* __restrict__ R, const int* __restrict__ prow) {
-  __shared__ double Fs[32][GJB];
-  __shared__ int sub[32];  // sub-panel position of each row, or -1
+  __shared__ double Fs[UPR][GJB];
+  __shared__ int sub[UPR];  // sub-panel position of each row, or -1
   const int64_t w = 2 * (int64_t)n;
-  const int r0 = blockIdx.y * 32;
+  const int r0 = blockIdx.y * UPR;
   const int j = blockIdx.x * 256 + threadIdx.x;
-  for (int idx = threadIdx.x; idx < 32 * GJB; idx += 256) {
+  for (int idx = threadIdx.x; idx < UPR * GJB; idx += 256) {
     const int rr = idx / GJB, b = idx % GJB;
     Fs[rr][b] = (r0 + rr < n && b < B) ? F[(int64_t)(r0 + rr) * B + b] : 0.0;
   }
-  if (threadIdx.x < 32) sub[threadIdx.x] = -1;
+  if (threadIdx.x < UPR) sub[threadIdx.x] = -1;
   __syncthreads();
   if (threadIdx.x < B) {
     const int pr = prow[s0 + threadIdx.x];
-    if (pr >= r0 && pr < r0 + 32) sub[pr - r0] = threadIdx.x;
+    if (pr >= r0 && pr < r0 + UPR) sub[pr - r0] = threadIdx.x;
   }
   __syncthreads();
   if (j >= 2 * nbw) return;
@@ -258,7 +272,7 @@ __global__ void __launch_bounds__(256) gj_update_kernel(int n, int c0, int nbw, 
   double Rc[GJB];
 #pragma unroll
   for (int b = 0; b < GJB; ++b) Rc[b] = (b < B) ? R[(int64_t)b * 2 * nbw + j] : 0.0;
-  for (int rr = 0; rr < 32; ++rr) {
+  for (int rr = 0; rr < UPR; ++rr) {
     const int i = r0 + rr;
     if (i >= n) break;
     const int pi = sub[rr];
@@ -275,6 +289,112 @@ __global__ void __launch_bounds__(256) gj_update_kernel(int n, int c0, int nbw, 
     }
     M[(int64_t)i * w + c] = v;
   }
+}
+
+// ---- wide sub-panels (n > 4 GJ_THREADS): one launch per column ----------
+// The sub-panel (n x B, B = GJB) does not fit in one workgroup's registers,
+// so it lives column-major in Wc (L2-resident) and every column is one
+// launch over all rows.  Pivot keys pack |v| (bits of a non-negative double
+// are ordered like its value) with the low KEY_BITS bits replaced by
+// (2^KEY_BITS - 1 - row): a 64-bit atomicMax selects the largest magnitude
+// (compared to 39 mantissa bits) and, among equal keys, the lowest row.
+constexpr int KEY_BITS = 13;  // n <= 8192
+__device__ __forceinline__ unsigned long long pivot_key(double a, int i) {
+  const unsigned long long mask = (1ull << KEY_BITS) - 1;
+  return ((unsigned long long)__double_as_longlong(a) & ~mask) | (unsigned long long)(mask - i);
+}
+__device__ __forceinline__ int key_row(unsigned long long k, int n) {
+  const unsigned long long mask = (1ull << KEY_BITS) - 1;
+  if (k <= mask) return -1;  // no candidate with a non-zero magnitude
+  const int i = (int)(mask - (k & mask));
+  return i < n ? i : -1;
+}
+
+// F[i][b] = Wc[b][i] = M[i][s0 + b]
+__global__ void __launch_bounds__(256) gj_fetch_kernel(int n, int s0, int B, const double* __restrict__ M,
+                                                       double* __restrict__ F, double* __restrict__ Wc) {
+  const int64_t w = 2 * (int64_t)n;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * B) return;
+  const int i = (int)(idx / B), b = (int)(idx - (int64_t)i * B);
+  const double v = M[(int64_t)i * w + s0 + b];
+  F[idx] = v;
+  Wc[(int64_t)b * n + i] = v;
+}
+
+// Column jj of the sub-panel at s0 (jj = 0 .. B; jj == B only finalises):
+//  1. the pivot p of column jj - 1 (from its key) is recorded and gets its
+//     unit column; every other active row eliminates column jj - 1 from its
+//     remaining sub-panel entries;
+//  2. the active rows' keys for column jj go to keys[s0 + jj] (wave max, then
+//     one atomicMax per wave).
+__global__ void __launch_bounds__(256) gj_col_kernel(int n, int s0, int B, int jj, double* __restrict__ Wc,
+                                                     unsigned long long* __restrict__ keys, int* __restrict__ done,
+                                                     int* __restrict__ prow, double* __restrict__ M, int* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t w = 2 * (int64_t)n;
+  int p = -1;
+  if (jj > 0) {
+    p = key_row(keys[s0 + jj - 1], n);
+    if (p < 0) {  // no non-zero pivot: singular (uniform over the grid)
+      if (i == 0) atomicOr(status, 1);
+      return;
+    }
+  }
+  const bool act = i < n && !done[i] && i != p;
+  if (jj > 0 && i == p) {
+    done[p] = 1;
+    prow[s0 + jj - 1] = p;
+    M[(int64_t)p * w + n + s0 + jj - 1] = 1.0;
+  }
+  unsigned long long key = 0;
+  if (act) {
+    double* wi = Wc + i;
+    double a = 0.0;
+    if (jj > 0) {
+      // all loads first (own row and pivot row), then the stores
+      const double* wp = Wc + p;
+      const double f = wi[(int64_t)(jj - 1) * n] / wp[(int64_t)(jj - 1) * n];
+      double own[GJB], piv[GJB];
+#pragma unroll
+      for (int b = 0; b < GJB; ++b)
+        if (b >= jj && b < B) {
+          own[b] = wi[(int64_t)b * n];
+          piv[b] = wp[(int64_t)b * n];
+        }
+#pragma unroll
+      for (int b = 0; b < GJB; ++b)
+        if (b >= jj && b < B) {
+          const double v = own[b] - f * piv[b];
+          wi[(int64_t)b * n] = v;
+          if (b == jj) a = fabs(v);
+        }
+    } else if (B > 0) {
+      a = fabs(wi[0]);
+    }
+    if (jj < B && a > 0.0) key = pivot_key(a, i);
+  }
+  if (jj < B) {
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(key, off, 64);
+      key = o > key ? o : key;
+    }
+    if ((threadIdx.x & 63) == 0 && key) atomicMax(&keys[s0 + jj], key);
+  }
+}
+
+// Pinv = inverse of the pivot block of the sub-panel at s0
+__global__ void __launch_bounds__(256) gj_pivinv_kernel(int s0, int B, const double* __restrict__ F,
+                                                        const int* __restrict__ prow, double* __restrict__ Pinv,
+                                                        int* status) {
+  __shared__ double Mp[GJB][2 * GJB];
+  __shared__ double fr[GJB];
+  __shared__ double sv[1];
+  __shared__ int si[1];
+  __shared__ int pr[GJB];
+  if (threadIdx.x < B) pr[threadIdx.x] = prow[s0 + threadIdx.x];
+  __syncthreads();
+  pivot_block_inverse<GJB>(B, F, pr, Pinv, status, Mp, fr, sv, si);
 }
 
 // Yo[i][k] = M[i][n + c0 + k] - [i == p_{c0+k}];  Rb[k][j] = M[p_{c0+k}][c0 + nbw + j]
@@ -350,13 +470,18 @@ __global__ void __launch_bounds__(256) gj_gemm_kernel(int n, int c0, int nbw, co
 }
 
 __global__ void __launch_bounds__(256) gj_init_kernel(int n, const double* __restrict__ a, double* __restrict__ M,
-                                                      int* __restrict__ done) {
+                                                      int* __restrict__ done, int* __restrict__ prow,
+                                                      unsigned long long* __restrict__ keys) {
   const int64_t w = 2 * (int64_t)n;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)n * w;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx / w, c = idx - i * w;
     M[idx] = (c < n) ? a[i * n + c] : 0.0;
-    if (c == 0) done[i] = 0;
+    if (c == 0) {
+      done[i] = 0;
+      prow[i] = 0;  // any valid row until the pivot is chosen
+      keys[i] = 0;
+    }
   }
 }
 
@@ -372,44 +497,52 @@ __global__ void __launch_bounds__(256) gj_extract_kernel(int n, const double* __
 }
 
 size_t dense_invert_work(int n) {
-  // M (2n^2) + F (n*GJB) + R (GJB*2*GJ_NB) + Pinv (GJB^2) + Yo (n*GJ_NB) + Rb (GJ_NB*n) doubles, then 2n ints
-  return (size_t)(2 * (int64_t)n * n + (int64_t)n * GJB + 2 * (int64_t)GJB * GJ_NB + GJB * GJB +
+  // doubles: M (2n^2), F and Wc (n*GJB each), R (GJB*2*GJ_NB), Pinv (GJB^2), Yo and Rb (n*GJ_NB each);
+  // then n 64-bit keys and 2n ints
+  return (size_t)(2 * (int64_t)n * n + 2 * (int64_t)n * GJB + 2 * (int64_t)GJB * GJ_NB + GJB * GJB +
                   2 * (int64_t)n * GJ_NB) * sizeof(double) +
-         (size_t)2 * n * sizeof(int);
+         (size_t)n * sizeof(unsigned long long) + (size_t)2 * n * sizeof(int);
 }
 
 // a: n x n input (not modified); inv: n x n output; work: dense_invert_work(n) bytes.
 int dense_invert(int n, double* a, double* inv, double* work, int* status, hipStream_t s) {
   double* M = work;
   double* F = M + 2 * (int64_t)n * n;
-  double* R = F + (int64_t)n * GJB;
+  double* Wc = F + (int64_t)n * GJB;
+  double* R = Wc + (int64_t)n * GJB;
   double* Pinv = R + 2 * (int64_t)GJB * GJ_NB;
   double* Yo = Pinv + GJB * GJB;
   double* Rb = Yo + (int64_t)n * GJ_NB;
-  int* done = (int*)(Rb + (int64_t)GJ_NB * n);
+  unsigned long long* keys = (unsigned long long*)(Rb + (int64_t)GJ_NB * n);
+  int* done = (int*)(keys + n);
   int* prow = done + n;
-  gj_init_kernel<<<1024, 256, 0, s>>>(n, a, M, done);
-  // sub-panel width: the rows' sub-panel entries must fit in registers
-  const int PBW = n <= 2 * GJ_THREADS ? 32 : n <= 4 * GJ_THREADS ? 16 : n <= 8 * GJ_THREADS ? 8 : 4;
+  if (n > (1 << KEY_BITS)) return -1;
+  gj_init_kernel<<<1024, 256, 0, s>>>(n, a, M, done, prow, keys);
+  // sub-panel width: up to 4 rows per thread the sub-panel is factored in one
+  // workgroup's registers, beyond that one launch per column
+  const bool wide = n > 4 * GJ_THREADS;
+  const int PBW = (wide || n <= 2 * GJ_THREADS) ? GJB : 16;
   for (int c0 = 0; c0 < n; c0 += GJ_NB) {
     const int nbw = std::min(GJ_NB, n - c0);
     for (int s0 = c0; s0 < c0 + nbw; s0 += PBW) {
       const int B = std::min(PBW, c0 + nbw - s0);
-      if (n <= GJ_THREADS)
+      if (wide) {
+        gj_fetch_kernel<<<(int)(((int64_t)n * B + 255) / 256), 256, 0, s>>>(n, s0, B, M, F, Wc);
+        for (int jj = 0; jj <= B; ++jj)
+          gj_col_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, s0, B, jj, Wc, keys, done, prow, M, status);
+        gj_pivinv_kernel<<<1, 256, 0, s>>>(s0, B, F, prow, Pinv, status);
+      } else if (n <= GJ_THREADS) {
         gj_panel_kernel<1, 32><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
-      else if (n <= 2 * GJ_THREADS)
+      } else if (n <= 2 * GJ_THREADS) {
         gj_panel_kernel<2, 32><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
-      else if (n <= 3 * GJ_THREADS)
+      } else if (n <= 3 * GJ_THREADS) {
         gj_panel_kernel<3, 16><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
-      else if (n <= 4 * GJ_THREADS)
+      } else {
         gj_panel_kernel<4, 16><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
-      else if (n <= 8 * GJ_THREADS)
-        gj_panel_kernel<8, 8><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
-      else
-        gj_panel_kernel<16, 4><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
+      }
       gj_rows_kernel<<<dim3((2 * nbw + 255) / 256, B), 256, 0, s>>>(n, c0, nbw, s0, B, M, prow, Pinv, R);
-      gj_update_kernel<<<dim3((2 * nbw + 255) / 256, (n + 31) / 32), 256, 0, s>>>(n, c0, nbw, s0, B, M, F, R,
-                                                                                   prow);
+      gj_update_kernel<<<dim3((2 * nbw + 255) / 256, (n + UPR - 1) / UPR), 256, 0, s>>>(n, c0, nbw, s0, B, M, F,
+                                                                                         R, prow);
     }
     if (n - nbw > 0) {
       gj_gather_kernel<<<1024, 256, 0, s>>>(n, c0, nbw, M, prow, Yo, Rb);

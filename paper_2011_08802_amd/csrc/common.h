@@ -106,6 +106,12 @@ struct KernelTimer {
 
 }  // namespace mvpf
 
+namespace mvpf {
+// coarsest levels up to this many unknowns are inverted on a side stream,
+// overlapping the assembly of the finer levels
+constexpr int COARSE_OVERLAP_MAX = 2048;
+}  // namespace mvpf
+
 struct mvpf_problem {
   mvpf_mesh mesh;
   mvpf_material mat;
@@ -150,6 +156,7 @@ struct mvpf_problem {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double* coarse_work = nullptr;     // dense scratch when V is too small
   bool coarse_pending = false;
+  int coarse_overlap = -1;           // 1: side stream, 0: problem stream, -1: by size
 };
 
 namespace mvpf {
