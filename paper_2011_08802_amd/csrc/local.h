@@ -332,9 +332,12 @@ __device__ __forceinline__ void local_gradient(const double F[9], const double e
   }
 }
 
-// Gradient and packed upper-triangular Hessian D[120] of the local density.
+// Gradient and packed upper-triangular Hessian of the local density; entry
+// hidx(p, q) of the Hessian is stored to D[hidx(p, q) * ds] as soon as it is
+// known (nothing of it is kept in registers).
 __device__ __forceinline__ void local_hessian(const double F[9], const double eh[6], const double ehn[6],
-                                              const DevCard& cd, double g[15], double D[120]) {
+                                              const DevCard& cd, double g[15], double* __restrict__ D,
+                                              int64_t ds) {
   LocalBase b;
   local_base(F, eh, cd, b);
   // ---- second derivatives in C-space -------------------------------------
@@ -475,7 +478,7 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
       for (int u = 0; u < 6; ++u) s += WCq[u] * dc[r][u];
       const int k = r / 3, l = r % 3;
       if (i == k) s += 2.0 * GSG[3 * j + l];
-      D[hidx(q, r)] = b.Jt * s;
+      D[hidx(q, r) * ds] = b.Jt * s;
     }
     // dC_q as a full matrix for the S : d2C term
     double dcq[6] = {dc[q][0], dc[q][1], dc[q][2], dc[q][3], dc[q][4], dc[q][5]};
@@ -491,7 +494,7 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
       s += -2.0 * ddot9(P, dcqf);
 #pragma unroll
       for (int v = 0; v < 6; ++v) s += wCeta[v][k] * dc[q][v];
-      D[hidx(q, 9 + k)] = b.Jt * s + Jq[k] * wq[q];
+      D[hidx(q, 9 + k) * ds] = b.Jt * s + Jq[k] * wq[q];
     }
   }
   // eta-eta block
@@ -537,7 +540,7 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
       // order-parameter terms
       val += cd.Sw[k][l] + cd.rho * ((k == l ? 1.0 : 0.0) + 1.0) + pen0;
       if (k == l && eta[k + 1] < 0.0) val += cd.eps;
-      D[hidx(9 + k, 9 + l)] = val;
+      D[hidx(9 + k, 9 + l) * ds] = val;
     }
   }
   // order-parameter gradient terms

@@ -82,10 +82,7 @@ __global__ void __launch_bounds__(128) qp_kernel(Grid g, const double* __restric
   double* out = qp + (int64_t)gp * g.NEpad + e;
   double gr[15];
   if (HESS) {
-    double D[120];
-    local_hessian(F, eh, ehn, *cd, gr, D);
-#pragma unroll
-    for (int c = 0; c < 120; ++c) out[(int64_t)(15 + c) * stride] = D[c];
+    local_hessian(F, eh, ehn, *cd, gr, out + (int64_t)15 * stride, stride);
   } else {
     local_gradient(F, eh, ehn, *cd, gr);
   }
@@ -177,7 +174,7 @@ __host__ __device__ constexpr int pair_index(int a, int b) {  // a <= b < 8
 // accumulators in registers (no spills).
 constexpr int EM_WAVES = 4;
 
-__global__ void __launch_bounds__(EM_WAVES * 64) element_matrix_kernel(Grid g, const double* __restrict__ qp,
+__global__ void __launch_bounds__(EM_WAVES * 64, 2) element_matrix_kernel(Grid g, const double* __restrict__ qp,
                                                                        const DevCard* __restrict__ cd,
                                                                        double* __restrict__ E) {
   __shared__ double Ds[120 * 64];
@@ -202,9 +199,20 @@ __global__ void __launch_bounds__(EM_WAVES * 64) element_matrix_kernel(Grid g, c
   for (int q = 0; q < 81; ++q) K[q] = 0.0;
   for (int gp = 0; gp < 8; ++gp) {
     __syncthreads();
-    for (int idx = threadIdx.x; idx < 120 * 64; idx += EM_WAVES * 64) {
-      const int comp = idx >> 6, el = idx & 63;
-      Ds[idx] = qp[(int64_t)(15 + comp) * stride + (int64_t)gp * g.NEpad + eg * 64 + el];
+    {
+      // direct global -> LDS loads (no registers involved): each wavefront
+      // instruction moves two Hessian components of the group's 64 elements,
+      // lanes 0-31 component c and lanes 32-63 component c + 1, 16 B (two
+      // elements) per lane, landing at LDS base + 16 * lane
+      const double* src = qp + (int64_t)(15 + 2 * w + (l >> 5)) * stride + (int64_t)gp * g.NEpad + eg * 64 +
+                          2 * (l & 31);
+#pragma unroll
+      for (int r = 0; r < 120 / (2 * EM_WAVES); ++r) {
+        const int c = 2 * (w + EM_WAVES * r);
+        __builtin_amdgcn_global_load_lds((const void*)(src + (int64_t)(2 * EM_WAVES * r) * stride),
+                                         (__attribute__((address_space(3))) void*)(Ds + c * 64), 16, 0, 0);
+      }
+      __builtin_amdgcn_s_waitcnt(0);
     }
     __syncthreads();
     const Shape sa = shape(gp, a), sb = shape(gp, b);
