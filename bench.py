@@ -37,6 +37,7 @@ WORKLOADS = {
     "tiny": synth.tiny,
     "medium": synth.medium,
     "large": synth.large,
+    "scale": synth.scale_limit,
 }
 
 
@@ -181,7 +182,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+f32",
         "data": "synthetic",
-        "config": {"workload": f"patch indentation {prob.nx}x{prob.ny}x{prob.nz} Q1 hex, "
+        "config": {"workload": f"{'patch' if prob.kind == 'patch' else 'spherical-cap'} indentation "
+                               f"{prob.nx}x{prob.ny}x{prob.nz} Q1 hex, "
                                f"{ndof} dof, {prob.n_levels}-level GMG V(2,2), FGMRES(30) rtol 1e-8",
                    "nx": prob.nx, "ny": prob.ny, "nz": prob.nz, "levels": prob.n_levels,
                    "depth": prob.depth_increment, "seed": prob.seed, "precision": "mixed"},

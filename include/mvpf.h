@@ -241,7 +241,13 @@ int mvpf_time_step(mvpf_problem* p, double depth, mvpf_step_stats* stats);
  * 1 = the coarsest level's dense inversion runs on a second (default
  * priority) stream, overlapping the assembly of the finer levels; 0 = in
  * order on the problem's stream before them (default: 1 up to 2048 coarse
- * unknowns, else 0; level ignored; results unchanged). */
+ * unknowns, else 0; level ignored; results unchanged).
+ * "assembly_slab_elements": elements per assembly slab (0 = the capacity
+ * allocated by mvpf_create: the whole finest level if its Gauss-point and
+ * element-matrix buffers take at most 96 GiB, else slabs of 40 GiB).  Levels
+ * with more elements are assembled in slabs of whole element layers, one
+ * halo layer recomputed per slab; at least 2 nx ny + 64, at most the
+ * capacity; level ignored; results bitwise unchanged. */
 int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value);
 int mvpf_get_tuning(const mvpf_problem* p, const char* key, int level, int* value);
 /* Time candidate launch shapes of the smoother (every level but the coarsest)

@@ -28,6 +28,28 @@ Grid make_grid(int nx, int ny, int nz, double h) {
   return g;
 }
 
+std::vector<Chunk> make_chunks(const Grid& g, int64_t ne_cap) {
+  std::vector<Chunk> out;
+  if ((int64_t)g.NEpad <= ne_cap) {
+    out.push_back(Chunk{0, g.NE, g.NEpad, 0, g.Npad});
+    return out;
+  }
+  const int64_t nxy = (int64_t)g.nx * g.ny, nnxy = (int64_t)g.nnx * g.nny;
+  const int L = (int)std::max<int64_t>((ne_cap - (TILE - 1)) / nxy - 1, 1);  // node layers per slab
+  for (int k0 = 0; k0 < g.nnz; k0 += L) {
+    const int k1 = std::min(k0 + L, g.nnz);
+    const int ez0 = std::max(k0 - 1, 0), ez1 = std::min(k1, g.nz);
+    Chunk c;
+    c.e0 = ez0 * nxy;
+    c.NEc = (int)((ez1 - ez0) * nxy);
+    c.NEcpad = (c.NEc + TILE - 1) / TILE * TILE;
+    c.n0 = (int)(k0 * nnxy);
+    c.n1 = (k1 == g.nnz) ? g.Npad : (int)(k1 * nnxy);
+    out.push_back(c);
+  }
+  return out;
+}
+
 }  // namespace mvpf
 
 namespace {
@@ -538,8 +560,20 @@ int allocate(mvpf_problem* p) {
   const Grid& g0 = p->lev[0].g;
   const int64_t n = nvec(g0);
   TRY(dalloc(p, &p->card, 1));
-  TRY(dalloc(p, &p->qp, (size_t)QP_HESS * 8 * g0.NEpad));
-  TRY(dalloc(p, &p->elem, (size_t)NPAIR * NBLK * g0.NEpad));
+  {
+    // Gauss-point and element-matrix buffers: the whole finest level if that
+    // fits ASSEMBLY_FULL_MAX bytes, else slabs of ASSEMBLY_SLAB_BYTES
+    const int64_t per = (int64_t)(QP_HESS * 8 + NPAIR * NBLK) * (int64_t)sizeof(double);
+    const int64_t nxy = (int64_t)g0.nx * g0.ny;
+    if ((int64_t)g0.NEpad * per <= ASSEMBLY_FULL_MAX)
+      p->ne_cap = g0.NEpad;
+    else
+      p->ne_cap = std::max<int64_t>(ASSEMBLY_SLAB_BYTES / per, 2 * nxy + TILE) / TILE * TILE;
+    p->ne_cap = std::min<int64_t>(p->ne_cap, g0.NEpad);
+    p->ne_use = p->ne_cap;
+    TRY(dalloc(p, &p->qp, (size_t)QP_HESS * 8 * p->ne_cap));
+    TRY(dalloc(p, &p->elem, (size_t)NPAIR * NBLK * p->ne_cap));
+  }
   {
     double* cb = nullptr;
     TRY(dalloc(p, &cb, (size_t)(NUP - 1) * NDOF * g0.Npad));
@@ -594,8 +628,10 @@ int free_norm(mvpf_problem* p, const double* v, double* out) {
 int compute_residual(mvpf_problem* p, double depth, double* norm_free) {
   Level& L0 = p->lev[0];
   launch_dirichlet_masks(L0.g, p->load, depth, L0.mask, L0.target, p->stream);
-  launch_qp(L0.g, L0.state, p->card, p->qp, false, p->stream);
-  launch_residual_gather(L0.g, L0.state, p->qp, p->card, p->R, p->stream);
+  for (const Chunk& ck : make_chunks(L0.g, p->ne_use)) {
+    launch_qp(L0.g, ck, L0.state, p->card, p->qp, false, p->stream);
+    launch_residual_gather(L0.g, ck, L0.state, p->qp, p->card, p->R, p->stream);
+  }
   TRY(launch_check(p, "residual"));
   if (norm_free) TRY(free_norm(p, p->R, norm_free));
   return 0;
@@ -605,9 +641,11 @@ int compute_residual(mvpf_problem* p, double depth, double* norm_free) {
 // coarse operators); the state must already be injected
 void assemble_coarse_level(mvpf_problem* p, int l) {
   Level& C = p->lev[l];
-  launch_qp(C.g, C.state, p->card, p->qp, true, p->stream);
-  launch_element_matrices(C.g, p->qp, p->card, p->elem, p->stream);
-  launch_jacobian_gather(C.g, p->elem, C.A64, C.A32, C.diag64, p->stream);
+  for (const Chunk& ck : make_chunks(C.g, p->ne_use)) {
+    launch_qp(C.g, ck, C.state, p->card, p->qp, true, p->stream);
+    launch_element_matrices(C.g, ck, p->qp, p->card, p->elem, p->stream);
+    launch_jacobian_gather(C.g, ck, p->elem, C.A64, C.A32, C.diag64, p->stream);
+  }
   launch_apply_dirichlet(C.g, C.mask, C.A64, C.A32, C.diag64, p->stream);
 }
 
@@ -655,10 +693,12 @@ int build_system(mvpf_problem* p, double depth) {
   }
   for (int l = Lc - 1; l >= 1; --l) assemble_coarse_level(p, l);
   // finest: residual and unconstrained tangent
-  launch_qp(L0.g, L0.state, p->card, p->qp, true, s);
-  launch_residual_gather(L0.g, L0.state, p->qp, p->card, p->R, s);
-  launch_element_matrices(L0.g, p->qp, p->card, p->elem, s);
-  launch_jacobian_gather(L0.g, p->elem, L0.A64, L0.A32, L0.diag64, s);
+  for (const Chunk& ck : make_chunks(L0.g, p->ne_use)) {
+    launch_qp(L0.g, ck, L0.state, p->card, p->qp, true, s);
+    launch_residual_gather(L0.g, ck, L0.state, p->qp, p->card, p->R, s);
+    launch_element_matrices(L0.g, ck, p->qp, p->card, p->elem, s);
+    launch_jacobian_gather(L0.g, ck, p->elem, L0.A64, L0.A32, L0.diag64, s);
+  }
   // lifting of the prescribed increment, then symmetric elimination
   launch_increment(L0.g, L0.mask, L0.target, L0.state, p->gvec, s);
   launch_spmv<double, double, double>(L0.g, L0.A64, p->gvec, p->tmp, p->Cbuf, s);
@@ -1066,6 +1106,14 @@ int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value) {
     p->small_nodes = value;
   } else if (!std::strcmp(key, "coarse_overlap")) {
     p->coarse_overlap = value;
+  } else if (!std::strcmp(key, "assembly_slab_elements")) {
+    // 0 = the allocated capacity; at least two element layers
+    const int64_t lo = 2 * (int64_t)p->lev[0].g.nx * p->lev[0].g.ny + TILE;
+    if (value != 0 && (value < lo || value > p->ne_cap)) {
+      p->err = "assembly_slab_elements out of range";
+      return MVPF_EINVAL;
+    }
+    p->ne_use = value == 0 ? p->ne_cap : value;
   } else {
     p->err = "unknown tuning key";
     return MVPF_EINVAL;
@@ -1082,6 +1130,8 @@ int mvpf_get_tuning(const mvpf_problem* p, const char* key, int level, int* valu
     *value = p->outer_G;
   } else if (!std::strcmp(key, "small_grid_nodes")) {
     *value = p->small_nodes;
+  } else if (!std::strcmp(key, "assembly_slab_elements")) {
+    *value = (int)p->ne_use;
   } else if (!std::strcmp(key, "coarse_overlap")) {
     const int nd = p->lev[p->L - 1].ndense;
     *value = p->coarse_overlap < 0 ? (nd <= COARSE_OVERLAP_MAX ? 1 : 0) : (p->coarse_overlap != 0);

@@ -59,6 +59,19 @@ struct Grid {
 
 Grid make_grid(int nx, int ny, int nz, double h);
 
+// A slab of the assembly: elements e0 .. e0 + NEc - 1 (whole element layers,
+// stored at local index e - e0 in the Gauss-point and element-matrix
+// buffers, padded to NEcpad) feed node rows n0 .. n1 - 1 (whole node layers;
+// the last slab also owns the padding rows up to Npad).  Slabs of one level
+// overlap by one element layer, which is assembled twice.
+struct Chunk {
+  int64_t e0;
+  int NEc, NEcpad;
+  int n0, n1;
+};
+// Slabs of at most ne_cap padded elements each (one slab if the level fits).
+std::vector<Chunk> make_chunks(const Grid& g, int64_t ne_cap);
+
 // Entry layout inside a 64-lane block slice (see the file comment).
 template <typename T>
 struct Lay {
@@ -110,6 +123,9 @@ namespace mvpf {
 // coarsest levels up to this many unknowns are inverted on a side stream,
 // overlapping the assembly of the finer levels
 constexpr int COARSE_OVERLAP_MAX = 2048;
+// assembly buffers: the whole finest level up to this size, else slabs
+constexpr int64_t ASSEMBLY_FULL_MAX = (int64_t)96 << 30;
+constexpr int64_t ASSEMBLY_SLAB_BYTES = (int64_t)40 << 30;
 }  // namespace mvpf
 
 struct mvpf_problem {
@@ -157,17 +173,21 @@ struct mvpf_problem {
   double* coarse_work = nullptr;     // dense scratch when V is too small
   bool coarse_pending = false;
   int coarse_overlap = -1;           // 1: side stream, 0: problem stream, -1: by size
+  int64_t ne_cap = 0;                // element capacity of qp / elem (assembly slab size)
+  int64_t ne_use = 0;                // slab size in use (<= ne_cap)
 };
 
 namespace mvpf {
 
 // ---- launchers (all asynchronous on `s`) ----------------------------------
 // quadrature / assembly
-void launch_qp(const Grid& g, const double* state, const DevCard* cd, double* qp, bool hess, hipStream_t s);
-void launch_residual_gather(const Grid& g, const double* state, const double* qp, const DevCard* cd,
+void launch_qp(const Grid& g, const Chunk& ck, const double* state, const DevCard* cd, double* qp, bool hess,
+               hipStream_t s);
+void launch_residual_gather(const Grid& g, const Chunk& ck, const double* state, const double* qp, const DevCard* cd,
                             double* R, hipStream_t s);
-void launch_element_matrices(const Grid& g, const double* qp, const DevCard* cd, double* elem, hipStream_t s);
-void launch_jacobian_gather(const Grid& g, const double* elem, double* A64, float* A32, double* diag64,
+void launch_element_matrices(const Grid& g, const Chunk& ck, const double* qp, const DevCard* cd, double* elem,
+                             hipStream_t s);
+void launch_jacobian_gather(const Grid& g, const Chunk& ck, const double* elem, double* A64, float* A32, double* diag64,
                             hipStream_t s);
 void launch_apply_dirichlet(const Grid& g, const uint16_t* mask, double* A64, float* A32, double* diag64,
                             hipStream_t s);

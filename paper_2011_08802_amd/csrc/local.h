@@ -283,6 +283,34 @@ __device__ __forceinline__ void dC_of(const LocalBase& b, const DevCard& cd, int
   dc[3] = dcf[5]; dc[4] = dcf[2]; dc[5] = dcf[1];
 }
 
+// Q_k = G dU_k (full)
+__device__ __forceinline__ void Q_of(const LocalBase& b, const DevCard& cd, int k, double Q[9]) {
+  double dU[9];
+  full_from_sym(cd.dU[k], dU);
+  mm(b.G, dU, Q);
+}
+
+// dC/deta_k = -(Q_k C + C Q_k^T) as symmetric components (and full)
+__device__ __forceinline__ void dC_eta(const LocalBase& b, const double Q[9], double dc[6], double dcf[9]) {
+  double X[9];
+  mm(Q, b.C, X);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dcf[3 * a + c] = -(X[3 * a + c] + X[3 * c + a]);
+  dc[0] = dcf[0]; dc[1] = dcf[4]; dc[2] = dcf[8];
+  dc[3] = dcf[5]; dc[4] = dcf[2]; dc[5] = dcf[1];
+}
+
+// dC/dF_ij (q = 3 i + j) as symmetric components
+__device__ __forceinline__ void dC_F(const LocalBase& b, int q, double dc[6]) {
+  const int i = q / 3, j = q % 3;
+  // dcf[a][c] = Fe[i][a] G[c][j] + G[a][j] Fe[i][c]
+  auto f = [&](int a, int c) { return b.Fe[3 * i + a] * b.G[3 * c + j] + b.G[3 * a + j] * b.Fe[3 * i + c]; };
+  dc[0] = f(0, 0); dc[1] = f(1, 1); dc[2] = f(2, 2);
+  dc[3] = f(1, 2); dc[4] = f(0, 2); dc[5] = f(0, 1);
+}
+
 __device__ __forceinline__ double neg_part(double x) { return x < 0.0 ? x : 0.0; }
 
 // Gradient of the local density: g[15].
@@ -427,85 +455,38 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
     }
   }
   // ---- chain rule ---------------------------------------------------------
+  // Few arrays stay live: dC along F is rebuilt from F G and G when needed,
+  // Q_k = G dU_k from the card, and the eta-eta products pair by pair.
   // S: symmetric tensor with S : dC = sum_v wC_v dc_v
   double Sf[9];
   {
     double Ss[6] = {b.wC[0], b.wC[1], b.wC[2], 0.5 * b.wC[3], 0.5 * b.wC[4], 0.5 * b.wC[5]};
     full_from_sym(Ss, Sf);
   }
-  double GS[9], GSG[9];
-  mm(b.G, Sf, GS);
-  mm(GS, b.G, GSG);
-  double dc[15][6];
-  double wq[15];
-  double Jq[6];
-#pragma unroll
-  for (int q = 0; q < 15; ++q) {
-    double dcf[9];
-    dC_of(b, cd, q, dc[q], dcf);
-    double s = 0.0;
-#pragma unroll
-    for (int v = 0; v < 6; ++v) s += b.wC[v] * dc[q][v];
-    wq[q] = s + (q >= 9 ? b.wEta[q - 9] : 0.0);
+  double GSG[9];
+  {
+    double GS[9];
+    mm(b.G, Sf, GS);
+    mm(GS, b.G, GSG);
   }
-  double Qk[6][9];
+  // per eta_k: dC (dce), dw/deta_k (wqe), dJ_t (Jq), and Ak[k][v] = wCeta[v][k] - 2 (S Q_k) : E_v
+  double dce[6][6], wqe[6], Jq[6], Ak[6][6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    double dU[9];
-    full_from_sym(cd.dU[k], dU);
-    mm(b.G, dU, Qk[k]);
-    Jq[k] = b.Jt * (Qk[k][0] + Qk[k][4] + Qk[k][8]);
-  }
+    double Q[9], dcf[9], P[9];
+    Q_of(b, cd, k, Q);
+    Jq[k] = b.Jt * (Q[0] + Q[4] + Q[8]);
+    dC_eta(b, Q, dce[k], dcf);
+    double s = b.wEta[k];
 #pragma unroll
-  for (int q = 0; q < 15; ++q) g[q] = b.Jt * wq[q] + (q >= 9 ? Jq[q - 9] * b.w : 0.0);
-
-  // F-F and F-eta blocks
+    for (int v = 0; v < 6; ++v) s += b.wC[v] * dce[k][v];
+    wqe[k] = s;
+    mm(Sf, Q, P);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    double WCq[6];
-#pragma unroll
-    for (int u = 0; u < 6; ++u) {
-      double s = 0.0;
-#pragma unroll
-      for (int v = 0; v < 6; ++v) s += wCC[u][v] * dc[q][v];
-      WCq[u] = s;
-    }
-    const int i = q / 3, j = q % 3;
-#pragma unroll
-    for (int r = q; r < 9; ++r) {
-      double s = 0.0;
-#pragma unroll
-      for (int u = 0; u < 6; ++u) s += WCq[u] * dc[r][u];
-      const int k = r / 3, l = r % 3;
-      if (i == k) s += 2.0 * GSG[3 * j + l];
-      D[hidx(q, r) * ds] = b.Jt * s;
-    }
-    // dC_q as a full matrix for the S : d2C term
-    double dcq[6] = {dc[q][0], dc[q][1], dc[q][2], dc[q][3], dc[q][4], dc[q][5]};
-    double dcqf[9];
-    full_from_sym(dcq, dcqf);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      double P[9];
-      mm(Sf, Qk[k], P);  // S G dU_k
-      double s = 0.0;
-#pragma unroll
-      for (int u = 0; u < 6; ++u) s += WCq[u] * dc[9 + k][u];
-      s += -2.0 * ddot9(P, dcqf);
-#pragma unroll
-      for (int v = 0; v < 6; ++v) s += wCeta[v][k] * dc[q][v];
-      D[hidx(q, 9 + k) * ds] = b.Jt * s + Jq[k] * wq[q];
-    }
+    for (int v = 0; v < 6; ++v) Ak[k][v] = wCeta[v][k] - 2.0 * contract_basis(P, v);
+    g[9 + k] = b.Jt * wqe[k] + Jq[k] * b.w;
   }
   // eta-eta block
-  double Rk[6][9], Uk[6][9];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    double SQ[9];
-    mm(Sf, Qk[k], SQ);
-    mm(b.C, SQ, Rk[k]);   // C S Q_k
-    mm(SQ, b.C, Uk[k]);   // S Q_k C
-  }
   double eta[7], etan[7];
   {
     double s = 0.0, sn = 0.0;
@@ -517,30 +498,75 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
   const double pen0 = (eta[0] < 0.0) ? cd.eps : 0.0;
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    double WCk[6];
+    double Qk[9], SQ[9], Rk[9], Uk[9], WCk[6];
+    Q_of(b, cd, k, Qk);
+    mm(Sf, Qk, SQ);
+    mm(b.C, SQ, Rk);  // C S Q_k
+    mm(SQ, b.C, Uk);  // S Q_k C
 #pragma unroll
     for (int u = 0; u < 6; ++u) {
       double s = 0.0;
 #pragma unroll
-      for (int v = 0; v < 6; ++v) s += wCC[u][v] * dc[9 + k][v];
+      for (int v = 0; v < 6; ++v) s += wCC[u][v] * dce[k][v];
       WCk[u] = s;
     }
-    const double trk = Qk[k][0] + Qk[k][4] + Qk[k][8];
+    const double trk = Qk[0] + Qk[4] + Qk[8];
 #pragma unroll
     for (int l = k; l < 6; ++l) {
+      double Ql[9], SQl[9], Rl[9];
+      Q_of(b, cd, l, Ql);
+      mm(Sf, Ql, SQl);
+      mm(b.C, SQl, Rl);  // C S Q_l
       double s = 0.0;
 #pragma unroll
-      for (int u = 0; u < 6; ++u) s += WCk[u] * dc[9 + l][u];
-      s += 2.0 * (trprod(Rk[k], Qk[l]) + trprod(Rk[l], Qk[k]) + ddot9(Uk[k], Qk[l]));
+      for (int u = 0; u < 6; ++u) s += WCk[u] * dce[l][u];
+      s += 2.0 * (trprod(Rk, Ql) + trprod(Rl, Qk) + ddot9(Uk, Ql));
 #pragma unroll
-      for (int v = 0; v < 6; ++v) s += wCeta[v][l] * dc[9 + k][v] + wCeta[v][k] * dc[9 + l][v];
-      const double trl = Qk[l][0] + Qk[l][4] + Qk[l][8];
-      const double Jkl = b.Jt * (trk * trl - trprod(Qk[k], Qk[l]));
-      double val = b.Jt * s + Jq[k] * wq[9 + l] + Jq[l] * wq[9 + k] + Jkl * b.w;
+      for (int v = 0; v < 6; ++v) s += wCeta[v][l] * dce[k][v] + wCeta[v][k] * dce[l][v];
+      const double trl = Ql[0] + Ql[4] + Ql[8];
+      const double Jkl = b.Jt * (trk * trl - trprod(Qk, Ql));
+      double val = b.Jt * s + Jq[k] * wqe[l] + Jq[l] * wqe[k] + Jkl * b.w;
       // order-parameter terms
       val += cd.Sw[k][l] + cd.rho * ((k == l ? 1.0 : 0.0) + 1.0) + pen0;
       if (k == l && eta[k + 1] < 0.0) val += cd.eps;
       D[hidx(9 + k, 9 + l) * ds] = val;
+    }
+  }
+  // F-F and F-eta blocks
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    double dcq[6];
+    dC_F(b, q, dcq);
+    double wq = 0.0;
+#pragma unroll
+    for (int v = 0; v < 6; ++v) wq += b.wC[v] * dcq[v];
+    g[q] = b.Jt * wq;
+    double WCq[6];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      double s = 0.0;
+#pragma unroll
+      for (int v = 0; v < 6; ++v) s += wCC[u][v] * dcq[v];
+      WCq[u] = s;
+    }
+    const int i = q / 3, j = q % 3;
+#pragma unroll
+    for (int r = q; r < 9; ++r) {
+      double dcr[6];
+      dC_F(b, r, dcr);
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < 6; ++u) s += WCq[u] * dcr[u];
+      const int k = r / 3, l = r % 3;
+      if (i == k) s += 2.0 * GSG[3 * j + l];
+      D[hidx(q, r) * ds] = b.Jt * s;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < 6; ++u) s += WCq[u] * dce[k][u] + Ak[k][u] * dcq[u];
+      D[hidx(q, 9 + k) * ds] = b.Jt * s + Jq[k] * wq;
     }
   }
   // order-parameter gradient terms

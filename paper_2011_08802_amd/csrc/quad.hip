@@ -52,13 +52,14 @@ __device__ __forceinline__ double lap_ref(int a, int b) {
 }
 
 template <bool HESS>
-__global__ void __launch_bounds__(128) qp_kernel(Grid g, const double* __restrict__ state,
+__global__ void __launch_bounds__(128) qp_kernel(Grid g, Chunk ck, const double* __restrict__ state,
                                                  const DevCard* __restrict__ cd, double* __restrict__ qp) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int gp = (int)(tid / g.NEpad);
-  const int e = (int)(tid - (int64_t)gp * g.NEpad);
-  if (gp >= 8 || e >= g.NE) return;
-  const int ex = e % g.nx, ey = (e / g.nx) % g.ny, ez = e / (g.nx * g.ny);
+  const int gp = (int)(tid / ck.NEcpad);
+  const int el = (int)(tid - (int64_t)gp * ck.NEcpad);
+  if (gp >= 8 || el >= ck.NEc) return;
+  const int64_t e = ck.e0 + el;
+  const int ex = (int)(e % g.nx), ey = (int)((e / g.nx) % g.ny), ez = (int)(e / ((int64_t)g.nx * g.ny));
   const double ih = 1.0 / g.h;
   double F[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   double eh[6] = {0, 0, 0, 0, 0, 0}, ehn[6] = {0, 0, 0, 0, 0, 0};
@@ -78,8 +79,8 @@ __global__ void __launch_bounds__(128) qp_kernel(Grid g, const double* __restric
       ehn[k] += s.N * state[(int64_t)(9 + k) * g.Npad + node];
     }
   }
-  const int64_t stride = (int64_t)8 * g.NEpad;
-  double* out = qp + (int64_t)gp * g.NEpad + e;
+  const int64_t stride = (int64_t)8 * ck.NEcpad;
+  double* out = qp + (int64_t)gp * ck.NEcpad + el;
   double gr[15];
   if (HESS) {
     local_hessian(F, eh, ehn, *cd, gr, out + (int64_t)15 * stride, stride);
@@ -90,36 +91,37 @@ __global__ void __launch_bounds__(128) qp_kernel(Grid g, const double* __restric
   for (int c = 0; c < 15; ++c) out[(int64_t)c * stride] = gr[c];
 }
 
-void launch_qp(const Grid& g, const double* state, const DevCard* cd, double* qp, bool hess, hipStream_t s) {
-  const int64_t n = (int64_t)8 * g.NEpad;
+void launch_qp(const Grid& g, const Chunk& ck, const double* state, const DevCard* cd, double* qp, bool hess,
+               hipStream_t s) {
+  const int64_t n = (int64_t)8 * ck.NEcpad;
   const int bs = 128;
   const int nb = (int)((n + bs - 1) / bs);
   if (hess)
-    qp_kernel<true><<<nb, bs, 0, s>>>(g, state, cd, qp);
+    qp_kernel<true><<<nb, bs, 0, s>>>(g, ck, state, cd, qp);
   else
-    qp_kernel<false><<<nb, bs, 0, s>>>(g, state, cd, qp);
+    qp_kernel<false><<<nb, bs, 0, s>>>(g, ck, state, cd, qp);
 }
 
-__global__ void __launch_bounds__(256) residual_gather_kernel(Grid g, const double* __restrict__ state,
+__global__ void __launch_bounds__(256) residual_gather_kernel(Grid g, Chunk ck, const double* __restrict__ state,
                                                               const double* __restrict__ qp,
                                                               const DevCard* __restrict__ cd,
                                                               double* __restrict__ R) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= g.Npad) return;
+  const int n = ck.n0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= ck.n1 || n >= g.Npad) return;
   double r[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (n < g.N) {
     const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
     const double cu = g.h * g.h * 0.125, ce = g.h * g.h * g.h * 0.125;
-    const int64_t stride = (int64_t)8 * g.NEpad;
+    const int64_t stride = (int64_t)8 * ck.NEcpad;
     for (int a = 0; a < 8; ++a) {
       const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
       const int ex = i - ax, ey = j - ay, ez = k - az;
       if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || ez < 0 || ez >= g.nz) continue;
-      const int e = ex + g.nx * (ey + g.ny * ez);
+      const int64_t el = ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez) - ck.e0;  // in [0, NEc) by construction
 #pragma unroll
       for (int gp = 0; gp < 8; ++gp) {
         const Shape s = shape(gp, a);
-        const double* q = qp + (int64_t)gp * g.NEpad + e;
+        const double* q = qp + (int64_t)gp * ck.NEcpad + el;
 #pragma unroll
         for (int i3 = 0; i3 < 3; ++i3)
           r[i3] += cu * (s.dN[0] * q[(3 * i3 + 0) * stride] + s.dN[1] * q[(3 * i3 + 1) * stride] +
@@ -148,9 +150,9 @@ __global__ void __launch_bounds__(256) residual_gather_kernel(Grid g, const doub
   for (int c = 0; c < 9; ++c) R[(int64_t)c * g.Npad + n] = r[c];
 }
 
-void launch_residual_gather(const Grid& g, const double* state, const double* qp, const DevCard* cd, double* R,
-                            hipStream_t s) {
-  residual_gather_kernel<<<(g.Npad + 255) / 256, 256, 0, s>>>(g, state, qp, cd, R);
+void launch_residual_gather(const Grid& g, const Chunk& ck, const double* state, const double* qp, const DevCard* cd,
+                            double* R, hipStream_t s) {
+  residual_gather_kernel<<<(ck.n1 - ck.n0 + 255) / 256, 256, 0, s>>>(g, ck, state, qp, cd, R);
 }
 
 // Logical block index with the 8 XCDs of the chip in mind: hardware places
@@ -174,14 +176,15 @@ __host__ __device__ constexpr int pair_index(int a, int b) {  // a <= b < 8
 // accumulators in registers (no spills).
 constexpr int EM_WAVES = 4;
 
-__global__ void __launch_bounds__(EM_WAVES * 64, 2) element_matrix_kernel(Grid g, const double* __restrict__ qp,
-                                                                       const DevCard* __restrict__ cd,
-                                                                       double* __restrict__ E) {
+__global__ void __launch_bounds__(EM_WAVES * 64, 2) element_matrix_kernel(Grid g, Chunk ck,
+                                                                          const double* __restrict__ qp,
+                                                                          const DevCard* __restrict__ cd,
+                                                                          double* __restrict__ E) {
   __shared__ double Ds[120 * 64];
   // the NPAIR / EM_WAVES pair chunks of one element group are consecutive
   // logical blocks on one XCD, so the group's Hessians are read from HBM once
   // and then hit that XCD's L2
-  const int groups = g.NEpad / 64;
+  const int groups = ck.NEcpad / 64;
   const int Lb = xcd_logical(blockIdx.x, gridDim.x);
   if (Lb >= groups * (NPAIR / EM_WAVES)) return;  // uniform; before any barrier
   const int eg = Lb / (NPAIR / EM_WAVES);
@@ -193,7 +196,7 @@ __global__ void __launch_bounds__(EM_WAVES * 64, 2) element_matrix_kernel(Grid g
   const int b = a + rem;
   const int e = eg * 64 + l;
   const double cuu = g.h * 0.125, cue = g.h * g.h * 0.125, cee = g.h * g.h * g.h * 0.125;
-  const int64_t stride = (int64_t)8 * g.NEpad;
+  const int64_t stride = (int64_t)8 * ck.NEcpad;
   double K[81];
 #pragma unroll
   for (int q = 0; q < 81; ++q) K[q] = 0.0;
@@ -204,7 +207,7 @@ __global__ void __launch_bounds__(EM_WAVES * 64, 2) element_matrix_kernel(Grid g
       // instruction moves two Hessian components of the group's 64 elements,
       // lanes 0-31 component c and lanes 32-63 component c + 1, 16 B (two
       // elements) per lane, landing at LDS base + 16 * lane
-      const double* src = qp + (int64_t)(15 + 2 * w + (l >> 5)) * stride + (int64_t)gp * g.NEpad + eg * 64 +
+      const double* src = qp + (int64_t)(15 + 2 * w + (l >> 5)) * stride + (int64_t)gp * ck.NEcpad + eg * 64 +
                           2 * (l & 31);
 #pragma unroll
       for (int r = 0; r < 120 / (2 * EM_WAVES); ++r) {
@@ -259,31 +262,33 @@ __global__ void __launch_bounds__(EM_WAVES * 64, 2) element_matrix_kernel(Grid g
   for (int m = 0; m < 6; ++m)
 #pragma unroll
     for (int m2 = 0; m2 < 6; ++m2) K[9 * (3 + m) + 3 + m2] += lap * cd->Mg[m][m2];
-  if (e < g.NE) {
+  if (e < ck.NEc) {
 #pragma unroll
-    for (int q = 0; q < 81; ++q) E[((int64_t)p * NBLK + q) * g.NEpad + e] = K[q];
+    for (int q = 0; q < 81; ++q) E[((int64_t)p * NBLK + q) * ck.NEcpad + e] = K[q];
   }
 }
 
-void launch_element_matrices(const Grid& g, const double* qp, const DevCard* cd, double* elem, hipStream_t s) {
-  const int groups = g.NEpad / 64;
+void launch_element_matrices(const Grid& g, const Chunk& ck, const double* qp, const DevCard* cd, double* elem,
+                             hipStream_t s) {
+  const int groups = ck.NEcpad / 64;
   const int nb = groups * (NPAIR / EM_WAVES);
-  element_matrix_kernel<<<(nb + 7) / 8 * 8, EM_WAVES * 64, 0, s>>>(g, qp, cd, elem);
+  element_matrix_kernel<<<(nb + 7) / 8 * 8, EM_WAVES * 64, 0, s>>>(g, ck, qp, cd, elem);
 }
 
 // Stored block (n, n + off(13 + u)) = sum over the <= 8 elements containing
 // both nodes of their element blocks, in a fixed order (bitwise reproducible).
 // One wavefront per (tile, u): 64 consecutive rows, coalesced element reads
 // and coalesced tiled writes.
-__global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, const double* __restrict__ E,
+__global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, Chunk ck, const double* __restrict__ E,
                                                              double* __restrict__ A64, float* __restrict__ A32,
                                                              double* __restrict__ diag64, int nblocks) {
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= nblocks) return;
-  const int t = L / NUP, u = L - t * NUP;
+  const int t = ck.n0 / TILE + L / NUP, u = L % NUP;
   const int sten = 13 + u;
   const int l = threadIdx.x;
   const int n = t * TILE + l;
+  if (n < ck.n0 || n >= ck.n1) return;  // rows of other slabs (no barriers below)
   const int dx = sten % 3 - 1, dy = (sten / 3) % 3 - 1, dz = sten / 9 - 1;
   const bool inside = n < g.N;
   const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
@@ -303,17 +308,18 @@ __global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, const doubl
         const int ex = i - ax, ey = j - ay, ez = k - az;
         if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || ez < 0 || ez >= g.nz) continue;
         const int b = bx + 2 * by + 4 * bz;
-        const int e = ex + g.nx * (ey + g.ny * ez);
+        const int64_t e = ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez) - ck.e0;  // local, in [0, NEc)
+        const int64_t es = ck.NEcpad;
         if (a <= b) {
-          const double* src = E + (int64_t)pair_index(a, b) * NBLK * g.NEpad + e;
+          const double* src = E + (int64_t)pair_index(a, b) * NBLK * es + e;
 #pragma unroll
-          for (int q = 0; q < 27; ++q) K[q] += src[(int64_t)(9 * r0 + q) * g.NEpad];
+          for (int q = 0; q < 27; ++q) K[q] += src[(int64_t)(9 * r0 + q) * es];
         } else {
-          const double* src = E + (int64_t)pair_index(b, a) * NBLK * g.NEpad + e;
+          const double* src = E + (int64_t)pair_index(b, a) * NBLK * es + e;
 #pragma unroll
           for (int rr = 0; rr < 3; ++rr)
 #pragma unroll
-            for (int c = 0; c < 9; ++c) K[9 * rr + c] += src[(int64_t)(9 * c + r0 + rr) * g.NEpad];
+            for (int c = 0; c < 9; ++c) K[9 * rr + c] += src[(int64_t)(9 * c + r0 + rr) * es];
         }
       }
     }
@@ -332,11 +338,12 @@ __global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, const doubl
   }
 }
 
-void launch_jacobian_gather(const Grid& g, const double* elem, double* A64, float* A32, double* diag64,
-                            hipStream_t s) {
-  const int nblocks = g.ntiles * NUP;
+void launch_jacobian_gather(const Grid& g, const Chunk& ck, const double* elem, double* A64, float* A32,
+                            double* diag64, hipStream_t s) {
+  const int t0 = ck.n0 / TILE, t1 = (ck.n1 + TILE - 1) / TILE;
+  const int nblocks = (t1 - t0) * NUP;
   const int nb_pad = (nblocks + 7) / 8 * 8;
-  jacobian_gather_kernel<<<nb_pad, TILE, 0, s>>>(g, elem, A64, A32, diag64, nblocks);
+  jacobian_gather_kernel<<<nb_pad, TILE, 0, s>>>(g, ck, elem, A64, A32, diag64, nblocks);
 }
 
 // Symmetric elimination on the stored blocks: entries in constrained rows of

@@ -23,6 +23,9 @@ CASES = {
     "ragged": (synth.Problem(8, 12, 4, ly=1.5, lz=0.5, n_levels=3, patch=2, depth_increment=0.01), 2e-3),
     # smallest: 2^3 elements, 2 levels (coarsest is one element)
     "minimal": (synth.Problem(2, 2, 2, n_levels=2, patch=2, depth_increment=0.05), 1e-3),
+    # spherical-cap indenter (R = 0.2) on a 1 x 1 x 0.5 box, the shape of the
+    # 256x256x128 workload: 5 top nodes in contact
+    "cap": (synth.Problem(16, 16, 8, lz=0.5, n_levels=3, kind="cap", radius=0.2, depth_increment=0.02), 1e-3),
 }
 
 
@@ -274,3 +277,38 @@ def test_large_coarse_inverse(n, levels, coarse_dof):
     assert st.converged and abs(st.iterations - sto.iterations) <= 1, (st.iterations, sto.iterations)
     assert rel(xs.cpu().numpy(), xo) < 1e-9
     gp.close()
+
+
+def test_assembly_slabs_bitwise():
+    """Assembly in slabs of element layers (one halo layer recomputed per
+    slab) gives bitwise the same residual, Newton system and solution as the
+    whole-level assembly."""
+    p = synth.tiny()
+    U, En = seeded_state(p, 1e-3)
+    rng = np.random.default_rng(8)
+    xs = None
+    outs = []
+    for slab in (0, 192, 256):  # whole level; 1 and 2 node layers per slab on 8^3
+        say(f"[slabs] assembly_slab_elements={slab}")
+        gp = gpu_problem(p, U, En, "mixed")
+        if slab:
+            gp.set_tuning("assembly_slab_elements", 0, slab)
+            assert gp.get_tuning("assembly_slab_elements") == slab
+        R, nf = gp.residual()
+        gp.newton_system(p.depth_increment)
+        b = gp.get_rhs()
+        info = gp.info()
+        if xs is None:
+            xs = [rng.standard_normal(9 * info.n_nodes[l]) for l in range(p.n_levels)]
+        from paper_2011_08802_amd import mvpf
+        ys = [gp.jacobian_apply(l, _dev(xs[l]), mvpf.FP64 if l in (0, p.n_levels - 1) else mvpf.MIXED).cpu().numpy()
+              for l in range(p.n_levels)]
+        x, st = gp.solve()
+        outs.append((R.cpu().numpy(), nf, b.cpu().numpy(), ys, x.cpu().numpy(), st.iterations))
+        gp.close()
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and o[1] == outs[0][1]
+        assert np.array_equal(o[2], outs[0][2])
+        for y, y0 in zip(o[3], outs[0][3]):
+            assert np.array_equal(y, y0)
+        assert np.array_equal(o[4], outs[0][4]) and o[5] == outs[0][5]
