@@ -32,6 +32,8 @@ import synth  # noqa: E402
 
 METRIC = "Newton-step solve time & DOF/s at 1e-8 rel. residual, FP32-GMG vs FP64 GMG"
 HBM_PEAK_GBS = 8000.0
+# calibrated rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the same kernels at 64^3
+COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_patch64_mixed.txt")
 
 WORKLOADS = {
     "tiny": synth.tiny,
@@ -93,6 +95,34 @@ def run_precision(prob, precision, steps, warmup, timing, tune=True):
     x, st = gp.solve()
     gp.close()
     return dict(total_s=total, recs=recs, kernels=kstats, x=x.cpu().numpy(), shapes=shapes)
+
+
+def sweep_traffic(prob):
+    """Measured HBM bytes of one finest-level smoother sweep (defect_upper +
+    pbj_lower) from the committed counter summary, for the workload it was
+    taken on (64^3), else None."""
+    if (prob.nx, prob.ny, prob.nz) != (64, 64, 64) or not os.path.exists(COUNTERS):
+        return None
+    npad = prob.n_nodes + (-prob.n_nodes) % 64
+    grid = ((npad + 255) // 256 + 7) // 8 * 8 * 256  # threads of the default finest row-kernel launch
+    total = 0.0
+    found = set()
+    with open(COUNTERS) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) < 7 or not parts[0].startswith("mvpf::"):
+                continue
+            name = parts[0]
+            if name.startswith("mvpf::defect_upper_kernel<float>") or name.startswith("mvpf::pbj_lower_kernel<float>"):
+                try:
+                    g = int(parts[1])
+                    rd, wr = float(parts[-2]), float(parts[-1])
+                except ValueError:
+                    continue
+                if g == grid and name not in found:
+                    found.add(name)
+                    total += (rd + wr) * 1e6
+    return total if len(found) == 2 else None
 
 
 def cpu_baseline(n=16, levels=4):
@@ -201,8 +231,8 @@ def main():
     k = mixed["kernels"].get("pbj_sweep")
     if k:
         out["roofline"] = {"bound": "hbm", "achieved": k["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": k["gbs"] / HBM_PEAK_GBS, "traffic": None,
-                           "kernel": "pbj_kernel<float,false> (finest level)",
+                           "frac": k["gbs"] / HBM_PEAK_GBS, "traffic": sweep_traffic(prob),
+                           "kernel": "finest-level FP32 smoother sweep (defect_upper + pbj_lower)",
                            "bytes_per_launch": k["bytes"], "avg_ms": k["avg_ms"], "launches": k["launches"]}
         out["kernels"] = mixed["kernels"]
     if not a.no_cpu_baseline:
