@@ -97,6 +97,127 @@ def run_precision(prob, precision, steps, warmup, timing, tune=True):
     return dict(total_s=total, recs=recs, kernels=kstats, x=x.cpu().numpy(), shapes=shapes)
 
 
+def run_batch(probs, precision, steps, warmup, tune=True):
+    """The batched workload: all problems' Newton systems, one lockstep
+    batched solve (V-cycles of all problems in one graph launch per Arnoldi
+    step), all updates."""
+    from paper_2011_08802_amd import mvpf
+    B = mvpf.Batch(probs, precision, rtol=1e-8)
+    init = []
+    for i, p in enumerate(probs):
+        gp = B.problem(i)
+        gp.init_random(p.seed)
+        u0, e0, en0, _ = gp.get_state()
+        init.append((u0.clone(), e0.clone(), en0.clone()))
+    depths = [p.depth_increment for p in probs]
+    if tune:
+        B.newton_system(depths)
+        for i in range(len(probs)):
+            B.problem(i).autotune()
+
+    def step(rec):
+        for i, (u0, e0, en0) in enumerate(init):
+            B.problem(i).set_state(u0, e0, en0, 0.0)
+        t0 = time.perf_counter()
+        B.newton_system(depths)
+        t1 = time.perf_counter()
+        st = B.solve()
+        B.newton_update()
+        if rec is not None:
+            rec.append(dict(system_ms=1e3 * (t1 - t0), solve_ms=st[0].solve_ms,
+                            its=[x.iterations for x in st], converged=all(x.converged for x in st),
+                            rel_res=max(x.rel_residual for x in st)))
+
+    for _ in range(warmup):
+        step(None)
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(recs)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    B.close()
+    return dict(total_s=total, recs=recs)
+
+
+def run_sequential(probs, precision, steps):
+    """The same problems solved one after the other (no batching), for comparison."""
+    from paper_2011_08802_amd import mvpf
+    gps = []
+    for p in probs:
+        gp = mvpf.Problem(p, precision, rtol=1e-8)
+        gp.init_random(p.seed)
+        u0, e0, en0, _ = gp.get_state()
+        gps.append((gp, p, (u0.clone(), e0.clone(), en0.clone())))
+    solve_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tot = 0.0
+        for gp, p, (u0, e0, en0) in gps:
+            gp.set_state(u0, e0, en0, 0.0)
+            gp.newton_system(p.depth_increment)
+            _, st = gp.solve(want_x=False)
+            gp.newton_update()
+            tot += st.solve_ms
+        solve_ms.append(tot)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    for gp, _, _ in gps:
+        gp.close()
+    return dict(ms_per_step=1e3 * total / steps, solve_ms_median=statistics.median(solve_ms))
+
+
+def batched_main(a):
+    probs = synth.batched(32)
+    ndof = sum(p.n_dof for p in probs)
+    sizes = [p.nx for p in probs]
+    log(f"[bench] batched workload: {len(probs)} problems, sizes {sizes}, {ndof} dof in total")
+    res = {}
+    for prec in ("mixed",) + (() if a.no_fp64 else ("fp64",)):
+        log(f"[bench] batch {prec} ...")
+        r = run_batch(probs, prec, a.steps, a.warmup, not a.no_tune)
+        recs = r["recs"]
+        res[prec] = dict(ms_per_step=1e3 * r["total_s"] / len(recs),
+                         value=ndof * len(recs) / r["total_s"],
+                         solve_ms_median=statistics.median(x["solve_ms"] for x in recs),
+                         system_ms_median=statistics.median(x["system_ms"] for x in recs),
+                         fgmres_iterations_max=max(max(x["its"]) for x in recs),
+                         fgmres_iterations_min=min(min(x["its"]) for x in recs),
+                         rel_residual_max=max(x["rel_res"] for x in recs),
+                         converged=all(x["converged"] for x in recs))
+        res[prec]["solve_dof_per_s"] = ndof / (res[prec]["solve_ms_median"] / 1e3)
+    log("[bench] same problems one by one (mixed) ...")
+    seq = run_sequential(probs, "mixed", max(1, min(a.steps, 2)))
+    ms = res["mixed"]
+    out = {
+        "metric": METRIC,
+        "value": ms["value"],
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {len(probs)} patch-indentation problems, n^3 hex with n in "
+                               f"{{16,24,32,40,48}}, random crystal rotations, depths U[0.005,0.02], "
+                               f"{ndof} dof in total, 4-level GMG V(2,2), FGMRES(30) rtol 1e-8",
+                   "sizes": sizes, "precision": "mixed"},
+        "mixed": ms,
+        "sequential_mixed": seq,
+        "speedup_solve_batched_vs_sequential": seq["solve_ms_median"] / ms["solve_ms_median"],
+    }
+    if "fp64" in res:
+        out["fp64_gmg"] = res["fp64"]
+        out["speedup_solve_mixed_vs_fp64"] = res["fp64"]["solve_ms_median"] / ms["solve_ms_median"]
+    print(json.dumps(out), flush=True)
+
+
 def sweep_traffic(prob):
     """Measured HBM bytes of one finest-level smoother sweep (defect_upper +
     pbj_lower) from the committed counter summary, for the workload it was
@@ -158,7 +279,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="medium", choices=list(WORKLOADS))
+    ap.add_argument("--workload", default="medium", choices=list(WORKLOADS) + ["batched"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-multigrid comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
@@ -177,6 +298,9 @@ def main():
         torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
         del x, y
+    if a.workload == "batched":
+        batched_main(a)
+        return
     prob = WORKLOADS[a.workload]()
     ndof = prob.n_dof
     log(f"[bench] workload {a.workload}: {prob.nx}x{prob.ny}x{prob.nz}, {ndof} dof, {prob.n_levels} levels")

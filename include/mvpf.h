@@ -53,6 +53,7 @@ enum { MVPF_FP64 = 0, MVPF_MIXED = 1 };          /* mvpf_opts.precision */
 enum { MVPF_LOAD_PATCH = 0, MVPF_LOAD_CAP = 1 };  /* mvpf_loading.kind */
 
 typedef struct mvpf_problem mvpf_problem;
+typedef struct mvpf_batch mvpf_batch;
 
 /* Structured mesh of nx*ny*nz cubes of side h, and the number of geometric
  * multigrid levels.  Level l has nx/2^l x ny/2^l x nz/2^l elements, so nx, ny,
@@ -65,6 +66,7 @@ typedef struct {
 } mvpf_mesh;
 
 #define MVPF_MAX_COARSE_DOF 8192
+#define MVPF_MAX_BATCH 256
 
 /* Material card (Sec. 2.2, 2.3, 3.1, 4.1; Table 1).  Stresses and energy
  * densities in GPa, lengths in units of the mesh coordinates.
@@ -264,6 +266,36 @@ int mvpf_autotune(mvpf_problem* p, int* row_blocks_out);
 int mvpf_kernel_timing(mvpf_problem* p, int enable);
 int mvpf_kernel_stats(mvpf_problem* p, const char* name, int* launches, double* total_ms,
                       double* bytes_per_launch);
+
+/* ---- Batches of independent problems --------------------------------------
+ * Many independent indentation problems of uneven size (each with its own
+ * mesh, material card -- e.g. its own crystal orientation -- and loading)
+ * solved together: the problems advance in lockstep, one Arnoldi step of
+ * every problem per host synchronisation, and the multigrid V-cycles of all
+ * problems run as parallel branches of one captured HIP graph (one graph
+ * launch per step).  Each problem's numbers are bitwise those of solving it
+ * alone with mvpf_solve.  Every problem is a full handle (mvpf_batch_problem)
+ * on which the single-problem calls work; the batch owns them. */
+
+/* Create n (1..MVPF_MAX_BATCH) problems: meshes[i], mats[i], loads[i] as for
+ * mvpf_create; opts (one for all) and stream shared.  On error nothing is
+ * left allocated and mvpf_batch_last_error(NULL) describes it. */
+int mvpf_create_batch(int n, const mvpf_mesh* meshes, const mvpf_material* mats, const mvpf_loading* loads,
+                      const mvpf_opts* opts, void* hip_stream, mvpf_batch** out);
+void mvpf_destroy_batch(mvpf_batch* b);
+const char* mvpf_batch_last_error(const mvpf_batch* b);
+/* Problem i of the batch (owned by the batch; NULL if out of range). */
+mvpf_problem* mvpf_batch_problem(mvpf_batch* b, int i);
+/* mvpf_newton_system on every problem; depths: n host doubles. */
+int mvpf_batch_newton_system(mvpf_batch* b, const double* depths);
+/* Solve every problem's Newton system (right-hand side and increment kept
+ * inside each problem, as mvpf_solve with b = x = NULL); stats: n entries,
+ * solve_ms = the whole batch's time.  The V-cycle graph is captured on the
+ * first call and again whenever a problem's options or tuning changed.
+ * Returns MVPF_ENOTCONV if any problem did not converge. */
+int mvpf_batch_solve(mvpf_batch* b, mvpf_solve_stats* stats);
+/* mvpf_newton_update on every problem. */
+int mvpf_batch_newton_update(mvpf_batch* b);
 
 #ifdef __cplusplus
 }

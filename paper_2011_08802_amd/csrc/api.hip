@@ -363,97 +363,193 @@ int norm_device(mvpf_problem* p, int64_t n, const double* v, double* out_host) {
 // Flexible GMRES(m), right preconditioned, x0 = 0, classical Gram-Schmidt
 // twice, Givens rotations; convergence on the recurrence residual, then a
 // true FP64 residual check (restart if it is not met).
+//
+// The iteration is a small state machine so that several problems can
+// advance in lockstep with one host synchronisation per step (batched
+// solves).  Each phase enqueues its device work on the problem's stream,
+// ending with a copy of the scalars the host needs into pinned memory; the
+// next phase runs on the host after the caller has synchronised.
+//   ARNOLDI: the caller puts z_j = M^-1 v_j into zj(), then arnoldi_enqueue()
+//            (outer product, CGS2, norm) ... sync ... arnoldi_finish()
+//   CHECK:   (end of a cycle, work enqueued by arnoldi_finish) ... sync ...
+//            check_finish(): converged, or restart (back to ARNOLDI)
 template <typename T, typename TZ>
-int fgmres(mvpf_problem* p, const double* b, double* x, mvpf_solve_stats* st) {
-  const Grid& g = p->lev[0].g;
-  const int64_t n = nvec(g);
-  const int m = std::min(p->opts.restart, p->restart_cap);
-  const int nb = red_blocks(n);
-  hipStream_t s = p->stream;
-  TZ* Z = (TZ*)p->Z;
-  double* V = p->V;
-  st->iterations = st->restarts = st->converged = 0;
-  st->rel_residual = 0.0;
-  launch_zero<double>(n, x, s);
-  double bnorm;
-  TRY(norm_device(p, n, b, &bnorm));
-  if (bnorm == 0.0) {
-    st->converged = 1;
+struct Krylov {
+  enum Phase { START, ARNOLDI, CHECK, DONE };
+  mvpf_problem* p = nullptr;
+  const double* b = nullptr;
+  double* x = nullptr;
+  mvpf_solve_stats* st = nullptr;
+  int64_t n = 0;
+  int m = 0, nb = 0, j = 0, k = 0, rc = 0;
+  Phase phase = START;
+  std::vector<double> H, cs, sn, gg, y;
+  double bnorm = 0.0, beta = 0.0;
+  const double* r0 = nullptr;
+
+  double& Hij(int i, int c) { return H[(size_t)i * m + c]; }
+  double* h1() { return p->hcol; }
+  double* h2() { return p->hcol + (MAX_RESTART + 2); }
+  double* hn() { return p->hcol + 2 * (MAX_RESTART + 2); }
+  double* vj() { return p->V + (int64_t)j * n; }
+  TZ* zj() { return (TZ*)p->Z + (int64_t)j * n; }
+  int fail(int code) {
+    rc = code;
+    phase = DONE;
+    return code;
+  }
+
+  // zero x, ||b|| -> hhost[0]
+  int begin(mvpf_problem* pp, const double* bb, double* xx, mvpf_solve_stats* ss) {
+    p = pp;
+    b = bb;
+    x = xx;
+    st = ss;
+    n = nvec(p->lev[0].g);
+    m = std::min(p->opts.restart, p->restart_cap);
+    nb = red_blocks(n);
+    H.assign((size_t)(m + 1) * m, 0.0);
+    cs.assign(m, 0.0);
+    sn.assign(m, 0.0);
+    gg.assign(m + 1, 0.0);
+    y.assign(m, 0.0);
+    st->iterations = st->restarts = st->converged = 0;
+    st->rel_residual = 0.0;
+    hipStream_t s = p->stream;
+    launch_zero<double>(n, x, s);
+    launch_multidot(n, b, n, 1, b, p->red, s);
+    launch_reduce(1, nb, p->red, p->hcol, 0, s);
+    if (launch_check(p, "fgmres start") < 0) return fail(MVPF_EDEVICE);
+    if (hipMemcpyAsync(p->hhost, p->hcol, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return fail(MVPF_EDEVICE);
+    phase = START;
     return 0;
   }
-  const double rtol = p->opts.rtol;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gg(m + 1), y(m);
-  auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
-  double beta = bnorm;
-  const double* r0 = b;
-  double* h1 = p->hcol;
-  double* h2 = p->hcol + (MAX_RESTART + 2);
-  double* hn = p->hcol + 2 * (MAX_RESTART + 2);
-  while (true) {
-    launch_axpby(n, 1.0 / beta, r0, 0.0, nullptr, V, s);
+  void start_cycle() {
+    launch_axpby(n, 1.0 / beta, r0, 0.0, nullptr, p->V, p->stream);
     std::fill(gg.begin(), gg.end(), 0.0);
     gg[0] = beta;
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
-      double* vj = V + (int64_t)j * n;
-      double* w = V + (int64_t)(j + 1) * n;
-      TZ* zj = Z + (int64_t)j * n;
-      precondition<T, TZ>(p, vj, zj);
-      if (p->timing) timer_begin(p, p->t_outer);
-      launch_spmv<double, TZ, double>(g, p->lev[0].A64, zj, w, p->Cbuf, s, p->outer_G);
-      if (p->timing)
-        timer_end(p, p->t_outer,
-                  8.0 * stored_blocks(g) * NBLK + (double)g.N * NDOF * (sizeof(TZ) + sizeof(double)));
-      launch_multidot(n, V, n, j + 1, w, p->red, s);
-      launch_reduce(j + 1, nb, p->red, h1, 0, s);
-      launch_multiaxpy(n, V, n, j + 1, h1, w, nullptr, s);
-      launch_multidot(n, V, n, j + 1, w, p->red, s);
-      launch_reduce(j + 1, nb, p->red, h2, 0, s);
-      launch_multiaxpy(n, V, n, j + 1, h2, w, p->red, s);
-      launch_reduce(1, nb, p->red, hn, 0, s);
-      TRY(launch_check(p, "fgmres arnoldi"));
-      TRY(fetch(p, p->hcol, 3 * (MAX_RESTART + 2)));
-      for (int i = 0; i <= j; ++i) Hij(i, j) = p->hhost[i] + p->hhost[(MAX_RESTART + 2) + i];
-      const double hnext = std::sqrt(p->hhost[2 * (MAX_RESTART + 2)]);
-      Hij(j + 1, j) = hnext;
-      if (hnext > 0.0) launch_axpby(n, 1.0 / hnext, w, 0.0, nullptr, w, s);
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
-        Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
-        Hij(i, j) = t;
-      }
-      const double den = std::hypot(Hij(j, j), Hij(j + 1, j));
-      cs[j] = Hij(j, j) / den;
-      sn[j] = Hij(j + 1, j) / den;
-      Hij(j, j) = den;
-      Hij(j + 1, j) = 0.0;
-      gg[j + 1] = -sn[j] * gg[j];
-      gg[j] = cs[j] * gg[j];
-      st->iterations++;
-      k = j + 1;
-      if (std::fabs(gg[j + 1]) <= rtol * bnorm || st->iterations >= p->opts.max_it) break;
+    j = 0;
+    phase = ARNOLDI;
+  }
+  void after_begin() {
+    bnorm = std::sqrt(p->hhost[0]);
+    if (bnorm == 0.0) {
+      st->converged = 1;
+      phase = DONE;
+      return;
     }
+    beta = bnorm;
+    r0 = b;
+    start_cycle();
+  }
+  // w = A z_j, two Gram-Schmidt passes, ||w||^2; the three columns -> hhost
+  int arnoldi_enqueue() {
+    hipStream_t s = p->stream;
+    const Grid& g = p->lev[0].g;
+    double* w = p->V + (int64_t)(j + 1) * n;
+    if (p->timing) timer_begin(p, p->t_outer);
+    launch_spmv<double, TZ, double>(g, p->lev[0].A64, zj(), w, p->Cbuf, s, p->outer_G);
+    if (p->timing)
+      timer_end(p, p->t_outer, 8.0 * stored_blocks(g) * NBLK + (double)g.N * NDOF * (sizeof(TZ) + sizeof(double)));
+    launch_multidot(n, p->V, n, j + 1, w, p->red, s);
+    launch_reduce(j + 1, nb, p->red, h1(), 0, s);
+    launch_multiaxpy(n, p->V, n, j + 1, h1(), w, nullptr, s);
+    launch_multidot(n, p->V, n, j + 1, w, p->red, s);
+    launch_reduce(j + 1, nb, p->red, h2(), 0, s);
+    launch_multiaxpy(n, p->V, n, j + 1, h2(), w, p->red, s);
+    launch_reduce(1, nb, p->red, hn(), 0, s);
+    if (launch_check(p, "fgmres arnoldi") < 0) return fail(MVPF_EDEVICE);
+    if (hipMemcpyAsync(p->hhost, p->hcol, sizeof(double) * 3 * (MAX_RESTART + 2), hipMemcpyDeviceToHost, s) !=
+        hipSuccess)
+      return fail(MVPF_EDEVICE);
+    return 0;
+  }
+  // Hessenberg column, Givens rotations; continue, or end the cycle
+  int arnoldi_finish() {
+    for (int i = 0; i <= j; ++i) Hij(i, j) = p->hhost[i] + p->hhost[(MAX_RESTART + 2) + i];
+    const double hnext = std::sqrt(p->hhost[2 * (MAX_RESTART + 2)]);
+    Hij(j + 1, j) = hnext;
+    double* w = p->V + (int64_t)(j + 1) * n;
+    if (hnext > 0.0) launch_axpby(n, 1.0 / hnext, w, 0.0, nullptr, w, p->stream);
+    for (int i = 0; i < j; ++i) {
+      const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
+      Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
+      Hij(i, j) = t;
+    }
+    const double den = std::hypot(Hij(j, j), Hij(j + 1, j));
+    cs[j] = Hij(j, j) / den;
+    sn[j] = Hij(j + 1, j) / den;
+    Hij(j, j) = den;
+    Hij(j + 1, j) = 0.0;
+    gg[j + 1] = -sn[j] * gg[j];
+    gg[j] = cs[j] * gg[j];
+    st->iterations++;
+    k = j + 1;
+    if (std::fabs(gg[j + 1]) <= p->opts.rtol * bnorm || st->iterations >= p->opts.max_it || k == m)
+      return end_cycle_enqueue();
+    ++j;
+    return 0;
+  }
+  // x += Z y, r = b - A x, ||r|| -> hhost[0]
+  int end_cycle_enqueue() {
+    hipStream_t s = p->stream;
+    const Grid& g = p->lev[0].g;
     for (int i = k - 1; i >= 0; --i) {
       double sacc = gg[i];
       for (int c = i + 1; c < k; ++c) sacc -= Hij(i, c) * y[c];
       y[i] = sacc / Hij(i, i);
     }
-    HIPCHK(hipMemcpyAsync(h1, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-    launch_combine<TZ>(n, Z, n, k, h1, x, s);
-    // true residual r = b - A x
+    if (hipMemcpyAsync(h1(), y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(MVPF_EDEVICE);
+    launch_combine<TZ>(n, (const TZ*)p->Z, n, k, h1(), x, s);
     launch_spmv<double, double, double>(g, p->lev[0].A64, x, p->tmp, p->Cbuf, s, p->outer_G);
     launch_axpby(n, 1.0, b, -1.0, p->tmp, p->tmp, s);
-    TRY(norm_device(p, n, p->tmp, &beta));  // synchronises (y upload complete)
-    st->rel_residual = beta / bnorm;
-    if (st->rel_residual <= rtol) {
-      st->converged = 1;
-      return 0;
-    }
-    if (st->iterations >= p->opts.max_it) return MVPF_ENOTCONV;
-    st->restarts++;
-    r0 = p->tmp;
-    // the next restart overwrites V[0] from tmp before tmp is reused
+    launch_multidot(n, p->tmp, n, 1, p->tmp, p->red, s);
+    launch_reduce(1, nb, p->red, p->hcol, 0, s);
+    if (launch_check(p, "fgmres residual") < 0) return fail(MVPF_EDEVICE);
+    if (hipMemcpyAsync(p->hhost, p->hcol, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return fail(MVPF_EDEVICE);
+    phase = CHECK;
+    return 0;
   }
+  void check_finish() {
+    beta = std::sqrt(p->hhost[0]);
+    st->rel_residual = beta / bnorm;
+    if (st->rel_residual <= p->opts.rtol) {
+      st->converged = 1;
+      phase = DONE;
+      return;
+    }
+    if (st->iterations >= p->opts.max_it) {
+      rc = MVPF_ENOTCONV;
+      phase = DONE;
+      return;
+    }
+    st->restarts++;
+    r0 = p->tmp;  // the next cycle overwrites V[0] from tmp before tmp is reused
+    start_cycle();
+  }
+};
+
+template <typename T, typename TZ>
+int fgmres(mvpf_problem* p, const double* b, double* x, mvpf_solve_stats* st) {
+  Krylov<T, TZ> K;
+  TRY(K.begin(p, b, x, st));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  K.after_begin();
+  while (K.phase != Krylov<T, TZ>::DONE) {
+    if (K.phase == Krylov<T, TZ>::ARNOLDI) {
+      precondition<T, TZ>(p, K.vj(), K.zj());
+      TRY(K.arnoldi_enqueue());
+    }
+    HIPCHK(hipStreamSynchronize(p->stream));
+    if (K.phase == Krylov<T, TZ>::ARNOLDI)
+      TRY(K.arnoldi_finish());
+    else
+      K.check_finish();
+  }
+  return K.rc;
 }
 
 int validate(const mvpf_mesh* mesh, const mvpf_material* mat, const mvpf_loading* load, const mvpf_opts* o,
@@ -807,6 +903,166 @@ void autotune_levels(mvpf_problem* p, int* tuned) {
 }  // namespace
 
 // =============================================================================
+// Batches of independent problems
+// =============================================================================
+// HIPCHK for batch-level code (error text goes to the batch)
+#define BCHK(call)                                                               \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      b->err = std::string(#call) + " failed: " + hipGetErrorString(e_);         \
+      return MVPF_EDEVICE;                                                       \
+    }                                                                            \
+  } while (0)
+
+struct mvpf_batch {
+  int n = 0;
+  bool mixed = false;
+  hipStream_t stream = nullptr;
+  std::vector<mvpf_problem*> probs;
+  // V-cycles of all problems as parallel branches of one graph, reading
+  // vin[i] (FP64) and writing zout[i] (FP32 in mixed mode)
+  std::vector<double*> vin;
+  std::vector<void*> zout;
+  std::vector<hipStream_t> branch;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  // the batched solve runs on its own stream (graphs cannot be captured on
+  // the legacy default stream), ordered after and before the caller's stream
+  hipStream_t work = nullptr;
+  hipEvent_t enter = nullptr, leave = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int> graph_version;  // config_version of each problem at capture
+  std::string err;
+};
+
+namespace {
+
+void batch_drop_graph(mvpf_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+template <typename T, typename TZ>
+int batch_capture(mvpf_batch* b) {
+  batch_drop_graph(b);
+  hipStream_t s = b->work;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    b->err = "hipStreamBeginCapture failed";
+    return MVPF_EDEVICE;
+  }
+  bool ok = hipEventRecord(b->fork, s) == hipSuccess;
+  for (int i = 0; i < b->n && ok; ++i) {
+    mvpf_problem* p = b->probs[i];
+    ok = hipStreamWaitEvent(b->branch[i], b->fork, 0) == hipSuccess;
+    const bool timing = p->timing;
+    p->timing = false;
+    p->stream = b->branch[i];
+    if (ok) precondition<T, TZ>(p, b->vin[i], (TZ*)b->zout[i]);
+    p->stream = s;
+    p->timing = timing;
+    ok = ok && hipEventRecord(b->join[i], b->branch[i]) == hipSuccess &&
+         hipStreamWaitEvent(s, b->join[i], 0) == hipSuccess;
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (!ok || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    b->err = "V-cycle graph capture failed";
+    return MVPF_EDEVICE;
+  }
+  b->graph = g;
+  if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    batch_drop_graph(b);
+    b->err = "V-cycle graph instantiation failed";
+    return MVPF_EDEVICE;
+  }
+  for (int i = 0; i < b->n; ++i) b->graph_version[i] = b->probs[i]->config_version;
+  return 0;
+}
+
+// Lockstep FGMRES over the batch: per Arnoldi step one graph launch runs the
+// V-cycles of all problems, then every active problem enqueues its outer
+// product and Gram-Schmidt work, and one stream synchronisation serves all.
+template <typename T, typename TZ>
+int batch_fgmres(mvpf_batch* b, mvpf_solve_stats* st) {
+  bool stale = !b->exec;
+  for (int i = 0; i < b->n && !stale; ++i) stale = b->graph_version[i] != b->probs[i]->config_version;
+  if (stale) TRY((batch_capture<T, TZ>(b)));
+  hipStream_t s = b->work;
+  std::vector<Krylov<T, TZ>> K(b->n);
+  for (int i = 0; i < b->n; ++i) {
+    mvpf_problem* p = b->probs[i];
+    TRY(K[i].begin(p, p->rhs, p->dx, &st[i]));
+  }
+  BCHK(hipStreamSynchronize(s));
+  for (auto& k : K) k.after_begin();
+  using KP = typename Krylov<T, TZ>::Phase;
+  while (true) {
+    bool any = false, arnoldi = false;
+    for (auto& k : K) {
+      any = any || k.phase != KP::DONE;
+      arnoldi = arnoldi || k.phase == KP::ARNOLDI;
+    }
+    if (!any) break;
+    if (arnoldi) {
+      for (int i = 0; i < b->n; ++i)
+        if (K[i].phase == KP::ARNOLDI)
+          BCHK(hipMemcpyAsync(b->vin[i], K[i].vj(), sizeof(double) * K[i].n, hipMemcpyDeviceToDevice, s));
+      BCHK(hipGraphLaunch(b->exec, s));
+      for (int i = 0; i < b->n; ++i)
+        if (K[i].phase == KP::ARNOLDI) {
+          BCHK(hipMemcpyAsync(K[i].zj(), b->zout[i], sizeof(TZ) * K[i].n, hipMemcpyDeviceToDevice, s));
+          TRY(K[i].arnoldi_enqueue());
+        }
+    }
+    BCHK(hipStreamSynchronize(s));
+    for (auto& k : K) {
+      if (k.phase == KP::ARNOLDI)
+        TRY(k.arnoldi_finish());
+      else if (k.phase == KP::CHECK)
+        k.check_finish();
+    }
+  }
+  int rc = 0;
+  for (auto& k : K)
+    if (k.rc) rc = k.rc;
+  return rc;
+}
+
+void batch_free(mvpf_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  batch_drop_graph(b);
+  for (double*& v : b->vin) dfree(v);
+  for (void*& z : b->zout) {
+    if (z) (void)hipFree(z);
+    z = nullptr;
+  }
+  for (hipStream_t& st : b->branch)
+    if (st) (void)hipStreamDestroy(st);
+  for (hipEvent_t& e : b->join)
+    if (e) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->enter) (void)hipEventDestroy(b->enter);
+  if (b->leave) (void)hipEventDestroy(b->leave);
+  if (b->work) {
+    (void)hipStreamSynchronize(b->work);
+    (void)hipStreamDestroy(b->work);
+  }
+  b->work = nullptr;
+  for (mvpf_problem* p : b->probs)
+    if (p) mvpf_destroy(p);
+  b->probs.clear();
+}
+
+}  // namespace
+
+// =============================================================================
 // C ABI
 // =============================================================================
 extern "C" {
@@ -883,6 +1139,7 @@ int mvpf_set_opts(mvpf_problem* p, const mvpf_opts* o) {
     return MVPF_EINVAL;
   }
   p->opts = *o;
+  p->config_version++;
   return 0;
 }
 
@@ -1097,6 +1354,7 @@ int mvpf_time_step(mvpf_problem* p, double depth, mvpf_step_stats* stats) {
 
 int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value) {
   if (!p || !key || value < 0) return MVPF_EINVAL;
+  p->config_version++;
   if (!std::strcmp(key, "row_blocks")) {
     if (level < 0 || level >= p->L) return MVPF_EINVAL;
     p->row_G[level] = value;
@@ -1144,6 +1402,7 @@ int mvpf_get_tuning(const mvpf_problem* p, const char* key, int level, int* valu
 
 int mvpf_autotune(mvpf_problem* p, int* row_blocks_out) {
   if (!p) return MVPF_EINVAL;
+  p->config_version++;
   if (!p->have_system) { p->err = "autotune needs a Newton system"; return MVPF_ESTATE; }
   int tuned[MAX_LEVELS] = {0};
   if (p->mixed)
@@ -1179,6 +1438,131 @@ int mvpf_kernel_stats(mvpf_problem* p, const char* name, int* launches, double* 
   if (launches) *launches = t->launches;
   if (total_ms) *total_ms = t->total_ms;
   if (bytes_per_launch) *bytes_per_launch = t->bytes;
+  return 0;
+}
+
+
+// ---- batches ----------------------------------------------------------------
+
+int mvpf_create_batch(int n, const mvpf_mesh* meshes, const mvpf_material* mats, const mvpf_loading* loads,
+                      const mvpf_opts* opts, void* stream, mvpf_batch** out) {
+  if (!out) return MVPF_EINVAL;
+  *out = nullptr;
+  if (n < 1 || n > MVPF_MAX_BATCH || !meshes || !mats || !loads || !opts) {
+    g_create_err = "bad batch arguments";
+    return MVPF_EINVAL;
+  }
+  mvpf_batch* b = new mvpf_batch();
+  b->n = n;
+  b->mixed = opts->precision == MVPF_MIXED;
+  b->stream = (hipStream_t)stream;
+  b->probs.assign(n, nullptr);
+  b->vin.assign(n, nullptr);
+  b->zout.assign(n, nullptr);
+  b->branch.assign(n, nullptr);
+  b->join.assign(n, nullptr);
+  b->graph_version.assign(n, -1);
+  int rc = 0;
+  for (int i = 0; i < n && rc == 0; ++i) {
+    rc = mvpf_create(&meshes[i], &mats[i], &loads[i], opts, stream, &b->probs[i]);
+    if (rc) break;
+    const int64_t nv = nvec(b->probs[i]->lev[0].g);
+    if (hipMalloc((void**)&b->vin[i], sizeof(double) * nv) != hipSuccess ||
+        hipMalloc(&b->zout[i], (b->mixed ? sizeof(float) : sizeof(double)) * nv) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->branch[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming) != hipSuccess) {
+      g_create_err = "batch allocation failed";
+      rc = MVPF_ENOMEM;
+    }
+  }
+  if (rc == 0 && (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+                  hipEventCreateWithFlags(&b->enter, hipEventDisableTiming) != hipSuccess ||
+                  hipEventCreateWithFlags(&b->leave, hipEventDisableTiming) != hipSuccess ||
+                  hipStreamCreateWithFlags(&b->work, hipStreamNonBlocking) != hipSuccess)) {
+    g_create_err = "batch stream/event creation failed";
+    rc = MVPF_EDEVICE;
+  }
+  if (rc) {
+    batch_free(b);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return 0;
+}
+
+void mvpf_destroy_batch(mvpf_batch* b) {
+  if (!b) return;
+  batch_free(b);
+  delete b;
+}
+
+const char* mvpf_batch_last_error(const mvpf_batch* b) {
+  if (!b) return g_create_err.c_str();
+  return b->err.c_str();
+}
+
+mvpf_problem* mvpf_batch_problem(mvpf_batch* b, int i) {
+  if (!b || i < 0 || i >= b->n) return nullptr;
+  return b->probs[i];
+}
+
+int mvpf_batch_newton_system(mvpf_batch* b, const double* depths) {
+  if (!b || !depths) return MVPF_EINVAL;
+  for (int i = 0; i < b->n; ++i) {
+    const int rc = mvpf_newton_system(b->probs[i], depths[i]);
+    if (rc) {
+      b->err = "problem " + std::to_string(i) + ": " + b->probs[i]->err;
+      return rc;
+    }
+  }
+  return 0;
+}
+
+int mvpf_batch_solve(mvpf_batch* b, mvpf_solve_stats* stats) {
+  if (!b || !stats) return MVPF_EINVAL;
+  for (int i = 0; i < b->n; ++i)
+    if (!b->probs[i]->have_system) {
+      b->err = "problem " + std::to_string(i) + " has no Newton system";
+      return MVPF_ESTATE;
+    }
+  hipEvent_t e0, e1;
+  BCHK(hipEventCreate(&e0));
+  BCHK(hipEventCreate(&e1));
+  BCHK(hipEventRecord(b->enter, b->stream));
+  BCHK(hipStreamWaitEvent(b->work, b->enter, 0));
+  for (mvpf_problem* p : b->probs) p->stream = b->work;
+  (void)hipEventRecord(e0, b->work);
+  int rc = b->mixed ? batch_fgmres<float, float>(b, stats) : batch_fgmres<double, double>(b, stats);
+  (void)hipEventRecord(e1, b->work);
+  for (mvpf_problem* p : b->probs) p->stream = b->stream;
+  (void)hipEventRecord(b->leave, b->work);
+  (void)hipStreamWaitEvent(b->stream, b->leave, 0);
+  (void)hipEventSynchronize(e1);
+  const double ms = elapsed_ms(e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc < 0) {
+    if (b->err.empty()) b->err = "batched solve failed";
+    return rc;
+  }
+  for (int i = 0; i < b->n; ++i) {
+    stats[i].solve_ms = ms;
+    b->probs[i]->have_solution = true;
+  }
+  if (rc == MVPF_ENOTCONV) b->err = "FGMRES reached max_it on at least one problem";
+  return rc;
+}
+
+int mvpf_batch_newton_update(mvpf_batch* b) {
+  if (!b) return MVPF_EINVAL;
+  for (int i = 0; i < b->n; ++i) {
+    const int rc = mvpf_newton_update(b->probs[i]);
+    if (rc) {
+      b->err = "problem " + std::to_string(i) + ": " + b->probs[i]->err;
+      return rc;
+    }
+  }
   return 0;
 }
 

@@ -175,6 +175,7 @@ struct mvpf_problem {
   int coarse_overlap = -1;           // 1: side stream, 0: problem stream, -1: by size
   int64_t ne_cap = 0;                // element capacity of qp / elem (assembly slab size)
   int64_t ne_use = 0;                // slab size in use (<= ne_cap)
+  int config_version = 0;            // bumped by set_opts / set_tuning / autotune (captured graphs)
 };
 
 namespace mvpf {

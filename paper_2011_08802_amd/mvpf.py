@@ -95,6 +95,14 @@ SIGNATURES = {
     "mvpf_autotune": (C.c_int, [_P, C.POINTER(C.c_int)]),
     "mvpf_kernel_timing": (C.c_int, [_P, C.c_int]),
     "mvpf_kernel_stats": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int), _D, _D]),
+    "mvpf_create_batch": (C.c_int, [C.c_int, C.POINTER(Mesh), C.POINTER(Material), C.POINTER(Loading),
+                                    C.POINTER(Opts), _P, C.POINTER(_P)]),
+    "mvpf_destroy_batch": (None, [_P]),
+    "mvpf_batch_last_error": (C.c_char_p, [_P]),
+    "mvpf_batch_problem": (_P, [_P, C.c_int]),
+    "mvpf_batch_newton_system": (C.c_int, [_P, _D]),
+    "mvpf_batch_solve": (C.c_int, [_P, C.POINTER(SolveStats)]),
+    "mvpf_batch_newton_update": (C.c_int, [_P]),
 }
 
 _lib = None
@@ -141,30 +149,46 @@ def default_opts() -> Opts:
     return o
 
 
+def mesh_struct(prob) -> Mesh:
+    return Mesh(prob.nx, prob.ny, prob.nz, prob.lx / prob.nx, prob.n_levels)
+
+
+def loading_struct(prob) -> Loading:
+    return Loading(LOAD_PATCH if prob.kind == "patch" else LOAD_CAP, prob.patch, prob.radius)
+
+
+def opts_struct(precision: str, **opts) -> Opts:
+    o = default_opts()
+    o.precision = MIXED if precision == "mixed" else FP64
+    for k, v in opts.items():
+        setattr(o, k, v)
+    return o
+
+
 class Problem:
     """One indentation problem on the GPU (handle of mvpf_create)."""
 
-    def __init__(self, prob, precision: str = "fp64", device: int = 0, **opts):
+    def __init__(self, prob, precision: str = "fp64", device: int = 0, _handle=None, _opts=None, **opts):
         lib = load()
         self.lib = lib
         self.prob = prob
         self.device = torch.device("cuda", device)
         self.stream = torch.cuda.current_stream(self.device)
-        mesh = Mesh(prob.nx, prob.ny, prob.nz, prob.lx / prob.nx, prob.n_levels)
-        ld = Loading(LOAD_PATCH if prob.kind == "patch" else LOAD_CAP, prob.patch, prob.radius)
-        o = default_opts()
-        o.precision = MIXED if precision == "mixed" else FP64
-        for k, v in opts.items():
-            setattr(o, k, v)
+        self.n_nodes = prob.n_nodes
+        self.owned = _handle is None
+        if _handle is not None:  # a problem owned by a Batch
+            self.h = _handle
+            self.opts = _opts
+            return
+        o = opts_struct(precision, **opts)
         self.opts = o
         self.mat = material_struct(prob.material)
         h = C.c_void_p()
-        rc = lib.mvpf_create(C.byref(mesh), C.byref(self.mat), C.byref(ld), C.byref(o),
+        rc = lib.mvpf_create(C.byref(mesh_struct(prob)), C.byref(self.mat), C.byref(loading_struct(prob)), C.byref(o),
                              C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if rc != 0:
             raise MvpfError(rc, lib.mvpf_last_error(None).decode())
         self.h = h
-        self.n_nodes = prob.n_nodes
 
     def _check(self, rc, allow=(OK,)):
         if rc not in allow:
@@ -173,7 +197,8 @@ class Problem:
 
     def close(self):
         if getattr(self, "h", None):
-            self.lib.mvpf_destroy(self.h)
+            if self.owned:
+                self.lib.mvpf_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -270,6 +295,67 @@ class Problem:
         n, ms, by = C.c_int(), C.c_double(), C.c_double()
         self._check(self.lib.mvpf_kernel_stats(self.h, name.encode(), C.byref(n), C.byref(ms), C.byref(by)))
         return n.value, ms.value, by.value
+
+
+class Batch:
+    """Independent problems solved in lockstep (mvpf_create_batch); problem(i)
+    returns a Problem view of problem i (owned by the batch)."""
+
+    def __init__(self, probs, precision: str = "mixed", device: int = 0, **opts):
+        lib = load()
+        self.lib = lib
+        self.probs = list(probs)
+        n = len(self.probs)
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.opts = opts_struct(precision, **opts)
+        meshes = (Mesh * n)(*[mesh_struct(p) for p in self.probs])
+        mats = (Material * n)(*[material_struct(p.material) for p in self.probs])
+        loads = (Loading * n)(*[loading_struct(p) for p in self.probs])
+        h = C.c_void_p()
+        rc = lib.mvpf_create_batch(n, meshes, mats, loads, C.byref(self.opts), C.c_void_p(self.stream.cuda_stream),
+                                   C.byref(h))
+        if rc != 0:
+            raise MvpfError(rc, lib.mvpf_batch_last_error(None).decode())
+        self.h = h
+        self.views = [Problem(p, device=device, _handle=C.c_void_p(lib.mvpf_batch_problem(h, i)), _opts=self.opts)
+                      for i, p in enumerate(self.probs)]
+
+    def __len__(self):
+        return len(self.probs)
+
+    def problem(self, i: int) -> Problem:
+        return self.views[i]
+
+    def _check(self, rc, allow=(OK,)):
+        if rc not in allow:
+            raise MvpfError(rc, self.lib.mvpf_batch_last_error(self.h).decode())
+        return rc
+
+    def newton_system(self, depths):
+        d = (C.c_double * len(self.probs))(*[float(x) for x in depths])
+        self._check(self.lib.mvpf_batch_newton_system(self.h, d))
+
+    def solve(self):
+        st = (SolveStats * len(self.probs))()
+        self._check(self.lib.mvpf_batch_solve(self.h, st), allow=(OK, ENOTCONV))
+        return list(st)
+
+    def newton_update(self):
+        self._check(self.lib.mvpf_batch_newton_update(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            for v in self.views:
+                v.h = None
+            self.lib.mvpf_destroy_batch(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def stats_dict(st) -> dict:

@@ -74,3 +74,22 @@ def test_create_rejects_bad_options(lib):
     assert rc == -1 and "Pade" in err
     rc, h, err = _create(lib, mvpf.Mesh(8, 8, 8, 0.125, 3), load=mvpf.Loading(mvpf.LOAD_PATCH, 3, 0.2))
     assert rc == -1 and "patch" in err
+
+
+def test_create_batch_rejects_bad_arguments(lib):
+    """Argument checks of mvpf_create_batch run before any device work."""
+    from paper_2011_08802_amd import mvpf
+    h = C.c_void_p()
+    opts = mvpf.default_opts()
+    rc = lib.mvpf_create_batch(0, None, None, None, C.byref(opts), None, C.byref(h))
+    assert rc == -1 and not h.value and "batch" in lib.mvpf_batch_last_error(None).decode()
+    p = synth.tiny()
+    meshes = (mvpf.Mesh * 1)(mvpf.mesh_struct(p))
+    mats = (mvpf.Material * 1)(mvpf.material_struct(p.material))
+    loads = (mvpf.Loading * 1)(mvpf.loading_struct(p))
+    rc = lib.mvpf_create_batch(1000, meshes, mats, loads, C.byref(opts), None, C.byref(h))
+    assert rc == -1 and not h.value
+    bad = (mvpf.Mesh * 1)(mvpf.Mesh(8, 8, 6, 0.125, 3))
+    rc = lib.mvpf_create_batch(1, bad, mats, loads, C.byref(opts), None, C.byref(h))
+    assert rc == -1 and not h.value and "divisible" in lib.mvpf_batch_last_error(None).decode()
+    assert lib.mvpf_batch_problem(None, 0) is None
