@@ -3,6 +3,7 @@
 // only orchestrates; every arithmetic step on the solve path runs in the HIP
 // kernels of this library.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -686,7 +687,8 @@ int allocate(mvpf_problem* p) {
   TRY(dalloc(p, &p->red, (size_t)(MAX_RESTART + 2) * 1024));
   TRY(dalloc(p, &p->hcol, (size_t)3 * (MAX_RESTART + 2)));
   TRY(dalloc(p, &p->save_state, (size_t)NSTATE * g0.Npad));
-  hipError_t e = hipHostMalloc((void**)&p->hhost, sizeof(double) * 3 * (MAX_RESTART + 2));
+  // Krylov scalars (3 columns) + one slot for the setup status
+  hipError_t e = hipHostMalloc((void**)&p->hhost, sizeof(double) * (3 * (MAX_RESTART + 2) + 1));
   if (e != hipSuccess) {
     p->err = "hipHostMalloc failed";
     return MVPF_ENOMEM;
@@ -805,7 +807,11 @@ int build_system(mvpf_problem* p, double depth) {
 }
 
 // block inverses of the smoother; joins the coarse inversion
-int setup_solver(mvpf_problem* p) {
+// pinned host slot of the setup status
+int* host_status(mvpf_problem* p) { return (int*)(p->hhost + 3 * (MAX_RESTART + 2)); }
+
+// block inverses of the smoother; joins the coarse inversion; status -> host
+int setup_enqueue(mvpf_problem* p) {
   hipStream_t s = p->stream;
   int* status = setup_status(p);
   for (int l = 0; l < p->L - 1; ++l) {
@@ -817,14 +823,23 @@ int setup_solver(mvpf_problem* p) {
     p->coarse_pending = false;
   }
   TRY(launch_check(p, "solver setup"));
-  int hs = 0;
-  HIPCHK(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  if (hs) {
+  HIPCHK(hipMemcpyAsync(host_status(p), status, sizeof(int), hipMemcpyDeviceToHost, s));
+  return 0;
+}
+
+// after the problem's stream has been synchronised
+int setup_finish(mvpf_problem* p) {
+  if (*host_status(p)) {
     p->err = "singular 9x9 diagonal block or coarse operator";
     return MVPF_ESINGULAR;
   }
   return 0;
+}
+
+int setup_solver(mvpf_problem* p) {
+  TRY(setup_enqueue(p));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return setup_finish(p);
 }
 
 double elapsed_ms(hipEvent_t a, hipEvent_t b) {
@@ -959,10 +974,11 @@ int batch_capture(mvpf_batch* b) {
     mvpf_problem* p = b->probs[i];
     ok = hipStreamWaitEvent(b->branch[i], b->fork, 0) == hipSuccess;
     const bool timing = p->timing;
+    const hipStream_t own = p->stream;
     p->timing = false;
     p->stream = b->branch[i];
     if (ok) precondition<T, TZ>(p, b->vin[i], (TZ*)b->zout[i]);
-    p->stream = s;
+    p->stream = own;
     p->timing = timing;
     ok = ok && hipEventRecord(b->join[i], b->branch[i]) == hipSuccess &&
          hipStreamWaitEvent(s, b->join[i], 0) == hipSuccess;
@@ -985,9 +1001,12 @@ int batch_capture(mvpf_batch* b) {
   return 0;
 }
 
-// Lockstep FGMRES over the batch: per Arnoldi step one graph launch runs the
-// V-cycles of all problems, then every active problem enqueues its outer
-// product and Gram-Schmidt work, and one stream synchronisation serves all.
+// Lockstep FGMRES over the batch.  Each problem's own work (outer product,
+// Gram-Schmidt, Givens bookkeeping) runs on its branch stream; per Arnoldi
+// step one graph launch on the work stream runs the V-cycles of all problems
+// (ordered after every branch's pending work and before its next work, so
+// the V-cycles never overlap a problem's own use of its buffers), and one
+// synchronisation of the branches serves all problems.
 template <typename T, typename TZ>
 int batch_fgmres(mvpf_batch* b, mvpf_solve_stats* st) {
   bool stale = !b->exec;
@@ -999,7 +1018,7 @@ int batch_fgmres(mvpf_batch* b, mvpf_solve_stats* st) {
     mvpf_problem* p = b->probs[i];
     TRY(K[i].begin(p, p->rhs, p->dx, &st[i]));
   }
-  BCHK(hipStreamSynchronize(s));
+  for (int i = 0; i < b->n; ++i) BCHK(hipStreamSynchronize(b->branch[i]));
   for (auto& k : K) k.after_begin();
   using KP = typename Krylov<T, TZ>::Phase;
   while (true) {
@@ -1010,17 +1029,27 @@ int batch_fgmres(mvpf_batch* b, mvpf_solve_stats* st) {
     }
     if (!any) break;
     if (arnoldi) {
-      for (int i = 0; i < b->n; ++i)
+      for (int i = 0; i < b->n; ++i) {
+        if (K[i].phase == KP::DONE) continue;
         if (K[i].phase == KP::ARNOLDI)
-          BCHK(hipMemcpyAsync(b->vin[i], K[i].vj(), sizeof(double) * K[i].n, hipMemcpyDeviceToDevice, s));
+          BCHK(hipMemcpyAsync(b->vin[i], K[i].vj(), sizeof(double) * K[i].n, hipMemcpyDeviceToDevice,
+                              b->branch[i]));
+        BCHK(hipEventRecord(b->join[i], b->branch[i]));
+        BCHK(hipStreamWaitEvent(s, b->join[i], 0));
+      }
       BCHK(hipGraphLaunch(b->exec, s));
-      for (int i = 0; i < b->n; ++i)
+      BCHK(hipEventRecord(b->fork, s));
+      for (int i = 0; i < b->n; ++i) {
+        if (K[i].phase == KP::DONE) continue;
+        BCHK(hipStreamWaitEvent(b->branch[i], b->fork, 0));
         if (K[i].phase == KP::ARNOLDI) {
-          BCHK(hipMemcpyAsync(K[i].zj(), b->zout[i], sizeof(TZ) * K[i].n, hipMemcpyDeviceToDevice, s));
+          BCHK(hipMemcpyAsync(K[i].zj(), b->zout[i], sizeof(TZ) * K[i].n, hipMemcpyDeviceToDevice, b->branch[i]));
           TRY(K[i].arnoldi_enqueue());
         }
+      }
     }
-    BCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < b->n; ++i)
+      if (K[i].phase != KP::DONE) BCHK(hipStreamSynchronize(b->branch[i]));
     for (auto& k : K) {
       if (k.phase == KP::ARNOLDI)
         TRY(k.arnoldi_finish());
@@ -1507,14 +1536,37 @@ mvpf_problem* mvpf_batch_problem(mvpf_batch* b, int i) {
   return b->probs[i];
 }
 
+// All problems' assembly and setup are enqueued before one synchronisation,
+// each on its own branch stream (ordered after the caller's stream), so the
+// small problems' latency-bound phases (coarse inversions above all) overlap.
 int mvpf_batch_newton_system(mvpf_batch* b, const double* depths) {
   if (!b || !depths) return MVPF_EINVAL;
+  BCHK(hipEventRecord(b->enter, b->stream));
+  int rc = 0, bad = -1;
+  for (int i = 0; i < b->n && rc == 0; ++i) {
+    mvpf_problem* p = b->probs[i];
+    p->have_system = p->have_solution = false;
+    BCHK(hipStreamWaitEvent(b->branch[i], b->enter, 0));
+    p->stream = b->branch[i];
+    rc = build_system(p, depths[i]);
+    if (rc == 0) rc = setup_enqueue(p);
+    p->stream = b->stream;
+    if (rc) bad = i;
+  }
+  for (int i = 0; i < b->n; ++i) (void)hipStreamSynchronize(b->branch[i]);
+  if (rc) {
+    b->err = "problem " + std::to_string(bad) + ": " + b->probs[bad]->err;
+    return rc;
+  }
   for (int i = 0; i < b->n; ++i) {
-    const int rc = mvpf_newton_system(b->probs[i], depths[i]);
+    mvpf_problem* p = b->probs[i];
+    rc = setup_finish(p);
     if (rc) {
-      b->err = "problem " + std::to_string(i) + ": " + b->probs[i]->err;
+      b->err = "problem " + std::to_string(i) + ": " + p->err;
       return rc;
     }
+    p->sys_depth = depths[i];
+    p->have_system = true;
   }
   return 0;
 }
@@ -1526,22 +1578,16 @@ int mvpf_batch_solve(mvpf_batch* b, mvpf_solve_stats* stats) {
       b->err = "problem " + std::to_string(i) + " has no Newton system";
       return MVPF_ESTATE;
     }
-  hipEvent_t e0, e1;
-  BCHK(hipEventCreate(&e0));
-  BCHK(hipEventCreate(&e1));
-  BCHK(hipEventRecord(b->enter, b->stream));
-  BCHK(hipStreamWaitEvent(b->work, b->enter, 0));
-  for (mvpf_problem* p : b->probs) p->stream = b->work;
-  (void)hipEventRecord(e0, b->work);
+  BCHK(hipStreamSynchronize(b->stream));  // the caller's pending work (states, systems)
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int i = 0; i < b->n; ++i) b->probs[i]->stream = b->branch[i];
   int rc = b->mixed ? batch_fgmres<float, float>(b, stats) : batch_fgmres<double, double>(b, stats);
-  (void)hipEventRecord(e1, b->work);
-  for (mvpf_problem* p : b->probs) p->stream = b->stream;
-  (void)hipEventRecord(b->leave, b->work);
-  (void)hipStreamWaitEvent(b->stream, b->leave, 0);
-  (void)hipEventSynchronize(e1);
-  const double ms = elapsed_ms(e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  for (int i = 0; i < b->n; ++i) {
+    b->probs[i]->stream = b->stream;
+    (void)hipStreamSynchronize(b->branch[i]);
+  }
+  (void)hipStreamSynchronize(b->work);
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (rc < 0) {
     if (b->err.empty()) b->err = "batched solve failed";
     return rc;
