@@ -882,15 +882,24 @@ double time_launches(mvpf_problem* p, int reps, Fn f) {
   return ms;
 }
 
+// Candidate persistent launch shapes for a level: fixed sizes, plus the
+// divisors of the row-block count that give every workgroup the same number
+// of blocks in one residency round (no partial last wave).
+std::vector<int> launch_candidates(const Grid& g) {
+  std::vector<int> c = {0, 4096, 2048, 1536, 1024, 768, 512, 384, 256, 192, 128, 96, 64};
+  const int nb = (g.Npad + 255) / 256;
+  for (int k = 2; k <= 4; ++k) c.push_back(((nb + k - 1) / k + 7) / 8 * 8);
+  return c;
+}
+
 template <typename T>
 void autotune_levels(mvpf_problem* p, int* tuned) {
-  const int cands[] = {0, 4096, 2048, 1536, 1024, 768, 512, 384, 256, 192, 128, 96, 64};
   for (int l = 0; l < p->L - 1; ++l) {
     Level& L = p->lev[l];
     if (L.g.N <= p->small_nodes) continue;  // small-grid kernels have a fixed shape
     double best = 1e30;
     int bestG = 0;
-    for (int G : cands) {
+    for (int G : launch_candidates(L.g)) {
       const double ms = time_launches(p, 5, [&] {
         launch_pbj<T>(L.g, opA<T>(L), opD<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.x2, (T)p->opts.omega, false,
                       p->Cbuf, p->stream, G);
@@ -903,7 +912,7 @@ void autotune_levels(mvpf_problem* p, int* tuned) {
   const Grid& g = p->lev[0].g;
   double best = 1e30;
   int bestG = 0;
-  for (int G : cands) {
+  for (int G : launch_candidates(g)) {
     const double ms = time_launches(p, 5, [&] {
       if (p->mixed)
         launch_spmv<double, float, double>(g, p->lev[0].A64, (const float*)p->Z, p->tmp, p->Cbuf, p->stream, G);

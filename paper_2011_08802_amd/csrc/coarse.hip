@@ -54,11 +54,14 @@ void launch_dense_from_bsr(const Grid& g, const double* A64, double* dense, hipS
 //
 // Outer panels of NB columns c0 .. c0 + nbw - 1.  Inside a panel, sub-panels
 // of PB columns are eliminated with partial pivoting by
-//   1. gj_panel: one workgroup snapshots the sub-panel F = M[:, sub-panel]
-//      in registers, chooses the pivot rows by Gauss-Jordan with partial
-//      pivoting restricted to the sub-panel (rows pivoted earlier are
-//      excluded), places the unit columns and inverts the pivot block
-//      Mp = F[P, :] (Gauss-Jordan with partial pivoting in LDS);
+//   0. gj_fetch: copies the sub-panel F = M[:, sub-panel] (row-major F and
+//      column-major Wc);
+//   1. gj_panel: one workgroup holds the sub-panel in registers, chooses the
+//      pivot rows by elimination with partial pivoting restricted to the
+//      sub-panel (rows pivoted earlier are excluded), places the unit
+//      columns and inverts the pivot block Mp = F[P, :] (Gauss-Jordan in
+//      LDS, rows in pivot order); beyond 4 GJ_THREADS rows the same is done
+//      by one launch per column (gj_col) and gj_pivinv;
 //   2. gj_rows: R = Mp^-1 M[P, active] (the new pivot rows);
 //   3. gj_update: rows in P become R, every other row i becomes
 //      M[i, active] - F[i, :] R,
@@ -74,36 +77,14 @@ constexpr int GJB = 32;   // widest sub-panel
 constexpr int GJ_NB = 128;  // outer panel width
 constexpr int GJ_THREADS = 512;
 
-// argmax of v (ties: lowest index; idx < 0 = no candidate) over the block
-__device__ __forceinline__ void block_argmax(double& v, int& idx, double* sv, int* si) {
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_down(v, off, 64);
-    const int oi = __shfl_down(idx, off, 64);
-    if (oi >= 0 && (ov > v || (ov == v && (idx < 0 || oi < idx)))) { v = ov; idx = oi; }
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) { sv[wid] = v; si[wid] = idx; }
-  __syncthreads();
-  if (wid == 0) {
-    v = (lane < (int)(blockDim.x >> 6)) ? sv[lane] : -1.0;
-    idx = (lane < (int)(blockDim.x >> 6)) ? si[lane] : -1;
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_down(v, off, 64);
-      const int oi = __shfl_down(idx, off, 64);
-      if (oi >= 0 && (ov > v || (ov == v && (idx < 0 || oi < idx)))) { v = ov; idx = oi; }
-    }
-    if (lane == 0) { sv[0] = v; si[0] = idx; }
-  }
-  __syncthreads();
-  v = sv[0];
-  idx = si[0];
-}
-
-// Inverse of the pivot block Mp = F[pr[a], b] (B x B, B <= PB) by Gauss-Jordan
-// with partial pivoting, [Mp | I] in LDS; needs blockDim.x >= 2 B.
+// Inverse of the pivot block Mp = F[pr[a], b] (B x B, B <= PB), rows in
+// pivot order, by Gauss-Jordan on [Mp | I] in LDS.  No pivot search: each
+// pivot was the largest remaining entry of its column over all candidate
+// rows, these rows included, so in pivot order the diagonal is the
+// partial-pivoting choice.  Needs blockDim.x >= 2 B; 2 barriers per column.
 template <int PB>
 __device__ void pivot_block_inverse(int B, const double* __restrict__ F, const int* pr, double* __restrict__ Pinv,
-                                    int* status, double (*Mp)[2 * PB], double* fr, double* sv, int* si) {
+                                    int* status, double (*Mp)[2 * PB], double* fr, double* rowc) {
   const int tid = threadIdx.x;
   for (int idx = tid; idx < B * B; idx += blockDim.x) {
     const int a = idx / B, b = idx % B;
@@ -112,39 +93,17 @@ __device__ void pivot_block_inverse(int B, const double* __restrict__ F, const i
   }
   __syncthreads();
   for (int c = 0; c < B; ++c) {
-    if (tid < 64) {  // pivot search over rows c .. B - 1 (B <= 64) in the first wavefront
-      double bv = (tid >= c && tid < B) ? fabs(Mp[tid][c]) : -1.0;
-      int q = (tid >= c && tid < B) ? tid : -1;
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_down(bv, off, 64);
-        const int oq = __shfl_down(q, off, 64);
-        if (oq >= 0 && (ov > bv || (ov == bv && (q < 0 || oq < q)))) { bv = ov; q = oq; }
-      }
-      if (tid == 0) {
-        si[0] = q;
-        sv[0] = bv;
-      }
-    }
-    __syncthreads();
-    const int q = si[0];
-    if (!(sv[0] > 0.0)) {
+    const double piv = Mp[c][c];
+    if (!(fabs(piv) > 0.0)) {
       if (tid == 0) atomicOr(status, 1);
       return;  // uniform
     }
-    if (q != c && tid < 2 * B) {
-      const double tmp = Mp[c][tid];
-      Mp[c][tid] = Mp[q][tid];
-      Mp[q][tid] = tmp;
-    }
-    __syncthreads();
-    const double ipc = 1.0 / Mp[c][c];
-    __syncthreads();
-    if (tid < 2 * B) Mp[c][tid] *= ipc;
-    if (tid < B) fr[tid] = (tid == c) ? 0.0 : Mp[tid][c];
+    if (tid < 2 * B) rowc[tid] = Mp[c][tid] / piv;
+    if (tid < B) fr[tid] = Mp[tid][c];
     __syncthreads();
     for (int idx = tid; idx < B * 2 * B; idx += blockDim.x) {
       const int r = idx / (2 * B), cc = idx % (2 * B);
-      if (r != c) Mp[r][cc] -= fr[r] * Mp[c][cc];
+      Mp[r][cc] = (r == c) ? rowc[cc] : Mp[r][cc] - fr[r] * rowc[cc];
     }
     __syncthreads();
   }
@@ -157,32 +116,43 @@ __device__ void pivot_block_inverse(int B, const double* __restrict__ F, const i
 // n <= GJ_THREADS * RPT.
 template <int RPT, int PB>
 __global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int B, double* __restrict__ M,
-                                                              double* __restrict__ F, int* __restrict__ done,
+                                                              const double* __restrict__ F,
+                                                              const double* __restrict__ Wc, int* __restrict__ done,
                                                               int* __restrict__ prow, double* __restrict__ Pinv,
                                                               int* status) {
-  __shared__ double sv[GJ_THREADS / 64];
-  __shared__ int si[GJ_THREADS / 64];
-  __shared__ double prowv[PB];
   __shared__ double Mp[PB][2 * PB];
   __shared__ double fr[PB];
+  __shared__ double rowc[2 * PB];
   __shared__ int pr[PB];
   const int tid = threadIdx.x;
   const int64_t w = 2 * (int64_t)n;
   double W[RPT][PB];
   bool act[RPT];
+  // The sub-panel comes column-major from gj_fetch (Wc[b][i], F = its
+  // row-major copy), so the loads of a wavefront are 64 consecutive rows.
+  // Addresses are clamped and loaded unconditionally (all in flight at
+  // once); window entries of rows i >= n or columns b >= B are never used
+  // (such rows are inactive, and window positions at or beyond B - jj never
+  // become the active column).
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int i = tid + q * GJ_THREADS;
-    act[q] = i < n && !done[i];
+    const bool ok = i < n;
+    const int ic = ok ? i : 0;
+    act[q] = !done[ic] && ok;
 #pragma unroll
-    for (int b = 0; b < PB; ++b) {
-      const double v = (i < n && b < B) ? M[(int64_t)i * w + c0 + b] : 0.0;
-      W[q][b] = v;
-      if (i < n && b < B) F[(int64_t)i * B + b] = v;
-    }
+    for (int b = 0; b < PB; ++b) W[q][b] = Wc[(int64_t)(b < B ? b : B - 1) * n + ic];
   }
   // Register window: after each step the rows' entries shift left by one, so
   // the active column is always W[q][0] (all register indices static).
+  // One barrier per column: every wavefront's best row publishes its value,
+  // index and window in LDS slots (double-buffered by column parity), and
+  // every thread then picks the block's winner from the NW slots itself.
+  constexpr int NW = GJ_THREADS / 64;
+  __shared__ double cv[2][NW];
+  __shared__ int ci[2][NW];
+  __shared__ double crow[2][NW][PB];
+  const int wid = tid >> 6, lane = tid & 63;
 #pragma unroll 1
   for (int jj = 0; jj < B; ++jj) {
     double v = -1.0;
@@ -192,38 +162,62 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int
       const double cand = fabs(W[q][0]);
       if (act[q] && cand > v) { v = cand; idx = tid + q * GJ_THREADS; }
     }
-    block_argmax(v, idx, sv, si);
-    if (!(v > 0.0) || idx < 0) {
+    // wavefront argmax, ties to the lowest row; every lane ends with it
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off, 64);
+      const int oi = __shfl_xor(idx, off, 64);
+      if (oi >= 0 && (idx < 0 || ov > v || (ov == v && oi < idx))) { v = ov; idx = oi; }
+    }
+    const int par = jj & 1;
+    if (idx >= 0 && idx % GJ_THREADS == tid) {
+      const int q = idx / GJ_THREADS;
+      cv[par][wid] = v;
+      ci[par][wid] = idx;
+#pragma unroll
+      for (int qq = 0; qq < RPT; ++qq)
+        if (qq == q) {
+#pragma unroll
+          for (int b = 0; b < PB; ++b) crow[par][wid][b] = W[qq][b];
+        }
+    } else if (idx < 0 && lane == 0) {
+      cv[par][wid] = -1.0;
+      ci[par][wid] = -1;
+    }
+    __syncthreads();
+    double bv = -1.0;
+    int p = -1, pw = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const double ov = cv[par][k];
+      const int oi = ci[par][k];
+      if (oi >= 0 && (p < 0 || ov > bv || (ov == bv && oi < p))) { bv = ov; p = oi; pw = k; }
+    }
+    if (!(bv > 0.0) || p < 0) {
       if (tid == 0) atomicOr(status, 1);
       return;  // uniform
     }
-    const int p = idx;
     if (p % GJ_THREADS == tid) {
       const int q = p / GJ_THREADS;
 #pragma unroll
       for (int qq = 0; qq < RPT; ++qq)
-        if (qq == q) {
-          act[qq] = false;
-#pragma unroll
-          for (int b = 0; b < PB; ++b) prowv[b] = W[qq][b];
-        }
+        if (qq == q) act[qq] = false;
       done[p] = 1;
       prow[c0 + jj] = p;
       pr[jj] = p;
       M[(int64_t)p * w + n + c0 + jj] = 1.0;  // unit column of the new pivot
     }
-    __syncthreads();
-    const double ip = 1.0 / prowv[0];
+    const double* prw = crow[par][pw];
+    const double ip = 1.0 / prw[0];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const double f = act[q] ? W[q][0] * ip : 0.0;
 #pragma unroll
-      for (int b = 1; b < PB; ++b) W[q][b - 1] = W[q][b] - f * prowv[b];
+      for (int b = 1; b < PB; ++b) W[q][b - 1] = W[q][b] - f * prw[b];
       W[q][PB - 1] = 0.0;
     }
-    __syncthreads();
   }
-  pivot_block_inverse<PB>(B, F, pr, Pinv, status, Mp, fr, sv, si);
+  __syncthreads();  // pr[] complete
+  pivot_block_inverse<PB>(B, F, pr, Pinv, status, Mp, fr, rowc);
 }
 
 // active column j (0 .. 2 nbw - 1) of the outer panel at c0
@@ -240,8 +234,13 @@ __global__ void __launch_bounds__(256) gj_rows_kernel(int n, int c0, int nbw, in
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= 2 * nbw) return;
   const int64_t c = gj_col(n, c0, nbw, j);
+  double mv[GJB];
+#pragma unroll
+  for (int b = 0; b < GJB; ++b) mv[b] = M[(int64_t)prow[s0 + (b < B ? b : B - 1)] * w + c];  // all loads at once
   double s = 0.0;
-  for (int b = 0; b < B; ++b) s += Pinv[a * B + b] * M[(int64_t)prow[s0 + b] * w + c];
+#pragma unroll
+  for (int b = 0; b < GJB; ++b)
+    if (b < B) s += Pinv[a * B + b] * mv[b];
   R[(int64_t)a * 2 * nbw + j] = s;
 }
 
@@ -269,9 +268,11 @@ __global__ void __launch_bounds__(256) gj_update_kernel(int n, int c0, int nbw, 
   __syncthreads();
   if (j >= 2 * nbw) return;
   const int64_t c = gj_col(n, c0, nbw, j);
+  // unconditional clamped loads; entries b >= B meet zero padding in Fs and
+  // are never selected as a pivot row's value
   double Rc[GJB];
 #pragma unroll
-  for (int b = 0; b < GJB; ++b) Rc[b] = (b < B) ? R[(int64_t)b * 2 * nbw + j] : 0.0;
+  for (int b = 0; b < GJB; ++b) Rc[b] = R[(int64_t)(b < B ? b : B - 1) * 2 * nbw + j];
   for (int rr = 0; rr < UPR; ++rr) {
     const int i = r0 + rr;
     if (i >= n) break;
@@ -389,12 +390,11 @@ __global__ void __launch_bounds__(256) gj_pivinv_kernel(int s0, int B, const dou
                                                         int* status) {
   __shared__ double Mp[GJB][2 * GJB];
   __shared__ double fr[GJB];
-  __shared__ double sv[1];
-  __shared__ int si[1];
+  __shared__ double rowc[2 * GJB];
   __shared__ int pr[GJB];
   if (threadIdx.x < B) pr[threadIdx.x] = prow[s0 + threadIdx.x];
   __syncthreads();
-  pivot_block_inverse<GJB>(B, F, pr, Pinv, status, Mp, fr, sv, si);
+  pivot_block_inverse<GJB>(B, F, pr, Pinv, status, Mp, fr, rowc);
 }
 
 // Yo[i][k] = M[i][n + c0 + k] - [i == p_{c0+k}];  Rb[k][j] = M[p_{c0+k}][c0 + nbw + j]
@@ -526,19 +526,19 @@ int dense_invert(int n, double* a, double* inv, double* work, int* status, hipSt
     const int nbw = std::min(GJ_NB, n - c0);
     for (int s0 = c0; s0 < c0 + nbw; s0 += PBW) {
       const int B = std::min(PBW, c0 + nbw - s0);
+      gj_fetch_kernel<<<(int)(((int64_t)n * B + 255) / 256), 256, 0, s>>>(n, s0, B, M, F, Wc);
       if (wide) {
-        gj_fetch_kernel<<<(int)(((int64_t)n * B + 255) / 256), 256, 0, s>>>(n, s0, B, M, F, Wc);
         for (int jj = 0; jj <= B; ++jj)
           gj_col_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, s0, B, jj, Wc, keys, done, prow, M, status);
         gj_pivinv_kernel<<<1, 256, 0, s>>>(s0, B, F, prow, Pinv, status);
       } else if (n <= GJ_THREADS) {
-        gj_panel_kernel<1, 32><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
+        gj_panel_kernel<1, 32><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, Wc, done, prow, Pinv, status);
       } else if (n <= 2 * GJ_THREADS) {
-        gj_panel_kernel<2, 32><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
+        gj_panel_kernel<2, 32><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, Wc, done, prow, Pinv, status);
       } else if (n <= 3 * GJ_THREADS) {
-        gj_panel_kernel<3, 16><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
+        gj_panel_kernel<3, 16><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, Wc, done, prow, Pinv, status);
       } else {
-        gj_panel_kernel<4, 16><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, done, prow, Pinv, status);
+        gj_panel_kernel<4, 16><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, Wc, done, prow, Pinv, status);
       }
       gj_rows_kernel<<<dim3((2 * nbw + 255) / 256, B), 256, 0, s>>>(n, c0, nbw, s0, B, M, prow, Pinv, R);
       gj_update_kernel<<<dim3((2 * nbw + 255) / 256, (n + UPR - 1) / UPR), 256, 0, s>>>(n, c0, nbw, s0, B, M, F,
