@@ -684,7 +684,7 @@ int allocate(mvpf_problem* p) {
     TRY(dalloc(p, &z, (size_t)p->restart_cap * n * (p->mixed ? sizeof(float) : sizeof(double))));
     p->Z = z;
   }
-  TRY(dalloc(p, &p->red, (size_t)(MAX_RESTART + 2) * 1024));
+  TRY(dalloc(p, &p->red, (size_t)(MAX_RESTART + 2) * MAX_RED_BLOCKS));
   TRY(dalloc(p, &p->hcol, (size_t)3 * (MAX_RESTART + 2)));
   TRY(dalloc(p, &p->save_state, (size_t)NSTATE * g0.Npad));
   // Krylov scalars (3 columns) + one slot for the setup status

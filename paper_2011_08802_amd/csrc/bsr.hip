@@ -47,16 +47,17 @@ inline int row_grid(const Grid& g, int G) {
 //  pass 2 (row m): acc_m (-)= sum_u C[u-1][.][m] over the in-grid lower
 //    neighbours, then the kernel's epilogue (defect, Jacobi update, product).
 // C holds 13 * 9 * Npad values of the accumulation type.
+// Stored blocks u0 .. u1 - 1 of row n (see upper_pass).
 template <bool SUB, typename TA, typename TX, typename TC>
-__device__ __forceinline__ void upper_pass(const Grid& g, const TA* __restrict__ A, const TX* __restrict__ x, int n,
-                                           TC acc[9], TC* __restrict__ C) {
+__device__ __forceinline__ void upper_range(const Grid& g, const TA* __restrict__ A, const TX* __restrict__ x, int n,
+                                            int u0, int u1, TC acc[9], TC* __restrict__ C) {
   const int t = n >> 6, l = n & 63;
   const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
   TC xn[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) xn[c] = (TC)x[(int64_t)c * g.Npad + n];
 #pragma unroll 1
-  for (int u = 0; u < NUP; ++u) {
+  for (int u = u0; u < u1; ++u) {
     const int s = 13 + u;
     const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
     if (!((i + dx >= 0) && (i + dx < g.nnx) && (j + dy >= 0) && (j + dy < g.nny) && (k + dz < g.nnz))) continue;
@@ -94,6 +95,24 @@ __device__ __forceinline__ void upper_pass(const Grid& g, const TA* __restrict__
 #pragma unroll
       for (int c = 0; c < 9; ++c) Cu[(int64_t)c * g.Npad] = ct[c];
     }
+  }
+}
+
+// The 14 stored blocks are summed in two halves, u < USPLIT into acc and
+// u >= USPLIT into a separate partial that is then added (or subtracted):
+// the split kernels give each half its own wavefront, and every kernel
+// family uses this same order, so results do not depend on the launch shape.
+constexpr int USPLIT = 7;
+
+template <bool SUB, typename TA, typename TX, typename TC>
+__device__ __forceinline__ void upper_pass(const Grid& g, const TA* __restrict__ A, const TX* __restrict__ x, int n,
+                                           TC acc[9], TC* __restrict__ C) {
+  upper_range<SUB>(g, A, x, n, 0, USPLIT, acc, C);
+  TC p1[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  upper_range<false>(g, A, x, n, USPLIT, NUP, p1, C);
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
+    if (SUB) acc[r] -= p1[r]; else acc[r] += p1[r];
   }
 }
 
@@ -139,10 +158,47 @@ __global__ void __launch_bounds__(256) spmv_lower_kernel(Grid g, TY* __restrict_
   }
 }
 
+// Pass 1 with the two halves of each tile's blocks on two wavefronts: a
+// workgroup = 2 tiles x 2 halves; the second half's partial row sums go
+// through LDS to the first, which finishes the row (same order as
+// upper_pass).  Twice as many, shorter wavefronts as the one-wave kernels.
+__device__ __forceinline__ int split_tile(int b, int nb_pad) {
+  const int per = nb_pad >> 3;
+  return ((b & 7) * per + (b >> 3)) * 2;  // first tile of logical block (XCD-contiguous)
+}
+inline int split_grid(const Grid& g) { return ((g.ntiles + 1) / 2 + 7) / 8 * 8; }
+
+template <typename TA, typename TX, typename TY>
+__global__ void __launch_bounds__(256) spmv_upper_split_kernel(Grid g, const TA* __restrict__ A,
+                                                               const TX* __restrict__ x, TY* __restrict__ y,
+                                                               TY* __restrict__ C) {
+  __shared__ TY sh[2][9][64];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, tl = w >> 1, half = w & 1;
+  const int t = split_tile(blockIdx.x, gridDim.x) + tl;
+  const int n = t * TILE + l;
+  const bool valid = t < g.ntiles;
+  TY acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (valid && n < g.N) upper_range<false>(g, A, x, n, half ? USPLIT : 0, half ? NUP : USPLIT, acc, C);
+  if (half) {
+#pragma unroll
+    for (int r = 0; r < 9; ++r) sh[tl][r][l] = acc[r];
+  }
+  __syncthreads();
+  if (!half && valid) {
+#pragma unroll
+    for (int r = 0; r < 9; ++r) y[(int64_t)r * g.Npad + n] = acc[r] + sh[tl][r][l];
+  }
+}
+
 template <typename TA, typename TX, typename TY>
 void launch_spmv(const Grid& g, const TA* A, const TX* x, TY* y, void* C, hipStream_t s, int G) {
   const int nb = row_grid(g, G);
-  spmv_upper_kernel<TA, TX, TY><<<nb, 256, 0, s>>>(g, A, x, y, (TY*)C);
+  // FP64 operators keep one wavefront per tile (2 waves per SIMD fit either
+  // way and the split measured slower); FP32 ones split
+  if (G <= 0 && sizeof(TA) == 4)
+    spmv_upper_split_kernel<TA, TX, TY><<<split_grid(g), 256, 0, s>>>(g, A, x, y, (TY*)C);
+  else
+    spmv_upper_kernel<TA, TX, TY><<<nb, 256, 0, s>>>(g, A, x, y, (TY*)C);
   spmv_lower_kernel<TY><<<nb, 256, 0, s>>>(g, y, (const TY*)C);
 }
 template void launch_spmv<double, double, double>(const Grid&, const double*, const double*, double*, void*,
@@ -182,9 +238,43 @@ __global__ void __launch_bounds__(256) defect_lower_kernel(Grid g, T* __restrict
 }
 
 template <typename T>
+__global__ void __launch_bounds__(256) defect_upper_split_kernel(Grid g, const T* __restrict__ A,
+                                                                 const T* __restrict__ x, const T* __restrict__ b,
+                                                                 T* __restrict__ r, T* __restrict__ C) {
+  __shared__ T sh[2][9][64];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, tl = w >> 1, half = w & 1;
+  const int t = split_tile(blockIdx.x, gridDim.x) + tl;
+  const int n = t * TILE + l;
+  const bool valid = t < g.ntiles;
+  T acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (valid && !half) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] = b[(int64_t)c * g.Npad + n];
+  }
+  if (valid && n < g.N) {
+    if (half)
+      upper_range<false>(g, A, x, n, USPLIT, NUP, acc, C);
+    else
+      upper_range<true>(g, A, x, n, 0, USPLIT, acc, C);
+  }
+  if (half) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) sh[tl][c][l] = acc[c];
+  }
+  __syncthreads();
+  if (!half && valid) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) r[(int64_t)c * g.Npad + n] = (n < g.N) ? acc[c] - sh[tl][c][l] : (T)0;
+  }
+}
+
+template <typename T>
 void launch_defect(const Grid& g, const T* A, const T* x, const T* b, T* r, void* C, hipStream_t s, int G) {
   const int nb = row_grid(g, G);
-  defect_upper_kernel<T><<<nb, 256, 0, s>>>(g, A, x, b, r, (T*)C);
+  if (G <= 0)
+    defect_upper_split_kernel<T><<<split_grid(g), 256, 0, s>>>(g, A, x, b, r, (T*)C);
+  else
+    defect_upper_kernel<T><<<nb, 256, 0, s>>>(g, A, x, b, r, (T*)C);
   defect_lower_kernel<T><<<nb, 256, 0, s>>>(g, r, (const T*)C);
 }
 template void launch_defect<float>(const Grid&, const float*, const float*, const float*, float*, void*, hipStream_t,
@@ -244,7 +334,10 @@ void launch_pbj(const Grid& g, const T* A, const T* Dinv, const T* x, const T* b
     pbj_zero_kernel<T><<<nb, 256, 0, s>>>(g, Dinv, b, xo, omega);
     return;
   }
-  defect_upper_kernel<T><<<nb, 256, 0, s>>>(g, A, x, b, xo, (T*)C);
+  if (G <= 0)
+    defect_upper_split_kernel<T><<<split_grid(g), 256, 0, s>>>(g, A, x, b, xo, (T*)C);
+  else
+    defect_upper_kernel<T><<<nb, 256, 0, s>>>(g, A, x, b, xo, (T*)C);
   pbj_lower_kernel<T><<<nb, 256, 0, s>>>(g, Dinv, x, xo, (const T*)C, omega);
 }
 template void launch_pbj<float>(const Grid&, const float*, const float*, const float*, const float*, float*, float,

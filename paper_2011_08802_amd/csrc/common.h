@@ -123,6 +123,8 @@ namespace mvpf {
 // coarsest levels up to this many unknowns are inverted on a side stream,
 // overlapping the assembly of the finer levels
 constexpr int COARSE_OVERLAP_MAX = 2048;
+// most blocks of a two-stage reduction (partials per reduced value)
+constexpr int MAX_RED_BLOCKS = 4096;
 // assembly buffers: the whole finest level up to this size, else slabs
 constexpr int64_t ASSEMBLY_FULL_MAX = (int64_t)96 << 30;
 constexpr int64_t ASSEMBLY_SLAB_BYTES = (int64_t)40 << 30;

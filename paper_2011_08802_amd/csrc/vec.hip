@@ -19,23 +19,47 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 int red_blocks(int64_t n) {
-  const int64_t b = (n + 4095) / 4096;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 1024));
+  const int64_t b = (n + 1023) / 1024;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, MAX_RED_BLOCKS));
 }
 
-// part[j * nblk + blk] = sum over the block's chunk of V_j . w, j < k
+// part[j * nblk + blk] = sum over the block's chunk of V_j . w, j < k.
+// The vectors are taken MD_G at a time, so w is read once per group (not
+// once per vector), and the group's MD_G block sums share one barrier.
+constexpr int MD_G = 8;
 __global__ void __launch_bounds__(RB) multidot_kernel(int64_t n, const double* __restrict__ V, int64_t ldv, int k,
                                                       const double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double sh[RB / 64];
+  __shared__ double sh[MD_G][RB / 64];
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = std::min<int64_t>(n, lo + chunk);
-  for (int j = 0; j < k; ++j) {
-    const double* vj = V + (int64_t)j * ldv;
-    double s = 0.0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += RB) s += vj[i] * w[i];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = s;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < k; j0 += MD_G) {
+    const int g_n = std::min(MD_G, k - j0);  // uniform
+    double s[MD_G];
+#pragma unroll
+    for (int g = 0; g < MD_G; ++g) s[g] = 0.0;
+    const double* v0 = V + (int64_t)j0 * ldv;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += RB) {
+      const double wi = w[i];
+#pragma unroll
+      for (int g = 0; g < MD_G; ++g)
+        if (g < g_n) s[g] += v0[(int64_t)g * ldv + i] * wi;
+    }
+#pragma unroll
+    for (int g = 0; g < MD_G; ++g) {
+      double v = s[g];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if (lane == 0) sh[g][wid] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < g_n) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < RB / 64; ++q) t += sh[threadIdx.x][q];
+      part[(int64_t)(j0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
+    }
+    __syncthreads();
   }
 }
 
