@@ -219,30 +219,32 @@ def batched_main(a):
 
 
 def sweep_traffic(prob):
-    """Measured HBM bytes of one finest-level smoother sweep (defect_upper +
-    pbj_lower) from the committed counter summary, for the workload it was
-    taken on (64^3), else None."""
+    """Measured HBM bytes of one finest-level smoother sweep (pass 1 on two
+    wavefronts per tile + pass 2) from the committed counter summary, for the
+    workload it was taken on (64^3), else None."""
     if (prob.nx, prob.ny, prob.nz) != (64, 64, 64) or not os.path.exists(COUNTERS):
         return None
     npad = prob.n_nodes + (-prob.n_nodes) % 64
-    grid = ((npad + 255) // 256 + 7) // 8 * 8 * 256  # threads of the default finest row-kernel launch
+    ntiles = npad // 64
+    want = {
+        "mvpf::defect_upper_split_kernel<float>": ((ntiles + 1) // 2 + 7) // 8 * 8 * 256,
+        "mvpf::pbj_lower_kernel<float>": ((npad + 255) // 256 + 7) // 8 * 8 * 256,
+    }
     total = 0.0
     found = set()
     with open(COUNTERS) as f:
         for line in f:
             parts = line.split()
-            if len(parts) < 7 or not parts[0].startswith("mvpf::"):
+            if len(parts) < 7 or parts[0] not in want:
                 continue
-            name = parts[0]
-            if name.startswith("mvpf::defect_upper_kernel<float>") or name.startswith("mvpf::pbj_lower_kernel<float>"):
-                try:
-                    g = int(parts[1])
-                    rd, wr = float(parts[-2]), float(parts[-1])
-                except ValueError:
-                    continue
-                if g == grid and name not in found:
-                    found.add(name)
-                    total += (rd + wr) * 1e6
+            try:
+                g = int(parts[1])
+                rd, wr = float(parts[-2]), float(parts[-1])
+            except ValueError:
+                continue
+            if g == want[parts[0]] and parts[0] not in found:
+                found.add(parts[0])
+                total += (rd + wr) * 1e6
     return total if len(found) == 2 else None
 
 
@@ -356,7 +358,7 @@ def main():
     if k:
         out["roofline"] = {"bound": "hbm", "achieved": k["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": k["gbs"] / HBM_PEAK_GBS, "traffic": sweep_traffic(prob),
-                           "kernel": "finest-level FP32 smoother sweep (defect_upper + pbj_lower)",
+                           "kernel": "finest-level FP32 smoother sweep (defect_upper_split + pbj_lower)",
                            "bytes_per_launch": k["bytes"], "avg_ms": k["avg_ms"], "launches": k["launches"]}
         out["kernels"] = mixed["kernels"]
     if not a.no_cpu_baseline:
