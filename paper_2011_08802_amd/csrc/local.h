@@ -283,6 +283,17 @@ __device__ __forceinline__ void dC_of(const LocalBase& b, const DevCard& cd, int
   dc[3] = dcf[5]; dc[4] = dcf[2]; dc[5] = dcf[1];
 }
 
+// a[i] for a runtime i in 0..5 from six values (selection, no indexing)
+__device__ __forceinline__ double pick6(int i, double a0, double a1, double a2, double a3, double a4, double a5) {
+  double r = a0;
+  r = (i == 1) ? a1 : r;
+  r = (i == 2) ? a2 : r;
+  r = (i == 3) ? a3 : r;
+  r = (i == 4) ? a4 : r;
+  r = (i == 5) ? a5 : r;
+  return r;
+}
+
 // Q_k = G dU_k (full)
 __device__ __forceinline__ void Q_of(const LocalBase& b, const DevCard& cd, int k, double Q[9]) {
   double dU[9];
@@ -469,11 +480,11 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
     mm(b.G, Sf, GS);
     mm(GS, b.G, GSG);
   }
-  // per eta_k: dC (dce), dw/deta_k (wqe), dJ_t (Jq), and Ak[k][v] = wCeta[v][k] - 2 (S Q_k) : E_v
-  double dce[6][6], wqe[6], Jq[6], Ak[6][6];
+  // per eta_k: dC (dce), dw/deta_k (wqe), dJ_t (Jq)
+  double dce[6][6], wqe[6], Jq[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    double Q[9], dcf[9], P[9];
+    double Q[9], dcf[9];
     Q_of(b, cd, k, Q);
     Jq[k] = b.Jt * (Q[0] + Q[4] + Q[8]);
     dC_eta(b, Q, dce[k], dcf);
@@ -481,9 +492,6 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
 #pragma unroll
     for (int v = 0; v < 6; ++v) s += b.wC[v] * dce[k][v];
     wqe[k] = s;
-    mm(Sf, Q, P);
-#pragma unroll
-    for (int v = 0; v < 6; ++v) Ak[k][v] = wCeta[v][k] - 2.0 * contract_basis(P, v);
     g[9 + k] = b.Jt * wqe[k] + Jq[k] * b.w;
   }
   // eta-eta block
@@ -496,43 +504,92 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
     etan[0] = 1.0 - sn;
   }
   const double pen0 = (eta[0] < 0.0) ? cd.eps : 0.0;
-#pragma unroll
+  // Runtime (not unrolled) loops over the pairs k <= l: unrolled, the
+  // compiler keeps every Q_l product of all pairs live at once.  Values of
+  // the per-eta register arrays are picked by static-index selection.
+#pragma unroll 1
   for (int k = 0; k < 6; ++k) {
-    double Qk[9], SQ[9], Rk[9], Uk[9], WCk[6];
+    double Qk[9], SQ[9], Rk[9], Uk[9], WCk[6], dk[6], wek[6];
     Q_of(b, cd, k, Qk);
     mm(Sf, Qk, SQ);
     mm(b.C, SQ, Rk);  // C S Q_k
     mm(SQ, b.C, Uk);  // S Q_k C
 #pragma unroll
+    for (int v = 0; v < 6; ++v) {
+      dk[v] = pick6(k, dce[0][v], dce[1][v], dce[2][v], dce[3][v], dce[4][v], dce[5][v]);
+      wek[v] = pick6(k, wCeta[v][0], wCeta[v][1], wCeta[v][2], wCeta[v][3], wCeta[v][4], wCeta[v][5]);
+    }
+#pragma unroll
     for (int u = 0; u < 6; ++u) {
       double s = 0.0;
 #pragma unroll
-      for (int v = 0; v < 6; ++v) s += wCC[u][v] * dce[k][v];
+      for (int v = 0; v < 6; ++v) s += wCC[u][v] * dk[v];
       WCk[u] = s;
     }
     const double trk = Qk[0] + Qk[4] + Qk[8];
-#pragma unroll
+    const double Jqk = pick6(k, Jq[0], Jq[1], Jq[2], Jq[3], Jq[4], Jq[5]);
+    const double wqk = pick6(k, wqe[0], wqe[1], wqe[2], wqe[3], wqe[4], wqe[5]);
+    const double etak = pick6(k, eta[1], eta[2], eta[3], eta[4], eta[5], eta[6]);
+#pragma unroll 1
     for (int l = k; l < 6; ++l) {
-      double Ql[9], SQl[9], Rl[9];
+      double Ql[9], SQl[9], Rl[9], dl[6], wel[6];
       Q_of(b, cd, l, Ql);
       mm(Sf, Ql, SQl);
       mm(b.C, SQl, Rl);  // C S Q_l
+#pragma unroll
+      for (int v = 0; v < 6; ++v) {
+        dl[v] = pick6(l, dce[0][v], dce[1][v], dce[2][v], dce[3][v], dce[4][v], dce[5][v]);
+        wel[v] = pick6(l, wCeta[v][0], wCeta[v][1], wCeta[v][2], wCeta[v][3], wCeta[v][4], wCeta[v][5]);
+      }
       double s = 0.0;
 #pragma unroll
-      for (int u = 0; u < 6; ++u) s += WCk[u] * dce[l][u];
+      for (int u = 0; u < 6; ++u) s += WCk[u] * dl[u];
       s += 2.0 * (trprod(Rk, Ql) + trprod(Rl, Qk) + ddot9(Uk, Ql));
 #pragma unroll
-      for (int v = 0; v < 6; ++v) s += wCeta[v][l] * dce[k][v] + wCeta[v][k] * dce[l][v];
+      for (int v = 0; v < 6; ++v) s += wel[v] * dk[v] + wek[v] * dl[v];
       const double trl = Ql[0] + Ql[4] + Ql[8];
       const double Jkl = b.Jt * (trk * trl - trprod(Qk, Ql));
-      double val = b.Jt * s + Jq[k] * wqe[l] + Jq[l] * wqe[k] + Jkl * b.w;
+      const double Jql = pick6(l, Jq[0], Jq[1], Jq[2], Jq[3], Jq[4], Jq[5]);
+      const double wql = pick6(l, wqe[0], wqe[1], wqe[2], wqe[3], wqe[4], wqe[5]);
+      double val = b.Jt * s + Jqk * wql + Jql * wqk + Jkl * b.w;
       // order-parameter terms
       val += cd.Sw[k][l] + cd.rho * ((k == l ? 1.0 : 0.0) + 1.0) + pen0;
-      if (k == l && eta[k + 1] < 0.0) val += cd.eps;
+      if (k == l && etak < 0.0) val += cd.eps;
       D[hidx(9 + k, 9 + l) * ds] = val;
     }
   }
-  // F-F and F-eta blocks
+  // F-eta block, runtime loop over k: with ak = wCeta[., k] - 2 (S Q_k) : E_.
+  // and wdk = wCC dC_k (wCC symmetric), entry (F_q, eta_k) is
+  // J_t (wdk + ak) . dC_q + dJ_t/deta_k  dw/dF_q
+#pragma unroll 1
+  for (int k = 0; k < 6; ++k) {
+    double Q[9], P[9], t[6];
+    Q_of(b, cd, k, Q);
+    mm(Sf, Q, P);  // S G dU_k
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      double wdk = 0.0;
+#pragma unroll
+      for (int v = 0; v < 6; ++v)
+        wdk += wCC[u][v] * pick6(k, dce[0][v], dce[1][v], dce[2][v], dce[3][v], dce[4][v], dce[5][v]);
+      t[u] = wdk + pick6(k, wCeta[u][0], wCeta[u][1], wCeta[u][2], wCeta[u][3], wCeta[u][4], wCeta[u][5]) -
+             2.0 * contract_basis(P, u);
+    }
+    const double Jqk = pick6(k, Jq[0], Jq[1], Jq[2], Jq[3], Jq[4], Jq[5]);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      double dcq[6];
+      dC_F(b, q, dcq);
+      double wq = 0.0, s = 0.0;
+#pragma unroll
+      for (int v = 0; v < 6; ++v) {
+        wq += b.wC[v] * dcq[v];
+        s += t[v] * dcq[v];
+      }
+      D[hidx(q, 9 + k) * ds] = b.Jt * s + Jqk * wq;
+    }
+  }
+  // F-F block and the F part of the gradient
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     double dcq[6];
@@ -560,13 +617,6 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
       const int k = r / 3, l = r % 3;
       if (i == k) s += 2.0 * GSG[3 * j + l];
       D[hidx(q, r) * ds] = b.Jt * s;
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      double s = 0.0;
-#pragma unroll
-      for (int u = 0; u < 6; ++u) s += WCq[u] * dce[k][u] + Ak[k][u] * dcq[u];
-      D[hidx(q, 9 + k) * ds] = b.Jt * s + Jq[k] * wq;
     }
   }
   // order-parameter gradient terms
