@@ -312,3 +312,26 @@ def test_assembly_slabs_bitwise():
         for y, y0 in zip(o[3], outs[0][3]):
             assert np.array_equal(y, y0)
         assert np.array_equal(o[4], outs[0][4]) and o[5] == outs[0][5]
+
+
+def test_time_step_failure_restores_state():
+    """Newton failure handling, forced from the host through the options (one
+    Newton iteration allowed, unreachable tolerance): every attempt fails, the
+    increment is halved 8 times, the call reports non-convergence and the
+    state and depth are exactly those before the call."""
+    from paper_2011_08802_amd import mvpf
+    p = synth.tiny()
+    U, En = seeded_state(p, 1e-3)
+    gp = gpu_problem(p, U, En, "mixed", newton_max=1, newton_rtol=1e-30)
+    before = gp.get_state()
+    st = gp.time_step(p.depth_increment)
+    after = gp.get_state()
+    assert not st.converged and st.halvings == 9 and st.newton_iterations == 9
+    for a, b in zip(before[:3], after[:3]):
+        assert torch.equal(a, b)
+    assert after[3] == before[3] == 0.0
+    # the problem stays usable: a normal step from the restored state converges
+    gp.set_opts(newton_max=12, newton_rtol=1e-9)
+    st = gp.time_step(p.depth_increment)
+    assert st.converged and st.halvings == 0
+    gp.close()
