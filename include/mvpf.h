@@ -242,8 +242,8 @@ int mvpf_time_step(mvpf_problem* p, double depth, mvpf_step_stats* stats);
  * changes results at rounding level; the others never do.  "coarse_overlap":
  * 1 = the coarsest level's dense inversion runs on a second (default
  * priority) stream, overlapping the assembly of the finer levels; 0 = in
- * order on the problem's stream before them (default: 1 up to 2048 coarse
- * unknowns, else 0; level ignored; results unchanged).
+ * order on the problem's stream before them (default 1; level ignored;
+ * results unchanged).
  * "assembly_slab_elements": elements per assembly slab (0 = the capacity
  * allocated by mvpf_create: the whole finest level if its Gauss-point and
  * element-matrix buffers take at most 96 GiB, else slabs of 40 GiB).  Levels

@@ -769,9 +769,6 @@ int build_system(mvpf_problem* p, double depth) {
     Level& C = p->lev[Lc];
     const int nd = C.ndense;
     double* work = p->coarse_work ? p->coarse_work : p->V;
-    // The overlap pays while the inversion is a few hundred launches; for
-    // large coarsest levels its thousands of small launches starve behind
-    // the assembly kernels, and running it first, alone, is faster.
     const bool overlap = p->coarse_overlap < 0 ? nd <= COARSE_OVERLAP_MAX : p->coarse_overlap != 0;
     hipStream_t cs = overlap ? p->side : s;
     if (overlap) {

@@ -61,7 +61,7 @@ void launch_dense_from_bsr(const Grid& g, const double* A64, double* dense, hipS
 //      sub-panel (rows pivoted earlier are excluded), places the unit
 //      columns and inverts the pivot block Mp = F[P, :] (Gauss-Jordan in
 //      LDS, rows in pivot order); beyond 4 GJ_THREADS rows the same is done
-//      by one launch per column (gj_col) and gj_pivinv;
+//      by tournament pivoting (gj_tourn0, gj_tourn1);
 //   2. gj_rows: R = Mp^-1 M[P, active] (the new pivot rows);
 //   3. gj_update: rows in P become R, every other row i becomes
 //      M[i, active] - F[i, :] R,
@@ -110,10 +110,86 @@ __device__ void pivot_block_inverse(int B, const double* __restrict__ F, const i
   for (int idx = tid; idx < B * B; idx += blockDim.x) Pinv[idx] = Mp[idx / B][B + idx % B];
 }
 
-// Sub-panel factorisation (columns c0 .. c0 + B - 1).  Thread t owns rows t,
-// t + GJ_THREADS, ... (RPT of them) and keeps their sub-panel entries (PB >= B
-// columns) in registers; the pivot row is broadcast through LDS.
-// n <= GJ_THREADS * RPT.
+// Elimination with partial pivoting over the rows a workgroup holds in its
+// registers: W[q][.] is the sub-panel window of row rid[q] (act[q]: still a
+// candidate).  After each step the windows shift left by one, so the active
+// column is always W[q][0] (all register indices static).  One barrier per
+// column: every wavefront's best row publishes its value, index and window
+// in LDS slots (double-buffered by column parity), and every thread picks the
+// block's winner from the slots itself; ties go to the lowest row.
+// on_pivot(jj, p) runs in the thread that holds the chosen row p.
+// strict: a column without a non-zero candidate makes the block singular
+// (returns -1); otherwise such a column takes its lowest candidate row without
+// elimination, and the loop ends early (returns the count) when no candidate
+// rows are left.
+constexpr int NWV = GJ_THREADS / 64;
+template <int RPT, int PB, typename OnPivot>
+__device__ int window_eliminate(double (&W)[RPT][PB], bool (&act)[RPT], const int (&rid)[RPT], int B, bool strict,
+                                OnPivot on_pivot, double (*cv)[NWV], int (*ci)[NWV], double (*crow)[NWV][PB]) {
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+#pragma unroll 1
+  for (int jj = 0; jj < B; ++jj) {
+    double v = -1.0;
+    int idx = -1;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const double cand = fabs(W[q][0]);
+      if (act[q] && (cand > v || (cand == v && rid[q] < idx))) { v = cand; idx = rid[q]; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off, 64);
+      const int oi = __shfl_xor(idx, off, 64);
+      if (oi >= 0 && (idx < 0 || ov > v || (ov == v && oi < idx))) { v = ov; idx = oi; }
+    }
+    const int par = jj & 1;
+    bool mine = false;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) mine = mine || (act[q] && rid[q] == idx);
+    if (idx >= 0 && mine) {
+      cv[par][wid] = v;
+      ci[par][wid] = idx;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q)
+        if (act[q] && rid[q] == idx) {
+#pragma unroll
+          for (int b = 0; b < PB; ++b) crow[par][wid][b] = W[q][b];
+        }
+    } else if (idx < 0 && lane == 0) {
+      cv[par][wid] = -1.0;
+      ci[par][wid] = -1;
+    }
+    __syncthreads();
+    double bv = -1.0;
+    int p = -1, pw = 0;
+#pragma unroll
+    for (int k = 0; k < NWV; ++k) {
+      const double ov = cv[par][k];
+      const int oi = ci[par][k];
+      if (oi >= 0 && (p < 0 || ov > bv || (ov == bv && oi < p))) { bv = ov; p = oi; pw = k; }
+    }
+    if (p < 0) return strict ? -1 : jj;  // uniform: no candidate rows left
+    if (strict && !(bv > 0.0)) return -1;  // uniform: singular
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+      if (act[q] && rid[q] == p) {
+        act[q] = false;
+        on_pivot(jj, p);
+      }
+    const double* prw = crow[par][pw];
+    const double ip = bv > 0.0 ? 1.0 / prw[0] : 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const double f = act[q] ? W[q][0] * ip : 0.0;
+#pragma unroll
+      for (int b = 1; b < PB; ++b) W[q][b - 1] = W[q][b] - f * prw[b];
+      W[q][PB - 1] = 0.0;
+    }
+  }
+  return B;
+}
+
+// Sub-panel factorisation (columns c0 .. c0 + B - 1) in one workgroup.
+// Thread t owns rows t, t + GJ_THREADS, ... (RPT of them); n <= GJ_THREADS * RPT.
 template <int RPT, int PB>
 __global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int B, double* __restrict__ M,
                                                               const double* __restrict__ F,
@@ -124,10 +200,14 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int
   __shared__ double fr[PB];
   __shared__ double rowc[2 * PB];
   __shared__ int pr[PB];
+  __shared__ double cv[2][NWV];
+  __shared__ int ci[2][NWV];
+  __shared__ double crow[2][NWV][PB];
   const int tid = threadIdx.x;
   const int64_t w = 2 * (int64_t)n;
   double W[RPT][PB];
   bool act[RPT];
+  int rid[RPT];
   // The sub-panel comes column-major from gj_fetch (Wc[b][i], F = its
   // row-major copy), so the loads of a wavefront are 64 consecutive rows.
   // Addresses are clamped and loaded unconditionally (all in flight at
@@ -139,82 +219,20 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int
     const int i = tid + q * GJ_THREADS;
     const bool ok = i < n;
     const int ic = ok ? i : 0;
+    rid[q] = i;
     act[q] = !done[ic] && ok;
 #pragma unroll
     for (int b = 0; b < PB; ++b) W[q][b] = Wc[(int64_t)(b < B ? b : B - 1) * n + ic];
   }
-  // Register window: after each step the rows' entries shift left by one, so
-  // the active column is always W[q][0] (all register indices static).
-  // One barrier per column: every wavefront's best row publishes its value,
-  // index and window in LDS slots (double-buffered by column parity), and
-  // every thread then picks the block's winner from the NW slots itself.
-  constexpr int NW = GJ_THREADS / 64;
-  __shared__ double cv[2][NW];
-  __shared__ int ci[2][NW];
-  __shared__ double crow[2][NW][PB];
-  const int wid = tid >> 6, lane = tid & 63;
-#pragma unroll 1
-  for (int jj = 0; jj < B; ++jj) {
-    double v = -1.0;
-    int idx = -1;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const double cand = fabs(W[q][0]);
-      if (act[q] && cand > v) { v = cand; idx = tid + q * GJ_THREADS; }
-    }
-    // wavefront argmax, ties to the lowest row; every lane ends with it
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(v, off, 64);
-      const int oi = __shfl_xor(idx, off, 64);
-      if (oi >= 0 && (idx < 0 || ov > v || (ov == v && oi < idx))) { v = ov; idx = oi; }
-    }
-    const int par = jj & 1;
-    if (idx >= 0 && idx % GJ_THREADS == tid) {
-      const int q = idx / GJ_THREADS;
-      cv[par][wid] = v;
-      ci[par][wid] = idx;
-#pragma unroll
-      for (int qq = 0; qq < RPT; ++qq)
-        if (qq == q) {
-#pragma unroll
-          for (int b = 0; b < PB; ++b) crow[par][wid][b] = W[qq][b];
-        }
-    } else if (idx < 0 && lane == 0) {
-      cv[par][wid] = -1.0;
-      ci[par][wid] = -1;
-    }
-    __syncthreads();
-    double bv = -1.0;
-    int p = -1, pw = 0;
-#pragma unroll
-    for (int k = 0; k < NW; ++k) {
-      const double ov = cv[par][k];
-      const int oi = ci[par][k];
-      if (oi >= 0 && (p < 0 || ov > bv || (ov == bv && oi < p))) { bv = ov; p = oi; pw = k; }
-    }
-    if (!(bv > 0.0) || p < 0) {
-      if (tid == 0) atomicOr(status, 1);
-      return;  // uniform
-    }
-    if (p % GJ_THREADS == tid) {
-      const int q = p / GJ_THREADS;
-#pragma unroll
-      for (int qq = 0; qq < RPT; ++qq)
-        if (qq == q) act[qq] = false;
-      done[p] = 1;
-      prow[c0 + jj] = p;
-      pr[jj] = p;
-      M[(int64_t)p * w + n + c0 + jj] = 1.0;  // unit column of the new pivot
-    }
-    const double* prw = crow[par][pw];
-    const double ip = 1.0 / prw[0];
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const double f = act[q] ? W[q][0] * ip : 0.0;
-#pragma unroll
-      for (int b = 1; b < PB; ++b) W[q][b - 1] = W[q][b] - f * prw[b];
-      W[q][PB - 1] = 0.0;
-    }
+  const int got = window_eliminate<RPT, PB>(W, act, rid, B, true, [&](int jj, int p) {
+    done[p] = 1;
+    prow[c0 + jj] = p;
+    pr[jj] = p;
+    M[(int64_t)p * w + n + c0 + jj] = 1.0;  // unit column of the new pivot
+  }, cv, ci, crow);
+  if (got < 0) {
+    if (tid == 0) atomicOr(status, 1);
+    return;  // uniform
   }
   __syncthreads();  // pr[] complete
   pivot_block_inverse<PB>(B, F, pr, Pinv, status, Mp, fr, rowc);
@@ -292,24 +310,18 @@ __global__ void __launch_bounds__(256) gj_update_kernel(int n, int c0, int nbw, 
   }
 }
 
-// ---- wide sub-panels (n > 4 GJ_THREADS): one launch per column ----------
-// The sub-panel (n x B, B = GJB) does not fit in one workgroup's registers,
-// so it lives column-major in Wc (L2-resident) and every column is one
-// launch over all rows.  Pivot keys pack |v| (bits of a non-negative double
-// are ordered like its value) with the low KEY_BITS bits replaced by
-// (2^KEY_BITS - 1 - row): a 64-bit atomicMax selects the largest magnitude
-// (compared to 39 mantissa bits) and, among equal keys, the lowest row.
-constexpr int KEY_BITS = 13;  // n <= 8192
-__device__ __forceinline__ unsigned long long pivot_key(double a, int i) {
-  const unsigned long long mask = (1ull << KEY_BITS) - 1;
-  return ((unsigned long long)__double_as_longlong(a) & ~mask) | (unsigned long long)(mask - i);
-}
-__device__ __forceinline__ int key_row(unsigned long long k, int n) {
-  const unsigned long long mask = (1ull << KEY_BITS) - 1;
-  if (k <= mask) return -1;  // no candidate with a non-zero magnitude
-  const int i = (int)(mask - (k & mask));
-  return i < n ? i : -1;
-}
+// ---- wide sub-panels (n > 4 GJ_THREADS): tournament pivoting -------------
+// Beyond 4 rows per thread a sub-panel (B = GJB columns) no longer fits one
+// workgroup's registers.  Its pivot rows are chosen by tournament pivoting
+// (communication-avoiding LU, Grigori, Demmel and Xiang 2011) in two rounds:
+//   gj_tourn0: each block of GJ_THREADS rows eliminates the sub-panel over its
+//              own candidate rows and nominates the rows it pivoted on;
+//   gj_tourn1: one workgroup eliminates the original sub-panel rows of all
+//              nominees (at most 16 x GJB <= GJ_THREADS of them) and takes its
+//              pivots as the sub-panel's, then inverts the pivot block.
+// The pivots differ from column-by-column partial pivoting over all rows
+// (each is the largest among the nominees); the inverse is the same up to
+// rounding.  Two launches per sub-panel instead of one per column.
 
 // F[i][b] = Wc[b][i] = M[i][s0 + b]
 __global__ void __launch_bounds__(256) gj_fetch_kernel(int n, int s0, int B, const double* __restrict__ M,
@@ -323,76 +335,56 @@ __global__ void __launch_bounds__(256) gj_fetch_kernel(int n, int s0, int B, con
   Wc[(int64_t)b * n + i] = v;
 }
 
-// Column jj of the sub-panel at s0 (jj = 0 .. B; jj == B only finalises):
-//  1. the pivot p of column jj - 1 (from its key) is recorded and gets its
-//     unit column; every other active row eliminates column jj - 1 from its
-//     remaining sub-panel entries;
-//  2. the active rows' keys for column jj go to keys[s0 + jj] (wave max, then
-//     one atomicMax per wave).
-__global__ void __launch_bounds__(256) gj_col_kernel(int n, int s0, int B, int jj, double* __restrict__ Wc,
-                                                     unsigned long long* __restrict__ keys, int* __restrict__ done,
-                                                     int* __restrict__ prow, double* __restrict__ M, int* status) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t w = 2 * (int64_t)n;
-  int p = -1;
-  if (jj > 0) {
-    p = key_row(keys[s0 + jj - 1], n);
-    if (p < 0) {  // no non-zero pivot: singular (uniform over the grid)
-      if (i == 0) atomicOr(status, 1);
-      return;
-    }
-  }
-  const bool act = i < n && !done[i] && i != p;
-  if (jj > 0 && i == p) {
-    done[p] = 1;
-    prow[s0 + jj - 1] = p;
-    M[(int64_t)p * w + n + s0 + jj - 1] = 1.0;
-  }
-  unsigned long long key = 0;
-  if (act) {
-    double* wi = Wc + i;
-    double a = 0.0;
-    if (jj > 0) {
-      // all loads first (own row and pivot row), then the stores
-      const double* wp = Wc + p;
-      const double f = wi[(int64_t)(jj - 1) * n] / wp[(int64_t)(jj - 1) * n];
-      double own[GJB], piv[GJB];
+__global__ void __launch_bounds__(GJ_THREADS) gj_tourn0_kernel(int n, int B, const double* __restrict__ Wc,
+                                                               const int* __restrict__ done, int* __restrict__ cand) {
+  __shared__ double cv[2][NWV];
+  __shared__ int ci[2][NWV];
+  __shared__ double crow[2][NWV][GJB];
+  const int i = blockIdx.x * GJ_THREADS + threadIdx.x;
+  const bool ok = i < n;
+  const int ic = ok ? i : 0;
+  double W[1][GJB];
+  bool act[1] = {!done[ic] && ok};
+  const int rid[1] = {i};
 #pragma unroll
-      for (int b = 0; b < GJB; ++b)
-        if (b >= jj && b < B) {
-          own[b] = wi[(int64_t)b * n];
-          piv[b] = wp[(int64_t)b * n];
-        }
-#pragma unroll
-      for (int b = 0; b < GJB; ++b)
-        if (b >= jj && b < B) {
-          const double v = own[b] - f * piv[b];
-          wi[(int64_t)b * n] = v;
-          if (b == jj) a = fabs(v);
-        }
-    } else if (B > 0) {
-      a = fabs(wi[0]);
-    }
-    if (jj < B && a > 0.0) key = pivot_key(a, i);
-  }
-  if (jj < B) {
-    for (int off = 32; off > 0; off >>= 1) {
-      const unsigned long long o = __shfl_xor(key, off, 64);
-      key = o > key ? o : key;
-    }
-    if ((threadIdx.x & 63) == 0 && key) atomicMax(&keys[s0 + jj], key);
-  }
+  for (int b = 0; b < GJB; ++b) W[0][b] = Wc[(int64_t)(b < B ? b : B - 1) * n + ic];
+  int* mine = cand + blockIdx.x * GJB;
+  const int got = window_eliminate<1, GJB>(W, act, rid, B, false, [&](int jj, int p) { mine[jj] = p; }, cv, ci,
+                                           crow);
+  for (int jj = got + (int)threadIdx.x; jj < GJB; jj += blockDim.x) mine[jj] = -1;
 }
 
-// Pinv = inverse of the pivot block of the sub-panel at s0
-__global__ void __launch_bounds__(256) gj_pivinv_kernel(int s0, int B, const double* __restrict__ F,
-                                                        const int* __restrict__ prow, double* __restrict__ Pinv,
-                                                        int* status) {
+__global__ void __launch_bounds__(GJ_THREADS) gj_tourn1_kernel(int n, int s0, int B, int nblk, double* __restrict__ M,
+                                                               const double* __restrict__ F,
+                                                               const int* __restrict__ cand, int* __restrict__ done,
+                                                               int* __restrict__ prow, double* __restrict__ Pinv,
+                                                               int* status) {
   __shared__ double Mp[GJB][2 * GJB];
   __shared__ double fr[GJB];
   __shared__ double rowc[2 * GJB];
   __shared__ int pr[GJB];
-  if (threadIdx.x < B) pr[threadIdx.x] = prow[s0 + threadIdx.x];
+  __shared__ double cv[2][NWV];
+  __shared__ int ci[2][NWV];
+  __shared__ double crow[2][NWV][GJB];
+  const int tid = threadIdx.x;
+  const int64_t w = 2 * (int64_t)n;
+  const int r = tid < nblk * GJB ? cand[tid] : -1;
+  const int rc = r >= 0 ? r : 0;
+  double W[1][GJB];
+  bool act[1] = {r >= 0};
+  const int rid[1] = {r >= 0 ? r : n + tid};  // distinct ids for empty slots (never active)
+#pragma unroll
+  for (int b = 0; b < GJB; ++b) W[0][b] = F[(int64_t)rc * B + (b < B ? b : B - 1)];
+  const int got = window_eliminate<1, GJB>(W, act, rid, B, true, [&](int jj, int p) {
+    done[p] = 1;
+    prow[s0 + jj] = p;
+    pr[jj] = p;
+    M[(int64_t)p * w + n + s0 + jj] = 1.0;
+  }, cv, ci, crow);
+  if (got < 0) {
+    if (tid == 0) atomicOr(status, 1);
+    return;  // uniform
+  }
   __syncthreads();
   pivot_block_inverse<GJB>(B, F, pr, Pinv, status, Mp, fr, rowc);
 }
@@ -471,7 +463,7 @@ __global__ void __launch_bounds__(256) gj_gemm_kernel(int n, int c0, int nbw, co
 
 __global__ void __launch_bounds__(256) gj_init_kernel(int n, const double* __restrict__ a, double* __restrict__ M,
                                                       int* __restrict__ done, int* __restrict__ prow,
-                                                      unsigned long long* __restrict__ keys) {
+                                                      int* __restrict__ cand) {
   const int64_t w = 2 * (int64_t)n;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)n * w;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -480,7 +472,7 @@ __global__ void __launch_bounds__(256) gj_init_kernel(int n, const double* __res
     if (c == 0) {
       done[i] = 0;
       prow[i] = 0;  // any valid row until the pivot is chosen
-      keys[i] = 0;
+      if (i < 16 * GJB) cand[i] = -1;
     }
   }
 }
@@ -498,14 +490,15 @@ __global__ void __launch_bounds__(256) gj_extract_kernel(int n, const double* __
 
 size_t dense_invert_work(int n) {
   // doubles: M (2n^2), F and Wc (n*GJB each), R (GJB*2*GJ_NB), Pinv (GJB^2), Yo and Rb (n*GJ_NB each);
-  // then n 64-bit keys and 2n ints
+  // then 16*GJB tournament candidates and 2n ints
   return (size_t)(2 * (int64_t)n * n + 2 * (int64_t)n * GJB + 2 * (int64_t)GJB * GJ_NB + GJB * GJB +
                   2 * (int64_t)n * GJ_NB) * sizeof(double) +
-         (size_t)n * sizeof(unsigned long long) + (size_t)2 * n * sizeof(int);
+         (size_t)(16 * GJB + 2 * n) * sizeof(int);
 }
 
 // a: n x n input (not modified); inv: n x n output; work: dense_invert_work(n) bytes.
 int dense_invert(int n, double* a, double* inv, double* work, int* status, hipStream_t s) {
+  if (n > 16 * GJ_THREADS) return -1;  // at most 16 tournament blocks
   double* M = work;
   double* F = M + 2 * (int64_t)n * n;
   double* Wc = F + (int64_t)n * GJB;
@@ -513,14 +506,14 @@ int dense_invert(int n, double* a, double* inv, double* work, int* status, hipSt
   double* Pinv = R + 2 * (int64_t)GJB * GJ_NB;
   double* Yo = Pinv + GJB * GJB;
   double* Rb = Yo + (int64_t)n * GJ_NB;
-  unsigned long long* keys = (unsigned long long*)(Rb + (int64_t)GJ_NB * n);
-  int* done = (int*)(keys + n);
+  int* cand = (int*)(Rb + (int64_t)GJ_NB * n);
+  int* done = cand + 16 * GJB;
   int* prow = done + n;
-  if (n > (1 << KEY_BITS)) return -1;
-  gj_init_kernel<<<1024, 256, 0, s>>>(n, a, M, done, prow, keys);
+  gj_init_kernel<<<1024, 256, 0, s>>>(n, a, M, done, prow, cand);
   // sub-panel width: up to 4 rows per thread the sub-panel is factored in one
-  // workgroup's registers, beyond that one launch per column
+  // workgroup's registers, beyond that by tournament pivoting
   const bool wide = n > 4 * GJ_THREADS;
+  const int nblk = (n + GJ_THREADS - 1) / GJ_THREADS;
   const int PBW = (wide || n <= 2 * GJ_THREADS) ? GJB : 16;
   for (int c0 = 0; c0 < n; c0 += GJ_NB) {
     const int nbw = std::min(GJ_NB, n - c0);
@@ -528,9 +521,8 @@ int dense_invert(int n, double* a, double* inv, double* work, int* status, hipSt
       const int B = std::min(PBW, c0 + nbw - s0);
       gj_fetch_kernel<<<(int)(((int64_t)n * B + 255) / 256), 256, 0, s>>>(n, s0, B, M, F, Wc);
       if (wide) {
-        for (int jj = 0; jj <= B; ++jj)
-          gj_col_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, s0, B, jj, Wc, keys, done, prow, M, status);
-        gj_pivinv_kernel<<<1, 256, 0, s>>>(s0, B, F, prow, Pinv, status);
+        gj_tourn0_kernel<<<nblk, GJ_THREADS, 0, s>>>(n, B, Wc, done, cand);
+        gj_tourn1_kernel<<<1, GJ_THREADS, 0, s>>>(n, s0, B, nblk, M, F, cand, done, prow, Pinv, status);
       } else if (n <= GJ_THREADS) {
         gj_panel_kernel<1, 32><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, Wc, done, prow, Pinv, status);
       } else if (n <= 2 * GJ_THREADS) {

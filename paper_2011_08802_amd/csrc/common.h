@@ -121,8 +121,9 @@ struct KernelTimer {
 
 namespace mvpf {
 // coarsest levels up to this many unknowns are inverted on a side stream,
-// overlapping the assembly of the finer levels
-constexpr int COARSE_OVERLAP_MAX = 2048;
+// overlapping the assembly of the finer levels (all sizes: measured faster
+// than in order at 1 125 and 6 561 unknowns)
+constexpr int COARSE_OVERLAP_MAX = MVPF_MAX_COARSE_DOF;
 // most blocks of a two-stage reduction (partials per reduced value)
 constexpr int MAX_RED_BLOCKS = 4096;
 // assembly buffers: the whole finest level up to this size, else slabs
