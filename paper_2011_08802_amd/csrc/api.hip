@@ -752,7 +752,10 @@ int* setup_status(mvpf_problem* p) { return (int*)p->red; }  // first word of th
 // The coarsest operator is assembled first; its dense gather and inversion
 // then run on the side stream while the main stream assembles the finer
 // levels.  setup_solver joins the two streams.
-int build_system(mvpf_problem* p, double depth) {
+// coarse_inline = false (batches): the coarsest operator is gathered into its
+// dense matrix on the problem's stream, ev_fork marks it ready, and the
+// batch inverts all problems' matrices at once and records ev_join.
+int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
   hipStream_t s = p->stream;
   Level& L0 = p->lev[0];
   const int Lc = p->L - 1;
@@ -769,18 +772,25 @@ int build_system(mvpf_problem* p, double depth) {
     Level& C = p->lev[Lc];
     const int nd = C.ndense;
     double* work = p->coarse_work ? p->coarse_work : p->V;
+    if (!coarse_inline) {
+      launch_dense_from_bsr(C.g, C.A64, work, s);
+      HIPCHK(hipEventRecord(p->ev_fork, s));
+      p->coarse_pending = true;
+    }
     const bool overlap = p->coarse_overlap < 0 ? nd <= COARSE_OVERLAP_MAX : p->coarse_overlap != 0;
     hipStream_t cs = overlap ? p->side : s;
-    if (overlap) {
+    if (coarse_inline && overlap) {
       HIPCHK(hipEventRecord(p->ev_fork, s));
       HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
     }
-    launch_dense_from_bsr(C.g, C.A64, work, cs);
-    if (dense_invert(nd, work, C.Ainv, work + (int64_t)nd * nd, setup_status(p), cs) != 0) {
-      p->err = "coarse inversion launch failed";
-      return MVPF_EDEVICE;
+    if (coarse_inline) {
+      launch_dense_from_bsr(C.g, C.A64, work, cs);
+      if (dense_invert(nd, work, C.Ainv, work + (int64_t)nd * nd, setup_status(p), cs) != 0) {
+        p->err = "coarse inversion launch failed";
+        return MVPF_EDEVICE;
+      }
     }
-    if (overlap) {
+    if (coarse_inline && overlap) {
       HIPCHK(hipEventRecord(p->ev_join, p->side));
       p->coarse_pending = true;
     }
@@ -952,6 +962,10 @@ struct mvpf_batch {
   // the legacy default stream), ordered after and before the caller's stream
   hipStream_t work = nullptr;
   hipEvent_t enter = nullptr, leave = nullptr;
+  // the coarsest-level inversions of all problems as one batched inversion
+  mvpf::GJJob* gj_tab = nullptr;
+  int* gj_sel = nullptr;
+  std::vector<int> gj_n;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<int> graph_version;  // config_version of each problem at capture
@@ -1085,6 +1099,10 @@ void batch_free(mvpf_batch* b) {
   if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->enter) (void)hipEventDestroy(b->enter);
   if (b->leave) (void)hipEventDestroy(b->leave);
+  if (b->gj_tab) (void)hipFree(b->gj_tab);
+  if (b->gj_sel) (void)hipFree(b->gj_sel);
+  b->gj_tab = nullptr;
+  b->gj_sel = nullptr;
   if (b->work) {
     (void)hipStreamSynchronize(b->work);
     (void)hipStreamDestroy(b->work);
@@ -1517,6 +1535,27 @@ int mvpf_create_batch(int n, const mvpf_mesh* meshes, const mvpf_material* mats,
     g_create_err = "batch stream/event creation failed";
     rc = MVPF_EDEVICE;
   }
+  if (rc == 0) {
+    // job table of the batched coarse inversion (workspaces fixed per problem)
+    std::vector<GJJob> tab(n);
+    b->gj_n.resize(n);
+    for (int i = 0; i < n; ++i) {
+      mvpf_problem* p = b->probs[i];
+      Level& C = p->lev[p->L - 1];
+      const int nd = C.ndense;
+      double* work = p->coarse_work ? p->coarse_work : p->V;
+      tab[i] = gj_make_job(nd, work, C.Ainv, work + (int64_t)nd * nd, setup_status(p));
+      b->gj_n[i] = nd;
+    }
+    const std::vector<int> sel = dense_invert_batch_selection(b->gj_n);
+    if (hipMalloc((void**)&b->gj_tab, sizeof(GJJob) * n) != hipSuccess ||
+        hipMalloc((void**)&b->gj_sel, sizeof(int) * n) != hipSuccess ||
+        hipMemcpy(b->gj_tab, tab.data(), sizeof(GJJob) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->gj_sel, sel.data(), sizeof(int) * n, hipMemcpyHostToDevice) != hipSuccess) {
+      g_create_err = "batch job tables failed";
+      rc = MVPF_ENOMEM;
+    }
+  }
   if (rc) {
     batch_free(b);
     delete b;
@@ -1548,14 +1587,39 @@ mvpf_problem* mvpf_batch_problem(mvpf_batch* b, int i) {
 int mvpf_batch_newton_system(mvpf_batch* b, const double* depths) {
   if (!b || !depths) return MVPF_EINVAL;
   BCHK(hipEventRecord(b->enter, b->stream));
+  // largest coarsest levels first: their latency-bound inversions are the
+  // longest chains and start while the other problems assemble
+  std::vector<int> order(b->n);
+  for (int i = 0; i < b->n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return b->probs[x]->lev[b->probs[x]->L - 1].ndense > b->probs[y]->lev[b->probs[y]->L - 1].ndense;
+  });
   int rc = 0, bad = -1;
-  for (int i = 0; i < b->n && rc == 0; ++i) {
+  for (int oi = 0; oi < b->n && rc == 0; ++oi) {
+    const int i = order[oi];
     mvpf_problem* p = b->probs[i];
     p->have_system = p->have_solution = false;
     BCHK(hipStreamWaitEvent(b->branch[i], b->enter, 0));
     p->stream = b->branch[i];
-    rc = build_system(p, depths[i]);
-    if (rc == 0) rc = setup_enqueue(p);
+    rc = build_system(p, depths[i], false);
+    p->stream = b->stream;
+    if (rc) bad = i;
+  }
+  // all coarsest-level inversions at once, on the batch's work stream, after
+  // every problem's dense coarse matrix is ready; each problem's setup waits
+  if (rc == 0) {
+    for (int i = 0; i < b->n; ++i) BCHK(hipStreamWaitEvent(b->work, b->probs[i]->ev_fork, 0));
+    if (dense_invert_batch(b->gj_tab, b->gj_sel, b->gj_n, b->work) != 0) {
+      b->err = "batched coarse inversion launch failed";
+      rc = MVPF_EDEVICE;
+    }
+    for (int i = 0; i < b->n && rc == 0; ++i) BCHK(hipEventRecord(b->probs[i]->ev_join, b->work));
+  }
+  for (int oi = 0; oi < b->n && rc == 0; ++oi) {
+    const int i = order[oi];
+    mvpf_problem* p = b->probs[i];
+    p->stream = b->branch[i];
+    rc = setup_enqueue(p);
     p->stream = b->stream;
     if (rc) bad = i;
   }

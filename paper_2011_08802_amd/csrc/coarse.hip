@@ -10,25 +10,26 @@
 
 namespace mvpf {
 
+// one thread per (node, stored block, block row): the 9 entries of that row
+// and, for off-diagonal blocks, their transposes (the lower half)
 __global__ void __launch_bounds__(256) dense_from_bsr_kernel(Grid g, const double* __restrict__ A,
                                                              double* __restrict__ D) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= g.N) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.N * NUP * 9) return;
+  const int r = idx % 9, u = (idx / 9) % NUP, n = idx / (9 * NUP);
   const int64_t nd = (int64_t)NDOF * g.N;
   const int t = n >> 6, l = n & 63;
   const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
-  for (int u = 0; u < NUP; ++u) {
-    const int s = 13 + u;
-    const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
-    if (i + dx < 0 || i + dx >= g.nnx || j + dy < 0 || j + dy >= g.nny || k + dz < 0 || k + dz >= g.nnz) continue;
-    const int m = n + dx + g.nnx * (dy + g.nny * dz);
-    const double* Ab = A + (int64_t)(t * NUP + u) * Lay<double>::SLICE;
-    for (int r = 0; r < 9; ++r)
-      for (int c = 0; c < 9; ++c) {
-        const double v = Ab[Lay<double>::off(r * 9 + c, l)];
-        D[((int64_t)r * g.N + n) * nd + (int64_t)c * g.N + m] = v;
-        if (u > 0) D[((int64_t)c * g.N + m) * nd + (int64_t)r * g.N + n] = v;  // lower half by symmetry
-      }
+  const int s = 13 + u;
+  const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+  if (i + dx < 0 || i + dx >= g.nnx || j + dy < 0 || j + dy >= g.nny || k + dz < 0 || k + dz >= g.nnz) return;
+  const int m = n + dx + g.nnx * (dy + g.nny * dz);
+  const double* Ab = A + (int64_t)(t * NUP + u) * Lay<double>::SLICE;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    const double v = Ab[Lay<double>::off(r * 9 + c, l)];
+    D[((int64_t)r * g.N + n) * nd + (int64_t)c * g.N + m] = v;
+    if (u > 0) D[((int64_t)c * g.N + m) * nd + (int64_t)r * g.N + n] = v;  // lower half by symmetry
   }
 }
 
@@ -40,7 +41,7 @@ __global__ void zero_kernel_d(int64_t n, double* p) {
 void launch_dense_from_bsr(const Grid& g, const double* A64, double* dense, hipStream_t s) {
   const int64_t nd = (int64_t)NDOF * g.N;
   zero_kernel_d<<<1024, 256, 0, s>>>(nd * nd, dense);
-  dense_from_bsr_kernel<<<(g.N + 255) / 256, 256, 0, s>>>(g, A64, dense);
+  dense_from_bsr_kernel<<<(g.N * NUP * 9 + 255) / 256, 256, 0, s>>>(g, A64, dense);
 }
 
 // Two-level blocked Gauss-Jordan inversion with partial pivoting.
@@ -76,6 +77,32 @@ void launch_dense_from_bsr(const Grid& g, const double* A64, double* dense, hipS
 constexpr int GJB = 32;   // widest sub-panel
 constexpr int GJ_NB = 128;  // outer panel width
 constexpr int GJ_THREADS = 512;
+
+// Several inversions can run as one: every kernel below takes a job table
+// (workgroup z of a launch works on job sel[z], or z without a selection
+// list) or, for a single inversion, the job by value.  Each job keeps its
+// own sub-panel width and kernel variant, so a job computes the same
+// numbers alone or in a batch.
+struct GJJobs {
+  const GJJob* tab;  // device table, or nullptr: use the job passed by value
+  const int* sel;    // device selection list (job indices), or nullptr
+};
+__device__ __forceinline__ const GJJob& gj_job(const GJJobs& J, const GJJob& one) {
+  if (!J.tab) return one;
+  return J.tab[J.sel ? J.sel[blockIdx.z] : blockIdx.z];
+}
+// sub-panel width: up to 4 rows per thread the sub-panel is factored in one
+// workgroup's registers, beyond that by tournament pivoting
+__host__ __device__ inline int gj_pbw(int n) { return (n > 4 * GJ_THREADS || n <= 2 * GJ_THREADS) ? GJB : 16; }
+// the job's sub-panel at (c0, s0), if it has one: outer-panel width nbw, width B
+__device__ __forceinline__ bool gj_step(int n, int c0, int s0, int& nbw, int& B) {
+  if (c0 >= n) return false;
+  nbw = min(GJ_NB, n - c0);
+  const int pb = gj_pbw(n);
+  if (s0 >= c0 + nbw || (s0 - c0) % pb) return false;
+  B = min(pb, c0 + nbw - s0);
+  return true;
+}
 
 // Inverse of the pivot block Mp = F[pr[a], b] (B x B, B <= PB), rows in
 // pivot order, by Gauss-Jordan on [Mp | I] in LDS.  No pivot search: each
@@ -191,11 +218,18 @@ __device__ int window_eliminate(double (&W)[RPT][PB], bool (&act)[RPT], const in
 // Sub-panel factorisation (columns c0 .. c0 + B - 1) in one workgroup.
 // Thread t owns rows t, t + GJ_THREADS, ... (RPT of them); n <= GJ_THREADS * RPT.
 template <int RPT, int PB>
-__global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(int n, int c0, int B, double* __restrict__ M,
-                                                              const double* __restrict__ F,
-                                                              const double* __restrict__ Wc, int* __restrict__ done,
-                                                              int* __restrict__ prow, double* __restrict__ Pinv,
-                                                              int* status) {
+__global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(GJJobs J, GJJob one, int oc0, int c0) {
+  const GJJob& jb = gj_job(J, one);
+  const int n = jb.n;
+  int nbw_, B;
+  if (!gj_step(n, oc0, c0, nbw_, B)) return;  // uniform
+  double* __restrict__ M = jb.M;
+  const double* __restrict__ F = jb.F;
+  const double* __restrict__ Wc = jb.Wc;
+  int* __restrict__ done = jb.done;
+  int* __restrict__ prow = jb.prow;
+  double* __restrict__ Pinv = jb.Pinv;
+  int* status = jb.status;
   __shared__ double Mp[PB][2 * PB];
   __shared__ double fr[PB];
   __shared__ double rowc[2 * PB];
@@ -244,13 +278,19 @@ __device__ __forceinline__ int64_t gj_col(int n, int c0, int nbw, int j) {
 }
 
 // R[a][j] = sum_b Pinv[a][b] M[prow[s0 + b]][col(j)] over the active columns
-__global__ void __launch_bounds__(256) gj_rows_kernel(int n, int c0, int nbw, int s0, int B,
-                                                      const double* __restrict__ M, const int* __restrict__ prow,
-                                                      const double* __restrict__ Pinv, double* __restrict__ R) {
+__global__ void __launch_bounds__(256) gj_rows_kernel(GJJobs J, GJJob one, int c0, int s0) {
+  const GJJob& jb = gj_job(J, one);
+  const int n = jb.n;
+  int nbw, B;
+  if (!gj_step(n, c0, s0, nbw, B)) return;
+  const double* __restrict__ M = jb.M;
+  const int* __restrict__ prow = jb.prow;
+  const double* __restrict__ Pinv = jb.Pinv;
+  double* __restrict__ R = jb.R;
   const int64_t w = 2 * (int64_t)n;
   const int a = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= 2 * nbw) return;
+  if (a >= B || j >= 2 * nbw) return;
   const int64_t c = gj_col(n, c0, nbw, j);
   double mv[GJB];
 #pragma unroll
@@ -265,13 +305,20 @@ __global__ void __launch_bounds__(256) gj_rows_kernel(int n, int c0, int nbw, in
 // Over the active columns: rows pivoted in this sub-panel become R, every
 // other row i becomes M[i] - F[i, :] R.  Block: UPR rows x 256 columns.
 constexpr int UPR = 8;
-__global__ void __launch_bounds__(256) gj_update_kernel(int n, int c0, int nbw, int s0, int B,
-                                                        double* __restrict__ M, const double* __restrict__ F,
-                                                        const double* __restrict__ R, const int* __restrict__ prow) {
+__global__ void __launch_bounds__(256) gj_update_kernel(GJJobs J, GJJob one, int c0, int s0) {
   __shared__ double Fs[UPR][GJB];
   __shared__ int sub[UPR];  // sub-panel position of each row, or -1
-  const int64_t w = 2 * (int64_t)n;
+  const GJJob& jb = gj_job(J, one);
+  const int n = jb.n;
+  int nbw, B;
+  if (!gj_step(n, c0, s0, nbw, B)) return;  // uniform
   const int r0 = blockIdx.y * UPR;
+  if (r0 >= n || blockIdx.x * 256 >= 2 * nbw) return;  // uniform, before the barriers
+  double* __restrict__ M = jb.M;
+  const double* __restrict__ F = jb.F;
+  const double* __restrict__ R = jb.R;
+  const int* __restrict__ prow = jb.prow;
+  const int64_t w = 2 * (int64_t)n;
   const int j = blockIdx.x * 256 + threadIdx.x;
   for (int idx = threadIdx.x; idx < UPR * GJB; idx += 256) {
     const int rr = idx / GJB, b = idx % GJB;
@@ -324,8 +371,14 @@ __global__ void __launch_bounds__(256) gj_update_kernel(int n, int c0, int nbw, 
 // rounding.  Two launches per sub-panel instead of one per column.
 
 // F[i][b] = Wc[b][i] = M[i][s0 + b]
-__global__ void __launch_bounds__(256) gj_fetch_kernel(int n, int s0, int B, const double* __restrict__ M,
-                                                       double* __restrict__ F, double* __restrict__ Wc) {
+__global__ void __launch_bounds__(256) gj_fetch_kernel(GJJobs J, GJJob one, int c0, int s0) {
+  const GJJob& jb = gj_job(J, one);
+  const int n = jb.n;
+  int nbw, B;
+  if (!gj_step(n, c0, s0, nbw, B)) return;
+  const double* __restrict__ M = jb.M;
+  double* __restrict__ F = jb.F;
+  double* __restrict__ Wc = jb.Wc;
   const int64_t w = 2 * (int64_t)n;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * B) return;
@@ -335,11 +388,18 @@ __global__ void __launch_bounds__(256) gj_fetch_kernel(int n, int s0, int B, con
   Wc[(int64_t)b * n + i] = v;
 }
 
-__global__ void __launch_bounds__(GJ_THREADS) gj_tourn0_kernel(int n, int B, const double* __restrict__ Wc,
-                                                               const int* __restrict__ done, int* __restrict__ cand) {
+__global__ void __launch_bounds__(GJ_THREADS) gj_tourn0_kernel(GJJobs J, GJJob one, int c0, int s0) {
   __shared__ double cv[2][NWV];
   __shared__ int ci[2][NWV];
   __shared__ double crow[2][NWV][GJB];
+  const GJJob& jb = gj_job(J, one);
+  const int n = jb.n;
+  int nbw, B;
+  if (!gj_step(n, c0, s0, nbw, B)) return;  // uniform
+  if ((int)blockIdx.x * GJ_THREADS >= n) return;  // uniform: beyond the job's row blocks
+  const double* __restrict__ Wc = jb.Wc;
+  const int* __restrict__ done = jb.done;
+  int* __restrict__ cand = jb.cand;
   const int i = blockIdx.x * GJ_THREADS + threadIdx.x;
   const bool ok = i < n;
   const int ic = ok ? i : 0;
@@ -354,11 +414,7 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_tourn0_kernel(int n, int B, con
   for (int jj = got + (int)threadIdx.x; jj < GJB; jj += blockDim.x) mine[jj] = -1;
 }
 
-__global__ void __launch_bounds__(GJ_THREADS) gj_tourn1_kernel(int n, int s0, int B, int nblk, double* __restrict__ M,
-                                                               const double* __restrict__ F,
-                                                               const int* __restrict__ cand, int* __restrict__ done,
-                                                               int* __restrict__ prow, double* __restrict__ Pinv,
-                                                               int* status) {
+__global__ void __launch_bounds__(GJ_THREADS) gj_tourn1_kernel(GJJobs J, GJJob one, int c0, int s0) {
   __shared__ double Mp[GJB][2 * GJB];
   __shared__ double fr[GJB];
   __shared__ double rowc[2 * GJB];
@@ -366,6 +422,18 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_tourn1_kernel(int n, int s0, in
   __shared__ double cv[2][NWV];
   __shared__ int ci[2][NWV];
   __shared__ double crow[2][NWV][GJB];
+  const GJJob& jb = gj_job(J, one);
+  const int n = jb.n;
+  int nbw, B;
+  if (!gj_step(n, c0, s0, nbw, B)) return;  // uniform
+  const int nblk = (n + GJ_THREADS - 1) / GJ_THREADS;
+  double* __restrict__ M = jb.M;
+  const double* __restrict__ F = jb.F;
+  const int* __restrict__ cand = jb.cand;
+  int* __restrict__ done = jb.done;
+  int* __restrict__ prow = jb.prow;
+  double* __restrict__ Pinv = jb.Pinv;
+  int* status = jb.status;
   const int tid = threadIdx.x;
   const int64_t w = 2 * (int64_t)n;
   const int r = tid < nblk * GJB ? cand[tid] : -1;
@@ -390,9 +458,15 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_tourn1_kernel(int n, int s0, in
 }
 
 // Yo[i][k] = M[i][n + c0 + k] - [i == p_{c0+k}];  Rb[k][j] = M[p_{c0+k}][c0 + nbw + j]
-__global__ void __launch_bounds__(256) gj_gather_kernel(int n, int c0, int nbw, const double* __restrict__ M,
-                                                        const int* __restrict__ prow, double* __restrict__ Yo,
-                                                        double* __restrict__ Rb) {
+__global__ void __launch_bounds__(256) gj_gather_kernel(GJJobs J, GJJob one, int c0) {
+  const GJJob& jb = gj_job(J, one);
+  const int n = jb.n;
+  if (c0 >= n) return;
+  const int nbw = min(GJ_NB, n - c0);
+  const double* __restrict__ M = jb.M;
+  const int* __restrict__ prow = jb.prow;
+  double* __restrict__ Yo = jb.Yo;
+  double* __restrict__ Rb = jb.Rb;
   const int64_t w = 2 * (int64_t)n;
   const int64_t nr = n - nbw;
   const int64_t ny = (int64_t)n * nbw, nrb = (int64_t)nbw * nr;
@@ -414,13 +488,20 @@ __global__ void __launch_bounds__(256) gj_gather_kernel(int n, int c0, int nbw, 
 // M[i][c0 + nbw + j] += sum_k Yo[i][k] Rb[k][j]  (i < n, j < n - nbw).
 // 64 x 64 output tile per workgroup, 4 x 4 per thread, K staged in LDS by 16.
 constexpr int GT = 64, GK = 16;
-__global__ void __launch_bounds__(256) gj_gemm_kernel(int n, int c0, int nbw, const double* __restrict__ Yo,
-                                                      const double* __restrict__ Rb, double* __restrict__ M) {
+__global__ void __launch_bounds__(256) gj_gemm_kernel(GJJobs J, GJJob one, int c0) {
   __shared__ double Ys[GK][GT + 1];
   __shared__ double Rs[GK][GT + 1];
-  const int64_t w = 2 * (int64_t)n;
+  const GJJob& jb = gj_job(J, one);
+  const int n = jb.n;
+  if (c0 >= n) return;  // uniform
+  const int nbw = min(GJ_NB, n - c0);
   const int nr = n - nbw;
   const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
+  if (i0 >= n || j0 >= nr) return;  // uniform, before the barriers
+  const double* __restrict__ Yo = jb.Yo;
+  const double* __restrict__ Rb = jb.Rb;
+  double* __restrict__ M = jb.M;
+  const int64_t w = 2 * (int64_t)n;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   double acc[4][4];
 #pragma unroll
@@ -461,9 +542,14 @@ __global__ void __launch_bounds__(256) gj_gemm_kernel(int n, int c0, int nbw, co
   }
 }
 
-__global__ void __launch_bounds__(256) gj_init_kernel(int n, const double* __restrict__ a, double* __restrict__ M,
-                                                      int* __restrict__ done, int* __restrict__ prow,
-                                                      int* __restrict__ cand) {
+__global__ void __launch_bounds__(256) gj_init_kernel(GJJobs J, GJJob one) {
+  const GJJob& jb = gj_job(J, one);
+  const int n = jb.n;
+  const double* __restrict__ a = jb.a;
+  double* __restrict__ M = jb.M;
+  int* __restrict__ done = jb.done;
+  int* __restrict__ prow = jb.prow;
+  int* __restrict__ cand = jb.cand;
   const int64_t w = 2 * (int64_t)n;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)n * w;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -478,8 +564,12 @@ __global__ void __launch_bounds__(256) gj_init_kernel(int n, const double* __res
 }
 
 // A^-1[k][p_m] = M[p_k][n + m]
-__global__ void __launch_bounds__(256) gj_extract_kernel(int n, const double* __restrict__ M,
-                                                         const int* __restrict__ prow, double* __restrict__ inv) {
+__global__ void __launch_bounds__(256) gj_extract_kernel(GJJobs J, GJJob one) {
+  const GJJob& jb = gj_job(J, one);
+  const int n = jb.n;
+  const double* __restrict__ M = jb.M;
+  const int* __restrict__ prow = jb.prow;
+  double* __restrict__ inv = jb.inv;
   const int64_t w = 2 * (int64_t)n;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)n * n;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -496,53 +586,104 @@ size_t dense_invert_work(int n) {
          (size_t)(16 * GJB + 2 * n) * sizeof(int);
 }
 
+GJJob gj_make_job(int n, const double* a, double* inv, double* work, int* status) {
+  GJJob j;
+  j.n = n;
+  j.a = a;
+  j.inv = inv;
+  j.status = status;
+  j.M = work;
+  j.F = j.M + 2 * (int64_t)n * n;
+  j.Wc = j.F + (int64_t)n * GJB;
+  j.R = j.Wc + (int64_t)n * GJB;
+  j.Pinv = j.R + 2 * (int64_t)GJB * GJ_NB;
+  j.Yo = j.Pinv + GJB * GJB;
+  j.Rb = j.Yo + (int64_t)n * GJ_NB;
+  j.cand = (int*)(j.Rb + (int64_t)GJ_NB * n);
+  j.done = j.cand + 16 * GJB;
+  j.prow = j.done + n;
+  return j;
+}
+
+// panel kernel variant of a size (0..3: RPT 1..4 in registers, 4: tournament)
+int gj_variant(int n) {
+  if (n > 4 * GJ_THREADS) return 4;
+  return (n - 1) / GJ_THREADS;
+}
+
+// The step loop over the widest job.  ns: job sizes in table order; groups:
+// for each variant, its device selection list and size (single job: J.tab
+// null, the job in `one`).
+int gj_run(const GJJobs& J, const GJJob& one, const std::vector<int>& ns, const int* const groups[5],
+           const int gsize[5], hipStream_t s) {
+  const int nj = (int)ns.size();
+  int nmax = 0;
+  for (int n : ns) nmax = std::max(nmax, n);
+  if (nmax > 16 * GJ_THREADS) return -1;  // at most 16 tournament blocks
+  const dim3 zj(1024, 1, nj);
+  gj_init_kernel<<<zj, 256, 0, s>>>(J, one);
+  const int step = 16;  // every sub-panel width is a multiple
+  for (int c0 = 0; c0 < nmax; c0 += GJ_NB) {
+    for (int s0 = c0; s0 < std::min(nmax, c0 + GJ_NB); s0 += step) {
+      bool any = false;
+      for (int n : ns)
+        any = any || (c0 < n && s0 < std::min(n, c0 + GJ_NB) && (s0 - c0) % gj_pbw(n) == 0);
+      if (!any) continue;
+      gj_fetch_kernel<<<dim3((nmax * GJB + 255) / 256, 1, nj), 256, 0, s>>>(J, one, c0, s0);
+      for (int v = 0; v < 5; ++v) {
+        if (!gsize[v]) continue;
+        const GJJobs G{J.tab, groups[v]};
+        switch (v) {
+          case 0: gj_panel_kernel<1, 32><<<dim3(1, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0); break;
+          case 1: gj_panel_kernel<2, 32><<<dim3(1, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0); break;
+          case 2: gj_panel_kernel<3, 16><<<dim3(1, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0); break;
+          case 3: gj_panel_kernel<4, 16><<<dim3(1, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0); break;
+          default:
+            gj_tourn0_kernel<<<dim3(16, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0);
+            gj_tourn1_kernel<<<dim3(1, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0);
+        }
+      }
+      gj_rows_kernel<<<dim3((2 * GJ_NB + 255) / 256, GJB, nj), 256, 0, s>>>(J, one, c0, s0);
+      gj_update_kernel<<<dim3((2 * GJ_NB + 255) / 256, (nmax + UPR - 1) / UPR, nj), 256, 0, s>>>(J, one, c0, s0);
+    }
+    gj_gather_kernel<<<dim3(1024, 1, nj), 256, 0, s>>>(J, one, c0);
+    gj_gemm_kernel<<<dim3((nmax + GT - 1) / GT, (nmax + GT - 1) / GT, nj), 256, 0, s>>>(J, one, c0);
+  }
+  gj_extract_kernel<<<zj, 256, 0, s>>>(J, one);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // a: n x n input (not modified); inv: n x n output; work: dense_invert_work(n) bytes.
 int dense_invert(int n, double* a, double* inv, double* work, int* status, hipStream_t s) {
-  if (n > 16 * GJ_THREADS) return -1;  // at most 16 tournament blocks
-  double* M = work;
-  double* F = M + 2 * (int64_t)n * n;
-  double* Wc = F + (int64_t)n * GJB;
-  double* R = Wc + (int64_t)n * GJB;
-  double* Pinv = R + 2 * (int64_t)GJB * GJ_NB;
-  double* Yo = Pinv + GJB * GJB;
-  double* Rb = Yo + (int64_t)n * GJ_NB;
-  int* cand = (int*)(Rb + (int64_t)GJ_NB * n);
-  int* done = cand + 16 * GJB;
-  int* prow = done + n;
-  gj_init_kernel<<<1024, 256, 0, s>>>(n, a, M, done, prow, cand);
-  // sub-panel width: up to 4 rows per thread the sub-panel is factored in one
-  // workgroup's registers, beyond that by tournament pivoting
-  const bool wide = n > 4 * GJ_THREADS;
-  const int nblk = (n + GJ_THREADS - 1) / GJ_THREADS;
-  const int PBW = (wide || n <= 2 * GJ_THREADS) ? GJB : 16;
-  for (int c0 = 0; c0 < n; c0 += GJ_NB) {
-    const int nbw = std::min(GJ_NB, n - c0);
-    for (int s0 = c0; s0 < c0 + nbw; s0 += PBW) {
-      const int B = std::min(PBW, c0 + nbw - s0);
-      gj_fetch_kernel<<<(int)(((int64_t)n * B + 255) / 256), 256, 0, s>>>(n, s0, B, M, F, Wc);
-      if (wide) {
-        gj_tourn0_kernel<<<nblk, GJ_THREADS, 0, s>>>(n, B, Wc, done, cand);
-        gj_tourn1_kernel<<<1, GJ_THREADS, 0, s>>>(n, s0, B, nblk, M, F, cand, done, prow, Pinv, status);
-      } else if (n <= GJ_THREADS) {
-        gj_panel_kernel<1, 32><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, Wc, done, prow, Pinv, status);
-      } else if (n <= 2 * GJ_THREADS) {
-        gj_panel_kernel<2, 32><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, Wc, done, prow, Pinv, status);
-      } else if (n <= 3 * GJ_THREADS) {
-        gj_panel_kernel<3, 16><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, Wc, done, prow, Pinv, status);
-      } else {
-        gj_panel_kernel<4, 16><<<1, GJ_THREADS, 0, s>>>(n, s0, B, M, F, Wc, done, prow, Pinv, status);
-      }
-      gj_rows_kernel<<<dim3((2 * nbw + 255) / 256, B), 256, 0, s>>>(n, c0, nbw, s0, B, M, prow, Pinv, R);
-      gj_update_kernel<<<dim3((2 * nbw + 255) / 256, (n + UPR - 1) / UPR), 256, 0, s>>>(n, c0, nbw, s0, B, M, F,
-                                                                                         R, prow);
-    }
-    if (n - nbw > 0) {
-      gj_gather_kernel<<<1024, 256, 0, s>>>(n, c0, nbw, M, prow, Yo, Rb);
-      gj_gemm_kernel<<<dim3((n - nbw + GT - 1) / GT, (n + GT - 1) / GT), 256, 0, s>>>(n, c0, nbw, Yo, Rb, M);
-    }
+  const GJJob one = gj_make_job(n, a, inv, work, status);
+  const int* groups[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int gsize[5] = {0, 0, 0, 0, 0};
+  gsize[gj_variant(n)] = 1;
+  return gj_run(GJJobs{nullptr, nullptr}, one, std::vector<int>{n}, groups, gsize, s);
+}
+
+// Batched: job tables built by dense_invert_batch_setup (device memory the
+// caller owns); sizes in table order.
+int dense_invert_batch(const GJJob* tab_dev, const int* sel_dev, const std::vector<int>& ns, hipStream_t s) {
+  const int* groups[5];
+  int gsize[5] = {0, 0, 0, 0, 0};
+  for (int n : ns) gsize[gj_variant(n)]++;
+  int off = 0;
+  for (int v = 0; v < 5; ++v) {
+    groups[v] = sel_dev + off;
+    off += gsize[v];
   }
-  gj_extract_kernel<<<1024, 256, 0, s>>>(n, M, prow, inv);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  GJJob dummy{};
+  return gj_run(GJJobs{tab_dev, nullptr}, dummy, ns, groups, gsize, s);
+}
+
+// host-side selection lists for dense_invert_batch: job indices grouped by variant
+std::vector<int> dense_invert_batch_selection(const std::vector<int>& ns) {
+  std::vector<int> sel;
+  for (int v = 0; v < 5; ++v)
+    for (int i = 0; i < (int)ns.size(); ++i)
+      if (gj_variant(ns[i]) == v) sel.push_back(i);
+  return sel;
 }
 
 // x = Ainv b on the coarsest level; one wavefront per output unknown, FP64

@@ -227,6 +227,20 @@ void launch_inject_mask(const Grid& fine, const Grid& coarse, const uint16_t* mf
 // coarse direct solve
 void launch_dense_from_bsr(const Grid& g, const double* A64, double* dense, hipStream_t s);
 size_t dense_invert_work(int n);  // bytes of scratch needed by dense_invert
+// one dense inversion: pointers into its dense_invert_work(n) workspace
+struct GJJob {
+  int n;
+  const double* a;  // input n x n (not modified)
+  double* inv;      // output n x n
+  double *M, *F, *Wc, *R, *Pinv, *Yo, *Rb;
+  int *cand, *done, *prow;
+  int* status;
+};
+GJJob gj_make_job(int n, const double* a, double* inv, double* work, int* status);
+// several inversions at once: tab_dev = device table of jobs, sel_dev =
+// device copy of dense_invert_batch_selection(ns), ns = job sizes
+int dense_invert_batch(const GJJob* tab_dev, const int* sel_dev, const std::vector<int>& ns, hipStream_t s);
+std::vector<int> dense_invert_batch_selection(const std::vector<int>& ns);
 int dense_invert(int n, double* a, double* inv, double* work, int* piv_status, hipStream_t s);
 template <typename T>
 void launch_coarse_solve(const Grid& g, const double* Ainv, const T* b, T* x, hipStream_t s);
