@@ -97,6 +97,33 @@ def run_precision(prob, precision, steps, warmup, timing, tune=True):
     return dict(total_s=total, recs=recs, kernels=kstats, x=x.cpu().numpy(), shapes=shapes)
 
 
+def pade_assembly(prob, reps=5):
+    """Assembly cost per Pade order of the Hencky strain (Eqs. pade11, pade22,
+    pade33; compared in the paper's Table 3): median Newton-system time and
+    median time of the finest-level Gauss-point Hessian kernel, same state."""
+    from dataclasses import replace
+    from paper_2011_08802_amd import mvpf
+    out = {}
+    for order in (11, 22, 33):
+        pr = replace(prob, material=replace(prob.material, pade=order))
+        gp = mvpf.Problem(pr, "mixed", rtol=1e-8)
+        gp.init_random(pr.seed)
+        gp.newton_system(pr.depth_increment)  # warm-up
+        gp.kernel_timing(True)
+        sys_ms = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gp.newton_system(pr.depth_increment)
+            torch.cuda.synchronize()
+            sys_ms.append(1e3 * (time.perf_counter() - t0))
+        n, ms, _ = gp.kernel_stats("qp_hessian")
+        gp.kernel_timing(False)
+        gp.close()
+        out[str(order)] = dict(system_ms_median=statistics.median(sys_ms), qp_hessian_ms=ms / max(n, 1))
+    return out
+
+
 def run_batch(probs, precision, steps, warmup, tune=True):
     """The batched workload: all problems' Newton systems, one lockstep
     batched solve (V-cycles of all problems in one graph launch per Arnoldi
@@ -286,6 +313,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes (no autotuning)")
+    ap.add_argument("--no-pade", action="store_true", help="skip the assembly cost per Pade order")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run an elementwise copy of this many MiB (counter calibration)")
     a = ap.parse_args()
@@ -361,6 +389,9 @@ def main():
                            "kernel": "finest-level FP32 smoother sweep (defect_upper_split + pbj_lower)",
                            "bytes_per_launch": k["bytes"], "avg_ms": k["avg_ms"], "launches": k["launches"]}
         out["kernels"] = mixed["kernels"]
+    if not a.no_pade and a.workload in ("tiny", "medium"):
+        log("[bench] assembly per Pade order ...")
+        out["pade_assembly"] = pade_assembly(prob)
     if not a.no_cpu_baseline:
         log("[bench] oracle cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline()

@@ -82,7 +82,9 @@ typedef struct {
  *  ell     interface thickness parameter l_ij (all pairs)
  *  rho     viscous coefficient 1/(m tau) (all phases, Sec. 2.3)
  *  eps_eta penalty parameter of eta_i >= 0 (Eq. PenPot)
- *  pade    Pade order of the Hencky strain: 22 ((2,2), Eq. pade22) */
+ *  pade    Pade order of the Hencky strain: 11, 22 or 33 for the (1,1), (2,2) or
+ *          (3,3) approximant (Eqs. pade11, pade22, pade33); other values are
+ *          rejected with MVPF_EINVAL */
 typedef struct {
   double cubic[3];
   double ortho[9];
@@ -260,7 +262,9 @@ int mvpf_autotune(mvpf_problem* p, int* row_blocks_out);
 
 /* Per-kernel device timing with HIP events on the problem's stream.  name:
  * "pbj_sweep" (finest-level smoother sweep), "spmv_outer" (finest FP64
- * operator product), "residual" (finest defect).  enable != 0 starts
+ * operator product), "residual" (finest defect), "qp_hessian" (finest-level
+ * Gauss-point gradient and Hessian of the density, Sec. 3.2; bytes = its
+ * output).  enable != 0 starts
  * recording (and clears totals); stats: launches, summed ms, algorithmic
  * bytes moved per launch. */
 int mvpf_kernel_timing(mvpf_problem* p, int enable);

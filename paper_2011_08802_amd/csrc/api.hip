@@ -570,7 +570,10 @@ int validate(const mvpf_mesh* mesh, const mvpf_material* mat, const mvpf_loading
     err = "mesh too large";
     return MVPF_EINVAL;
   }
-  if (mat->pade != 22) { err = "only the Pade (2,2) Hencky approximation is implemented"; return MVPF_EINVAL; }
+  if (mat->pade != 11 && mat->pade != 22 && mat->pade != 33) {
+    err = "Pade order of the Hencky strain must be 11, 22 or 33";
+    return MVPF_EINVAL;
+  }
   if (load->kind == MVPF_LOAD_PATCH) {
     if (load->patch < 0 || load->patch % 2 || mesh->nx % 2 || mesh->ny % 2) {
       err = "patch loading needs even patch, nx and ny";
@@ -613,7 +616,7 @@ void destroy_all(mvpf_problem* p) {
   if (p->side) (void)hipStreamDestroy(p->side);
   p->ev_fork = p->ev_join = nullptr;
   p->side = nullptr;
-  for (KernelTimer* t : {&p->t_sweep, &p->t_outer, &p->t_resid})
+  for (KernelTimer* t : {&p->t_sweep, &p->t_outer, &p->t_resid, &p->t_qp})
     for (hipEvent_t e : t->ev) (void)hipEventDestroy(e);
 }
 
@@ -706,6 +709,7 @@ int allocate(mvpf_problem* p) {
   }
   DevCard hc;
   build_card(p->mat, hc);
+  p->pade = p->mat.pade;
   HIPCHK(hipMemcpyAsync(p->card, &hc, sizeof(DevCard), hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   return 0;
@@ -727,7 +731,7 @@ int compute_residual(mvpf_problem* p, double depth, double* norm_free) {
   Level& L0 = p->lev[0];
   launch_dirichlet_masks(L0.g, p->load, depth, L0.mask, L0.target, p->stream);
   for (const Chunk& ck : make_chunks(L0.g, p->ne_use)) {
-    launch_qp(L0.g, ck, L0.state, p->card, p->qp, false, p->stream);
+    launch_qp(L0.g, ck, L0.state, p->card, p->pade, p->qp, false, p->stream);
     launch_residual_gather(L0.g, ck, L0.state, p->qp, p->card, p->R, p->stream);
   }
   TRY(launch_check(p, "residual"));
@@ -740,7 +744,7 @@ int compute_residual(mvpf_problem* p, double depth, double* norm_free) {
 void assemble_coarse_level(mvpf_problem* p, int l) {
   Level& C = p->lev[l];
   for (const Chunk& ck : make_chunks(C.g, p->ne_use)) {
-    launch_qp(C.g, ck, C.state, p->card, p->qp, true, p->stream);
+    launch_qp(C.g, ck, C.state, p->card, p->pade, p->qp, true, p->stream);
     launch_element_matrices(C.g, ck, p->qp, p->card, p->elem, p->stream);
     launch_jacobian_gather(C.g, ck, p->elem, C.A64, C.A32, C.diag64, p->stream);
   }
@@ -799,7 +803,10 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
   for (int l = Lc - 1; l >= 1; --l) assemble_coarse_level(p, l);
   // finest: residual and unconstrained tangent
   for (const Chunk& ck : make_chunks(L0.g, p->ne_use)) {
-    launch_qp(L0.g, ck, L0.state, p->card, p->qp, true, s);
+    timer_begin(p, p->t_qp);
+    launch_qp(L0.g, ck, L0.state, p->card, p->pade, p->qp, true, s);
+    // written: gradient (15) and packed Hessian (120) per Gauss point
+    timer_end(p, p->t_qp, 8.0 * 8 * 135 * (double)ck.NEc);
     launch_residual_gather(L0.g, ck, L0.state, p->qp, p->card, p->R, s);
     launch_element_matrices(L0.g, ck, p->qp, p->card, p->elem, s);
     launch_jacobian_gather(L0.g, ck, p->elem, L0.A64, L0.A32, L0.diag64, s);
@@ -1471,7 +1478,7 @@ int mvpf_autotune(mvpf_problem* p, int* row_blocks_out) {
 int mvpf_kernel_timing(mvpf_problem* p, int enable) {
   if (!p) return MVPF_EINVAL;
   (void)hipStreamSynchronize(p->stream);
-  for (KernelTimer* t : {&p->t_sweep, &p->t_outer, &p->t_resid}) {
+  for (KernelTimer* t : {&p->t_sweep, &p->t_outer, &p->t_resid, &p->t_qp}) {
     t->used = 0;
     t->launches = 0;
     t->total_ms = 0.0;
@@ -1486,6 +1493,7 @@ int mvpf_kernel_stats(mvpf_problem* p, const char* name, int* launches, double* 
   if (!std::strcmp(name, "pbj_sweep")) t = &p->t_sweep;
   else if (!std::strcmp(name, "spmv_outer")) t = &p->t_outer;
   else if (!std::strcmp(name, "residual")) t = &p->t_resid;
+  else if (!std::strcmp(name, "qp_hessian")) t = &p->t_qp;
   else { p->err = "unknown kernel name"; return MVPF_EINVAL; }
   timer_collect(p, *t);
   if (launches) *launches = t->launches;

@@ -143,6 +143,7 @@ struct mvpf_problem {
   bool mixed = false;
   mvpf::Level lev[mvpf::MAX_LEVELS];
   mvpf::DevCard* card = nullptr;     // device copy
+  int pade = 22;                     // Pade order of the Hencky strain (11, 22, 33)
   double* qp = nullptr;              // per-Gauss-point scratch (finest size)
   double* elem = nullptr;            // element matrices, upper node pairs (finest size)
   void* Cbuf = nullptr;              // lower-half contributions, 13 * 9 * Npad doubles (finest size)
@@ -168,7 +169,7 @@ struct mvpf_problem {
   int row_G[mvpf::MAX_LEVELS] = {0};  // launch shape of the smoother/defect kernels per level
   int outer_G = 0;                     // launch shape of the outer FP64 operator product
   int small_nodes = mvpf::SMALL_GRID_NODES;  // levels up to this size use the small-grid kernels
-  mvpf::KernelTimer t_sweep, t_outer, t_resid;
+  mvpf::KernelTimer t_sweep, t_outer, t_resid, t_qp;
   // the coarsest-level inversion runs on a second stream (default priority),
   // overlapping the assembly of the finer levels
   hipStream_t side = nullptr;
@@ -185,8 +186,8 @@ namespace mvpf {
 
 // ---- launchers (all asynchronous on `s`) ----------------------------------
 // quadrature / assembly
-void launch_qp(const Grid& g, const Chunk& ck, const double* state, const DevCard* cd, double* qp, bool hess,
-               hipStream_t s);
+void launch_qp(const Grid& g, const Chunk& ck, const double* state, const DevCard* cd, int pade, double* qp,
+               bool hess, hipStream_t s);
 void launch_residual_gather(const Grid& g, const Chunk& ck, const double* state, const double* qp, const DevCard* cd,
                             double* R, hipStream_t s);
 void launch_element_matrices(const Grid& g, const Chunk& ck, const double* qp, const DevCard* cd, double* elem,

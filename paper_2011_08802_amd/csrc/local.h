@@ -7,13 +7,19 @@
 //         + sum_i rho/2 (eta_i - eta_in)^2 + sum_i eps/2 <eta_i>_-^2
 //   F^t = I + sum_k eta_k dU_k  (Eq. LinMix with U_0 = I, condensed),
 //   J_t = det F^t, G = (F^t)^-1, C = G F^T F G  (C^e of Eq. elasticEn),
-//   H = 3/2 (C^2 - I)(C^2 + 4C + I)^-1  (Eq. pade22), L = L_0 + sum eta_k dL_k.
+//   H = A(C) B(C)^-1, the Pade approximant of 1/2 log C of order (1,1), (2,2)
+//   or (3,3) (Eqs. pade11, pade22, pade33; A and B are matrix polynomials in
+//   C, the leading factor folded into A), L = L_0 + sum eta_k dL_k.
 //
 // Derivatives are closed-form:
 //  * in C-space along the symmetric basis E_v (xx,yy,zz,yz,xz,xy; the shear
-//    ones are e_a e_b^T + e_b e_a^T):  with A = C^2 - I, B = C^2 + 4C + I,
-//    dH = (3/2 dA - H dB) B^-1,
-//    d2H = (3/2 d2A - dH_u dB_v - dH_v dB_u - H d2B) B^-1, d2A = d2B = E_u E_v + E_v E_u;
+//    ones are e_a e_b^T + e_b e_a^T); A, B commute with C, so with
+//    dX_v = dX/dC[E_v] and d2X_uv its second derivative (X = A, B):
+//    dH = (dA - H dB) B^-1,
+//    d2H = (d2A - dH_u dB_v - dH_v dB_u - H d2B) B^-1, where
+//    d(C^2)[E] = CE + EC, d(C^3)[E] = EC^2 + CEC + C^2E,
+//    d2(C^2)[E_u, E_v] = E_u E_v + E_v E_u,
+//    d2(C^3)[E_u, E_v] = (E_u E_v + E_v E_u) C + C (E_u E_v + E_v E_u) + E_u C E_v + E_v C E_u;
 //  * chain rule through C(F, G(eta)), J_t(eta), L(eta):
 //    dC/dF_ij = a_i (x) G_j + G_j (x) a_i  (a_i = row i of F G),
 //    dC/deta_k = -(Q_k C + C Q_k^T), Q_k = G dU_k,  dJ_t/deta_k = J_t tr Q_k,
@@ -140,6 +146,34 @@ __host__ __device__ constexpr int hidx(int p, int q) {  // packed upper triangle
   return p * 15 - (p * (p - 1)) / 2 + (q - p);
 }
 
+// Coefficients of H = A B^-1 with A = sum_p a_p C^p, B = sum_p b_p C^p.
+template <int ORDER> struct Pade;
+template <> struct Pade<11> {  // (C - I)(C + I)^-1
+  static constexpr int deg = 1;
+  __host__ __device__ static constexpr double a(int p) { return p == 0 ? -1.0 : (p == 1 ? 1.0 : 0.0); }
+  __host__ __device__ static constexpr double b(int p) { return p <= 1 ? 1.0 : 0.0; }
+};
+template <> struct Pade<22> {  // 3/2 (C^2 - I)(C^2 + 4C + I)^-1
+  static constexpr int deg = 2;
+  __host__ __device__ static constexpr double a(int p) { return p == 0 ? -1.5 : (p == 2 ? 1.5 : 0.0); }
+  __host__ __device__ static constexpr double b(int p) { return p == 1 ? 4.0 : (p <= 2 ? 1.0 : 0.0); }
+};
+template <> struct Pade<33> {  // 1/6 (11C^3 + 27C^2 - 27C - 11I)(C^3 + 9C^2 + 9C + I)^-1
+  static constexpr int deg = 3;
+  __host__ __device__ static constexpr double a(int p) {
+    return p == 0 ? -11.0 / 6.0 : (p == 1 ? -4.5 : (p == 2 ? 4.5 : 11.0 / 6.0));
+  }
+  __host__ __device__ static constexpr double b(int p) { return (p == 0 || p == 3) ? 1.0 : 9.0; }
+};
+
+// x += c m, the term dropped at compile time when c is zero
+template <int N>
+__device__ __forceinline__ void axpy_c(double c, const double m[N], double x[N]) {
+  if (c == 0.0) return;
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] += c * m[i];
+}
+
 // Quantities shared by the gradient and the Hessian.
 struct LocalBase {
   double Jt;
@@ -156,9 +190,11 @@ struct LocalBase {
   double H[9];
 };
 
-// Padé (2,2) Hencky energy and its first C-derivatives.
+// Hencky energy (Pade order PD) and its first C-derivatives.
+template <int PD>
 __device__ __forceinline__ void local_base(const double F[9], const double eh[6], const DevCard& cd,
                                            LocalBase& b) {
+  using P = Pade<PD>;
   double Ft[6];
 #pragma unroll
   for (int v = 0; v < 6; ++v) {
@@ -177,26 +213,32 @@ __device__ __forceinline__ void local_base(const double F[9], const double eh[6]
 #pragma unroll
     for (int c = 0; c < 3; ++c)
       b.C[3 * a + c] = b.Fe[a] * b.Fe[c] + b.Fe[3 + a] * b.Fe[3 + c] + b.Fe[6 + a] * b.Fe[6 + c];
-  double C2[9];
-  mm(b.C, b.C, C2);
-  double Bs[6], Bi[6];
-  {
-    double Bf[9];
+  double C2[9], C3[9];
+  if constexpr (P::deg >= 2) mm(b.C, b.C, C2);
+  if constexpr (P::deg >= 3) mm(C2, b.C, C3);
+  double Am[9], Bf[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Bf[i] = C2[i] + 4.0 * b.C[i] + ((i % 4 == 0) ? 1.0 : 0.0);
-    sym_of(Bf, Bs);
+  for (int i = 0; i < 9; ++i) {
+    const double id = (i % 4 == 0) ? 1.0 : 0.0;
+    Am[i] = P::a(0) * id + P::a(1) * b.C[i];
+    Bf[i] = P::b(0) * id + P::b(1) * b.C[i];
   }
+  if constexpr (P::deg >= 2) {
+    axpy_c<9>(P::a(2), C2, Am);
+    axpy_c<9>(P::b(2), C2, Bf);
+  }
+  if constexpr (P::deg >= 3) {
+    axpy_c<9>(P::a(3), C3, Am);
+    axpy_c<9>(P::b(3), C3, Bf);
+  }
+  double Bs[6], Bi[6];
+  sym_of(Bf, Bs);
   sym_inv(Bs, Bi);
   full_from_sym(Bi, b.Binv);
-  double Am[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) Am[i] = C2[i] - ((i % 4 == 0) ? 1.0 : 0.0);
   double Hf[9];
   mm(Am, b.Binv, Hf);
   double Hs[6];
   sym_of(Hf, Hs);
-#pragma unroll
-  for (int v = 0; v < 6; ++v) Hs[v] *= 1.5;
   full_from_sym(Hs, b.H);
   eng(Hs, b.h);
   // mixed stiffness and Hencky stress
@@ -236,18 +278,37 @@ __device__ __forceinline__ void local_base(const double F[9], const double eh[6]
   // dH along the C basis and dw/dC
 #pragma unroll
   for (int v = 0; v < 6; ++v) {
-    double E[9], P[9], dA[9], dB[9], HdB[9], X[9], dHf[9], dHs[6];
+    double E[9], dA[9], dB[9], HdB[9], X[9], dHf[9], dHs[6];
     basis(v, E);
-    mm(b.C, E, P);
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int i = 0; i < 9; ++i) {
+      dA[i] = P::a(1) * E[i];
+      dB[i] = P::b(1) * E[i];
+    }
+    if constexpr (P::deg >= 2) {
+      double CE[9], d2[9];
+      mm(b.C, E, CE);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) dA[3 * a + c] = P[3 * a + c] + P[3 * c + a];
+      for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int i = 0; i < 9; ++i) dB[i] = dA[i] + 4.0 * E[i];
+        for (int c = 0; c < 3; ++c) d2[3 * a + c] = CE[3 * a + c] + CE[3 * c + a];
+      axpy_c<9>(P::a(2), d2, dA);
+      axpy_c<9>(P::b(2), d2, dB);
+      if constexpr (P::deg >= 3) {
+        double C2E[9], CEC[9], d3[9];
+        mm(C2, E, C2E);
+        mm(CE, b.C, CEC);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) d3[3 * a + c] = C2E[3 * a + c] + C2E[3 * c + a] + CEC[3 * a + c];
+        axpy_c<9>(P::a(3), d3, dA);
+        axpy_c<9>(P::b(3), d3, dB);
+      }
+    }
     mm(b.H, dB, HdB);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) X[i] = 1.5 * dA[i] - HdB[i];
+    for (int i = 0; i < 9; ++i) X[i] = dA[i] - HdB[i];
     mm(X, b.Binv, dHf);
     sym_of(dHf, dHs);
     eng(dHs, b.dh[v]);
@@ -325,10 +386,11 @@ __device__ __forceinline__ void dC_F(const LocalBase& b, int q, double dc[6]) {
 __device__ __forceinline__ double neg_part(double x) { return x < 0.0 ? x : 0.0; }
 
 // Gradient of the local density: g[15].
+template <int PD>
 __device__ __forceinline__ void local_gradient(const double F[9], const double eh[6], const double ehn[6],
                                                const DevCard& cd, double g[15]) {
   LocalBase b;
-  local_base(F, eh, cd, b);
+  local_base<PD>(F, eh, cd, b);
 #pragma unroll
   for (int q = 0; q < 15; ++q) {
     double dc[6], dcf[9];
@@ -374,11 +436,13 @@ __device__ __forceinline__ void local_gradient(const double F[9], const double e
 // Gradient and packed upper-triangular Hessian of the local density; entry
 // hidx(p, q) of the Hessian is stored to D[hidx(p, q) * ds] as soon as it is
 // known (nothing of it is kept in registers).
+template <int PD>
 __device__ __forceinline__ void local_hessian(const double F[9], const double eh[6], const double ehn[6],
                                               const DevCard& cd, double g[15], double* __restrict__ D,
                                               int64_t ds) {
+  using P = Pade<PD>;
   LocalBase b;
-  local_base(F, eh, cd, b);
+  local_base<PD>(F, eh, cd, b);
   // ---- second derivatives in C-space -------------------------------------
   double wCC[6][6];
   double wCeta[6][6];  // [v][k]
@@ -393,27 +457,55 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
         for (int k = 0; k < 6; ++k) s += eh[k] * cd.dL[k][i][j];
         Lm[i][j] = s;
       }
-    // Y = T B^-1, Z = (3/2 I - H) Y
+    // T : d2H_uv = Y : (d2A - H d2B) - V_u : dB_v - V_v : dB_u with Y = T B^-1,
+    // V_u = dH_u Y.  Y : (d2A - H d2B) = Zt : (E_u E_v + E_v E_u)
+    // + Z_3 : (E_u C E_v + E_v C E_u) with Z_p = a_p Y - b_p H Y and
+    // Zt = Z_2 + Z_3 C + C Z_3;  V : dB_v = Vt : E_v with
+    // Vt = b_1 V + b_2 (CV + VC) + b_3 (V C^2 + C V C + C^2 V).
     double Tf[9], Ts[6] = {b.T[0], b.T[1], b.T[2], b.T[3], b.T[4], b.T[5]};
     full_from_sym(Ts, Tf);
-    double Y[9], HY[9], Z[9];
+    double Y[9], HY[9], Zt[9], Z3[9], C2[9];
     mm(Tf, b.Binv, Y);
     mm(b.H, Y, HY);
+    if constexpr (P::deg >= 2) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Z[i] = 1.5 * Y[i] - HY[i];
-    // vt[u][v] = (C V_u + V_u C + 4 V_u) : E_v with V_u = dH_u Y
+      for (int i = 0; i < 9; ++i) Zt[i] = P::a(2) * Y[i] - P::b(2) * HY[i];
+    }
+    if constexpr (P::deg >= 3) {
+      double ZC[9], CZ[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Z3[i] = P::a(3) * Y[i] - P::b(3) * HY[i];
+      mm(Z3, b.C, ZC);
+      mm(b.C, Z3, CZ);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Zt[i] += ZC[i] + CZ[i];
+      mm(b.C, b.C, C2);
+    }
     double vt[6][6];
 #pragma unroll
     for (int u = 0; u < 6; ++u) {
       double dHs[6] = {b.dh[u][0], b.dh[u][1], b.dh[u][2],
                        0.5 * b.dh[u][3], 0.5 * b.dh[u][4], 0.5 * b.dh[u][5]};
-      double dHf[9], V[9], CV[9], VC[9], Vt[9];
+      double dHf[9], V[9], Vt[9];
       full_from_sym(dHs, dHf);
       mm(dHf, Y, V);
-      mm(b.C, V, CV);
-      mm(V, b.C, VC);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) Vt[i] = CV[i] + VC[i] + 4.0 * V[i];
+      for (int i = 0; i < 9; ++i) Vt[i] = P::b(1) * V[i];
+      if constexpr (P::deg >= 2) {
+        double CV[9], VC[9];
+        mm(b.C, V, CV);
+        mm(V, b.C, VC);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Vt[i] += P::b(2) * (CV[i] + VC[i]);
+        if constexpr (P::deg >= 3) {
+          double VC2[9], CVC[9], C2V[9];
+          mm(V, C2, VC2);
+          mm(CV, b.C, CVC);
+          mm(C2, V, C2V);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) Vt[i] += P::b(3) * (VC2[i] + CVC[i] + C2V[i]);
+        }
+      }
 #pragma unroll
       for (int v = 0; v < 6; ++v) vt[u][v] = contract_basis(Vt, v);
     }
@@ -432,15 +524,25 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < 6; ++i) s += b.dh[v][i] * LdH[i];
-        // Z : (E_u E_v + E_v E_u)
-        double Eu[9], Ev[9], P1[9], P2[9];
-        basis(u, Eu);
-        basis(v, Ev);
-        mm(Eu, Ev, P1);
-        mm(Ev, Eu, P2);
         double zd = 0.0;
+        if constexpr (P::deg >= 2) {
+          double Eu[9], Ev[9], P1[9], P2[9];
+          basis(u, Eu);
+          basis(v, Ev);
+          mm(Eu, Ev, P1);
+          mm(Ev, Eu, P2);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) zd += Z[i] * (P1[i] + P2[i]);
+          for (int i = 0; i < 9; ++i) zd += Zt[i] * (P1[i] + P2[i]);
+          if constexpr (P::deg >= 3) {
+            double EC[9], ECE1[9], ECE2[9];
+            mm(Eu, b.C, EC);
+            mm(EC, Ev, ECE1);
+            mm(Ev, b.C, EC);
+            mm(EC, Eu, ECE2);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) zd += Z3[i] * (ECE1[i] + ECE2[i]);
+          }
+        }
         const double val = s + zd - vt[u][v] - vt[v][u];
         wCC[u][v] = val;
         wCC[v][u] = val;

@@ -51,7 +51,7 @@ __device__ __forceinline__ double lap_ref(int a, int b) {
   return 0.125 * s;
 }
 
-template <bool HESS>
+template <bool HESS, int PD>
 __global__ void __launch_bounds__(128) qp_kernel(Grid g, Chunk ck, const double* __restrict__ state,
                                                  const DevCard* __restrict__ cd, double* __restrict__ qp) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -83,23 +83,34 @@ __global__ void __launch_bounds__(128) qp_kernel(Grid g, Chunk ck, const double*
   double* out = qp + (int64_t)gp * ck.NEcpad + el;
   double gr[15];
   if (HESS) {
-    local_hessian(F, eh, ehn, *cd, gr, out + (int64_t)15 * stride, stride);
+    local_hessian<PD>(F, eh, ehn, *cd, gr, out + (int64_t)15 * stride, stride);
   } else {
-    local_gradient(F, eh, ehn, *cd, gr);
+    local_gradient<PD>(F, eh, ehn, *cd, gr);
   }
 #pragma unroll
   for (int c = 0; c < 15; ++c) out[(int64_t)c * stride] = gr[c];
 }
 
-void launch_qp(const Grid& g, const Chunk& ck, const double* state, const DevCard* cd, double* qp, bool hess,
-               hipStream_t s) {
+template <int PD>
+void launch_qp_order(const Grid& g, const Chunk& ck, const double* state, const DevCard* cd, double* qp, bool hess,
+                     hipStream_t s) {
   const int64_t n = (int64_t)8 * ck.NEcpad;
   const int bs = 128;
   const int nb = (int)((n + bs - 1) / bs);
   if (hess)
-    qp_kernel<true><<<nb, bs, 0, s>>>(g, ck, state, cd, qp);
+    qp_kernel<true, PD><<<nb, bs, 0, s>>>(g, ck, state, cd, qp);
   else
-    qp_kernel<false><<<nb, bs, 0, s>>>(g, ck, state, cd, qp);
+    qp_kernel<false, PD><<<nb, bs, 0, s>>>(g, ck, state, cd, qp);
+}
+
+// pade: 11, 22 or 33 (validated at creation)
+void launch_qp(const Grid& g, const Chunk& ck, const double* state, const DevCard* cd, int pade, double* qp,
+               bool hess, hipStream_t s) {
+  switch (pade) {
+    case 11: launch_qp_order<11>(g, ck, state, cd, qp, hess, s); break;
+    case 33: launch_qp_order<33>(g, ck, state, cd, qp, hess, s); break;
+    default: launch_qp_order<22>(g, ck, state, cd, qp, hess, s); break;
+  }
 }
 
 __global__ void __launch_bounds__(256) residual_gather_kernel(Grid g, Chunk ck, const double* __restrict__ state,

@@ -69,7 +69,7 @@ class MaterialParams:
     ell: interface thickness parameter l_ij (same for all pairs).
     rho: viscous coefficient 1/(m*tau) (same for all phases).
     eps_eta: penalty parameter of the order-parameter constraints.
-    pade: Pade order of the Hencky strain approximation (22 = (2,2)).
+    pade: Pade order of the Hencky strain approximation (11, 22 or 33 = (1,1), (2,2), (3,3)).
     """
     cubic: tuple = (142.0, 126.0, 96.0)
     ortho: tuple = (189.0, 141.0, 205.0, 54.9, 19.7, 62.6, 124.0, 45.5, 115.0)

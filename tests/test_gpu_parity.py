@@ -335,3 +335,38 @@ def test_time_step_failure_restores_state():
     st = gp.time_step(p.depth_increment)
     assert st.converged and st.halvings == 0
     gp.close()
+
+
+@pytest.mark.parametrize("order", [11, 22, 33])
+def test_pade_orders_match_oracle(order):
+    """Hencky strain by the (1,1), (2,2) or (3,3) Pade approximant (Eqs.
+    pade11, pade22, pade33): residual, right-hand side and finest-level K x
+    at <= 1e-12 against the oracle of the same order (AD of its own matrix
+    polynomials), and a solve at rtol 1e-12 within 1e-9 of the oracle's
+    direct solve.  The strains are large enough (random displacements of
+    amplitude 5e-3 on h = 1/8) that the orders' residuals differ by far more
+    than the tolerance, so a kernel of the wrong order cannot pass."""
+    p = synth.Problem(8, 8, 6, lz=0.75, n_levels=2, patch=2, depth_increment=0.01,
+                      material=synth.config_material(pade=order))
+    U, En = seeded_state(p, 5e-3)
+    say(f"[pade {order}] oracle")
+    oc = OracleCase(p, U, En, p.depth_increment, build_mg=False)
+    if order != 22:
+        p22 = synth.Problem(8, 8, 6, lz=0.75, n_levels=2, patch=2, depth_increment=0.01)
+        o22 = OracleCase(p22, U, En, p22.depth_increment, build_mg=False, direct=False)
+        assert rel(o22.sys.R, oc.sys.R) > 1e-7, rel(o22.sys.R, oc.sys.R)
+    say(f"[pade {order}] GPU")
+    gp = gpu_problem(p, U, En, "fp64", rtol=1e-12)
+    gp.newton_system(p.depth_increment)
+    R, _ = gp.residual()
+    ru, re = rel_blocks(R.cpu().numpy(), oc.sys.R)
+    assert ru < 1e-12 and re < 1e-12, (ru, re)
+    bu, be = rel_blocks(gp.get_rhs().cpu().numpy(), oc.sys.b)
+    assert bu < 1e-12 and be < 1e-12, (bu, be)
+    x = np.random.default_rng(5).standard_normal(oc.sys.A.shape[0])
+    yu, ye = rel_blocks(gp.jacobian_apply(0, _dev(x)).cpu().numpy(), oc.sys.A @ x)
+    assert yu < 1e-12 and ye < 1e-12, (yu, ye)
+    dx, st = gp.solve()
+    gp.close()
+    assert st.converged and st.rel_residual <= 1e-12
+    assert rel(dx.cpu().numpy(), oc.x) <= 1e-9, rel(dx.cpu().numpy(), oc.x)

@@ -69,9 +69,10 @@ def test_create_rejects_bad_options(lib):
     rc, h, err = _create(lib, mvpf.Mesh(8, 8, 8, 0.125, 3), opts=o)
     assert rc == -1 and "Krylov" in err
     mat = mvpf.material_struct(synth.config_material())
-    mat.pade = 33
-    rc, h, err = _create(lib, mvpf.Mesh(8, 8, 8, 0.125, 3), mat=mat)
-    assert rc == -1 and "Pade" in err
+    for bad in (0, 21, 44):
+        mat.pade = bad
+        rc, h, err = _create(lib, mvpf.Mesh(8, 8, 8, 0.125, 3), mat=mat)
+        assert rc == -1 and "Pade" in err
     rc, h, err = _create(lib, mvpf.Mesh(8, 8, 8, 0.125, 3), load=mvpf.Loading(mvpf.LOAD_PATCH, 3, 0.2))
     assert rc == -1 and "patch" in err
 
