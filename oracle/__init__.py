@@ -17,8 +17,11 @@ energy    local free energy + dissipation + penalty density (Sec. 2.2, 2.3,
           as the paper obtains them from UFL's (Sec. 3.4)
 fem       Q1 hex meshes, element integrals, global residual and tangent as
           first and second derivatives of the discrete potential (Sec. 3.3-3.4)
+contact   frictionless penalty contact with a rigid spherical indenter and
+          the indentation load (Sec. 2.4, Eqs. Ngap and PenPot)
 solver    sparse assembly, Dirichlet lifting, point-block Jacobi, geometric
-          multigrid V-cycle, FGMRES, Newton (Sec. 3.4)
+          multigrid V-cycle, FGMRES, Newton, the indentation driver with
+          adaptive time steps (Sec. 3.4)
 
 Parity status: every function is pinned by a CPU test (``tests/test_oracle_*``)
 except the end-to-end indentation physics on the synthetic workloads, which is

@@ -40,6 +40,7 @@ import scipy.linalg
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+from .contact import SphereContact
 from .fem import NDOF, NETA, Discretisation, Mesh
 from .material import Card
 
@@ -56,8 +57,9 @@ def dirichlet(mesh: Mesh, kind: str = "patch", patch: int = 2, radius: float = 0
     face: kind 'patch' -- nodes of the centred patch x patch element square
     have u_z = -depth; kind 'cap' -- nodes under a rigid sphere of radius R
     at total depth d, r^2 < 2 R d - d^2 (r measured from the top-face
-    centre), have u_z = -(d - (R - sqrt(R^2 - r^2))).  Order parameters are
-    never constrained (natural boundary conditions).
+    centre), have u_z = -(d - (R - sqrt(R^2 - r^2))); kind 'sphere' -- none
+    (the indenter acts through penalty contact, module ``contact``).  Order
+    parameters are never constrained (natural boundary conditions).
     """
     nn = mesh.n_nodes
     mask = np.zeros((nn, NDOF), dtype=bool)
@@ -79,7 +81,7 @@ def dirichlet(mesh: Mesh, kind: str = "patch", patch: int = 2, radius: float = 0
         sel = top & (r2 < 2.0 * radius * depth - depth * depth)
         mask[sel, 2] = True
         target[sel, 2] = -(depth - (radius - np.sqrt(radius * radius - r2[sel])))
-    else:
+    elif kind != "sphere":
         raise ValueError(kind)
     return mask, target
 
@@ -105,11 +107,23 @@ def inject(fine_mesh: Mesh, fine_nodal: np.ndarray, coarse_mesh: Mesh) -> np.nda
 # operators
 # ---------------------------------------------------------------------------
 
-def assemble(disc: Discretisation, U: np.ndarray, Eta_n: np.ndarray) -> sp.csr_matrix:
-    """Unconstrained tangent K as CSR (duplicates summed by scipy)."""
+def assemble(disc: Discretisation, U: np.ndarray, Eta_n: np.ndarray,
+             contact: Optional[SphereContact] = None, depth: float = 0.0) -> sp.csr_matrix:
+    """Unconstrained tangent K as CSR (duplicates summed by scipy), with the
+    contact tangent at indenter depth ``depth`` when ``contact`` is given."""
     n = disc.mesh.n_nodes * NDOF
     r, c, v = disc.tangent_coo(U, Eta_n)
+    if contact is not None:
+        rc, cc, vc = contact.tangent_coo(U, depth)
+        r, c, v = np.concatenate([r, rc]), np.concatenate([c, cc]), np.concatenate([v, vc])
     return sp.coo_matrix((v, (r, c)), shape=(n, n)).tocsr()
+
+
+def contact_of(problem, mesh: Mesh) -> Optional[SphereContact]:
+    """The indenter's penalty contact on ``mesh`` for kind 'sphere', else None."""
+    if getattr(problem, "kind", "patch") != "sphere":
+        return None
+    return SphereContact(mesh, problem.radius, problem.eps_n)
 
 
 def eliminate(K: sp.csr_matrix, mask: np.ndarray) -> sp.csr_matrix:
@@ -179,7 +193,8 @@ class Multigrid:
 
     def __init__(self, problem, card: Card, U: np.ndarray, Eta_n: np.ndarray,
                  fine_mask: np.ndarray, n_levels: Optional[int] = None,
-                 opts: MGOptions = MGOptions(), K_fine: Optional[sp.csr_matrix] = None):
+                 opts: MGOptions = MGOptions(), K_fine: Optional[sp.csr_matrix] = None,
+                 depth: float = 0.0):
         self.opts = opts
         self.bs = NDOF
         L = problem.n_levels if n_levels is None else n_levels
@@ -195,7 +210,8 @@ class Multigrid:
                 self.levels[-1].P = prolongation(cm, mesh)
                 mesh = cm
             disc = Discretisation(mesh, card)
-            K = K_fine if (l == 0 and K_fine is not None) else assemble(disc, Ul.ravel(), En.ravel())
+            K = K_fine if (l == 0 and K_fine is not None) else \
+                assemble(disc, Ul.ravel(), En.ravel(), contact_of(problem, mesh), depth)
             A = eliminate(K, mask)
             self.levels.append(Level(mesh=mesh, mask=mask, A=A))
         self._finish()
@@ -361,14 +377,18 @@ def direct_solve(A: sp.csr_matrix, b: np.ndarray) -> np.ndarray:
 class NewtonSystem:
     """Linear system of one Newton iteration (Eq. linAlgEq) with Dirichlet
     lifting: A = K with constrained rows/cols eliminated, b as described in the
-    module docstring."""
+    module docstring.  For an indenter in contact (kind 'sphere') R and K
+    include the penalty contact terms at indenter depth ``depth``."""
 
     def __init__(self, problem, card: Card, U: np.ndarray, Eta_n: np.ndarray,
-                 mask: np.ndarray, g: np.ndarray):
+                 mask: np.ndarray, g: np.ndarray, depth: float = 0.0):
         self.mesh = Mesh.from_problem(problem, 0)
         self.disc = Discretisation(self.mesh, card)
+        self.contact = contact_of(problem, self.mesh)
         self.R = self.disc.residual(U, Eta_n)
-        self.K = assemble(self.disc, U, Eta_n)
+        if self.contact is not None:
+            self.R = self.R + self.contact.residual(U, depth)
+        self.K = assemble(self.disc, U, Eta_n, self.contact, depth)
         m = mask.ravel()
         gv = np.where(m, g.ravel(), 0.0)
         b = -self.R - self.K @ gv
@@ -380,7 +400,7 @@ class NewtonSystem:
 
 def newton_step(problem, card: Card, U: np.ndarray, Eta_n: np.ndarray, mask: np.ndarray,
                 g: np.ndarray, rtol: float = 1e-9, max_iter: int = 12, linear: str = "direct",
-                lin_rtol: float = 1e-12, log: Optional[list] = None):
+                lin_rtol: float = 1e-12, log: Optional[list] = None, depth: float = 0.0):
     """Newton iterations of one implicit step.  The first system carries the
     prescribed increment g; later ones are homogeneous on constrained dofs.
     Converged when ||R_free|| <= rtol * ||b_0|| (b_0 = first right-hand side).
@@ -389,7 +409,7 @@ def newton_step(problem, card: Card, U: np.ndarray, Eta_n: np.ndarray, mask: np.
     b0 = None
     gk = g
     for it in range(max_iter):
-        sysk = NewtonSystem(problem, card, U, Eta_n, mask, gk)
+        sysk = NewtonSystem(problem, card, U, Eta_n, mask, gk, depth)
         if b0 is None:
             b0 = float(np.linalg.norm(sysk.b))
         rfree = float(np.linalg.norm(np.where(mask.ravel(), 0.0, sysk.R)))
@@ -400,10 +420,95 @@ def newton_step(problem, card: Card, U: np.ndarray, Eta_n: np.ndarray, mask: np.
         if linear == "direct":
             dx = direct_solve(sysk.A, sysk.b)
         else:
-            mg = Multigrid(problem, card, U, Eta_n, mask, K_fine=sysk.K)
+            mg = Multigrid(problem, card, U, Eta_n, mask, K_fine=sysk.K, depth=depth)
             dx, _ = fgmres(sysk.A, sysk.b, mg.precondition, rtol=lin_rtol)
         U = U + dx
+        if not np.all(np.isfinite(U)):  # diverged: the step fails
+            return U, max_iter, False
         gk = np.zeros_like(g)
-    sysk = NewtonSystem(problem, card, U, Eta_n, mask, gk)
+    sysk = NewtonSystem(problem, card, U, Eta_n, mask, gk, depth)
     rfree = float(np.linalg.norm(np.where(mask.ravel(), 0.0, sysk.R)))
     return U, max_iter, rfree <= rtol * b0
+
+
+# ---------------------------------------------------------------------------
+# indentation driver with adaptive time steps
+# ---------------------------------------------------------------------------
+
+@dataclass
+class IndentOptions:
+    """Loading to ``depth_max`` (then unloading to 0 when ``unload``) by a
+    rigid spherical indenter moving at constant speed v.  The time step
+    enters through the viscous coefficient rho = 1/(m tau) with tau = dd / v,
+    i.e. rho = visc_depth / |dd| with visc_depth = v / m.  Step control
+    (Sec. 3.4): after an accepted step with n Newton iterations the next
+    depth increment is multiplied by ``grow`` if n < newton_desired and by
+    ``shrink`` if n > newton_desired (kept within [dd_min, dd_max]); a step
+    whose Newton iterations exceed newton_max is rejected and retried with
+    half the increment.  Steps never overshoot the end of a phase: when at
+    most dd + dd_min is left, the step goes exactly to the phase's end."""
+    depth_max: float
+    dd_init: float
+    dd_min: float
+    dd_max: float
+    visc_depth: float
+    grow: float = 1.25
+    shrink: float = 0.8
+    newton_desired: int = 7
+    newton_max: int = 12
+    unload: bool = True
+    max_steps: int = 1000
+
+
+@dataclass
+class IndentRecord:
+    depth: float
+    load: float
+    newton_iterations: int
+    rejected: int
+
+
+def indent(problem, U: np.ndarray, Eta_n: np.ndarray, opts: IndentOptions,
+           newton_rtol: float = 1e-9):
+    """Quasi-static indentation run (kind 'sphere') from depth 0 with the
+    state (U, Eta_n).  Returns (records of the accepted steps, U, ok)."""
+    from dataclasses import replace
+    mesh = Mesh.from_problem(problem, 0)
+    contact = contact_of(problem, mesh)
+    if contact is None:
+        raise ValueError("indentation needs the 'sphere' loading")
+    mask, _ = dirichlet(mesh, "sphere")
+    zero = np.zeros(mask.shape)
+    U, Eta_n = U.copy(), Eta_n.copy()
+    depth, dd = 0.0, opts.dd_init
+    targets = [opts.depth_max] + ([0.0] if opts.unload else [])
+    records: List[IndentRecord] = []
+    rejected = 0
+    for goal in targets:
+        sign = 1.0 if goal > depth else -1.0
+        while depth != goal:
+            if len(records) >= opts.max_steps:
+                return records, U, False
+            rem = abs(goal - depth)
+            if rem <= dd + opts.dd_min:  # the phase's last step: land on the goal
+                step, trial = rem, goal
+            else:
+                step, trial = dd, depth + sign * dd
+            card = Card(replace(problem.material, rho=opts.visc_depth / step))
+            U1, it, ok = newton_step(problem, card, U, Eta_n, mask, zero, rtol=newton_rtol,
+                                     max_iter=opts.newton_max, depth=trial)
+            if not ok:
+                rejected += 1
+                dd = 0.5 * step
+                if dd < opts.dd_min:
+                    return records, U, False
+                continue
+            U, depth = U1, trial
+            Eta_n = U.reshape(-1, NDOF)[:, 3:].ravel().copy()
+            records.append(IndentRecord(depth, contact.load(U, depth), it, rejected))
+            rejected = 0
+            if it < opts.newton_desired:
+                dd = min(dd * opts.grow, opts.dd_max)
+            elif it > opts.newton_desired:
+                dd = max(dd * opts.shrink, opts.dd_min)
+    return records, U, True

@@ -109,8 +109,12 @@ class Problem:
     Loading kind 'patch': the top-face nodes within the centred square of
     ``patch`` x ``patch`` elements get a prescribed vertical displacement
     increment of ``-depth_increment`` per step.  Kind 'cap': spherical cap
-    profile of radius ``radius`` (see the library header).  ``n_levels`` is
-    the number of multigrid levels (each coarsening halves nx, ny, nz).
+    profile of radius ``radius`` (see the library header).  Kind 'sphere':
+    no prescribed top displacements; a rigid sphere of radius ``radius``
+    centred above the top face acts by penalty contact with parameter
+    ``eps_n`` (energy per area per squared length; the paper's 10^2 GPa/nm is
+    3.5e4 in units of a 350 nm domain width).  ``n_levels`` is the number of
+    multigrid levels (each coarsening halves nx, ny, nz).
     """
     nx: int
     ny: int
@@ -122,6 +126,7 @@ class Problem:
     kind: str = "patch"
     patch: int = 2
     radius: float = 0.2
+    eps_n: float = 3.5e4
     depth_increment: float = 0.02
     steps: int = 1
     seed: int = BASE_SEED
@@ -158,6 +163,18 @@ def scale_limit() -> Problem:
     """256x256x128 (76,682,889 dof), domain 1x1x0.5, spherical cap R=0.2, 20 steps."""
     return Problem(256, 256, 128, lz=0.5, n_levels=6, kind="cap", radius=0.2,
                    depth_increment=0.0025, steps=20)
+
+
+def indentation() -> Problem:
+    """64x64x32 hex elements (1 254 825 dof), domain 1x1x0.5, rigid sphere
+    R = 0.2 in penalty contact (eps_N = 3.5e4), 4 levels."""
+    return Problem(64, 64, 32, lz=0.5, n_levels=4, kind="sphere", radius=0.2, depth_increment=0.0025)
+
+
+# Indentation run of the workload above: load to depth 0.05 and unload at
+# v / m = 2.857e-4 GPa (the paper's v = 1 nm/s and m = 0.01 (MPa s)^-1 in
+# units of a 350 nm domain width), steps from 0.0025 within [1e-5, 0.01].
+INDENT_RUN = dict(depth_max=0.05, dd_init=0.0025, dd_min=1e-5, dd_max=0.01, visc_depth=2.857e-4)
 
 
 def random_rotation(seed: int) -> np.ndarray:
