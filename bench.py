@@ -245,6 +245,89 @@ def batched_main(a):
     print(json.dumps(out), flush=True)
 
 
+def indent_main(a):
+    """Whole indentation runs (load to 0.05, unload to 0) of the sphere-contact
+    workload with the adaptive step rule; a step here is one such run."""
+    from paper_2011_08802_amd import mvpf
+    prob = synth.indentation()
+    ndof = prob.n_dof
+    run = dict(synth.INDENT_RUN)
+    log(f"[bench] indentation workload: {prob.nx}x{prob.ny}x{prob.nz}, {ndof} dof, run {run}")
+    res = {}
+    for prec in ("mixed",) + (() if a.no_fp64 else ("fp64",)):
+        gp = mvpf.Problem(prob, prec, rtol=1e-8)
+        gp.init_random(prob.seed)
+        u0, e0, en0, _ = gp.get_state()
+        u0, e0, en0 = u0.clone(), e0.clone(), en0.clone()
+        if not a.no_tune:  # untimed: launch shapes on the first contact system
+            gp.newton_system(run["dd_init"])
+            gp.autotune()
+        timing = prec == "mixed" and not a.no_timing
+        runs = []
+        for k in range(a.warmup + a.steps):
+            gp.set_state(u0, e0, en0, 0.0)
+            if timing and k == a.warmup:
+                gp.kernel_timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            recs, rc = gp.indent(on_step=lambda r, i: log(
+                f"[indent {prec} run {k}] step {i}: depth {r.depth:.5f} load {r.load:.5f} newton "
+                f"{r.newton_iterations} fgmres {r.linear_iterations} rejected {r.rejected}"), **run)
+            torch.cuda.synchronize()
+            if k >= a.warmup:
+                runs.append((time.perf_counter() - t0, recs, rc))
+        kst = {}
+        if timing:
+            n, ms, by = gp.kernel_stats("pbj_sweep")
+            if n:
+                kst = dict(launches=n, avg_ms=ms / n, bytes=by, gbs=by / (ms / n) / 1e6)
+            gp.kernel_timing(False)
+        gp.close()
+        total = sum(r[0] for r in runs)
+        recs = runs[-1][1]
+        newton = sum(r.newton_iterations for r in recs)
+        res[prec] = dict(
+            run_s=total / len(runs), ok=all(r[2] == 0 for r in runs), accepted_steps=len(recs),
+            rejected_steps=sum(r.rejected for r in recs), newton_iterations=newton,
+            fgmres_iterations=sum(r.linear_iterations for r in recs),
+            assemble_s=sum(r.assemble_ms for r in recs) / 1e3, setup_s=sum(r.setup_ms for r in recs) / 1e3,
+            solve_s=sum(r.solve_ms for r in recs) / 1e3,
+            value=ndof * newton * len(runs) / total,
+            load_max=max(r.load for r in recs),
+            p_delta=[[round(r.depth, 6), round(r.load, 6)] for r in recs], sweep=kst)
+    ms = res["mixed"]
+    out = {
+        "metric": METRIC,
+        "value": ms["value"],
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * ms["run_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"spherical indentation {prob.nx}x{prob.ny}x{prob.nz} Q1 hex (1x1x0.5), "
+                               f"{ndof} dof, rigid sphere R={prob.radius} in penalty contact "
+                               f"(eps_N={prob.eps_n:g}), load to {run['depth_max']} and unload, adaptive "
+                               f"steps (7 desired / 12 max Newton iterations), {prob.n_levels}-level GMG "
+                               f"V(2,2), FGMRES(30) rtol 1e-8; a step = one whole run; value = dof x Newton "
+                               f"iterations per second", "precision": "mixed", **run},
+        "mixed": ms,
+    }
+    if ms["sweep"]:
+        k = ms["sweep"]
+        out["roofline"] = {"bound": "hbm", "achieved": k["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": k["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "finest-level FP32 smoother sweep (defect_upper_split + pbj_lower)",
+                           "bytes_per_launch": k["bytes"], "avg_ms": k["avg_ms"], "launches": k["launches"]}
+    if "fp64" in res:
+        out["fp64_gmg"] = res["fp64"]
+    print(json.dumps(out), flush=True)
+
+
 def sweep_traffic(prob):
     """Measured HBM bytes of one finest-level smoother sweep (pass 1 on two
     wavefronts per tile + pass 2) from the committed counter summary, for the
@@ -308,7 +391,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="medium", choices=list(WORKLOADS) + ["batched"])
+    ap.add_argument("--workload", default="medium", choices=list(WORKLOADS) + ["batched", "indent"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-multigrid comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
@@ -330,6 +413,9 @@ def main():
         del x, y
     if a.workload == "batched":
         batched_main(a)
+        return
+    if a.workload == "indent":
+        indent_main(a)
         return
     prob = WORKLOADS[a.workload]()
     ndof = prob.n_dof

@@ -50,7 +50,7 @@ enum {
 };
 
 enum { MVPF_FP64 = 0, MVPF_MIXED = 1 };          /* mvpf_opts.precision */
-enum { MVPF_LOAD_PATCH = 0, MVPF_LOAD_CAP = 1 };  /* mvpf_loading.kind */
+enum { MVPF_LOAD_PATCH = 0, MVPF_LOAD_CAP = 1, MVPF_LOAD_SPHERE = 2 };  /* mvpf_loading.kind */
 
 typedef struct mvpf_problem mvpf_problem;
 typedef struct mvpf_batch mvpf_batch;
@@ -98,17 +98,25 @@ typedef struct {
   int pade;
 } mvpf_material;
 
-/* Indentation loading (Sec. 4.1, replaced by prescribed displacements).
- * Bottom face z = 0: u = 0.  Top face z = nz*h:
+/* Indentation loading (Sec. 4.1).  Bottom face z = 0: u = 0.  Top face
+ * z = nz*h, with d = the indenter depth (mvpf_set_state, mvpf_time_step):
  *  MVPF_LOAD_PATCH  nodes of the centred patch x patch element square have
- *                   u_z = -depth (patch, nx and ny even);
+ *                   u_z = -d (patch, nx and ny even);
  *  MVPF_LOAD_CAP    nodes with r^2 < 2 R d - d^2 (r from the top-face centre,
- *                   R = radius, d = depth) have u_z = -(d - (R - sqrt(R^2-r^2))).
+ *                   R = radius) have u_z = -(d - (R - sqrt(R^2-r^2)));
+ *  MVPF_LOAD_SPHERE no prescribed top displacements: a rigid sphere of radius
+ *                   R centred at (nx h/2, ny h/2, nz h + R - d) acts by
+ *                   frictionless penalty contact on the whole top face
+ *                   (Sec. 2.4, Eqs. Ngap and PenPot): gap g = |x - c| - R
+ *                   at the current position x = X + u, energy
+ *                   int 1/2 eps_n <g>_-^2 dS by 2x2 Gauss points per face
+ *                   (eps_n > 0, energy per area per squared length).
  * All other dofs are free; order parameters have natural conditions. */
 typedef struct {
   int kind;
   int patch;
   double radius;
+  double eps_n;
 } mvpf_loading;
 
 /* Solver options.  precision MVPF_FP64: every multigrid level in FP64;
@@ -231,6 +239,61 @@ int mvpf_newton_update(mvpf_problem* p);
  * restored and the depth increment halved (at most 8 times).  On success
  * eta_hat_n <- eta_hat and the depth is advanced. */
 int mvpf_time_step(mvpf_problem* p, double depth, mvpf_step_stats* stats);
+
+/* Indentation load of the sphere-contact loading at the current state and
+ * depth: P = d/dd of the contact energy at fixed displacements,
+ * int eps_n <g>_- n_z dS (n = the sphere's outward normal at the closest
+ * point; P >= 0 while the indenter presses).  FP64, deterministic.
+ * MVPF_EINVAL for other loadings. */
+int mvpf_contact_load(mvpf_problem* p, double* load);
+
+/* Quasi-static indentation run with adaptive time steps (Sec. 3.4, Sec. 4.1):
+ * the indenter moves from the current depth to depth_max, then (unload != 0)
+ * back to 0, at constant speed v.  The time step enters through the viscous
+ * coefficient rho = 1/(m tau), tau = dd / v, so every attempted step sets
+ * rho = visc_depth / |dd| (visc_depth = v / m); the material's rho is
+ * restored at exit.  Step control: after an accepted step with n Newton
+ * iterations the next increment is multiplied by grow if n < newton_desired
+ * (7 in the paper) and by shrink if n > newton_desired, within
+ * [dd_min, dd_max]; a step not converged within newton_max iterations
+ * (mvpf_opts, 12 in the paper) is rejected, the state restored and the step
+ * retried with half the increment.  When at most dd + dd_min is left in a
+ * phase, the step goes exactly to its end. */
+typedef struct {
+  double depth_max;
+  int unload;
+  double dd_init, dd_min, dd_max;
+  double grow, shrink;
+  int newton_desired;
+  double visc_depth;
+  int max_steps;
+} mvpf_indent_opts;
+
+/* One accepted step: depth after it, indentation load there (as
+ * mvpf_contact_load), its depth increment, Newton and FGMRES iterations,
+ * rejected attempts before it, and its device times (ms). */
+typedef struct {
+  double depth, load, dd;
+  int newton_iterations, linear_iterations, rejected;
+  double assemble_ms, setup_ms, solve_ms;
+} mvpf_indent_record;
+
+/* depth_max 0.05, unload 1, dd 0.0025 in [1e-5, 0.01], grow 1.25, shrink 0.8,
+ * newton_desired 7, visc_depth 2.857e-4, max_steps 1000. */
+void mvpf_default_indent_opts(mvpf_indent_opts* o);
+
+/* Called after every accepted step with its record and index (progress
+ * reporting); runs on the calling thread. */
+typedef void (*mvpf_indent_callback)(const mvpf_indent_record* rec, int index, void* user);
+
+/* Runs the indentation; rec: caller-owned host array of max_rec >= max_steps
+ * records, *n_rec = accepted steps; on_step (nullable) with `user` after each
+ * accepted step.  MVPF_EINVAL for another loading kind or bad options
+ * (depth_max must exceed the current depth); MVPF_ENOTCONV if a step falls
+ * below dd_min or max_steps is reached (the records so far and the last
+ * accepted state are kept). */
+int mvpf_indent(mvpf_problem* p, const mvpf_indent_opts* o, mvpf_indent_callback on_step, void* user,
+                mvpf_indent_record* rec, int max_rec, int* n_rec);
 
 /* Launch-shape tuning (results are bitwise independent of it).  key
  * "row_blocks": number of 256-thread workgroups of the smoother and defect

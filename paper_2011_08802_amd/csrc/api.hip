@@ -581,6 +581,11 @@ int validate(const mvpf_mesh* mesh, const mvpf_material* mat, const mvpf_loading
     }
   } else if (load->kind == MVPF_LOAD_CAP) {
     if (!(load->radius > 0)) { err = "cap radius must be positive"; return MVPF_EINVAL; }
+  } else if (load->kind == MVPF_LOAD_SPHERE) {
+    if (!(load->radius > 0) || !(load->eps_n > 0)) {
+      err = "sphere contact needs a positive radius and eps_n";
+      return MVPF_EINVAL;
+    }
   } else {
     err = "unknown loading kind";
     return MVPF_EINVAL;
@@ -727,6 +732,8 @@ int free_norm(mvpf_problem* p, const double* v, double* out) {
 }
 
 // residual at the current state into p->R (masks of `depth` for the norm)
+bool contact(const mvpf_problem* p) { return p->load.kind == MVPF_LOAD_SPHERE; }
+
 int compute_residual(mvpf_problem* p, double depth, double* norm_free) {
   Level& L0 = p->lev[0];
   launch_dirichlet_masks(L0.g, p->load, depth, L0.mask, L0.target, p->stream);
@@ -734,18 +741,20 @@ int compute_residual(mvpf_problem* p, double depth, double* norm_free) {
     launch_qp(L0.g, ck, L0.state, p->card, p->pade, p->qp, false, p->stream);
     launch_residual_gather(L0.g, ck, L0.state, p->qp, p->card, p->R, p->stream);
   }
+  if (contact(p)) launch_contact_residual(L0.g, make_sphere(L0.g, p->load, depth), L0.state, p->R, p->stream);
   TRY(launch_check(p, "residual"));
   if (norm_free) TRY(free_norm(p, p->R, norm_free));
   return 0;
 }
 
 // reassembly of level l >= 1 at its injected state (Sec. 3.4: rediscretised
-// coarse operators); the state must already be injected
-void assemble_coarse_level(mvpf_problem* p, int l) {
+// coarse operators, contact included); the state must already be injected
+void assemble_coarse_level(mvpf_problem* p, int l, double depth) {
   Level& C = p->lev[l];
   for (const Chunk& ck : make_chunks(C.g, p->ne_use)) {
     launch_qp(C.g, ck, C.state, p->card, p->pade, p->qp, true, p->stream);
     launch_element_matrices(C.g, ck, p->qp, p->card, p->elem, p->stream);
+    if (contact(p)) launch_contact_element(C.g, ck, make_sphere(C.g, p->load, depth), C.state, p->elem, p->stream);
     launch_jacobian_gather(C.g, ck, p->elem, C.A64, C.A32, C.diag64, p->stream);
   }
   launch_apply_dirichlet(C.g, C.mask, C.A64, C.A32, C.diag64, p->stream);
@@ -770,7 +779,7 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
     launch_inject(p->lev[l - 1].g, p->lev[l].g, p->lev[l - 1].state, p->lev[l].state, s);
   }
   // coarsest level, then its inversion on the side stream
-  assemble_coarse_level(p, Lc);
+  assemble_coarse_level(p, Lc, depth);
   TRY(launch_check(p, "coarse assembly"));
   {
     Level& C = p->lev[Lc];
@@ -800,7 +809,7 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
     }
     TRY(launch_check(p, "coarse inversion"));
   }
-  for (int l = Lc - 1; l >= 1; --l) assemble_coarse_level(p, l);
+  for (int l = Lc - 1; l >= 1; --l) assemble_coarse_level(p, l, depth);
   // finest: residual and unconstrained tangent
   for (const Chunk& ck : make_chunks(L0.g, p->ne_use)) {
     timer_begin(p, p->t_qp);
@@ -809,8 +818,10 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
     timer_end(p, p->t_qp, 8.0 * 8 * 135 * (double)ck.NEc);
     launch_residual_gather(L0.g, ck, L0.state, p->qp, p->card, p->R, s);
     launch_element_matrices(L0.g, ck, p->qp, p->card, p->elem, s);
+    if (contact(p)) launch_contact_element(L0.g, ck, make_sphere(L0.g, p->load, depth), L0.state, p->elem, s);
     launch_jacobian_gather(L0.g, ck, p->elem, L0.A64, L0.A32, L0.diag64, s);
   }
+  if (contact(p)) launch_contact_residual(L0.g, make_sphere(L0.g, p->load, depth), L0.state, p->R, s);
   // lifting of the prescribed increment, then symmetric elimination
   launch_increment(L0.g, L0.mask, L0.target, L0.state, p->gvec, s);
   launch_spmv<double, double, double>(L0.g, L0.A64, p->gvec, p->tmp, p->Cbuf, s);
@@ -1341,75 +1352,234 @@ int mvpf_newton_update(mvpf_problem* p) {
   return 0;
 }
 
+}  // extern "C"
+
+namespace {
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// One implicit step to indenter depth `trial` from the current state
+// (Sec. 3.4): Newton iterations (system, solve, update) until the free-dof
+// residual is <= newton_rtol ||b_0|| (b_0 = the first right-hand side),
+// checked before each of at most newton_max solves and after the last.  A
+// non-finite residual ends the attempt.  On success eta_hat_n <- eta_hat and
+// the depth becomes `trial`; otherwise the state is restored.  Timings and
+// iteration counts accumulate into st; *its = this attempt's solves.
+int newton_attempt(mvpf_problem* p, double trial, mvpf_step_stats* st, int* its, bool* ok) {
+  Level& L0 = p->lev[0];
+  const size_t sbytes = sizeof(double) * NSTATE * L0.g.Npad;
+  EventPair ev;
+  *ok = false;
+  *its = 0;
+  const double depth0 = p->depth;  // the updates move it with the state
+  HIPCHK(hipMemcpyAsync(p->save_state, L0.state, sbytes, hipMemcpyDeviceToDevice, p->stream));
+  double b0 = 0.0;
+  for (int it = 0; it <= p->opts.newton_max; ++it) {
+    double rfree = 0.0;
+    TRY(compute_residual(p, trial, &rfree));
+    st->residual = rfree;
+    if (!std::isfinite(rfree)) break;
+    if (it > 0 && rfree <= p->opts.newton_rtol * b0) {
+      *ok = true;
+      break;
+    }
+    if (it == p->opts.newton_max) break;
+    (void)hipEventRecord(ev.a, p->stream);
+    TRY(build_system(p, trial));
+    (void)hipEventRecord(ev.b, p->stream);
+    (void)hipEventSynchronize(ev.b);
+    st->assemble_ms += elapsed_ms(ev.a, ev.b);
+    (void)hipEventRecord(ev.a, p->stream);
+    TRY(setup_solver(p));
+    (void)hipEventRecord(ev.b, p->stream);
+    (void)hipEventSynchronize(ev.b);
+    st->setup_ms += elapsed_ms(ev.a, ev.b);
+    p->sys_depth = trial;
+    p->have_system = true;
+    if (it == 0) {
+      TRY(norm_device(p, nvec(L0.g), p->rhs, &b0));
+      st->residual0 = b0;
+    }
+    mvpf_solve_stats ss;
+    const int src = solve_internal(p, p->rhs, p->dx, &ss);
+    if (src < 0) return src;
+    st->linear_iterations += ss.iterations;
+    st->solve_ms += ss.solve_ms;
+    st->newton_iterations++;
+    (*its)++;
+    p->have_solution = true;
+    TRY(mvpf_newton_update(p));
+  }
+  if (*ok) {
+    HIPCHK(hipMemcpyAsync(L0.state + (int64_t)9 * L0.g.Npad, L0.state + (int64_t)3 * L0.g.Npad,
+                          sizeof(double) * 6 * L0.g.Npad, hipMemcpyDeviceToDevice, p->stream));
+    p->depth = trial;
+  } else {
+    HIPCHK(hipMemcpyAsync(L0.state, p->save_state, sbytes, hipMemcpyDeviceToDevice, p->stream));
+    p->depth = depth0;
+  }
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->have_system = p->have_solution = false;
+  return 0;
+}
+
+// viscous coefficient rho of the material card (time-step dependent)
+int set_rho(mvpf_problem* p, double rho) {
+  p->mat.rho = rho;
+  DevCard hc;
+  build_card(p->mat, hc);
+  HIPCHK(hipStreamSynchronize(p->stream));
+  HIPCHK(hipMemcpy(p->card, &hc, sizeof(DevCard), hipMemcpyHostToDevice));
+  return 0;
+}
+
+int contact_load(mvpf_problem* p, double depth, double* P) {
+  Level& L0 = p->lev[0];
+  launch_contact_load(L0.g, make_sphere(L0.g, p->load, depth), L0.state, p->tmp, p->stream);
+  TRY(launch_check(p, "contact load"));
+  HIPCHK(hipMemcpyAsync(P, p->tmp, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
 int mvpf_time_step(mvpf_problem* p, double depth, mvpf_step_stats* stats) {
   if (!p) return MVPF_EINVAL;
   mvpf_step_stats local;
   mvpf_step_stats* st = stats ? stats : &local;
   std::memset(st, 0, sizeof(*st));
-  Level& L0 = p->lev[0];
-  const size_t sbytes = sizeof(double) * NSTATE * L0.g.Npad;
   const double goal = depth;
   double trial = depth;
-  hipEvent_t a, b;
-  HIPCHK(hipEventCreate(&a));
-  HIPCHK(hipEventCreate(&b));
-  int rc = 0;
   while (true) {
     const double cur = p->depth;
-    HIPCHK(hipMemcpyAsync(p->save_state, L0.state, sbytes, hipMemcpyDeviceToDevice, p->stream));
     bool ok = false;
-    double b0 = 0.0;
-    for (int it = 0; it <= p->opts.newton_max; ++it) {
-      double rfree = 0.0;
-      TRY(compute_residual(p, trial, &rfree));
-      st->residual = rfree;
-      if (it > 0 && rfree <= p->opts.newton_rtol * b0) { ok = true; break; }
-      if (it == p->opts.newton_max) break;
-      (void)hipEventRecord(a, p->stream);
-      TRY(build_system(p, trial));
-      (void)hipEventRecord(b, p->stream);
-      (void)hipEventSynchronize(b);
-      st->assemble_ms += elapsed_ms(a, b);
-      (void)hipEventRecord(a, p->stream);
-      TRY(setup_solver(p));
-      (void)hipEventRecord(b, p->stream);
-      (void)hipEventSynchronize(b);
-      st->setup_ms += elapsed_ms(a, b);
-      p->sys_depth = trial;
-      p->have_system = true;
-      if (it == 0) {
-        TRY(norm_device(p, nvec(L0.g), p->rhs, &b0));
-        st->residual0 = b0;
-      }
-      mvpf_solve_stats ss;
-      int src = solve_internal(p, p->rhs, p->dx, &ss);
-      if (src < 0) return src;
-      st->linear_iterations += ss.iterations;
-      st->solve_ms += ss.solve_ms;
-      st->newton_iterations++;
-      p->have_solution = true;
-      TRY(mvpf_newton_update(p));
-    }
+    int its = 0;
+    TRY(newton_attempt(p, trial, st, &its, &ok));
     if (ok) {
-      // eta_n <- eta
-      HIPCHK(hipMemcpyAsync(L0.state + (int64_t)9 * L0.g.Npad, L0.state + (int64_t)3 * L0.g.Npad,
-                            sizeof(double) * 6 * L0.g.Npad, hipMemcpyDeviceToDevice, p->stream));
-      HIPCHK(hipStreamSynchronize(p->stream));
-      p->depth = trial;
-      if (trial == goal) { st->converged = 1; break; }
+      if (trial == goal) {
+        st->converged = 1;
+        return 0;
+      }
       trial = goal;
       continue;
     }
-    HIPCHK(hipMemcpyAsync(L0.state, p->save_state, sbytes, hipMemcpyDeviceToDevice, p->stream));
-    HIPCHK(hipStreamSynchronize(p->stream));
-    p->depth = cur;
-    if (++st->halvings > 8) { rc = MVPF_ENOTCONV; p->err = "Newton failed after 8 halvings"; break; }
+    if (++st->halvings > 8) {
+      p->err = "Newton failed after 8 halvings";
+      return MVPF_ENOTCONV;
+    }
     trial = cur + 0.5 * (trial - cur);
   }
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
-  p->have_system = p->have_solution = false;
-  return rc;
+}
+
+int mvpf_contact_load(mvpf_problem* p, double* load) {
+  if (!p || !load) return MVPF_EINVAL;
+  if (!contact(p)) {
+    p->err = "the indentation load needs the sphere-contact loading";
+    return MVPF_EINVAL;
+  }
+  return contact_load(p, p->depth, load);
+}
+
+void mvpf_default_indent_opts(mvpf_indent_opts* o) {
+  if (!o) return;
+  o->depth_max = 0.05;
+  o->unload = 1;
+  o->dd_init = 0.0025;
+  o->dd_min = 1e-5;
+  o->dd_max = 0.01;
+  o->grow = 1.25;
+  o->shrink = 0.8;
+  o->newton_desired = 7;
+  o->visc_depth = 2.857e-4;
+  o->max_steps = 1000;
+}
+
+int mvpf_indent(mvpf_problem* p, const mvpf_indent_opts* o, mvpf_indent_callback on_step, void* user,
+                mvpf_indent_record* rec, int max_rec, int* n_rec) {
+  if (!p || !o || !n_rec || (max_rec > 0 && !rec)) return MVPF_EINVAL;
+  *n_rec = 0;
+  if (!contact(p)) {
+    p->err = "indentation needs the sphere-contact loading";
+    return MVPF_EINVAL;
+  }
+  if (!(o->depth_max > p->depth) || !(o->dd_min > 0) || !(o->dd_init >= o->dd_min) || !(o->dd_max >= o->dd_init) ||
+      !(o->grow >= 1.0) || !(o->shrink > 0.0 && o->shrink <= 1.0) || !(o->visc_depth > 0) || o->max_steps < 1 ||
+      max_rec < o->max_steps) {
+    p->err = "bad indentation options";
+    return MVPF_EINVAL;
+  }
+  const double rho0 = p->mat.rho;
+  double dd = o->dd_init;
+  const double goals[2] = {o->depth_max, 0.0};
+  int rc = 0, rejected = 0;
+  for (int ph = 0; ph < (o->unload ? 2 : 1) && rc == 0; ++ph) {
+    const double goal = goals[ph];
+    const double sign = goal > p->depth ? 1.0 : -1.0;
+    while (p->depth != goal) {
+      if (*n_rec >= o->max_steps) {
+        p->err = "indentation: step limit reached";
+        rc = MVPF_ENOTCONV;
+        break;
+      }
+      const double rem = std::fabs(goal - p->depth);
+      double step, trial;
+      if (rem <= dd + o->dd_min) {  // the phase's last step lands on its goal
+        step = rem;
+        trial = goal;
+      } else {
+        step = dd;
+        trial = p->depth + sign * dd;
+      }
+      if ((rc = set_rho(p, o->visc_depth / step)) != 0) break;
+      mvpf_step_stats st;
+      std::memset(&st, 0, sizeof(st));
+      bool ok = false;
+      int its = 0;
+      if ((rc = newton_attempt(p, trial, &st, &its, &ok)) != 0) break;
+      if (!ok) {
+        ++rejected;
+        dd = 0.5 * step;
+        if (dd < o->dd_min) {
+          p->err = "indentation: step below dd_min";
+          rc = MVPF_ENOTCONV;
+          break;
+        }
+        continue;
+      }
+      mvpf_indent_record& r = rec[*n_rec];
+      r.depth = p->depth;
+      if ((rc = contact_load(p, p->depth, &r.load)) != 0) break;
+      r.dd = step;
+      r.newton_iterations = its;
+      r.linear_iterations = st.linear_iterations;
+      r.rejected = rejected;
+      r.assemble_ms = st.assemble_ms;
+      r.setup_ms = st.setup_ms;
+      r.solve_ms = st.solve_ms;
+      if (on_step) on_step(&r, *n_rec, user);
+      ++*n_rec;
+      rejected = 0;
+      if (its < o->newton_desired)
+        dd = std::min(dd * o->grow, o->dd_max);
+      else if (its > o->newton_desired)
+        dd = std::max(dd * o->shrink, o->dd_min);
+    }
+  }
+  const int rr = set_rho(p, rho0);
+  return rc ? rc : rr;
 }
 
 int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value) {

@@ -72,6 +72,14 @@ struct Chunk {
 // Slabs of at most ne_cap padded elements each (one slab if the level fits).
 std::vector<Chunk> make_chunks(const Grid& g, int64_t ne_cap);
 
+// element node pair a <= b < 8 -> 0..35
+__host__ __device__ constexpr int pair_index(int a, int b) { return a * 8 - (a * (a - 1)) / 2 + (b - a); }
+
+// Rigid spherical indenter: centre (cx, cy, cz), radius R, contact penalty eps.
+struct Sphere {
+  double cx, cy, cz, R, eps;
+};
+
 // Entry layout inside a 64-lane block slice (see the file comment).
 template <typename T>
 struct Lay {
@@ -198,6 +206,13 @@ void launch_apply_dirichlet(const Grid& g, const uint16_t* mask, double* A64, fl
                             hipStream_t s);
 void launch_block_inverse(const Grid& g, const double* diag64, double* Dinv64, float* Dinv32, int* status,
                           hipStream_t s);
+// penalty contact with a rigid sphere (MVPF_LOAD_SPHERE)
+Sphere make_sphere(const Grid& g, const mvpf_loading& ld, double depth);
+void launch_contact_residual(const Grid& g, const Sphere& sp, const double* state, double* R, hipStream_t s);
+// adds the face stiffness to the element matrices if the chunk holds the top element layer
+void launch_contact_element(const Grid& g, const Chunk& ck, const Sphere& sp, const double* state, double* elem,
+                            hipStream_t s);
+void launch_contact_load(const Grid& g, const Sphere& sp, const double* state, double* out, hipStream_t s);
 // BSR products (TA = operator type, TX = vector type)
 // G: number of workgroups (0 = one per 256 rows; smaller = persistent rounds).
 // C: scratch for the transposed lower-half contributions, >= 13 * 9 * Npad

@@ -174,9 +174,6 @@ __device__ __forceinline__ int xcd_logical(int b, int nb_pad) {
   return (b & 7) * per + (b >> 3);
 }
 
-__host__ __device__ constexpr int pair_index(int a, int b) {  // a <= b < 8
-  return a * 8 - (a * (a - 1)) / 2 + (b - a);
-}
 
 // Element matrices K_e = sum_g w_g B_g^T D_g B_g + h Lap (x) Mg for the 36
 // node pairs a <= b.  A workgroup of EM_WAVES wavefronts covers 64

@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(RB) dirichlet_masks_kernel(Grid g, int kind, i
           m |= 4u;
           t = -depth;
         }
-      } else {
+      } else if (kind == MVPF_LOAD_CAP) {
         const double x = i * g.h - 0.5 * g.nx * g.h, y = j * g.h - 0.5 * g.ny * g.h;
         const double r2 = x * x + y * y;
         if (r2 < 2.0 * radius * depth - depth * depth) {

@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmvpf.so")
 
 FP64, MIXED = 0, 1
-LOAD_PATCH, LOAD_CAP = 0, 1
+LOAD_PATCH, LOAD_CAP, LOAD_SPHERE = 0, 1, 2
+_LOAD_KINDS = {"patch": LOAD_PATCH, "cap": LOAD_CAP, "sphere": LOAD_SPHERE}
 OK, ENOTCONV = 0, 1
 MAX_COARSE_DOF = 8192
 
@@ -43,7 +44,7 @@ class Material(C.Structure):
 
 
 class Loading(C.Structure):
-    _fields_ = [("kind", C.c_int), ("patch", C.c_int), ("radius", C.c_double)]
+    _fields_ = [("kind", C.c_int), ("patch", C.c_int), ("radius", C.c_double), ("eps_n", C.c_double)]
 
 
 class Opts(C.Structure):
@@ -61,6 +62,21 @@ class StepStats(C.Structure):
     _fields_ = [("newton_iterations", C.c_int), ("linear_iterations", C.c_int), ("halvings", C.c_int),
                 ("converged", C.c_int), ("residual0", C.c_double), ("residual", C.c_double),
                 ("assemble_ms", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+
+
+class IndentOpts(C.Structure):
+    _fields_ = [("depth_max", C.c_double), ("unload", C.c_int), ("dd_init", C.c_double), ("dd_min", C.c_double),
+                ("dd_max", C.c_double), ("grow", C.c_double), ("shrink", C.c_double), ("newton_desired", C.c_int),
+                ("visc_depth", C.c_double), ("max_steps", C.c_int)]
+
+
+class IndentRecord(C.Structure):
+    _fields_ = [("depth", C.c_double), ("load", C.c_double), ("dd", C.c_double), ("newton_iterations", C.c_int),
+                ("linear_iterations", C.c_int), ("rejected", C.c_int), ("assemble_ms", C.c_double),
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+
+
+IndentCallback = C.CFUNCTYPE(None, C.POINTER(IndentRecord), C.c_int, C.c_void_p)
 
 
 class Info(C.Structure):
@@ -90,6 +106,10 @@ SIGNATURES = {
     "mvpf_solve": (C.c_int, [_P, _P, _P, C.POINTER(SolveStats)]),
     "mvpf_newton_update": (C.c_int, [_P]),
     "mvpf_time_step": (C.c_int, [_P, C.c_double, C.POINTER(StepStats)]),
+    "mvpf_contact_load": (C.c_int, [_P, _D]),
+    "mvpf_default_indent_opts": (None, [C.POINTER(IndentOpts)]),
+    "mvpf_indent": (C.c_int, [_P, C.POINTER(IndentOpts), C.c_void_p, _P, C.POINTER(IndentRecord), C.c_int,
+                             C.POINTER(C.c_int)]),
     "mvpf_set_tuning": (C.c_int, [_P, C.c_char_p, C.c_int, C.c_int]),
     "mvpf_get_tuning": (C.c_int, [_P, C.c_char_p, C.c_int, C.POINTER(C.c_int)]),
     "mvpf_autotune": (C.c_int, [_P, C.POINTER(C.c_int)]),
@@ -154,7 +174,15 @@ def mesh_struct(prob) -> Mesh:
 
 
 def loading_struct(prob) -> Loading:
-    return Loading(LOAD_PATCH if prob.kind == "patch" else LOAD_CAP, prob.patch, prob.radius)
+    return Loading(_LOAD_KINDS[prob.kind], prob.patch, prob.radius, getattr(prob, "eps_n", 0.0))
+
+
+def indent_opts(**kw) -> IndentOpts:
+    o = IndentOpts()
+    load().mvpf_default_indent_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
 
 
 def opts_struct(precision: str, **opts) -> Opts:
@@ -274,6 +302,23 @@ class Problem:
         st = StepStats()
         self._check(self.lib.mvpf_time_step(self.h, depth, C.byref(st)), allow=(OK, ENOTCONV))
         return st
+
+    def contact_load(self) -> float:
+        P = C.c_double()
+        self._check(self.lib.mvpf_contact_load(self.h, C.byref(P)))
+        return P.value
+
+    def indent(self, on_step=None, **kw):
+        """mvpf_indent with mvpf_default_indent_opts overridden by ``kw``;
+        on_step(record, index) is called after every accepted step.  Returns
+        (records of the accepted steps, return code)."""
+        o = indent_opts(**kw)
+        recs = (IndentRecord * o.max_steps)()
+        n = C.c_int()
+        cb = IndentCallback(lambda r, i, u: on_step(r.contents, i)) if on_step else None
+        rc = self._check(self.lib.mvpf_indent(self.h, C.byref(o), C.cast(cb, C.c_void_p) if cb else None, None, recs,
+                                              o.max_steps, C.byref(n)), allow=(OK, ENOTCONV))
+        return list(recs[: n.value]), rc
 
     def set_tuning(self, key: str, level: int, value: int):
         self._check(self.lib.mvpf_set_tuning(self.h, key.encode(), level, value))

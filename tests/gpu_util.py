@@ -38,8 +38,9 @@ class OracleCase:
         self.U, self.En = U, En
         self.mask, self.target = S.dirichlet(self.mesh, p.kind, p.patch, p.radius, depth=depth)
         self.g = S.increment(self.mask, self.target, U)
-        self.sys = S.NewtonSystem(p, self.card, U.ravel(), En.ravel(), self.mask, self.g)
-        self.mg = S.Multigrid(p, self.card, U.ravel(), En.ravel(), self.mask, K_fine=self.sys.K) if build_mg else None
+        self.sys = S.NewtonSystem(p, self.card, U.ravel(), En.ravel(), self.mask, self.g, depth)
+        self.mg = S.Multigrid(p, self.card, U.ravel(), En.ravel(), self.mask, K_fine=self.sys.K,
+                              depth=depth) if build_mg else None
         self.x = S.direct_solve(self.sys.A, self.sys.b) if direct else None
 
 
