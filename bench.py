@@ -246,7 +246,7 @@ def batched_main(a):
 
 
 def indent_main(a):
-    """Whole indentation runs (load to 0.05, unload to 0) of the sphere-contact
+    """Whole indentation runs (load to 0.03, unload to 0) of the sphere-contact
     workload with the adaptive step rule; a step here is one such run."""
     from paper_2011_08802_amd import mvpf
     prob = synth.indentation()

@@ -171,10 +171,10 @@ def indentation() -> Problem:
     return Problem(64, 64, 32, lz=0.5, n_levels=4, kind="sphere", radius=0.2, depth_increment=0.0025)
 
 
-# Indentation run of the workload above: load to depth 0.05 and unload at
+# Indentation run of the workload above: load to depth 0.03 and unload at
 # v / m = 2.857e-4 GPa (the paper's v = 1 nm/s and m = 0.01 (MPa s)^-1 in
 # units of a 350 nm domain width), steps from 0.0005 within [1e-5, 0.005].
-INDENT_RUN = dict(depth_max=0.05, dd_init=0.0005, dd_min=1e-5, dd_max=0.005, visc_depth=2.857e-4)
+INDENT_RUN = dict(depth_max=0.03, dd_init=0.0005, dd_min=1e-5, dd_max=0.005, visc_depth=2.857e-4)
 
 
 def random_rotation(seed: int) -> np.ndarray:
