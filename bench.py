@@ -47,9 +47,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_precision(prob, precision, steps, warmup, timing, tune=True):
+def run_precision(prob, precision, steps, warmup, timing, tune=True, matrix_free=-1):
     from paper_2011_08802_amd import mvpf
     gp = mvpf.Problem(prob, precision, rtol=1e-8)
+    if matrix_free >= 0:
+        gp.set_tuning("matrix_free", 0, matrix_free)
     gp.init_random(prob.seed)
     u0, e0, en0, _ = gp.get_state()
     u0, e0, en0 = u0.clone(), e0.clone(), en0.clone()
@@ -252,10 +254,13 @@ def indent_main(a):
     prob = synth.indentation()
     ndof = prob.n_dof
     run = dict(synth.INDENT_RUN)
-    log(f"[bench] indentation workload: {prob.nx}x{prob.ny}x{prob.nz}, {ndof} dof, run {run}")
+    if a.indent_depth > 0:
+        run["depth_max"] = a.indent_depth
+    sweeps = dict(nu_pre=a.sweeps, nu_post=a.sweeps) if a.sweeps > 0 else {}
+    log(f"[bench] indentation workload: {prob.nx}x{prob.ny}x{prob.nz}, {ndof} dof, run {run}, smoother {sweeps}")
     res = {}
     for prec in ("mixed",) + (() if a.no_fp64 else ("fp64",)):
-        gp = mvpf.Problem(prob, prec, rtol=1e-8)
+        gp = mvpf.Problem(prob, prec, rtol=1e-8, **sweeps)
         gp.init_random(prob.seed)
         u0, e0, en0, _ = gp.get_state()
         u0, e0, en0 = u0.clone(), e0.clone(), en0.clone()
@@ -313,8 +318,9 @@ def indent_main(a):
                                f"{ndof} dof, rigid sphere R={prob.radius} in penalty contact "
                                f"(eps_N={prob.eps_n:g}), load to {run['depth_max']} and unload, adaptive "
                                f"steps (7 desired / 12 max Newton iterations), {prob.n_levels}-level GMG "
-                               f"V(2,2), FGMRES(30) rtol 1e-8; a step = one whole run; value = dof x Newton "
-                               f"iterations per second", "precision": "mixed", **run},
+                               f"V({a.sweeps or 2},{a.sweeps or 2}), FGMRES(30) rtol 1e-8; a step = one whole "
+                               f"run; value = dof x Newton iterations per second", "precision": "mixed",
+                   "levels": prob.n_levels, **run},
         "mixed": ms,
     }
     if ms["sweep"]:
@@ -397,6 +403,12 @@ def main():
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes (no autotuning)")
     ap.add_argument("--no-pade", action="store_true", help="skip the assembly cost per Pade order")
+    ap.add_argument("--matrix-free", type=int, default=-1,
+                    help="finest level applied from its Gauss-point Hessians (1) or assembled (0); -1: the default")
+    ap.add_argument("--sweeps", type=int, default=0,
+                    help="indentation workload: pre- and post-smoothing sweeps (default: the library's 2)")
+    ap.add_argument("--indent-depth", type=float, default=0.0,
+                    help="indentation workload: maximum depth (default: the workload's 0.03)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run an elementwise copy of this many MiB (counter calibration)")
     a = ap.parse_args()
@@ -421,11 +433,11 @@ def main():
     ndof = prob.n_dof
     log(f"[bench] workload {a.workload}: {prob.nx}x{prob.ny}x{prob.nz}, {ndof} dof, {prob.n_levels} levels")
     log("[bench] mixed (FP32 multigrid) ...")
-    mixed = run_precision(prob, "mixed", a.steps, a.warmup, not a.no_timing, not a.no_tune)
+    mixed = run_precision(prob, "mixed", a.steps, a.warmup, not a.no_timing, not a.no_tune, a.matrix_free)
     fp64 = None
     if not a.no_fp64:
         log("[bench] fp64 multigrid ...")
-        fp64 = run_precision(prob, "fp64", a.steps, a.warmup, False, not a.no_tune)
+        fp64 = run_precision(prob, "fp64", a.steps, a.warmup, False, not a.no_tune, a.matrix_free)
 
     def summary(r):
         recs = r["recs"]

@@ -292,6 +292,25 @@ double sweep_bytes(const Grid& g) {
   return sizeof(T) * (stored_blocks(g) * NBLK + (double)g.N * (NBLK + 3 * NDOF));
 }
 
+// ---- matrix-free finest level --------------------------------------------------
+bool use_mf(const mvpf_problem* p) { return p->mf && p->Dmf64; }
+bool contact(const mvpf_problem* p);
+template <typename T> const T* mfD(const mvpf_problem* p);
+template <> const float* mfD<float>(const mvpf_problem* p) { return p->Dmf32; }
+template <> const double* mfD<double>(const mvpf_problem* p) { return p->Dmf64; }
+
+// element outputs of K x on the finest level (x masked on constrained dofs
+// when masked), contact stiffness included, into Cbuf
+template <typename T, typename TX>
+void mf_elements(mvpf_problem* p, const TX* x, bool masked) {
+  Level& L0 = p->lev[0];
+  const uint16_t* mask = masked ? L0.mask : nullptr;
+  launch_mf_element<T, TX, T>(L0.g, mfD<T>(p), x, mask, p->card, (T*)p->Cbuf, p->stream);
+  if (contact(p))
+    launch_contact_apply<T, TX>(L0.g, make_sphere(L0.g, p->load, p->sys_depth), L0.state, mask, x, (T*)p->Cbuf,
+                                p->stream);
+}
+
 // ---- V-cycle ------------------------------------------------------------------
 template <typename T>
 void sweep(mvpf_problem* p, int l, bool zero) {
@@ -299,7 +318,11 @@ void sweep(mvpf_problem* p, int l, bool zero) {
   const T om = (T)p->opts.omega;
   const bool timed = (l == 0 && !zero);
   if (timed) timer_begin(p, p->t_sweep);
-  if (!zero && L.g.N <= p->small_nodes)
+  if (!zero && l == 0 && use_mf(p)) {
+    mf_elements<T, T>(p, (const T*)L.x, true);
+    launch_mf_gather<2, T, T, T>(L.g, (const T*)p->Cbuf, L.mask, (const T*)L.x, (const T*)L.b, opD<T>(L), om,
+                                 (T*)L.x2, p->stream);
+  } else if (!zero && L.g.N <= p->small_nodes)
     launch_row_small<T>(L.g, opA<T>(L), opD<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.x2, om, true, p->stream);
   else
     launch_pbj<T>(L.g, opA<T>(L), opD<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.x2, om, zero, p->Cbuf, p->stream,
@@ -323,7 +346,11 @@ void vcycle(mvpf_problem* p, int l) {
     launch_zero<T>(nvec(L.g), (T*)L.x, s);
   }
   if (l == 0 && p->timing) timer_begin(p, p->t_resid);
-  if (L.g.N <= p->small_nodes)
+  if (l == 0 && use_mf(p)) {
+    mf_elements<T, T>(p, (const T*)L.x, true);
+    launch_mf_gather<1, T, T, T>(L.g, (const T*)p->Cbuf, L.mask, (const T*)L.x, (const T*)L.b, nullptr, (T)0,
+                                 (T*)L.r, s);
+  } else if (L.g.N <= p->small_nodes)
     launch_row_small<T>(L.g, opA<T>(L), opD<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.r, (T)0, false, s);
   else
     launch_defect<T>(L.g, opA<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.r, p->Cbuf, s, p->row_G[l]);
@@ -450,7 +477,13 @@ struct Krylov {
     const Grid& g = p->lev[0].g;
     double* w = p->V + (int64_t)(j + 1) * n;
     if (p->timing) timer_begin(p, p->t_outer);
-    launch_spmv<double, TZ, double>(g, p->lev[0].A64, zj(), w, p->Cbuf, s, p->outer_G);
+    if (use_mf(p)) {
+      mf_elements<double, TZ>(p, zj(), true);
+      launch_mf_gather<0, double, TZ, double>(g, (const double*)p->Cbuf, p->lev[0].mask, zj(), nullptr, nullptr, 0.0,
+                                              w, s);
+    } else {
+      launch_spmv<double, TZ, double>(g, p->lev[0].A64, zj(), w, p->Cbuf, s, p->outer_G);
+    }
     if (p->timing)
       timer_end(p, p->t_outer, 8.0 * stored_blocks(g) * NBLK + (double)g.N * NDOF * (sizeof(TZ) + sizeof(double)));
     launch_multidot(n, p->V, n, j + 1, w, p->red, s);
@@ -504,7 +537,13 @@ struct Krylov {
     if (hipMemcpyAsync(h1(), y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s) != hipSuccess)
       return fail(MVPF_EDEVICE);
     launch_combine<TZ>(n, (const TZ*)p->Z, n, k, h1(), x, s);
-    launch_spmv<double, double, double>(g, p->lev[0].A64, x, p->tmp, p->Cbuf, s, p->outer_G);
+    if (use_mf(p)) {
+      mf_elements<double, double>(p, x, true);
+      launch_mf_gather<0, double, double, double>(g, (const double*)p->Cbuf, p->lev[0].mask, x, nullptr, nullptr,
+                                                  0.0, p->tmp, s);
+    } else {
+      launch_spmv<double, double, double>(g, p->lev[0].A64, x, p->tmp, p->Cbuf, s, p->outer_G);
+    }
     launch_axpby(n, 1.0, b, -1.0, p->tmp, p->tmp, s);
     launch_multidot(n, p->tmp, n, 1, p->tmp, p->red, s);
     launch_reduce(1, nb, p->red, p->hcol, 0, s);
@@ -610,6 +649,7 @@ void destroy_all(mvpf_problem* p) {
     dfree(L.state); dfree(L.mask); dfree(L.target); dfree(L.A64); dfree(L.A32); dfree(L.diag64);
     dfree(L.Dinv64); dfree(L.Dinv32); dfree(L.x); dfree(L.x2); dfree(L.b); dfree(L.r); dfree(L.Ainv);
   }
+  dfree(p->Dmf64); dfree(p->Dmf32);
   dfree(p->card); dfree(p->qp); dfree(p->elem); dfree(p->Cbuf); dfree(p->R); dfree(p->rhs); dfree(p->gvec); dfree(p->dx); dfree(p->tmp);
   dfree(p->tmp2); dfree(p->V); dfree(p->Z); dfree(p->red); dfree(p->hcol); dfree(p->save_state);
   if (p->side) (void)hipStreamSynchronize(p->side);
@@ -816,6 +856,7 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
     launch_qp(L0.g, ck, L0.state, p->card, p->pade, p->qp, true, s);
     // written: gradient (15) and packed Hessian (120) per Gauss point
     timer_end(p, p->t_qp, 8.0 * 8 * 135 * (double)ck.NEc);
+    if (use_mf(p)) launch_mf_pack(L0.g, ck, p->qp, p->Dmf64, p->Dmf32, s);
     launch_residual_gather(L0.g, ck, L0.state, p->qp, p->card, p->R, s);
     launch_element_matrices(L0.g, ck, p->qp, p->card, p->elem, s);
     if (contact(p)) launch_contact_element(L0.g, ck, make_sphere(L0.g, p->load, depth), L0.state, p->elem, s);
@@ -1284,13 +1325,26 @@ int mvpf_jacobian_apply(mvpf_problem* p, int level, int precision, const double*
   const Grid& g = L.g;
   hipStream_t s = p->stream;
   launch_interleaved_to_soa(g, x, 9, 0, 9, p->tmp, s);
+  const bool mf = level == 0 && use_mf(p);
   if (precision == MVPF_FP64) {
-    if (!L.A64) { p->err = "no FP64 operator on this level"; return MVPF_EINVAL; }
-    launch_spmv<double, double, double>(g, L.A64, p->tmp, p->tmp2, p->Cbuf, s);
+    if (mf) {
+      mf_elements<double, double>(p, p->tmp, true);
+      launch_mf_gather<0, double, double, double>(g, (const double*)p->Cbuf, L.mask, p->tmp, nullptr, nullptr, 0.0,
+                                                  p->tmp2, s);
+    } else {
+      if (!L.A64) { p->err = "no FP64 operator on this level"; return MVPF_EINVAL; }
+      launch_spmv<double, double, double>(g, L.A64, p->tmp, p->tmp2, p->Cbuf, s);
+    }
   } else if (precision == MVPF_MIXED) {
-    if (!L.A32) { p->err = "no FP32 operator on this level"; return MVPF_EINVAL; }
+    if (mf ? !p->Dmf32 : !L.A32) { p->err = "no FP32 operator on this level"; return MVPF_EINVAL; }
     launch_convert<double, float>(nvec(g), p->tmp, (float*)L.x, s);
-    launch_spmv<float, float, float>(g, L.A32, (const float*)L.x, (float*)L.r, p->Cbuf, s);
+    if (mf) {
+      mf_elements<float, float>(p, (const float*)L.x, true);
+      launch_mf_gather<0, float, float, float>(g, (const float*)p->Cbuf, L.mask, (const float*)L.x, nullptr, nullptr,
+                                               0.0f, (float*)L.r, s);
+    } else {
+      launch_spmv<float, float, float>(g, L.A32, (const float*)L.x, (float*)L.r, p->Cbuf, s);
+    }
     launch_convert<float, double>(nvec(g), (const float*)L.r, p->tmp2, s);
   } else {
     return MVPF_EINVAL;
@@ -1602,6 +1656,15 @@ int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value) {
       return MVPF_EINVAL;
     }
     p->ne_use = value == 0 ? p->ne_cap : value;
+  } else if (!std::strcmp(key, "matrix_free")) {
+    if (value > 1) { p->err = "matrix_free is 0 or 1"; return MVPF_EINVAL; }
+    if (value && !p->Dmf64) {
+      const Grid& g0 = p->lev[0].g;
+      TRY(dalloc(p, &p->Dmf64, mf_hessian_values(g0)));
+      if (p->opts.precision == MVPF_MIXED) TRY(dalloc(p, &p->Dmf32, mf_hessian_values(g0)));
+    }
+    p->mf = value;
+    p->have_system = p->have_solution = false;  // the finest operator must be rebuilt
   } else {
     p->err = "unknown tuning key";
     return MVPF_EINVAL;
@@ -1620,6 +1683,8 @@ int mvpf_get_tuning(const mvpf_problem* p, const char* key, int level, int* valu
     *value = p->small_nodes;
   } else if (!std::strcmp(key, "assembly_slab_elements")) {
     *value = (int)p->ne_use;
+  } else if (!std::strcmp(key, "matrix_free")) {
+    *value = p->mf;
   } else if (!std::strcmp(key, "coarse_overlap")) {
     const int nd = p->lev[p->L - 1].ndense;
     *value = p->coarse_overlap < 0 ? (nd <= COARSE_OVERLAP_MAX ? 1 : 0) : (p->coarse_overlap != 0);

@@ -75,6 +75,15 @@ std::vector<Chunk> make_chunks(const Grid& g, int64_t ne_cap);
 // element node pair a <= b < 8 -> 0..35
 __host__ __device__ constexpr int pair_index(int a, int b) { return a * 8 - (a * (a - 1)) / 2 + (b - a); }
 
+// Matrix-free finest level: Gauss-point Hessian entry k (packed upper
+// triangle, 0..119) of point g of element e, and the element-output value c
+// of node a of element e; both grouped by 8 elements so that a wavefront of
+// 8 elements x 8 points reads or writes contiguous memory.
+__host__ __device__ inline int64_t mf_index(int64_t NEpad, int k, int g, int64_t e) {
+  return ((int64_t)k * (NEpad >> 3) + (e >> 3)) * 64 + g * 8 + (e & 7);
+}
+__host__ __device__ inline int64_t eo_index(int a, int c, int64_t e) { return ((e >> 3) * 72 + a * 9 + c) * 8 + (e & 7); }
+
 // Rigid spherical indenter: centre (cx, cy, cz), radius R, contact penalty eps.
 struct Sphere {
   double cx, cy, cz, R, eps;
@@ -155,6 +164,12 @@ struct mvpf_problem {
   double* qp = nullptr;              // per-Gauss-point scratch (finest size)
   double* elem = nullptr;            // element matrices, upper node pairs (finest size)
   void* Cbuf = nullptr;              // lower-half contributions, 13 * 9 * Npad doubles (finest size)
+  // matrix-free finest level (tuning key "matrix_free"): Gauss-point Hessians
+  // in the matrix-free layout, FP64 (outer product, FP64 mode) and FP32
+  // (mixed-mode smoother); element outputs go to Cbuf
+  int mf = 0;
+  double* Dmf64 = nullptr;
+  float* Dmf32 = nullptr;
   double depth = 0.0;                // depth of the current state
   double sys_depth = 0.0;            // depth used by the last Newton system
   bool have_system = false;
@@ -213,6 +228,20 @@ void launch_contact_residual(const Grid& g, const Sphere& sp, const double* stat
 void launch_contact_element(const Grid& g, const Chunk& ck, const Sphere& sp, const double* state, double* elem,
                             hipStream_t s);
 void launch_contact_load(const Grid& g, const Sphere& sp, const double* state, double* out, hipStream_t s);
+// matrix-free contact stiffness: E (element outputs of the top layer) += K_c x
+template <typename T, typename TX>
+void launch_contact_apply(const Grid& g, const Sphere& sp, const double* state, const uint16_t* mask, const TX* x, T* E,
+                          hipStream_t s);
+// matrix-free finest level (mf.hip)
+size_t mf_hessian_values(const Grid& g);
+void launch_mf_pack(const Grid& g, const Chunk& ck, const double* qp, double* D64, float* D32, hipStream_t s);
+template <typename TD, typename TX, typename T>
+void launch_mf_element(const Grid& g, const TD* D, const TX* x, const uint16_t* mask, const DevCard* cd, T* E,
+                       hipStream_t s);
+// MODE 0: y = K x; 1: y = b - K x; 2: y = x + omega Dinv (b - K x); constrained rows act as the identity
+template <int MODE, typename T, typename TX, typename TY>
+void launch_mf_gather(const Grid& g, const T* E, const uint16_t* mask, const TX* x, const T* b, const T* Dinv, T omega,
+                      TY* y, hipStream_t s);
 // BSR products (TA = operator type, TX = vector type)
 // G: number of workgroups (0 = one per 256 rows; smaller = persistent rounds).
 // C: scratch for the transposed lower-half contributions, >= 13 * 9 * Npad

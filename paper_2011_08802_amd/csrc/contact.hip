@@ -129,6 +129,57 @@ __global__ void __launch_bounds__(256) contact_element_kernel(Grid g, Chunk ck, 
     }
 }
 
+// E += face stiffness times x for the top element layer (matrix-free
+// finest level): one thread per top element, face nodes 0..3 = element
+// corners 4..7, x masked on constrained dofs.
+template <typename T, typename TX>
+__global__ void __launch_bounds__(256) contact_apply_kernel(Grid g, Sphere s, const double* __restrict__ state,
+                                                            const uint16_t* __restrict__ mask,
+                                                            const TX* __restrict__ x, T* __restrict__ E) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= g.nx * g.ny) return;
+  const int fi = t % g.nx, fj = t / g.nx;
+  const int64_t e = (int64_t)(g.nz - 1) * g.nx * g.ny + t;
+  const double w = 0.25 * g.h * g.h * s.eps;
+  double xb[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int node = (fi + (a & 1)) + g.nnx * ((fj + (a >> 1)) + g.nny * g.nz);
+    const unsigned mb = mask ? mask[node] : 0u;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xb[a][c] = ((mb >> c) & 1) ? 0.0 : (double)x[(int64_t)c * g.Npad + node];
+  }
+  double out[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  bool any = false;
+  for (int q = 0; q < 4; ++q) {
+    FacePoint fp;
+    face_point(g, s, state, fi, fj, q, fp);
+    if (!(fp.gap < 0.0)) continue;
+    any = true;
+    const double ir = 1.0 / fp.r;
+    const double n[3] = {fp.d[0] * ir, fp.d[1] * ir, fp.d[2] * ir};
+    const double gr = fp.gap * ir;
+    double tq[3] = {0, 0, 0};
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) tq[c] += fp.N[b] * xb[b][c];
+    const double nt = n[0] * tq[0] + n[1] * tq[1] + n[2] * tq[2];
+    // A t = w [(1 - g/r) n (n . t) + g/r t]
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double at = w * ((1.0 - gr) * n[c] * nt + gr * tq[c]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) out[a][c] += fp.N[a] * at;
+    }
+  }
+  if (!any) return;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) E[eo_index(4 + a, c, e)] += (T)out[a][c];
+}
+
 // P = sum over active face points of w eps g n_z (one workgroup, fixed order)
 __global__ void __launch_bounds__(256) contact_load_kernel(Grid g, Sphere s, const double* __restrict__ state,
                                                            double* __restrict__ out) {
@@ -183,5 +234,18 @@ void launch_contact_element(const Grid& g, const Chunk& ck, const Sphere& s, con
 void launch_contact_load(const Grid& g, const Sphere& s, const double* state, double* out, hipStream_t st) {
   contact_load_kernel<<<1, 256, 0, st>>>(g, s, state, out);
 }
+
+template <typename T, typename TX>
+void launch_contact_apply(const Grid& g, const Sphere& sp, const double* state, const uint16_t* mask, const TX* x, T* E,
+                          hipStream_t st) {
+  const int n = g.nx * g.ny;
+  contact_apply_kernel<T, TX><<<(n + 255) / 256, 256, 0, st>>>(g, sp, state, mask, x, E);
+}
+template void launch_contact_apply<float, float>(const Grid&, const Sphere&, const double*, const uint16_t*,
+                                                 const float*, float*, hipStream_t);
+template void launch_contact_apply<double, float>(const Grid&, const Sphere&, const double*, const uint16_t*,
+                                                  const float*, double*, hipStream_t);
+template void launch_contact_apply<double, double>(const Grid&, const Sphere&, const double*, const uint16_t*,
+                                                   const double*, double*, hipStream_t);
 
 }  // namespace mvpf
