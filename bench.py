@@ -95,8 +95,9 @@ def run_precision(prob, precision, steps, warmup, timing, tune=True, matrix_free
     gp.set_state(u0, e0, en0, 0.0)
     gp.newton_system(depth)
     x, st = gp.solve()
+    mf = gp.get_tuning("matrix_free")
     gp.close()
-    return dict(total_s=total, recs=recs, kernels=kstats, x=x.cpu().numpy(), shapes=shapes)
+    return dict(total_s=total, recs=recs, kernels=kstats, x=x.cpu().numpy(), shapes=shapes, matrix_free=mf)
 
 
 def pade_assembly(prob, reps=5):
@@ -327,25 +328,33 @@ def indent_main(a):
         k = ms["sweep"]
         out["roofline"] = {"bound": "hbm", "achieved": k["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": k["gbs"] / HBM_PEAK_GBS, "traffic": None,
-                           "kernel": "finest-level FP32 smoother sweep (defect_upper_split + pbj_lower)",
+                           "kernel": "finest-level FP32 smoother sweep (matrix-free: mf_element + mf_gather<2>)",
                            "bytes_per_launch": k["bytes"], "avg_ms": k["avg_ms"], "launches": k["launches"]}
     if "fp64" in res:
         out["fp64_gmg"] = res["fp64"]
     print(json.dumps(out), flush=True)
 
 
-def sweep_traffic(prob):
-    """Measured HBM bytes of one finest-level smoother sweep (pass 1 on two
-    wavefronts per tile + pass 2) from the committed counter summary, for the
-    workload it was taken on (64^3), else None."""
+def sweep_traffic(prob, matrix_free):
+    """Measured HBM bytes of one finest-level smoother sweep from the committed
+    counter summary, for the workload it was taken on (64^3), else None.
+    Assembled: pass 1 on two wavefronts per tile + pass 2; matrix-free: the
+    element kernel + the gather with the Jacobi update."""
     if (prob.nx, prob.ny, prob.nz) != (64, 64, 64) or not os.path.exists(COUNTERS):
         return None
     npad = prob.n_nodes + (-prob.n_nodes) % 64
     ntiles = npad // 64
-    want = {
-        "mvpf::defect_upper_split_kernel<float>": ((ntiles + 1) // 2 + 7) // 8 * 8 * 256,
-        "mvpf::pbj_lower_kernel<float>": ((npad + 255) // 256 + 7) // 8 * 8 * 256,
-    }
+    nepad = (prob.nx * prob.ny * prob.nz + 63) // 64 * 64
+    if matrix_free:
+        want = {
+            "mvpf::mf_element_kernel<float, float, float>": nepad * 8,
+            "mvpf::mf_gather_kernel<2, float, float, float>": (npad + 255) // 256 * 256,
+        }
+    else:
+        want = {
+            "mvpf::defect_upper_split_kernel<float>": ((ntiles + 1) // 2 + 7) // 8 * 8 * 256,
+            "mvpf::pbj_lower_kernel<float>": ((npad + 255) // 256 + 7) // 8 * 8 * 256,
+        }
     total = 0.0
     found = set()
     with open(COUNTERS) as f:
@@ -451,6 +460,7 @@ def main():
 
     ms = summary(mixed)
     ms["launch_shapes"] = mixed["shapes"]
+    ms["matrix_free"] = mixed["matrix_free"]
     out = {
         "metric": METRIC,
         "value": ndof * a.steps / mixed["total_s"],
@@ -482,9 +492,12 @@ def main():
             np.linalg.norm(mixed["x"] - fp64["x"]) / np.linalg.norm(fp64["x"]))
     k = mixed["kernels"].get("pbj_sweep")
     if k:
+        mf = mixed["matrix_free"]
         out["roofline"] = {"bound": "hbm", "achieved": k["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": k["gbs"] / HBM_PEAK_GBS, "traffic": sweep_traffic(prob),
-                           "kernel": "finest-level FP32 smoother sweep (defect_upper_split + pbj_lower)",
+                           "frac": k["gbs"] / HBM_PEAK_GBS, "traffic": sweep_traffic(prob, mf),
+                           "kernel": "finest-level FP32 smoother sweep "
+                                     + ("(matrix-free: mf_element + mf_gather<2>)" if mf
+                                        else "(defect_upper_split + pbj_lower)"),
                            "bytes_per_launch": k["bytes"], "avg_ms": k["avg_ms"], "launches": k["launches"]}
         out["kernels"] = mixed["kernels"]
     if not a.no_pade and a.workload in ("tiny", "medium"):

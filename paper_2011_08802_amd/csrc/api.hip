@@ -286,10 +286,14 @@ double stencil_blocks(const Grid& g) {
 }
 double stored_blocks(const Grid& g) { return 0.5 * (stencil_blocks(g) + g.N); }
 
-// Algorithmic bytes of one damped point-block Jacobi sweep on level g.
+// Algorithmic bytes of one damped point-block Jacobi sweep on level g:
+// the operator (stored half-stencil blocks, or on a matrix-free level the
+// 8 x 120 Gauss-point Hessian values per element), the block inverses, x, b
+// and the new x.
 template <typename T>
-double sweep_bytes(const Grid& g) {
-  return sizeof(T) * (stored_blocks(g) * NBLK + (double)g.N * (NBLK + 3 * NDOF));
+double sweep_bytes(const Grid& g, bool mf) {
+  const double op = mf ? 960.0 * g.NE : stored_blocks(g) * NBLK;
+  return sizeof(T) * (op + (double)g.N * (NBLK + 3 * NDOF));
 }
 
 // ---- matrix-free finest level --------------------------------------------------
@@ -300,15 +304,14 @@ template <> const float* mfD<float>(const mvpf_problem* p) { return p->Dmf32; }
 template <> const double* mfD<double>(const mvpf_problem* p) { return p->Dmf64; }
 
 // element outputs of K x on the finest level (x masked on constrained dofs
-// when masked), contact stiffness included, into Cbuf
+// when masked), contact stiffness included (indenter of the last
+// build_system), into Cbuf
 template <typename T, typename TX>
 void mf_elements(mvpf_problem* p, const TX* x, bool masked) {
   Level& L0 = p->lev[0];
   const uint16_t* mask = masked ? L0.mask : nullptr;
   launch_mf_element<T, TX, T>(L0.g, mfD<T>(p), x, mask, p->card, (T*)p->Cbuf, p->stream);
-  if (contact(p))
-    launch_contact_apply<T, TX>(L0.g, make_sphere(L0.g, p->load, p->sys_depth), L0.state, mask, x, (T*)p->Cbuf,
-                                p->stream);
+  if (contact(p)) launch_contact_apply<T, TX>(L0.g, p->sphere, L0.state, mask, x, (T*)p->Cbuf, p->stream);
 }
 
 // ---- V-cycle ------------------------------------------------------------------
@@ -327,7 +330,7 @@ void sweep(mvpf_problem* p, int l, bool zero) {
   else
     launch_pbj<T>(L.g, opA<T>(L), opD<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.x2, om, zero, p->Cbuf, p->stream,
                   p->row_G[l]);
-  if (timed) timer_end(p, p->t_sweep, sweep_bytes<T>(L.g));
+  if (timed) timer_end(p, p->t_sweep, sweep_bytes<T>(L.g, use_mf(p)));
   std::swap(L.x, L.x2);
 }
 
@@ -355,7 +358,8 @@ void vcycle(mvpf_problem* p, int l) {
   else
     launch_defect<T>(L.g, opA<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.r, p->Cbuf, s, p->row_G[l]);
   if (l == 0 && p->timing)
-    timer_end(p, p->t_resid, sizeof(T) * (stored_blocks(L.g) * NBLK + (double)L.g.N * 3 * NDOF));
+    timer_end(p, p->t_resid,
+              sizeof(T) * ((use_mf(p) ? 960.0 * L.g.NE : stored_blocks(L.g) * NBLK) + (double)L.g.N * 3 * NDOF));
   Level& C = p->lev[l + 1];
   launch_restrict<T>(L.g, C.g, (const T*)L.r, C.mask, (T*)C.b, s);
   vcycle<T>(p, l + 1);
@@ -485,7 +489,8 @@ struct Krylov {
       launch_spmv<double, TZ, double>(g, p->lev[0].A64, zj(), w, p->Cbuf, s, p->outer_G);
     }
     if (p->timing)
-      timer_end(p, p->t_outer, 8.0 * stored_blocks(g) * NBLK + (double)g.N * NDOF * (sizeof(TZ) + sizeof(double)));
+      timer_end(p, p->t_outer, 8.0 * (use_mf(p) ? 960.0 * g.NE : stored_blocks(g) * NBLK) +
+                                   (double)g.N * NDOF * (sizeof(TZ) + sizeof(double)));
     launch_multidot(n, p->V, n, j + 1, w, p->red, s);
     launch_reduce(j + 1, nb, p->red, h1(), 0, s);
     launch_multiaxpy(n, p->V, n, j + 1, h1(), w, nullptr, s);
@@ -649,7 +654,7 @@ void destroy_all(mvpf_problem* p) {
     dfree(L.state); dfree(L.mask); dfree(L.target); dfree(L.A64); dfree(L.A32); dfree(L.diag64);
     dfree(L.Dinv64); dfree(L.Dinv32); dfree(L.x); dfree(L.x2); dfree(L.b); dfree(L.r); dfree(L.Ainv);
   }
-  dfree(p->Dmf64); dfree(p->Dmf32);
+  dfree(p->Dmf64); dfree(p->Dmf32); dfree(p->sphere);
   dfree(p->card); dfree(p->qp); dfree(p->elem); dfree(p->Cbuf); dfree(p->R); dfree(p->rhs); dfree(p->gvec); dfree(p->dx); dfree(p->tmp);
   dfree(p->tmp2); dfree(p->V); dfree(p->Z); dfree(p->red); dfree(p->hcol); dfree(p->save_state);
   if (p->side) (void)hipStreamSynchronize(p->side);
@@ -669,6 +674,7 @@ int allocate(mvpf_problem* p) {
   const mvpf_mesh& M = p->mesh;
   p->L = M.n_levels;
   p->mixed = p->opts.precision == MVPF_MIXED;
+  p->mf = p->mf && p->L > 1;  // a one-level problem is solved densely
   for (int l = 0; l < p->L; ++l) {
     const int f = 1 << l;
     Level& L = p->lev[l];
@@ -682,8 +688,13 @@ int allocate(mvpf_problem* p) {
     TRY(dalloc(p, &L.state, (size_t)NSTATE * L.g.Npad));
     TRY(dalloc(p, &L.mask, (size_t)L.g.Npad));
     if (l == 0) TRY(dalloc(p, &L.target, (size_t)L.g.Npad));
-    if (l == 0 || !p->mixed || coarsest) TRY(dalloc(p, &L.A64, (size_t)nA64));
-    if (p->mixed && !coarsest) TRY(dalloc(p, &L.A32, (size_t)nA32));
+    const bool mf0 = l == 0 && p->mf;  // matrix-free finest level: no stored blocks
+    if (!mf0 && (l == 0 || !p->mixed || coarsest)) TRY(dalloc(p, &L.A64, (size_t)nA64));
+    if (!mf0 && p->mixed && !coarsest) TRY(dalloc(p, &L.A32, (size_t)nA32));
+    if (mf0) {
+      TRY(dalloc(p, &p->Dmf64, mf_hessian_values(L.g)));
+      if (p->mixed) TRY(dalloc(p, &p->Dmf32, mf_hessian_values(L.g)));
+    }
     if (!coarsest) {
       TRY(dalloc(p, &L.diag64, (size_t)nD64));
       if (p->mixed)
@@ -705,6 +716,7 @@ int allocate(mvpf_problem* p) {
   const Grid& g0 = p->lev[0].g;
   const int64_t n = nvec(g0);
   TRY(dalloc(p, &p->card, 1));
+  if (p->load.kind == MVPF_LOAD_SPHERE) TRY(dalloc(p, &p->sphere, 1));
   {
     // Gauss-point and element-matrix buffers: the whole finest level if that
     // fits ASSEMBLY_FULL_MAX bytes, else slabs of ASSEMBLY_SLAB_BYTES
@@ -856,16 +868,27 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
     launch_qp(L0.g, ck, L0.state, p->card, p->pade, p->qp, true, s);
     // written: gradient (15) and packed Hessian (120) per Gauss point
     timer_end(p, p->t_qp, 8.0 * 8 * 135 * (double)ck.NEc);
-    if (use_mf(p)) launch_mf_pack(L0.g, ck, p->qp, p->Dmf64, p->Dmf32, s);
+    const bool mf = use_mf(p);  // only the diagonal blocks are assembled
+    if (mf) launch_mf_pack(L0.g, ck, p->qp, p->Dmf64, p->Dmf32, s);
     launch_residual_gather(L0.g, ck, L0.state, p->qp, p->card, p->R, s);
-    launch_element_matrices(L0.g, ck, p->qp, p->card, p->elem, s);
-    if (contact(p)) launch_contact_element(L0.g, ck, make_sphere(L0.g, p->load, depth), L0.state, p->elem, s);
-    launch_jacobian_gather(L0.g, ck, p->elem, L0.A64, L0.A32, L0.diag64, s);
+    launch_element_matrices(L0.g, ck, p->qp, p->card, p->elem, s, mf);
+    if (contact(p)) launch_contact_element(L0.g, ck, make_sphere(L0.g, p->load, depth), L0.state, p->elem, s, mf);
+    launch_jacobian_gather(L0.g, ck, p->elem, L0.A64, L0.A32, L0.diag64, s, mf);
   }
-  if (contact(p)) launch_contact_residual(L0.g, make_sphere(L0.g, p->load, depth), L0.state, p->R, s);
+  if (contact(p)) {
+    launch_contact_residual(L0.g, make_sphere(L0.g, p->load, depth), L0.state, p->R, s);
+    const Sphere sp = make_sphere(L0.g, p->load, depth);
+    HIPCHK(hipMemcpyAsync(p->sphere, &sp, sizeof(Sphere), hipMemcpyHostToDevice, s));
+  }
   // lifting of the prescribed increment, then symmetric elimination
   launch_increment(L0.g, L0.mask, L0.target, L0.state, p->gvec, s);
-  launch_spmv<double, double, double>(L0.g, L0.A64, p->gvec, p->tmp, p->Cbuf, s);
+  if (use_mf(p)) {
+    mf_elements<double, double>(p, p->gvec, false);
+    launch_mf_gather<0, double, double, double>(L0.g, (const double*)p->Cbuf, nullptr, p->gvec, nullptr, nullptr,
+                                                0.0, p->tmp, s);
+  } else {
+    launch_spmv<double, double, double>(L0.g, L0.A64, p->gvec, p->tmp, p->Cbuf, s);
+  }
   launch_newton_rhs(L0.g, L0.mask, p->R, p->tmp, p->gvec, p->rhs, s);
   launch_apply_dirichlet(L0.g, L0.mask, L0.A64, L0.A32, L0.diag64, s);
   TRY(launch_check(p, "assembly"));
@@ -963,6 +986,7 @@ void autotune_levels(mvpf_problem* p, int* tuned) {
   for (int l = 0; l < p->L - 1; ++l) {
     Level& L = p->lev[l];
     if (L.g.N <= p->small_nodes) continue;  // small-grid kernels have a fixed shape
+    if (l == 0 && use_mf(p)) continue;      // matrix-free kernels have a fixed shape
     double best = 1e30;
     int bestG = 0;
     for (int G : launch_candidates(L.g)) {
@@ -976,6 +1000,7 @@ void autotune_levels(mvpf_problem* p, int* tuned) {
     tuned[l] = bestG;
   }
   const Grid& g = p->lev[0].g;
+  if (use_mf(p)) return;
   double best = 1e30;
   int bestG = 0;
   for (int G : launch_candidates(g)) {
@@ -1657,11 +1682,15 @@ int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value) {
     }
     p->ne_use = value == 0 ? p->ne_cap : value;
   } else if (!std::strcmp(key, "matrix_free")) {
-    if (value > 1) { p->err = "matrix_free is 0 or 1"; return MVPF_EINVAL; }
+    if (value > 1 || (value && p->L < 2)) { p->err = "matrix_free is 0 or 1 (and needs two levels)"; return MVPF_EINVAL; }
+    Level& L0 = p->lev[0];
     if (value && !p->Dmf64) {
-      const Grid& g0 = p->lev[0].g;
-      TRY(dalloc(p, &p->Dmf64, mf_hessian_values(g0)));
-      if (p->opts.precision == MVPF_MIXED) TRY(dalloc(p, &p->Dmf32, mf_hessian_values(g0)));
+      TRY(dalloc(p, &p->Dmf64, mf_hessian_values(L0.g)));
+      if (p->mixed) TRY(dalloc(p, &p->Dmf32, mf_hessian_values(L0.g)));
+    }
+    if (!value && !L0.A64) {  // the stored finest operator, on first use
+      TRY(dalloc(p, &L0.A64, (size_t)L0.g.ntiles * NUP * Lay<double>::SLICE));
+      if (p->mixed) TRY(dalloc(p, &L0.A32, (size_t)L0.g.ntiles * NUP * Lay<float>::SLICE));
     }
     p->mf = value;
     p->have_system = p->have_solution = false;  // the finest operator must be rebuilt

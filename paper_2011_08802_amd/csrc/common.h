@@ -76,11 +76,15 @@ std::vector<Chunk> make_chunks(const Grid& g, int64_t ne_cap);
 __host__ __device__ constexpr int pair_index(int a, int b) { return a * 8 - (a * (a - 1)) / 2 + (b - a); }
 
 // Matrix-free finest level: Gauss-point Hessian entry k (packed upper
-// triangle, 0..119) of point g of element e, and the element-output value c
-// of node a of element e; both grouped by 8 elements so that a wavefront of
-// 8 elements x 8 points reads or writes contiguous memory.
+// triangle, 0..119) of point g of element e in storage type T, and the
+// element-output value c of node a of element e.  Hessian entries come in
+// groups of V = 16 / sizeof(T) per lane (one 16-byte load) and 64 lanes
+// (8 elements x 8 points) per group, so a wavefront reads 1 KB contiguous;
+// element outputs are grouped by 8 elements.
+template <typename T>
 __host__ __device__ inline int64_t mf_index(int64_t NEpad, int k, int g, int64_t e) {
-  return ((int64_t)k * (NEpad >> 3) + (e >> 3)) * 64 + g * 8 + (e & 7);
+  constexpr int V = 16 / (int)sizeof(T);
+  return (((int64_t)(k / V) * (NEpad >> 3) + (e >> 3)) * 64 + g * 8 + (e & 7)) * V + k % V;
 }
 __host__ __device__ inline int64_t eo_index(int a, int c, int64_t e) { return ((e >> 3) * 72 + a * 9 + c) * 8 + (e & 7); }
 
@@ -167,9 +171,10 @@ struct mvpf_problem {
   // matrix-free finest level (tuning key "matrix_free"): Gauss-point Hessians
   // in the matrix-free layout, FP64 (outer product, FP64 mode) and FP32
   // (mixed-mode smoother); element outputs go to Cbuf
-  int mf = 0;
+  int mf = 1;
   double* Dmf64 = nullptr;
   float* Dmf32 = nullptr;
+  mvpf::Sphere* sphere = nullptr;    // the indenter of the current system (device), sphere contact only
   double depth = 0.0;                // depth of the current state
   double sys_depth = 0.0;            // depth used by the last Newton system
   bool have_system = false;
@@ -213,10 +218,12 @@ void launch_qp(const Grid& g, const Chunk& ck, const double* state, const DevCar
                bool hess, hipStream_t s);
 void launch_residual_gather(const Grid& g, const Chunk& ck, const double* state, const double* qp, const DevCard* cd,
                             double* R, hipStream_t s);
+// diag_only: only the 8 diagonal node pairs / the diagonal blocks (the
+// matrix-free finest level needs nothing else)
 void launch_element_matrices(const Grid& g, const Chunk& ck, const double* qp, const DevCard* cd, double* elem,
-                             hipStream_t s);
+                             hipStream_t s, bool diag_only = false);
 void launch_jacobian_gather(const Grid& g, const Chunk& ck, const double* elem, double* A64, float* A32, double* diag64,
-                            hipStream_t s);
+                            hipStream_t s, bool diag_only = false);
 void launch_apply_dirichlet(const Grid& g, const uint16_t* mask, double* A64, float* A32, double* diag64,
                             hipStream_t s);
 void launch_block_inverse(const Grid& g, const double* diag64, double* Dinv64, float* Dinv32, int* status,
@@ -224,13 +231,15 @@ void launch_block_inverse(const Grid& g, const double* diag64, double* Dinv64, f
 // penalty contact with a rigid sphere (MVPF_LOAD_SPHERE)
 Sphere make_sphere(const Grid& g, const mvpf_loading& ld, double depth);
 void launch_contact_residual(const Grid& g, const Sphere& sp, const double* state, double* R, hipStream_t s);
-// adds the face stiffness to the element matrices if the chunk holds the top element layer
+// adds the face stiffness to the element matrices if the chunk holds the top
+// element layer (diagonal node pairs only when diag_only)
 void launch_contact_element(const Grid& g, const Chunk& ck, const Sphere& sp, const double* state, double* elem,
-                            hipStream_t s);
+                            hipStream_t s, bool diag_only = false);
 void launch_contact_load(const Grid& g, const Sphere& sp, const double* state, double* out, hipStream_t s);
-// matrix-free contact stiffness: E (element outputs of the top layer) += K_c x
+// matrix-free contact stiffness: E (element outputs of the top layer) += K_c x;
+// sp: the indenter in device memory
 template <typename T, typename TX>
-void launch_contact_apply(const Grid& g, const Sphere& sp, const double* state, const uint16_t* mask, const TX* x, T* E,
+void launch_contact_apply(const Grid& g, const Sphere* sp, const double* state, const uint16_t* mask, const TX* x, T* E,
                           hipStream_t s);
 // matrix-free finest level (mf.hip)
 size_t mf_hessian_values(const Grid& g);

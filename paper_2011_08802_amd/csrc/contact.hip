@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(256) contact_residual_kernel(Grid g, Sphere s,
 // top element; element-local nodes 4..7 are the face's nodes 0..3).
 __global__ void __launch_bounds__(256) contact_element_kernel(Grid g, Chunk ck, Sphere s,
                                                               const double* __restrict__ state,
-                                                              double* __restrict__ E) {
+                                                              double* __restrict__ E, bool diag_only) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= g.nx * g.ny) return;
   const int fi = t % g.nx, fj = t / g.nx;
@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(256) contact_element_kernel(Grid g, Chunk ck, 
   }
   if (!any) return;
   for (int a = 0; a < 4; ++a)
-    for (int b = a; b < 4; ++b) {
+    for (int b = a; b < (diag_only ? a + 1 : 4); ++b) {
       double K[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -131,13 +131,16 @@ __global__ void __launch_bounds__(256) contact_element_kernel(Grid g, Chunk ck, 
 
 // E += face stiffness times x for the top element layer (matrix-free
 // finest level): one thread per top element, face nodes 0..3 = element
-// corners 4..7, x masked on constrained dofs.
+// corners 4..7, x masked on constrained dofs.  The indenter is read from
+// device memory, so a captured graph follows its depth.
 template <typename T, typename TX>
-__global__ void __launch_bounds__(256) contact_apply_kernel(Grid g, Sphere s, const double* __restrict__ state,
+__global__ void __launch_bounds__(256) contact_apply_kernel(Grid g, const Sphere* __restrict__ sp,
+                                                            const double* __restrict__ state,
                                                             const uint16_t* __restrict__ mask,
                                                             const TX* __restrict__ x, T* __restrict__ E) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= g.nx * g.ny) return;
+  const Sphere s = *sp;
   const int fi = t % g.nx, fj = t / g.nx;
   const int64_t e = (int64_t)(g.nz - 1) * g.nx * g.ny + t;
   const double w = 0.25 * g.h * g.h * s.eps;
@@ -225,10 +228,10 @@ bool chunk_has_top_layer(const Grid& g, const Chunk& ck) {
 }
 
 void launch_contact_element(const Grid& g, const Chunk& ck, const Sphere& s, const double* state, double* elem,
-                            hipStream_t st) {
+                            hipStream_t st, bool diag_only) {
   if (!chunk_has_top_layer(g, ck)) return;
   const int n = g.nx * g.ny;
-  contact_element_kernel<<<(n + 255) / 256, 256, 0, st>>>(g, ck, s, state, elem);
+  contact_element_kernel<<<(n + 255) / 256, 256, 0, st>>>(g, ck, s, state, elem, diag_only);
 }
 
 void launch_contact_load(const Grid& g, const Sphere& s, const double* state, double* out, hipStream_t st) {
@@ -236,16 +239,16 @@ void launch_contact_load(const Grid& g, const Sphere& s, const double* state, do
 }
 
 template <typename T, typename TX>
-void launch_contact_apply(const Grid& g, const Sphere& sp, const double* state, const uint16_t* mask, const TX* x, T* E,
+void launch_contact_apply(const Grid& g, const Sphere* sp, const double* state, const uint16_t* mask, const TX* x, T* E,
                           hipStream_t st) {
   const int n = g.nx * g.ny;
   contact_apply_kernel<T, TX><<<(n + 255) / 256, 256, 0, st>>>(g, sp, state, mask, x, E);
 }
-template void launch_contact_apply<float, float>(const Grid&, const Sphere&, const double*, const uint16_t*,
+template void launch_contact_apply<float, float>(const Grid&, const Sphere*, const double*, const uint16_t*,
                                                  const float*, float*, hipStream_t);
-template void launch_contact_apply<double, float>(const Grid&, const Sphere&, const double*, const uint16_t*,
+template void launch_contact_apply<double, float>(const Grid&, const Sphere*, const double*, const uint16_t*,
                                                   const float*, double*, hipStream_t);
-template void launch_contact_apply<double, double>(const Grid&, const Sphere&, const double*, const uint16_t*,
+template void launch_contact_apply<double, double>(const Grid&, const Sphere*, const double*, const uint16_t*,
                                                    const double*, double*, hipStream_t);
 
 }  // namespace mvpf

@@ -24,8 +24,6 @@
 
 namespace mvpf {
 
-namespace {
-
 constexpr double MGQ0 = 0.21132486540518711775;  // (1 - 1/sqrt 3) / 2
 constexpr double MGQ1 = 0.78867513459481288225;
 
@@ -82,7 +80,8 @@ __global__ void __launch_bounds__(256) mf_element_kernel(Grid g, const TD* __res
       const T dN[3] = {df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]};
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
-        const T xv = ((mb >> c) & 1) ? (T)0 : (T)x[(int64_t)c * g.Npad + node];
+        const T xl = (T)x[(int64_t)c * g.Npad + node];  // unconditional load, then select
+        const T xv = ((mb >> c) & 1) ? (T)0 : xl;
         if (c < 3) {
 #pragma unroll
           for (int j = 0; j < 3; ++j) v[3 * c + j] += dN[j] * xv;
@@ -94,18 +93,25 @@ __global__ void __launch_bounds__(256) mf_element_kernel(Grid g, const TD* __res
       }
     }
   }
-  // w = D v (packed upper triangle, row-major p <= q)
+  // w = D v (packed upper triangle, row-major p <= q), 16-byte loads
   T w[15];
 #pragma unroll
   for (int k = 0; k < 15; ++k) w[k] = 0;
   if (active) {
-    const TD* Dp = D + ((e >> 3) * 64 + gp * 8 + (e & 7));
+    using VT = typename Vec16<TD>::type;
+    constexpr int V = 16 / (int)sizeof(TD);
+    const VT* Dp = reinterpret_cast<const VT*>(D) + ((e >> 3) * 64 + gp * 8 + (e & 7));
     const int64_t ks = (int64_t)(g.NEpad >> 3) * 64;
+    TD dv[V];
 #pragma unroll
-    for (int pq = 0, p = 0; p < 15; ++p)
+    for (int p = 0, k = 0; p < 15; ++p)
 #pragma unroll
-      for (int q = p; q < 15; ++q, ++pq) {
-        const T d = (T)Dp[pq * ks];
+      for (int q = p; q < 15; ++q, ++k) {
+        if (k % V == 0) {
+          const VT vq = Dp[(k / V) * ks];
+          __builtin_memcpy(dv, &vq, sizeof(VT));
+        }
+        const T d = (T)dv[k % V];
         w[p] += d * v[q];
         if (q != p) w[q] += d * v[p];
       }
@@ -215,13 +221,10 @@ __global__ void __launch_bounds__(256) mf_pack_kernel(Grid g, Chunk ck, const do
   const double* src = qp + (int64_t)15 * stride + (int64_t)gp * ck.NEcpad + el;
   for (int k = 0; k < 120; ++k) {
     const double d = src[(int64_t)k * stride];
-    const int64_t o = mf_index(g.NEpad, k, gp, e);
-    if (D64) D64[o] = d;
-    if (D32) D32[o] = (float)d;
+    if (D64) D64[mf_index<double>(g.NEpad, k, gp, e)] = d;
+    if (D32) D32[mf_index<float>(g.NEpad, k, gp, e)] = (float)d;
   }
 }
-
-}  // namespace
 
 size_t mf_hessian_values(const Grid& g) { return (size_t)120 * 8 * g.NEpad; }
 

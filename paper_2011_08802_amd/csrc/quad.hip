@@ -184,24 +184,31 @@ __device__ __forceinline__ int xcd_logical(int b, int nb_pad) {
 // accumulators in registers (no spills).
 constexpr int EM_WAVES = 4;
 
+// npair = NPAIR: all 36 pairs; npair = 8: the diagonal pairs (a, a) only.
 __global__ void __launch_bounds__(EM_WAVES * 64, 2) element_matrix_kernel(Grid g, Chunk ck,
                                                                           const double* __restrict__ qp,
                                                                           const DevCard* __restrict__ cd,
-                                                                          double* __restrict__ E) {
+                                                                          double* __restrict__ E, int npair) {
   __shared__ double Ds[120 * 64];
   // the NPAIR / EM_WAVES pair chunks of one element group are consecutive
   // logical blocks on one XCD, so the group's Hessians are read from HBM once
   // and then hit that XCD's L2
   const int groups = ck.NEcpad / 64;
+  const int chunks = npair / EM_WAVES;
   const int Lb = xcd_logical(blockIdx.x, gridDim.x);
-  if (Lb >= groups * (NPAIR / EM_WAVES)) return;  // uniform; before any barrier
-  const int eg = Lb / (NPAIR / EM_WAVES);
-  const int pc = Lb % (NPAIR / EM_WAVES);  // pair chunk
+  if (Lb >= groups * chunks) return;  // uniform; before any barrier
+  const int eg = Lb / chunks;
+  const int pc = Lb % chunks;  // pair chunk
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int p = pc * EM_WAVES + w;     // pair 0..35
-  int a = 0, rem = p;
-  while (rem >= 8 - a) { rem -= 8 - a; ++a; }
-  const int b = a + rem;
+  int a = 0, b = 0;
+  if (npair == NPAIR) {
+    int rem = pc * EM_WAVES + w;  // pair 0..35
+    while (rem >= 8 - a) { rem -= 8 - a; ++a; }
+    b = a + rem;
+  } else {
+    a = b = pc * EM_WAVES + w;
+  }
+  const int p = pair_index(a, b);
   const int e = eg * 64 + l;
   const double cuu = g.h * 0.125, cue = g.h * g.h * 0.125, cee = g.h * g.h * g.h * 0.125;
   const int64_t stride = (int64_t)8 * ck.NEcpad;
@@ -277,22 +284,24 @@ __global__ void __launch_bounds__(EM_WAVES * 64, 2) element_matrix_kernel(Grid g
 }
 
 void launch_element_matrices(const Grid& g, const Chunk& ck, const double* qp, const DevCard* cd, double* elem,
-                             hipStream_t s) {
+                             hipStream_t s, bool diag_only) {
   const int groups = ck.NEcpad / 64;
-  const int nb = groups * (NPAIR / EM_WAVES);
-  element_matrix_kernel<<<(nb + 7) / 8 * 8, EM_WAVES * 64, 0, s>>>(g, ck, qp, cd, elem);
+  const int npair = diag_only ? 8 : NPAIR;
+  const int nb = groups * (npair / EM_WAVES);
+  element_matrix_kernel<<<(nb + 7) / 8 * 8, EM_WAVES * 64, 0, s>>>(g, ck, qp, cd, elem, npair);
 }
 
 // Stored block (n, n + off(13 + u)) = sum over the <= 8 elements containing
 // both nodes of their element blocks, in a fixed order (bitwise reproducible).
 // One wavefront per (tile, u): 64 consecutive rows, coalesced element reads
 // and coalesced tiled writes.
+// nup = NUP: every stored block; nup = 1: the diagonal blocks only.
 __global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, Chunk ck, const double* __restrict__ E,
                                                              double* __restrict__ A64, float* __restrict__ A32,
-                                                             double* __restrict__ diag64, int nblocks) {
+                                                             double* __restrict__ diag64, int nblocks, int nup) {
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= nblocks) return;
-  const int t = ck.n0 / TILE + L / NUP, u = L % NUP;
+  const int t = ck.n0 / TILE + L / nup, u = L % nup;
   const int sten = 13 + u;
   const int l = threadIdx.x;
   const int n = t * TILE + l;
@@ -347,11 +356,13 @@ __global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, Chunk ck, c
 }
 
 void launch_jacobian_gather(const Grid& g, const Chunk& ck, const double* elem, double* A64, float* A32,
-                            double* diag64, hipStream_t s) {
+                            double* diag64, hipStream_t s, bool diag_only) {
   const int t0 = ck.n0 / TILE, t1 = (ck.n1 + TILE - 1) / TILE;
-  const int nblocks = (t1 - t0) * NUP;
+  const int nup = diag_only ? 1 : NUP;
+  const int nblocks = (t1 - t0) * nup;
   const int nb_pad = (nblocks + 7) / 8 * 8;
-  jacobian_gather_kernel<<<nb_pad, TILE, 0, s>>>(g, ck, elem, A64, A32, diag64, nblocks);
+  jacobian_gather_kernel<<<nb_pad, TILE, 0, s>>>(g, ck, elem, diag_only ? nullptr : A64, diag_only ? nullptr : A32,
+                                                 diag64, nblocks, nup);
 }
 
 // Symmetric elimination on the stored blocks: entries in constrained rows of
