@@ -257,7 +257,8 @@ def indent_main(a):
     run = dict(synth.INDENT_RUN)
     if a.indent_depth > 0:
         run["depth_max"] = a.indent_depth
-    sweeps = dict(nu_pre=a.sweeps, nu_post=a.sweeps) if a.sweeps > 0 else {}
+    nu = a.sweeps if a.sweeps > 0 else 3  # V(3,3): fewer FGMRES iterations once martensite forms
+    sweeps = dict(nu_pre=nu, nu_post=nu)
     log(f"[bench] indentation workload: {prob.nx}x{prob.ny}x{prob.nz}, {ndof} dof, run {run}, smoother {sweeps}")
     res = {}
     for prec in ("mixed",) + (() if a.no_fp64 else ("fp64",)):
@@ -319,7 +320,7 @@ def indent_main(a):
                                f"{ndof} dof, rigid sphere R={prob.radius} in penalty contact "
                                f"(eps_N={prob.eps_n:g}), load to {run['depth_max']} and unload, adaptive "
                                f"steps (7 desired / 12 max Newton iterations), {prob.n_levels}-level GMG "
-                               f"V({a.sweeps or 2},{a.sweeps or 2}), FGMRES(30) rtol 1e-8; a step = one whole "
+                               f"V({nu},{nu}), FGMRES(30) rtol 1e-8; a step = one whole "
                                f"run; value = dof x Newton iterations per second", "precision": "mixed",
                    "levels": prob.n_levels, **run},
         "mixed": ms,
@@ -415,7 +416,7 @@ def main():
     ap.add_argument("--matrix-free", type=int, default=-1,
                     help="finest level applied from its Gauss-point Hessians (1) or assembled (0); -1: the default")
     ap.add_argument("--sweeps", type=int, default=0,
-                    help="indentation workload: pre- and post-smoothing sweeps (default: the library's 2)")
+                    help="indentation workload: pre- and post-smoothing sweeps (default 3)")
     ap.add_argument("--indent-depth", type=float, default=0.0,
                     help="indentation workload: maximum depth (default: the workload's 0.03)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,

@@ -46,9 +46,11 @@ __device__ __forceinline__ void node_part(int a, const T xg[3], const T w[15], c
     out[3 + m] = c1 * (h * N * w[9 + m] + dN[0] * z[3 * m] + dN[1] * z[3 * m + 1] + dN[2] * z[3 * m + 2]);
 }
 
-// E = element parts of K x_e (x masked on constrained dofs when mask != null)
-template <typename TD, typename TX, typename T>
-__global__ void __launch_bounds__(256) mf_element_kernel(Grid g, const TD* __restrict__ D, const TX* __restrict__ x,
+// E = element parts of K x_e (x masked on constrained dofs when mask != null).
+// MINB: workgroups per CU the register budget is sized for (3 keeps the FP64
+// product with FP32 input at 3 waves per SIMD without spills).
+template <typename TD, typename TX, typename T, int MINB>
+__global__ void __launch_bounds__(256, MINB) mf_element_kernel(Grid g, const TD* __restrict__ D, const TX* __restrict__ x,
                                                          const uint16_t* __restrict__ mask,
                                                          const DevCard* __restrict__ cd, T* __restrict__ E) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -237,7 +239,8 @@ template <typename TD, typename TX, typename T>
 void launch_mf_element(const Grid& g, const TD* D, const TX* x, const uint16_t* mask, const DevCard* cd, T* E,
                        hipStream_t s) {
   const int64_t threads = (int64_t)g.NEpad * 8;  // NEpad is a multiple of 64: whole wavefronts
-  mf_element_kernel<TD, TX, T><<<(int)((threads + 255) / 256), 256, 0, s>>>(g, D, x, mask, cd, E);
+  constexpr int MINB = (sizeof(TD) == 8 && sizeof(TX) == 8) ? 2 : 3;  // all-FP64: no spills at 2
+  mf_element_kernel<TD, TX, T, MINB><<<(int)((threads + 255) / 256), 256, 0, s>>>(g, D, x, mask, cd, E);
 }
 
 template <int MODE, typename T, typename TX, typename TY>
