@@ -211,28 +211,42 @@ __global__ void __launch_bounds__(256) mf_gather_kernel(Grid g, const T* __restr
 }
 
 // Gauss-point Hessians of a slab (standard Gauss-point layout, entries
-// 15.. of qp) -> matrix-free layout, FP64 and (optionally) FP32
+// 15.. of qp) -> matrix-free layout, FP64 and (optionally) FP32.  One thread
+// per group of 4 consecutive entries of one (point, element), in the order of
+// the matrix-free layout, so that every wavefront writes whole 1 KB spans.
 __global__ void __launch_bounds__(256) mf_pack_kernel(Grid g, Chunk ck, const double* __restrict__ qp,
-                                                      double* __restrict__ D64, float* __restrict__ D32) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int gp = (int)(tid / ck.NEcpad);
-  const int el = (int)(tid - (int64_t)gp * ck.NEcpad);
-  if (gp >= 8 || el >= ck.NEc) return;
-  const int64_t e = ck.e0 + el;
+                                                      double* __restrict__ D64, float* __restrict__ D32,
+                                                      int64_t eb0, int64_t neb) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = neb * 64;  // threads per entry group
+  const int k4 = (int)(t / per);
+  if (k4 >= 30) return;
+  const int64_t r = t - (int64_t)k4 * per;
+  const int lane = (int)(r & 63);
+  const int gp = lane >> 3;
+  const int64_t e = (eb0 + (r >> 6)) * 8 + (lane & 7);
+  const int64_t el = e - ck.e0;
+  if (el < 0 || el >= ck.NEc) return;
   const int64_t stride = (int64_t)8 * ck.NEcpad;
-  const double* src = qp + (int64_t)15 * stride + (int64_t)gp * ck.NEcpad + el;
-  for (int k = 0; k < 120; ++k) {
-    const double d = src[(int64_t)k * stride];
-    if (D64) D64[mf_index<double>(g.NEpad, k, gp, e)] = d;
-    if (D32) D32[mf_index<float>(g.NEpad, k, gp, e)] = (float)d;
+  const double* src = qp + (int64_t)(15 + 4 * k4) * stride + (int64_t)gp * ck.NEcpad + el;
+  double d[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) d[u] = src[(int64_t)u * stride];
+  if (D64) {
+    *reinterpret_cast<double2*>(D64 + mf_index<double>(g.NEpad, 4 * k4, gp, e)) = make_double2(d[0], d[1]);
+    *reinterpret_cast<double2*>(D64 + mf_index<double>(g.NEpad, 4 * k4 + 2, gp, e)) = make_double2(d[2], d[3]);
   }
+  if (D32)
+    *reinterpret_cast<float4*>(D32 + mf_index<float>(g.NEpad, 4 * k4, gp, e)) =
+        make_float4((float)d[0], (float)d[1], (float)d[2], (float)d[3]);
 }
 
 size_t mf_hessian_values(const Grid& g) { return (size_t)120 * 8 * g.NEpad; }
 
 void launch_mf_pack(const Grid& g, const Chunk& ck, const double* qp, double* D64, float* D32, hipStream_t s) {
-  const int64_t n = (int64_t)8 * ck.NEcpad;
-  mf_pack_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(g, ck, qp, D64, D32);
+  const int64_t eb0 = ck.e0 / 8, eb1 = (ck.e0 + ck.NEc + 7) / 8;  // element groups of 8 touching the slab
+  const int64_t n = 30 * (eb1 - eb0) * 64;
+  mf_pack_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(g, ck, qp, D64, D32, eb0, eb1 - eb0);
 }
 
 template <typename TD, typename TX, typename T>

@@ -167,8 +167,8 @@ def scale_limit() -> Problem:
 
 def indentation() -> Problem:
     """64x64x32 hex elements (1 254 825 dof), domain 1x1x0.5, rigid sphere
-    R = 0.2 in penalty contact (eps_N = 3.5e4), 4 levels."""
-    return Problem(64, 64, 32, lz=0.5, n_levels=4, kind="sphere", radius=0.2, depth_increment=0.0025)
+    R = 0.2 in penalty contact (eps_N = 3.5e4), 5 levels (4x4x2 coarsest)."""
+    return Problem(64, 64, 32, lz=0.5, n_levels=5, kind="sphere", radius=0.2, depth_increment=0.0025)
 
 
 # Indentation run of the workload above: load to depth 0.03 and unload at
