@@ -323,10 +323,6 @@ int red_blocks(int64_t n);
 void launch_multidot(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part,
                      hipStream_t s);
 void launch_reduce(int k, int nblk, const double* part, double* out, int accumulate, hipStream_t s);
-// w -= V h fused with the dot products of the updated w (k <= 32; returns
-// false, launching nothing, above that)
-bool launch_multiaxpy_dot(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w, double* part,
-                          hipStream_t s);
 void launch_multiaxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w,
                       double* part_norm, hipStream_t s);
 void launch_scale(int64_t n, const double* w, const double* beta, double* v, hipStream_t s);

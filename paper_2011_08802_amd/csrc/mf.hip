@@ -95,11 +95,18 @@ __global__ void __launch_bounds__(256, MINB) mf_element_kernel(Grid g, const TD*
       }
     }
   }
-  // w = D v (packed upper triangle, row-major p <= q), 16-byte loads
+  // w = D v (packed upper triangle, row-major p <= q), 16-byte loads; an
+  // element whose unknowns are all zero (the lifting of a prescribed
+  // increment touches few) contributes nothing and reads no Hessians
+  bool nonzero = false;
+#pragma unroll
+  for (int k = 0; k < 15; ++k) nonzero = nonzero || v[k] != (T)0;
+#pragma unroll
+  for (int k = 0; k < 18; ++k) nonzero = nonzero || ge[k] != (T)0;
   T w[15];
 #pragma unroll
   for (int k = 0; k < 15; ++k) w[k] = 0;
-  if (active) {
+  if (active && nonzero) {
     using VT = typename Vec16<TD>::type;
     constexpr int V = 16 / (int)sizeof(TD);
     const VT* Dp = reinterpret_cast<const VT*>(D) + ((e >> 3) * 64 + gp * 8 + (e & 7));

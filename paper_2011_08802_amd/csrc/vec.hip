@@ -106,71 +106,6 @@ __global__ void __launch_bounds__(RB) multiaxpy_kernel(int64_t n, const double* 
   }
 }
 
-// w -= V h, then part[j * nblk + blk] = the block's sums of V_j . w (new w),
-// j < k <= MAXK_FUSED: the second Gram-Schmidt pass's dot products taken in
-// the same sweep over V as the first pass's update.  Per-thread sums and the
-// block reduction follow multiaxpy and multidot exactly, so the results are
-// bitwise those of the two separate kernels.
-constexpr int MAXK_FUSED = 32;
-__global__ void __launch_bounds__(RB) multiaxpy_dot_kernel(int64_t n, const double* __restrict__ V, int64_t ldv,
-                                                           int k, const double* __restrict__ h,
-                                                           double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double hs[MAXK_FUSED];
-  __shared__ double sh[MAXK_FUSED][RB / 64];
-  for (int j = threadIdx.x; j < k; j += RB) hs[j] = h[j];
-  __syncthreads();
-  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t lo = (int64_t)blockIdx.x * chunk;
-  const int64_t hi = std::min<int64_t>(n, lo + chunk);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double acc[MAXK_FUSED];
-#pragma unroll
-  for (int j = 0; j < MAXK_FUSED; ++j) acc[j] = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += RB) {
-    double vv[MAXK_FUSED];
-    double s = w[i];
-#pragma unroll
-    for (int j = 0; j < MAXK_FUSED; ++j)
-      if (j < k) {
-        vv[j] = V[(int64_t)j * ldv + i];
-        s -= hs[j] * vv[j];
-      }
-    w[i] = s;
-#pragma unroll
-    for (int j = 0; j < MAXK_FUSED; ++j)
-      if (j < k) acc[j] += vv[j] * s;
-  }
-  // the same reduction as multidot, in groups of MD_G vectors
-  for (int j0 = 0; j0 < k; j0 += MD_G) {
-    const int g_n = std::min(MD_G, k - j0);  // uniform
-#pragma unroll
-    for (int g = 0; g < MD_G; ++g) {
-      double v = 0.0;
-#pragma unroll
-      for (int j = 0; j < MAXK_FUSED; ++j)
-        if (j == j0 + g) v = acc[j];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-      if (lane == 0) sh[g][wid] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < g_n) {
-      double t = 0.0;
-#pragma unroll
-      for (int q = 0; q < RB / 64; ++q) t += sh[threadIdx.x][q];
-      part[(int64_t)(j0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
-    }
-    __syncthreads();
-  }
-}
-
-// false if k is too large for the fused kernel (then multiaxpy + multidot)
-bool launch_multiaxpy_dot(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w, double* part,
-                          hipStream_t s) {
-  if (k > MAXK_FUSED) return false;
-  multiaxpy_dot_kernel<<<red_blocks(n), RB, 0, s>>>(n, V, ldv, k, h, w, part);
-  return true;
-}
-
 void launch_multiaxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w, double* part_norm,
                       hipStream_t s) {
   multiaxpy_kernel<<<red_blocks(n), RB, 0, s>>>(n, V, ldv, k, h, w, part_norm);
