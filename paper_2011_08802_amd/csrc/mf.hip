@@ -107,8 +107,10 @@ __global__ void __launch_bounds__(256, MINB) mf_element_kernel(Grid g, const TD*
 #pragma unroll
   for (int k = 0; k < 15; ++k) w[k] = 0;
   if (active && nonzero) {
-    using VT = typename Vec16<TD>::type;
+    // streamed once per product: non-temporal 16-byte loads keep x and the
+    // element outputs in the caches
     constexpr int V = 16 / (int)sizeof(TD);
+    typedef TD VT __attribute__((ext_vector_type(V)));
     const VT* Dp = reinterpret_cast<const VT*>(D) + ((e >> 3) * 64 + gp * 8 + (e & 7));
     const int64_t ks = (int64_t)(g.NEpad >> 3) * 64;
     TD dv[V];
@@ -117,7 +119,7 @@ __global__ void __launch_bounds__(256, MINB) mf_element_kernel(Grid g, const TD*
 #pragma unroll
       for (int q = p; q < 15; ++q, ++k) {
         if (k % V == 0) {
-          const VT vq = Dp[(k / V) * ks];
+          const VT vq = __builtin_nontemporal_load(Dp + (k / V) * ks);
           __builtin_memcpy(dv, &vq, sizeof(VT));
         }
         const T d = (T)dv[k % V];
