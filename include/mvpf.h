@@ -215,7 +215,8 @@ int mvpf_get_rhs(mvpf_problem* p, double* b);
 /* y = A_level x with the eliminated operator of the last mvpf_newton_system
  * (Dirichlet rows/columns = identity).  level 0 = finest.  precision
  * MVPF_FP64 uses the FP64 copy (finest level, or every level in FP64 mode),
- * MVPF_MIXED the FP32 copy (mixed mode, levels above the coarsest).  x, y:
+ * MVPF_MIXED the FP32 copy (mixed mode, levels above the coarsest); on a
+ * matrix-free finest level the FP64 / FP32 Gauss-point Hessians.  x, y:
  * device, length 9*n_nodes(level). */
 int mvpf_jacobian_apply(mvpf_problem* p, int level, int precision, const double* x, double* y);
 
@@ -314,12 +315,23 @@ int mvpf_indent(mvpf_problem* p, const mvpf_indent_opts* o, mvpf_indent_callback
  * element-matrix buffers take at most 96 GiB, else slabs of 40 GiB).  Levels
  * with more elements are assembled in slabs of whole element layers, one
  * halo layer recomputed per slab; at least 2 nx ny + 64, at most the
- * capacity; level ignored; results bitwise unchanged. */
+ * capacity; level ignored; results bitwise unchanged.
+ * "matrix_free": 1 (default for problems with two or more levels) = the
+ * finest-level tangent is never assembled: its Gauss-point Hessians (Sec.
+ * 3.4; 8 x 120 per element, FP64 and, in mixed mode, FP32) are stored and
+ * applied directly in the smoother, the defect and the outer product, and
+ * only the diagonal blocks the smoother inverts are assembled; 0 = the
+ * finest level is assembled into half-stencil blocks like the others (the
+ * blocks are allocated on first use).  Both give the same operator up to
+ * rounding (summation order); takes effect at the next mvpf_newton_system;
+ * level ignored.  row_blocks on level 0 and outer_blocks apply to the
+ * assembled finest level only. */
 int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value);
 int mvpf_get_tuning(const mvpf_problem* p, const char* key, int level, int* value);
-/* Time candidate launch shapes of the smoother (every level but the coarsest)
- * and of the outer product on the operators of the last mvpf_newton_system,
- * and keep the fastest.  row_blocks_out (nullable, n_levels ints): chosen
+/* Time candidate launch shapes of the smoother (every level but the coarsest;
+ * not the finest when it is matrix-free) and of the outer product (assembled
+ * finest level only) on the operators of the last mvpf_newton_system, and
+ * keep the fastest.  row_blocks_out (nullable, n_levels ints): chosen
  * values per level, the last entry being the outer product's. */
 int mvpf_autotune(mvpf_problem* p, int* row_blocks_out);
 
