@@ -305,12 +305,12 @@ template <> const double* mfD<double>(const mvpf_problem* p) { return p->Dmf64; 
 
 // element outputs of K x on the finest level (x masked on constrained dofs
 // when masked), contact stiffness included (indenter of the last
-// build_system), into Cbuf
+// build_system), into Cbuf; sparse: x is zero on most elements
 template <typename T, typename TX>
-void mf_elements(mvpf_problem* p, const TX* x, bool masked) {
+void mf_elements(mvpf_problem* p, const TX* x, bool masked, bool sparse = false) {
   Level& L0 = p->lev[0];
   const uint16_t* mask = masked ? L0.mask : nullptr;
-  launch_mf_element<T, TX, T>(L0.g, mfD<T>(p), x, mask, p->card, (T*)p->Cbuf, p->stream);
+  launch_mf_element<T, TX, T>(L0.g, mfD<T>(p), x, mask, p->card, (T*)p->Cbuf, p->stream, sparse);
   if (contact(p)) launch_contact_apply<T, TX>(L0.g, p->sphere, L0.state, mask, x, (T*)p->Cbuf, p->stream);
 }
 
@@ -883,7 +883,7 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
   // lifting of the prescribed increment, then symmetric elimination
   launch_increment(L0.g, L0.mask, L0.target, L0.state, p->gvec, s);
   if (use_mf(p)) {
-    mf_elements<double, double>(p, p->gvec, false);
+    mf_elements<double, double>(p, p->gvec, false, true);
     launch_mf_gather<0, double, double, double>(L0.g, (const double*)p->Cbuf, nullptr, p->gvec, nullptr, nullptr,
                                                 0.0, p->tmp, s);
   } else {

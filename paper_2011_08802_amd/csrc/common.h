@@ -79,14 +79,17 @@ __host__ __device__ constexpr int pair_index(int a, int b) { return a * 8 - (a *
 // triangle, 0..119) of point g of element e in storage type T, and the
 // element-output value c of node a of element e.  Hessian entries come in
 // groups of V = 16 / sizeof(T) per lane (one 16-byte load) and 64 lanes
-// (8 elements x 8 points) per group, so a wavefront reads 1 KB contiguous;
-// element outputs are grouped by 8 elements.
+// (8 elements x 8 points) per group, so a wavefront reads 1 KB contiguous
+// (and, wave-contiguous, the 8 elements' 120 x 64 entries in one span).
+// Element outputs are stored per corner a and indexed by the corner's node n
+// (each (a, n) names one element), so a gather over consecutive nodes reads
+// consecutive addresses.
 template <typename T>
 __host__ __device__ inline int64_t mf_index(int64_t NEpad, int k, int g, int64_t e) {
   constexpr int V = 16 / (int)sizeof(T);
-  return (((int64_t)(k / V) * (NEpad >> 3) + (e >> 3)) * 64 + g * 8 + (e & 7)) * V + k % V;
+  return ((((e >> 3) * (120 / V) + k / V) * 64) + g * 8 + (e & 7)) * V + k % V;
 }
-__host__ __device__ inline int64_t eo_index(int a, int c, int64_t e) { return ((e >> 3) * 72 + a * 9 + c) * 8 + (e & 7); }
+__host__ __device__ inline int64_t eo_index(int a, int c, int64_t n, int64_t Npad) { return (int64_t)(a * 9 + c) * Npad + n; }
 
 // Rigid spherical indenter: centre (cx, cy, cz), radius R, contact penalty eps.
 struct Sphere {
@@ -246,7 +249,7 @@ size_t mf_hessian_values(const Grid& g);
 void launch_mf_pack(const Grid& g, const Chunk& ck, const double* qp, double* D64, float* D32, hipStream_t s);
 template <typename TD, typename TX, typename T>
 void launch_mf_element(const Grid& g, const TD* D, const TX* x, const uint16_t* mask, const DevCard* cd, T* E,
-                       hipStream_t s);
+                       hipStream_t s, bool sparse_x = false);
 // MODE 0: y = K x; 1: y = b - K x; 2: y = x + omega Dinv (b - K x); constrained rows act as the identity
 template <int MODE, typename T, typename TX, typename TY>
 void launch_mf_gather(const Grid& g, const T* E, const uint16_t* mask, const TX* x, const T* b, const T* Dinv, T omega,

@@ -13,13 +13,16 @@
 // transposed contributions (0.9 KB written and read per sweep).
 //
 // Kernel layout: a wavefront covers 8 elements x 8 Gauss points (lane =
-// 8 * element + point).  Each lane forms v_g, w = D_g v_g and the gradient
-// energy's Mg grad eta, then its contributions to all 8 nodes of the element;
-// a reduce-scatter over the 8 point lanes (xor 4, 2, 1) leaves lane g with
-// the sum for node a = g, written to the element-output buffer.  A node
-// gather sums its <= 8 elements in a fixed order and applies the epilogue
-// (product, defect or damped point-block Jacobi update), so results are
-// reproducible bit for bit.
+// 8 * element + j).  Lane j loads the 9 unknowns of corner j of its element
+// and evaluates Gauss point j: since the Q1 shape functions and the 2x2x2
+// points are tensor products, v_g follows from three one-dimensional
+// interpolation stages over lane pairs (sum factorisation; lanes exchange
+// values by DPP moves, xor 1, 2, 4), and the contributions B^T [w; z] go
+// back to the corners through the transposed stages, so that lane j ends
+// with the element's part for corner j, written to the element-output
+// buffer.  A node gather sums its <= 8 elements in a fixed order and applies
+// the epilogue (product, defect or damped point-block Jacobi update), so
+// results are reproducible bit for bit.
 #include "common.h"
 
 namespace mvpf {
@@ -27,104 +30,161 @@ namespace mvpf {
 constexpr double MGQ0 = 0.21132486540518711775;  // (1 - 1/sqrt 3) / 2
 constexpr double MGQ1 = 0.78867513459481288225;
 
-// Contribution of one Gauss point to node a: c1 * B_a^T [w; z]
-template <typename T>
-__device__ __forceinline__ void node_part(int a, const T xg[3], const T w[15], const T z[18], T h, T c1, T out[9]) {
-  T f[3], df[3];
+// Lane exchanges inside groups of 8 lanes by DPP (no LDS traffic): xor 1 and
+// xor 2 are quad permutations; xor 4 is the half-row mirror (lane i <- 7 - i)
+// followed by the quad reversal (i <- i ^ 3), since (7 - i) ^ 3 = i ^ 4.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_t(float v) {
+  return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_t(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)u), hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <int X, typename T>
+__device__ __forceinline__ T lane_xor(T v) {
+  if constexpr (X == 1) return dpp_t<0xB1>(v);       // quad_perm [1,0,3,2]
+  else if constexpr (X == 2) return dpp_t<0x4E>(v);  // quad_perm [2,3,0,1]
+  else return dpp_t<0x1B>(dpp_t<0x141>(v));          // row_half_mirror, then quad_perm [3,2,1,0]
+}
+
+// One direction of the trilinear interpolation at the Gauss points, by lane
+// pairs (sum factorisation).  Each lane holds n values belonging to its node
+// index bit b along this direction; afterwards it holds, at its Gauss
+// coordinate q (the same bit selects q), the interpolated values (s) and,
+// for the first nd of them, the difference across the pair (the derivative
+// along this direction on the unit reference cube).
+template <int X, typename T, int n>
+__device__ __forceinline__ void interp_pair(const T (&in)[n], bool bit, T q, T (&s)[n], T (&d)[n]) {
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const bool bit = (a >> d) & 1;
-    f[d] = bit ? xg[d] : (T)1 - xg[d];
-    df[d] = bit ? (T)1 : (T)-1;
+  for (int k = 0; k < n; ++k) {
+    const T other = lane_xor<X>(in[k]);
+    const T lo = bit ? other : in[k], hi = bit ? in[k] : other;
+    d[k] = hi - lo;
+    s[k] = lo + q * d[k];
   }
-  const T N = f[0] * f[1] * f[2];
-  const T dN[3] = {df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]};
+}
+
+// Transpose of interp_pair: a lane at Gauss coordinate q along this
+// direction holds coefficients a (of the values) and b (of the derivatives);
+// afterwards it holds, for its node bit, the sum over both Gauss points of
+// a * phi(q) + b * phi', phi = 1 - q or q, phi' = -1 or +1.
+template <int X, typename T, int n>
+__device__ __forceinline__ void interp_pair_t(const T (&a)[n], const T (&b)[n], bool bit, T q, T (&out)[n]) {
 #pragma unroll
-  for (int i = 0; i < 3; ++i) out[i] = c1 * (dN[0] * w[3 * i] + dN[1] * w[3 * i + 1] + dN[2] * w[3 * i + 2]);
-#pragma unroll
-  for (int m = 0; m < 6; ++m)
-    out[3 + m] = c1 * (h * N * w[9 + m] + dN[0] * z[3 * m] + dN[1] * z[3 * m + 1] + dN[2] * z[3 * m + 2]);
+  for (int k = 0; k < n; ++k) {
+    const T to0 = a[k] * ((T)1 - q) - b[k];  // contribution to node bit 0
+    const T to1 = a[k] * q + b[k];           // contribution to node bit 1
+    const T mine = bit ? to1 : to0, theirs = bit ? to0 : to1;
+    out[k] = mine + lane_xor<X>(theirs);
+  }
 }
 
 // E = element parts of K x_e (x masked on constrained dofs when mask != null).
-// MINB: workgroups per CU the register budget is sized for (3 keeps the FP64
-// product with FP32 input at 3 waves per SIMD without spills).
-template <typename TD, typename TX, typename T, int MINB>
+// Lane = 8 * element + j: the lane loads the unknowns of corner j of its
+// element and evaluates Gauss point j; the 15 local variables of every
+// point come from three interpolation stages over lane pairs (x, y, z), and
+// its contributions go back to the corners through the transposed stages
+// (z, y, x), so that lane j ends with the element's part for corner j.
+// SPARSE: x has few nonzero entries (the lifting of a prescribed increment):
+// an element whose unknowns are all zero reads no Hessians; otherwise the
+// Hessian loads are issued before the unknowns arrive.
+// PF: Hessian vectors loaded ahead of the contraction (the rest are loaded
+// PF vectors ahead of their use); MINB: minimum waves per SIMD the register
+// budget is sized for.
+template <typename TD, typename TX, typename T, int MINB, int PF, bool SPARSE>
 __global__ void __launch_bounds__(256, MINB) mf_element_kernel(Grid g, const TD* __restrict__ D, const TX* __restrict__ x,
-                                                         const uint16_t* __restrict__ mask,
-                                                         const DevCard* __restrict__ cd, T* __restrict__ E) {
+                                                               const uint16_t* __restrict__ mask,
+                                                               const DevCard* __restrict__ cd, T* __restrict__ E) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const int gp = lane & 7;
   const int64_t e = (t >> 6) * 8 + (lane >> 3);
-  const bool active = e < g.NE;  // inactive lanes still take part in the shuffles
+  const bool active = e < g.NE;  // inactive lanes hold zeros and still take part in the exchanges
+  const bool b0 = gp & 1, b1 = (gp >> 1) & 1, b2 = (gp >> 2) & 1;
+  const T q0 = (T)(b0 ? MGQ1 : MGQ0), q1 = (T)(b1 ? MGQ1 : MGQ0), q2 = (T)(b2 ? MGQ1 : MGQ0);
   const T h = (T)g.h, c1 = (T)(0.125 * g.h);
-  const T xg[3] = {(T)((gp & 1) ? MGQ1 : MGQ0), (T)((gp & 2) ? MGQ1 : MGQ0), (T)((gp & 4) ? MGQ1 : MGQ0)};
-  T v[15], ge[18];
+  // the unknowns of corner gp
+  T xa[9];
 #pragma unroll
-  for (int k = 0; k < 15; ++k) v[k] = 0;
-#pragma unroll
-  for (int k = 0; k < 18; ++k) ge[k] = 0;
+  for (int c = 0; c < 9; ++c) xa[c] = 0;
+  int node = 0;
   if (active) {
     const int ex = (int)(e % g.nx), ey = (int)((e / g.nx) % g.ny), ez = (int)(e / ((int64_t)g.nx * g.ny));
+    node = (ex + b0) + g.nnx * ((ey + b1) + g.nny * (ez + b2));
+    const unsigned mb = mask ? mask[node] : 0u;
+    TX xl[9];
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const int node = (ex + (a & 1)) + g.nnx * ((ey + ((a >> 1) & 1)) + g.nny * (ez + ((a >> 2) & 1)));
-      const unsigned mb = mask ? mask[node] : 0u;
-      T f[3], df[3];
+    for (int c = 0; c < 9; ++c) xl[c] = x[(int64_t)c * g.Npad + node];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const bool bit = (a >> d) & 1;
-        f[d] = bit ? xg[d] : (T)1 - xg[d];
-        df[d] = bit ? (T)1 : (T)-1;
-      }
-      const T N = f[0] * f[1] * f[2];
-      const T dN[3] = {df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]};
-#pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        const T xl = (T)x[(int64_t)c * g.Npad + node];  // unconditional load, then select
-        const T xv = ((mb >> c) & 1) ? (T)0 : xl;
-        if (c < 3) {
-#pragma unroll
-          for (int j = 0; j < 3; ++j) v[3 * c + j] += dN[j] * xv;
-        } else {
-          v[9 + c - 3] += h * N * xv;
-#pragma unroll
-          for (int j = 0; j < 3; ++j) ge[3 * (c - 3) + j] += dN[j] * xv;
-        }
-      }
-    }
+    for (int c = 0; c < 9; ++c) xa[c] = ((mb >> c) & 1) ? (T)0 : (T)xl[c];
   }
-  // w = D v (packed upper triangle, row-major p <= q), 16-byte loads; an
-  // element whose unknowns are all zero (the lifting of a prescribed
-  // increment touches few) contributes nothing and reads no Hessians
-  bool nonzero = false;
+  // Hessians of Gauss point gp (packed upper triangle, row-major p <= q),
+  // 16-byte non-temporal loads (streamed once per product: x and the
+  // element outputs stay in the caches)
+  constexpr int V = 16 / (int)sizeof(TD);
+  constexpr int NV = 120 / V;
+  typedef TD VT __attribute__((ext_vector_type(V)));
+  const VT* Dp = reinterpret_cast<const VT*>(D) + ((e >> 3) * NV * 64 + gp * 8 + (e & 7));
+  constexpr int64_t ks = 64;
+  VT dq[NV];
+  if (!SPARSE && active) {
 #pragma unroll
-  for (int k = 0; k < 15; ++k) nonzero = nonzero || v[k] != (T)0;
+    for (int k = 0; k < PF; ++k) dq[k] = __builtin_nontemporal_load(Dp + k * ks);
+  }
+  // interpolation to Gauss point gp: x, then y, then z
+  T s1[9], d1[9];
+  interp_pair<1>(xa, b0, q0, s1, d1);
+  T sd1[18], s2[18], d2[18];
 #pragma unroll
-  for (int k = 0; k < 18; ++k) nonzero = nonzero || ge[k] != (T)0;
+  for (int c = 0; c < 9; ++c) sd1[c] = s1[c], sd1[9 + c] = d1[c];
+  interp_pair<2>(sd1, b1, q1, s2, d2);  // s2 = (value, d/dx) at (q0, q1); d2[0..8] = d/dy
+  T sd2[27], s3[27], d3[27];
+#pragma unroll
+  for (int c = 0; c < 18; ++c) sd2[c] = s2[c];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) sd2[18 + c] = d2[c];
+  interp_pair<4>(sd2, b2, q2, s3, d3);  // s3 = (value, d/dx, d/dy); d3[0..8] = d/dz
+  // v: reference gradients of u (3 x 3), h * eta (6); ge: reference gradients of eta
+  T v[15], ge[18];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v[3 * c] = s3[9 + c], v[3 * c + 1] = s3[18 + c], v[3 * c + 2] = d3[c];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    v[9 + m] = h * s3[3 + m];
+    ge[3 * m] = s3[12 + m], ge[3 * m + 1] = s3[21 + m], ge[3 * m + 2] = d3[3 + m];
+  }
+  // w = D v
   T w[15];
 #pragma unroll
   for (int k = 0; k < 15; ++k) w[k] = 0;
-  if (active && nonzero) {
-    // streamed once per product: non-temporal 16-byte loads keep x and the
-    // element outputs in the caches
-    constexpr int V = 16 / (int)sizeof(TD);
-    typedef TD VT __attribute__((ext_vector_type(V)));
-    const VT* Dp = reinterpret_cast<const VT*>(D) + ((e >> 3) * 64 + gp * 8 + (e & 7));
-    const int64_t ks = (int64_t)(g.NEpad >> 3) * 64;
-    TD dv[V];
+  bool load = active;
+  if (SPARSE) {  // the element is zero iff the unknowns of its 8 corners (lanes) are
+    bool nz = false;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) nz = nz || xa[c] != (T)0;
+    const unsigned long long bal = __ballot(nz);
+    load = active && ((bal >> (lane & ~7)) & 0xFFull) != 0;
+    if (load) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) dq[k] = __builtin_nontemporal_load(Dp + k * ks);
+    }
+  }
+  if (load) {
 #pragma unroll
     for (int p = 0, k = 0; p < 15; ++p)
 #pragma unroll
-      for (int q = p; q < 15; ++q, ++k) {
-        if (k % V == 0) {
-          const VT vq = __builtin_nontemporal_load(Dp + (k / V) * ks);
-          __builtin_memcpy(dv, &vq, sizeof(VT));
-        }
-        const T d = (T)dv[k % V];
-        w[p] += d * v[q];
-        if (q != p) w[q] += d * v[p];
+      for (int qq = p; qq < 15; ++qq, ++k) {
+        if (!SPARSE && k % V == 0 && k / V + PF < NV) dq[k / V + PF] = __builtin_nontemporal_load(Dp + (k / V + PF) * ks);
+        const T d = (T)dq[k / V][k % V];
+        w[p] += d * v[qq];
+        if (qq != p) w[qq] += d * v[p];
       }
   }
   // gradient energy: z = (Mg (x) I) grad_ref eta
@@ -133,41 +193,42 @@ __global__ void __launch_bounds__(256, MINB) mf_element_kernel(Grid g, const TD*
   for (int m = 0; m < 6; ++m)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      T s = 0;
+      T sum = 0;
 #pragma unroll
-      for (int m2 = 0; m2 < 6; ++m2) s += (T)cd->Mg[m][m2] * ge[3 * m2 + j];
-      z[3 * m + j] = s;
+      for (int m2 = 0; m2 < 6; ++m2) sum += (T)cd->Mg[m][m2] * ge[3 * m2 + j];
+      z[3 * m + j] = sum;
     }
-  // reduce-scatter over the 8 point lanes of the element
-  const int b2 = (gp >> 2) & 1, b1 = (gp >> 1) & 1, b0 = gp & 1;
-  T acc1[4][9];
+  // coefficients of point gp: a = of the shape-function values, (bx, by, bz)
+  // = of their reference derivatives, per component
+  T a3[27], bz[27];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    T mine[9], other[9];
-    node_part<T>(4 * b2 + k, xg, w, z, h, c1, mine);
-    node_part<T>(4 * (1 - b2) + k, xg, w, z, h, c1, other);
-#pragma unroll
-    for (int c = 0; c < 9; ++c) acc1[k][c] = mine[c] + __shfl_xor(other[c], 4, 64);
+  for (int c = 0; c < 3; ++c) {
+    a3[c] = 0, a3[9 + c] = c1 * w[3 * c], a3[18 + c] = c1 * w[3 * c + 1];
+    bz[c] = c1 * w[3 * c + 2];
   }
-  T acc2[2][9];
 #pragma unroll
-  for (int j = 0; j < 2; ++j)
-#pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      const T mine = b1 ? acc1[2 + j][c] : acc1[j][c];
-      const T other = b1 ? acc1[j][c] : acc1[2 + j][c];
-      acc2[j][c] = mine + __shfl_xor(other, 2, 64);
-    }
-  T out[9];
-#pragma unroll
-  for (int c = 0; c < 9; ++c) {
-    const T mine = b0 ? acc2[1][c] : acc2[0][c];
-    const T other = b0 ? acc2[0][c] : acc2[1][c];
-    out[c] = mine + __shfl_xor(other, 1, 64);
+  for (int m = 0; m < 6; ++m) {
+    a3[3 + m] = c1 * h * w[9 + m], a3[12 + m] = c1 * z[3 * m], a3[21 + m] = c1 * z[3 * m + 1];
+    bz[3 + m] = c1 * z[3 * m + 2];
   }
+#pragma unroll
+  for (int c = 0; c < 9; ++c) bz[9 + c] = 0, bz[18 + c] = 0;
+  // back to the corners: z (27 sums: value, x, y coefficients), then y, then x
+  T r3[27];
+  interp_pair_t<4>(a3, bz, b2, q2, r3);
+  T a2[18], by[18], r2[18];
+#pragma unroll
+  for (int c = 0; c < 18; ++c) a2[c] = r3[c], by[c] = 0;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) by[c] = r3[18 + c];
+  interp_pair_t<2>(a2, by, b1, q1, r2);
+  T a1[9], bx[9], out[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) a1[c] = r2[c], bx[c] = r2[9 + c];
+  interp_pair_t<1>(a1, bx, b0, q0, out);
   if (active) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) E[eo_index(gp, c, e)] = out[c];
+    for (int c = 0; c < 9; ++c) E[eo_index(gp, c, node, g.Npad)] = out[c];
   }
 }
 
@@ -191,9 +252,8 @@ __global__ void __launch_bounds__(256) mf_gather_kernel(Grid g, const T* __restr
   for (int a = 7; a >= 0; --a) {  // element (i - ax, j - ay, k - az) has this node as corner a
     const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - ((a >> 2) & 1);
     if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || ez < 0 || ez >= g.nz) continue;
-    const int64_t e = ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) s[c] += E[eo_index(a, c, e)];
+    for (int c = 0; c < 9; ++c) s[c] += E[eo_index(a, c, n, g.Npad)];
   }
   const unsigned mb = mask ? mask[n] : 0u;
   T r[9];
@@ -258,12 +318,21 @@ void launch_mf_pack(const Grid& g, const Chunk& ck, const double* qp, double* D6
   mf_pack_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(g, ck, qp, D64, D32, eb0, eb1 - eb0);
 }
 
+// Register budgets (measured equal within 1 % for prefetch depths 12 ... 30
+// at 2 ... 4 waves per SIMD): FP32 Hessians 20 vectors ahead at >= 3 waves
+// per SIMD, FP64 16 ahead at >= 2.
+constexpr int MF_PF32 = 20, MF_MINB32 = 3, MF_PF64 = 16, MF_MINB64 = 2;
 template <typename TD, typename TX, typename T>
 void launch_mf_element(const Grid& g, const TD* D, const TX* x, const uint16_t* mask, const DevCard* cd, T* E,
-                       hipStream_t s) {
+                       hipStream_t s, bool sparse_x) {
   const int64_t threads = (int64_t)g.NEpad * 8;  // NEpad is a multiple of 64: whole wavefronts
-  constexpr int MINB = (sizeof(TD) == 8 && sizeof(TX) == 8) ? 2 : 3;  // all-FP64: no spills at 2
-  mf_element_kernel<TD, TX, T, MINB><<<(int)((threads + 255) / 256), 256, 0, s>>>(g, D, x, mask, cd, E);
+  constexpr bool f64 = sizeof(TD) == 8;
+  constexpr int MINB = f64 ? MF_MINB64 : MF_MINB32, PF = f64 ? MF_PF64 : MF_PF32;
+  const int blocks = (int)((threads + 255) / 256);
+  if (sparse_x)
+    mf_element_kernel<TD, TX, T, MINB, PF, true><<<blocks, 256, 0, s>>>(g, D, x, mask, cd, E);
+  else
+    mf_element_kernel<TD, TX, T, MINB, PF, false><<<blocks, 256, 0, s>>>(g, D, x, mask, cd, E);
 }
 
 template <int MODE, typename T, typename TX, typename TY>
@@ -273,11 +342,11 @@ void launch_mf_gather(const Grid& g, const T* E, const uint16_t* mask, const TX*
 }
 
 template void launch_mf_element<float, float, float>(const Grid&, const float*, const float*, const uint16_t*,
-                                                     const DevCard*, float*, hipStream_t);
+                                                     const DevCard*, float*, hipStream_t, bool);
 template void launch_mf_element<double, float, double>(const Grid&, const double*, const float*, const uint16_t*,
-                                                       const DevCard*, double*, hipStream_t);
+                                                       const DevCard*, double*, hipStream_t, bool);
 template void launch_mf_element<double, double, double>(const Grid&, const double*, const double*, const uint16_t*,
-                                                        const DevCard*, double*, hipStream_t);
+                                                        const DevCard*, double*, hipStream_t, bool);
 template void launch_mf_gather<0, float, float, float>(const Grid&, const float*, const uint16_t*, const float*,
                                                        const float*, const float*, float, float*, hipStream_t);
 template void launch_mf_gather<1, float, float, float>(const Grid&, const float*, const uint16_t*, const float*,
