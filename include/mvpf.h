@@ -351,9 +351,11 @@ int mvpf_kernel_stats(mvpf_problem* p, const char* name, int* launches, double* 
  * mesh, material card -- e.g. its own crystal orientation -- and loading)
  * solved together: the problems advance in lockstep, one Arnoldi step of
  * every problem per host synchronisation, and the multigrid V-cycles of all
- * problems run as parallel branches of one captured HIP graph (one graph
- * launch per step).  Each problem's numbers are bitwise those of solving it
- * alone with mvpf_solve.  Every problem is a full handle (mvpf_batch_problem)
+ * problems run as one captured HIP graph (one graph launch per step) in
+ * which every V-cycle operator (sweep, defect, transfer, coarse solve) is
+ * one launch covering all problems, whatever their sizes: each problem is a
+ * job of the launch, owning a range of its workgroups.  Each problem's
+ * numbers are bitwise those of solving it alone with mvpf_solve.  Every problem is a full handle (mvpf_batch_problem)
  * on which the single-problem calls work; the batch owns them. */
 
 /* Create n (1..MVPF_MAX_BATCH) problems: meshes[i], mats[i], loads[i] as for

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <string>
 
 #include "common.h"
@@ -1053,6 +1054,9 @@ struct mvpf_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<int> graph_version;  // config_version of each problem at capture
+  // job tables of the graph's batched launches (device)
+  mvpf::BJob* jobs_dev = nullptr;
+  size_t jobs_cap = 0;
   std::string err;
 };
 
@@ -1065,28 +1069,298 @@ void batch_drop_graph(mvpf_batch* b) {
   b->graph = nullptr;
 }
 
+// ---- the batched V-cycle: one launch per operator for all problems ----------
+// The V-cycles of all problems are laid out as one sequence of batched
+// launches.  At every step of the cycle the problems are grouped by kernel
+// family (matrix-free finest level, two-pass half-stencil, small grid), each
+// group being one launch whose jobs are the problems of the group; every
+// problem sees exactly the kernels and summation orders of its own V-cycle,
+// so its result is bitwise that of preconditioning it alone.  The few
+// per-problem launches left (contact stiffness, a zero first guess without
+// pre-smoothing) are kept as such.
+struct PlanOp {
+  int op = -1;  // BatchOp, or -1 for a per-problem launch
+  std::vector<BJob> jobs;
+  size_t off = 0;
+  int blocks = 0;
+  std::function<void(hipStream_t)> solo;
+};
+
+struct Planner {
+  std::vector<PlanOp> ops;
+  // one launch per op kind: jobs[k] go into a new op of kind kinds[k]
+  void add(int op, std::vector<BJob>&& jobs) {
+    if (jobs.empty()) return;
+    PlanOp o;
+    o.op = op;
+    o.jobs = std::move(jobs);
+    ops.push_back(std::move(o));
+  }
+  void solo(std::function<void(hipStream_t)> f) {
+    PlanOp o;
+    o.solo = std::move(f);
+    ops.push_back(std::move(o));
+  }
+};
+
+BJob job_of(const Level& L) {
+  BJob j{};
+  j.g = L.g;
+  j.mask = L.mask;
+  return j;
+}
+
+template <typename T>
+void plan_mf_elements(Planner& pl, const std::vector<mvpf_problem*>& mf) {
+  std::vector<BJob> el;
+  for (mvpf_problem* p : mf) {
+    Level& L = p->lev[0];
+    BJob j = job_of(L);
+    j.A = mfD<T>(p);
+    j.x = L.x;
+    j.cd = p->card;
+    j.C = p->Cbuf;
+    el.push_back(j);
+  }
+  pl.add(BOP_MF_ELEMENT, std::move(el));
+  for (mvpf_problem* p : mf)
+    if (contact(p)) {
+      Level& L = p->lev[0];
+      const T* x = (const T*)L.x;
+      pl.solo([p, x](hipStream_t s) {
+        Level& L0 = p->lev[0];
+        launch_contact_apply<T, T>(L0.g, p->sphere, L0.state, L0.mask, x, (T*)p->Cbuf, s);
+      });
+    }
+}
+
+// damped point-block Jacobi sweeps on level l of every problem in ps
+template <typename T>
+void plan_sweep(Planner& pl, const std::vector<mvpf_problem*>& ps, int l, bool zero) {
+  std::vector<mvpf_problem*> mf;
+  std::vector<BJob> z, split, lower, small, gather;
+  for (mvpf_problem* p : ps) {
+    Level& L = p->lev[l];
+    BJob j = job_of(L);
+    j.omega = p->opts.omega;
+    j.D = opD<T>(L);
+    j.x = L.x;
+    j.b = L.b;
+    j.y = L.x2;
+    if (zero) {
+      z.push_back(j);
+    } else if (l == 0 && use_mf(p)) {
+      mf.push_back(p);
+      j.C = p->Cbuf;
+      gather.push_back(j);
+    } else if (L.g.N <= p->small_nodes) {
+      j.A = opA<T>(L);
+      small.push_back(j);
+    } else {
+      j.A = opA<T>(L);
+      j.C = p->Cbuf;
+      split.push_back(j);
+      lower.push_back(j);
+    }
+  }
+  plan_mf_elements<T>(pl, mf);
+  pl.add(BOP_PBJ_ZERO, std::move(z));
+  pl.add(BOP_DEFECT_SPLIT, std::move(split));
+  pl.add(BOP_ROW_SMALL_PBJ, std::move(small));
+  pl.add(BOP_MF_GATHER_PBJ, std::move(gather));
+  pl.add(BOP_PBJ_LOWER, std::move(lower));
+  for (mvpf_problem* p : ps) std::swap(p->lev[l].x, p->lev[l].x2);
+}
+
+// r = b - A x on level l of every problem in ps
+template <typename T>
+void plan_defect(Planner& pl, const std::vector<mvpf_problem*>& ps, int l) {
+  std::vector<mvpf_problem*> mf;
+  std::vector<BJob> split, lower, small, gather;
+  for (mvpf_problem* p : ps) {
+    Level& L = p->lev[l];
+    BJob j = job_of(L);
+    j.D = opD<T>(L);
+    j.x = L.x;
+    j.b = L.b;
+    j.y = L.r;
+    if (l == 0 && use_mf(p)) {
+      mf.push_back(p);
+      j.C = p->Cbuf;
+      gather.push_back(j);
+    } else if (L.g.N <= p->small_nodes) {
+      j.A = opA<T>(L);
+      small.push_back(j);
+    } else {
+      j.A = opA<T>(L);
+      j.C = p->Cbuf;
+      split.push_back(j);
+      lower.push_back(j);
+    }
+  }
+  plan_mf_elements<T>(pl, mf);
+  pl.add(BOP_DEFECT_SPLIT, std::move(split));
+  pl.add(BOP_ROW_SMALL_DEFECT, std::move(small));
+  pl.add(BOP_MF_GATHER_DEFECT, std::move(gather));
+  pl.add(BOP_DEFECT_LOWER, std::move(lower));
+}
+
+template <typename T>
+void plan_vcycle(Planner& pl, const std::vector<mvpf_problem*>& ps, int l) {
+  std::vector<mvpf_problem*> fine;
+  std::vector<BJob> coarse;
+  for (mvpf_problem* p : ps) {
+    Level& L = p->lev[l];
+    if (l == p->L - 1) {
+      BJob j = job_of(L);
+      j.A = L.Ainv;
+      j.b = L.b;
+      j.y = L.x;
+      coarse.push_back(j);
+    } else {
+      fine.push_back(p);
+    }
+  }
+  pl.add(BOP_COARSE, std::move(coarse));
+  if (fine.empty()) return;
+  int nu_pre = 0, nu_post = 0;
+  for (mvpf_problem* p : fine) {
+    nu_pre = std::max(nu_pre, p->opts.nu_pre);
+    nu_post = std::max(nu_post, p->opts.nu_post);
+  }
+  // pre-smoothing: sweep k of the problems that take more than k sweeps
+  std::vector<mvpf_problem*> act;
+  for (mvpf_problem* p : fine) {
+    if (p->opts.nu_pre > 0) {
+      act.push_back(p);
+    } else {
+      Level& L = p->lev[l];
+      T* x = (T*)L.x;
+      const int64_t n = nvec(L.g);
+      pl.solo([x, n](hipStream_t s) { launch_zero<T>(n, x, s); });
+    }
+  }
+  plan_sweep<T>(pl, act, l, true);
+  for (int k = 1; k < nu_pre; ++k) {
+    act.clear();
+    for (mvpf_problem* p : fine)
+      if (p->opts.nu_pre > k) act.push_back(p);
+    plan_sweep<T>(pl, act, l, false);
+  }
+  plan_defect<T>(pl, fine, l);
+  std::vector<BJob> rs;
+  for (mvpf_problem* p : fine) {
+    Level &L = p->lev[l], &C = p->lev[l + 1];
+    BJob j{};
+    j.g = L.g;
+    j.g2 = C.g;
+    j.x = L.r;
+    j.mask = C.mask;
+    j.y = C.b;
+    rs.push_back(j);
+  }
+  pl.add(BOP_RESTRICT, std::move(rs));
+  plan_vcycle<T>(pl, fine, l + 1);
+  std::vector<BJob> pr;
+  for (mvpf_problem* p : fine) {
+    Level &L = p->lev[l], &C = p->lev[l + 1];
+    BJob j{};
+    j.g = L.g;
+    j.g2 = C.g;
+    j.x = C.x;
+    j.mask = L.mask;
+    j.y = L.x;
+    pr.push_back(j);
+  }
+  pl.add(BOP_PROLONG, std::move(pr));
+  for (int k = 0; k < nu_post; ++k) {
+    act.clear();
+    for (mvpf_problem* p : fine)
+      if (p->opts.nu_post > k) act.push_back(p);
+    plan_sweep<T>(pl, act, l, false);
+  }
+}
+
+// z_i = M_i^-1 v_i for every problem of the batch (v = vin, z = zout)
+template <typename T>
+void plan_precondition(Planner& pl, mvpf_batch* b) {
+  std::vector<BJob> cv, fin;
+  for (int i = 0; i < b->n; ++i) {
+    Level& L = b->probs[i]->lev[0];
+    BJob j = job_of(L);
+    j.b = b->vin[i];
+    j.y = L.b;
+    cv.push_back(j);
+  }
+  pl.add(BOP_CONVERT, std::move(cv));
+  plan_vcycle<T>(pl, b->probs, 0);
+  for (int i = 0; i < b->n; ++i) {
+    Level& L = b->probs[i]->lev[0];
+    BJob j = job_of(L);
+    j.x = L.x;
+    j.b = b->vin[i];
+    j.y = b->zout[i];
+    fin.push_back(j);
+  }
+  pl.add(BOP_FINISH, std::move(fin));
+}
+
 template <typename T, typename TZ>
 int batch_capture(mvpf_batch* b) {
   batch_drop_graph(b);
+  // plan (the sweeps' buffer swaps are replayed on the host, then undone)
+  std::vector<std::pair<void*, void*>> saved;
+  for (mvpf_problem* p : b->probs)
+    for (int l = 0; l < p->L; ++l) saved.emplace_back(p->lev[l].x, p->lev[l].x2);
+  Planner pl;
+  plan_precondition<T>(pl, b);
+  {
+    size_t k = 0;
+    for (mvpf_problem* p : b->probs)
+      for (int l = 0; l < p->L; ++l, ++k) {
+        p->lev[l].x = saved[k].first;
+        p->lev[l].x2 = saved[k].second;
+      }
+  }
+  // job tables: block ranges, then one upload
+  std::vector<BJob> all;
+  for (PlanOp& o : pl.ops) {
+    if (o.op < 0) continue;
+    o.off = all.size();
+    int blocks = 0;
+    for (BJob& j : o.jobs) {
+      j.nblk = batch_job_blocks(o.op, j);
+      j.block0 = blocks;
+      blocks += j.nblk;
+      all.push_back(j);
+    }
+    o.blocks = blocks;
+  }
+  if (all.size() > b->jobs_cap) {
+    if (b->jobs_dev) (void)hipFree(b->jobs_dev);
+    b->jobs_dev = nullptr;
+    b->jobs_cap = 0;
+    if (hipMalloc((void**)&b->jobs_dev, sizeof(BJob) * all.size()) != hipSuccess) {
+      (void)hipGetLastError();
+      b->err = "batch job table allocation failed";
+      return MVPF_ENOMEM;
+    }
+    b->jobs_cap = all.size();
+  }
+  if (!all.empty())
+    BCHK(hipMemcpy(b->jobs_dev, all.data(), sizeof(BJob) * all.size(), hipMemcpyHostToDevice));
   hipStream_t s = b->work;
   if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     b->err = "hipStreamBeginCapture failed";
     return MVPF_EDEVICE;
   }
-  bool ok = hipEventRecord(b->fork, s) == hipSuccess;
-  for (int i = 0; i < b->n && ok; ++i) {
-    mvpf_problem* p = b->probs[i];
-    ok = hipStreamWaitEvent(b->branch[i], b->fork, 0) == hipSuccess;
-    const bool timing = p->timing;
-    const hipStream_t own = p->stream;
-    p->timing = false;
-    p->stream = b->branch[i];
-    if (ok) precondition<T, TZ>(p, b->vin[i], (TZ*)b->zout[i]);
-    p->stream = own;
-    p->timing = timing;
-    ok = ok && hipEventRecord(b->join[i], b->branch[i]) == hipSuccess &&
-         hipStreamWaitEvent(s, b->join[i], 0) == hipSuccess;
+  for (PlanOp& o : pl.ops) {
+    if (o.op < 0)
+      o.solo(s);
+    else
+      launch_batch<T, TZ>(o.op, b->jobs_dev + o.off, (int)o.jobs.size(), o.blocks, s);
   }
+  const bool ok = hipGetLastError() == hipSuccess;
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(s, &g);
   if (!ok || e != hipSuccess || !g) {
@@ -1185,6 +1459,9 @@ void batch_free(mvpf_batch* b) {
   if (b->leave) (void)hipEventDestroy(b->leave);
   if (b->gj_tab) (void)hipFree(b->gj_tab);
   if (b->gj_sel) (void)hipFree(b->gj_sel);
+  if (b->jobs_dev) (void)hipFree(b->jobs_dev);
+  b->jobs_dev = nullptr;
+  b->jobs_cap = 0;
   b->gj_tab = nullptr;
   b->gj_sel = nullptr;
   if (b->work) {

@@ -32,11 +32,13 @@ inline int row_grid(const Grid& g, int G) {
   return std::max(8, G / 8 * 8);
 }
 
-#define ROW_LOOP(g)                                                                    \
-  const int nb_ = row_blocks(g);                                                      \
-  const int per_ = gridDim.x >> 3;                                                     \
-  for (int L_ = (blockIdx.x & 7) * per_ + (blockIdx.x >> 3); L_ < nb_; L_ += gridDim.x) \
+// ROW_LOOP_B: the same for workgroup bid of nblk (a job of a batched launch)
+#define ROW_LOOP_B(g, bid, nblk)                                                   \
+  const int nb_ = row_blocks(g);                                                  \
+  const int per_ = (nblk) >> 3;                                                    \
+  for (int L_ = ((bid) & 7) * per_ + ((bid) >> 3); L_ < nb_; L_ += (nblk))         \
     for (int n = L_ * 256 + threadIdx.x, once_ = 1; once_; once_ = 0)
+#define ROW_LOOP(g) ROW_LOOP_B(g, (int)blockIdx.x, (int)gridDim.x)
 
 // Symmetric product in two passes, so that every stored block is read from
 // memory exactly once whatever the cache does:
@@ -225,8 +227,9 @@ __global__ void __launch_bounds__(256) defect_upper_kernel(Grid g, const T* __re
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) defect_lower_kernel(Grid g, T* __restrict__ r, const T* __restrict__ C) {
-  ROW_LOOP(g) {
+__device__ __forceinline__ void defect_lower_body(const Grid& g, T* __restrict__ r, const T* __restrict__ C, int bid,
+                                                  int nblk) {
+  ROW_LOOP_B(g, bid, nblk) {
     if (n >= g.N) continue;
     T acc[9];
 #pragma unroll
@@ -236,14 +239,18 @@ __global__ void __launch_bounds__(256) defect_lower_kernel(Grid g, T* __restrict
     for (int c = 0; c < 9; ++c) r[(int64_t)c * g.Npad + n] = acc[c];
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(256) defect_lower_kernel(Grid g, T* __restrict__ r, const T* __restrict__ C) {
+  defect_lower_body<T>(g, r, C, blockIdx.x, gridDim.x);
+}
 
 template <typename T>
-__global__ void __launch_bounds__(256) defect_upper_split_kernel(Grid g, const T* __restrict__ A,
-                                                                 const T* __restrict__ x, const T* __restrict__ b,
-                                                                 T* __restrict__ r, T* __restrict__ C) {
+__device__ __forceinline__ void defect_upper_split_body(const Grid& g, const T* __restrict__ A,
+                                                        const T* __restrict__ x, const T* __restrict__ b,
+                                                        T* __restrict__ r, T* __restrict__ C, int bid, int nblk) {
   __shared__ T sh[2][9][64];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, tl = w >> 1, half = w & 1;
-  const int t = split_tile(blockIdx.x, gridDim.x) + tl;
+  const int t = split_tile(bid, nblk) + tl;
   const int n = t * TILE + l;
   const bool valid = t < g.ntiles;
   T acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -267,6 +274,12 @@ __global__ void __launch_bounds__(256) defect_upper_split_kernel(Grid g, const T
     for (int c = 0; c < 9; ++c) r[(int64_t)c * g.Npad + n] = (n < g.N) ? acc[c] - sh[tl][c][l] : (T)0;
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(256) defect_upper_split_kernel(Grid g, const T* __restrict__ A,
+                                                                 const T* __restrict__ x, const T* __restrict__ b,
+                                                                 T* __restrict__ r, T* __restrict__ C) {
+  defect_upper_split_body<T>(g, A, x, b, r, C, blockIdx.x, gridDim.x);
+}
 
 template <typename T>
 void launch_defect(const Grid& g, const T* A, const T* x, const T* b, T* r, void* C, hipStream_t s, int G) {
@@ -286,9 +299,9 @@ template void launch_defect<double>(const Grid&, const double*, const double*, c
 // Pass 1 leaves the partial residual in xo; pass 2 completes it and updates.
 // With a zero initial guess the product with A vanishes: xo = omega D^-1 b.
 template <typename T>
-__global__ void __launch_bounds__(256) pbj_zero_kernel(Grid g, const T* __restrict__ Dinv, const T* __restrict__ b,
-                                                       T* __restrict__ xo, T omega) {
-  ROW_LOOP(g) {
+__device__ __forceinline__ void pbj_zero_body(const Grid& g, const T* __restrict__ Dinv, const T* __restrict__ b,
+                                              T* __restrict__ xo, T omega, int bid, int nblk) {
+  ROW_LOOP_B(g, bid, nblk) {
     if (n >= g.Npad) continue;
     const int t = n >> 6, l = n & 63;
     const T* Db = Dinv + (int64_t)t * Lay<T>::SLICE;
@@ -304,11 +317,17 @@ __global__ void __launch_bounds__(256) pbj_zero_kernel(Grid g, const T* __restri
     }
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(256) pbj_zero_kernel(Grid g, const T* __restrict__ Dinv, const T* __restrict__ b,
+                                                       T* __restrict__ xo, T omega) {
+  pbj_zero_body<T>(g, Dinv, b, xo, omega, blockIdx.x, gridDim.x);
+}
 
 template <typename T>
-__global__ void __launch_bounds__(256) pbj_lower_kernel(Grid g, const T* __restrict__ Dinv, const T* __restrict__ x,
-                                                        T* __restrict__ xo, const T* __restrict__ C, T omega) {
-  ROW_LOOP(g) {
+__device__ __forceinline__ void pbj_lower_body(const Grid& g, const T* __restrict__ Dinv, const T* __restrict__ x,
+                                               T* __restrict__ xo, const T* __restrict__ C, T omega, int bid,
+                                               int nblk) {
+  ROW_LOOP_B(g, bid, nblk) {
     if (n >= g.N) continue;
     T res[9];
 #pragma unroll
@@ -324,6 +343,11 @@ __global__ void __launch_bounds__(256) pbj_lower_kernel(Grid g, const T* __restr
       xo[(int64_t)r * g.Npad + n] = x[(int64_t)r * g.Npad + n] + omega * s;
     }
   }
+}
+template <typename T>
+__global__ void __launch_bounds__(256) pbj_lower_kernel(Grid g, const T* __restrict__ Dinv, const T* __restrict__ x,
+                                                        T* __restrict__ xo, const T* __restrict__ C, T omega) {
+  pbj_lower_body<T>(g, Dinv, x, xo, C, omega, blockIdx.x, gridDim.x);
 }
 
 template <typename T>
@@ -354,14 +378,14 @@ template void launch_pbj<double>(const Grid&, const double*, const double*, cons
 constexpr int SMALL_ROWS = 9;
 
 template <typename T, bool PBJ>
-__global__ void __launch_bounds__(256) row_small_kernel(Grid g, const T* __restrict__ A, const T* __restrict__ Dinv,
-                                                        const T* __restrict__ x, const T* __restrict__ b,
-                                                        T* __restrict__ out, T omega) {
+__device__ __forceinline__ void row_small_body(const Grid& g, const T* __restrict__ A, const T* __restrict__ Dinv,
+                                               const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ out,
+                                               T omega, int bid) {
   __shared__ T part[SMALL_ROWS][NSTEN][9];
   __shared__ T res[SMALL_ROWS][9];
   const int tid = threadIdx.x;
   const int s = tid / SMALL_ROWS, ln = tid % SMALL_ROWS;
-  const int n = blockIdx.x * SMALL_ROWS + ln;
+  const int n = bid * SMALL_ROWS + ln;
   T pr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (tid < SMALL_ROWS * NSTEN && n < g.N) {
     const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
@@ -399,7 +423,7 @@ __global__ void __launch_bounds__(256) row_small_kernel(Grid g, const T* __restr
     for (int r = 0; r < 9; ++r) part[ln][s][r] = pr[r];
   __syncthreads();
   const int ln2 = tid / 9, r2 = tid % 9;
-  const int n2 = blockIdx.x * SMALL_ROWS + ln2;
+  const int n2 = bid * SMALL_ROWS + ln2;
   const bool own = tid < SMALL_ROWS * 9 && n2 < g.N;
   if (own) {
     T acc = b[(int64_t)r2 * g.Npad + n2];
@@ -419,6 +443,12 @@ __global__ void __launch_bounds__(256) row_small_kernel(Grid g, const T* __restr
     }
   }
 }
+template <typename T, bool PBJ>
+__global__ void __launch_bounds__(256) row_small_kernel(Grid g, const T* __restrict__ A, const T* __restrict__ Dinv,
+                                                        const T* __restrict__ x, const T* __restrict__ b,
+                                                        T* __restrict__ out, T omega) {
+  row_small_body<T, PBJ>(g, A, Dinv, x, b, out, omega, blockIdx.x);
+}
 
 template <typename T>
 void launch_row_small(const Grid& g, const T* A, const T* Dinv, const T* x, const T* b, T* out, T omega, bool pbj,
@@ -433,5 +463,66 @@ template void launch_row_small<float>(const Grid&, const float*, const float*, c
                                       float, bool, hipStream_t);
 template void launch_row_small<double>(const Grid&, const double*, const double*, const double*, const double*,
                                        double*, double, bool, hipStream_t);
+
+// ---- batched launches (one launch for the jobs of many problems) ------------
+template <typename T>
+__global__ void __launch_bounds__(256) pbj_zero_batch(const BJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const BJob& j = find_job(jobs, njobs, bid);
+  pbj_zero_body<T>(j.g, (const T*)j.D, (const T*)j.b, (T*)j.y, (T)j.omega, bid, j.nblk);
+}
+template <typename T>
+__global__ void __launch_bounds__(256) defect_upper_split_batch(const BJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const BJob& j = find_job(jobs, njobs, bid);
+  defect_upper_split_body<T>(j.g, (const T*)j.A, (const T*)j.x, (const T*)j.b, (T*)j.y, (T*)j.C, bid, j.nblk);
+}
+template <typename T>
+__global__ void __launch_bounds__(256) pbj_lower_batch(const BJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const BJob& j = find_job(jobs, njobs, bid);
+  pbj_lower_body<T>(j.g, (const T*)j.D, (const T*)j.x, (T*)j.y, (const T*)j.C, (T)j.omega, bid, j.nblk);
+}
+template <typename T>
+__global__ void __launch_bounds__(256) defect_lower_batch(const BJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const BJob& j = find_job(jobs, njobs, bid);
+  defect_lower_body<T>(j.g, (T*)j.y, (const T*)j.C, bid, j.nblk);
+}
+template <typename T, bool PBJ>
+__global__ void __launch_bounds__(256) row_small_batch(const BJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const BJob& j = find_job(jobs, njobs, bid);
+  row_small_body<T, PBJ>(j.g, (const T*)j.A, (const T*)j.D, (const T*)j.x, (const T*)j.b, (T*)j.y, (T)j.omega, bid);
+}
+
+template <typename T>
+void launch_bsr_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s) {
+  switch (op) {
+    case BOP_PBJ_ZERO: pbj_zero_batch<T><<<blocks, 256, 0, s>>>(jobs, njobs); break;
+    case BOP_DEFECT_SPLIT: defect_upper_split_batch<T><<<blocks, 256, 0, s>>>(jobs, njobs); break;
+    case BOP_PBJ_LOWER: pbj_lower_batch<T><<<blocks, 256, 0, s>>>(jobs, njobs); break;
+    case BOP_DEFECT_LOWER: defect_lower_batch<T><<<blocks, 256, 0, s>>>(jobs, njobs); break;
+    case BOP_ROW_SMALL_PBJ: row_small_batch<T, true><<<blocks, 256, 0, s>>>(jobs, njobs); break;
+    case BOP_ROW_SMALL_DEFECT: row_small_batch<T, false><<<blocks, 256, 0, s>>>(jobs, njobs); break;
+    default: break;
+  }
+}
+template void launch_bsr_batch<float>(int, const BJob*, int, int, hipStream_t);
+template void launch_bsr_batch<double>(int, const BJob*, int, int, hipStream_t);
+
+// workgroups of one job (plain shapes: one logical block of 256 rows per
+// workgroup, rounded up to whole rounds over the 8 XCDs)
+int bsr_job_blocks(int op, const Grid& g) {
+  switch (op) {
+    case BOP_PBJ_ZERO:
+    case BOP_PBJ_LOWER:
+    case BOP_DEFECT_LOWER: return row_grid(g, 0);
+    case BOP_DEFECT_SPLIT: return split_grid(g);
+    case BOP_ROW_SMALL_PBJ:
+    case BOP_ROW_SMALL_DEFECT: return (g.N + SMALL_ROWS - 1) / SMALL_ROWS;
+    default: return 0;
+  }
+}
 
 }  // namespace mvpf

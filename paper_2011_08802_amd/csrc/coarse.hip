@@ -689,10 +689,10 @@ std::vector<int> dense_invert_batch_selection(const std::vector<int>& ns) {
 // x = Ainv b on the coarsest level; one wavefront per output unknown, FP64
 // accumulation; b and x are level vectors (component-major, padded).
 template <typename T>
-__global__ void __launch_bounds__(256) coarse_solve_kernel(Grid g, const double* __restrict__ Ainv,
-                                                           const T* __restrict__ b, T* __restrict__ x) {
+__device__ __forceinline__ void coarse_solve_body(const Grid& g, const double* __restrict__ Ainv,
+                                                  const T* __restrict__ b, T* __restrict__ x, int bid) {
   const int64_t nd = (int64_t)NDOF * g.N;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int row = bid * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= nd) return;
   double s = 0.0;
@@ -707,6 +707,17 @@ __global__ void __launch_bounds__(256) coarse_solve_kernel(Grid g, const double*
     x[(int64_t)comp * g.Npad + node] = (T)s;
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(256) coarse_solve_kernel(Grid g, const double* __restrict__ Ainv,
+                                                           const T* __restrict__ b, T* __restrict__ x) {
+  coarse_solve_body<T>(g, Ainv, b, x, blockIdx.x);
+}
+template <typename T>
+__global__ void __launch_bounds__(256) coarse_solve_batch(const BJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const BJob& j = find_job(jobs, njobs, bid);
+  coarse_solve_body<T>(j.g, (const double*)j.A, (const T*)j.b, (T*)j.y, bid);
+}
 
 template <typename T>
 void launch_coarse_solve(const Grid& g, const double* Ainv, const T* b, T* x, hipStream_t s) {
@@ -715,5 +726,12 @@ void launch_coarse_solve(const Grid& g, const double* Ainv, const T* b, T* x, hi
 }
 template void launch_coarse_solve<float>(const Grid&, const double*, const float*, float*, hipStream_t);
 template void launch_coarse_solve<double>(const Grid&, const double*, const double*, double*, hipStream_t);
+
+template <typename T>
+void launch_coarse_solve_batch(const BJob* jobs, int njobs, int blocks, hipStream_t s) {
+  coarse_solve_batch<T><<<blocks, 256, 0, s>>>(jobs, njobs);
+}
+template void launch_coarse_solve_batch<float>(const BJob*, int, int, hipStream_t);
+template void launch_coarse_solve_batch<double>(const BJob*, int, int, hipStream_t);
 
 }  // namespace mvpf

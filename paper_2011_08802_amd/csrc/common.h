@@ -340,4 +340,67 @@ void launch_convert(int64_t n, const TI* in, TO* out, hipStream_t s);
 template <typename T, typename TZ>
 void launch_precond_finish(const Grid& g, const T* x, const double* v, const uint16_t* mask, TZ* z, hipStream_t s);
 
+// ---- batched launches: one launch of an operator for many problems -----------
+// A job is one problem's part of a launch: its workgroups block0 ..
+// block0 + nblk - 1.  The job table sits in device memory, sorted by block0;
+// every workgroup finds its job by binary search.
+struct BJob {
+  Grid g;                  // the level (finest grid of a transfer)
+  Grid g2;                 // coarse grid of a transfer
+  const void* A;           // half-stencil operator, Gauss-point Hessians or dense coarse inverse
+  const void* D;           // block inverses
+  const void* x;           // input vector
+  const void* b;           // right-hand side; FP64 vector v at the preconditioner's ends
+  void* y;                 // output vector
+  void* C;                 // scratch: transposed contributions or element outputs
+  const uint16_t* mask;    // constrained-dof masks of the output's level
+  const DevCard* cd;       // material card (matrix-free element kernel)
+  double omega;            // damping of the Jacobi sweeps
+  int block0, nblk;
+};
+// job of this workgroup in a batched launch; bid = its workgroup index within the job
+__device__ inline const BJob& find_job(const BJob* __restrict__ jobs, int njobs, int& bid) {
+  int lo = 0, hi = njobs;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (jobs[mid].block0 <= (int)blockIdx.x) lo = mid; else hi = mid;
+  }
+  bid = (int)blockIdx.x - jobs[lo].block0;
+  return jobs[lo];
+}
+enum BatchOp {
+  BOP_CONVERT,          // b = mask(v), FP64 -> T
+  BOP_PBJ_ZERO,         // y = omega D^-1 b
+  BOP_DEFECT_SPLIT,     // pass 1 of b - A x (y = partial, C = transposed contributions)
+  BOP_PBJ_LOWER,        // pass 2, then y = x + omega D^-1 (b - A x)
+  BOP_DEFECT_LOWER,     // pass 2 of y = b - A x
+  BOP_ROW_SMALL_PBJ,    // small-grid Jacobi sweep
+  BOP_ROW_SMALL_DEFECT, // small-grid defect
+  BOP_RESTRICT,         // y (coarse) = masked P^T x (fine)
+  BOP_PROLONG,          // y (fine) += P x (coarse), constrained dofs untouched
+  BOP_COARSE,           // y = Ainv b (dense FP64 inverse)
+  BOP_MF_ELEMENT,       // C = element parts of K x (matrix-free finest level)
+  BOP_MF_GATHER_PBJ,    // y = x + omega D^-1 (b - sum C)
+  BOP_MF_GATHER_DEFECT, // y = b - sum C
+  BOP_FINISH,           // z = x, v on constrained dofs, T -> TZ
+};
+// workgroups one job of op needs
+int batch_job_blocks(int op, const BJob& j);
+int bsr_job_blocks(int op, const Grid& g);
+int mf_job_blocks(int op, const Grid& g);
+int vec_job_blocks(const Grid& g);
+// T: multigrid precision; TZ: type of the preconditioned vector (BOP_FINISH)
+template <typename T, typename TZ>
+void launch_batch(int op, const BJob* jobs_dev, int njobs, int total_blocks, hipStream_t s);
+template <typename T>
+void launch_bsr_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s);
+template <typename T>
+void launch_transfer_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s);
+template <typename T>
+void launch_coarse_solve_batch(const BJob* jobs, int njobs, int blocks, hipStream_t s);
+template <typename T>
+void launch_mf_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s);
+template <typename T, typename TZ>
+void launch_vec_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s);
+
 }  // namespace mvpf

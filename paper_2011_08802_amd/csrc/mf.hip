@@ -98,11 +98,16 @@ __device__ __forceinline__ void interp_pair_t(const T (&a)[n], const T (&b)[n], 
 // PF: Hessian vectors loaded ahead of the contraction (the rest are loaded
 // PF vectors ahead of their use); MINB: minimum waves per SIMD the register
 // budget is sized for.
-template <typename TD, typename TX, typename T, int MINB, int PF, bool SPARSE>
-__global__ void __launch_bounds__(256, MINB) mf_element_kernel(Grid g, const TD* __restrict__ D, const TX* __restrict__ x,
-                                                               const uint16_t* __restrict__ mask,
-                                                               const DevCard* __restrict__ cd, T* __restrict__ E) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <typename TD, typename TX, typename T, int PF, bool SPARSE>
+__device__ __forceinline__ void mf_element_body(const Grid& g, const TD* __restrict__ D, const TX* __restrict__ x,
+                                                const uint16_t* __restrict__ mask, const DevCard* __restrict__ cd,
+                                                T* __restrict__ E, int wg, int nb) {
+  // workgroups are dealt to the 8 XCDs in turn: renumber them so that each
+  // XCD takes one contiguous range of elements (corner unknowns shared by
+  // neighbouring elements then hit that XCD's L2)
+  const int xcd = wg & 7;
+  const int bid = xcd * (nb >> 3) + min(xcd, nb & 7) + (wg >> 3);
+  const int64_t t = (int64_t)bid * 256 + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const int gp = lane & 7;
   const int64_t e = (t >> 6) * 8 + (lane >> 3);
@@ -231,15 +236,21 @@ __global__ void __launch_bounds__(256, MINB) mf_element_kernel(Grid g, const TD*
     for (int c = 0; c < 9; ++c) E[eo_index(gp, c, node, g.Npad)] = out[c];
   }
 }
+template <typename TD, typename TX, typename T, int MINB, int PF, bool SPARSE>
+__global__ void __launch_bounds__(256, MINB) mf_element_kernel(Grid g, const TD* __restrict__ D, const TX* __restrict__ x,
+                                                               const uint16_t* __restrict__ mask,
+                                                               const DevCard* __restrict__ cd, T* __restrict__ E) {
+  mf_element_body<TD, TX, T, PF, SPARSE>(g, D, x, mask, cd, E, blockIdx.x, gridDim.x);
+}
 
 // Node gather with epilogue.  MODE 0: y = K x; 1: r = b - K x;
 // 2: xo = x + omega Dinv (b - K x).  Constrained rows (mask) act as the
 // identity, as in the eliminated assembled operator.
 template <int MODE, typename T, typename TX, typename TY>
-__global__ void __launch_bounds__(256) mf_gather_kernel(Grid g, const T* __restrict__ E, const uint16_t* __restrict__ mask,
-                                                        const TX* __restrict__ x, const T* __restrict__ b,
-                                                        const T* __restrict__ Dinv, T omega, TY* __restrict__ y) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void mf_gather_body(const Grid& g, const T* __restrict__ E, const uint16_t* __restrict__ mask,
+                                               const TX* __restrict__ x, const T* __restrict__ b,
+                                               const T* __restrict__ Dinv, T omega, TY* __restrict__ y, int bid) {
+  const int n = bid * 256 + threadIdx.x;
   if (n >= g.Npad) return;
   if (n >= g.N) {
 #pragma unroll
@@ -277,6 +288,12 @@ __global__ void __launch_bounds__(256) mf_gather_kernel(Grid g, const T* __restr
 #pragma unroll
     for (int c = 0; c < 9; ++c) y[(int64_t)c * g.Npad + n] = (TY)r[c];
   }
+}
+template <int MODE, typename T, typename TX, typename TY>
+__global__ void __launch_bounds__(256) mf_gather_kernel(Grid g, const T* __restrict__ E, const uint16_t* __restrict__ mask,
+                                                        const TX* __restrict__ x, const T* __restrict__ b,
+                                                        const T* __restrict__ Dinv, T omega, TY* __restrict__ y) {
+  mf_gather_body<MODE, T, TX, TY>(g, E, mask, x, b, Dinv, omega, y, blockIdx.x);
 }
 
 // Gauss-point Hessians of a slab (standard Gauss-point layout, entries
@@ -361,5 +378,35 @@ template void launch_mf_gather<1, double, double, double>(const Grid&, const dou
                                                           const double*, const double*, double, double*, hipStream_t);
 template void launch_mf_gather<2, double, double, double>(const Grid&, const double*, const uint16_t*, const double*,
                                                           const double*, const double*, double, double*, hipStream_t);
+
+// ---- batched launches (FP32 or FP64 smoothing on matrix-free finest levels) ----
+template <typename T, int MINB, int PF>
+__global__ void __launch_bounds__(256, MINB) mf_element_batch(const BJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const BJob& j = find_job(jobs, njobs, bid);
+  mf_element_body<T, T, T, PF, false>(j.g, (const T*)j.A, (const T*)j.x, j.mask, j.cd, (T*)j.C, bid, j.nblk);
+}
+template <int MODE, typename T>
+__global__ void __launch_bounds__(256) mf_gather_batch(const BJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const BJob& j = find_job(jobs, njobs, bid);
+  mf_gather_body<MODE, T, T, T>(j.g, (const T*)j.C, j.mask, (const T*)j.x, (const T*)j.b, (const T*)j.D, (T)j.omega,
+                                (T*)j.y, bid);
+}
+template <typename T>
+void launch_mf_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s) {
+  constexpr bool f64 = sizeof(T) == 8;
+  if (op == BOP_MF_ELEMENT)
+    mf_element_batch<T, f64 ? MF_MINB64 : MF_MINB32, f64 ? MF_PF64 : MF_PF32><<<blocks, 256, 0, s>>>(jobs, njobs);
+  else if (op == BOP_MF_GATHER_PBJ)
+    mf_gather_batch<2, T><<<blocks, 256, 0, s>>>(jobs, njobs);
+  else if (op == BOP_MF_GATHER_DEFECT)
+    mf_gather_batch<1, T><<<blocks, 256, 0, s>>>(jobs, njobs);
+}
+template void launch_mf_batch<float>(int, const BJob*, int, int, hipStream_t);
+template void launch_mf_batch<double>(int, const BJob*, int, int, hipStream_t);
+int mf_job_blocks(int op, const Grid& g) {
+  return op == BOP_MF_ELEMENT ? (int)(((int64_t)g.NEpad * 8 + 255) / 256) : (g.Npad + 255) / 256;
+}
 
 }  // namespace mvpf

@@ -12,9 +12,9 @@
 namespace mvpf {
 
 template <typename T>
-__global__ void __launch_bounds__(256) restrict_kernel(Grid f, Grid c, const T* __restrict__ rf,
-                                                       const uint16_t* __restrict__ cmask, T* __restrict__ bc) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void restrict_body(const Grid& f, const Grid& c, const T* __restrict__ rf,
+                                              const uint16_t* __restrict__ cmask, T* __restrict__ bc, int bid) {
+  const int I = bid * 256 + threadIdx.x;
   if (I >= c.Npad) return;
   T acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   unsigned msk = 0x1ff;
@@ -42,6 +42,11 @@ __global__ void __launch_bounds__(256) restrict_kernel(Grid f, Grid c, const T* 
 #pragma unroll
   for (int q = 0; q < 9; ++q) bc[(int64_t)q * c.Npad + I] = ((msk >> q) & 1) ? (T)0 : acc[q];
 }
+template <typename T>
+__global__ void __launch_bounds__(256) restrict_kernel(Grid f, Grid c, const T* __restrict__ rf,
+                                                       const uint16_t* __restrict__ cmask, T* __restrict__ bc) {
+  restrict_body<T>(f, c, rf, cmask, bc, blockIdx.x);
+}
 
 template <typename T>
 void launch_restrict(const Grid& fine, const Grid& coarse, const T* rf, const uint16_t* cmask, T* bc,
@@ -53,9 +58,9 @@ template void launch_restrict<double>(const Grid&, const Grid&, const double*, c
                                       hipStream_t);
 
 template <typename T>
-__global__ void __launch_bounds__(256) prolong_add_kernel(Grid f, Grid c, const T* __restrict__ ec,
-                                                          const uint16_t* __restrict__ fmask, T* __restrict__ xf) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void prolong_add_body(const Grid& f, const Grid& c, const T* __restrict__ ec,
+                                                 const uint16_t* __restrict__ fmask, T* __restrict__ xf, int bid) {
+  const int n = bid * 256 + threadIdx.x;
   if (n >= f.N) return;
   const unsigned msk = fmask[n];
   if (msk == 0x1ff) return;
@@ -78,6 +83,11 @@ __global__ void __launch_bounds__(256) prolong_add_kernel(Grid f, Grid c, const 
 #pragma unroll
   for (int q = 0; q < 9; ++q)
     if (!((msk >> q) & 1)) xf[(int64_t)q * f.Npad + n] += w * acc[q];
+}
+template <typename T>
+__global__ void __launch_bounds__(256) prolong_add_kernel(Grid f, Grid c, const T* __restrict__ ec,
+                                                          const uint16_t* __restrict__ fmask, T* __restrict__ xf) {
+  prolong_add_body<T>(f, c, ec, fmask, xf, blockIdx.x);
 }
 
 template <typename T>
@@ -119,5 +129,28 @@ __global__ void __launch_bounds__(256) inject_mask_kernel(Grid f, Grid c, const 
 void launch_inject_mask(const Grid& fine, const Grid& coarse, const uint16_t* mf, uint16_t* mc, hipStream_t s) {
   inject_mask_kernel<<<(coarse.Npad + 255) / 256, 256, 0, s>>>(fine, coarse, mf, mc);
 }
+
+// ---- batched launches: g = fine grid, g2 = coarse grid of every job ---------
+template <typename T>
+__global__ void __launch_bounds__(256) restrict_batch(const BJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const BJob& j = find_job(jobs, njobs, bid);
+  restrict_body<T>(j.g, j.g2, (const T*)j.x, j.mask, (T*)j.y, bid);
+}
+template <typename T>
+__global__ void __launch_bounds__(256) prolong_add_batch(const BJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const BJob& j = find_job(jobs, njobs, bid);
+  prolong_add_body<T>(j.g, j.g2, (const T*)j.x, j.mask, (T*)j.y, bid);
+}
+template <typename T>
+void launch_transfer_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s) {
+  if (op == BOP_RESTRICT)
+    restrict_batch<T><<<blocks, 256, 0, s>>>(jobs, njobs);
+  else if (op == BOP_PROLONG)
+    prolong_add_batch<T><<<blocks, 256, 0, s>>>(jobs, njobs);
+}
+template void launch_transfer_batch<float>(int, const BJob*, int, int, hipStream_t);
+template void launch_transfer_batch<double>(int, const BJob*, int, int, hipStream_t);
 
 }  // namespace mvpf

@@ -194,14 +194,19 @@ void launch_soa_to_interleaved(const Grid& g, const double* in, int ncomp, int c
 
 // out = in with constrained dofs (and padding) zeroed, converted to TO
 template <typename TI, typename TO>
-__global__ void __launch_bounds__(RB) convert_masked_kernel(Grid g, const TI* __restrict__ in,
-                                                            const uint16_t* __restrict__ mask, TO* __restrict__ out) {
-  const int n = blockIdx.x * RB + threadIdx.x;
+__device__ __forceinline__ void convert_masked_body(const Grid& g, const TI* __restrict__ in,
+                                                    const uint16_t* __restrict__ mask, TO* __restrict__ out, int bid) {
+  const int n = bid * RB + threadIdx.x;
   if (n >= g.Npad) return;
   const unsigned m = (n < g.N) ? mask[n] : 0x1ff;
 #pragma unroll
   for (int c = 0; c < 9; ++c)
     out[(int64_t)c * g.Npad + n] = ((m >> c) & 1) ? (TO)0 : (TO)in[(int64_t)c * g.Npad + n];
+}
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(RB) convert_masked_kernel(Grid g, const TI* __restrict__ in,
+                                                            const uint16_t* __restrict__ mask, TO* __restrict__ out) {
+  convert_masked_body<TI, TO>(g, in, mask, out, blockIdx.x);
 }
 
 template <typename TI, typename TO>
@@ -387,10 +392,10 @@ template void launch_convert<double, float>(int64_t, const double*, float*, hipS
 // Preconditioner output: z = V-cycle result on free dofs, z = v on
 // constrained dofs of the finest level (identity there).
 template <typename T, typename TZ>
-__global__ void __launch_bounds__(RB) precond_finish_kernel(Grid g, const T* __restrict__ x,
-                                                            const double* __restrict__ v,
-                                                            const uint16_t* __restrict__ mask, TZ* __restrict__ z) {
-  const int n = blockIdx.x * RB + threadIdx.x;
+__device__ __forceinline__ void precond_finish_body(const Grid& g, const T* __restrict__ x,
+                                                    const double* __restrict__ v, const uint16_t* __restrict__ mask,
+                                                    TZ* __restrict__ z, int bid) {
+  const int n = bid * RB + threadIdx.x;
   if (n >= g.Npad) return;
   const unsigned m = (n < g.N) ? mask[n] : 0;
 #pragma unroll
@@ -398,6 +403,12 @@ __global__ void __launch_bounds__(RB) precond_finish_kernel(Grid g, const T* __r
     const int64_t q = (int64_t)c * g.Npad + n;
     z[q] = ((m >> c) & 1) ? (TZ)v[q] : (TZ)x[q];
   }
+}
+template <typename T, typename TZ>
+__global__ void __launch_bounds__(RB) precond_finish_kernel(Grid g, const T* __restrict__ x,
+                                                            const double* __restrict__ v,
+                                                            const uint16_t* __restrict__ mask, TZ* __restrict__ z) {
+  precond_finish_body<T, TZ>(g, x, v, mask, z, blockIdx.x);
 }
 
 template <typename T, typename TZ>
@@ -410,5 +421,31 @@ template void launch_precond_finish<float, double>(const Grid&, const float*, co
                                                    double*, hipStream_t);
 template void launch_precond_finish<double, double>(const Grid&, const double*, const double*, const uint16_t*,
                                                     double*, hipStream_t);
+
+// batched ends of the preconditioner: BOP_CONVERT b (y, T) = masked v (b,
+// FP64); BOP_FINISH z (y, TZ) = x (T), v on constrained dofs
+template <typename T>
+__global__ void __launch_bounds__(RB) convert_masked_batch(const BJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const BJob& j = find_job(jobs, njobs, bid);
+  convert_masked_body<double, T>(j.g, (const double*)j.b, j.mask, (T*)j.y, bid);
+}
+template <typename T, typename TZ>
+__global__ void __launch_bounds__(RB) precond_finish_batch(const BJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const BJob& j = find_job(jobs, njobs, bid);
+  precond_finish_body<T, TZ>(j.g, (const T*)j.x, (const double*)j.b, j.mask, (TZ*)j.y, bid);
+}
+template <typename T, typename TZ>
+void launch_vec_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s) {
+  if (op == BOP_CONVERT)
+    convert_masked_batch<T><<<blocks, RB, 0, s>>>(jobs, njobs);
+  else if (op == BOP_FINISH)
+    precond_finish_batch<T, TZ><<<blocks, RB, 0, s>>>(jobs, njobs);
+}
+template void launch_vec_batch<float, float>(int, const BJob*, int, int, hipStream_t);
+template void launch_vec_batch<float, double>(int, const BJob*, int, int, hipStream_t);
+template void launch_vec_batch<double, double>(int, const BJob*, int, int, hipStream_t);
+int vec_job_blocks(const Grid& g) { return (g.Npad + RB - 1) / RB; }
 
 }  // namespace mvpf

@@ -1,5 +1,6 @@
 """Batches of independent problems (mvpf_create_batch): lockstep FGMRES with
-the V-cycles of all problems in one captured HIP graph.
+the V-cycles of all problems in one captured HIP graph, one launch per
+V-cycle operator for all problems.
 
 * Every problem's result is bitwise the one of solving it alone (same kernels
   in the same order), on every replay of the graph, with eager work on the
