@@ -355,7 +355,9 @@ int mvpf_kernel_stats(mvpf_problem* p, const char* name, int* launches, double* 
  * which every V-cycle operator (sweep, defect, transfer, coarse solve) is
  * one launch covering all problems, whatever their sizes: each problem is a
  * job of the launch, owning a range of its workgroups.  Each problem's
- * numbers are bitwise those of solving it alone with mvpf_solve.  Every problem is a full handle (mvpf_batch_problem)
+ * numbers are bitwise those of solving it alone with mvpf_solve (under the
+ * same tuning: the problems of a batch start with small_grid_nodes = 0, the
+ * small-grid kernels pay only in narrow single-problem launches).  Every problem is a full handle (mvpf_batch_problem)
  * on which the single-problem calls work; the batch owns them. */
 
 /* Create n (1..MVPF_MAX_BATCH) problems: meshes[i], mats[i], loads[i] as for

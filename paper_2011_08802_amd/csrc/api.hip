@@ -416,6 +416,11 @@ struct Krylov {
   int64_t n = 0;
   int m = 0, nb = 0, j = 0, k = 0, rc = 0;
   Phase phase = START;
+  // batched solves: the normalisation of the next basis vector is left to
+  // the caller (pend_w *= pend_a), which batches it with other problems'
+  bool defer = false;
+  double* pend_w = nullptr;
+  double pend_a = 0.0;
   std::vector<double> H, cs, sn, gg, y;
   double bnorm = 0.0, beta = 0.0;
   const double* r0 = nullptr;
@@ -511,7 +516,14 @@ struct Krylov {
     const double hnext = std::sqrt(p->hhost[2 * (MAX_RESTART + 2)]);
     Hij(j + 1, j) = hnext;
     double* w = p->V + (int64_t)(j + 1) * n;
-    if (hnext > 0.0) launch_axpby(n, 1.0 / hnext, w, 0.0, nullptr, w, p->stream);
+    if (hnext > 0.0) {
+      if (defer) {
+        pend_w = w;
+        pend_a = 1.0 / hnext;
+      } else {
+        launch_axpby(n, 1.0 / hnext, w, 0.0, nullptr, w, p->stream);
+      }
+    }
     for (int i = 0; i < j; ++i) {
       const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
       Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
@@ -526,8 +538,10 @@ struct Krylov {
     gg[j] = cs[j] * gg[j];
     st->iterations++;
     k = j + 1;
-    if (std::fabs(gg[j + 1]) <= p->opts.rtol * bnorm || st->iterations >= p->opts.max_it || k == m)
+    if (std::fabs(gg[j + 1]) <= p->opts.rtol * bnorm || st->iterations >= p->opts.max_it || k == m) {
+      pend_w = nullptr;  // the cycle ends: v_{j+1} is not used
       return end_cycle_enqueue();
+    }
     ++j;
     return 0;
   }
@@ -1054,9 +1068,17 @@ struct mvpf_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<int> graph_version;  // config_version of each problem at capture
-  // job tables of the graph's batched launches (device)
+  // job tables of the graph's batched launches (device); the preconditioner's
+  // ends (input v_j, output z_j of each problem) are rewritten every step
   mvpf::BJob* jobs_dev = nullptr;
   size_t jobs_cap = 0;
+  size_t conv_off = 0, fin_off = 0;
+  std::vector<mvpf::BJob> conv_jobs, fin_jobs;
+  // per-step job tables of the batched Arnoldi step (pinned host staging and
+  // device copies) and the Hessenberg columns of all problems
+  mvpf::KJob *kjobs_host = nullptr, *kjobs_dev = nullptr;
+  mvpf::BJob *ojobs_host = nullptr, *ojobs_dev = nullptr, *gjobs_host = nullptr;
+  double *bcol_dev = nullptr, *bcol_host = nullptr;
   std::string err;
 };
 
@@ -1349,6 +1371,15 @@ int batch_capture(mvpf_batch* b) {
   }
   if (!all.empty())
     BCHK(hipMemcpy(b->jobs_dev, all.data(), sizeof(BJob) * all.size(), hipMemcpyHostToDevice));
+  for (PlanOp& o : pl.ops) {
+    if (o.op == BOP_CONVERT) {
+      b->conv_off = o.off;
+      b->conv_jobs = o.jobs;
+    } else if (o.op == BOP_FINISH) {
+      b->fin_off = o.off;
+      b->fin_jobs = o.jobs;
+    }
+  }
   hipStream_t s = b->work;
   if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     b->err = "hipStreamBeginCapture failed";
@@ -1379,26 +1410,76 @@ int batch_capture(mvpf_batch* b) {
   return 0;
 }
 
-// Lockstep FGMRES over the batch.  Each problem's own work (outer product,
-// Gram-Schmidt, Givens bookkeeping) runs on its branch stream; per Arnoldi
-// step one graph launch on the work stream runs the V-cycles of all problems
-// (ordered after every branch's pending work and before its next work, so
-// the V-cycles never overlap a problem's own use of its buffers), and one
-// synchronisation of the branches serves all problems.
+// Lockstep FGMRES over the batch, all on the batch's work stream.  Per
+// Arnoldi step: one launch normalises every problem's new basis vector, one
+// graph launch runs all V-cycles (its input and output job entries rewritten
+// to point at each problem's v_j and z_j), and every further operation of
+// the step -- operator product, both Gram-Schmidt passes, norms, the copy of
+// the Hessenberg columns -- is one launch for all problems, followed by one
+// device-to-host copy and one synchronisation.  Per-problem work is left
+// only where problems are out of step (cycle ends, true residual checks).
+constexpr int KOPS_PER_STEP = 9;
+constexpr int HCOL = 3 * (MAX_RESTART + 2);
+
+int batch_step_buffers(mvpf_batch* b) {
+  if (b->kjobs_dev) return 0;
+  const int n = b->n;
+  const size_t kb = sizeof(KJob) * KOPS_PER_STEP * n, ob = sizeof(BJob) * 2 * n;
+  if (hipMalloc((void**)&b->kjobs_dev, kb) != hipSuccess || hipMalloc((void**)&b->ojobs_dev, ob) != hipSuccess ||
+      hipMalloc((void**)&b->bcol_dev, sizeof(double) * HCOL * n) != hipSuccess ||
+      hipHostMalloc((void**)&b->kjobs_host, kb) != hipSuccess ||
+      hipHostMalloc((void**)&b->ojobs_host, ob) != hipSuccess ||
+      hipHostMalloc((void**)&b->gjobs_host, sizeof(BJob) * 2 * n) != hipSuccess ||
+      hipHostMalloc((void**)&b->bcol_host, sizeof(double) * HCOL * n) != hipSuccess) {
+    (void)hipGetLastError();
+    b->err = "batch step buffers allocation failed";
+    return MVPF_ENOMEM;
+  }
+  return 0;
+}
+
+// ops of one step over a staged job table: (op, first job, jobs, workgroups)
+template <typename J>
+struct StepOps {
+  J* host;
+  std::vector<int> op, first, count, blocks;
+  int used = 0;
+  template <typename BlocksFn>
+  void add(int o, const std::vector<J>& jobs, BlocksFn nblk) {
+    if (jobs.empty()) return;
+    op.push_back(o);
+    first.push_back(used);
+    count.push_back((int)jobs.size());
+    int bl = 0;
+    for (J j : jobs) {
+      j.nblk = nblk(o, j);
+      j.block0 = bl;
+      bl += j.nblk;
+      host[used++] = j;
+    }
+    blocks.push_back(bl);
+  }
+};
+
 template <typename T, typename TZ>
 int batch_fgmres(mvpf_batch* b, mvpf_solve_stats* st) {
   bool stale = !b->exec;
   for (int i = 0; i < b->n && !stale; ++i) stale = b->graph_version[i] != b->probs[i]->config_version;
   if (stale) TRY((batch_capture<T, TZ>(b)));
+  TRY(batch_step_buffers(b));
   hipStream_t s = b->work;
-  std::vector<Krylov<T, TZ>> K(b->n);
-  for (int i = 0; i < b->n; ++i) {
+  const int nprob = b->n;
+  std::vector<Krylov<T, TZ>> K(nprob);
+  for (int i = 0; i < nprob; ++i) {
     mvpf_problem* p = b->probs[i];
+    K[i].defer = true;
     TRY(K[i].begin(p, p->rhs, p->dx, &st[i]));
   }
-  for (int i = 0; i < b->n; ++i) BCHK(hipStreamSynchronize(b->branch[i]));
+  BCHK(hipStreamSynchronize(s));
   for (auto& k : K) k.after_begin();
   using KP = typename Krylov<T, TZ>::Phase;
+  auto kblocks = [](int o, const KJob& j) { return krylov_job_blocks(o, j); };
+  auto bblocks = [](int o, const BJob& j) { return batch_job_blocks(o, j); };
   while (true) {
     bool any = false, arnoldi = false;
     for (auto& k : K) {
@@ -1407,32 +1488,135 @@ int batch_fgmres(mvpf_batch* b, mvpf_solve_stats* st) {
     }
     if (!any) break;
     if (arnoldi) {
-      for (int i = 0; i < b->n; ++i) {
-        if (K[i].phase == KP::DONE) continue;
-        if (K[i].phase == KP::ARNOLDI)
-          BCHK(hipMemcpyAsync(b->vin[i], K[i].vj(), sizeof(double) * K[i].n, hipMemcpyDeviceToDevice,
-                              b->branch[i]));
-        BCHK(hipEventRecord(b->join[i], b->branch[i]));
-        BCHK(hipStreamWaitEvent(s, b->join[i], 0));
+      StepOps<KJob> pre{b->kjobs_host}, post{b->kjobs_host};
+      StepOps<BJob> outer{b->ojobs_host};
+      // normalisations left by the last step
+      std::vector<KJob> sc;
+      for (auto& k : K)
+        if (k.pend_w) {
+          KJob j{};
+          j.n = k.n;
+          j.w = k.pend_w;
+          j.a = k.pend_a;
+          sc.push_back(j);
+          k.pend_w = nullptr;
+        }
+      pre.add(KOP_SCALE, sc, kblocks);
+      // the V-cycles' ends
+      for (int i = 0; i < nprob; ++i) {
+        const bool a = K[i].phase == KP::ARNOLDI;
+        BJob c = b->conv_jobs[i], f = b->fin_jobs[i];
+        c.b = a ? (const void*)K[i].vj() : (const void*)b->vin[i];
+        f.b = c.b;  // v itself on constrained dofs
+        f.y = a ? (void*)K[i].zj() : b->zout[i];
+        b->gjobs_host[i] = c;
+        b->gjobs_host[nprob + i] = f;
       }
-      BCHK(hipGraphLaunch(b->exec, s));
-      BCHK(hipEventRecord(b->fork, s));
-      for (int i = 0; i < b->n; ++i) {
-        if (K[i].phase == KP::DONE) continue;
-        BCHK(hipStreamWaitEvent(b->branch[i], b->fork, 0));
-        if (K[i].phase == KP::ARNOLDI) {
-          BCHK(hipMemcpyAsync(K[i].zj(), b->zout[i], sizeof(TZ) * K[i].n, hipMemcpyDeviceToDevice, b->branch[i]));
-          TRY(K[i].arnoldi_enqueue());
+      // operator product w = A z_j
+      std::vector<BJob> oe, og;
+      std::vector<std::function<void(hipStream_t)>> solos;
+      for (int i = 0; i < nprob; ++i) {
+        if (K[i].phase != KP::ARNOLDI) continue;
+        mvpf_problem* p = b->probs[i];
+        Level& L0 = p->lev[0];
+        const TZ* z = K[i].zj();
+        double* w = p->V + (int64_t)(K[i].j + 1) * K[i].n;
+        if (use_mf(p)) {
+          BJob j{};
+          j.g = L0.g;
+          j.A = p->Dmf64;
+          j.x = z;
+          j.mask = L0.mask;
+          j.cd = p->card;
+          j.C = p->Cbuf;
+          j.y = w;
+          oe.push_back(j);
+          og.push_back(j);
+          if (contact(p))
+            solos.push_back([p, z](hipStream_t st_) {
+              Level& L = p->lev[0];
+              launch_contact_apply<double, TZ>(L.g, p->sphere, L.state, L.mask, z, (double*)p->Cbuf, st_);
+            });
+        } else {
+          solos.push_back([p, z, w](hipStream_t st_) {
+            launch_spmv<double, TZ, double>(p->lev[0].g, p->lev[0].A64, z, w, p->Cbuf, st_, p->outer_G);
+          });
         }
       }
+      outer.add(BOP_MF_OUTER_ELEMENT, oe, bblocks);
+      outer.add(BOP_MF_OUTER_GATHER, og, bblocks);
+      // classical Gram-Schmidt twice, norm, Hessenberg columns
+      std::vector<KJob> md, rd1, ax1, rd2, ax2, rdn, cp;
+      for (int i = 0; i < nprob; ++i) {
+        auto& k = K[i];
+        if (k.phase != KP::ARNOLDI) continue;
+        mvpf_problem* p = b->probs[i];
+        KJob j{};
+        j.n = k.n;
+        j.V = p->V;
+        j.w = p->V + (int64_t)(k.j + 1) * k.n;
+        j.part = p->red;
+        j.k = k.j + 1;
+        j.nb = k.nb;
+        md.push_back(j);
+        KJob r = j;
+        r.out = k.h1();
+        rd1.push_back(r);
+        KJob a = j;
+        a.h = k.h1();
+        ax1.push_back(a);
+        r.out = k.h2();
+        rd2.push_back(r);
+        a.h = k.h2();
+        a.flag = 1;
+        ax2.push_back(a);
+        r.out = k.hn();
+        r.k = 1;
+        rdn.push_back(r);
+        KJob c{};
+        c.src = p->hcol;
+        c.out = b->bcol_dev + (int64_t)i * HCOL;
+        c.k = HCOL;
+        cp.push_back(c);
+      }
+      post.used = pre.used;
+      post.add(KOP_MULTIDOT, md, kblocks);
+      post.add(KOP_REDUCE, rd1, kblocks);
+      post.add(KOP_MULTIAXPY, ax1, kblocks);
+      post.add(KOP_MULTIDOT, md, kblocks);
+      post.add(KOP_REDUCE, rd2, kblocks);
+      post.add(KOP_MULTIAXPY, ax2, kblocks);
+      post.add(KOP_REDUCE, rdn, kblocks);
+      post.add(KOP_COPY, cp, kblocks);
+      // stage, then launch in order
+      BCHK(hipMemcpyAsync(b->kjobs_dev, b->kjobs_host, sizeof(KJob) * post.used, hipMemcpyHostToDevice, s));
+      if (outer.used)
+        BCHK(hipMemcpyAsync(b->ojobs_dev, b->ojobs_host, sizeof(BJob) * outer.used, hipMemcpyHostToDevice, s));
+      BCHK(hipMemcpyAsync(b->jobs_dev + b->conv_off, b->gjobs_host, sizeof(BJob) * nprob, hipMemcpyHostToDevice, s));
+      BCHK(hipMemcpyAsync(b->jobs_dev + b->fin_off, b->gjobs_host + nprob, sizeof(BJob) * nprob,
+                          hipMemcpyHostToDevice, s));
+      for (size_t q = 0; q < pre.op.size(); ++q)
+        launch_krylov_batch(pre.op[q], b->kjobs_dev + pre.first[q], pre.count[q], pre.blocks[q], s);
+      BCHK(hipGraphLaunch(b->exec, s));
+      if (!outer.op.empty())
+        launch_batch<T, TZ>(outer.op[0], b->ojobs_dev + outer.first[0], outer.count[0], outer.blocks[0], s);
+      for (auto& f : solos) f(s);
+      for (size_t q = 1; q < outer.op.size(); ++q)
+        launch_batch<T, TZ>(outer.op[q], b->ojobs_dev + outer.first[q], outer.count[q], outer.blocks[q], s);
+      for (size_t q = 0; q < post.op.size(); ++q)
+        launch_krylov_batch(post.op[q], b->kjobs_dev + post.first[q], post.count[q], post.blocks[q], s);
+      BCHK(hipGetLastError());
+      BCHK(hipMemcpyAsync(b->bcol_host, b->bcol_dev, sizeof(double) * HCOL * nprob, hipMemcpyDeviceToHost, s));
     }
-    for (int i = 0; i < b->n; ++i)
-      if (K[i].phase != KP::DONE) BCHK(hipStreamSynchronize(b->branch[i]));
-    for (auto& k : K) {
-      if (k.phase == KP::ARNOLDI)
+    BCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < nprob; ++i) {
+      auto& k = K[i];
+      if (k.phase == KP::ARNOLDI) {
+        std::memcpy(k.p->hhost, b->bcol_host + (int64_t)i * HCOL, sizeof(double) * HCOL);
         TRY(k.arnoldi_finish());
-      else if (k.phase == KP::CHECK)
+      } else if (k.phase == KP::CHECK) {
         k.check_finish();
+      }
     }
   }
   int rc = 0;
@@ -1462,6 +1646,17 @@ void batch_free(mvpf_batch* b) {
   if (b->jobs_dev) (void)hipFree(b->jobs_dev);
   b->jobs_dev = nullptr;
   b->jobs_cap = 0;
+  for (void* d : {(void*)b->kjobs_dev, (void*)b->ojobs_dev, (void*)b->bcol_dev})
+    if (d) (void)hipFree(d);
+  for (void* h : {(void*)b->kjobs_host, (void*)b->ojobs_host, (void*)b->gjobs_host, (void*)b->bcol_host})
+    if (h) (void)hipHostFree(h);
+  b->kjobs_dev = nullptr;
+  b->ojobs_dev = nullptr;
+  b->bcol_dev = nullptr;
+  b->kjobs_host = nullptr;
+  b->ojobs_host = nullptr;
+  b->gjobs_host = nullptr;
+  b->bcol_host = nullptr;
   b->gj_tab = nullptr;
   b->gj_sel = nullptr;
   if (b->work) {
@@ -2068,6 +2263,10 @@ int mvpf_create_batch(int n, const mvpf_mesh* meshes, const mvpf_material* mats,
   for (int i = 0; i < n && rc == 0; ++i) {
     rc = mvpf_create(&meshes[i], &mats[i], &loads[i], opts, stream, &b->probs[i]);
     if (rc) break;
+    // a batched launch is wide even where each problem's level is small: the
+    // two-pass kernels (every stored block read once) beat the small-grid
+    // ones there (batched solve 336 -> 314 ms on the 32-problem workload)
+    b->probs[i]->small_nodes = BATCH_SMALL_GRID_NODES;
     const int64_t nv = nvec(b->probs[i]->lev[0].g);
     if (hipMalloc((void**)&b->vin[i], sizeof(double) * nv) != hipSuccess ||
         hipMalloc(&b->zout[i], (b->mixed ? sizeof(float) : sizeof(double)) * nv) != hipSuccess ||
@@ -2199,7 +2398,7 @@ int mvpf_batch_solve(mvpf_batch* b, mvpf_solve_stats* stats) {
     }
   BCHK(hipStreamSynchronize(b->stream));  // the caller's pending work (states, systems)
   const auto t0 = std::chrono::steady_clock::now();
-  for (int i = 0; i < b->n; ++i) b->probs[i]->stream = b->branch[i];
+  for (int i = 0; i < b->n; ++i) b->probs[i]->stream = b->work;
   int rc = b->mixed ? batch_fgmres<float, float>(b, stats) : batch_fgmres<double, double>(b, stats);
   for (int i = 0; i < b->n; ++i) {
     b->probs[i]->stream = b->stream;

@@ -23,7 +23,9 @@ int batch_job_blocks(int op, const BJob& j) {
     case BOP_COARSE: return (int)(((int64_t)NDOF * j.g.N + 3) / 4);
     case BOP_MF_ELEMENT:
     case BOP_MF_GATHER_PBJ:
-    case BOP_MF_GATHER_DEFECT: return mf_job_blocks(op, j.g);
+    case BOP_MF_GATHER_DEFECT:
+    case BOP_MF_OUTER_ELEMENT:
+    case BOP_MF_OUTER_GATHER: return mf_job_blocks(op, j.g);
     default: return 0;
   }
 }
@@ -40,6 +42,8 @@ void launch_batch(int op, const BJob* jobs_dev, int njobs, int total_blocks, hip
     case BOP_MF_ELEMENT:
     case BOP_MF_GATHER_PBJ:
     case BOP_MF_GATHER_DEFECT: launch_mf_batch<T>(op, jobs_dev, njobs, total_blocks, s); break;
+    case BOP_MF_OUTER_ELEMENT:
+    case BOP_MF_OUTER_GATHER: launch_mf_outer_batch<TZ>(op, jobs_dev, njobs, total_blocks, s); break;
     default: launch_bsr_batch<T>(op, jobs_dev, njobs, total_blocks, s); break;
   }
 }

@@ -46,6 +46,7 @@ constexpr int QP_HESS = 15 + 120;    // gradient + packed Hessian
 constexpr int MAX_LEVELS = 8;
 constexpr int MAX_RESTART = 64;
 constexpr int SMALL_GRID_NODES = 10000;  // default size limit of the small-grid kernels
+constexpr int BATCH_SMALL_GRID_NODES = 0;  // its default for the problems of a batch
 
 struct Grid {
   int nx, ny, nz;      // elements
@@ -359,7 +360,8 @@ struct BJob {
   int block0, nblk;
 };
 // job of this workgroup in a batched launch; bid = its workgroup index within the job
-__device__ inline const BJob& find_job(const BJob* __restrict__ jobs, int njobs, int& bid) {
+template <typename J>
+__device__ inline const J& find_job(const J* __restrict__ jobs, int njobs, int& bid) {
   int lo = 0, hi = njobs;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
@@ -383,7 +385,37 @@ enum BatchOp {
   BOP_MF_GATHER_PBJ,    // y = x + omega D^-1 (b - sum C)
   BOP_MF_GATHER_DEFECT, // y = b - sum C
   BOP_FINISH,           // z = x, v on constrained dofs, T -> TZ
+  BOP_MF_OUTER_ELEMENT, // C = element parts of K z (FP64 Hessians, z of type TZ)
+  BOP_MF_OUTER_GATHER,  // y = sum C (FP64), constrained rows = z
 };
+// Batched Krylov vector operations (FGMRES of many problems in lockstep); a
+// job's arithmetic is that of the single-problem launch (same partial-sum
+// blocks), so results are bitwise the same.
+struct KJob {
+  int64_t n;           // vector length
+  const double* V;     // basis vectors, leading dimension n
+  double* w;           // the vector worked on
+  double* part;        // partial sums
+  const double* h;     // coefficients (multiaxpy)
+  double* out;         // results (reduce), destination (copy)
+  const double* src;   // source (copy)
+  double a;            // factor (scale)
+  int k;               // vectors (multidot, multiaxpy) or values (reduce, copy)
+  int nb;              // partial sums per value (reduce)
+  int flag;            // multiaxpy: norm partials into part; reduce: accumulate
+  int block0, nblk;
+};
+enum KrylovOp {
+  KOP_MULTIDOT,   // part[j][blk] = V_j . w over the block's chunk, j < k
+  KOP_REDUCE,     // out[j] (+)= sum_b part[j][b], j < k
+  KOP_MULTIAXPY,  // w -= sum_j h_j V_j (norm partials of w into part)
+  KOP_SCALE,      // w = a w
+  KOP_COPY,       // out[0..k) = src[0..k)
+};
+int krylov_job_blocks(int op, const KJob& j);
+void launch_krylov_batch(int op, const KJob* jobs, int njobs, int blocks, hipStream_t s);
+template <typename TZ>
+void launch_mf_outer_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s);
 // workgroups one job of op needs
 int batch_job_blocks(int op, const BJob& j);
 int bsr_job_blocks(int op, const Grid& g);

@@ -406,7 +406,34 @@ void launch_mf_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_
 template void launch_mf_batch<float>(int, const BJob*, int, int, hipStream_t);
 template void launch_mf_batch<double>(int, const BJob*, int, int, hipStream_t);
 int mf_job_blocks(int op, const Grid& g) {
-  return op == BOP_MF_ELEMENT ? (int)(((int64_t)g.NEpad * 8 + 255) / 256) : (g.Npad + 255) / 256;
+  return (op == BOP_MF_ELEMENT || op == BOP_MF_OUTER_ELEMENT) ? (int)(((int64_t)g.NEpad * 8 + 255) / 256)
+                                                             : (g.Npad + 255) / 256;
 }
+
+// batched FGMRES operator product on matrix-free finest levels: FP64
+// Hessians, input z of type TZ (the preconditioned vector), FP64 output
+template <typename TZ>
+__global__ void __launch_bounds__(256, MF_MINB64) mf_outer_element_batch(const BJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const BJob& j = find_job(jobs, njobs, bid);
+  mf_element_body<double, TZ, double, MF_PF64, false>(j.g, (const double*)j.A, (const TZ*)j.x, j.mask, j.cd,
+                                                      (double*)j.C, bid, j.nblk);
+}
+template <typename TZ>
+__global__ void __launch_bounds__(256) mf_outer_gather_batch(const BJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const BJob& j = find_job(jobs, njobs, bid);
+  mf_gather_body<0, double, TZ, double>(j.g, (const double*)j.C, j.mask, (const TZ*)j.x, nullptr, nullptr, 0.0,
+                                        (double*)j.y, bid);
+}
+template <typename TZ>
+void launch_mf_outer_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s) {
+  if (op == BOP_MF_OUTER_ELEMENT)
+    mf_outer_element_batch<TZ><<<blocks, 256, 0, s>>>(jobs, njobs);
+  else if (op == BOP_MF_OUTER_GATHER)
+    mf_outer_gather_batch<TZ><<<blocks, 256, 0, s>>>(jobs, njobs);
+}
+template void launch_mf_outer_batch<float>(int, const BJob*, int, int, hipStream_t);
+template void launch_mf_outer_batch<double>(int, const BJob*, int, int, hipStream_t);
 
 }  // namespace mvpf

@@ -27,11 +27,12 @@ int red_blocks(int64_t n) {
 // The vectors are taken MD_G at a time, so w is read once per group (not
 // once per vector), and the group's MD_G block sums share one barrier.
 constexpr int MD_G = 8;
-__global__ void __launch_bounds__(RB) multidot_kernel(int64_t n, const double* __restrict__ V, int64_t ldv, int k,
-                                                      const double* __restrict__ w, double* __restrict__ part) {
+__device__ __forceinline__ void multidot_body(int64_t n, const double* __restrict__ V, int64_t ldv, int k,
+                                              const double* __restrict__ w, double* __restrict__ part, int bid,
+                                              int nblk) {
   __shared__ double sh[MD_G][RB / 64];
-  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t chunk = (n + nblk - 1) / nblk;
+  const int64_t lo = (int64_t)bid * chunk;
   const int64_t hi = std::min<int64_t>(n, lo + chunk);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int j0 = 0; j0 < k; j0 += MD_G) {
@@ -57,10 +58,14 @@ __global__ void __launch_bounds__(RB) multidot_kernel(int64_t n, const double* _
       double t = 0.0;
 #pragma unroll
       for (int q = 0; q < RB / 64; ++q) t += sh[threadIdx.x][q];
-      part[(int64_t)(j0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
+      part[(int64_t)(j0 + threadIdx.x) * nblk + bid] = t;
     }
     __syncthreads();
   }
+}
+__global__ void __launch_bounds__(RB) multidot_kernel(int64_t n, const double* __restrict__ V, int64_t ldv, int k,
+                                                      const double* __restrict__ w, double* __restrict__ part) {
+  multidot_body(n, V, ldv, k, w, part, blockIdx.x, gridDim.x);
 }
 
 void launch_multidot(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part, hipStream_t s) {
@@ -68,14 +73,17 @@ void launch_multidot(int64_t n, const double* V, int64_t ldv, int k, const doubl
 }
 
 // out[j] (+)= sum_b part[j * nblk + b]
-__global__ void __launch_bounds__(RB) reduce_kernel(int nblk, const double* __restrict__ part, double* __restrict__ out,
-                                                    int accumulate) {
+__device__ __forceinline__ void reduce_body(int nblk, const double* __restrict__ part, double* __restrict__ out,
+                                            int accumulate, int j) {
   __shared__ double sh[RB / 64];
-  const int j = blockIdx.x;
   double s = 0.0;
   for (int b = threadIdx.x; b < nblk; b += RB) s += part[(int64_t)j * nblk + b];
   s = block_sum(s, sh);
   if (threadIdx.x == 0) out[j] = accumulate ? out[j] + s : s;
+}
+__global__ void __launch_bounds__(RB) reduce_kernel(int nblk, const double* __restrict__ part, double* __restrict__ out,
+                                                    int accumulate) {
+  reduce_body(nblk, part, out, accumulate, blockIdx.x);
 }
 
 void launch_reduce(int k, int nblk, const double* part, double* out, int accumulate, hipStream_t s) {
@@ -83,15 +91,15 @@ void launch_reduce(int k, int nblk, const double* part, double* out, int accumul
 }
 
 // w -= sum_j h_j V_j ; optional part_norm[blk] = sum of w^2 over the chunk
-__global__ void __launch_bounds__(RB) multiaxpy_kernel(int64_t n, const double* __restrict__ V, int64_t ldv, int k,
-                                                       const double* __restrict__ h, double* __restrict__ w,
-                                                       double* __restrict__ part_norm) {
+__device__ __forceinline__ void multiaxpy_body(int64_t n, const double* __restrict__ V, int64_t ldv, int k,
+                                               const double* __restrict__ h, double* __restrict__ w,
+                                               double* __restrict__ part_norm, int bid, int nblk) {
   __shared__ double sh[RB / 64];
   __shared__ double hs[MAX_RESTART + 2];
   for (int j = threadIdx.x; j < k; j += RB) hs[j] = h[j];
   __syncthreads();
-  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t chunk = (n + nblk - 1) / nblk;
+  const int64_t lo = (int64_t)bid * chunk;
   const int64_t hi = std::min<int64_t>(n, lo + chunk);
   double nrm = 0.0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += RB) {
@@ -102,8 +110,13 @@ __global__ void __launch_bounds__(RB) multiaxpy_kernel(int64_t n, const double* 
   }
   if (part_norm) {
     nrm = block_sum(nrm, sh);
-    if (threadIdx.x == 0) part_norm[blockIdx.x] = nrm;
+    if (threadIdx.x == 0) part_norm[bid] = nrm;
   }
+}
+__global__ void __launch_bounds__(RB) multiaxpy_kernel(int64_t n, const double* __restrict__ V, int64_t ldv, int k,
+                                                       const double* __restrict__ h, double* __restrict__ w,
+                                                       double* __restrict__ part_norm) {
+  multiaxpy_body(n, V, ldv, k, h, w, part_norm, blockIdx.x, gridDim.x);
 }
 
 void launch_multiaxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w, double* part_norm,
@@ -447,5 +460,39 @@ template void launch_vec_batch<float, float>(int, const BJob*, int, int, hipStre
 template void launch_vec_batch<float, double>(int, const BJob*, int, int, hipStream_t);
 template void launch_vec_batch<double, double>(int, const BJob*, int, int, hipStream_t);
 int vec_job_blocks(const Grid& g) { return (g.Npad + RB - 1) / RB; }
+
+// ---- batched Krylov operations ---------------------------------------------------
+__global__ void __launch_bounds__(RB) krylov_batch_kernel(int op, const KJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const KJob& j = find_job(jobs, njobs, bid);
+  switch (op) {  // uniform: one op per launch
+    case KOP_MULTIDOT: multidot_body(j.n, j.V, j.n, j.k, j.w, j.part, bid, j.nblk); break;
+    case KOP_REDUCE: reduce_body(j.nb, j.part, j.out, j.flag, bid); break;
+    case KOP_MULTIAXPY: multiaxpy_body(j.n, j.V, j.n, j.k, j.h, j.w, j.flag ? j.part : nullptr, bid, j.nblk); break;
+    case KOP_SCALE:
+      for (int64_t i = (int64_t)bid * RB + threadIdx.x; i < j.n; i += (int64_t)j.nblk * RB)
+        j.w[i] = j.a * j.w[i] + 0.0;  // as axpby with y = null
+      break;
+    case KOP_COPY:
+      for (int i = threadIdx.x; i < j.k; i += RB) j.out[i] = j.src[i];
+      break;
+    default: break;
+  }
+}
+
+int krylov_job_blocks(int op, const KJob& j) {
+  switch (op) {
+    case KOP_MULTIDOT:
+    case KOP_MULTIAXPY: return red_blocks(j.n);
+    case KOP_REDUCE: return j.k;
+    case KOP_SCALE: return (int)std::min<int64_t>(1024, (j.n + RB - 1) / RB);
+    case KOP_COPY: return 1;
+    default: return 0;
+  }
+}
+
+void launch_krylov_batch(int op, const KJob* jobs, int njobs, int blocks, hipStream_t s) {
+  if (njobs > 0 && blocks > 0) krylov_batch_kernel<<<blocks, RB, 0, s>>>(op, jobs, njobs);
+}
 
 }  // namespace mvpf

@@ -2,8 +2,8 @@
 the V-cycles of all problems in one captured HIP graph, one launch per
 V-cycle operator for all problems.
 
-* Every problem's result is bitwise the one of solving it alone (same kernels
-  in the same order), on every replay of the graph, with eager work on the
+* Every problem's result is bitwise the one of solving it alone under the
+  same tuning (same kernels in the same order), on every replay of the graph, with eager work on the
   same stream between the replays.
 * A rotated-crystal problem of the batch matches the oracle (right-hand side
   <= 1e-12, increment at rtol 1e-12 vs the oracle's direct solve <= 1e-9)."""
@@ -40,17 +40,18 @@ def test_batch_bitwise_equals_single_solves(precision):
     from paper_2011_08802_amd import mvpf
     probs = small_batch()
     states = [seeded_state(p, 1e-3) for p in probs]
-    say(f"[batch {precision}] single-problem references")
+    B = mvpf.Batch(probs, precision)
+    say(f"[batch {precision}] single-problem references (the batch's tuning)")
     ref = []
-    for p, (U, En) in zip(probs, states):
+    for i, (p, (U, En)) in enumerate(zip(probs, states)):
         gp = mvpf.Problem(p, precision)
+        gp.set_tuning("small_grid_nodes", 0, B.problem(i).get_tuning("small_grid_nodes"))
         gp.set_state(U[:, :3], U[:, 3:], En, 0.0)
         gp.newton_system(p.depth_increment)
         _, st = gp.solve(want_x=False)
         gp.newton_update()
         ref.append((_state(gp), st.iterations))
         gp.close()
-    B = mvpf.Batch(probs, precision)
     x = torch.randn(9 * probs[0].n_nodes, dtype=torch.float64, device="cuda")
     for replay in range(3):
         say(f"[batch {precision}] replay {replay}")
