@@ -236,7 +236,7 @@ def batched_main(a):
         "data": "synthetic",
         "config": {"workload": f"batched: {len(probs)} patch-indentation problems, n^3 hex with n in "
                                f"{{16,24,32,40,48}}, random crystal rotations, depths U[0.005,0.02], "
-                               f"{ndof} dof in total, 4-level GMG V(2,2), FGMRES(30) rtol 1e-8",
+                               f"{ndof} dof in total, 4-5-level GMG V(2,2) (n halved while even and at least 2), FGMRES(30) rtol 1e-8",
                    "sizes": sizes, "precision": "mixed"},
         "mixed": ms,
         "sequential_mixed": seq,

@@ -835,16 +835,46 @@ int* setup_status(mvpf_problem* p) { return (int*)p->red; }  // first word of th
 // coarse_inline = false (batches): the coarsest operator is gathered into its
 // dense matrix on the problem's stream, ev_fork marks it ready, and the
 // batch inverts all problems' matrices at once and records ev_join.
-int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
+// status word, Dirichlet masks of `depth`, injected masks and states
+int system_prelude(mvpf_problem* p, double depth) {
   hipStream_t s = p->stream;
   Level& L0 = p->lev[0];
-  const int Lc = p->L - 1;
   HIPCHK(hipMemsetAsync(setup_status(p), 0, sizeof(int), s));
   launch_dirichlet_masks(L0.g, p->load, depth, L0.mask, L0.target, s);
   for (int l = 1; l < p->L; ++l) {
     launch_inject_mask(p->lev[l - 1].g, p->lev[l].g, p->lev[l - 1].mask, p->lev[l].mask, s);
     launch_inject(p->lev[l - 1].g, p->lev[l].g, p->lev[l - 1].state, p->lev[l].state, s);
   }
+  return 0;
+}
+
+// after the finest tangent: contact residual, lifting of the prescribed
+// increment and the right-hand side (the symmetric elimination follows)
+int system_rhs(mvpf_problem* p, double depth) {
+  hipStream_t s = p->stream;
+  Level& L0 = p->lev[0];
+  if (contact(p)) {
+    launch_contact_residual(L0.g, make_sphere(L0.g, p->load, depth), L0.state, p->R, s);
+    const Sphere sp = make_sphere(L0.g, p->load, depth);
+    HIPCHK(hipMemcpyAsync(p->sphere, &sp, sizeof(Sphere), hipMemcpyHostToDevice, s));
+  }
+  launch_increment(L0.g, L0.mask, L0.target, L0.state, p->gvec, s);
+  if (use_mf(p)) {
+    mf_elements<double, double>(p, p->gvec, false, true);
+    launch_mf_gather<0, double, double, double>(L0.g, (const double*)p->Cbuf, nullptr, p->gvec, nullptr, nullptr,
+                                                0.0, p->tmp, s);
+  } else {
+    launch_spmv<double, double, double>(L0.g, L0.A64, p->gvec, p->tmp, p->Cbuf, s);
+  }
+  launch_newton_rhs(L0.g, L0.mask, p->R, p->tmp, p->gvec, p->rhs, s);
+  return 0;
+}
+
+int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
+  hipStream_t s = p->stream;
+  Level& L0 = p->lev[0];
+  const int Lc = p->L - 1;
+  TRY(system_prelude(p, depth));
   // coarsest level, then its inversion on the side stream
   assemble_coarse_level(p, Lc, depth);
   TRY(launch_check(p, "coarse assembly"));
@@ -890,21 +920,8 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
     if (contact(p)) launch_contact_element(L0.g, ck, make_sphere(L0.g, p->load, depth), L0.state, p->elem, s, mf);
     launch_jacobian_gather(L0.g, ck, p->elem, L0.A64, L0.A32, L0.diag64, s, mf);
   }
-  if (contact(p)) {
-    launch_contact_residual(L0.g, make_sphere(L0.g, p->load, depth), L0.state, p->R, s);
-    const Sphere sp = make_sphere(L0.g, p->load, depth);
-    HIPCHK(hipMemcpyAsync(p->sphere, &sp, sizeof(Sphere), hipMemcpyHostToDevice, s));
-  }
   // lifting of the prescribed increment, then symmetric elimination
-  launch_increment(L0.g, L0.mask, L0.target, L0.state, p->gvec, s);
-  if (use_mf(p)) {
-    mf_elements<double, double>(p, p->gvec, false, true);
-    launch_mf_gather<0, double, double, double>(L0.g, (const double*)p->Cbuf, nullptr, p->gvec, nullptr, nullptr,
-                                                0.0, p->tmp, s);
-  } else {
-    launch_spmv<double, double, double>(L0.g, L0.A64, p->gvec, p->tmp, p->Cbuf, s);
-  }
-  launch_newton_rhs(L0.g, L0.mask, p->R, p->tmp, p->gvec, p->rhs, s);
+  TRY(system_rhs(p, depth));
   launch_apply_dirichlet(L0.g, L0.mask, L0.A64, L0.A32, L0.diag64, s);
   TRY(launch_check(p, "assembly"));
   return 0;
@@ -1077,6 +1094,9 @@ struct mvpf_batch {
   // per-step job tables of the batched Arnoldi step (pinned host staging and
   // device copies) and the Hessenberg columns of all problems
   mvpf::KJob *kjobs_host = nullptr, *kjobs_dev = nullptr;
+  // job table of the batched assembly (device)
+  mvpf::AJob* ajobs_dev = nullptr;
+  size_t ajobs_cap = 0;
   mvpf::BJob *ojobs_host = nullptr, *ojobs_dev = nullptr, *gjobs_host = nullptr;
   double *bcol_dev = nullptr, *bcol_host = nullptr;
   std::string err;
@@ -1625,6 +1645,226 @@ int batch_fgmres(mvpf_batch* b, mvpf_solve_stats* st) {
   return rc;
 }
 
+// ---- batched Newton systems ----------------------------------------------------
+// The heavy assembly kernels (Gauss-point Hessians, element matrices, block
+// gathers, symmetric elimination, Hessian pack, residual rows, block
+// inverses) run as one launch per kernel and level for all problems, level
+// by level from each problem's coarsest; the light per-problem steps (masks,
+// injections, dense coarse gather, contact terms, lifting, right-hand side)
+// stay per problem.  Same kernels and arithmetic per problem as
+// build_system, so the systems are bitwise the same.  All on one stream; the
+// batched coarse inversion overlaps on the work stream once every coarsest
+// level is assembled.  Needs every level of every problem in one slab.
+bool batch_single_slabs(const mvpf_batch* b) {
+  for (const mvpf_problem* p : b->probs)
+    for (int l = 0; l < p->L; ++l)
+      if (make_chunks(p->lev[l].g, p->ne_use).size() != 1) return false;
+  return true;
+}
+
+struct AsmStep {
+  int op = -1;  // AssemblyOp, or -1 for host code that enqueues per-problem work
+  int pade = 22;
+  size_t first = 0;
+  int count = 0, blocks = 0;
+  std::function<int()> host;
+};
+
+int batch_assemble(mvpf_batch* b, const double* depths, hipStream_t s) {
+  std::vector<AsmStep> steps;
+  std::vector<AJob> all;
+  auto add = [&](int op, int pade, const std::vector<AJob>& jobs, const std::vector<char>& diag) {
+    if (jobs.empty()) return;
+    AsmStep st;
+    st.op = op;
+    st.pade = pade;
+    st.first = all.size();
+    st.count = (int)jobs.size();
+    for (size_t k = 0; k < jobs.size(); ++k) {
+      AJob j = jobs[k];
+      j.nblk = assembly_job_blocks(op, j, !diag.empty() && diag[k]);
+      j.block0 = st.blocks;
+      st.blocks += j.nblk;
+      all.push_back(j);
+    }
+    steps.push_back(st);
+  };
+  auto host = [&](std::function<int()> f) {
+    AsmStep st;
+    st.host = std::move(f);
+    steps.push_back(std::move(st));
+  };
+  auto job = [](mvpf_problem* p, int l) {
+    Level& L = p->lev[l];
+    AJob j{};
+    j.g = L.g;
+    j.ck = make_chunks(L.g, p->ne_use)[0];
+    j.state = L.state;
+    j.cd = p->card;
+    j.qp = p->qp;
+    j.elem = p->elem;
+    j.A64 = L.A64;
+    j.A32 = L.A32;
+    j.diag64 = L.diag64;
+    j.mask = L.mask;
+    return j;
+  };
+  auto qp_steps = [&](const std::vector<mvpf_problem*>& ps, const std::vector<AJob>& js) {
+    for (int pd : {11, 22, 33}) {
+      std::vector<AJob> sel;
+      for (size_t k = 0; k < ps.size(); ++k)
+        if (ps[k]->pade == pd || (pd == 22 && ps[k]->pade != 11 && ps[k]->pade != 33)) sel.push_back(js[k]);
+      add(AOP_QP_HESS, pd, sel, {});
+    }
+  };
+  const int n = b->n;
+  int maxL = 0;
+  for (mvpf_problem* p : b->probs) maxL = std::max(maxL, p->L);
+  for (int i = 0; i < n; ++i) {
+    mvpf_problem* p = b->probs[i];
+    const double d = depths[i];
+    host([p, d] { return system_prelude(p, d); });
+  }
+  // coarse levels, each problem's coarsest first
+  for (int k = 0; k < maxL - 1; ++k) {
+    std::vector<mvpf_problem*> ps;
+    std::vector<AJob> js;
+    std::vector<int> lv;
+    for (mvpf_problem* p : b->probs) {
+      const int l = p->L - 1 - k;
+      if (l < 1) continue;
+      ps.push_back(p);
+      js.push_back(job(p, l));
+      lv.push_back(l);
+    }
+    qp_steps(ps, js);
+    add(AOP_ELEMENT, 0, js, {});
+    for (size_t q = 0; q < ps.size(); ++q)
+      if (contact(ps[q])) {
+        mvpf_problem* p = ps[q];
+        const int l = lv[q];
+        const double d = depths[std::find(b->probs.begin(), b->probs.end(), p) - b->probs.begin()];
+        host([p, l, d] {
+          Level& C = p->lev[l];
+          launch_contact_element(C.g, make_chunks(C.g, p->ne_use)[0], make_sphere(C.g, p->load, d), C.state,
+                                 p->elem, p->stream);
+          return 0;
+        });
+      }
+    add(AOP_GATHER, 0, js, {});
+    add(AOP_DIRICHLET, 0, js, {});
+    if (k == 0) {
+      // every coarsest operator into its dense matrix, then all inversions
+      // at once on the work stream
+      host([b, s]() -> int {
+        for (mvpf_problem* p : b->probs) {
+          Level& C = p->lev[p->L - 1];
+          launch_dense_from_bsr(C.g, C.A64, p->coarse_work ? p->coarse_work : p->V, s);
+          p->coarse_pending = false;
+        }
+        BCHK(hipEventRecord(b->fork, s));
+        BCHK(hipStreamWaitEvent(b->work, b->fork, 0));
+        if (dense_invert_batch(b->gj_tab, b->gj_sel, b->gj_n, b->work) != 0) {
+          b->err = "batched coarse inversion launch failed";
+          return MVPF_EDEVICE;
+        }
+        BCHK(hipEventRecord(b->leave, b->work));
+        return 0;
+      });
+    }
+  }
+  // finest level: only the diagonal blocks on matrix-free levels
+  {
+    std::vector<AJob> js, pk;
+    std::vector<char> diag;
+    for (mvpf_problem* p : b->probs) {
+      AJob j = job(p, 0);
+      j.R = p->R;
+      js.push_back(j);
+      diag.push_back(use_mf(p) ? 1 : 0);
+      if (use_mf(p)) {
+        AJob q = j;
+        q.D64 = p->Dmf64;
+        q.D32 = p->Dmf32;
+        pk.push_back(q);
+      }
+    }
+    qp_steps(b->probs, js);
+    add(AOP_MF_PACK, 0, pk, {});
+    add(AOP_RESIDUAL, 0, js, {});
+    add(AOP_ELEMENT, 0, js, diag);
+    for (int i = 0; i < n; ++i)
+      if (contact(b->probs[i])) {
+        mvpf_problem* p = b->probs[i];
+        const double d = depths[i];
+        host([p, d] {
+          Level& L0 = p->lev[0];
+          launch_contact_element(L0.g, make_chunks(L0.g, p->ne_use)[0], make_sphere(L0.g, p->load, d), L0.state,
+                                 p->elem, p->stream, use_mf(p));
+          return 0;
+        });
+      }
+    std::vector<AJob> ga = js;
+    for (size_t q = 0; q < ga.size(); ++q)
+      if (diag[q]) ga[q].A64 = nullptr, ga[q].A32 = nullptr;  // diagonal blocks only
+    add(AOP_GATHER, 0, ga, diag);
+    for (int i = 0; i < n; ++i) {
+      mvpf_problem* p = b->probs[i];
+      const double d = depths[i];
+      host([p, d] { return system_rhs(p, d); });
+    }
+    add(AOP_DIRICHLET, 0, js, {});
+  }
+  // smoother setup on every level but the coarsest, then join the inversions
+  {
+    std::vector<AJob> bi;
+    for (mvpf_problem* p : b->probs)
+      for (int l = 0; l < p->L - 1; ++l) {
+        Level& L = p->lev[l];
+        AJob j{};
+        j.g = L.g;
+        j.diag64 = L.diag64;
+        j.Dinv64 = L.Dinv64;
+        j.Dinv32 = L.Dinv32;
+        j.status = setup_status(p);
+        bi.push_back(j);
+      }
+    add(AOP_BLOCK_INVERSE, 0, bi, {});
+    host([b, s]() -> int {
+      BCHK(hipStreamWaitEvent(s, b->leave, 0));
+      for (mvpf_problem* p : b->probs)
+        HIPCHK(hipMemcpyAsync(host_status(p), setup_status(p), sizeof(int), hipMemcpyDeviceToHost, s));
+      return 0;
+    });
+  }
+  // one upload of all job tables, then the steps in order
+  if (all.size() > b->ajobs_cap) {
+    if (b->ajobs_dev) (void)hipFree(b->ajobs_dev);
+    b->ajobs_dev = nullptr;
+    b->ajobs_cap = 0;
+    if (hipMalloc((void**)&b->ajobs_dev, sizeof(AJob) * all.size()) != hipSuccess) {
+      (void)hipGetLastError();
+      b->err = "batch assembly job table allocation failed";
+      return MVPF_ENOMEM;
+    }
+    b->ajobs_cap = all.size();
+  }
+  BCHK(hipMemcpy(b->ajobs_dev, all.data(), sizeof(AJob) * all.size(), hipMemcpyHostToDevice));
+  for (AsmStep& st : steps) {
+    if (st.op < 0) {
+      const int rc = st.host();
+      if (rc) {
+        if (b->err.empty()) b->err = "batched assembly failed";
+        return rc;
+      }
+    } else {
+      launch_assembly_batch(st.op, st.pade, b->ajobs_dev + st.first, st.count, st.blocks, s);
+    }
+  }
+  BCHK(hipGetLastError());
+  return 0;
+}
+
 void batch_free(mvpf_batch* b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
@@ -1646,8 +1886,10 @@ void batch_free(mvpf_batch* b) {
   if (b->jobs_dev) (void)hipFree(b->jobs_dev);
   b->jobs_dev = nullptr;
   b->jobs_cap = 0;
-  for (void* d : {(void*)b->kjobs_dev, (void*)b->ojobs_dev, (void*)b->bcol_dev})
+  for (void* d : {(void*)b->kjobs_dev, (void*)b->ojobs_dev, (void*)b->bcol_dev, (void*)b->ajobs_dev})
     if (d) (void)hipFree(d);
+  b->ajobs_dev = nullptr;
+  b->ajobs_cap = 0;
   for (void* h : {(void*)b->kjobs_host, (void*)b->ojobs_host, (void*)b->gjobs_host, (void*)b->bcol_host})
     if (h) (void)hipHostFree(h);
   b->kjobs_dev = nullptr;
@@ -2335,46 +2577,61 @@ mvpf_problem* mvpf_batch_problem(mvpf_batch* b, int i) {
 int mvpf_batch_newton_system(mvpf_batch* b, const double* depths) {
   if (!b || !depths) return MVPF_EINVAL;
   BCHK(hipEventRecord(b->enter, b->stream));
-  // largest coarsest levels first: their latency-bound inversions are the
-  // longest chains and start while the other problems assemble
-  std::vector<int> order(b->n);
-  for (int i = 0; i < b->n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    return b->probs[x]->lev[b->probs[x]->L - 1].ndense > b->probs[y]->lev[b->probs[y]->L - 1].ndense;
-  });
   int rc = 0, bad = -1;
-  for (int oi = 0; oi < b->n && rc == 0; ++oi) {
-    const int i = order[oi];
-    mvpf_problem* p = b->probs[i];
-    p->have_system = p->have_solution = false;
-    BCHK(hipStreamWaitEvent(b->branch[i], b->enter, 0));
-    p->stream = b->branch[i];
-    rc = build_system(p, depths[i], false);
-    p->stream = b->stream;
-    if (rc) bad = i;
-  }
-  // all coarsest-level inversions at once, on the batch's work stream, after
-  // every problem's dense coarse matrix is ready; each problem's setup waits
-  if (rc == 0) {
-    for (int i = 0; i < b->n; ++i) BCHK(hipStreamWaitEvent(b->work, b->probs[i]->ev_fork, 0));
-    if (dense_invert_batch(b->gj_tab, b->gj_sel, b->gj_n, b->work) != 0) {
-      b->err = "batched coarse inversion launch failed";
-      rc = MVPF_EDEVICE;
+  if (batch_single_slabs(b)) {
+    // batched launches on one stream
+    hipStream_t s = b->branch[0];
+    BCHK(hipStreamWaitEvent(s, b->enter, 0));
+    for (mvpf_problem* p : b->probs) {
+      p->have_system = p->have_solution = false;
+      p->stream = s;
     }
-    for (int i = 0; i < b->n && rc == 0; ++i) BCHK(hipEventRecord(b->probs[i]->ev_join, b->work));
-  }
-  for (int oi = 0; oi < b->n && rc == 0; ++oi) {
-    const int i = order[oi];
-    mvpf_problem* p = b->probs[i];
-    p->stream = b->branch[i];
-    rc = setup_enqueue(p);
-    p->stream = b->stream;
-    if (rc) bad = i;
-  }
-  for (int i = 0; i < b->n; ++i) (void)hipStreamSynchronize(b->branch[i]);
-  if (rc) {
-    b->err = "problem " + std::to_string(bad) + ": " + b->probs[bad]->err;
-    return rc;
+    rc = batch_assemble(b, depths, s);
+    for (mvpf_problem* p : b->probs) p->stream = b->stream;
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(b->work);
+    if (rc) return rc;
+  } else {
+    // largest coarsest levels first: their latency-bound inversions are the
+    // longest chains and start while the other problems assemble
+    std::vector<int> order(b->n);
+    for (int i = 0; i < b->n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return b->probs[x]->lev[b->probs[x]->L - 1].ndense > b->probs[y]->lev[b->probs[y]->L - 1].ndense;
+    });
+    for (int oi = 0; oi < b->n && rc == 0; ++oi) {
+      const int i = order[oi];
+      mvpf_problem* p = b->probs[i];
+      p->have_system = p->have_solution = false;
+      BCHK(hipStreamWaitEvent(b->branch[i], b->enter, 0));
+      p->stream = b->branch[i];
+      rc = build_system(p, depths[i], false);
+      p->stream = b->stream;
+      if (rc) bad = i;
+    }
+    // all coarsest-level inversions at once, on the batch's work stream, after
+    // every problem's dense coarse matrix is ready; each problem's setup waits
+    if (rc == 0) {
+      for (int i = 0; i < b->n; ++i) BCHK(hipStreamWaitEvent(b->work, b->probs[i]->ev_fork, 0));
+      if (dense_invert_batch(b->gj_tab, b->gj_sel, b->gj_n, b->work) != 0) {
+        b->err = "batched coarse inversion launch failed";
+        rc = MVPF_EDEVICE;
+      }
+      for (int i = 0; i < b->n && rc == 0; ++i) BCHK(hipEventRecord(b->probs[i]->ev_join, b->work));
+    }
+    for (int oi = 0; oi < b->n && rc == 0; ++oi) {
+      const int i = order[oi];
+      mvpf_problem* p = b->probs[i];
+      p->stream = b->branch[i];
+      rc = setup_enqueue(p);
+      p->stream = b->stream;
+      if (rc) bad = i;
+    }
+    for (int i = 0; i < b->n; ++i) (void)hipStreamSynchronize(b->branch[i]);
+    if (rc) {
+      b->err = "problem " + std::to_string(bad) + ": " + b->probs[bad]->err;
+      return rc;
+    }
   }
   for (int i = 0; i < b->n; ++i) {
     mvpf_problem* p = b->probs[i];

@@ -413,6 +413,37 @@ enum KrylovOp {
   KOP_COPY,       // out[0..k) = src[0..k)
 };
 int krylov_job_blocks(int op, const KJob& j);
+// Batched assembly of the Newton systems of many problems: one launch per
+// assembly kernel and level for all problems (each a single slab).
+struct AJob {
+  Grid g;
+  Chunk ck;
+  const double* state;
+  const DevCard* cd;
+  double* qp;                // Gauss-point scratch
+  double* elem;              // element matrices
+  double *A64, *diag64, *Dinv64, *R, *D64;
+  float *A32, *Dinv32, *D32;
+  const uint16_t* mask;
+  int* status;
+  int64_t eb0, neb;          // element groups of the Hessian pack
+  int npair, nblocks, nup;   // pairs of the element matrices; gather blocks
+  int block0, nblk;
+};
+enum AssemblyOp {
+  AOP_QP_HESS,        // Gauss-point gradients and Hessians (Pade order: the launch's template)
+  AOP_ELEMENT,        // element matrices (npair pairs)
+  AOP_GATHER,         // stored blocks (nup per tile; A64 / A32 null: diagonal only)
+  AOP_DIRICHLET,      // symmetric elimination on the stored blocks
+  AOP_BLOCK_INVERSE,  // 9x9 diagonal-block inverses
+  AOP_RESIDUAL,       // residual rows from the Gauss-point gradients
+  AOP_MF_PACK,        // Gauss-point Hessians into the matrix-free layout
+};
+// fills the job's derived fields (npair, nblocks, nup, eb0, neb) and returns its workgroups
+int assembly_job_blocks(int op, AJob& j, bool diag_only);
+void launch_assembly_batch(int op, int pade, const AJob* jobs, int njobs, int blocks, hipStream_t s);
+void launch_mf_pack_batch(const AJob* jobs, int njobs, int blocks, hipStream_t s);
+int mf_pack_job_blocks(AJob& j);
 void launch_krylov_batch(int op, const KJob* jobs, int njobs, int blocks, hipStream_t s);
 template <typename TZ>
 void launch_mf_outer_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s);

@@ -300,10 +300,10 @@ __global__ void __launch_bounds__(256) mf_gather_kernel(Grid g, const T* __restr
 // 15.. of qp) -> matrix-free layout, FP64 and (optionally) FP32.  One thread
 // per group of 4 consecutive entries of one (point, element), in the order of
 // the matrix-free layout, so that every wavefront writes whole 1 KB spans.
-__global__ void __launch_bounds__(256) mf_pack_kernel(Grid g, Chunk ck, const double* __restrict__ qp,
-                                                      double* __restrict__ D64, float* __restrict__ D32,
-                                                      int64_t eb0, int64_t neb) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void mf_pack_body(const Grid& g, const Chunk& ck, const double* __restrict__ qp,
+                                             double* __restrict__ D64, float* __restrict__ D32, int64_t eb0,
+                                             int64_t neb, int bid) {
+  const int64_t t = (int64_t)bid * 256 + threadIdx.x;
   const int64_t per = neb * 64;  // threads per entry group
   const int k4 = (int)(t / per);
   if (k4 >= 30) return;
@@ -325,6 +325,25 @@ __global__ void __launch_bounds__(256) mf_pack_kernel(Grid g, Chunk ck, const do
   if (D32)
     *reinterpret_cast<float4*>(D32 + mf_index<float>(g.NEpad, 4 * k4, gp, e)) =
         make_float4((float)d[0], (float)d[1], (float)d[2], (float)d[3]);
+}
+
+__global__ void __launch_bounds__(256) mf_pack_kernel(Grid g, Chunk ck, const double* __restrict__ qp,
+                                                      double* __restrict__ D64, float* __restrict__ D32,
+                                                      int64_t eb0, int64_t neb) {
+  mf_pack_body(g, ck, qp, D64, D32, eb0, neb, blockIdx.x);
+}
+__global__ void __launch_bounds__(256) mf_pack_batch(const AJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const AJob& j = find_job(jobs, njobs, bid);
+  mf_pack_body(j.g, j.ck, j.qp, j.D64, j.D32, j.eb0, j.neb, bid);
+}
+void launch_mf_pack_batch(const AJob* jobs, int njobs, int blocks, hipStream_t s) {
+  mf_pack_batch<<<blocks, 256, 0, s>>>(jobs, njobs);
+}
+int mf_pack_job_blocks(AJob& j) {
+  j.eb0 = j.ck.e0 / 8;
+  j.neb = (j.ck.e0 + j.ck.NEc + 7) / 8 - j.eb0;
+  return (int)((30 * j.neb * 64 + 255) / 256);
 }
 
 size_t mf_hessian_values(const Grid& g) { return (size_t)120 * 8 * g.NEpad; }

@@ -52,9 +52,9 @@ __device__ __forceinline__ double lap_ref(int a, int b) {
 }
 
 template <bool HESS, int PD>
-__global__ void __launch_bounds__(128) qp_kernel(Grid g, Chunk ck, const double* __restrict__ state,
-                                                 const DevCard* __restrict__ cd, double* __restrict__ qp) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void qp_body(const Grid& g, const Chunk& ck, const double* __restrict__ state,
+                                        const DevCard* __restrict__ cd, double* __restrict__ qp, int bid) {
+  const int64_t tid = (int64_t)bid * 128 + threadIdx.x;
   const int gp = (int)(tid / ck.NEcpad);
   const int el = (int)(tid - (int64_t)gp * ck.NEcpad);
   if (gp >= 8 || el >= ck.NEc) return;
@@ -90,6 +90,11 @@ __global__ void __launch_bounds__(128) qp_kernel(Grid g, Chunk ck, const double*
 #pragma unroll
   for (int c = 0; c < 15; ++c) out[(int64_t)c * stride] = gr[c];
 }
+template <bool HESS, int PD>
+__global__ void __launch_bounds__(128) qp_kernel(Grid g, Chunk ck, const double* __restrict__ state,
+                                                 const DevCard* __restrict__ cd, double* __restrict__ qp) {
+  qp_body<HESS, PD>(g, ck, state, cd, qp, blockIdx.x);
+}
 
 template <int PD>
 void launch_qp_order(const Grid& g, const Chunk& ck, const double* state, const DevCard* cd, double* qp, bool hess,
@@ -113,11 +118,10 @@ void launch_qp(const Grid& g, const Chunk& ck, const double* state, const DevCar
   }
 }
 
-__global__ void __launch_bounds__(256) residual_gather_kernel(Grid g, Chunk ck, const double* __restrict__ state,
-                                                              const double* __restrict__ qp,
-                                                              const DevCard* __restrict__ cd,
-                                                              double* __restrict__ R) {
-  const int n = ck.n0 + blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void residual_gather_body(const Grid& g, const Chunk& ck, const double* __restrict__ state,
+                                                     const double* __restrict__ qp, const DevCard* __restrict__ cd,
+                                                     double* __restrict__ R, int bid) {
+  const int n = ck.n0 + bid * 256 + threadIdx.x;
   if (n >= ck.n1 || n >= g.Npad) return;
   double r[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (n < g.N) {
@@ -160,6 +164,12 @@ __global__ void __launch_bounds__(256) residual_gather_kernel(Grid g, Chunk ck, 
 #pragma unroll
   for (int c = 0; c < 9; ++c) R[(int64_t)c * g.Npad + n] = r[c];
 }
+__global__ void __launch_bounds__(256) residual_gather_kernel(Grid g, Chunk ck, const double* __restrict__ state,
+                                                              const double* __restrict__ qp,
+                                                              const DevCard* __restrict__ cd,
+                                                              double* __restrict__ R) {
+  residual_gather_body(g, ck, state, qp, cd, R, blockIdx.x);
+}
 
 void launch_residual_gather(const Grid& g, const Chunk& ck, const double* state, const double* qp, const DevCard* cd,
                             double* R, hipStream_t s) {
@@ -185,17 +195,16 @@ __device__ __forceinline__ int xcd_logical(int b, int nb_pad) {
 constexpr int EM_WAVES = 4;
 
 // npair = NPAIR: all 36 pairs; npair = 8: the diagonal pairs (a, a) only.
-__global__ void __launch_bounds__(EM_WAVES * 64, 2) element_matrix_kernel(Grid g, Chunk ck,
-                                                                          const double* __restrict__ qp,
-                                                                          const DevCard* __restrict__ cd,
-                                                                          double* __restrict__ E, int npair) {
+__device__ __forceinline__ void element_matrix_body(const Grid& g, const Chunk& ck, const double* __restrict__ qp,
+                                                    const DevCard* __restrict__ cd, double* __restrict__ E, int npair,
+                                                    int bid, int nblk) {
   __shared__ double Ds[120 * 64];
   // the NPAIR / EM_WAVES pair chunks of one element group are consecutive
   // logical blocks on one XCD, so the group's Hessians are read from HBM once
   // and then hit that XCD's L2
   const int groups = ck.NEcpad / 64;
   const int chunks = npair / EM_WAVES;
-  const int Lb = xcd_logical(blockIdx.x, gridDim.x);
+  const int Lb = xcd_logical(bid, nblk);
   if (Lb >= groups * chunks) return;  // uniform; before any barrier
   const int eg = Lb / chunks;
   const int pc = Lb % chunks;  // pair chunk
@@ -282,6 +291,12 @@ __global__ void __launch_bounds__(EM_WAVES * 64, 2) element_matrix_kernel(Grid g
     for (int q = 0; q < 81; ++q) E[((int64_t)p * NBLK + q) * ck.NEcpad + e] = K[q];
   }
 }
+__global__ void __launch_bounds__(EM_WAVES * 64, 2) element_matrix_kernel(Grid g, Chunk ck,
+                                                                          const double* __restrict__ qp,
+                                                                          const DevCard* __restrict__ cd,
+                                                                          double* __restrict__ E, int npair) {
+  element_matrix_body(g, ck, qp, cd, E, npair, blockIdx.x, gridDim.x);
+}
 
 void launch_element_matrices(const Grid& g, const Chunk& ck, const double* qp, const DevCard* cd, double* elem,
                              hipStream_t s, bool diag_only) {
@@ -296,10 +311,11 @@ void launch_element_matrices(const Grid& g, const Chunk& ck, const double* qp, c
 // One wavefront per (tile, u): 64 consecutive rows, coalesced element reads
 // and coalesced tiled writes.
 // nup = NUP: every stored block; nup = 1: the diagonal blocks only.
-__global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, Chunk ck, const double* __restrict__ E,
-                                                             double* __restrict__ A64, float* __restrict__ A32,
-                                                             double* __restrict__ diag64, int nblocks, int nup) {
-  const int L = xcd_logical(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void jacobian_gather_body(const Grid& g, const Chunk& ck, const double* __restrict__ E,
+                                                     double* __restrict__ A64, float* __restrict__ A32,
+                                                     double* __restrict__ diag64, int nblocks, int nup, int bid,
+                                                     int nblk) {
+  const int L = xcd_logical(bid, nblk);
   if (L >= nblocks) return;
   const int t = ck.n0 / TILE + L / nup, u = L % nup;
   const int sten = 13 + u;
@@ -354,6 +370,11 @@ __global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, Chunk ck, c
     }
   }
 }
+__global__ void __launch_bounds__(64) jacobian_gather_kernel(Grid g, Chunk ck, const double* __restrict__ E,
+                                                             double* __restrict__ A64, float* __restrict__ A32,
+                                                             double* __restrict__ diag64, int nblocks, int nup) {
+  jacobian_gather_body(g, ck, E, A64, A32, diag64, nblocks, nup, blockIdx.x, gridDim.x);
+}
 
 void launch_jacobian_gather(const Grid& g, const Chunk& ck, const double* elem, double* A64, float* A32,
                             double* diag64, hipStream_t s, bool diag_only) {
@@ -368,10 +389,10 @@ void launch_jacobian_gather(const Grid& g, const Chunk& ck, const double* elem, 
 // Symmetric elimination on the stored blocks: entries in constrained rows of
 // node n or constrained columns of node m are zeroed, the diagonal of a
 // constrained dof is 1.
-__global__ void __launch_bounds__(64) apply_dirichlet_kernel(Grid g, const uint16_t* __restrict__ mask,
-                                                             double* __restrict__ A64, float* __restrict__ A32,
-                                                             double* __restrict__ diag64, int nblocks) {
-  const int L = xcd_logical(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void apply_dirichlet_body(const Grid& g, const uint16_t* __restrict__ mask,
+                                                     double* __restrict__ A64, float* __restrict__ A32,
+                                                     double* __restrict__ diag64, int nblocks, int bid, int nblk) {
+  const int L = xcd_logical(bid, nblk);
   if (L >= nblocks) return;
   const int t = L / NUP, u = L - t * NUP;
   const int sten = 13 + u;
@@ -397,6 +418,11 @@ __global__ void __launch_bounds__(64) apply_dirichlet_kernel(Grid g, const uint1
     }
   }
 }
+__global__ void __launch_bounds__(64) apply_dirichlet_kernel(Grid g, const uint16_t* __restrict__ mask,
+                                                             double* __restrict__ A64, float* __restrict__ A32,
+                                                             double* __restrict__ diag64, int nblocks) {
+  apply_dirichlet_body(g, mask, A64, A32, diag64, nblocks, blockIdx.x, gridDim.x);
+}
 
 void launch_apply_dirichlet(const Grid& g, const uint16_t* mask, double* A64, float* A32, double* diag64,
                             hipStream_t s) {
@@ -410,11 +436,11 @@ void launch_apply_dirichlet(const Grid& g, const uint16_t* mask, double* A64, fl
 // thread keeps its augmented [A | I] in LDS, lane-interleaved.
 constexpr int BI_THREADS = 32;  // 32 x 9 x 18 doubles = 41 KB of LDS per block
 
-__global__ void __launch_bounds__(BI_THREADS) block_inverse_kernel(Grid g, const double* __restrict__ diag64,
-                                                                   double* __restrict__ Dinv64,
-                                                                   float* __restrict__ Dinv32, int* status) {
+__device__ __forceinline__ void block_inverse_body(const Grid& g, const double* __restrict__ diag64,
+                                                   double* __restrict__ Dinv64, float* __restrict__ Dinv32,
+                                                   int* status, int bid) {
   __shared__ double M[9 * 18 * BI_THREADS];
-  const int n = blockIdx.x * BI_THREADS + threadIdx.x;
+  const int n = bid * BI_THREADS + threadIdx.x;
   const int t = n / TILE, l = n % TILE, lt = threadIdx.x;
   if (n >= g.Npad) return;
   const int64_t db = (int64_t)t * Lay<double>::SLICE;
@@ -459,11 +485,97 @@ __global__ void __launch_bounds__(BI_THREADS) block_inverse_kernel(Grid g, const
   }
 #undef MM
 }
+__global__ void __launch_bounds__(BI_THREADS) block_inverse_kernel(Grid g, const double* __restrict__ diag64,
+                                                                   double* __restrict__ Dinv64,
+                                                                   float* __restrict__ Dinv32, int* status) {
+  block_inverse_body(g, diag64, Dinv64, Dinv32, status, blockIdx.x);
+}
 
 void launch_block_inverse(const Grid& g, const double* diag64, double* Dinv64, float* Dinv32, int* status,
                           hipStream_t s) {
   block_inverse_kernel<<<(g.Npad + BI_THREADS - 1) / BI_THREADS, BI_THREADS, 0, s>>>(g, diag64, Dinv64, Dinv32,
                                                                                       status);
+}
+
+// ---- batched assembly (jobs of many problems in one launch) --------------------
+template <int PD>
+__global__ void __launch_bounds__(128) qp_hess_batch(const AJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const AJob& j = find_job(jobs, njobs, bid);
+  qp_body<true, PD>(j.g, j.ck, j.state, j.cd, j.qp, bid);
+}
+__global__ void __launch_bounds__(EM_WAVES * 64, 2) element_matrix_batch(const AJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const AJob& j = find_job(jobs, njobs, bid);
+  element_matrix_body(j.g, j.ck, j.qp, j.cd, j.elem, j.npair, bid, j.nblk);
+}
+__global__ void __launch_bounds__(64) jacobian_gather_batch(const AJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const AJob& j = find_job(jobs, njobs, bid);
+  jacobian_gather_body(j.g, j.ck, j.elem, j.A64, j.A32, j.diag64, j.nblocks, j.nup, bid, j.nblk);
+}
+__global__ void __launch_bounds__(64) apply_dirichlet_batch(const AJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const AJob& j = find_job(jobs, njobs, bid);
+  apply_dirichlet_body(j.g, j.mask, j.A64, j.A32, j.diag64, j.nblocks, bid, j.nblk);
+}
+__global__ void __launch_bounds__(BI_THREADS) block_inverse_batch(const AJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const AJob& j = find_job(jobs, njobs, bid);
+  block_inverse_body(j.g, j.diag64, j.Dinv64, j.Dinv32, j.status, bid);
+}
+__global__ void __launch_bounds__(256) residual_gather_batch(const AJob* __restrict__ jobs, int njobs) {
+  int bid;
+  const AJob& j = find_job(jobs, njobs, bid);
+  residual_gather_body(j.g, j.ck, j.state, j.qp, j.cd, j.R, bid);
+}
+
+// the launch shapes of the single-problem launchers, per job
+int assembly_job_blocks(int op, AJob& j, bool diag_only) {
+  const Grid& g = j.g;
+  const Chunk& ck = j.ck;
+  switch (op) {
+    case AOP_QP_HESS: return (int)(((int64_t)8 * ck.NEcpad + 127) / 128);
+    case AOP_ELEMENT: {
+      j.npair = diag_only ? 8 : NPAIR;
+      const int nb = (ck.NEcpad / 64) * (j.npair / EM_WAVES);
+      return (nb + 7) / 8 * 8;
+    }
+    case AOP_GATHER: {
+      const int t0 = ck.n0 / TILE, t1 = (ck.n1 + TILE - 1) / TILE;
+      j.nup = diag_only ? 1 : NUP;
+      j.nblocks = (t1 - t0) * j.nup;
+      return (j.nblocks + 7) / 8 * 8;
+    }
+    case AOP_DIRICHLET:
+      j.nblocks = g.ntiles * NUP;
+      return (j.nblocks + 7) / 8 * 8;
+    case AOP_BLOCK_INVERSE: return (g.Npad + BI_THREADS - 1) / BI_THREADS;
+    case AOP_RESIDUAL: return (ck.n1 - ck.n0 + 255) / 256;
+    case AOP_MF_PACK: return mf_pack_job_blocks(j);
+    default: return 0;
+  }
+}
+
+void launch_assembly_batch(int op, int pade, const AJob* jobs, int njobs, int blocks, hipStream_t s) {
+  if (njobs <= 0 || blocks <= 0) return;
+  switch (op) {
+    case AOP_QP_HESS:
+      if (pade == 11)
+        qp_hess_batch<11><<<blocks, 128, 0, s>>>(jobs, njobs);
+      else if (pade == 33)
+        qp_hess_batch<33><<<blocks, 128, 0, s>>>(jobs, njobs);
+      else
+        qp_hess_batch<22><<<blocks, 128, 0, s>>>(jobs, njobs);
+      break;
+    case AOP_ELEMENT: element_matrix_batch<<<blocks, EM_WAVES * 64, 0, s>>>(jobs, njobs); break;
+    case AOP_GATHER: jacobian_gather_batch<<<blocks, TILE, 0, s>>>(jobs, njobs); break;
+    case AOP_DIRICHLET: apply_dirichlet_batch<<<blocks, TILE, 0, s>>>(jobs, njobs); break;
+    case AOP_BLOCK_INVERSE: block_inverse_batch<<<blocks, BI_THREADS, 0, s>>>(jobs, njobs); break;
+    case AOP_RESIDUAL: residual_gather_batch<<<blocks, 256, 0, s>>>(jobs, njobs); break;
+    case AOP_MF_PACK: launch_mf_pack_batch(jobs, njobs, blocks, s); break;
+    default: break;
+  }
 }
 
 }  // namespace mvpf

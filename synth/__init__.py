@@ -195,7 +195,10 @@ def batched(n_problems: int = 32, base_seed: int = BASE_SEED) -> List[Problem]:
     """Independent problems with n in {16,24,32,40,48}, depth U[0.005,0.02],
     a random crystal rotation and their own eta seed (problem p: base + p).
     The top patch spans 2*max(1, n//16) elements (even, so it is centred on a
-    node)."""
+    node).  Levels: n is halved while it is even and the half is at least 2
+    (48: 5 levels down to 3^3, 40: 4 down to 5^3, 32: 5 down to 2^3, 24: 4
+    down to 3^3, 16: 4 down to 2^3), so no coarsest level exceeds 1944
+    unknowns."""
     out = []
     for p in range(n_problems):
         s = base_seed + p
@@ -203,7 +206,11 @@ def batched(n_problems: int = 32, base_seed: int = BASE_SEED) -> List[Problem]:
         n = (16, 24, 32, 40, 48)[min(int(u[0] * 5), 4)]
         d = 0.005 + 0.015 * u[1]
         Q = random_rotation(s)
-        out.append(Problem(n, n, n, n_levels=4, patch=2 * max(1, n // 16),
+        levels, m = 1, n
+        while m % 2 == 0 and m // 2 >= 2:
+            m //= 2
+            levels += 1
+        out.append(Problem(n, n, n, n_levels=levels, patch=2 * max(1, n // 16),
                            depth_increment=float(d), steps=1, seed=s,
                            material=config_material(Q=tuple(Q.ravel()))))
     return out
