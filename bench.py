@@ -348,7 +348,7 @@ def sweep_traffic(prob, matrix_free):
     nepad = (prob.nx * prob.ny * prob.nz + 63) // 64 * 64
     if matrix_free:
         want = {
-            "mvpf::mf_element_kernel<float,float,float,3>": nepad * 8,
+            "mvpf::mf_element_kernel<float,float,float,3,20,false>": nepad * 8,
             "mvpf::mf_gather_kernel<2,float,float,float>": (npad + 255) // 256 * 256,
         }
     else:
