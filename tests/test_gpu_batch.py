@@ -91,3 +91,43 @@ def test_batch_problem_matches_oracle():
     dx = _state(B.problem(i)) - U
     assert rel(dx, oc.x) <= 1e-9, rel(dx, oc.x)
     B.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_batch_contact_and_assembled_finest_bitwise(precision):
+    """A batch mixing a sphere-contact problem (its contact terms are
+    per-problem launches inside the batched chains) and a problem on the
+    assembled finest level (tuning matrix_free = 0: half-stencil sweeps and
+    operator product) with a matrix-free patch problem: every problem bitwise
+    as solved alone under the same tuning, on two replays."""
+    from paper_2011_08802_amd import mvpf
+    sb = small_batch()
+    probs = [synth.Problem(8, 8, 4, lz=0.5, n_levels=3, kind="sphere", radius=0.5, seed=synth.BASE_SEED + 7),
+             sb[0], sb[1]]
+    depths = [0.03, sb[0].depth_increment, sb[1].depth_increment]
+    states = [seeded_state(p, 1e-3) for p in probs]
+    B = mvpf.Batch(probs, precision)
+    B.problem(2).set_tuning("matrix_free", 0, 0)
+    say(f"[batch mixed kinds {precision}] single-problem references")
+    ref = []
+    for i, (p, (U, En)) in enumerate(zip(probs, states)):
+        gp = mvpf.Problem(p, precision)
+        for key in ("small_grid_nodes", "matrix_free"):
+            gp.set_tuning(key, 0, B.problem(i).get_tuning(key))
+        gp.set_state(U[:, :3], U[:, 3:], En, 0.0)
+        gp.newton_system(depths[i])
+        _, st = gp.solve(want_x=False)
+        gp.newton_update()
+        ref.append((_state(gp), st.iterations))
+        gp.close()
+    for replay in range(2):
+        say(f"[batch mixed kinds {precision}] replay {replay}")
+        for i, (U, En) in enumerate(states):
+            B.problem(i).set_state(U[:, :3], U[:, 3:], En, 0.0)
+        B.newton_system(depths)
+        stats = B.solve()
+        B.newton_update()
+        for i in range(len(probs)):
+            assert stats[i].converged and stats[i].iterations == ref[i][1], (i, stats[i].iterations, ref[i][1])
+            assert np.array_equal(_state(B.problem(i)), ref[i][0]), i
+    B.close()
