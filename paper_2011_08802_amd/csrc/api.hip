@@ -875,37 +875,18 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
   Level& L0 = p->lev[0];
   const int Lc = p->L - 1;
   TRY(system_prelude(p, depth));
-  // coarsest level, then its inversion on the side stream
+  // coarsest level first, as a dense matrix; its inversion (a chain of
+  // several hundred launches) is enqueued after the finer levels' assembly,
+  // so that the host feeds the main stream first and the side stream's chain
+  // then runs beside it
   assemble_coarse_level(p, Lc, depth);
   TRY(launch_check(p, "coarse assembly"));
-  {
-    Level& C = p->lev[Lc];
-    const int nd = C.ndense;
-    double* work = p->coarse_work ? p->coarse_work : p->V;
-    if (!coarse_inline) {
-      launch_dense_from_bsr(C.g, C.A64, work, s);
-      HIPCHK(hipEventRecord(p->ev_fork, s));
-      p->coarse_pending = true;
-    }
-    const bool overlap = p->coarse_overlap < 0 ? nd <= COARSE_OVERLAP_MAX : p->coarse_overlap != 0;
-    hipStream_t cs = overlap ? p->side : s;
-    if (coarse_inline && overlap) {
-      HIPCHK(hipEventRecord(p->ev_fork, s));
-      HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
-    }
-    if (coarse_inline) {
-      launch_dense_from_bsr(C.g, C.A64, work, cs);
-      if (dense_invert(nd, work, C.Ainv, work + (int64_t)nd * nd, setup_status(p), cs) != 0) {
-        p->err = "coarse inversion launch failed";
-        return MVPF_EDEVICE;
-      }
-    }
-    if (coarse_inline && overlap) {
-      HIPCHK(hipEventRecord(p->ev_join, p->side));
-      p->coarse_pending = true;
-    }
-    TRY(launch_check(p, "coarse inversion"));
-  }
+  Level& C = p->lev[Lc];
+  const int nd = C.ndense;
+  double* work = p->coarse_work ? p->coarse_work : p->V;
+  launch_dense_from_bsr(C.g, C.A64, work, s);
+  HIPCHK(hipEventRecord(p->ev_fork, s));
+  if (!coarse_inline) p->coarse_pending = true;
   for (int l = Lc - 1; l >= 1; --l) assemble_coarse_level(p, l, depth);
   // finest: residual and unconstrained tangent
   for (const Chunk& ck : make_chunks(L0.g, p->ne_use)) {
@@ -924,6 +905,20 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
   TRY(system_rhs(p, depth));
   launch_apply_dirichlet(L0.g, L0.mask, L0.A64, L0.A32, L0.diag64, s);
   TRY(launch_check(p, "assembly"));
+  if (coarse_inline) {
+    const bool overlap = p->coarse_overlap < 0 ? nd <= COARSE_OVERLAP_MAX : p->coarse_overlap != 0;
+    hipStream_t cs = overlap ? p->side : s;
+    if (overlap) HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+    if (dense_invert(nd, work, C.Ainv, work + (int64_t)nd * nd, setup_status(p), cs) != 0) {
+      p->err = "coarse inversion launch failed";
+      return MVPF_EDEVICE;
+    }
+    if (overlap) {
+      HIPCHK(hipEventRecord(p->ev_join, p->side));
+      p->coarse_pending = true;
+    }
+    TRY(launch_check(p, "coarse inversion"));
+  }
   return 0;
 }
 
@@ -1754,8 +1749,7 @@ int batch_assemble(mvpf_batch* b, const double* depths, hipStream_t s) {
     add(AOP_GATHER, 0, js, {});
     add(AOP_DIRICHLET, 0, js, {});
     if (k == 0) {
-      // every coarsest operator into its dense matrix, then all inversions
-      // at once on the work stream
+      // every coarsest operator into its dense matrix (inverted below)
       host([b, s]() -> int {
         for (mvpf_problem* p : b->probs) {
           Level& C = p->lev[p->L - 1];
@@ -1763,12 +1757,6 @@ int batch_assemble(mvpf_batch* b, const double* depths, hipStream_t s) {
           p->coarse_pending = false;
         }
         BCHK(hipEventRecord(b->fork, s));
-        BCHK(hipStreamWaitEvent(b->work, b->fork, 0));
-        if (dense_invert_batch(b->gj_tab, b->gj_sel, b->gj_n, b->work) != 0) {
-          b->err = "batched coarse inversion launch failed";
-          return MVPF_EDEVICE;
-        }
-        BCHK(hipEventRecord(b->leave, b->work));
         return 0;
       });
     }
@@ -1815,7 +1803,7 @@ int batch_assemble(mvpf_batch* b, const double* depths, hipStream_t s) {
     }
     add(AOP_DIRICHLET, 0, js, {});
   }
-  // smoother setup on every level but the coarsest, then join the inversions
+  // smoother setup on every level but the coarsest, the inversions, the join
   {
     std::vector<AJob> bi;
     for (mvpf_problem* p : b->probs)
@@ -1830,6 +1818,17 @@ int batch_assemble(mvpf_batch* b, const double* depths, hipStream_t s) {
         bi.push_back(j);
       }
     add(AOP_BLOCK_INVERSE, 0, bi, {});
+    // all coarsest-level inversions at once on the work stream, enqueued
+    // after the assembly so that the host feeds the assembly stream first
+    host([b]() -> int {
+      BCHK(hipStreamWaitEvent(b->work, b->fork, 0));
+      if (dense_invert_batch(b->gj_tab, b->gj_sel, b->gj_n, b->work) != 0) {
+        b->err = "batched coarse inversion launch failed";
+        return MVPF_EDEVICE;
+      }
+      BCHK(hipEventRecord(b->leave, b->work));
+      return 0;
+    });
     host([b, s]() -> int {
       BCHK(hipStreamWaitEvent(s, b->leave, 0));
       for (mvpf_problem* p : b->probs)
