@@ -27,6 +27,7 @@ int red_blocks(int64_t n) {
 // The vectors are taken MD_G at a time, so w is read once per group (not
 // once per vector), and the group's MD_G block sums share one barrier.
 constexpr int MD_G = 8;
+constexpr int MD_U = 4;
 __device__ __forceinline__ void multidot_body(int64_t n, const double* __restrict__ V, int64_t ldv, int k,
                                               const double* __restrict__ w, double* __restrict__ part, int bid,
                                               int nblk) {
@@ -41,7 +42,24 @@ __device__ __forceinline__ void multidot_body(int64_t n, const double* __restric
 #pragma unroll
     for (int g = 0; g < MD_G; ++g) s[g] = 0.0;
     const double* v0 = V + (int64_t)j0 * ldv;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += RB) {
+    // MD_U rows per thread loaded together (one memory round trip instead of
+    // MD_U), summed in the same order as one row at a time
+    int64_t i = lo + threadIdx.x;
+    for (; i + (MD_U - 1) * RB < hi; i += MD_U * RB) {
+      double wv[MD_U], vv[MD_U][MD_G];
+#pragma unroll
+      for (int u = 0; u < MD_U; ++u) wv[u] = w[i + u * RB];
+#pragma unroll
+      for (int u = 0; u < MD_U; ++u)
+#pragma unroll
+        for (int g = 0; g < MD_G; ++g) vv[u][g] = g < g_n ? v0[(int64_t)g * ldv + i + u * RB] : 0.0;
+#pragma unroll
+      for (int u = 0; u < MD_U; ++u)
+#pragma unroll
+        for (int g = 0; g < MD_G; ++g)
+          if (g < g_n) s[g] += vv[u][g] * wv[u];
+    }
+    for (; i < hi; i += RB) {
       const double wi = w[i];
 #pragma unroll
       for (int g = 0; g < MD_G; ++g)
