@@ -1062,10 +1062,12 @@ struct mvpf_batch {
   bool mixed = false;
   hipStream_t stream = nullptr;
   std::vector<mvpf_problem*> probs;
-  // V-cycles of all problems as parallel branches of one graph, reading
-  // vin[i] (FP64) and writing zout[i] (FP32 in mixed mode)
+  // inputs and outputs of the V-cycle graph for problems not in an Arnoldi
+  // step (FP64 in, FP32 out in mixed mode); the others read v_j, write z_j
   std::vector<double*> vin;
   std::vector<void*> zout;
+  // per-problem streams (the assembly stream of batched systems is branch[0];
+  // systems with slabs assemble each problem on its own stream)
   std::vector<hipStream_t> branch;
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr;
@@ -2570,9 +2572,10 @@ mvpf_problem* mvpf_batch_problem(mvpf_batch* b, int i) {
   return b->probs[i];
 }
 
-// All problems' assembly and setup are enqueued before one synchronisation,
-// each on its own branch stream (ordered after the caller's stream), so the
-// small problems' latency-bound phases (coarse inversions above all) overlap.
+// All problems' assembly and setup are enqueued before one synchronisation:
+// batched launches on one stream when every level of every problem is a
+// single slab, else each problem on its own branch stream; in both cases
+// the coarsest-level inversions of all problems run as one batched chain.
 int mvpf_batch_newton_system(mvpf_batch* b, const double* depths) {
   if (!b || !depths) return MVPF_EINVAL;
   BCHK(hipEventRecord(b->enter, b->stream));
