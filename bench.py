@@ -376,21 +376,23 @@ def sweep_traffic(prob, matrix_free):
     return total if len(found) == 2 else None
 
 
-def cpu_baseline(n=16, levels=4):
+def cpu_baseline(n=16, levels=4, prob=None):
     """The oracle (test infrastructure) on a bounded sample of the workload:
     one Newton iteration (autodiff assembly of the tangent, multigrid setup,
-    FGMRES+GMG to 1e-8) of the same indentation problem at n^3 elements."""
+    FGMRES+GMG to 1e-8) of the same indentation problem at n^3 elements, or
+    of `prob` itself when the workload is small enough (8^3)."""
     from oracle import solver as S
     from oracle.fem import Mesh, NDOF
     from oracle.material import Card
     threads = min(16, os.cpu_count() or 1)
     torch.set_num_threads(threads)
-    p = synth.Problem(n, n, n, n_levels=levels, patch=max(2, n // 8), depth_increment=0.01)
+    p = prob or synth.Problem(n, n, n, n_levels=levels, patch=max(2, n // 8), depth_increment=0.01)
+    n, levels = p.nx, p.n_levels
     card = Card(p.material)
     m = Mesh.from_problem(p)
     U = np.zeros((m.n_nodes, NDOF))
     U[:, 3:] = p.eta0()
-    mask, target = S.dirichlet(m, "patch", p.patch, depth=p.depth_increment)
+    mask, target = S.dirichlet(m, p.kind, p.patch, p.radius, depth=p.depth_increment)
     t0 = time.perf_counter()
     sysk = S.NewtonSystem(p, card, U.ravel(), U[:, 3:].ravel().copy(), mask, S.increment(mask, target, U))
     mg = S.Multigrid(p, card, U.ravel(), U[:, 3:].ravel().copy(), mask, K_fine=sysk.K)
@@ -399,6 +401,7 @@ def cpu_baseline(n=16, levels=4):
     t2 = time.perf_counter()
     return dict(value=p.n_dof / (t2 - t0), unit="DOF/s", cores=threads, kind="oracle",
                 sample=f"one Newton iteration of the patch-indentation workload at {n}^3 elements "
+                       f"{'(the whole workload) ' if prob is not None else ''}"
                        f"({p.n_dof} dof, {levels} levels): autodiff assembly + MG setup {t1 - t0:.1f} s, "
                        f"FGMRES+GMG {st.iterations} its {t2 - t1:.1f} s",
                 solve_dof_per_s=p.n_dof / (t2 - t1), iterations=st.iterations)
@@ -508,7 +511,7 @@ def main():
         out["pade_assembly"] = pade_assembly(prob)
     if not a.no_cpu_baseline:
         log("[bench] oracle cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(prob=prob if a.workload == "tiny" else None)
     print(json.dumps(out), flush=True)
 
 
