@@ -325,14 +325,17 @@ int mvpf_indent(mvpf_problem* p, const mvpf_indent_opts* o, mvpf_indent_callback
  * blocks are allocated on first use).  Both give the same operator up to
  * rounding (summation order); takes effect at the next mvpf_newton_system;
  * level ignored.  row_blocks on level 0 and outer_blocks apply to the
- * assembled finest level only. */
+ * assembled finest level only.  "mf_elements_per_block": elements per
+ * workgroup of the matrix-free element kernel, 8, 16 or 32 (64, 128 or 256
+ * threads; default 32; level ignored; results bitwise unchanged). */
 int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value);
 int mvpf_get_tuning(const mvpf_problem* p, const char* key, int level, int* value);
 /* Time candidate launch shapes of the smoother (every level but the coarsest;
- * not the finest when it is matrix-free) and of the outer product (assembled
- * finest level only) on the operators of the last mvpf_newton_system, and
- * keep the fastest.  row_blocks_out (nullable, n_levels ints): chosen
- * values per level, the last entry being the outer product's. */
+ * on a matrix-free finest level its elements per workgroup) and of the outer
+ * product (assembled finest level only) on the operators of the last
+ * mvpf_newton_system, and keep the fastest.  row_blocks_out (nullable,
+ * n_levels ints): chosen values per level (on a matrix-free finest level:
+ * elements per workgroup), the last entry being the outer product's. */
 int mvpf_autotune(mvpf_problem* p, int* row_blocks_out);
 
 /* Per-kernel device timing with HIP events on the problem's stream.  name:

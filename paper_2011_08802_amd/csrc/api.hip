@@ -311,7 +311,7 @@ template <typename T, typename TX>
 void mf_elements(mvpf_problem* p, const TX* x, bool masked, bool sparse = false) {
   Level& L0 = p->lev[0];
   const uint16_t* mask = masked ? L0.mask : nullptr;
-  launch_mf_element<T, TX, T>(L0.g, mfD<T>(p), x, mask, p->card, (T*)p->Cbuf, p->stream, sparse);
+  launch_mf_element<T, TX, T>(L0.g, mfD<T>(p), x, mask, p->card, (T*)p->Cbuf, p->stream, sparse, p->mf_epw);
   if (contact(p)) launch_contact_apply<T, TX>(L0.g, p->sphere, L0.state, mask, x, (T*)p->Cbuf, p->stream);
 }
 
@@ -1010,10 +1010,26 @@ std::vector<int> launch_candidates(const Grid& g) {
 
 template <typename T>
 void autotune_levels(mvpf_problem* p, int* tuned) {
+  if (use_mf(p)) {  // elements per workgroup of the matrix-free smoother sweep
+    Level& L = p->lev[0];
+    double best = 1e30;
+    int bestE = 32;
+    for (int epw : {32, 16, 8}) {
+      p->mf_epw = epw;
+      const double ms = time_launches(p, 5, [&] {
+        mf_elements<T, T>(p, (const T*)L.x, true);
+        launch_mf_gather<2, T, T, T>(L.g, (const T*)p->Cbuf, L.mask, (const T*)L.x, (const T*)L.b, opD<T>(L),
+                                     (T)p->opts.omega, (T*)L.x2, p->stream);
+      });
+      if (ms < best * 0.98) { best = ms; bestE = epw; }
+    }
+    p->mf_epw = bestE;
+    tuned[0] = bestE;
+  }
   for (int l = 0; l < p->L - 1; ++l) {
     Level& L = p->lev[l];
     if (L.g.N <= p->small_nodes) continue;  // small-grid kernels have a fixed shape
-    if (l == 0 && use_mf(p)) continue;      // matrix-free kernels have a fixed shape
+    if (l == 0 && use_mf(p)) continue;      // tuned above
     double best = 1e30;
     int bestG = 0;
     for (int G : launch_candidates(L.g)) {
@@ -2388,6 +2404,9 @@ int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value) {
     p->small_nodes = value;
   } else if (!std::strcmp(key, "coarse_overlap")) {
     p->coarse_overlap = value;
+  } else if (!std::strcmp(key, "mf_elements_per_block")) {
+    if (value != 8 && value != 16 && value != 32) { p->err = "mf_elements_per_block is 8, 16 or 32"; return MVPF_EINVAL; }
+    p->mf_epw = value;
   } else if (!std::strcmp(key, "assembly_slab_elements")) {
     // 0 = the allocated capacity; at least two element layers
     const int64_t lo = 2 * (int64_t)p->lev[0].g.nx * p->lev[0].g.ny + TILE;
@@ -2429,6 +2448,8 @@ int mvpf_get_tuning(const mvpf_problem* p, const char* key, int level, int* valu
     *value = (int)p->ne_use;
   } else if (!std::strcmp(key, "matrix_free")) {
     *value = p->mf;
+  } else if (!std::strcmp(key, "mf_elements_per_block")) {
+    *value = p->mf_epw;
   } else if (!std::strcmp(key, "coarse_overlap")) {
     const int nd = p->lev[p->L - 1].ndense;
     *value = p->coarse_overlap < 0 ? (nd <= COARSE_OVERLAP_MAX ? 1 : 0) : (p->coarse_overlap != 0);

@@ -176,6 +176,7 @@ struct mvpf_problem {
   // in the matrix-free layout, FP64 (outer product, FP64 mode) and FP32
   // (mixed-mode smoother); element outputs go to Cbuf
   int mf = 1;
+  int mf_epw = 32;                   // elements per workgroup of the matrix-free element kernel (8, 16, 32)
   double* Dmf64 = nullptr;
   float* Dmf32 = nullptr;
   mvpf::Sphere* sphere = nullptr;    // the indenter of the current system (device), sphere contact only
@@ -249,8 +250,9 @@ void launch_contact_apply(const Grid& g, const Sphere* sp, const double* state, 
 size_t mf_hessian_values(const Grid& g);
 void launch_mf_pack(const Grid& g, const Chunk& ck, const double* qp, double* D64, float* D32, hipStream_t s);
 template <typename TD, typename TX, typename T>
+// elems_per_wg: elements per workgroup (8, 16 or 32 = 64, 128 or 256 threads)
 void launch_mf_element(const Grid& g, const TD* D, const TX* x, const uint16_t* mask, const DevCard* cd, T* E,
-                       hipStream_t s, bool sparse_x = false);
+                       hipStream_t s, bool sparse_x = false, int elems_per_wg = 32);
 // MODE 0: y = K x; 1: y = b - K x; 2: y = x + omega Dinv (b - K x); constrained rows act as the identity
 template <int MODE, typename T, typename TX, typename TY>
 void launch_mf_gather(const Grid& g, const T* E, const uint16_t* mask, const TX* x, const T* b, const T* Dinv, T omega,

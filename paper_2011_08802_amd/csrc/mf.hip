@@ -107,7 +107,7 @@ __device__ __forceinline__ void mf_element_body(const Grid& g, const TD* __restr
   // neighbouring elements then hit that XCD's L2)
   const int xcd = wg & 7;
   const int bid = xcd * (nb >> 3) + min(xcd, nb & 7) + (wg >> 3);
-  const int64_t t = (int64_t)bid * 256 + threadIdx.x;
+  const int64_t t = (int64_t)bid * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const int gp = lane & 7;
   const int64_t e = (t >> 6) * 8 + (lane >> 3);
@@ -360,15 +360,16 @@ void launch_mf_pack(const Grid& g, const Chunk& ck, const double* qp, double* D6
 constexpr int MF_PF32 = 20, MF_MINB32 = 3, MF_PF64 = 16, MF_MINB64 = 2;
 template <typename TD, typename TX, typename T>
 void launch_mf_element(const Grid& g, const TD* D, const TX* x, const uint16_t* mask, const DevCard* cd, T* E,
-                       hipStream_t s, bool sparse_x) {
+                       hipStream_t s, bool sparse_x, int elems_per_wg) {
   const int64_t threads = (int64_t)g.NEpad * 8;  // NEpad is a multiple of 64: whole wavefronts
   constexpr bool f64 = sizeof(TD) == 8;
   constexpr int MINB = f64 ? MF_MINB64 : MF_MINB32, PF = f64 ? MF_PF64 : MF_PF32;
-  const int blocks = (int)((threads + 255) / 256);
+  const int wg = (elems_per_wg == 8 || elems_per_wg == 16) ? 8 * elems_per_wg : 256;  // divides threads
+  const int blocks = (int)(threads / wg);
   if (sparse_x)
-    mf_element_kernel<TD, TX, T, MINB, PF, true><<<blocks, 256, 0, s>>>(g, D, x, mask, cd, E);
+    mf_element_kernel<TD, TX, T, MINB, PF, true><<<blocks, wg, 0, s>>>(g, D, x, mask, cd, E);
   else
-    mf_element_kernel<TD, TX, T, MINB, PF, false><<<blocks, 256, 0, s>>>(g, D, x, mask, cd, E);
+    mf_element_kernel<TD, TX, T, MINB, PF, false><<<blocks, wg, 0, s>>>(g, D, x, mask, cd, E);
 }
 
 template <int MODE, typename T, typename TX, typename TY>
@@ -378,11 +379,11 @@ void launch_mf_gather(const Grid& g, const T* E, const uint16_t* mask, const TX*
 }
 
 template void launch_mf_element<float, float, float>(const Grid&, const float*, const float*, const uint16_t*,
-                                                     const DevCard*, float*, hipStream_t, bool);
+                                                     const DevCard*, float*, hipStream_t, bool, int);
 template void launch_mf_element<double, float, double>(const Grid&, const double*, const float*, const uint16_t*,
-                                                       const DevCard*, double*, hipStream_t, bool);
+                                                       const DevCard*, double*, hipStream_t, bool, int);
 template void launch_mf_element<double, double, double>(const Grid&, const double*, const double*, const uint16_t*,
-                                                        const DevCard*, double*, hipStream_t, bool);
+                                                        const DevCard*, double*, hipStream_t, bool, int);
 template void launch_mf_gather<0, float, float, float>(const Grid&, const float*, const uint16_t*, const float*,
                                                        const float*, const float*, float, float*, hipStream_t);
 template void launch_mf_gather<1, float, float, float>(const Grid&, const float*, const uint16_t*, const float*,

@@ -200,9 +200,9 @@ def test_launch_shape_does_not_change_results():
     autotuner) leave every result bitwise unchanged."""
     p = synth.tiny()
     U, En = seeded_state(p, 1e-3)
-    say("[launch shape] default vs minimal grids vs autotuned")
+    say("[launch shape] default vs minimal grids vs small matrix-free workgroups vs autotuned")
     outs = []
-    for mode in ("default", "minimal", "autotune"):
+    for mode in ("default", "minimal", "mf8", "autotune"):
         gp = gpu_problem(p, U, En, "mixed")
         gp.newton_system(p.depth_increment)
         if mode == "minimal":
@@ -210,6 +210,9 @@ def test_launch_shape_does_not_change_results():
                 gp.set_tuning("row_blocks", l, 8)
             gp.set_tuning("outer_blocks", 0, 8)
             assert gp.get_tuning("row_blocks", 0) == 8
+        elif mode == "mf8":
+            gp.set_tuning("mf_elements_per_block", 0, 8)
+            assert gp.get_tuning("mf_elements_per_block") == 8
         elif mode == "autotune":
             shapes = gp.autotune()
             assert len(shapes) == p.n_levels
