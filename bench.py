@@ -429,8 +429,9 @@ def main():
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the solve would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path (the structured grid would "
+              "shard into z-slabs, one per GPU, with one node-plane halo per operator application)",
+              file=sys.stderr)
         sys.exit(2)
     if a.calib_copy_mb:
         x = torch.ones(a.calib_copy_mb << 18, dtype=torch.float32, device="cuda")

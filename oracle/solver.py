@@ -12,7 +12,7 @@ solve on the coarsest level, prolongation and post-smoothing, with point-block
 Jacobi relaxation whose 9x9 blocks gather all unknowns of a node and are
 inverted by LU with partial pivoting.
 
-Readings where the paper is silent (all listed in the design doc):
+Readings where the paper is silent:
 * Dirichlet conditions: symmetric elimination (constrained rows and columns of
   K replaced by the identity); a prescribed increment g enters the first
   Newton system by lifting: b_free = -R_free - (K g)_free, b_con = g.

@@ -3,7 +3,7 @@
 Tolerances: FP64 operators (residual, right-hand side, K x on every level,
 V-cycle) <= 1e-12 relative unless stated (double rounding of differently
 ordered sums); FP32 operators <= 2e-6 relative; solves at rtol 1e-12 match
-the oracle's direct solve to <= 1e-9 relative (the benchmark spec's target)."""
+the oracle's direct solve to <= 1e-9 relative."""
 import numpy as np
 import pytest
 import torch
