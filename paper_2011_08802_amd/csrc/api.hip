@@ -1138,17 +1138,19 @@ struct PlanOp {
   std::vector<BJob> jobs;
   size_t off = 0;
   int blocks = 0;
+  int threads = 256;  // workgroup size of the matrix-free element kernels
   std::function<void(hipStream_t)> solo;
 };
 
 struct Planner {
   std::vector<PlanOp> ops;
   // one launch per op kind: jobs[k] go into a new op of kind kinds[k]
-  void add(int op, std::vector<BJob>&& jobs) {
+  void add(int op, std::vector<BJob>&& jobs, int threads = 256) {
     if (jobs.empty()) return;
     PlanOp o;
     o.op = op;
     o.jobs = std::move(jobs);
+    o.threads = threads;
     ops.push_back(std::move(o));
   }
   void solo(std::function<void(hipStream_t)> f) {
@@ -1165,6 +1167,19 @@ BJob job_of(const Level& L) {
   return j;
 }
 
+// Elements per workgroup of a batched matrix-free element launch: the tuned
+// value of its largest problem (results do not depend on it).
+int batch_mf_epw(const std::vector<mvpf_problem*>& ps) {
+  int epw = 32;
+  int64_t most = -1;
+  for (const mvpf_problem* p : ps)
+    if (p->lev[0].g.NE > most) {
+      most = p->lev[0].g.NE;
+      epw = p->mf_epw;
+    }
+  return epw;
+}
+
 template <typename T>
 void plan_mf_elements(Planner& pl, const std::vector<mvpf_problem*>& mf) {
   std::vector<BJob> el;
@@ -1177,7 +1192,7 @@ void plan_mf_elements(Planner& pl, const std::vector<mvpf_problem*>& mf) {
     j.C = p->Cbuf;
     el.push_back(j);
   }
-  pl.add(BOP_MF_ELEMENT, std::move(el));
+  pl.add(BOP_MF_ELEMENT, std::move(el), 8 * batch_mf_epw(mf));
   for (mvpf_problem* p : mf)
     if (contact(p)) {
       Level& L = p->lev[0];
@@ -1384,7 +1399,7 @@ int batch_capture(mvpf_batch* b) {
     o.off = all.size();
     int blocks = 0;
     for (BJob& j : o.jobs) {
-      j.nblk = batch_job_blocks(o.op, j);
+      j.nblk = batch_job_blocks(o.op, j, o.threads);
       j.block0 = blocks;
       blocks += j.nblk;
       all.push_back(j);
@@ -1422,7 +1437,7 @@ int batch_capture(mvpf_batch* b) {
     if (o.op < 0)
       o.solo(s);
     else
-      launch_batch<T, TZ>(o.op, b->jobs_dev + o.off, (int)o.jobs.size(), o.blocks, s);
+      launch_batch<T, TZ>(o.op, b->jobs_dev + o.off, (int)o.jobs.size(), o.blocks, s, o.threads);
   }
   const bool ok = hipGetLastError() == hipSuccess;
   hipGraph_t g = nullptr;
@@ -1475,17 +1490,18 @@ int batch_step_buffers(mvpf_batch* b) {
 template <typename J>
 struct StepOps {
   J* host;
-  std::vector<int> op, first, count, blocks;
+  std::vector<int> op, first, count, blocks, threads;
   int used = 0;
   template <typename BlocksFn>
-  void add(int o, const std::vector<J>& jobs, BlocksFn nblk) {
+  void add(int o, const std::vector<J>& jobs, BlocksFn nblk, int nthreads = 256) {
     if (jobs.empty()) return;
     op.push_back(o);
     first.push_back(used);
     count.push_back((int)jobs.size());
+    threads.push_back(nthreads);
     int bl = 0;
     for (J j : jobs) {
-      j.nblk = nblk(o, j);
+      j.nblk = nblk(o, j, nthreads);
       j.block0 = bl;
       bl += j.nblk;
       host[used++] = j;
@@ -1511,8 +1527,8 @@ int batch_fgmres(mvpf_batch* b, mvpf_solve_stats* st) {
   BCHK(hipStreamSynchronize(s));
   for (auto& k : K) k.after_begin();
   using KP = typename Krylov<T, TZ>::Phase;
-  auto kblocks = [](int o, const KJob& j) { return krylov_job_blocks(o, j); };
-  auto bblocks = [](int o, const BJob& j) { return batch_job_blocks(o, j); };
+  auto kblocks = [](int o, const KJob& j, int) { return krylov_job_blocks(o, j); };
+  auto bblocks = [](int o, const BJob& j, int threads) { return batch_job_blocks(o, j, threads); };
   while (true) {
     bool any = false, arnoldi = false;
     for (auto& k : K) {
@@ -1547,6 +1563,7 @@ int batch_fgmres(mvpf_batch* b, mvpf_solve_stats* st) {
       }
       // operator product w = A z_j
       std::vector<BJob> oe, og;
+      std::vector<mvpf_problem*> omf;
       std::vector<std::function<void(hipStream_t)>> solos;
       for (int i = 0; i < nprob; ++i) {
         if (K[i].phase != KP::ARNOLDI) continue;
@@ -1565,6 +1582,7 @@ int batch_fgmres(mvpf_batch* b, mvpf_solve_stats* st) {
           j.y = w;
           oe.push_back(j);
           og.push_back(j);
+          omf.push_back(p);
           if (contact(p))
             solos.push_back([p, z](hipStream_t st_) {
               Level& L = p->lev[0];
@@ -1576,7 +1594,7 @@ int batch_fgmres(mvpf_batch* b, mvpf_solve_stats* st) {
           });
         }
       }
-      outer.add(BOP_MF_OUTER_ELEMENT, oe, bblocks);
+      outer.add(BOP_MF_OUTER_ELEMENT, oe, bblocks, 8 * batch_mf_epw(omf));
       outer.add(BOP_MF_OUTER_GATHER, og, bblocks);
       // classical Gram-Schmidt twice, norm, Hessenberg columns
       std::vector<KJob> md, rd1, ax1, rd2, ax2, rdn, cp;
@@ -1631,11 +1649,15 @@ int batch_fgmres(mvpf_batch* b, mvpf_solve_stats* st) {
       for (size_t q = 0; q < pre.op.size(); ++q)
         launch_krylov_batch(pre.op[q], b->kjobs_dev + pre.first[q], pre.count[q], pre.blocks[q], s);
       BCHK(hipGraphLaunch(b->exec, s));
-      if (!outer.op.empty())
-        launch_batch<T, TZ>(outer.op[0], b->ojobs_dev + outer.first[0], outer.count[0], outer.blocks[0], s);
+      // element launches, then the per-problem contact and product launches, then the gather
+      size_t q = 0;
+      for (; q < outer.op.size() && outer.op[q] == BOP_MF_OUTER_ELEMENT; ++q)
+        launch_batch<T, TZ>(outer.op[q], b->ojobs_dev + outer.first[q], outer.count[q], outer.blocks[q], s,
+                            outer.threads[q]);
       for (auto& f : solos) f(s);
-      for (size_t q = 1; q < outer.op.size(); ++q)
-        launch_batch<T, TZ>(outer.op[q], b->ojobs_dev + outer.first[q], outer.count[q], outer.blocks[q], s);
+      for (; q < outer.op.size(); ++q)
+        launch_batch<T, TZ>(outer.op[q], b->ojobs_dev + outer.first[q], outer.count[q], outer.blocks[q], s,
+                            outer.threads[q]);
       for (size_t q = 0; q < post.op.size(); ++q)
         launch_krylov_batch(post.op[q], b->kjobs_dev + post.first[q], post.count[q], post.blocks[q], s);
       BCHK(hipGetLastError());

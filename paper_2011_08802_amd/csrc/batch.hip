@@ -8,7 +8,7 @@
 
 namespace mvpf {
 
-int batch_job_blocks(int op, const BJob& j) {
+int batch_job_blocks(int op, const BJob& j, int threads) {
   switch (op) {
     case BOP_CONVERT:
     case BOP_FINISH: return vec_job_blocks(j.g);
@@ -25,13 +25,13 @@ int batch_job_blocks(int op, const BJob& j) {
     case BOP_MF_GATHER_PBJ:
     case BOP_MF_GATHER_DEFECT:
     case BOP_MF_OUTER_ELEMENT:
-    case BOP_MF_OUTER_GATHER: return mf_job_blocks(op, j.g);
+    case BOP_MF_OUTER_GATHER: return mf_job_blocks(op, j.g, threads);
     default: return 0;
   }
 }
 
 template <typename T, typename TZ>
-void launch_batch(int op, const BJob* jobs_dev, int njobs, int total_blocks, hipStream_t s) {
+void launch_batch(int op, const BJob* jobs_dev, int njobs, int total_blocks, hipStream_t s, int threads) {
   if (njobs <= 0 || total_blocks <= 0) return;
   switch (op) {
     case BOP_CONVERT:
@@ -41,14 +41,14 @@ void launch_batch(int op, const BJob* jobs_dev, int njobs, int total_blocks, hip
     case BOP_COARSE: launch_coarse_solve_batch<T>(jobs_dev, njobs, total_blocks, s); break;
     case BOP_MF_ELEMENT:
     case BOP_MF_GATHER_PBJ:
-    case BOP_MF_GATHER_DEFECT: launch_mf_batch<T>(op, jobs_dev, njobs, total_blocks, s); break;
+    case BOP_MF_GATHER_DEFECT: launch_mf_batch<T>(op, jobs_dev, njobs, total_blocks, s, threads); break;
     case BOP_MF_OUTER_ELEMENT:
-    case BOP_MF_OUTER_GATHER: launch_mf_outer_batch<TZ>(op, jobs_dev, njobs, total_blocks, s); break;
+    case BOP_MF_OUTER_GATHER: launch_mf_outer_batch<TZ>(op, jobs_dev, njobs, total_blocks, s, threads); break;
     default: launch_bsr_batch<T>(op, jobs_dev, njobs, total_blocks, s); break;
   }
 }
-template void launch_batch<float, float>(int, const BJob*, int, int, hipStream_t);
-template void launch_batch<float, double>(int, const BJob*, int, int, hipStream_t);
-template void launch_batch<double, double>(int, const BJob*, int, int, hipStream_t);
+template void launch_batch<float, float>(int, const BJob*, int, int, hipStream_t, int);
+template void launch_batch<float, double>(int, const BJob*, int, int, hipStream_t, int);
+template void launch_batch<double, double>(int, const BJob*, int, int, hipStream_t, int);
 
 }  // namespace mvpf

@@ -448,15 +448,16 @@ void launch_mf_pack_batch(const AJob* jobs, int njobs, int blocks, hipStream_t s
 int mf_pack_job_blocks(AJob& j);
 void launch_krylov_batch(int op, const KJob* jobs, int njobs, int blocks, hipStream_t s);
 template <typename TZ>
-void launch_mf_outer_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s);
-// workgroups one job of op needs
-int batch_job_blocks(int op, const BJob& j);
+void launch_mf_outer_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s, int threads = 256);
+// workgroups one job of op needs (threads: workgroup size of the
+// matrix-free element kernels, 64, 128 or 256)
+int batch_job_blocks(int op, const BJob& j, int threads = 256);
 int bsr_job_blocks(int op, const Grid& g);
-int mf_job_blocks(int op, const Grid& g);
+int mf_job_blocks(int op, const Grid& g, int threads = 256);
 int vec_job_blocks(const Grid& g);
 // T: multigrid precision; TZ: type of the preconditioned vector (BOP_FINISH)
 template <typename T, typename TZ>
-void launch_batch(int op, const BJob* jobs_dev, int njobs, int total_blocks, hipStream_t s);
+void launch_batch(int op, const BJob* jobs_dev, int njobs, int total_blocks, hipStream_t s, int threads = 256);
 template <typename T>
 void launch_bsr_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s);
 template <typename T>
@@ -464,7 +465,7 @@ void launch_transfer_batch(int op, const BJob* jobs, int njobs, int blocks, hipS
 template <typename T>
 void launch_coarse_solve_batch(const BJob* jobs, int njobs, int blocks, hipStream_t s);
 template <typename T>
-void launch_mf_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s);
+void launch_mf_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s, int threads = 256);
 template <typename T, typename TZ>
 void launch_vec_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s);
 

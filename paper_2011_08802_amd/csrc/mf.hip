@@ -414,19 +414,20 @@ __global__ void __launch_bounds__(256) mf_gather_batch(const BJob* __restrict__ 
                                 (T*)j.y, bid);
 }
 template <typename T>
-void launch_mf_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s) {
+void launch_mf_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s, int threads) {
   constexpr bool f64 = sizeof(T) == 8;
   if (op == BOP_MF_ELEMENT)
-    mf_element_batch<T, f64 ? MF_MINB64 : MF_MINB32, f64 ? MF_PF64 : MF_PF32><<<blocks, 256, 0, s>>>(jobs, njobs);
+    mf_element_batch<T, f64 ? MF_MINB64 : MF_MINB32, f64 ? MF_PF64 : MF_PF32><<<blocks, threads, 0, s>>>(jobs, njobs);
   else if (op == BOP_MF_GATHER_PBJ)
     mf_gather_batch<2, T><<<blocks, 256, 0, s>>>(jobs, njobs);
   else if (op == BOP_MF_GATHER_DEFECT)
     mf_gather_batch<1, T><<<blocks, 256, 0, s>>>(jobs, njobs);
 }
-template void launch_mf_batch<float>(int, const BJob*, int, int, hipStream_t);
-template void launch_mf_batch<double>(int, const BJob*, int, int, hipStream_t);
-int mf_job_blocks(int op, const Grid& g) {
-  return (op == BOP_MF_ELEMENT || op == BOP_MF_OUTER_ELEMENT) ? (int)(((int64_t)g.NEpad * 8 + 255) / 256)
+template void launch_mf_batch<float>(int, const BJob*, int, int, hipStream_t, int);
+template void launch_mf_batch<double>(int, const BJob*, int, int, hipStream_t, int);
+// element kernels: threads (64, 128 or 256) divide the 8 NEpad lanes exactly
+int mf_job_blocks(int op, const Grid& g, int threads) {
+  return (op == BOP_MF_ELEMENT || op == BOP_MF_OUTER_ELEMENT) ? (int)((int64_t)g.NEpad * 8 / threads)
                                                              : (g.Npad + 255) / 256;
 }
 
@@ -447,13 +448,13 @@ __global__ void __launch_bounds__(256) mf_outer_gather_batch(const BJob* __restr
                                         (double*)j.y, bid);
 }
 template <typename TZ>
-void launch_mf_outer_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s) {
+void launch_mf_outer_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s, int threads) {
   if (op == BOP_MF_OUTER_ELEMENT)
-    mf_outer_element_batch<TZ><<<blocks, 256, 0, s>>>(jobs, njobs);
+    mf_outer_element_batch<TZ><<<blocks, threads, 0, s>>>(jobs, njobs);
   else if (op == BOP_MF_OUTER_GATHER)
     mf_outer_gather_batch<TZ><<<blocks, 256, 0, s>>>(jobs, njobs);
 }
-template void launch_mf_outer_batch<float>(int, const BJob*, int, int, hipStream_t);
-template void launch_mf_outer_batch<double>(int, const BJob*, int, int, hipStream_t);
+template void launch_mf_outer_batch<float>(int, const BJob*, int, int, hipStream_t, int);
+template void launch_mf_outer_batch<double>(int, const BJob*, int, int, hipStream_t, int);
 
 }  // namespace mvpf

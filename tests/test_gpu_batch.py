@@ -96,10 +96,12 @@ def test_batch_problem_matches_oracle():
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_batch_contact_and_assembled_finest_bitwise(precision):
     """A batch mixing a sphere-contact problem (its contact terms are
-    per-problem launches inside the batched chains) and a problem on the
+    per-problem launches inside the batched chains), a problem on the
     assembled finest level (tuning matrix_free = 0: half-stencil sweeps and
-    operator product) with a matrix-free patch problem: every problem bitwise
-    as solved alone under the same tuning, on two replays."""
+    operator product) and a matrix-free patch problem tuned to 16 elements per
+    workgroup (the largest problem, so the batched element launches take 16
+    elements per workgroup): every problem bitwise as solved alone under the
+    same tuning, on two replays."""
     from paper_2011_08802_amd import mvpf
     sb = small_batch()
     probs = [synth.Problem(8, 8, 4, lz=0.5, n_levels=3, kind="sphere", radius=0.5, seed=synth.BASE_SEED + 7),
@@ -108,11 +110,12 @@ def test_batch_contact_and_assembled_finest_bitwise(precision):
     states = [seeded_state(p, 1e-3) for p in probs]
     B = mvpf.Batch(probs, precision)
     B.problem(2).set_tuning("matrix_free", 0, 0)
+    B.problem(1).set_tuning("mf_elements_per_block", 0, 16)  # the largest problem: sets the batch's launches
     say(f"[batch mixed kinds {precision}] single-problem references")
     ref = []
     for i, (p, (U, En)) in enumerate(zip(probs, states)):
         gp = mvpf.Problem(p, precision)
-        for key in ("small_grid_nodes", "matrix_free"):
+        for key in ("small_grid_nodes", "matrix_free", "mf_elements_per_block"):
             gp.set_tuning(key, 0, B.problem(i).get_tuning(key))
         gp.set_state(U[:, :3], U[:, 3:], En, 0.0)
         gp.newton_system(depths[i])
