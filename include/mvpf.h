@@ -154,8 +154,8 @@ typedef struct {
   int converged;
   double residual0;      /* ||b|| of the first Newton system */
   double residual;       /* final free-dof residual norm */
-  double assemble_ms;    /* residual + tangent assembly on all levels */
-  double setup_ms;       /* block inverses + coarse factorisation */
+  double assemble_ms;    /* residual + tangent assembly on all levels, block inverses */
+  double setup_ms;       /* rest of the coarse factorisation (it overlaps the assembly) */
   double solve_ms;       /* all FGMRES solves */
 } mvpf_step_stats;
 

@@ -904,6 +904,12 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
   // lifting of the prescribed increment, then symmetric elimination
   TRY(system_rhs(p, depth));
   launch_apply_dirichlet(L0.g, L0.mask, L0.A64, L0.A32, L0.diag64, s);
+  // the smoother's block inverses, enqueued before the coarse inversion's
+  // long chain of launches (the host can block while it enqueues that chain)
+  for (int l = 0; l < p->L - 1; ++l) {
+    Level& L = p->lev[l];
+    launch_block_inverse(L.g, L.diag64, L.Dinv64, L.Dinv32, setup_status(p), s);
+  }
   TRY(launch_check(p, "assembly"));
   if (coarse_inline) {
     const bool overlap = p->coarse_overlap < 0 ? nd <= COARSE_OVERLAP_MAX : p->coarse_overlap != 0;
@@ -922,18 +928,14 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
   return 0;
 }
 
-// block inverses of the smoother; joins the coarse inversion
 // pinned host slot of the setup status
 int* host_status(mvpf_problem* p) { return (int*)(p->hhost + 3 * (MAX_RESTART + 2)); }
 
-// block inverses of the smoother; joins the coarse inversion; status -> host
+// joins the coarse inversion; status -> host (build_system enqueued the
+// smoother's block inverses)
 int setup_enqueue(mvpf_problem* p) {
   hipStream_t s = p->stream;
   int* status = setup_status(p);
-  for (int l = 0; l < p->L - 1; ++l) {
-    Level& L = p->lev[l];
-    launch_block_inverse(L.g, L.diag64, L.Dinv64, L.Dinv32, status, s);
-  }
   if (p->coarse_pending) {
     HIPCHK(hipStreamWaitEvent(s, p->ev_join, 0));
     p->coarse_pending = false;

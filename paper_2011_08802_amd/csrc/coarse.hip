@@ -142,17 +142,72 @@ __device__ void pivot_block_inverse(int B, const double* __restrict__ F, const i
 // candidate).  After each step the windows shift left by one, so the active
 // column is always W[q][0] (all register indices static).  One barrier per
 // column: every wavefront's best row publishes its value, index and window
-// in LDS slots (double-buffered by column parity), and every thread picks the
-// block's winner from the slots itself; ties go to the lowest row.
-// on_pivot(jj, p) runs in the thread that holds the chosen row p.
+// in LDS slots (double-buffered by column parity), and every wavefront picks
+// the block's winner from the slots itself; ties go to the lowest row.
+// Candidates are ordered by |entry|, then by the lower row; the order is
+// total, so the winner does not depend on the order in which pairs are
+// compared.  Inside a wavefront the comparisons run over DPP lane exchanges
+// and scalar lane reads (no LDS round trips).
+// on_pivot(jj, p) runs in the thread that holds the chosen row p; it writes
+// LDS only, since a global store in the loop would hold up the next barrier
+// (flat stores count against the LDS wait counter).
 // strict: a column without a non-zero candidate makes the block singular
 // (returns -1); otherwise such a column takes its lowest candidate row without
 // elimination, and the loop ends early (returns the count) when no candidate
 // rows are left.
 constexpr int NWV = GJ_THREADS / 64;
-template <int RPT, int PB, typename OnPivot>
+static_assert(NWV == 8, "the slot reduction covers one group of 8 lanes");
+
+// (ov, oi) beats (v, idx): a candidate (row >= 0) beats none, then the larger
+// value, then the lower row
+__device__ __forceinline__ bool cand_better(double ov, int oi, double v, int idx) {
+  return oi >= 0 && (idx < 0 || ov > v || (ov == v && oi < idx));
+}
+template <int CTRL>
+__device__ __forceinline__ void cand_step(double& v, int& idx, int& slot) {
+  const double ov = dpp_t<CTRL>(v);
+  const int oi = dpp_i<CTRL>(idx), os = dpp_i<CTRL>(slot);
+  if (cand_better(ov, oi, v, idx)) { v = ov; idx = oi; slot = os; }
+}
+// the best of groups of 8 lanes in each of their lanes: xor 1, xor 2, then the
+// half-row mirror (lane i <-> 7 - i) joins the two quads
+__device__ __forceinline__ void cand_best8(double& v, int& idx, int& slot) {
+  cand_step<0xB1>(v, idx, slot);
+  cand_step<0x4E>(v, idx, slot);
+  cand_step<0x141>(v, idx, slot);
+}
+// the best of lane `src` of the wavefront, in every lane
+__device__ __forceinline__ void cand_read(double& v, int& idx, int& slot, int src) {
+  v = read_lane(v, src);
+  idx = __builtin_amdgcn_readlane(idx, src);
+  slot = __builtin_amdgcn_readlane(slot, src);
+}
+// the best of the wavefront in every lane: rows of 16 lanes by DPP (groups of
+// 8, then the row mirror lane i <-> 15 - i), then the four rows from scalar
+// reads of lanes 0, 16, 32 and 48
+__device__ __forceinline__ void cand_best64(double& v, int& idx, int& slot) {
+  cand_best8(v, idx, slot);
+  cand_step<0x140>(v, idx, slot);
+  double bv = v;
+  int bi = idx, bs = slot;
+  cand_read(bv, bi, bs, 0);
+#pragma unroll
+  for (int r = 16; r < 64; r += 16) {
+    double ov = v;
+    int oi = idx, os = slot;
+    cand_read(ov, oi, os, r);
+    if (cand_better(ov, oi, bv, bi)) { bv = ov; bi = oi; bs = os; }
+  }
+  v = bv;
+  idx = bi;
+  slot = bs;
+}
+
+// NW: wavefronts of the workgroup (at most NWV)
+template <int RPT, int PB, int NW, typename OnPivot>
 __device__ int window_eliminate(double (&W)[RPT][PB], bool (&act)[RPT], const int (&rid)[RPT], int B, bool strict,
                                 OnPivot on_pivot, double (*cv)[NWV], int (*ci)[NWV], double (*crow)[NWV][PB]) {
+  static_assert(NW >= 1 && NW <= NWV, "one slot per wavefront");
   const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
 #pragma unroll 1
   for (int jj = 0; jj < B; ++jj) {
@@ -163,37 +218,35 @@ __device__ int window_eliminate(double (&W)[RPT][PB], bool (&act)[RPT], const in
       const double cand = fabs(W[q][0]);
       if (act[q] && (cand > v || (cand == v && rid[q] < idx))) { v = cand; idx = rid[q]; }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(v, off, 64);
-      const int oi = __shfl_xor(idx, off, 64);
-      if (oi >= 0 && (idx < 0 || ov > v || (ov == v && oi < idx))) { v = ov; idx = oi; }
-    }
+    int unused = 0;
+    cand_best64(v, idx, unused);
     const int par = jj & 1;
     bool mine = false;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) mine = mine || (act[q] && rid[q] == idx);
-    if (idx >= 0 && mine) {
+    if (lane == 0) {
       cv[par][wid] = v;
       ci[par][wid] = idx;
+    }
+    if (idx >= 0 && mine) {
 #pragma unroll
       for (int q = 0; q < RPT; ++q)
         if (act[q] && rid[q] == idx) {
 #pragma unroll
           for (int b = 0; b < PB; ++b) crow[par][wid][b] = W[q][b];
         }
-    } else if (idx < 0 && lane == 0) {
-      cv[par][wid] = -1.0;
-      ci[par][wid] = -1;
     }
     __syncthreads();
+    // lanes 0 .. NW - 1 take one slot each; the best of them, in every lane
     double bv = -1.0;
     int p = -1, pw = 0;
-#pragma unroll
-    for (int k = 0; k < NWV; ++k) {
-      const double ov = cv[par][k];
-      const int oi = ci[par][k];
-      if (oi >= 0 && (p < 0 || ov > bv || (ov == bv && oi < p))) { bv = ov; p = oi; pw = k; }
+    if (lane < NW) {
+      bv = cv[par][lane];
+      p = ci[par][lane];
+      pw = lane;
     }
+    cand_best8(bv, p, pw);
+    cand_read(bv, p, pw, 0);
     if (p < 0) return strict ? -1 : jj;  // uniform: no candidate rows left
     if (strict && !(bv > 0.0)) return -1;  // uniform: singular
 #pragma unroll
@@ -215,10 +268,13 @@ __device__ int window_eliminate(double (&W)[RPT][PB], bool (&act)[RPT], const in
   return B;
 }
 
-// Sub-panel factorisation (columns c0 .. c0 + B - 1) in one workgroup.
-// Thread t owns rows t, t + GJ_THREADS, ... (RPT of them); n <= GJ_THREADS * RPT.
-template <int RPT, int PB>
-__global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(GJJobs J, GJJob one, int oc0, int c0) {
+// Sub-panel factorisation (columns c0 .. c0 + B - 1) in one workgroup of NT
+// threads.  Thread t owns rows t, t + NT, ... (RPT of them); n <= NT * RPT.
+// A column costs every wavefront the same pivot search whatever its row
+// count, so fewer, fuller wavefronts (NT = 256, 5 rows per thread) take less
+// time per column than 512 threads with 3 rows each.
+template <int RPT, int PB, int NT>
+__global__ void __launch_bounds__(NT) gj_panel_kernel(GJJobs J, GJJob one, int oc0, int c0) {
   const GJJob& jb = gj_job(J, one);
   const int n = jb.n;
   int nbw_, B;
@@ -250,7 +306,7 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(GJJobs J, GJJob on
   // become the active column).
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int i = tid + q * GJ_THREADS;
+    const int i = tid + q * NT;
     const bool ok = i < n;
     const int ic = ok ? i : 0;
     rid[q] = i;
@@ -258,18 +314,22 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_panel_kernel(GJJobs J, GJJob on
 #pragma unroll
     for (int b = 0; b < PB; ++b) W[q][b] = Wc[(int64_t)(b < B ? b : B - 1) * n + ic];
   }
-  const int got = window_eliminate<RPT, PB>(W, act, rid, B, true, [&](int jj, int p) {
-    done[p] = 1;
-    prow[c0 + jj] = p;
-    pr[jj] = p;
-    M[(int64_t)p * w + n + c0 + jj] = 1.0;  // unit column of the new pivot
-  }, cv, ci, crow);
+  // the pivots go to LDS during the elimination and to global memory after it
+  // (a global store inside the column loop would hold up every barrier)
+  const int got =
+      window_eliminate<RPT, PB, NT / 64>(W, act, rid, B, true, [&](int jj, int p) { pr[jj] = p; }, cv, ci, crow);
   if (got < 0) {
     if (tid == 0) atomicOr(status, 1);
     return;  // uniform
   }
   __syncthreads();  // pr[] complete
   pivot_block_inverse<PB>(B, F, pr, Pinv, status, Mp, fr, rowc);
+  if (tid < B) {  // after the inverse's barriers, which would wait for these stores
+    const int p = pr[tid];
+    done[p] = 1;
+    prow[c0 + tid] = p;
+    M[(int64_t)p * w + n + c0 + tid] = 1.0;  // unit column of the new pivot
+  }
 }
 
 // active column j (0 .. 2 nbw - 1) of the outer panel at c0
@@ -338,10 +398,22 @@ __global__ void __launch_bounds__(256) gj_update_kernel(GJJobs J, GJJob one, int
   double Rc[GJB];
 #pragma unroll
   for (int b = 0; b < GJB; ++b) Rc[b] = R[(int64_t)(b < B ? b : B - 1) * 2 * nbw + j];
+  // all rows' old values are loaded before the first store (each store would
+  // otherwise complete before the next row's load is waited for)
+  int sr[UPR];
+#pragma unroll
+  for (int rr = 0; rr < UPR; ++rr) sr[rr] = sub[rr];
+  double old[UPR];
+#pragma unroll
+  for (int rr = 0; rr < UPR; ++rr) {
+    const int i = r0 + rr;
+    old[rr] = (i < n && sr[rr] < 0) ? M[(int64_t)i * w + c] : 0.0;
+  }
+#pragma unroll
   for (int rr = 0; rr < UPR; ++rr) {
     const int i = r0 + rr;
     if (i >= n) break;
-    const int pi = sub[rr];
+    const int pi = sr[rr];
     double v;
     if (pi >= 0) {
       v = Rc[0];
@@ -349,7 +421,7 @@ __global__ void __launch_bounds__(256) gj_update_kernel(GJJobs J, GJJob one, int
       for (int b = 1; b < GJB; ++b)
         if (b == pi) v = Rc[b];
     } else {
-      v = M[(int64_t)i * w + c];
+      v = old[rr];
 #pragma unroll
       for (int b = 0; b < GJB; ++b) v -= Fs[rr][b] * Rc[b];
     }
@@ -392,6 +464,7 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_tourn0_kernel(GJJobs J, GJJob o
   __shared__ double cv[2][NWV];
   __shared__ int ci[2][NWV];
   __shared__ double crow[2][NWV][GJB];
+  __shared__ int pv[GJB];  // the block's pivot rows (written to global memory after the elimination)
   const GJJob& jb = gj_job(J, one);
   const int n = jb.n;
   int nbw, B;
@@ -409,9 +482,10 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_tourn0_kernel(GJJobs J, GJJob o
 #pragma unroll
   for (int b = 0; b < GJB; ++b) W[0][b] = Wc[(int64_t)(b < B ? b : B - 1) * n + ic];
   int* mine = cand + blockIdx.x * GJB;
-  const int got = window_eliminate<1, GJB>(W, act, rid, B, false, [&](int jj, int p) { mine[jj] = p; }, cv, ci,
-                                           crow);
-  for (int jj = got + (int)threadIdx.x; jj < GJB; jj += blockDim.x) mine[jj] = -1;
+  const int got =
+      window_eliminate<1, GJB, NWV>(W, act, rid, B, false, [&](int jj, int p) { pv[jj] = p; }, cv, ci, crow);
+  __syncthreads();  // pv[] complete
+  for (int jj = threadIdx.x; jj < GJB; jj += blockDim.x) mine[jj] = jj < got ? pv[jj] : -1;
 }
 
 __global__ void __launch_bounds__(GJ_THREADS) gj_tourn1_kernel(GJJobs J, GJJob one, int c0, int s0) {
@@ -443,18 +517,20 @@ __global__ void __launch_bounds__(GJ_THREADS) gj_tourn1_kernel(GJJobs J, GJJob o
   const int rid[1] = {r >= 0 ? r : n + tid};  // distinct ids for empty slots (never active)
 #pragma unroll
   for (int b = 0; b < GJB; ++b) W[0][b] = F[(int64_t)rc * B + (b < B ? b : B - 1)];
-  const int got = window_eliminate<1, GJB>(W, act, rid, B, true, [&](int jj, int p) {
-    done[p] = 1;
-    prow[s0 + jj] = p;
-    pr[jj] = p;
-    M[(int64_t)p * w + n + s0 + jj] = 1.0;
-  }, cv, ci, crow);
+  const int got =
+      window_eliminate<1, GJB, NWV>(W, act, rid, B, true, [&](int jj, int p) { pr[jj] = p; }, cv, ci, crow);
   if (got < 0) {
     if (tid == 0) atomicOr(status, 1);
     return;  // uniform
   }
-  __syncthreads();
+  __syncthreads();  // pr[] complete
   pivot_block_inverse<GJB>(B, F, pr, Pinv, status, Mp, fr, rowc);
+  if (tid < B) {
+    const int p = pr[tid];
+    done[p] = 1;
+    prow[s0 + tid] = p;
+    M[(int64_t)p * w + n + s0 + tid] = 1.0;
+  }
 }
 
 // Yo[i][k] = M[i][n + c0 + k] - [i == p_{c0+k}];  Rb[k][j] = M[p_{c0+k}][c0 + nbw + j]
@@ -605,17 +681,20 @@ GJJob gj_make_job(int n, const double* a, double* inv, double* work, int* status
   return j;
 }
 
-// panel kernel variant of a size (0..3: RPT 1..4 in registers, 4: tournament)
+// panel kernel variant of a size (0..3: RPT 1..4 rows per thread of 512 in
+// registers, 4: tournament, 5: 5 rows per thread of 256)
+constexpr int GJ_VARIANTS = 6;
 int gj_variant(int n) {
   if (n > 4 * GJ_THREADS) return 4;
+  if (n > 2 * GJ_THREADS && n <= 5 * 256) return 5;
   return (n - 1) / GJ_THREADS;
 }
 
 // The step loop over the widest job.  ns: job sizes in table order; groups:
 // for each variant, its device selection list and size (single job: J.tab
 // null, the job in `one`).
-int gj_run(const GJJobs& J, const GJJob& one, const std::vector<int>& ns, const int* const groups[5],
-           const int gsize[5], hipStream_t s) {
+int gj_run(const GJJobs& J, const GJJob& one, const std::vector<int>& ns, const int* const groups[GJ_VARIANTS],
+           const int gsize[GJ_VARIANTS], hipStream_t s) {
   const int nj = (int)ns.size();
   int nmax = 0;
   for (int n : ns) nmax = std::max(nmax, n);
@@ -630,14 +709,15 @@ int gj_run(const GJJobs& J, const GJJob& one, const std::vector<int>& ns, const 
         any = any || (c0 < n && s0 < std::min(n, c0 + GJ_NB) && (s0 - c0) % gj_pbw(n) == 0);
       if (!any) continue;
       gj_fetch_kernel<<<dim3((nmax * GJB + 255) / 256, 1, nj), 256, 0, s>>>(J, one, c0, s0);
-      for (int v = 0; v < 5; ++v) {
+      for (int v = 0; v < GJ_VARIANTS; ++v) {
         if (!gsize[v]) continue;
         const GJJobs G{J.tab, groups[v]};
         switch (v) {
-          case 0: gj_panel_kernel<1, 32><<<dim3(1, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0); break;
-          case 1: gj_panel_kernel<2, 32><<<dim3(1, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0); break;
-          case 2: gj_panel_kernel<3, 16><<<dim3(1, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0); break;
-          case 3: gj_panel_kernel<4, 16><<<dim3(1, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0); break;
+          case 0: gj_panel_kernel<1, 32, GJ_THREADS><<<dim3(1, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0); break;
+          case 1: gj_panel_kernel<2, 32, GJ_THREADS><<<dim3(1, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0); break;
+          case 2: gj_panel_kernel<3, 16, GJ_THREADS><<<dim3(1, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0); break;
+          case 3: gj_panel_kernel<4, 16, GJ_THREADS><<<dim3(1, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0); break;
+          case 5: gj_panel_kernel<5, 16, 256><<<dim3(1, 1, gsize[v]), 256, 0, s>>>(G, one, c0, s0); break;
           default:
             gj_tourn0_kernel<<<dim3(16, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0);
             gj_tourn1_kernel<<<dim3(1, 1, gsize[v]), GJ_THREADS, 0, s>>>(G, one, c0, s0);
@@ -656,8 +736,8 @@ int gj_run(const GJJobs& J, const GJJob& one, const std::vector<int>& ns, const 
 // a: n x n input (not modified); inv: n x n output; work: dense_invert_work(n) bytes.
 int dense_invert(int n, double* a, double* inv, double* work, int* status, hipStream_t s) {
   const GJJob one = gj_make_job(n, a, inv, work, status);
-  const int* groups[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  int gsize[5] = {0, 0, 0, 0, 0};
+  const int* groups[GJ_VARIANTS] = {};
+  int gsize[GJ_VARIANTS] = {};
   gsize[gj_variant(n)] = 1;
   return gj_run(GJJobs{nullptr, nullptr}, one, std::vector<int>{n}, groups, gsize, s);
 }
@@ -665,11 +745,11 @@ int dense_invert(int n, double* a, double* inv, double* work, int* status, hipSt
 // Batched: job tables built by dense_invert_batch_setup (device memory the
 // caller owns); sizes in table order.
 int dense_invert_batch(const GJJob* tab_dev, const int* sel_dev, const std::vector<int>& ns, hipStream_t s) {
-  const int* groups[5];
-  int gsize[5] = {0, 0, 0, 0, 0};
+  const int* groups[GJ_VARIANTS];
+  int gsize[GJ_VARIANTS] = {};
   for (int n : ns) gsize[gj_variant(n)]++;
   int off = 0;
-  for (int v = 0; v < 5; ++v) {
+  for (int v = 0; v < GJ_VARIANTS; ++v) {
     groups[v] = sel_dev + off;
     off += gsize[v];
   }
@@ -680,7 +760,7 @@ int dense_invert_batch(const GJJob* tab_dev, const int* sel_dev, const std::vect
 // host-side selection lists for dense_invert_batch: job indices grouped by variant
 std::vector<int> dense_invert_batch_selection(const std::vector<int>& ns) {
   std::vector<int> sel;
-  for (int v = 0; v < 5; ++v)
+  for (int v = 0; v < GJ_VARIANTS; ++v)
     for (int i = 0; i < (int)ns.size(); ++i)
       if (gj_variant(ns[i]) == v) sel.push_back(i);
   return sel;

@@ -38,6 +38,30 @@ constexpr int NDOF = 9;
 constexpr int NSTATE = 15;
 constexpr int NSTEN = 27;
 constexpr int NUP = 14;              // stored stencil blocks per row (diagonal + 13 upper)
+
+// Lane exchange by a DPP control word (quad permutations, row mirrors): the
+// value of the lane the control selects, moved through the VALU (no LDS).
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_t(float v) {
+  return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_t(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)u), hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// the value of lane `lane` in every lane (a scalar register read)
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
 constexpr int NPAIR = 36;            // element node pairs a <= b
 constexpr int NBLK = 81;
 constexpr int TILE = 64;

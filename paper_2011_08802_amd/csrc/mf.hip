@@ -33,20 +33,6 @@ constexpr double MGQ1 = 0.78867513459481288225;
 // Lane exchanges inside groups of 8 lanes by DPP (no LDS traffic): xor 1 and
 // xor 2 are quad permutations; xor 4 is the half-row mirror (lane i <- 7 - i)
 // followed by the quad reversal (i <- i ^ 3), since (7 - i) ^ 3 = i ^ 4.
-template <int CTRL>
-__device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
-}
-template <int CTRL>
-__device__ __forceinline__ float dpp_t(float v) {
-  return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_t(double v) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)u), hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(u >> 32));
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
 template <int X, typename T>
 __device__ __forceinline__ T lane_xor(T v) {
   if constexpr (X == 1) return dpp_t<0xB1>(v);       // quad_perm [1,0,3,2]
