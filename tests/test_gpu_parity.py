@@ -260,15 +260,31 @@ def test_large_coarse_inverse(n, levels, coarse_dof):
     blocked Gauss-Jordan with several outer panels and narrow sub-panels.
     Coarse operator, V-cycle and FGMRES solve vs the oracle."""
     p = synth.Problem(n, n, n, n_levels=levels, patch=4, depth_increment=0.01)
+    _coarse_case(p, levels, coarse_dof, f"{n}^3 L{levels}")
+
+
+@pytest.mark.parametrize("nx,ny,nz,coarse_dof", [(6, 8, 10, 1080), (6, 10, 10, 1296)])
+def test_coarse_panel_variants(nx, ny, nz, coarse_dof):
+    """Two-level hierarchies on box meshes whose coarsest level has 1 080
+    unknowns (sub-panels factored by 256 threads holding 5 rows each, the
+    variant for 1 025 to 1 280 unknowns) or 1 296 unknowns (512 threads
+    holding 3 rows each): coarse operator, V-cycle and FGMRES solve vs the
+    oracle."""
+    h = 1.0 / max(nx, ny, nz)
+    p = synth.Problem(nx, ny, nz, lx=nx * h, ly=ny * h, lz=nz * h, n_levels=2, patch=4, depth_increment=0.01)
+    _coarse_case(p, 2, coarse_dof, f"{nx}x{ny}x{nz} L2")
+
+
+def _coarse_case(p, levels, coarse_dof, tag):
     U, En = seeded_state(p, 5e-4)
-    say(f"[{n}^3 L{levels}] oracle (coarse {coarse_dof} dof)")
+    say(f"[{tag}] oracle (coarse {coarse_dof} dof)")
     oc = OracleCase(p, U, En, p.depth_increment, direct=False)
     assert oc.mg.levels[-1].A.shape[0] == coarse_dof
     rng = np.random.default_rng(7)
     v = rng.standard_normal(oc.sys.b.shape[0])
     zo = oc.mg.precondition(v)
     xo, sto = S.fgmres(oc.sys.A, oc.sys.b, oc.mg.precondition, rtol=1e-12)
-    say(f"[{n}^3 L{levels}] GPU")
+    say(f"[{tag}] GPU")
     gp = gpu_problem(p, U, En, "fp64", rtol=1e-12)
     gp.newton_system(p.depth_increment)
     x = rng.standard_normal(coarse_dof)
