@@ -167,7 +167,7 @@ typedef struct {
 } mvpf_info;
 
 /* Fill opts with the defaults (FP64, rtol 1e-8, restart 30, max_it 500,
- * V(2,2), omega 0.5, newton_max 12, newton_rtol 1e-9). */
+ * V(2,2), omega 0.55, newton_max 12, newton_rtol 1e-9). */
 void mvpf_default_opts(mvpf_opts* opts);
 
 /* Create a problem: validates the inputs, builds the material card in the

@@ -1967,7 +1967,7 @@ void mvpf_default_opts(mvpf_opts* o) {
   o->max_it = 500;
   o->nu_pre = 2;
   o->nu_post = 2;
-  o->omega = 0.5;
+  o->omega = 0.55;
   o->newton_max = 12;
   o->newton_rtol = 1e-9;
 }

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
 def test_default_opts(lib):
     from paper_2011_08802_amd import mvpf
     o = mvpf.default_opts()
-    assert o.precision == mvpf.FP64 and o.rtol == 1e-8 and o.restart == 30 and o.omega == 0.5
+    assert o.precision == mvpf.FP64 and o.rtol == 1e-8 and o.restart == 30 and o.omega == 0.55
     assert o.nu_pre == 2 and o.nu_post == 2 and o.newton_max == 12
 
 
