@@ -181,3 +181,51 @@ def test_penalty_kink_has_zero_curvature_at_zero():
     f = lambda t: 0.5 * (E.neg_part(t) ** 2).sum()
     Hd = torch.diagonal(hessian(f)(x)).numpy()
     assert list(Hd) == [0.0, 1.0, 0.0]
+
+
+def _scalar_pade(order, c):
+    """Scalar forms of the Pade approximants of 1/2 ln c (Eqs. pade11, pade22,
+    pade33 evaluated on c I)."""
+    if order == 11:
+        return (c - 1.0) / (c + 1.0)
+    if order == 22:
+        return 1.5 * (c * c - 1.0) / (c * c + 4.0 * c + 1.0)
+    return (11 * c ** 3 + 27 * c * c - 27 * c - 11) / (6.0 * (c ** 3 + 9 * c * c + 9 * c + 1))
+
+
+@pytest.mark.parametrize("order", [11, 22, 33])
+def test_elastic_prefactor_and_stiffness_mixing(order):
+    """Eq. elasticEn with the mixed stiffness L(eta) = sum eta_i L_i.  Along
+    F = lam F^t(eta) the elastic stretch is lam I, so C^e = lam^2 I, H^e = r I
+    with r the scalar approximant at lam^2, and
+        psi_el = 1/2 det(F^t) r^2 sum_i eta_i (I : L_i : I).
+    I : L : I is 3 c11 + 6 c12 = 1182 GPa for the cubic austenite and
+    c11 + c22 + c33 + 2 (c12 + c13 + c23) = 1104 GPa for every martensite
+    variant (Table 1; invariant under rotation).  On the edge between the
+    austenite and variant k, F^t = I + t (U_k - I) has the eigenvalues
+    1 + t (s - 1), s in {alpha, beta, gamma}, so det F^t is their product.
+    Dropping det F^t, taking det F instead, or freezing L at L_0 all fail."""
+    mp = synth.config_material(pade=order)
+    tc = E.TorchCard(Card(mp))
+    a, b, g = mp.alpha, mp.beta, mp.gamma
+    lam = 1.03
+    r = _scalar_pade(order, lam * lam)
+    for k in (1, 4, 6):
+        for t in (0.0, 0.37, 1.0):
+            eh = torch.zeros(6, dtype=DT)
+            eh[k - 1] = t
+            eta = E.full_eta(eh)
+            Jt = np.prod([1.0 + t * (s - 1.0) for s in (a, b, g)])
+            F = lam * E.transformation_gradient(eta, tc)
+            got = float(E.elastic_energy(F, eta, tc))
+            want = 0.5 * Jt * r * r * ((1.0 - t) * 1182.0 + t * 1104.0)
+            assert abs(got - want) <= 1e-12 * abs(want), (k, t, got, want)
+    # an interior point of the simplex: two variants and the austenite
+    eh = torch.zeros(6, dtype=DT)
+    eh[1], eh[4] = 0.3, 0.25
+    eta = E.full_eta(eh)
+    Ft = E.transformation_gradient(eta, tc)
+    Jt = float(np.prod(np.linalg.eigvalsh(Ft.numpy())))
+    got = float(E.elastic_energy(lam * Ft, eta, tc))
+    want = 0.5 * Jt * r * r * (0.45 * 1182.0 + 0.55 * 1104.0)
+    assert abs(got - want) <= 1e-12 * abs(want)

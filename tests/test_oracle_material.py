@@ -103,3 +103,45 @@ def test_splitmix64_published_sequence():
     e = synth.initial_eta(synth.BASE_SEED, 1000)
     assert e.shape == (1000, 6) and e.min() >= 0.0 and e.max() < 0.05
     assert abs(e.mean() - 0.025) < 0.002
+
+
+def test_variant_stiffness_axes_in_sample_frame():
+    """Reading of Table 1: variant k's orthorhombic axes 1, 2, 3 are the
+    eigenvectors of its stretch tensor for alpha, beta, gamma.  In the sample
+    frame (with [011] along z) the normal stiffness along each axis n,
+    (n n) : L_k : (n n), is c11 = 189, c22 = 141, c33 = 205 GPa, the mixed
+    normal terms are c12, c13, c23, and the shear stiffness of each axis pair
+    (sym(a b) : L_k : sym(b a) with sym(a b) = (a b + b a)/2) is c66 (alpha-beta),
+    c55 (alpha-gamma), c44 (beta-gamma).  The axes come from the eigenvectors
+    of the sample-frame U_k, so a transposed rotation of the stiffness fails."""
+    mp = synth.config_material()
+    card = M.Card(mp)
+    c11, c22, c33, c44, c55, c66, c12, c13, c23 = mp.ortho
+    for k in range(1, 7):
+        w, v = np.linalg.eigh(card.U[k])
+        axis = {s: v[:, int(np.argmin(np.abs(w - s)))] for s in (mp.alpha, mp.beta, mp.gamma)}
+        na, nb, ng = axis[mp.alpha], axis[mp.beta], axis[mp.gamma]
+        L = card.L[k]
+
+        def q(A, B):
+            return float(np.einsum("ij,ijkl,kl->", A, L, B))
+
+        def nn(n):
+            return np.outer(n, n)
+
+        def sym(x, y):
+            return 0.5 * (np.outer(x, y) + np.outer(y, x))
+
+        assert np.isclose(q(nn(na), nn(na)), c11, rtol=1e-12)
+        assert np.isclose(q(nn(nb), nn(nb)), c22, rtol=1e-12)
+        assert np.isclose(q(nn(ng), nn(ng)), c33, rtol=1e-12)
+        assert np.isclose(q(nn(na), nn(nb)), c12, rtol=1e-12)
+        assert np.isclose(q(nn(na), nn(ng)), c13, rtol=1e-12)
+        assert np.isclose(q(nn(nb), nn(ng)), c23, rtol=1e-12)
+        assert np.isclose(q(sym(na, nb), sym(na, nb)), c66, rtol=1e-12)
+        assert np.isclose(q(sym(na, ng), sym(na, ng)), c55, rtol=1e-12)
+        assert np.isclose(q(sym(nb, ng), sym(nb, ng)), c44, rtol=1e-12)
+    # the austenite keeps its cubic constants along the crystal axes
+    Qm = np.asarray(mp.Q).reshape(3, 3)
+    e1 = Qm @ np.array([1.0, 0.0, 0.0])
+    assert np.isclose(np.einsum("i,j,ijkl,k,l->", e1, e1, card.L[0], e1, e1), mp.cubic[0], rtol=1e-12)

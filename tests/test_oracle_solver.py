@@ -145,3 +145,58 @@ def test_newton_converges_quadratically():
     ratios = [r[k + 1] / r[k] ** 2 for k in range(len(r) - 1) if r[k] < 1e-2 and r[k + 1] > 1e-12]
     assert ratios and max(ratios) < 1e2
     assert np.allclose(U1.reshape(-1, NDOF)[mask], (U.reshape(-1, NDOF) + g)[mask])
+
+
+def _block_system(n=6, bs=9, coupled=True, seed=3):
+    """Random operator with well-conditioned dense bs x bs diagonal blocks and
+    (optionally) off-diagonal blocks coupling neighbouring nodes."""
+    rng = np.random.default_rng(seed)
+    A = np.zeros((n * bs, n * bs))
+    for a in range(n):
+        blk = rng.standard_normal((bs, bs)) + bs * np.eye(bs)
+        A[a * bs:(a + 1) * bs, a * bs:(a + 1) * bs] = blk
+        if coupled and a + 1 < n:
+            off = 0.3 * rng.standard_normal((bs, bs))
+            A[a * bs:(a + 1) * bs, (a + 1) * bs:(a + 2) * bs] = off
+            A[(a + 1) * bs:(a + 2) * bs, a * bs:(a + 1) * bs] = off.T
+    return A, rng.standard_normal(n * bs)
+
+
+def _one_level_mg(A, bs, omega):
+    lev = S.Level(mesh=None, mask=np.zeros((A.shape[0] // bs, bs), dtype=bool), A=sp.csr_matrix(A))
+    last = S.Level(mesh=None, mask=np.zeros((1, bs), dtype=bool), A=sp.identity(bs, format="csr"))
+    return S.Multigrid.from_levels([lev, last], bs, S.MGOptions(omega=omega)), lev
+
+
+def test_point_block_inverse_and_first_sweep():
+    """Point-block Jacobi (Sec. 3.4): the smoother inverts the whole 9x9 block
+    of each node.  block_diagonal_inverse(A)[n] A_nn = I for the dense
+    diagonal blocks, and one damped sweep from x = 0 gives
+    x = omega A_nn^-1 b_n on every node whatever the off-diagonal blocks are.
+    A scalar (pointwise) Jacobi, a wrong block size, a wrong sign or a missing
+    damping factor all fail."""
+    bs, omega = 9, 0.55
+    A, b = _block_system(bs=bs)
+    n = A.shape[0] // bs
+    Dinv = S.block_diagonal_inverse(sp.csr_matrix(A), bs)
+    for a in range(n):
+        Ann = A[a * bs:(a + 1) * bs, a * bs:(a + 1) * bs]
+        assert np.allclose(Dinv[a] @ Ann, np.eye(bs), atol=1e-13)
+    mg, lev = _one_level_mg(A, bs, omega)
+    x = mg.smooth(lev, np.zeros_like(b), b, 1)
+    for a in range(n):
+        Ann = A[a * bs:(a + 1) * bs, a * bs:(a + 1) * bs]
+        assert np.allclose(Ann @ x[a * bs:(a + 1) * bs], omega * b[a * bs:(a + 1) * bs], atol=1e-12)
+
+
+def test_point_block_jacobi_exact_on_block_diagonal():
+    """On a block-diagonal operator each node's error is multiplied by
+    (1 - omega) per sweep, so k sweeps from zero give
+    x_k = (1 - (1 - omega)^k) A^-1 b."""
+    bs, omega = 9, 0.55
+    A, b = _block_system(coupled=False, seed=5)
+    mg, lev = _one_level_mg(A, bs, omega)
+    xs = np.linalg.solve(A, b)
+    for k in (1, 2, 3):
+        x = mg.smooth(lev, np.zeros_like(b), b, k)
+        assert np.allclose(x, (1.0 - (1.0 - omega) ** k) * xs, rtol=1e-12, atol=1e-13)
