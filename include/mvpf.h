@@ -236,9 +236,13 @@ int mvpf_newton_update(mvpf_problem* p);
 
 /* One implicit time step to total depth `depth` (Sec. 3.4): Newton
  * iterations (newton_system, solve, update) until the free-dof residual is
- * <= newton_rtol * ||b_0||; if not within newton_max iterations, the state is
- * restored and the depth increment halved (at most 8 times).  On success
- * eta_hat_n <- eta_hat and the depth is advanced. */
+ * <= newton_rtol * ||b_0||; if not within newton_max iterations, or if a 9x9
+ * diagonal block or the coarsest operator is singular, or the residual is not
+ * finite, the attempt fails: the state and depth are restored to their values
+ * before the attempt and the depth increment is halved (at most 8 times, then
+ * MVPF_ENOTCONV).  Any error returned (negative) also leaves the state and
+ * depth as they were before the failing attempt.  On success eta_hat_n <-
+ * eta_hat and the depth is advanced. */
 int mvpf_time_step(mvpf_problem* p, double depth, mvpf_step_stats* stats);
 
 /* Indentation load of the sphere-contact loading at the current state and

@@ -2202,13 +2202,61 @@ struct EventPair {
   }
 };
 
-// One implicit step to indenter depth `trial` from the current state
-// (Sec. 3.4): Newton iterations (system, solve, update) until the free-dof
-// residual is <= newton_rtol ||b_0|| (b_0 = the first right-hand side),
-// checked before each of at most newton_max solves and after the last.  A
-// non-finite residual ends the attempt.  On success eta_hat_n <- eta_hat and
-// the depth becomes `trial`; otherwise the state is restored.  Timings and
-// iteration counts accumulate into st; *its = this attempt's solves.
+// Newton iterations of one implicit step to indenter depth `trial` from the
+// current state (Sec. 3.4): system, solve, update until the free-dof residual
+// is <= newton_rtol ||b_0|| (b_0 = the first right-hand side), checked before
+// each of at most newton_max solves and after the last.  A non-finite
+// residual or a singular 9x9 block / coarse operator ends the iterations
+// without success (*ok false, return 0); other errors are returned.  Timings
+// and iteration counts accumulate into st; *its = the solves made.
+int newton_iterate(mvpf_problem* p, double trial, mvpf_step_stats* st, int* its, bool* ok, EventPair& ev) {
+  Level& L0 = p->lev[0];
+  double b0 = 0.0;
+  for (int it = 0; it <= p->opts.newton_max; ++it) {
+    double rfree = 0.0;
+    TRY(compute_residual(p, trial, &rfree));
+    st->residual = rfree;
+    if (!std::isfinite(rfree)) return 0;
+    if (it > 0 && rfree <= p->opts.newton_rtol * b0) {
+      *ok = true;
+      return 0;
+    }
+    if (it == p->opts.newton_max) return 0;
+    (void)hipEventRecord(ev.a, p->stream);
+    TRY(build_system(p, trial));
+    (void)hipEventRecord(ev.b, p->stream);
+    (void)hipEventSynchronize(ev.b);
+    st->assemble_ms += elapsed_ms(ev.a, ev.b);
+    (void)hipEventRecord(ev.a, p->stream);
+    const int srs = setup_solver(p);
+    (void)hipEventRecord(ev.b, p->stream);
+    (void)hipEventSynchronize(ev.b);
+    st->setup_ms += elapsed_ms(ev.a, ev.b);
+    if (srs == MVPF_ESINGULAR) return 0;  // a failed attempt: the caller halves the increment
+    TRY(srs);
+    p->sys_depth = trial;
+    p->have_system = true;
+    if (it == 0) {
+      TRY(norm_device(p, nvec(L0.g), p->rhs, &b0));
+      st->residual0 = b0;
+    }
+    mvpf_solve_stats ss;
+    TRY(solve_internal(p, p->rhs, p->dx, &ss));
+    st->linear_iterations += ss.iterations;
+    st->solve_ms += ss.solve_ms;
+    st->newton_iterations++;
+    (*its)++;
+    p->have_solution = true;
+    TRY(mvpf_newton_update(p));
+  }
+  return 0;
+}
+
+// One implicit step to indenter depth `trial` (newton_iterate).  On success
+// eta_hat_n <- eta_hat and the depth becomes `trial`.  On every other exit --
+// no convergence, a singular block, or an error returned by any call after
+// the state was saved -- the state and the depth are restored to their
+// values at entry before returning.
 int newton_attempt(mvpf_problem* p, double trial, mvpf_step_stats* st, int* its, bool* ok) {
   Level& L0 = p->lev[0];
   const size_t sbytes = sizeof(double) * NSTATE * L0.g.Npad;
@@ -2217,53 +2265,31 @@ int newton_attempt(mvpf_problem* p, double trial, mvpf_step_stats* st, int* its,
   *its = 0;
   const double depth0 = p->depth;  // the updates move it with the state
   HIPCHK(hipMemcpyAsync(p->save_state, L0.state, sbytes, hipMemcpyDeviceToDevice, p->stream));
-  double b0 = 0.0;
-  for (int it = 0; it <= p->opts.newton_max; ++it) {
-    double rfree = 0.0;
-    TRY(compute_residual(p, trial, &rfree));
-    st->residual = rfree;
-    if (!std::isfinite(rfree)) break;
-    if (it > 0 && rfree <= p->opts.newton_rtol * b0) {
-      *ok = true;
-      break;
-    }
-    if (it == p->opts.newton_max) break;
-    (void)hipEventRecord(ev.a, p->stream);
-    TRY(build_system(p, trial));
-    (void)hipEventRecord(ev.b, p->stream);
-    (void)hipEventSynchronize(ev.b);
-    st->assemble_ms += elapsed_ms(ev.a, ev.b);
-    (void)hipEventRecord(ev.a, p->stream);
-    TRY(setup_solver(p));
-    (void)hipEventRecord(ev.b, p->stream);
-    (void)hipEventSynchronize(ev.b);
-    st->setup_ms += elapsed_ms(ev.a, ev.b);
-    p->sys_depth = trial;
-    p->have_system = true;
-    if (it == 0) {
-      TRY(norm_device(p, nvec(L0.g), p->rhs, &b0));
-      st->residual0 = b0;
-    }
-    mvpf_solve_stats ss;
-    const int src = solve_internal(p, p->rhs, p->dx, &ss);
-    if (src < 0) return src;
-    st->linear_iterations += ss.iterations;
-    st->solve_ms += ss.solve_ms;
-    st->newton_iterations++;
-    (*its)++;
-    p->have_solution = true;
-    TRY(mvpf_newton_update(p));
-  }
-  if (*ok) {
+  const int rc = newton_iterate(p, trial, st, its, ok, ev);
+  if (rc == 0 && *ok) {
     HIPCHK(hipMemcpyAsync(L0.state + (int64_t)9 * L0.g.Npad, L0.state + (int64_t)3 * L0.g.Npad,
                           sizeof(double) * 6 * L0.g.Npad, hipMemcpyDeviceToDevice, p->stream));
     p->depth = trial;
   } else {
-    HIPCHK(hipMemcpyAsync(L0.state, p->save_state, sbytes, hipMemcpyDeviceToDevice, p->stream));
+    *ok = false;
+    if (p->coarse_pending) {  // an error between the coarse inversion's fork and its join
+      (void)hipStreamWaitEvent(p->stream, p->ev_join, 0);
+      p->coarse_pending = false;
+    }
+    const hipError_t e = hipMemcpyAsync(L0.state, p->save_state, sbytes, hipMemcpyDeviceToDevice, p->stream);
     p->depth = depth0;
+    if (rc == 0 && e != hipSuccess) {
+      p->err = std::string("state restore failed: ") + hipGetErrorString(e);
+      return MVPF_EDEVICE;
+    }
   }
-  HIPCHK(hipStreamSynchronize(p->stream));
+  const hipError_t es = hipStreamSynchronize(p->stream);
   p->have_system = p->have_solution = false;
+  if (rc != 0) return rc;
+  if (es != hipSuccess) {
+    p->err = std::string("hipStreamSynchronize failed: ") + hipGetErrorString(es);
+    return MVPF_EDEVICE;
+  }
   return 0;
 }
 

@@ -62,3 +62,38 @@ def rel_blocks(a, b):
     a = np.asarray(a).reshape(-1, NDOF)
     b = np.asarray(b).reshape(-1, NDOF)
     return rel(a[:, :3], b[:, :3]), rel(a[:, 3:], b[:, 3:])
+
+
+def entry_errors(a, b, scale=None):
+    """Per-entry error ratios |a_i - b_i| / (|b_i| + s_i (+ c_i)), where s_i is
+    the largest |b| among the 9 unknowns of entry i's node and c (optional)
+    an extra per-entry rounding scale, e.g. (|A| |x|)_i for a product A x."""
+    a = np.asarray(a, dtype=float).ravel()
+    b = np.asarray(b, dtype=float).ravel()
+    s = np.repeat(np.abs(b).reshape(-1, NDOF).max(axis=1), NDOF)
+    den = np.abs(b) + s
+    if scale is not None:
+        den = den + np.abs(np.asarray(scale, dtype=float).ravel())
+    return np.abs(a - b) / np.maximum(den, 1e-300)
+
+
+def check_entries(a, b, tol, what, scale=None):
+    """Element-wise parity gate (see entry_errors): every entry within tol of
+    the oracle's, relative to its node's scale.  On failure the worst entry
+    (node, unknown, both values) is reported; the norm-wise relative errors of
+    the displacement and order-parameter parts are printed as diagnostics."""
+    e = entry_errors(a, b, scale)
+    i = int(np.argmax(e))
+    a = np.asarray(a, dtype=float).ravel()
+    b = np.asarray(b, dtype=float).ravel()
+    ru, re = rel_blocks(a, b)
+    say(f"    {what}: worst entry ratio {e[i]:.2e} (node {i // NDOF}, unknown {i % NDOF}); "
+        f"norm-wise u {ru:.2e}, eta {re:.2e}")
+    assert e[i] <= tol, (f"{what}: entry {i} (node {i // NDOF}, unknown {i % NDOF}) "
+                         f"gpu {a[i]!r} oracle {b[i]!r}, ratio {e[i]:.3e} > {tol:g}")
+    return float(e[i])
+
+
+def abs_product(A, x):
+    """(|A| |x|): the per-entry rounding scale of the product A x."""
+    return abs(A) @ np.abs(np.asarray(x, dtype=float).ravel())

@@ -6,8 +6,10 @@ nodes' rows of the residual, the right-hand side and the eliminated
 tangent exactly.
 
 Samples: the 8 corners, edge and face midpoints, nodes of the loaded top
-region, and 40 seeded random nodes.  Tolerances: FP64 rows <= 1e-12 relative
-to the sample's norm, FP32 operator rows <= 2e-6; the solve's true FP64
+region, and 40 seeded random nodes.  Tolerances, entry by entry relative to
+the entry's node scale (the largest oracle value among its 9 unknowns, plus
+(|A||x|) for operator products): FP64 rows <= 1e-12, FP32 operator rows
+<= 2e-6; the solve's true FP64
 relative residual (evaluated by the GPU's FP64 operator, whose rows are the
 checked ones) <= 1e-8, the accuracy the solver is run at."""
 import numpy as np
@@ -16,7 +18,7 @@ import scipy.sparse as sp
 import torch
 
 import synth
-from gpu_util import say
+from gpu_util import check_entries, say
 from oracle import solver as S
 from oracle.contact import SphereContact
 from oracle.fem import Discretisation, Mesh, NDOF
@@ -42,10 +44,21 @@ def sample_nodes(m, top_centre_radius, seed=17):
 
 
 class LocalRows:
-    """Oracle rows of the sampled nodes from the elements around them."""
+    """Oracle rows of the sampled nodes from the elements around them.  On a
+    coarser level (level > 0) the state is the injection of the finest state
+    and a dof is constrained iff its coincident finest dof is (the multigrid
+    hierarchy's rediscretisation); only the operator rows are formed there."""
 
-    def __init__(self, p, U, En, depth, nodes):
-        m = Mesh.from_problem(p)
+    def __init__(self, p, U, En, depth, nodes, level=0):
+        m0 = Mesh.from_problem(p)
+        mask0, target = S.dirichlet(m0, p.kind, p.patch, p.radius, depth=depth)
+        g0 = S.increment(mask0, target, U)
+        m = Mesh.from_problem(p, level)
+        if level:
+            f = 2 ** level
+            I, J, K = m.node_ijk(np.arange(m.n_nodes))
+            fid = m0.node_id(f * I, f * J, f * K)
+            U, En, mask0, g0 = U[fid], En[fid], mask0[fid], np.zeros_like(g0[fid])
         self.m, self.nodes = m, nodes
         disc = Discretisation(m, Card(p.material))
         elems = m.elements_of_nodes(nodes)
@@ -58,8 +71,8 @@ class LocalRows:
             rc, cc, vc = sc.tangent_coo(U.ravel(), depth)
             r, c, v = np.concatenate([r, rc]), np.concatenate([c, cc]), np.concatenate([v, vc])
         self.K = sp.coo_matrix((v, (r, c)), shape=(n, n)).tocsr()
-        self.mask, target = S.dirichlet(m, p.kind, p.patch, p.radius, depth=depth)
-        self.g = S.increment(self.mask, target, U).ravel()
+        self.mask = mask0
+        self.g = g0.ravel()
         self.dofs = (nodes[:, None] * NDOF + np.arange(NDOF)).ravel()
 
     def rhs(self):
@@ -70,11 +83,15 @@ class LocalRows:
         b[con] = gv[self.dofs][con]
         return b
 
-    def apply(self, x):
+    def apply(self, x, absolute=False):
+        """Sampled rows of the eliminated operator times x; with absolute,
+        (|A| |x|) on those rows (the rounding scale of the product)."""
         m = self.mask.ravel()
-        y = self.K[self.dofs] @ np.where(m, 0.0, x)
+        K = abs(self.K) if absolute else self.K
+        xf = np.where(m, 0.0, x)
+        y = K[self.dofs] @ (np.abs(xf) if absolute else xf)
         con = m[self.dofs]
-        y[con] = x[self.dofs][con]
+        y[con] = (np.abs(x) if absolute else x)[self.dofs][con]
         return y
 
 
@@ -82,7 +99,12 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def _check(p, depth, radius_nodes, tag):
+def _check(p, depth, radius_nodes, tag, precision="mixed", coarse_levels=False):
+    """Sampled rows of the residual, the right-hand side and the finest
+    operator (FP64 copy; in mixed mode also the FP32 copy), each entry against
+    the oracle's (element-wise, relative to its node's scale); with
+    coarse_levels the sampled rows of every coarser level's operator too; then
+    the solve's true FP64 residual."""
     from paper_2011_08802_amd import mvpf
     m = Mesh.from_problem(p)
     U = np.zeros((m.n_nodes, NDOF))
@@ -90,21 +112,33 @@ def _check(p, depth, radius_nodes, tag):
     nodes = sample_nodes(m, radius_nodes)
     say(f"[{tag}] oracle rows of {len(nodes)} sampled nodes")
     lr = LocalRows(p, U, U[:, 3:], depth, nodes)
-    say(f"[{tag}] GPU system {p.nx}x{p.ny}x{p.nz}")
-    gp = mvpf.Problem(p, "mixed", rtol=1e-8)
+    coarse = []
+    if coarse_levels:
+        for l in range(1, p.n_levels):
+            cm = Mesh.from_problem(p, l)
+            cn = sample_nodes(cm, max(1, radius_nodes >> l), seed=17 + l)
+            say(f"[{tag}] oracle rows of {len(cn)} sampled nodes on level {l}")
+            coarse.append((l, LocalRows(p, U, U[:, 3:], depth, cn, level=l)))
+    say(f"[{tag}] GPU system {p.nx}x{p.ny}x{p.nz} {precision}")
+    gp = mvpf.Problem(p, precision, rtol=1e-8)
     assert gp.get_tuning("matrix_free") == 1
     gp.init_random(p.seed)
     gp.newton_system(depth)
     gp.autotune()
     R, _ = gp.residual()
-    assert _rel(R.cpu().numpy()[lr.dofs], lr.R[lr.dofs]) < 1e-12
-    assert _rel(gp.get_rhs().cpu().numpy()[lr.dofs], lr.rhs()) < 1e-12
+    check_entries(R.cpu().numpy()[lr.dofs], lr.R[lr.dofs], 1e-12, "residual")
+    check_entries(gp.get_rhs().cpu().numpy()[lr.dofs], lr.rhs(), 1e-12, "rhs")
     rng = np.random.default_rng(5)
     x = rng.standard_normal(m.n_nodes * NDOF)
     xd = torch.as_tensor(x).cuda()
-    yo = lr.apply(x)
-    assert _rel(gp.jacobian_apply(0, xd, mvpf.FP64).cpu().numpy()[lr.dofs], yo) < 1e-12
-    assert _rel(gp.jacobian_apply(0, xd, mvpf.MIXED).cpu().numpy()[lr.dofs], yo) < 2e-6
+    yo, ya = lr.apply(x), lr.apply(x, absolute=True)
+    check_entries(gp.jacobian_apply(0, xd, mvpf.FP64).cpu().numpy()[lr.dofs], yo, 1e-12, "FP64 K x", ya)
+    if precision == "mixed":
+        check_entries(gp.jacobian_apply(0, xd, mvpf.MIXED).cpu().numpy()[lr.dofs], yo, 2e-6, "FP32 K x", ya)
+    for l, cr in coarse:
+        xc = rng.standard_normal(cr.m.n_nodes * NDOF)
+        yc = gp.jacobian_apply(l, torch.as_tensor(xc).cuda(), mvpf.FP64).cpu().numpy()[cr.dofs]
+        check_entries(yc, cr.apply(xc), 1e-12, f"FP64 K x level {l}", cr.apply(xc, absolute=True))
     say(f"[{tag}] solve")
     dx, st = gp.solve()
     b = gp.get_rhs()
@@ -112,12 +146,22 @@ def _check(p, depth, radius_nodes, tag):
     gp.close()
     assert st.converged and st.rel_residual <= 1e-8
     assert float(torch.linalg.norm(r) / torch.linalg.norm(b)) <= 1.0001e-8
+    return st
 
 
 def test_fullsize_patch_64():
     """The 64^3 patch workload (2,471,625 dof, 5 levels)."""
     p = synth.medium()
     _check(p, p.depth_increment, p.patch // 2 + 1, "64^3")
+
+
+def test_fullsize_patch_64_fp64():
+    """The 64^3 patch workload in the plain FP64 method (every multigrid level
+    and the smoother in FP64): sampled rows of the residual, the right-hand
+    side and the operator on all 5 levels (the coarser ones assembled at the
+    injected state), and the solve's true FP64 residual."""
+    p = synth.medium()
+    _check(p, p.depth_increment, p.patch // 2 + 1, "64^3 fp64", precision="fp64", coarse_levels=True)
 
 
 def test_fullsize_patch_128():
@@ -165,14 +209,14 @@ def test_fullsize_batched():
     for i, (U, lr) in enumerate(rows):
         gp = B.problem(i)
         R, _ = gp.residual()
-        assert _rel(R.cpu().numpy()[lr.dofs], lr.R[lr.dofs]) < 1e-12, i
+        check_entries(R.cpu().numpy()[lr.dofs], lr.R[lr.dofs], 1e-12, f"problem {i} residual")
         b = gp.get_rhs()
-        assert _rel(b.cpu().numpy()[lr.dofs], lr.rhs()) < 1e-12, i
+        check_entries(b.cpu().numpy()[lr.dofs], lr.rhs(), 1e-12, f"problem {i} rhs")
         x = rng.standard_normal(U.size)
         xd = torch.as_tensor(x).cuda()
-        yo = lr.apply(x)
-        assert _rel(gp.jacobian_apply(0, xd, mvpf.FP64).cpu().numpy()[lr.dofs], yo) < 1e-12, i
-        assert _rel(gp.jacobian_apply(0, xd, mvpf.MIXED).cpu().numpy()[lr.dofs], yo) < 2e-6, i
+        yo, ya = lr.apply(x), lr.apply(x, absolute=True)
+        check_entries(gp.jacobian_apply(0, xd, mvpf.FP64).cpu().numpy()[lr.dofs], yo, 1e-12, f"problem {i} FP64 K x", ya)
+        check_entries(gp.jacobian_apply(0, xd, mvpf.MIXED).cpu().numpy()[lr.dofs], yo, 2e-6, f"problem {i} FP32 K x", ya)
         bs.append(b)
     say("[batch] lockstep solve")
     stats = B.solve()

@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import synth
-from gpu_util import OracleCase, gpu_problem, rel, rel_blocks, say, seeded_state
+from gpu_util import OracleCase, abs_product, check_entries, gpu_problem, rel, say, seeded_state
 
 pytestmark = pytest.mark.gpu
 
@@ -52,12 +52,11 @@ def test_mf_fp64_operator_vcycle_solve(mf_case):
     gp = _mf_problem(p, U, En, d, "fp64", rtol=1e-12)
     rng = np.random.default_rng(21)
     x = rng.standard_normal(oc.sys.b.shape[0])
-    yu, ye = rel_blocks(gp.jacobian_apply(0, _dev(x), mvpf.FP64).cpu().numpy(), oc.sys.A @ x)
-    assert yu < 1e-12 and ye < 1e-12, (yu, ye)
+    check_entries(gp.jacobian_apply(0, _dev(x), mvpf.FP64).cpu().numpy(), oc.sys.A @ x, 1e-12, "FP64 K x",
+                  abs_product(oc.sys.A, x))
     v = rng.standard_normal(oc.sys.b.shape[0])
     assert rel(gp.precondition(_dev(v)).cpu().numpy(), oc.mg.precondition(v)) < 1e-10
-    bu, be = rel_blocks(gp.get_rhs().cpu().numpy(), oc.sys.b)
-    assert bu < 1e-12 and be < 1e-12, (bu, be)
+    check_entries(gp.get_rhs().cpu().numpy(), oc.sys.b, 1e-12, "rhs")
     dx, st = gp.solve()
     gp.close()
     assert st.converged and st.rel_residual <= 1e-12
@@ -71,9 +70,9 @@ def test_mf_mixed_operator_and_solve(mf_case):
     gp = _mf_problem(p, U, En, d, "mixed", rtol=1e-12)
     rng = np.random.default_rng(22)
     x = rng.standard_normal(oc.sys.b.shape[0])
-    yu, ye = rel_blocks(gp.jacobian_apply(0, _dev(x), mvpf.MIXED).cpu().numpy(), oc.sys.A @ x)
-    assert yu < 2e-6 and ye < 2e-6, (yu, ye)
-    assert rel(gp.jacobian_apply(0, _dev(x), mvpf.FP64).cpu().numpy(), oc.sys.A @ x) < 1e-12
+    ax = abs_product(oc.sys.A, x)
+    check_entries(gp.jacobian_apply(0, _dev(x), mvpf.MIXED).cpu().numpy(), oc.sys.A @ x, 2e-6, "FP32 K x", ax)
+    check_entries(gp.jacobian_apply(0, _dev(x), mvpf.FP64).cpu().numpy(), oc.sys.A @ x, 1e-12, "FP64 K x", ax)
     dx, st = gp.solve()
     gp.close()
     assert st.converged and st.rel_residual <= 1e-12

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import synth
-from gpu_util import OracleCase, gpu_problem, rel, rel_blocks, say, seeded_state
+from gpu_util import OracleCase, abs_product, check_entries, gpu_problem, rel, rel_blocks, say, seeded_state
 from oracle import solver as S
 from oracle.fem import Discretisation, Mesh, NDOF
 from oracle.material import Card
@@ -66,8 +66,7 @@ def test_residual_parity(case):
     say(f"[{name}] residual")
     R, nf = gp.residual()
     Ro = oc.sys.R
-    ru, re = rel_blocks(R.cpu().numpy(), Ro)
-    assert ru < 1e-12 and re < 1e-12, (ru, re)
+    check_entries(R.cpu().numpy(), Ro, 1e-12, "residual")
     free = ~oc.mask.ravel()
     assert abs(nf - np.linalg.norm(Ro[free])) <= 1e-12 * np.linalg.norm(Ro[free])
 
@@ -76,8 +75,7 @@ def test_rhs_parity(case):
     name, p, U, En, oc, gp = case
     say(f"[{name}] rhs")
     b = gp.get_rhs().cpu().numpy()
-    bu, be = rel_blocks(b, oc.sys.b)
-    assert bu < 1e-12 and be < 1e-12, (bu, be)
+    check_entries(b, oc.sys.b, 1e-12, "rhs")
 
 
 def test_operator_parity_all_levels(case):
@@ -87,9 +85,7 @@ def test_operator_parity_all_levels(case):
         say(f"[{name}] K x level {l}")
         x = rng.standard_normal(lev.A.shape[0])
         y = gp.jacobian_apply(l, _dev(x)).cpu().numpy()
-        yo = lev.A @ x
-        yu, ye = rel_blocks(y, yo)
-        assert yu < 1e-12 and ye < 1e-12, (l, yu, ye)
+        check_entries(y, lev.A @ x, 1e-12, f"K x level {l}", abs_product(lev.A, x))
 
 
 def test_preconditioner_parity_fp64(case):
@@ -136,12 +132,11 @@ def test_mixed_operators_fp32(case):
     for l, lev in enumerate(oc.mg.levels[:-1]):
         x = rng.standard_normal(lev.A.shape[0])
         y = gp.jacobian_apply(l, _dev(x), mvpf.MIXED).cpu().numpy()
-        yu, ye = rel_blocks(y, lev.A @ x)
-        assert yu < 2e-6 and ye < 2e-6, (l, yu, ye)
+        check_entries(y, lev.A @ x, 2e-6, f"FP32 K x level {l}", abs_product(lev.A, x))
     # the FP64 copy of the finest operator is exact
     x = rng.standard_normal(oc.sys.b.shape[0])
     y = gp.jacobian_apply(0, _dev(x), mvpf.FP64).cpu().numpy()
-    assert rel(y, oc.sys.A @ x) < 1e-12
+    check_entries(y, oc.sys.A @ x, 1e-12, "FP64 K x finest", abs_product(oc.sys.A, x))
     v = rng.standard_normal(oc.sys.b.shape[0])
     z = gp.precondition(_dev(v)).cpu().numpy()
     assert rel(z, oc.mg.precondition(v)) < 1e-4
@@ -241,10 +236,11 @@ def test_sixteen_cubed_coarse_1125():
         gp.set_tuning("small_grid_nodes", 0, small)
         gp.newton_system(p.depth_increment)
         b = gp.get_rhs().cpu().numpy()
-        assert max(rel_blocks(b, oc.sys.b)) < 1e-12
+        check_entries(b, oc.sys.b, 1e-12, "rhs")
         for l, lev in enumerate(oc.mg.levels):
             x = rng.standard_normal(lev.A.shape[0])
-            assert max(rel_blocks(gp.jacobian_apply(l, _dev(x)).cpu().numpy(), lev.A @ x)) < 1e-12
+            check_entries(gp.jacobian_apply(l, _dev(x)).cpu().numpy(), lev.A @ x, 1e-12, f"K x level {l}",
+                          abs_product(lev.A, x))
         z = gp.precondition(_dev(v)).cpu().numpy()
         assert rel(z, zo) < 1e-10, rel(z, zo)
         x, st = gp.solve()
@@ -289,7 +285,8 @@ def _coarse_case(p, levels, coarse_dof, tag):
     gp.newton_system(p.depth_increment)
     x = rng.standard_normal(coarse_dof)
     yc = gp.jacobian_apply(levels - 1, _dev(x)).cpu().numpy()
-    assert max(rel_blocks(yc, oc.mg.levels[-1].A @ x)) < 1e-12
+    Ac = oc.mg.levels[-1].A
+    check_entries(yc, Ac @ x, 1e-12, "coarse K x", abs_product(Ac, x))
     z = gp.precondition(_dev(v)).cpu().numpy()
     assert rel(z, zo) < 1e-10, rel(z, zo)
     xs, st = gp.solve()
@@ -356,6 +353,34 @@ def test_time_step_failure_restores_state():
     gp.close()
 
 
+def test_time_step_singular_setup_restores_state():
+    """A singular 9x9 diagonal block ends a Newton attempt like a failed one
+    (Sec. 3.4: the increment is halved), and the state is restored.  The
+    singular blocks are forced from the host by a material card with zero
+    stiffness: the displacement rows of every free node's diagonal block are
+    then exactly zero.  Every attempt fails at its first solver setup, the
+    increment is halved 8 times, the call reports non-convergence, and the
+    state and depth are bitwise those before the call."""
+    from dataclasses import replace
+    from paper_2011_08802_amd import mvpf
+    p = synth.tiny()
+    p = replace(p, material=replace(p.material, cubic=(0.0, 0.0, 0.0), ortho=(0.0,) * 9))
+    U, En = seeded_state(p, 1e-3)
+    say("[singular setup] zero-stiffness card, time step")
+    gp = gpu_problem(p, U, En, "mixed")
+    before = gp.get_state()
+    st = gp.time_step(p.depth_increment)
+    after = gp.get_state()
+    assert not st.converged and st.halvings == 9 and st.newton_iterations == 0
+    for a, b in zip(before[:3], after[:3]):
+        assert torch.equal(a, b)
+    assert after[3] == before[3] == 0.0
+    # the newton-system call itself reports the singular block
+    with pytest.raises(RuntimeError, match="singular"):
+        gp.newton_system(p.depth_increment)
+    gp.close()
+
+
 @pytest.mark.parametrize("order", [11, 22, 33])
 def test_pade_orders_match_oracle(order):
     """Hencky strain by the (1,1), (2,2) or (3,3) Pade approximant (Eqs.
@@ -378,13 +403,11 @@ def test_pade_orders_match_oracle(order):
     gp = gpu_problem(p, U, En, "fp64", rtol=1e-12)
     gp.newton_system(p.depth_increment)
     R, _ = gp.residual()
-    ru, re = rel_blocks(R.cpu().numpy(), oc.sys.R)
-    assert ru < 1e-12 and re < 1e-12, (ru, re)
-    bu, be = rel_blocks(gp.get_rhs().cpu().numpy(), oc.sys.b)
-    assert bu < 1e-12 and be < 1e-12, (bu, be)
+    check_entries(R.cpu().numpy(), oc.sys.R, 1e-12, "residual")
+    check_entries(gp.get_rhs().cpu().numpy(), oc.sys.b, 1e-12, "rhs")
     x = np.random.default_rng(5).standard_normal(oc.sys.A.shape[0])
-    yu, ye = rel_blocks(gp.jacobian_apply(0, _dev(x)).cpu().numpy(), oc.sys.A @ x)
-    assert yu < 1e-12 and ye < 1e-12, (yu, ye)
+    check_entries(gp.jacobian_apply(0, _dev(x)).cpu().numpy(), oc.sys.A @ x, 1e-12, "K x",
+                  abs_product(oc.sys.A, x))
     dx, st = gp.solve()
     gp.close()
     assert st.converged and st.rel_residual <= 1e-12
