@@ -28,6 +28,20 @@ def seeded_state(p, u_amp=0.0, seed=7):
     return U, U[:, 3:].copy()
 
 
+def residual_abs(disc, U, En, elems=None):
+    """Per-entry sum of the absolute element contributions to the residual,
+    sum_e |R_e| (the rounding scale of the assembled sum: a node's element
+    contributions cancel at equilibrium, so |R| alone understates it)."""
+    if elems is None:
+        elems = np.arange(disc.mesh.n_elem)
+    out = np.zeros(disc.mesh.n_nodes * NDOF)
+    for s in range(0, len(elems), 4096):
+        en, Re = disc.element_residuals(np.ravel(U), np.ravel(En), elems[s:s + 4096])
+        dofs = (en[:, :, None] * NDOF + np.arange(NDOF)).reshape(len(en), 8 * NDOF)
+        np.add.at(out, dofs.ravel(), np.abs(Re).ravel())
+    return out
+
+
 class OracleCase:
     """Oracle Newton system + multigrid for one problem/state/depth."""
 
@@ -42,6 +56,24 @@ class OracleCase:
         self.mg = S.Multigrid(p, self.card, U.ravel(), En.ravel(), self.mask, K_fine=self.sys.K,
                               depth=depth) if build_mg else None
         self.x = S.direct_solve(self.sys.A, self.sys.b) if direct else None
+        self.depth = depth
+        self._scales = None
+
+    def abs_scales(self):
+        """(R_abs, b_abs): per-entry rounding scales of the residual and the
+        right-hand side, sum_e |R_e| (+ |contact part|) and R_abs + |K| |g|
+        (|g| on constrained dofs, where b = g exactly)."""
+        if self._scales is None:
+            sy = self.sys
+            R_abs = residual_abs(sy.disc, self.U, self.En)
+            if sy.contact is not None:
+                R_abs = R_abs + np.abs(sy.contact.residual(self.U.ravel(), self.depth))
+            m = self.mask.ravel()
+            gv = np.where(m, self.g.ravel(), 0.0)
+            b_abs = R_abs + abs(sy.K) @ np.abs(gv)
+            b_abs[m] = np.abs(gv[m])
+            self._scales = (R_abs, b_abs)
+        return self._scales
 
 
 def gpu_problem(p, U, En, precision="fp64", depth=0.0, **opts):
@@ -67,7 +99,12 @@ def rel_blocks(a, b):
 def entry_errors(a, b, scale=None):
     """Per-entry error ratios |a_i - b_i| / (|b_i| + s_i (+ c_i)), where s_i is
     the largest |b| among the 9 unknowns of entry i's node and c (optional)
-    an extra per-entry rounding scale, e.g. (|A| |x|)_i for a product A x."""
+    the entry's rounding scale: the sum of the absolute values of the terms
+    that make it up, (|A| |x|)_i for a product A x, sum_e |R_e| for an
+    assembled residual.  A computed sum of terms t_k differs from the exact
+    one by at most (n eps) sum_k |t_k| (standard error analysis of summation,
+    e.g. Higham, Accuracy and Stability of Numerical Algorithms, Sec. 4.2), so
+    two correct evaluations in different orders agree to that scale."""
     a = np.asarray(a, dtype=float).ravel()
     b = np.asarray(b, dtype=float).ravel()
     s = np.repeat(np.abs(b).reshape(-1, NDOF).max(axis=1), NDOF)

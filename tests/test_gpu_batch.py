@@ -85,7 +85,7 @@ def test_batch_problem_matches_oracle():
     say("[batch oracle] oracle system + direct solve")
     oc = OracleCase(p, U, En, p.depth_increment, build_mg=False)
     b = B.problem(i).get_rhs().cpu().numpy()
-    check_entries(b, oc.sys.b, 1e-12, "rhs")
+    check_entries(b, oc.sys.b, 1e-12, "rhs", oc.abs_scales()[1])
     assert stats[i].converged and stats[i].rel_residual <= 1e-12
     B.newton_update()
     dx = _state(B.problem(i)) - U

@@ -54,8 +54,8 @@ def test_contact_residual_rhs_parity(contact_case):
     p, U, En, d, oc, gp = contact_case
     say("[contact] residual, rhs")
     R, nf = gp.residual()
-    check_entries(R.cpu().numpy(), oc.sys.R, 1e-12, "residual")
-    check_entries(gp.get_rhs().cpu().numpy(), oc.sys.b, 1e-12, "rhs")
+    check_entries(R.cpu().numpy(), oc.sys.R, 1e-12, "residual", oc.abs_scales()[0])
+    check_entries(gp.get_rhs().cpu().numpy(), oc.sys.b, 1e-12, "rhs", oc.abs_scales()[1])
 
 
 def test_contact_operator_parity_all_levels(contact_case):

@@ -7,9 +7,10 @@ tangent exactly.
 
 Samples: the 8 corners, edge and face midpoints, nodes of the loaded top
 region, and 40 seeded random nodes.  Tolerances, entry by entry relative to
-the entry's node scale (the largest oracle value among its 9 unknowns, plus
-(|A||x|) for operator products): FP64 rows <= 1e-12, FP32 operator rows
-<= 2e-6; the solve's true FP64
+the entry's node scale (the largest oracle value among its 9 unknowns) plus
+its rounding scale (the sum of the absolute values of the terms summed:
+(|A||x|) for operator products, sum_e |R_e| over the element contributions
+for the residual): FP64 rows <= 1e-12, FP32 operator rows <= 2e-6; the solve's true FP64
 relative residual (evaluated by the GPU's FP64 operator, whose rows are the
 checked ones) <= 1e-8, the accuracy the solver is run at."""
 import numpy as np
@@ -18,7 +19,7 @@ import scipy.sparse as sp
 import torch
 
 import synth
-from gpu_util import check_entries, say
+from gpu_util import check_entries, residual_abs, say
 from oracle import solver as S
 from oracle.contact import SphereContact
 from oracle.fem import Discretisation, Mesh, NDOF
@@ -71,16 +72,25 @@ class LocalRows:
             rc, cc, vc = sc.tangent_coo(U.ravel(), depth)
             r, c, v = np.concatenate([r, rc]), np.concatenate([c, cc]), np.concatenate([v, vc])
         self.K = sp.coo_matrix((v, (r, c)), shape=(n, n)).tocsr()
+        # rounding scale of the residual rows: sum of |element contributions|
+        self.R_abs = residual_abs(disc, U, En, elems)
+        if p.kind == "sphere":
+            self.R_abs = self.R_abs + np.abs(sc.residual(U.ravel(), depth))
         self.mask = mask0
         self.g = g0.ravel()
         self.dofs = (nodes[:, None] * NDOF + np.arange(NDOF)).ravel()
 
-    def rhs(self):
+    def rhs(self, absolute=False):
+        """Sampled rows of the right-hand side; with absolute, their rounding
+        scale sum_e |R_e| + |K| |g| (|g| on constrained dofs)."""
         m = self.mask.ravel()
         gv = np.where(m, self.g, 0.0)
-        b = -self.R[self.dofs] - self.K[self.dofs] @ gv
+        if absolute:
+            b = self.R_abs[self.dofs] + abs(self.K[self.dofs]) @ np.abs(gv)
+        else:
+            b = -self.R[self.dofs] - self.K[self.dofs] @ gv
         con = m[self.dofs]
-        b[con] = gv[self.dofs][con]
+        b[con] = (np.abs(gv) if absolute else gv)[self.dofs][con]
         return b
 
     def apply(self, x, absolute=False):
@@ -121,13 +131,21 @@ def _check(p, depth, radius_nodes, tag, precision="mixed", coarse_levels=False):
             coarse.append((l, LocalRows(p, U, U[:, 3:], depth, cn, level=l)))
     say(f"[{tag}] GPU system {p.nx}x{p.ny}x{p.nz} {precision}")
     gp = mvpf.Problem(p, precision, rtol=1e-8)
+    try:
+        return _check_gpu(gp, p, depth, tag, precision, lr, coarse, m)
+    finally:
+        gp.close()
+
+
+def _check_gpu(gp, p, depth, tag, precision, lr, coarse, m):
+    from paper_2011_08802_amd import mvpf
     assert gp.get_tuning("matrix_free") == 1
     gp.init_random(p.seed)
     gp.newton_system(depth)
     gp.autotune()
     R, _ = gp.residual()
-    check_entries(R.cpu().numpy()[lr.dofs], lr.R[lr.dofs], 1e-12, "residual")
-    check_entries(gp.get_rhs().cpu().numpy()[lr.dofs], lr.rhs(), 1e-12, "rhs")
+    check_entries(R.cpu().numpy()[lr.dofs], lr.R[lr.dofs], 1e-12, "residual", lr.R_abs[lr.dofs])
+    check_entries(gp.get_rhs().cpu().numpy()[lr.dofs], lr.rhs(), 1e-12, "rhs", lr.rhs(absolute=True))
     rng = np.random.default_rng(5)
     x = rng.standard_normal(m.n_nodes * NDOF)
     xd = torch.as_tensor(x).cuda()
@@ -143,7 +161,6 @@ def _check(p, depth, radius_nodes, tag, precision="mixed", coarse_levels=False):
     dx, st = gp.solve()
     b = gp.get_rhs()
     r = b - gp.jacobian_apply(0, dx, mvpf.FP64)
-    gp.close()
     assert st.converged and st.rel_residual <= 1e-8
     assert float(torch.linalg.norm(r) / torch.linalg.norm(b)) <= 1.0001e-8
     return st
@@ -197,6 +214,14 @@ def test_fullsize_batched():
         rows.append((U, LocalRows(p, U, U[:, 3:], p.depth_increment, sample_nodes(m, p.patch // 2 + 1, seed=17 + i))))
     say(f"[batch] GPU systems of {len(probs)} problems")
     B = mvpf.Batch(probs, "mixed", rtol=1e-8)
+    try:
+        _batched_gpu(B, probs, rows)
+    finally:
+        B.close()
+
+
+def _batched_gpu(B, probs, rows):
+    from paper_2011_08802_amd import mvpf
     for i, p in enumerate(probs):
         B.problem(i).init_random(p.seed)
     depths = [p.depth_increment for p in probs]
@@ -209,9 +234,9 @@ def test_fullsize_batched():
     for i, (U, lr) in enumerate(rows):
         gp = B.problem(i)
         R, _ = gp.residual()
-        check_entries(R.cpu().numpy()[lr.dofs], lr.R[lr.dofs], 1e-12, f"problem {i} residual")
+        check_entries(R.cpu().numpy()[lr.dofs], lr.R[lr.dofs], 1e-12, f"problem {i} residual", lr.R_abs[lr.dofs])
         b = gp.get_rhs()
-        check_entries(b.cpu().numpy()[lr.dofs], lr.rhs(), 1e-12, f"problem {i} rhs")
+        check_entries(b.cpu().numpy()[lr.dofs], lr.rhs(), 1e-12, f"problem {i} rhs", lr.rhs(absolute=True))
         x = rng.standard_normal(U.size)
         xd = torch.as_tensor(x).cuda()
         yo, ya = lr.apply(x), lr.apply(x, absolute=True)
@@ -233,7 +258,6 @@ def test_fullsize_batched():
         assert torch.equal(B.problem(i).get_rhs(), b), i
         r = b - B.problem(i).jacobian_apply(0, dx, mvpf.FP64)
         assert float(torch.linalg.norm(r) / torch.linalg.norm(b)) <= 1.0001e-8, i
-    B.close()
 
 
 def test_fullsize_sphere_indentation():

@@ -56,7 +56,7 @@ def test_mf_fp64_operator_vcycle_solve(mf_case):
                   abs_product(oc.sys.A, x))
     v = rng.standard_normal(oc.sys.b.shape[0])
     assert rel(gp.precondition(_dev(v)).cpu().numpy(), oc.mg.precondition(v)) < 1e-10
-    check_entries(gp.get_rhs().cpu().numpy(), oc.sys.b, 1e-12, "rhs")
+    check_entries(gp.get_rhs().cpu().numpy(), oc.sys.b, 1e-12, "rhs", oc.abs_scales()[1])
     dx, st = gp.solve()
     gp.close()
     assert st.converged and st.rel_residual <= 1e-12

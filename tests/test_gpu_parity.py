@@ -66,7 +66,7 @@ def test_residual_parity(case):
     say(f"[{name}] residual")
     R, nf = gp.residual()
     Ro = oc.sys.R
-    check_entries(R.cpu().numpy(), Ro, 1e-12, "residual")
+    check_entries(R.cpu().numpy(), Ro, 1e-12, "residual", oc.abs_scales()[0])
     free = ~oc.mask.ravel()
     assert abs(nf - np.linalg.norm(Ro[free])) <= 1e-12 * np.linalg.norm(Ro[free])
 
@@ -75,7 +75,7 @@ def test_rhs_parity(case):
     name, p, U, En, oc, gp = case
     say(f"[{name}] rhs")
     b = gp.get_rhs().cpu().numpy()
-    check_entries(b, oc.sys.b, 1e-12, "rhs")
+    check_entries(b, oc.sys.b, 1e-12, "rhs", oc.abs_scales()[1])
 
 
 def test_operator_parity_all_levels(case):
@@ -236,7 +236,7 @@ def test_sixteen_cubed_coarse_1125():
         gp.set_tuning("small_grid_nodes", 0, small)
         gp.newton_system(p.depth_increment)
         b = gp.get_rhs().cpu().numpy()
-        check_entries(b, oc.sys.b, 1e-12, "rhs")
+        check_entries(b, oc.sys.b, 1e-12, "rhs", oc.abs_scales()[1])
         for l, lev in enumerate(oc.mg.levels):
             x = rng.standard_normal(lev.A.shape[0])
             check_entries(gp.jacobian_apply(l, _dev(x)).cpu().numpy(), lev.A @ x, 1e-12, f"K x level {l}",
@@ -403,8 +403,8 @@ def test_pade_orders_match_oracle(order):
     gp = gpu_problem(p, U, En, "fp64", rtol=1e-12)
     gp.newton_system(p.depth_increment)
     R, _ = gp.residual()
-    check_entries(R.cpu().numpy(), oc.sys.R, 1e-12, "residual")
-    check_entries(gp.get_rhs().cpu().numpy(), oc.sys.b, 1e-12, "rhs")
+    check_entries(R.cpu().numpy(), oc.sys.R, 1e-12, "residual", oc.abs_scales()[0])
+    check_entries(gp.get_rhs().cpu().numpy(), oc.sys.b, 1e-12, "rhs", oc.abs_scales()[1])
     x = np.random.default_rng(5).standard_normal(oc.sys.A.shape[0])
     check_entries(gp.jacobian_apply(0, _dev(x)).cpu().numpy(), oc.sys.A @ x, 1e-12, "K x",
                   abs_product(oc.sys.A, x))
