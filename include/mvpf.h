@@ -201,6 +201,23 @@ int mvpf_init_random(mvpf_problem* p, uint64_t seed);
  * current depth. */
 int mvpf_residual(mvpf_problem* p, double* R, double* norm_free);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * residual of mvpf_residual (same arguments, same results bitwise) computed
+ * with a fixed scratch region compiled into the library -- 64 MiB of device
+ * memory per GPU, held from the first call on that GPU until the process
+ * ends -- instead of the problem's assembly scratch; neither the call nor the
+ * library allocates device memory for it.  The Gauss-point gradients go
+ * through the scratch in slabs of whole element layers, so a layer may hold
+ * at most mvpf_residual_noalloc_max_layer() elements (nx * ny; 34 880, e.g.
+ * 128 x 256); larger layers are rejected with MVPF_EINVAL.  Every call on a
+ * GPU shares that GPU's scratch: calls that overlap on one GPU (different
+ * host threads, or different streams in flight) race and must be serialised
+ * by the caller.  Each call writes every scratch value it reads, so nothing
+ * carries over between calls. */
+int mvpf_residual_noalloc(mvpf_problem* p, double* R, double* norm_free);
+int mvpf_residual_noalloc_max_layer(void);
+
 /* Build the Newton system of Eq. linAlgEq at the current state for the
  * loading at total depth `depth`: tangent K = d^2 Pi / dU^2 reassembled on
  * every level at the injected state (Sec. 3.4), Dirichlet rows/columns

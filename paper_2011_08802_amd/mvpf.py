@@ -99,6 +99,8 @@ SIGNATURES = {
     "mvpf_get_state": (C.c_int, [_P, _P, _P, _P, _D]),
     "mvpf_init_random": (C.c_int, [_P, C.c_uint64]),
     "mvpf_residual": (C.c_int, [_P, _P, _D]),
+    "mvpf_residual_noalloc": (C.c_int, [_P, _P, _D]),
+    "mvpf_residual_noalloc_max_layer": (C.c_int, []),
     "mvpf_newton_system": (C.c_int, [_P, C.c_double]),
     "mvpf_get_rhs": (C.c_int, [_P, _P]),
     "mvpf_jacobian_apply": (C.c_int, [_P, C.c_int, C.c_int, _P, _P]),
@@ -269,6 +271,15 @@ class Problem:
         R = self._vec()
         nf = C.c_double()
         self._check(self.lib.mvpf_residual(self.h, _ptr(R), C.byref(nf)))
+        return R, nf.value
+
+    def residual_noalloc(self, R: Optional[torch.Tensor] = None):
+        """mvpf_residual_noalloc: the residual with the library's fixed device
+        scratch (no allocation by the library); R: optional caller-owned
+        output (a new tensor if None)."""
+        R = self._vec() if R is None else R
+        nf = C.c_double()
+        self._check(self.lib.mvpf_residual_noalloc(self.h, _ptr(R), C.byref(nf)))
         return R, nf.value
 
     def newton_system(self, depth: float):
