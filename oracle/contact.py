@@ -38,7 +38,7 @@ import torch
 from torch.func import grad, hessian, vmap
 
 from .energy import DT
-from .fem import NDOF, Mesh
+from .fem import Mesh
 
 
 def face_gauss():
@@ -89,7 +89,7 @@ class SphereContact:
         return (self.w * 0.5 * self.eps * neg * neg).sum()
 
     def _u_faces(self, U: np.ndarray) -> torch.Tensor:
-        return torch.as_tensor(U.reshape(-1, NDOF)[self.face_nodes][:, :, :3], dtype=DT)
+        return torch.as_tensor(U.reshape(self.mesh.n_nodes, -1)[self.face_nodes][:, :, :3], dtype=DT)
 
     def energy(self, U: np.ndarray, depth: float) -> float:
         d = torch.as_tensor(depth, dtype=DT)
@@ -100,8 +100,9 @@ class SphereContact:
         """dPi_c/dU, node-interleaved (only top-face u components nonzero)."""
         d = torch.as_tensor(depth, dtype=DT)
         Gf = vmap(grad(self.face_energy), in_dims=(0, 0, None))(self._u_faces(U), self.X, d).numpy()
-        R = np.zeros(self.mesh.n_nodes * NDOF)
-        dofs = self.face_nodes[:, :, None] * NDOF + np.arange(3)
+        nd = U.size // self.mesh.n_nodes
+        R = np.zeros(self.mesh.n_nodes * nd)
+        dofs = self.face_nodes[:, :, None] * nd + np.arange(3)
         np.add.at(R, dofs.ravel(), Gf.ravel())
         return R
 
@@ -110,7 +111,8 @@ class SphereContact:
         d = torch.as_tensor(depth, dtype=DT)
         Hf = vmap(hessian(self.face_energy), in_dims=(0, 0, None))(self._u_faces(U), self.X, d)
         Hf = Hf.reshape(len(self.face_nodes), 12, 12).numpy()
-        dofs = (self.face_nodes[:, :, None] * NDOF + np.arange(3)).reshape(-1, 12)
+        nd = U.size // self.mesh.n_nodes
+        dofs = (self.face_nodes[:, :, None] * nd + np.arange(3)).reshape(-1, 12)
         rows = np.repeat(dofs, 12, axis=1).ravel()
         cols = np.tile(dofs, (1, 12)).ravel()
         return rows, cols, Hf.ravel()

@@ -9,6 +9,7 @@ global incremental potential (Eq. PenPot, Sec. 3.1) without its contact term
   chemical      sum_i eta_i F_i^0                               (Sec. 2.2)
   elastic       1/2 det(F^t) H^e : L(eta) H^e                   (Eq. elasticEn)
                 F^t = sum_i eta_i U_i                           (Eq. LinMix)
+                or F^t = exp(sum_i eta_i log U_i)   (logarithmic mixing, Sec. 2.1)
                 F^e = F (F^t)^-1,  C^e = (F^e)^T F^e
                 H^e = Pade approximant of 1/2 log C^e           (Eqs. pade11/22/33)
                 L(eta) = sum_i eta_i L_i
@@ -80,10 +81,33 @@ class TorchCard:
         self.rho = torch.as_tensor(card.rho, dtype=DT)
         self.eps = float(card.eps)
         self.pade = int(card.pade)
+        self.mixing = getattr(card, "mixing", "linear")
+        self.logU = torch.as_tensor(card.logU, dtype=DT) if self.mixing == "log" else None
+
+
+EXP_TERMS = 30
+
+
+def expm_series(M: torch.Tensor) -> torch.Tensor:
+    """exp(M) by its defining power series sum_{n <= 30} M^n / n!.  For
+    ||M||_F <= 1 the omitted tail is below 1/31! ~ 1e-34, so the result is
+    exact up to rounding; larger arguments are refused (the log-mixed
+    arguments here have ||M|| ~ sum |eta_i| ||log U_i|| ~ 0.1)."""
+    if float(torch.linalg.matrix_norm(M.detach()).max()) > 1.0:
+        raise ValueError("expm_series: ||M||_F > 1 is outside the oracle's range")
+    term = torch.eye(3, dtype=M.dtype).expand(M.shape)
+    out = term
+    for n in range(1, EXP_TERMS + 1):
+        term = term @ M / n
+        out = out + term
+    return out
 
 
 def transformation_gradient(eta: torch.Tensor, tc: TorchCard) -> torch.Tensor:
-    """F^t = sum_i eta_i U_i (Eq. LinMix)."""
+    """F^t = sum_i eta_i U_i (Eq. LinMix), or with logarithmic mixing
+    F^t = exp(sum_i eta_i log U_i) (Sec. 2.1)."""
+    if tc.mixing == "log":
+        return expm_series(torch.einsum("...i,ijk->...jk", eta, tc.logU))
     return torch.einsum("...i,ijk->...jk", eta, tc.U)
 
 

@@ -29,6 +29,8 @@ from torch.func import grad, hessian, vmap
 from . import energy
 from .energy import DT
 
+# unknowns per node and variants of the six-variant card; a card of N
+# variants has 3 + N unknowns per node (Discretisation.ndof)
 NDOF = 9
 NETA = 6
 
@@ -118,6 +120,8 @@ class Discretisation:
     def __init__(self, mesh: Mesh, card, chunk: int = 1024):
         self.mesh = mesh
         self.tc = energy.TorchCard(card)
+        self.nv = int(card.U.shape[0]) - 1   # variants N
+        self.ndof = 3 + self.nv              # unknowns per node
         N, dN, w = gauss_tables(mesh.h)
         self.N = torch.as_tensor(N, dtype=DT)
         self.dN = torch.as_tensor(dN, dtype=DT)
@@ -139,18 +143,19 @@ class Discretisation:
 
     def _gather(self, U: np.ndarray, Eta_n: np.ndarray, elems):
         en = self.mesh.element_nodes(elems)
-        d = torch.as_tensor(U.reshape(-1, NDOF)[en], dtype=DT)
-        dn = torch.as_tensor(Eta_n.reshape(-1, NETA)[en], dtype=DT)
+        d = torch.as_tensor(U.reshape(-1, self.ndof)[en], dtype=DT)
+        dn = torch.as_tensor(Eta_n.reshape(-1, self.nv)[en], dtype=DT)
         return en, d, dn
 
     def element_residuals(self, U, Eta_n, elems):
         en, d, dn = self._gather(U, Eta_n, elems)
-        return en, vmap(grad(self.element_potential))(d, dn).reshape(len(en), 72).numpy()
+        return en, vmap(grad(self.element_potential))(d, dn).reshape(len(en), 8 * self.ndof).numpy()
 
     def element_tangents(self, U, Eta_n, elems):
         en, d, dn = self._gather(U, Eta_n, elems)
         K = vmap(hessian(self.element_potential))(d, dn)
-        return en, K.reshape(len(en), 72, 72).numpy()
+        m = 8 * self.ndof
+        return en, K.reshape(len(en), m, m).numpy()
 
     def potential(self, U, Eta_n) -> float:
         en, d, dn = self._gather(U, Eta_n, np.arange(self.mesh.n_elem))
@@ -161,10 +166,11 @@ class Discretisation:
         With ``elems`` only those elements' contributions are summed."""
         if elems is None:
             elems = np.arange(self.mesh.n_elem)
-        R = np.zeros(self.mesh.n_nodes * NDOF)
+        nd, m = self.ndof, 8 * self.ndof
+        R = np.zeros(self.mesh.n_nodes * nd)
         for s in range(0, len(elems), self.chunk):
             en, Re = self.element_residuals(U, Eta_n, elems[s:s + self.chunk])
-            dofs = (en[:, :, None] * NDOF + np.arange(NDOF)).reshape(len(en), 72)
+            dofs = (en[:, :, None] * nd + np.arange(nd)).reshape(len(en), m)
             np.add.at(R, dofs.ravel(), Re.ravel())
         return R
 
@@ -173,10 +179,11 @@ class Discretisation:
         if elems is None:
             elems = np.arange(self.mesh.n_elem)
         rows, cols, vals = [], [], []
+        nd, m = self.ndof, 8 * self.ndof
         for s in range(0, len(elems), self.chunk):
             en, Ke = self.element_tangents(U, Eta_n, elems[s:s + self.chunk])
-            dofs = (en[:, :, None] * NDOF + np.arange(NDOF)).reshape(len(en), 72)
-            rows.append(np.repeat(dofs, 72, axis=1).ravel())
-            cols.append(np.tile(dofs, (1, 72)).ravel())
+            dofs = (en[:, :, None] * nd + np.arange(nd)).reshape(len(en), m)
+            rows.append(np.repeat(dofs, m, axis=1).ravel())
+            cols.append(np.tile(dofs, (1, m)).ravel())
             vals.append(Ke.ravel())
         return np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)

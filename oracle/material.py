@@ -14,6 +14,18 @@ Oracle (test infrastructure only; see the package docstring).
   sample axes in cubic coordinates), Sec. 4.1: [011] parallel to the loading
   axis z.
 
+A second kind of card describes materials with any number N of variants
+(the paper's footnote in Sec. 4.4 mentions NiTi with 12 variants, i.e. 15
+unknowns per node): the variants are the distinct images Q U_1 Q^T of one
+given stretch tensor U_1 under the 24 rotations of the cube (the
+transformation's crystallographic equivalence, Sec. 2.1), each with the
+stiffness L_1 rotated alike.  No NiTi data is used: the values are synthetic.
+
+Mixing rule of the transformation stretch (Sec. 2.1): linear, F^t = sum
+eta_i U_i (Eq. LinMix, the paper's choice), or logarithmic, F^t =
+exp(sum eta_i log U_i) (the alternative the paper discusses); log U_i of the
+symmetric positive definite U_i is taken through its spectral decomposition.
+
 Fourth-order tensors are kept as full 3x3x3x3 arrays (no Voigt bookkeeping)
 so that each operation can be checked by eye.
 """
@@ -106,6 +118,41 @@ def rotate2(A: np.ndarray, R: np.ndarray) -> np.ndarray:
     return R @ A @ R.T
 
 
+def cubic_rotations() -> list:
+    """The 24 proper rotations of the cube: signed permutation matrices with
+    determinant +1, Q[i, perm[i]] = sign[i], in a fixed order (permutations
+    of (0, 1, 2) in lexicographic order, then sign patterns with the sign of
+    row 0 varying slowest, + before -)."""
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1.0, -1.0), repeat=3):
+            Q = np.zeros((3, 3))
+            for i in range(3):
+                Q[i, perm[i]] = signs[i]
+            if np.linalg.det(Q) > 0:
+                out.append(Q)
+    return out
+
+
+def orbit_variants(U1: np.ndarray, tol: float = 1e-12):
+    """Distinct Q U1 Q^T over cubic_rotations(), in that order, with the
+    first rotation that produces each: (list of U_k, list of R_k)."""
+    Us, Rs = [], []
+    for Q in cubic_rotations():
+        V = Q @ U1 @ Q.T
+        if not any(np.max(np.abs(V - W)) <= tol for W in Us):
+            Us.append(V)
+            Rs.append(Q)
+    return Us, Rs
+
+
+def spd_log(U: np.ndarray) -> np.ndarray:
+    """log U of a symmetric positive definite matrix: V diag(log lambda) V^T."""
+    lam, V = np.linalg.eigh(U)
+    return V @ np.diag(np.log(lam)) @ V.T
+
+
 class Card:
     """All material data in the sample frame.
 
@@ -120,6 +167,9 @@ class Card:
     """
 
     def __init__(self, mp):
+        if hasattr(mp, "U1"):  # a card generated from one stretch tensor
+            self._init_orbit(mp)
+            return
         Q = np.asarray(mp.Q, dtype=float).reshape(3, 3)
         Uc = stretch_tensors(mp.alpha, mp.beta, mp.gamma)
         Rv = variant_axes()
@@ -137,3 +187,39 @@ class Card:
         self.rho = np.full(7, mp.rho)
         self.eps = float(mp.eps_eta)
         self.pade = int(mp.pade)
+        self._mixing(getattr(mp, "mixing", "linear"))
+
+    def _mixing(self, mixing: str):
+        if mixing not in ("linear", "log"):
+            raise ValueError(f"unknown mixing rule {mixing}")
+        self.mixing = mixing
+        self.logU = np.stack([spd_log(U) for U in self.U])
+
+    @property
+    def n_var(self) -> int:
+        return self.U.shape[0] - 1
+
+    def _init_orbit(self, om):
+        """Card of N variants from one stretch tensor (see the module
+        docstring): om holds U1 (3x3, cubic axes), L1 (6x6 Voigt, engineering
+        shear, cubic axes), cubic (austenite c11, c12, c44), Q (sample
+        rotation), F0_a, F0_m, w_am, w_mm, ell, rho, eps_eta, pade, mixing."""
+        c = self
+        Q = np.asarray(om.Q, dtype=float).reshape(3, 3)
+        Us, Rs = orbit_variants(np.asarray(om.U1, dtype=float).reshape(3, 3))
+        L1 = voigt_to_tensor(np.asarray(om.L1, dtype=float).reshape(6, 6))
+        n = len(Us)
+        c.U = np.stack([np.eye(3)] + [rotate2(U, Q) for U in Us])
+        c.L = np.stack([rotate4(cubic_stiffness(*om.cubic), Q)] + [rotate4(rotate4(L1, R), Q) for R in Rs])
+        c.F0 = np.array([om.F0_a] + [om.F0_m] * n)
+        W = np.full((n + 1, n + 1), om.w_mm)
+        W[0, :] = W[:, 0] = om.w_am
+        np.fill_diagonal(W, 0.0)
+        c.W = W
+        c.ell2 = np.full((n + 1, n + 1), om.ell ** 2)
+        c.rho = np.full(n + 1, om.rho)
+        c.eps = float(om.eps_eta)
+        c.pade = int(om.pade)
+        c._mixing(om.mixing)
+        if c.n_var != om.n_var:
+            raise ValueError(f"the orbit of U1 has {c.n_var} variants, the card states {om.n_var}")

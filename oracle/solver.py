@@ -52,8 +52,9 @@ from .material import Card
 # ---------------------------------------------------------------------------
 
 def dirichlet(mesh: Mesh, kind: str = "patch", patch: int = 2, radius: float = 0.2,
-              depth: float = 0.0):
-    """Constrained-dof mask (n_nodes, 9) bool and target values (n_nodes, 9).
+              depth: float = 0.0, ndof: int = NDOF):
+    """Constrained-dof mask (n_nodes, ndof) bool and target values (n_nodes, ndof)
+    (ndof = 3 + N unknowns per node, N variants).
 
     Bottom face z = 0: all three displacement components fixed at 0.  Top
     face: kind 'patch' -- nodes of the centred patch x patch element square
@@ -64,8 +65,8 @@ def dirichlet(mesh: Mesh, kind: str = "patch", patch: int = 2, radius: float = 0
     parameters are never constrained (natural boundary conditions).
     """
     nn = mesh.n_nodes
-    mask = np.zeros((nn, NDOF), dtype=bool)
-    target = np.zeros((nn, NDOF))
+    mask = np.zeros((nn, ndof), dtype=bool)
+    target = np.zeros((nn, ndof))
     i, j, k = mesh.node_ijk(np.arange(nn))
     mask[k == 0, 0:3] = True
     top = k == mesh.nz
@@ -113,7 +114,7 @@ def assemble(disc: Discretisation, U: np.ndarray, Eta_n: np.ndarray,
              contact: Optional[SphereContact] = None, depth: float = 0.0) -> sp.csr_matrix:
     """Unconstrained tangent K as CSR (duplicates summed by scipy), with the
     contact tangent at indenter depth ``depth`` when ``contact`` is given."""
-    n = disc.mesh.n_nodes * NDOF
+    n = disc.mesh.n_nodes * disc.ndof
     r, c, v = disc.tangent_coo(U, Eta_n)
     if contact is not None:
         rc, cc, vc = contact.tangent_coo(U, depth)
@@ -198,18 +199,18 @@ class Multigrid:
                  opts: MGOptions = MGOptions(), K_fine: Optional[sp.csr_matrix] = None,
                  depth: float = 0.0):
         self.opts = opts
-        self.bs = NDOF
+        self.bs = 3 + card.n_var
         L = problem.n_levels if n_levels is None else n_levels
         self.levels: List[Level] = []
         mesh = Mesh.from_problem(problem, 0)
-        Ul, En, mask = U.reshape(-1, NDOF), Eta_n.reshape(-1, NETA), fine_mask
+        Ul, En, mask = U.reshape(-1, self.bs), Eta_n.reshape(-1, self.bs - 3), fine_mask
         for l in range(L):
             if l > 0:
                 cm = Mesh.from_problem(problem, l)
                 Ul = inject(mesh, Ul, cm)
                 En = inject(mesh, En, cm)
                 mask = coarse_mask(mesh, mask, cm)
-                self.levels[-1].P = prolongation(cm, mesh)
+                self.levels[-1].P = prolongation(cm, mesh, self.bs)
                 mesh = cm
             disc = Discretisation(mesh, card)
             K = K_fine if (l == 0 and K_fine is not None) else \
@@ -479,7 +480,7 @@ def indent(problem, U: np.ndarray, Eta_n: np.ndarray, opts: IndentOptions,
     contact = contact_of(problem, mesh)
     if contact is None:
         raise ValueError("indentation needs the 'sphere' loading")
-    mask, _ = dirichlet(mesh, "sphere")
+    mask, _ = dirichlet(mesh, "sphere", ndof=U.size // mesh.n_nodes)
     zero = np.zeros(mask.shape)
     U, Eta_n = U.copy(), Eta_n.copy()
     depth, dd = 0.0, opts.dd_init
@@ -506,7 +507,7 @@ def indent(problem, U: np.ndarray, Eta_n: np.ndarray, opts: IndentOptions,
                     return records, U, False
                 continue
             U, depth = U1, trial
-            Eta_n = U.reshape(-1, NDOF)[:, 3:].ravel().copy()
+            Eta_n = U.reshape(-1, mask.shape[1])[:, 3:].ravel().copy()
             records.append(IndentRecord(depth, contact.load(U, depth), it, rejected))
             rejected = 0
             if it < opts.newton_desired:

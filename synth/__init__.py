@@ -1,7 +1,8 @@
 """Seeded synthetic inputs for the indentation workloads.
 
-This module is shared by the tests, the benchmark, the HIP-path binding and the
-CPU oracle.  It holds raw input values only -- mesh sizes, loading geometry,
+This module is used by the tests, the benchmark and the CPU oracle (the HIP
+path's binding imports nothing from it; callers hand it Problem objects).  It
+holds raw input values only -- mesh sizes, loading geometry,
 material constants as printed in the paper, seeds and counter-based random
 numbers -- and none of the method's arithmetic (no stiffness rotation, no
 transformation stretch matrices, no boundary-condition logic).
@@ -43,11 +44,13 @@ def uniform01(seed: int, counters: np.ndarray) -> np.ndarray:
     return (splitmix64(c) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
 
 
-def initial_eta(seed: int, n_nodes: int, amplitude: float = 0.05) -> np.ndarray:
-    """Initial order parameters, shape (n_nodes, 6), uniform in [0, amplitude)."""
+def initial_eta(seed: int, n_nodes: int, amplitude: float = 0.05, n_var: int = 6) -> np.ndarray:
+    """Initial order parameters, shape (n_nodes, n_var), uniform in
+    [0, amplitude); the counter of node a and variant i (0-based) is its
+    node-interleaved dof index (3 + n_var) a + 3 + i."""
     a = np.arange(n_nodes, dtype=np.uint64)[:, None]
-    i = np.arange(6, dtype=np.uint64)[None, :]
-    return amplitude * uniform01(seed, np.uint64(9) * a + np.uint64(3) + i)
+    i = np.arange(n_var, dtype=np.uint64)[None, :]
+    return amplitude * uniform01(seed, np.uint64(3 + n_var) * a + np.uint64(3) + i)
 
 
 # ---------------------------------------------------------------------------
@@ -84,6 +87,63 @@ class MaterialParams:
     rho: float = 1.0
     eps_eta: float = 1000.0
     pade: int = 22
+    mixing: str = "linear"
+    n_var: int = 6
+
+
+@dataclass
+class OrbitMaterial:
+    """Raw inputs of a synthetic card with N variants generated from one
+    stretch tensor by the cubic symmetry (the variants are the distinct
+    images Q U1 Q^T under the 24 rotations of the cube, each with L1 rotated
+    alike).  Stresses in GPa.
+
+    U1: variant 1's stretch tensor (row-major 3x3, symmetric, cubic axes).
+    L1: variant 1's stiffness, 6x6 Voigt (order 11,22,33,23,13,12,
+        engineering shear strains), cubic axes.
+    cubic: austenite (c11, c12, c44).  Q: sample rotation (rows = sample
+    axes in cubic coordinates).  F0_a, F0_m: chemical energy of the
+    austenite and of every variant.  n_var: the number of distinct variants
+    the orbit gives (stated, so that sizes are known without building the
+    card)."""
+    U1: tuple
+    L1: tuple
+    n_var: int
+    cubic: tuple = (142.0, 126.0, 96.0)
+    Q: tuple = tuple(np.eye(3).ravel())
+    F0_a: float = 0.0
+    F0_m: float = 0.005
+    w_am: float = 0.25
+    w_mm: float = 0.025
+    ell: float = 0.01
+    rho: float = 1.0
+    eps_eta: float = 1000.0
+    pade: int = 22
+    mixing: str = "linear"
+
+
+def _ortho_voigt(c11, c22, c33, c44, c55, c66, c12, c13, c23):
+    """The nine orthotropic constants laid out as a 6x6 Voigt matrix (raw
+    layout of input values, row-major)."""
+    return (c11, c12, c13, 0, 0, 0,
+            c12, c22, c23, 0, 0, 0,
+            c13, c23, c33, 0, 0, 0,
+            0, 0, 0, c44, 0, 0,
+            0, 0, 0, 0, c55, 0,
+            0, 0, 0, 0, 0, c66)
+
+
+def twelve_variant_material(**over) -> OrbitMaterial:
+    """A synthetic 12-variant card (not NiTi data): a monoclinic-type
+    stretch U1 = [[1.05, 0.02, 0.02], [0.02, 0.98, 0.04], [0.02, 0.04, 0.98]]
+    (eigenvalues 0.940, 1.003, 1.067; 12 distinct images under the cubic
+    rotations) with the orthorhombic constants of Table 1 as its stiffness in
+    the cubic axes, the austenite and the remaining coefficients of the
+    six-variant workloads, [011] along z."""
+    base = dict(U1=(1.05, 0.02, 0.02, 0.02, 0.98, 0.04, 0.02, 0.04, 0.98),
+                L1=_ortho_voigt(*MaterialParams().ortho), n_var=12, Q=Q_011_Z)
+    base.update(over)
+    return OrbitMaterial(**base)
 
 
 # Sample axes x = [100], y = [01-1]/sqrt2, z = [011]/sqrt2: the [011] crystal
@@ -137,11 +197,15 @@ class Problem:
         return (self.nx + 1) * (self.ny + 1) * (self.nz + 1)
 
     @property
+    def n_var(self) -> int:
+        return self.material.n_var
+
+    @property
     def n_dof(self) -> int:
-        return 9 * self.n_nodes
+        return (3 + self.n_var) * self.n_nodes
 
     def eta0(self) -> np.ndarray:
-        return initial_eta(self.seed, self.n_nodes)
+        return initial_eta(self.seed, self.n_nodes, n_var=self.n_var)
 
 
 def tiny() -> Problem:
