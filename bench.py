@@ -1,17 +1,25 @@
 #!/usr/bin/env python3
 """Newton-step benchmark on one MI355X.
 
-A step is one full Newton iteration of the indentation problem: residual and
-tangent reassembled on every multigrid level at the injected state, block
+A step is one Newton iteration of a running indentation simulation: residual
+and tangent reassembled on every multigrid level at the injected state, block
 inverses and coarse factorisation, FGMRES + geometric-multigrid solve to a
-1e-8 relative FP64 residual, state update.  The state is restored from a
-device-resident copy before every step, so each step solves the same (first,
-lifted) Newton system of the first load step.
+1e-8 relative FP64 residual, state update and the Newton convergence test.
+The simulation runs the workload's load steps in order (the state is never
+reset): each load step's Newton iterations continue until the free-dof
+residual is below 1e-9 of its first right-hand side, then the next load step
+starts from the converged state.  The first W iterations are untimed
+(warm-up); the next K are timed, so the timed systems are the later, harder
+ones of the run, not a repeat of the first.
 
-Default workload: 64^3 hex elements (274,625 nodes, 2,471,625 dof), 5 levels,
-8x8-element patch pushed 0.01, initial eta from seed 20110880.  The headline
-value is the FP32-multigrid (mixed) path; the all-FP64 multigrid path is timed
-on the same system and reported beside it.
+Default workload: the single-GPU scale limit, 256x256x128 hex elements on a
+1x1x0.5 box (76,682,889 dof), 6 levels, spherical-cap indenter of radius 0.2
+pushed 0.0025 per load step.  The headline value is the FP32-multigrid
+(mixed) path; the all-FP64 multigrid path runs the same Newton sequence and
+is timed beside it.  Also reported: the 64^3 patch workload's whole 5-step
+run with every Newton solve, and the CPU oracle on the whole 8^3 workload and
+on a bounded sample of the default workload, each with the GPU solutions'
+error against the oracle's.
 
 Prints one JSON line (see the README/DESIGN for the fields).
 """
@@ -32,8 +40,11 @@ import synth  # noqa: E402
 
 METRIC = "Newton-step solve time & DOF/s at 1e-8 rel. residual, FP32-GMG vs FP64 GMG"
 HBM_PEAK_GBS = 8000.0
-# calibrated rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the same kernels at 64^3
-COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_patch64_mixed.txt")
+# calibrated rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of the same kernels, per workload
+COUNTERS = {
+    "medium": os.path.join(ROOT, "profiles", "hbm_counters_patch64_mixed.txt"),
+    "scale": os.path.join(ROOT, "profiles", "hbm_counters_cap256x256x128_mixed.txt"),
+}
 
 WORKLOADS = {
     "tiny": synth.tiny,
@@ -47,57 +58,177 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_precision(prob, precision, steps, warmup, timing, tune=True, matrix_free=-1):
+class NewtonRun:
+    """Newton iterations of one problem's load-step sequence through the
+    C ABI, with the library's own step rule (Sec. 3.4, as mvpf_time_step):
+    iterate newton_system / solve / newton_update until the free-dof
+    residual is <= newton_rtol times the attempt's first right-hand side
+    norm.  An attempt fails after newton_max solves without convergence, on a
+    non-finite residual or on a singular 9x9 block / coarse operator; then
+    the state of the attempt's start is restored and the depth increment
+    halved (at most 8 times per load step).  An accepted attempt sets
+    eta_n <- eta and, if it stopped short of the load step's depth, the next
+    attempt goes on to it.  One call of iteration() is one Newton iteration
+    (a failed attempt's restore is part of the iteration that ended it)."""
+
+    def __init__(self, gp, prob, newton_rtol=1e-9, newton_max=12, tag=None):
+        self.gp, self.prob, self.tag = gp, prob, tag
+        self.rtol, self.nmax = newton_rtol, newton_max
+        self.k, self.j, self.b0 = 1, 0, 0.0
+        self.index = 0
+        self.depth = 0.0                     # depth of the last accepted state
+        self.trial = prob.depth_increment   # depth of the current attempt
+        self.halvings = 0
+        self.saved = None
+
+    def _save(self):
+        self.saved = [t.clone() for t in self.gp.get_state()[:3]]
+
+    def _fail(self):
+        u, e, en = self.saved
+        self.gp.set_state(u, e, en, self.depth)
+        self.halvings += 1
+        if self.halvings > 8:
+            raise RuntimeError(f"load step {self.k}: Newton failed after 8 halvings")
+        self.trial = self.depth + 0.5 * (self.trial - self.depth)
+        self.j = 0
+
+    def iteration(self):
+        from paper_2011_08802_amd import mvpf
+        gp = self.gp
+        if self.j == 0:
+            self._save()
+        depth = self.trial
+        rec = dict(index=self.index, load_step=self.k, depth=round(depth, 8), newton=self.j)
+        t0 = time.perf_counter()
+        try:
+            gp.newton_system(depth)
+        except mvpf.MvpfError as err:
+            if err.code != -4:  # MVPF_ESINGULAR: the attempt fails
+                raise
+            self._fail()
+            self.index += 1
+            rec.update(system_ms=1e3 * (time.perf_counter() - t0), solve_ms=0.0, fgmres=0, rel_residual=float("nan"),
+                       solve_converged=False, newton_rel_residual=float("nan"), attempt="singular block: halved",
+                       iteration_ms=1e3 * (time.perf_counter() - t0))
+            return rec
+        t1 = time.perf_counter()
+        if self.j == 0:
+            self.b0 = float(torch.linalg.norm(gp.get_rhs()))
+        _, st = gp.solve(want_x=False)
+        gp.newton_update()
+        _, rfree = gp.residual()
+        t2 = time.perf_counter()
+        rec.update(system_ms=1e3 * (t1 - t0), solve_ms=st.solve_ms, fgmres=st.iterations,
+                   rel_residual=st.rel_residual, solve_converged=bool(st.converged),
+                   newton_rel_residual=rfree / self.b0 if self.b0 else float("nan"))
+        self.index += 1
+        if np.isfinite(rfree) and rfree <= self.rtol * self.b0:
+            _, e, _, _ = gp.get_state()
+            gp.set_state(None, None, e, depth)
+            self.depth = depth
+            rec["attempt"] = "accepted"
+            self.j = 0
+            goal = self.k * self.prob.depth_increment
+            if depth == goal:
+                self.k += 1
+                self.halvings = 0
+                self.trial = self.k * self.prob.depth_increment
+            else:
+                self.trial = goal
+        elif not np.isfinite(rfree) or self.j + 1 >= self.nmax:
+            self._fail()
+            rec["attempt"] = "failed: halved"
+        else:
+            self.j += 1
+        rec["iteration_ms"] = 1e3 * (time.perf_counter() - t0)
+        if self.tag:
+            log(f"[{self.tag}] it {rec['index']}: load step {rec['load_step']} depth {rec['depth']:.5f} newton "
+                f"{rec['newton']} fgmres {rec['fgmres']} solve {rec['solve_ms']:.1f} ms, newton residual "
+                f"{rec['newton_rel_residual']:.2e} {rec.get('attempt', '')}")
+        return rec
+
+
+def run_sequence(prob, precision, warmup, steps, timing, tune=True, matrix_free=-1, snapshot_at=None, tag=None):
+    """W untimed + K timed Newton iterations of the workload's load-step
+    sequence from the seeded initial state.  Before it (untimed): launch
+    shapes autotuned on the first Newton system and that system's solution
+    kept for the error statement.  snapshot_at = n <= W keeps (u, eta) after
+    the first n iterations (taken in the warm-up, outside the timed region)."""
     from paper_2011_08802_amd import mvpf
     gp = mvpf.Problem(prob, precision, rtol=1e-8)
-    if matrix_free >= 0:
-        gp.set_tuning("matrix_free", 0, matrix_free)
-    gp.init_random(prob.seed)
-    u0, e0, en0, _ = gp.get_state()
-    u0, e0, en0 = u0.clone(), e0.clone(), en0.clone()
-    depth = prob.depth_increment
-    shapes = None
-    if tune:  # untimed setup: pick launch shapes on this Newton system
-        gp.newton_system(depth)
-        shapes = gp.autotune()
-
-    def step(rec):
+    try:
+        if matrix_free >= 0:
+            gp.set_tuning("matrix_free", 0, matrix_free)
+        gp.init_random(prob.seed)
+        u0, e0, en0, _ = gp.get_state()
+        u0, e0, en0 = u0.clone(), e0.clone(), en0.clone()
+        gp.newton_system(prob.depth_increment)
+        shapes = gp.autotune() if tune else None
+        gp.newton_system(prob.depth_increment)
+        x1, st1 = gp.solve()
         gp.set_state(u0, e0, en0, 0.0)
+        del u0, e0, en0
+        run = NewtonRun(gp, prob, tag=tag)
+        recs, snap = [], None
+        for _ in range(warmup):
+            recs.append(run.iteration())
+            if snapshot_at is not None and run.index == snapshot_at:
+                snap = [t.clone() for t in gp.get_state()[:2]]
+        if timing:
+            gp.kernel_timing(True)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        gp.newton_system(depth)
-        t1 = time.perf_counter()
-        x, st = gp.solve(want_x=False)
-        t2 = time.perf_counter()
-        gp.newton_update()
-        if rec is not None:
-            rec.append(dict(system_ms=1e3 * (t1 - t0), solve_ms=st.solve_ms, its=st.iterations,
-                            rel_res=st.rel_residual, converged=st.converged))
+        for _ in range(steps):
+            recs.append(run.iteration())
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        kstats = {}
+        if timing:
+            for name in ("pbj_sweep", "residual", "spmv_outer"):
+                n, ms, by = gp.kernel_stats(name)
+                if n:
+                    kstats[name] = dict(launches=n, avg_ms=ms / n, bytes=by, gbs=by / (ms / n) / 1e6)
+            gp.kernel_timing(False)
+        mf = gp.get_tuning("matrix_free")
+    finally:
+        gp.close()
+    for r in recs[:warmup]:
+        r["timed"] = False
+    for r in recs[warmup:]:
+        r["timed"] = True
+    return dict(total_s=total, recs=recs, kernels=kstats, x1=x1, first_its=st1.iterations, shapes=shapes,
+                matrix_free=mf, snapshot=snap)
 
-    for _ in range(warmup):
-        step(None)
-    recs = []
-    if timing:
-        gp.kernel_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step(recs)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    kstats = {}
-    if timing:
-        for name in ("pbj_sweep", "residual", "spmv_outer"):
-            n, ms, by = gp.kernel_stats(name)
-            if n:
-                kstats[name] = dict(launches=n, avg_ms=ms / n, bytes=by, gbs=by / (ms / n) / 1e6)
-        gp.kernel_timing(False)
-    # solution of the (same) Newton system for the error statement
-    gp.set_state(u0, e0, en0, 0.0)
-    gp.newton_system(depth)
-    x, st = gp.solve()
-    mf = gp.get_tuning("matrix_free")
-    gp.close()
-    return dict(total_s=total, recs=recs, kernels=kstats, x=x.cpu().numpy(), shapes=shapes, matrix_free=mf)
+
+def multistep(prob, precision, budget_s=120.0):
+    """The workload's whole run: every load step to convergence, every Newton
+    solve listed (untimed as a whole; each solve's own time is recorded).
+    Stops after budget_s seconds of wall time (then 'completed' is false)."""
+    from paper_2011_08802_amd import mvpf
+    gp = mvpf.Problem(prob, precision, rtol=1e-8)
+    try:
+        gp.init_random(prob.seed)
+        gp.newton_system(prob.depth_increment)
+        gp.autotune()
+        gp.init_random(prob.seed)
+        run = NewtonRun(gp, prob, tag=f"64^3 {precision}")
+        recs = []
+        t0 = time.perf_counter()
+        while run.k <= prob.steps and len(recs) < 400 and time.perf_counter() - t0 < budget_s:
+            recs.append(run.iteration())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        gp.close()
+    keep = ("load_step", "depth", "newton", "fgmres", "solve_ms", "system_ms", "rel_residual", "newton_rel_residual")
+    return dict(load_steps=prob.steps, completed=run.k > prob.steps, load_steps_done=run.k - 1,
+                budget_s=budget_s, depth_increment=prob.depth_increment, newton_iterations=len(recs),
+                fgmres_iterations=sum(r["fgmres"] for r in recs),
+                solve_ms=sum(r["solve_ms"] for r in recs), wall_s=wall,
+                failed_attempts=sum(1 for r in recs if r.get("attempt", "").startswith(("failed", "singular"))),
+                solves=[{k: (round(r[k], 4) if isinstance(r[k], float) and k.endswith("ms") else r[k])
+                         for k in keep} for r in recs])
 
 
 def pade_assembly(prob, reps=5):
@@ -338,12 +469,14 @@ def indent_main(a):
     print(json.dumps(out), flush=True)
 
 
-def sweep_traffic(prob, matrix_free):
+def sweep_traffic(workload, prob, matrix_free):
     """Measured HBM bytes of one finest-level smoother sweep from the committed
-    counter summary, for the workload it was taken on (64^3), else None.
-    Assembled: pass 1 on two wavefronts per tile + pass 2; matrix-free: the
-    element kernel + the gather with the Jacobi update."""
-    if (prob.nx, prob.ny, prob.nz) != (64, 64, 64) or not os.path.exists(COUNTERS):
+    counter summary of this workload (None if there is none).  Assembled:
+    pass 1 on two wavefronts per tile + pass 2; matrix-free: the element
+    kernel + the gather with the Jacobi update.  Rows are matched by kernel
+    name and grid size (the finest level's launch)."""
+    path = COUNTERS.get(workload)
+    if path is None or not os.path.exists(path):
         return None
     npad = prob.n_nodes + (-prob.n_nodes) % 64
     ntiles = npad // 64
@@ -360,7 +493,7 @@ def sweep_traffic(prob, matrix_free):
         }
     total = 0.0
     found = set()
-    with open(COUNTERS) as f:
+    with open(path) as f:
         for line in f:
             parts = line.split()
             if len(parts) < 7 or parts[0] not in want:
@@ -376,43 +509,107 @@ def sweep_traffic(prob, matrix_free):
     return total if len(found) == 2 else None
 
 
-def cpu_baseline(n=16, levels=4, prob=None):
-    """The oracle (test infrastructure) on a bounded sample of the workload:
-    one Newton iteration (autodiff assembly of the tangent, multigrid setup,
-    FGMRES+GMG to 1e-8) of the same indentation problem at n^3 elements, or
-    of `prob` itself when the workload is small enough (8^3)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_newton(p, threads, reference):
+    """The oracle (test infrastructure) on one Newton iteration of problem p
+    from its seeded initial state: autodiff assembly of the residual and
+    tangent on every level + multigrid setup, then FGMRES+GMG to 1e-8 (timed).
+    reference: 'direct' (the plain definition, sparse LU) or 'fgmres' (the
+    oracle's own FGMRES+GMG at rtol 1e-12), untimed."""
     from oracle import solver as S
     from oracle.fem import Mesh, NDOF
     from oracle.material import Card
-    threads = min(16, os.cpu_count() or 1)
     torch.set_num_threads(threads)
-    p = prob or synth.Problem(n, n, n, n_levels=levels, patch=max(2, n // 8), depth_increment=0.01)
-    n, levels = p.nx, p.n_levels
     card = Card(p.material)
     m = Mesh.from_problem(p)
     U = np.zeros((m.n_nodes, NDOF))
     U[:, 3:] = p.eta0()
     mask, target = S.dirichlet(m, p.kind, p.patch, p.radius, depth=p.depth_increment)
     t0 = time.perf_counter()
-    sysk = S.NewtonSystem(p, card, U.ravel(), U[:, 3:].ravel().copy(), mask, S.increment(mask, target, U))
-    mg = S.Multigrid(p, card, U.ravel(), U[:, 3:].ravel().copy(), mask, K_fine=sysk.K)
+    sysk = S.NewtonSystem(p, card, U.ravel(), U[:, 3:].ravel().copy(), mask, S.increment(mask, target, U),
+                          p.depth_increment)
+    mg = S.Multigrid(p, card, U.ravel(), U[:, 3:].ravel().copy(), mask, K_fine=sysk.K, depth=p.depth_increment)
     t1 = time.perf_counter()
     x, st = S.fgmres(sysk.A, sysk.b, mg.precondition, rtol=1e-8)
     t2 = time.perf_counter()
-    return dict(value=p.n_dof / (t2 - t0), unit="DOF/s", cores=threads, kind="oracle",
-                sample=f"one Newton iteration of the patch-indentation workload at {n}^3 elements "
-                       f"{'(the whole workload) ' if prob is not None else ''}"
-                       f"({p.n_dof} dof, {levels} levels): autodiff assembly + MG setup {t1 - t0:.1f} s, "
-                       f"FGMRES+GMG {st.iterations} its {t2 - t1:.1f} s",
-                solve_dof_per_s=p.n_dof / (t2 - t1), iterations=st.iterations)
+    if reference == "direct":
+        xref = S.direct_solve(sysk.A, sysk.b)
+    else:
+        xref, _ = S.fgmres(sysk.A, sysk.b, mg.precondition, rtol=1e-12)
+    return dict(assembly_s=t1 - t0, solve_s=t2 - t1, iterations=st.iterations, x=x, xref=xref)
+
+
+def gpu_errors(p, xref):
+    """GPU solves (mixed and FP64 multigrid, rtol 1e-8) of the same first
+    Newton system; relative error of each against the oracle's reference."""
+    from paper_2011_08802_amd import mvpf
+    out = {}
+    for prec in ("mixed", "fp64"):
+        gp = mvpf.Problem(p, prec, rtol=1e-8)
+        try:
+            gp.init_random(p.seed)
+            gp.newton_system(p.depth_increment)
+            x, st = gp.solve()
+            xg = x.cpu().numpy()
+        finally:
+            gp.close()
+        out[prec] = dict(rel_error=float(np.linalg.norm(xg - xref) / np.linalg.norm(xref)),
+                         fgmres_iterations=st.iterations)
+    return out
+
+
+def cpu_baseline(sample):
+    """The oracle on the host cores: the whole 8^3 workload (all threads and
+    one thread) and a bounded sample of the benchmarked workload; value = the
+    sample's DOF per second of one Newton iteration (assembly + solve)."""
+    threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or (os.cpu_count() or 1)
+    tiny = synth.tiny()
+    log(f"[bench] oracle: whole 8^3 workload, {threads} threads")
+    a = oracle_newton(tiny, threads, "direct")
+    log("[bench] oracle: whole 8^3 workload, 1 thread")
+    a1 = oracle_newton(tiny, 1, "direct")
+    err_tiny = gpu_errors(tiny, a["xref"])
+    log(f"[bench] oracle: sample {sample.nx}x{sample.ny}x{sample.nz}, {threads} threads")
+    b = oracle_newton(sample, threads, "fgmres")
+    err_sample = gpu_errors(sample, b["xref"])
+    torch.set_num_threads(threads)
+    step_s = b["assembly_s"] + b["solve_s"]
+    return dict(
+        value=sample.n_dof / step_s, unit="DOF/s", cores=threads, kind="oracle",
+        sample=(f"one Newton iteration (autodiff assembly on all {sample.n_levels} levels + multigrid setup "
+                f"{b['assembly_s']:.1f} s, FGMRES+GMG to 1e-8 {b['solve_s']:.1f} s, {b['iterations']} its) "
+                f"of the same {sample.kind} indentation at {sample.nx}x{sample.ny}x{sample.nz} elements "
+                f"({sample.n_dof} dof): the benchmarked workload's geometry and loading on a coarser mesh"),
+        solve_dof_per_s=sample.n_dof / b["solve_s"],
+        os_cpu_count=os.cpu_count(), cpu_model=cpu_model(),
+        threads_note="the box allots OMP_NUM_THREADS host threads per GPU; os_cpu_count is the host's total",
+        whole_8cubed={"dof": tiny.n_dof, "threads": threads, "newton_step_s": a["assembly_s"] + a["solve_s"],
+                      "solve_s": a["solve_s"], "iterations": a["iterations"],
+                      "one_thread_newton_step_s": a1["assembly_s"] + a1["solve_s"],
+                      "one_thread_solve_s": a1["solve_s"],
+                      "gpu_error_vs_oracle_direct_solve": err_tiny},
+        sample_gpu_error_vs_oracle_fgmres_rtol12=err_sample)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="medium", choices=list(WORKLOADS) + ["batched", "indent"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="scale", choices=list(WORKLOADS) + ["batched", "indent"])
+    ap.add_argument("--fp64-steps", type=int, default=5,
+                    help="timed Newton iterations of the FP64-multigrid comparison (after the same warm-up)")
+    ap.add_argument("--no-multistep", action="store_true", help="skip the whole 64^3 run")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-multigrid comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
@@ -445,36 +642,60 @@ def main():
     if a.workload == "indent":
         indent_main(a)
         return
+    single_main(a)
+
+
+SAMPLES = {  # bounded samples of each workload for the oracle (about 10-20 s of oracle work)
+    "tiny": lambda p: p,
+    "medium": lambda p: synth.Problem(16, 16, 16, n_levels=3, patch=2, depth_increment=p.depth_increment),
+    "large": lambda p: synth.Problem(16, 16, 16, n_levels=3, patch=2, depth_increment=p.depth_increment),
+    "scale": lambda p: synth.Problem(24, 24, 12, lz=0.5, n_levels=3, kind="cap", radius=p.radius,
+                                     depth_increment=p.depth_increment),
+}
+
+
+def single_main(a):
     prob = WORKLOADS[a.workload]()
     ndof = prob.n_dof
-    log(f"[bench] workload {a.workload}: {prob.nx}x{prob.ny}x{prob.nz}, {ndof} dof, {prob.n_levels} levels")
+    W, K = a.warmup, a.steps
+    log(f"[bench] workload {a.workload}: {prob.nx}x{prob.ny}x{prob.nz}, {ndof} dof, {prob.n_levels} levels; "
+        f"{W} + {K} Newton iterations of the load-step sequence")
     log("[bench] mixed (FP32 multigrid) ...")
-    mixed = run_precision(prob, "mixed", a.steps, a.warmup, not a.no_timing, not a.no_tune, a.matrix_free)
+    mixed = run_sequence(prob, "mixed", W, K, not a.no_timing, not a.no_tune, a.matrix_free, snapshot_at=W,
+                         tag="mixed")
+    x1m = mixed.pop("x1")
+    log(f"[bench] mixed: {ndof * K / mixed['total_s']:.4g} DOF/s, {1e3 * mixed['total_s'] / K:.1f} ms per Newton "
+        f"iteration; sweep {mixed['kernels'].get('pbj_sweep')}")
     fp64 = None
     if not a.no_fp64:
-        log("[bench] fp64 multigrid ...")
-        fp64 = run_precision(prob, "fp64", a.steps, a.warmup, False, not a.no_tune, a.matrix_free)
+        kf = min(K, a.fp64_steps)
+        log(f"[bench] fp64 multigrid: {W} + {kf} Newton iterations of the same sequence ...")
+        fp64 = run_sequence(prob, "fp64", W, kf, False, not a.no_tune, a.matrix_free, snapshot_at=W, tag="fp64")
+        x1f = fp64.pop("x1")
 
     def summary(r):
-        recs = r["recs"]
-        solve_ms = statistics.median(x["solve_ms"] for x in recs)
-        return dict(ms_per_step=1e3 * r["total_s"] / len(recs), solve_ms_median=solve_ms,
-                    solve_dof_per_s=ndof / (solve_ms / 1e3),
+        recs = [x for x in r["recs"] if x["timed"]]
+        return dict(ms_per_step=1e3 * r["total_s"] / len(recs),
+                    solve_ms_median=statistics.median(x["solve_ms"] for x in recs),
+                    solve_dof_per_s=ndof * len(recs) / (1e-3 * sum(x["solve_ms"] for x in recs)),
                     system_ms_median=statistics.median(x["system_ms"] for x in recs),
-                    fgmres_iterations=[x["its"] for x in recs],
-                    rel_residual_max=max(x["rel_res"] for x in recs),
-                    converged=all(x["converged"] for x in recs))
+                    fgmres_iterations=[x["fgmres"] for x in recs],
+                    rel_residual_max=max(x["rel_residual"] for x in recs),
+                    converged=all(x["solve_converged"] for x in recs),
+                    load_steps_touched=sorted({x["load_step"] for x in recs}))
 
     ms = summary(mixed)
     ms["launch_shapes"] = mixed["shapes"]
     ms["matrix_free"] = mixed["matrix_free"]
+    keep = ("index", "load_step", "depth", "newton", "fgmres", "solve_ms", "system_ms", "iteration_ms",
+            "rel_residual", "newton_rel_residual", "timed")
     out = {
         "metric": METRIC,
-        "value": ndof * a.steps / mixed["total_s"],
+        "value": ndof * K / mixed["total_s"],
         "unit": "DOF/s",
         "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
+        "steps": K,
+        "warmup": W,
         "ms_per_step": ms["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -482,37 +703,73 @@ def main():
         "dtype": "f64+f32",
         "data": "synthetic",
         "config": {"workload": f"{'patch' if prob.kind == 'patch' else 'spherical-cap'} indentation "
-                               f"{prob.nx}x{prob.ny}x{prob.nz} Q1 hex, "
-                               f"{ndof} dof, {prob.n_levels}-level GMG V(2,2), FGMRES(30) rtol 1e-8",
+                               f"{prob.nx}x{prob.ny}x{prob.nz} Q1 hex ({prob.lx:g}x{prob.ly:g}x{prob.lz:g}), "
+                               f"{ndof} dof, {prob.n_levels}-level GMG V(2,2), FGMRES(30) rtol 1e-8; "
+                               f"{prob.steps} load steps of {prob.depth_increment}; a step = one Newton "
+                               f"iteration of the running load-step sequence (Newton rtol 1e-9), iterations "
+                               f"{W}..{W + K - 1} timed",
                    "nx": prob.nx, "ny": prob.ny, "nz": prob.nz, "levels": prob.n_levels,
-                   "depth": prob.depth_increment, "seed": prob.seed, "precision": "mixed"},
+                   "load": prob.kind, "depth_increment": prob.depth_increment, "load_steps": prob.steps,
+                   "seed": prob.seed, "precision": "mixed"},
         "mixed": ms,
+        "newton_iterations": [{k: (round(r[k], 4) if isinstance(r[k], float) and k.endswith("ms") else r[k])
+                               for k in keep} for r in mixed["recs"]],
     }
     if fp64 is not None:
         fs = summary(fp64)
         fs["launch_shapes"] = fp64["shapes"]
+        fs["value"] = ndof * len([x for x in fp64["recs"] if x["timed"]]) / fp64["total_s"]
+        fs["fgmres_iterations_all"] = [x["fgmres"] for x in fp64["recs"]]
         out["fp64_gmg"] = fs
-        out["fp64_gmg"]["value"] = ndof * a.steps / fp64["total_s"]
-        out["speedup_solve_mixed_vs_fp64"] = fs["solve_ms_median"] / ms["solve_ms_median"]
-        out["speedup_step_mixed_vs_fp64"] = fs["ms_per_step"] / ms["ms_per_step"]
-        out["mixed_vs_fp64_solution_rel_diff"] = float(
-            np.linalg.norm(mixed["x"] - fp64["x"]) / np.linalg.norm(fp64["x"]))
+        # the same Newton systems (same position in the sequence), warm-up included but the first
+        common = range(1, min(len(mixed["recs"]), len(fp64["recs"])))
+        sm = [mixed["recs"][i]["solve_ms"] for i in common]
+        sf = [fp64["recs"][i]["solve_ms"] for i in common]
+        out["speedup_solve_mixed_vs_fp64"] = statistics.median(f / m for f, m in zip(sf, sm))
+        out["speedup_solve_mixed_vs_fp64_basis"] = f"median over Newton iterations 1..{len(sm)} of the sequence"
+        d1 = float(torch.linalg.norm(x1m - x1f) / torch.linalg.norm(x1f))
+        err = {"first_newton_system_solution_rel_diff": d1}
+        if mixed["snapshot"] is not None and fp64["snapshot"] is not None:
+            (um, em), (uf, ef) = mixed["snapshot"], fp64["snapshot"]
+            err[f"state_after_{W}_newton_iterations_rel_diff"] = {
+                "u": float(torch.linalg.norm(um - uf) / torch.linalg.norm(uf)),
+                "eta": float(torch.linalg.norm(em - ef) / torch.linalg.norm(ef))}
+        out["error_vs_fp64_gpu"] = err
+    del x1m
+    if fp64 is not None:
+        del x1f
+    mixed["snapshot"] = None
+    if fp64 is not None:
+        fp64["snapshot"] = None
+    torch.cuda.empty_cache()
+    out["error_vs_oracle"] = ("not computed at this size (the oracle's autodiff assembly would take hours); "
+                              "see cpu_baseline: GPU error vs the oracle on the whole 8^3 workload and on the "
+                              "sample" if a.workload != "tiny" else "see cpu_baseline")
     k = mixed["kernels"].get("pbj_sweep")
     if k:
         mf = mixed["matrix_free"]
         out["roofline"] = {"bound": "hbm", "achieved": k["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": k["gbs"] / HBM_PEAK_GBS, "traffic": sweep_traffic(prob, mf),
+                           "frac": k["gbs"] / HBM_PEAK_GBS, "traffic": sweep_traffic(a.workload, prob, mf),
                            "kernel": "finest-level FP32 smoother sweep "
                                      + ("(matrix-free: mf_element + mf_gather<2>)" if mf
                                         else "(defect_upper_split + pbj_lower)"),
                            "bytes_per_launch": k["bytes"], "avg_ms": k["avg_ms"], "launches": k["launches"]}
         out["kernels"] = mixed["kernels"]
+    if not a.no_multistep and a.workload != "medium":
+        med = synth.medium()
+        out["multistep_64cubed"] = {}
+        for prec in ("fp64", "mixed"):
+            log(f"[bench] whole 64^3 run ({med.steps} load steps of {med.depth_increment}), {prec} ...")
+            try:
+                out["multistep_64cubed"][prec] = multistep(med, prec)
+            except Exception as err:  # reported, not fatal for the headline
+                out["multistep_64cubed"][prec] = {"error": str(err)}
     if not a.no_pade and a.workload in ("tiny", "medium"):
         log("[bench] assembly per Pade order ...")
         out["pade_assembly"] = pade_assembly(prob)
     if not a.no_cpu_baseline:
         log("[bench] oracle cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(prob=prob if a.workload == "tiny" else None)
+        out["cpu_baseline"] = cpu_baseline(SAMPLES[a.workload](prob))
     print(json.dumps(out), flush=True)
 
 
