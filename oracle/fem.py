@@ -142,6 +142,7 @@ class Discretisation:
         return (self.w * psi).sum()
 
     def _gather(self, U: np.ndarray, Eta_n: np.ndarray, elems):
+        energy.check_log_range(U.reshape(-1, self.ndof)[:, 3:], self.tc)
         en = self.mesh.element_nodes(elems)
         d = torch.as_tensor(U.reshape(-1, self.ndof)[en], dtype=DT)
         dn = torch.as_tensor(Eta_n.reshape(-1, self.nv)[en], dtype=DT)
