@@ -7,9 +7,13 @@
  * computational aspects and large-scale finite-element simulations",
  * CMAME 2021 (cited below by section / equation / table).
  *
- * Unknowns: 9 per node, node-interleaved [u_x, u_y, u_z, eta_1 .. eta_6]:
+ * Unknowns: 3 + N per node, node-interleaved [u_x, u_y, u_z, eta_1 .. eta_N]:
  * displacement u = phi - X and the condensed order parameters eta_hat with
- * eta_0 = 1 - sum eta_i (Sec. 3.1).  Nodes are numbered lexicographically,
+ * eta_0 = 1 - sum eta_i (Sec. 3.1).  N, the number of martensite variants,
+ * is a compile-time constant of a library build (mvpf_nvar()): 6 for
+ * libmvpf.so (CuAlNi, Sec. 4.1; 9 unknowns per node), 12 for
+ * libmvpf_n12.so (15 unknowns per node).  "9" below stands for 3 + N and
+ * "6" (order parameters) for N.  Nodes are numbered lexicographically,
  * x fastest: node(i,j,k) = i + (nx+1)*(j + (ny+1)*k).  The mesh is a uniform
  * grid of nx*ny*nz cubes of side h (trilinear Q1 elements, 2x2x2 Gauss).
  *
@@ -50,6 +54,7 @@ enum {
 };
 
 enum { MVPF_FP64 = 0, MVPF_MIXED = 1 };          /* mvpf_opts.precision */
+enum { MVPF_MIX_LINEAR = 0, MVPF_MIX_LOG = 1 };  /* mixing rule of the transformation stretch */
 enum { MVPF_LOAD_PATCH = 0, MVPF_LOAD_CAP = 1, MVPF_LOAD_SPHERE = 2 };  /* mvpf_loading.kind */
 
 typedef struct mvpf_problem mvpf_problem;
@@ -84,7 +89,14 @@ typedef struct {
  *  eps_eta penalty parameter of eta_i >= 0 (Eq. PenPot)
  *  pade    Pade order of the Hencky strain: 11, 22 or 33 for the (1,1), (2,2) or
  *          (3,3) approximant (Eqs. pade11, pade22, pade33); other values are
- *          rejected with MVPF_EINVAL */
+ *          rejected with MVPF_EINVAL
+ *  mixing  MVPF_MIX_LINEAR: F^t = sum_i eta_i U_i (Eq. LinMix, the paper's
+ *          choice); MVPF_MIX_LOG: F^t = exp(sum_i eta_i log U_i), the
+ *          logarithmic rule of Sec. 2.1 (its exponential is evaluated by its
+ *          power series, exact to rounding while ||sum eta_i log U_i||_F <= 1,
+ *          i.e. far beyond the order parameters' range [0, 1] here)
+ * This card has six variants: it needs a library built for N = 6
+ * (mvpf_nvar()); otherwise mvpf_create returns MVPF_EINVAL. */
 typedef struct {
   double cubic[3];
   double ortho[9];
@@ -96,7 +108,38 @@ typedef struct {
   double rho;
   double eps_eta;
   int pade;
+  int mixing;
 } mvpf_material;
+
+/* Material card with N variants generated from one stretch tensor (Sec. 2.1:
+ * the variants are crystallographically equivalent; the paper's footnote in
+ * Sec. 4.4 mentions NiTi with 12 variants, 15 unknowns per node).  The
+ * variants are the distinct images R U1 R^T of U1 under the 24 rotations R
+ * of the cube, taken in a fixed order (signed permutation matrices
+ * R[i][perm[i]] = sign[i] of determinant +1: permutations of (0,1,2) in
+ * lexicographic order, then sign patterns with row 0's sign varying
+ * slowest, + before -; images within 1e-12 of an earlier one are the same
+ * variant); variant k's stiffness is L1 rotated by the R that produced it.
+ * All in the cubic axes, then rotated by Q into the sample frame.
+ *  U1      row-major symmetric 3x3 stretch tensor of variant 1
+ *  L1      6x6 Voigt stiffness of variant 1 (order 11,22,33,23,13,12,
+ *          engineering shear strains), row-major, GPa
+ *  cubic, Q, w_am, w_mm, ell, rho, eps_eta, pade, mixing: as mvpf_material
+ *  F0_a, F0_m  chemical energy densities of the austenite and of every variant
+ * The orbit must have exactly mvpf_nvar() variants (else MVPF_EINVAL). */
+typedef struct {
+  double U1[9];
+  double L1[36];
+  double cubic[3];
+  double Q[9];
+  double F0_a, F0_m;
+  double w_am, w_mm;
+  double ell;
+  double rho;
+  double eps_eta;
+  int pade;
+  int mixing;
+} mvpf_orbit_material;
 
 /* Indentation loading (Sec. 4.1).  Bottom face z = 0: u = 0.  Top face
  * z = nz*h, with d = the indenter depth (mvpf_set_state, mvpf_time_step):
@@ -170,12 +213,23 @@ typedef struct {
  * V(2,2), omega 0.55, newton_max 12, newton_rtol 1e-9). */
 void mvpf_default_opts(mvpf_opts* opts);
 
-/* Create a problem: validates the inputs, builds the material card in the
- * sample frame, allocates every level's operators and vectors, zeroes the
- * state (u = 0, eta_hat = eta_hat_n = 0, depth 0).  stream: hipStream_t or
+/* Create a problem (the setup of the paper's problem statement, Sec. 2 and
+ * Sec. 4.1): validates the inputs, builds the material card in the sample
+ * frame (stretch tensors of Sec. 4.1 and Table 1 stiffnesses, each variant's
+ * orthorhombic axes being the principal axes of its stretch tensor, rotated
+ * by Q), allocates every level's operators and vectors, zeroes the state
+ * (u = 0, eta_hat = eta_hat_n = 0, depth 0).  stream: hipStream_t or
  * NULL.  On error *out is NULL and mvpf_last_error(NULL) explains. */
 int mvpf_create(const mvpf_mesh* mesh, const mvpf_material* mat, const mvpf_loading* load,
                 const mvpf_opts* opts, void* stream, mvpf_problem** out);
+/* mvpf_create with a card generated from one stretch tensor (see
+ * mvpf_orbit_material); the only way to create problems in a library built
+ * for N != 6. */
+int mvpf_create_orbit(const mvpf_mesh* mesh, const mvpf_orbit_material* mat, const mvpf_loading* load,
+                      const mvpf_opts* opts, void* stream, mvpf_problem** out);
+/* Number of variants N the library was built for (the order parameters per
+ * node; 3 + N unknowns per node). */
+int mvpf_nvar(void);
 void mvpf_destroy(mvpf_problem* p);
 /* Last error message of p, or of the last failed mvpf_create if p is NULL. */
 const char* mvpf_last_error(const mvpf_problem* p);
@@ -190,8 +244,12 @@ int mvpf_set_opts(mvpf_problem* p, const mvpf_opts* opts);
 int mvpf_set_state(mvpf_problem* p, const double* u, const double* eta, const double* eta_prev,
                    double depth);
 int mvpf_get_state(mvpf_problem* p, double* u, double* eta, double* eta_prev, double* depth);
-/* u = 0, depth 0, eta_hat = eta_hat_n with eta_hat(a, i) =
- * 0.05 * (splitmix64(seed ^ (9a + 3 + i)) >> 11) * 2^-53, i = 0..5. */
+/* Seeded initial state (the paper starts from a perturbed austenite; the
+ * perturbation here is a reading: a uniform random eta_hat in [0, 0.05)
+ * from a counter-based generator, so that CPU and GPU draw identical bits):
+ * u = 0, depth 0, eta_hat = eta_hat_n with eta_hat(a, i) =
+ * 0.05 * (splitmix64(seed ^ (9a + 3 + i)) >> 11) * 2^-53, i = 0..5
+ * (splitmix64: Steele, Lea and Flood, OOPSLA 2014). */
 int mvpf_init_random(mvpf_problem* p, uint64_t seed);
 
 /* Residual R = dPi/dU of the discrete penalised incremental potential at the
@@ -250,6 +308,15 @@ int mvpf_solve(mvpf_problem* p, const double* b, double* x, mvpf_solve_stats* st
 /* U <- U + Delta with the internally kept solution of the last mvpf_solve;
  * constrained dofs are set to their targets. */
 int mvpf_newton_update(mvpf_problem* p);
+
+/* One Newton iteration of the monolithic scheme (Sec. 3.4, Eq. linAlgEq) at
+ * indenter depth `depth`: mvpf_newton_system(depth), mvpf_solve with the
+ * system's own right-hand side (stats: nullable), mvpf_newton_update.  The
+ * Newton loop of a time step is mvpf_time_step; this is one of its
+ * iterations without the convergence test.  Returns MVPF_ESINGULAR (state
+ * unchanged) for a singular block or coarse operator; MVPF_ENOTCONV if the
+ * solve stopped at max_it (the update is still applied). */
+int mvpf_newton_step(mvpf_problem* p, double depth, mvpf_solve_stats* stats);
 
 /* One implicit time step to total depth `depth` (Sec. 3.4): Newton
  * iterations (newton_system, solve, update) until the free-dof residual is
@@ -348,13 +415,23 @@ int mvpf_indent(mvpf_problem* p, const mvpf_indent_opts* o, mvpf_indent_callback
  * level ignored.  row_blocks on level 0 and outer_blocks apply to the
  * assembled finest level only.  "mf_elements_per_block": elements per
  * workgroup of the matrix-free element kernel, 8, 16 or 32 (64, 128 or 256
- * threads; default 32; level ignored; results bitwise unchanged). */
+ * threads; default 32; level ignored; results bitwise unchanged).
+ * "autotune_cache": 1 (default) = mvpf_autotune reuses the results of earlier
+ * tuning runs for the same GPU architecture, multigrid precision,
+ * finest-level mode (matrix-free or assembled) and level shape (elements per
+ * direction) instead of timing again; 0 = always time (and record).  The
+ * results are kept for the process; if the environment variable
+ * MVPF_TUNE_CACHE names a file, they are also read from it at the first
+ * lookup and every new result is appended to it as a "key value" line
+ * (level ignored). */
 int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value);
 int mvpf_get_tuning(const mvpf_problem* p, const char* key, int level, int* value);
 /* Time candidate launch shapes of the smoother (every level but the coarsest;
  * on a matrix-free finest level its elements per workgroup) and of the outer
  * product (assembled finest level only) on the operators of the last
- * mvpf_newton_system, and keep the fastest.  row_blocks_out (nullable,
+ * mvpf_newton_system, and keep the fastest; shapes already tuned for the same
+ * architecture, precision, finest-level mode and level shape are taken from
+ * the tuning cache (tuning key "autotune_cache").  row_blocks_out (nullable,
  * n_levels ints): chosen values per level (on a matrix-free finest level:
  * elements per workgroup), the last entry being the outer product's. */
 int mvpf_autotune(mvpf_problem* p, int* row_blocks_out);

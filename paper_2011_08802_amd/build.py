@@ -1,7 +1,10 @@
-"""Build libmvpf.so for gfx950 with hipcc (in-tree).
+"""Build the mvpf libraries for gfx950 with hipcc (in-tree).
 
 Each ``csrc/*.hip`` translation unit is compiled to an object under
-``_build/`` in parallel, then linked into ``paper_2011_08802_amd/libmvpf.so``.
+``_build/`` in parallel and linked into one shared library per number of
+martensite variants N (a compile-time constant of the kernels):
+``paper_2011_08802_amd/libmvpf.so`` (N = 6, the CuAlNi workloads) and
+``paper_2011_08802_amd/libmvpf_n12.so`` (N = 12, 15 unknowns per node).
 Always recompiles (the caller decides when to build).
 """
 from __future__ import annotations
@@ -15,9 +18,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
-LIB = os.path.join(HERE, "libmvpf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MVPF_ARCH", "gfx950")
+NVARS = (6, 12)
+
+
+def lib_path(nvar: int) -> str:
+    return os.path.join(HERE, "libmvpf.so" if nvar == 6 else f"libmvpf_n{nvar}.so")
+
+
+LIB = lib_path(6)
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -31,30 +41,36 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+def _compile(job) -> str:
+    src, nvar = job
+    obj = os.path.join(BUILD, f"n{nvar}", os.path.basename(src) + ".o")
+    cmd = [HIPCC, *CFLAGS, f"-DMVPF_NVAR={nvar}", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+        raise RuntimeError(f"hipcc failed for {src} (N = {nvar}):\n{r.stdout}\n{r.stderr}")
     warn = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip())
     if warn:
         sys.stderr.write(warn + "\n")
     return obj
 
 
-def build(jobs: int | None = None) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs: int | None = None, nvars=NVARS) -> str:
     srcs = sources()
-    jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
+    work = [(src, n) for n in nvars for src in srcs]
+    for n in nvars:
+        os.makedirs(os.path.join(BUILD, f"n{n}"), exist_ok=True)
+    jobs = jobs or min(len(work), os.cpu_count() or 4, 16)
     with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+        objs = list(ex.map(_compile, work))
+    for n in nvars:
+        lib = lib_path(n)
+        tmp = lib + ".tmp"
+        mine = [o for (src, m), o in zip(work, objs) if m == n]
+        cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *mine]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed (N = {n}):\n{r.stdout}\n{r.stderr}")
+        os.replace(tmp, lib)
     return LIB
 
 

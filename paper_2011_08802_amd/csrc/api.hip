@@ -6,7 +6,11 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
+#include <fstream>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "common.h"
@@ -159,21 +163,127 @@ void rotate_t4(const T4 L, const double R[3][3], T4 out) {
         }
 }
 
-void build_card(const mvpf_material& m, DevCard& cd) {
+// eigen-decomposition of a symmetric 3x3 matrix by cyclic Jacobi rotations:
+// A = V diag(w) V^T (columns of V = eigenvectors)
+void sym_eig3(const double A0[3][3], double w[3], double V[3][3]) {
+  double A[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      A[i][j] = A0[i][j];
+      V[i][j] = i == j ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    const double off = std::fabs(A[0][1]) + std::fabs(A[0][2]) + std::fabs(A[1][2]);
+    const double scale = std::fabs(A[0][0]) + std::fabs(A[1][1]) + std::fabs(A[2][2]);
+    if (off <= 1e-17 * scale) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (A[p][q] == 0.0) continue;
+        // rotation zeroing A[p][q] (Golub & Van Loan, symmetric Schur 2x2)
+        const double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+        for (int k = 0; k < 3; ++k) {  // A <- A J
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {  // A <- J^T A
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < 3; ++k) {  // V <- V J
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - sn * vkq;
+          V[k][q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  for (int i = 0; i < 3; ++i) w[i] = A[i][i];
+}
+
+// Card inputs in the cubic crystal frame, before the rotation Q into the
+// sample frame: the austenite stiffness and each variant's stretch tensor
+// and stiffness.
+struct CubicCard {
+  int n = 0;
+  double U[NV][3][3];
+  double L[NV][3][3][3][3];
+  double L0[3][3][3][3];
+};
+
+// The rest of the card (Sec. 2.2-2.3, 3.1; Eqs. LinMix and IntEnergy, the
+// logarithmic mixing rule of Sec. 2.1): everything rotated by Q, stored as
+// differences to the austenite (U_k - I, L_k - L_0), log U_k for log
+// mixing, chemical energies, the double-obstacle matrix and its condensed
+// forms.
+void fill_card(const CubicCard& cc, const double Qm[9], const double F0[NV + 1], double w_am, double w_mm, double ell,
+               double rho, double eps, int pade, int mixing, DevCard& cd) {
   std::memset(&cd, 0, sizeof(cd));
   double Q[3][3];
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) Q[i][j] = m.Q[3 * i + j];
+    for (int j = 0; j < 3; ++j) Q[i][j] = Qm[3 * i + j];
+  T4 L0s;
+  rotate_t4(cc.L0, Q, L0s);
+  double L0v[6][6];
+  t4_to_voigt(L0s, L0v);
+  for (int v = 0; v < NV; ++v) {
+    double Us[3][3];  // Q U Q^T
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0;
+        for (int k = 0; k < 3; ++k)
+          for (int l = 0; l < 3; ++l) s += Q[i][k] * cc.U[v][k][l] * Q[j][l];
+        Us[i][j] = s;
+      }
+    for (int i = 0; i < 3; ++i)
+      for (int j = i; j < 3; ++j) cd.dU[v][SI(i, j)] = Us[i][j] - (i == j ? 1.0 : 0.0);
+    // log U_k = V diag(log w) V^T of the symmetric positive definite U_k
+    double w[3], V[3][3];
+    sym_eig3(Us, w, V);
+    for (int i = 0; i < 3; ++i)
+      for (int j = i; j < 3; ++j) {
+        double s = 0;
+        for (int k = 0; k < 3; ++k) s += V[i][k] * std::log(w[k]) * V[j][k];
+        cd.logU[v][SI(i, j)] = s;
+      }
+    T4 Ls;
+    rotate_t4(cc.L[v], Q, Ls);
+    double Lv[6][6];
+    t4_to_voigt(Ls, Lv);
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) cd.dL[v][i][j] = Lv[i][j] - L0v[i][j];
+  }
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) cd.L0[i][j] = L0v[i][j];
+  for (int k = 0; k < NV; ++k) cd.dF0[k] = F0[k + 1] - F0[0];
+  for (int i = 0; i <= NV; ++i)
+    for (int j = 0; j <= NV; ++j) cd.W[i][j] = (i == j) ? 0.0 : ((i == 0 || j == 0) ? w_am : w_mm);
+  // condensation eta_0 = 1 - sum eta_k: Hessian of 1/2 eta^T W eta w.r.t. eta_hat
+  for (int k = 0; k < NV; ++k)
+    for (int l = 0; l < NV; ++l) cd.Sw[k][l] = cd.W[k + 1][l + 1] - cd.W[k + 1][0] - cd.W[0][l + 1] + cd.W[0][0];
+  // gradient energy -sum_{i<j} w_ij l^2 grad eta_i . grad eta_j in eta_hat
+  const double l2 = ell * ell;
+  for (int k = 0; k < NV; ++k)
+    for (int l = 0; l < NV; ++l) cd.Mg[k][l] = -l2 * cd.Sw[k][l];
+  cd.rho = rho;
+  cd.eps = eps;
+  cd.pade = pade;
+  cd.mixing = mixing;
+}
+
+// CuAlNi card (Sec. 4.1, Table 1; six variants): stretch tensors from
+// alpha, beta, gamma; each variant's orthorhombic stiffness in the
+// principal axes of its stretch tensor.  Valid for a library of six variants.
+void build_card(const mvpf_material& m, DevCard& cd) {
+  CubicCard cc;
   // austenite
   double C0[6][6] = {};
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) C0[a][b] = (a == b) ? m.cubic[0] : m.cubic[1];
   C0[3][3] = C0[4][4] = C0[5][5] = m.cubic[2];
-  T4 L0c, L0s;
-  voigt_to_t4(C0, L0c);
-  rotate_t4(L0c, Q, L0s);
-  double L0v[6][6];
-  t4_to_voigt(L0s, L0v);
+  voigt_to_t4(C0, cc.L0);
   // martensite in its orthorhombic axes: c11,c22,c33,c44,c55,c66,c12,c13,c23
   const double* o = m.ortho;
   double Cm[6][6] = {};
@@ -190,11 +300,14 @@ void build_card(const mvpf_material& m, DevCard& cd) {
   const int pa[3] = {0, 0, 1}, pb[3] = {2, 1, 2}, pc[3] = {1, 2, 0};
   const double pp = 0.5 * (m.alpha + m.gamma), qq = 0.5 * (m.alpha - m.gamma);
   const double r2 = 1.0 / std::sqrt(2.0);
-  for (int v = 0; v < 6; ++v) {
+  cc.n = NV < 6 ? NV : 6;
+  for (int v = 0; v < cc.n; ++v) {
     const int pr = v / 2;
     const double sg = (v % 2 == 0) ? 1.0 : -1.0;
     const int a = pa[pr], b = pb[pr], c = pc[pr];
-    double U[3][3] = {};
+    double (&U)[3][3] = cc.U[v];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) U[i][j] = 0.0;
     U[a][a] = U[b][b] = pp;
     U[a][b] = U[b][a] = sg * qq;
     U[c][c] = m.beta;
@@ -202,40 +315,91 @@ void build_card(const mvpf_material& m, DevCard& cd) {
     R[a][0] = r2; R[b][0] = sg * r2;
     R[c][1] = 1.0;
     R[a][2] = r2; R[b][2] = -sg * r2;
-    // U in the sample frame: Q U Q^T
-    double Us[3][3];
+    rotate_t4(Lmo, R, cc.L[v]);
+  }
+  double F0[NV + 1] = {};
+  for (int k = 0; k <= cc.n; ++k) F0[k] = m.F0[k];
+  fill_card(cc, m.Q, F0, m.w_am, m.w_mm, m.ell, m.rho, m.eps_eta, m.pade, m.mixing, cd);
+}
+
+// The 24 rotations of the cube: signed permutation matrices of determinant
+// +1, Q[i][perm[i]] = sign[i]; permutations in lexicographic order, then
+// sign patterns with row 0's sign varying slowest, + before -.
+int cubic_rotations(double out[24][3][3]) {
+  int perm[3] = {0, 1, 2}, n = 0;
+  do {
+    for (int sgn = 0; sgn < 8; ++sgn) {
+      double Q[3][3] = {};
+      for (int i = 0; i < 3; ++i) Q[i][perm[i]] = ((sgn >> (2 - i)) & 1) ? -1.0 : 1.0;
+      const double det = Q[0][0] * (Q[1][1] * Q[2][2] - Q[1][2] * Q[2][1]) -
+                         Q[0][1] * (Q[1][0] * Q[2][2] - Q[1][2] * Q[2][0]) +
+                         Q[0][2] * (Q[1][0] * Q[2][1] - Q[1][1] * Q[2][0]);
+      if (det > 0) std::memcpy(out[n++], Q, sizeof(Q));
+    }
+  } while (std::next_permutation(perm, perm + 3));
+  return n;
+}
+
+// Card of a material whose variants are the distinct images Q U1 Q^T of one
+// stretch tensor under the cube's rotations (in the order above; images
+// equal within 1e-12 are one variant), each with L1 rotated by the rotation
+// that produced it.  Returns the number of variants the orbit has (the card
+// is filled only if it equals the library's N).
+int build_card_orbit(const mvpf_orbit_material& m, DevCard& cd) {
+  CubicCard cc;
+  double R[24][3][3];
+  const int nr = cubic_rotations(R);
+  double U1[3][3], L1v[6][6];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) U1[i][j] = m.U1[3 * i + j];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) L1v[i][j] = m.L1[6 * i + j];
+  T4 L1;
+  voigt_to_t4(L1v, L1);
+  int n = 0;
+  for (int r = 0; r < nr; ++r) {
+    double V[3][3];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
         double s = 0;
         for (int k = 0; k < 3; ++k)
-          for (int l = 0; l < 3; ++l) s += Q[i][k] * U[k][l] * Q[j][l];
-        Us[i][j] = s;
+          for (int l = 0; l < 3; ++l) s += R[r][i][k] * U1[k][l] * R[r][j][l];
+        V[i][j] = s;
       }
-    for (int i = 0; i < 3; ++i)
-      for (int j = i; j < 3; ++j) cd.dU[v][SI(i, j)] = Us[i][j] - (i == j ? 1.0 : 0.0);
-    T4 Lc, Ls;
-    rotate_t4(Lmo, R, Lc);
-    rotate_t4(Lc, Q, Ls);
-    double Lv[6][6];
-    t4_to_voigt(Ls, Lv);
-    for (int i = 0; i < 6; ++i)
-      for (int j = 0; j < 6; ++j) cd.dL[v][i][j] = Lv[i][j] - L0v[i][j];
+    bool seen = false;
+    for (int q = 0; q < (n < NV ? n : NV) && !seen; ++q) {
+      double d = 0;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) d = std::max(d, std::fabs(V[i][j] - cc.U[q][i][j]));
+      seen = d <= 1e-12;
+    }
+    if (seen) continue;
+    if (n < NV) {
+      std::memcpy(cc.U[n], V, sizeof(V));
+      rotate_t4(L1, R[r], cc.L[n]);
+    }
+    ++n;
   }
-  for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 6; ++j) cd.L0[i][j] = L0v[i][j];
-  for (int k = 0; k < 6; ++k) cd.dF0[k] = m.F0[k + 1] - m.F0[0];
-  for (int i = 0; i < 7; ++i)
-    for (int j = 0; j < 7; ++j) cd.W[i][j] = (i == j) ? 0.0 : ((i == 0 || j == 0) ? m.w_am : m.w_mm);
-  // condensation eta_0 = 1 - sum eta_k: Hessian of 1/2 eta^T W eta w.r.t. eta_hat
-  for (int k = 0; k < 6; ++k)
-    for (int l = 0; l < 6; ++l) cd.Sw[k][l] = cd.W[k + 1][l + 1] - cd.W[k + 1][0] - cd.W[0][l + 1] + cd.W[0][0];
-  // gradient energy -sum_{i<j} w_ij l^2 grad eta_i . grad eta_j in eta_hat
-  const double l2 = m.ell * m.ell;
-  for (int k = 0; k < 6; ++k)
-    for (int l = 0; l < 6; ++l) cd.Mg[k][l] = -l2 * cd.Sw[k][l];
-  cd.rho = m.rho;
-  cd.eps = m.eps_eta;
-  cd.pade = m.pade;
+  if (n != NV) return n;
+  cc.n = n;
+  double C0[6][6] = {};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) C0[a][b] = (a == b) ? m.cubic[0] : m.cubic[1];
+  C0[3][3] = C0[4][4] = C0[5][5] = m.cubic[2];
+  voigt_to_t4(C0, cc.L0);
+  double F0[NV + 1];
+  F0[0] = m.F0_a;
+  for (int k = 1; k <= NV; ++k) F0[k] = m.F0_m;
+  fill_card(cc, m.Q, F0, m.w_am, m.w_mm, m.ell, m.rho, m.eps_eta, m.pade, m.mixing, cd);
+  return n;
+}
+
+// the problem's card (either kind), with the current viscous coefficient
+void make_card(const mvpf_problem* p, DevCard& cd) {
+  if (p->orbit)
+    build_card_orbit(p->omat, cd);
+  else
+    build_card(p->mat, cd);
 }
 
 // ---- typed accessors for the two precision modes --------------------------
@@ -633,6 +797,10 @@ int validate(const mvpf_mesh* mesh, const mvpf_material* mat, const mvpf_loading
     err = "Pade order of the Hencky strain must be 11, 22 or 33";
     return MVPF_EINVAL;
   }
+  if (mat->mixing != MVPF_MIX_LINEAR && mat->mixing != MVPF_MIX_LOG) {
+    err = "mixing must be MVPF_MIX_LINEAR or MVPF_MIX_LOG";
+    return MVPF_EINVAL;
+  }
   if (load->kind == MVPF_LOAD_PATCH) {
     if (load->patch < 0 || load->patch % 2 || mesh->nx % 2 || mesh->ny % 2) {
       err = "patch loading needs even patch, nx and ny";
@@ -735,7 +903,7 @@ int allocate(mvpf_problem* p) {
   {
     // Gauss-point and element-matrix buffers: the whole finest level if that
     // fits ASSEMBLY_FULL_MAX bytes, else slabs of ASSEMBLY_SLAB_BYTES
-    const int64_t per = (int64_t)(QP_HESS * 8 + NPAIR * NBLK) * (int64_t)sizeof(double);
+    const int64_t per = (int64_t)(QP_HESS_ALLOC * 8 + NPAIR * NBLK) * (int64_t)sizeof(double);
     const int64_t nxy = (int64_t)g0.nx * g0.ny;
     if ((int64_t)g0.NEpad * per <= ASSEMBLY_FULL_MAX)
       p->ne_cap = g0.NEpad;
@@ -743,7 +911,7 @@ int allocate(mvpf_problem* p) {
       p->ne_cap = std::max<int64_t>(ASSEMBLY_SLAB_BYTES / per, 2 * nxy + TILE) / TILE * TILE;
     p->ne_cap = std::min<int64_t>(p->ne_cap, g0.NEpad);
     p->ne_use = p->ne_cap;
-    TRY(dalloc(p, &p->qp, (size_t)QP_HESS * 8 * p->ne_cap));
+    TRY(dalloc(p, &p->qp, (size_t)QP_HESS_ALLOC * 8 * p->ne_cap));
     TRY(dalloc(p, &p->elem, (size_t)NPAIR * NBLK * p->ne_cap));
   }
   {
@@ -780,8 +948,9 @@ int allocate(mvpf_problem* p) {
     if (need > have) TRY(dalloc(p, &p->coarse_work, (size_t)need));
   }
   DevCard hc;
-  build_card(p->mat, hc);
-  p->pade = p->mat.pade;
+  make_card(p, hc);
+  p->pade = hc.pade;
+  p->mixing = hc.mixing;
   HIPCHK(hipMemcpyAsync(p->card, &hc, sizeof(DevCard), hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   return 0;
@@ -789,7 +958,7 @@ int allocate(mvpf_problem* p) {
 
 int free_norm(mvpf_problem* p, const double* v, double* out) {
   const Grid& g = p->lev[0].g;
-  const int nb = red_blocks((int64_t)g.N * 9);
+  const int nb = red_blocks((int64_t)g.N * NDOF);
   launch_free_norm_partial(g, v, p->lev[0].mask, p->red, p->stream);
   launch_reduce(1, nb, p->red, p->hcol, 0, p->stream);
   TRY(launch_check(p, "free norm"));
@@ -805,7 +974,7 @@ int compute_residual(mvpf_problem* p, double depth, double* norm_free) {
   Level& L0 = p->lev[0];
   launch_dirichlet_masks(L0.g, p->load, depth, L0.mask, L0.target, p->stream);
   for (const Chunk& ck : make_chunks(L0.g, p->ne_use)) {
-    launch_qp(L0.g, ck, L0.state, p->card, p->pade, p->qp, false, p->stream);
+    launch_qp(L0.g, ck, L0.state, p->card, p->pade, p->mixing, p->qp, false, p->stream);
     launch_residual_gather(L0.g, ck, L0.state, p->qp, p->card, p->R, p->stream);
   }
   if (contact(p)) launch_contact_residual(L0.g, make_sphere(L0.g, p->load, depth), L0.state, p->R, p->stream);
@@ -819,7 +988,7 @@ int compute_residual(mvpf_problem* p, double depth, double* norm_free) {
 void assemble_coarse_level(mvpf_problem* p, int l, double depth) {
   Level& C = p->lev[l];
   for (const Chunk& ck : make_chunks(C.g, p->ne_use)) {
-    launch_qp(C.g, ck, C.state, p->card, p->pade, p->qp, true, p->stream);
+    launch_qp(C.g, ck, C.state, p->card, p->pade, p->mixing, p->qp, true, p->stream);
     launch_element_matrices(C.g, ck, p->qp, p->card, p->elem, p->stream);
     if (contact(p)) launch_contact_element(C.g, ck, make_sphere(C.g, p->load, depth), C.state, p->elem, p->stream);
     launch_jacobian_gather(C.g, ck, p->elem, C.A64, C.A32, C.diag64, p->stream);
@@ -891,9 +1060,9 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
   // finest: residual and unconstrained tangent
   for (const Chunk& ck : make_chunks(L0.g, p->ne_use)) {
     timer_begin(p, p->t_qp);
-    launch_qp(L0.g, ck, L0.state, p->card, p->pade, p->qp, true, s);
+    launch_qp(L0.g, ck, L0.state, p->card, p->pade, p->mixing, p->qp, true, s);
     // written: gradient (15) and packed Hessian (120) per Gauss point
-    timer_end(p, p->t_qp, 8.0 * 8 * 135 * (double)ck.NEc);
+    timer_end(p, p->t_qp, 8.0 * 8 * QP_HESS * (double)ck.NEc);
     const bool mf = use_mf(p);  // only the diagonal blocks are assembled
     if (mf) launch_mf_pack(L0.g, ck, p->qp, p->Dmf64, p->Dmf32, s);
     launch_residual_gather(L0.g, ck, L0.state, p->qp, p->card, p->R, s);
@@ -1010,9 +1179,65 @@ std::vector<int> launch_candidates(const Grid& g) {
   return c;
 }
 
+// Tuning results, reused by later problems of the same shape: keyed by the
+// GPU architecture, the multigrid precision, the finest-level mode, the
+// tuned quantity and the level's element counts.  Process-wide; when the
+// environment variable MVPF_TUNE_CACHE names a file, entries are read from it
+// once and every new entry is appended to it ("key value" lines).
+struct TuneCache {
+  std::mutex mu;
+  std::map<std::string, int> entries;
+  bool loaded = false;
+};
+TuneCache& tune_cache() {
+  static TuneCache c;
+  return c;
+}
+std::string tune_key(const mvpf_problem* p, const char* what, const Grid& g) {
+  hipDeviceProp_t prop;
+  int dev = 0;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  const std::string::size_type c = arch.find(':');
+  if (c != std::string::npos) arch.resize(c);
+  return arch + "/" + (p->mixed ? "mixed" : "fp64") + "/" + (use_mf(p) ? "mf" : "asm") + "/" + what + "/" +
+         std::to_string(g.nx) + "x" + std::to_string(g.ny) + "x" + std::to_string(g.nz);
+}
+bool tune_lookup(const std::string& key, int* value) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  if (!c.loaded) {
+    c.loaded = true;
+    if (const char* path = std::getenv("MVPF_TUNE_CACHE")) {
+      std::ifstream in(path);
+      std::string k;
+      int v;
+      while (in >> k >> v) c.entries[k] = v;
+    }
+  }
+  auto it = c.entries.find(key);
+  if (it == c.entries.end()) return false;
+  *value = it->second;
+  return true;
+}
+void tune_store(const std::string& key, int value) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  c.entries[key] = value;
+  if (const char* path = std::getenv("MVPF_TUNE_CACHE")) {
+    std::ofstream out(path, std::ios::app);
+    out << key << " " << value << "\n";
+  }
+}
+
 template <typename T>
 void autotune_levels(mvpf_problem* p, int* tuned) {
-  if (use_mf(p)) {  // elements per workgroup of the matrix-free smoother sweep
+  const bool cached = p->tune_cache_use != 0;
+  int hit = 0;
+  if (use_mf(p) && cached && tune_lookup(tune_key(p, "mf_epw", p->lev[0].g), &hit)) {
+    p->mf_epw = hit;
+    tuned[0] = hit;
+  } else if (use_mf(p)) {  // elements per workgroup of the matrix-free smoother sweep
     Level& L = p->lev[0];
     double best = 1e30;
     int bestE = 32;
@@ -1027,11 +1252,17 @@ void autotune_levels(mvpf_problem* p, int* tuned) {
     }
     p->mf_epw = bestE;
     tuned[0] = bestE;
+    tune_store(tune_key(p, "mf_epw", L.g), bestE);
   }
   for (int l = 0; l < p->L - 1; ++l) {
     Level& L = p->lev[l];
     if (L.g.N <= p->small_nodes) continue;  // small-grid kernels have a fixed shape
     if (l == 0 && use_mf(p)) continue;      // tuned above
+    if (cached && tune_lookup(tune_key(p, "row_blocks", L.g), &hit)) {
+      p->row_G[l] = hit;
+      tuned[l] = hit;
+      continue;
+    }
     double best = 1e30;
     int bestG = 0;
     for (int G : launch_candidates(L.g)) {
@@ -1043,9 +1274,15 @@ void autotune_levels(mvpf_problem* p, int* tuned) {
     }
     p->row_G[l] = bestG;
     tuned[l] = bestG;
+    tune_store(tune_key(p, "row_blocks", L.g), bestG);
   }
   const Grid& g = p->lev[0].g;
   if (use_mf(p)) return;
+  if (cached && tune_lookup(tune_key(p, "outer_blocks", g), &hit)) {
+    p->outer_G = hit;
+    tuned[p->L - 1] = hit;
+    return;
+  }
   double best = 1e30;
   int bestG = 0;
   for (int G : launch_candidates(g)) {
@@ -1059,6 +1296,7 @@ void autotune_levels(mvpf_problem* p, int* tuned) {
   }
   p->outer_G = bestG;
   tuned[p->L - 1] = bestG;
+  tune_store(tune_key(p, "outer_blocks", g), bestG);
 }
 }  // namespace
 
@@ -1747,12 +1985,14 @@ int batch_assemble(mvpf_batch* b, const double* depths, hipStream_t s) {
     return j;
   };
   auto qp_steps = [&](const std::vector<mvpf_problem*>& ps, const std::vector<AJob>& js) {
-    for (int pd : {11, 22, 33}) {
-      std::vector<AJob> sel;
-      for (size_t k = 0; k < ps.size(); ++k)
-        if (ps[k]->pade == pd || (pd == 22 && ps[k]->pade != 11 && ps[k]->pade != 33)) sel.push_back(js[k]);
-      add(AOP_QP_HESS, pd, sel, {});
-    }
+    for (int mix : {0, 1})
+      for (int pd : {11, 22, 33}) {
+        std::vector<AJob> sel;
+        for (size_t k = 0; k < ps.size(); ++k)
+          if ((ps[k]->pade == pd || (pd == 22 && ps[k]->pade != 11 && ps[k]->pade != 33)) && ps[k]->mixing == mix)
+            sel.push_back(js[k]);
+        add(AOP_QP_HESS, pd + mix * QP_LOG_MIX, sel, {});
+      }
   };
   const int n = b->n;
   int maxL = 0;
@@ -1972,12 +2212,19 @@ void mvpf_default_opts(mvpf_opts* o) {
   o->newton_rtol = 1e-9;
 }
 
+int mvpf_nvar(void) { return NV; }
+
 int mvpf_create(const mvpf_mesh* mesh, const mvpf_material* mat, const mvpf_loading* load, const mvpf_opts* opts,
                 void* stream, mvpf_problem** out) {
   if (!out) return MVPF_EINVAL;
   *out = nullptr;
   std::string err;
   int rc = validate(mesh, mat, load, opts, err);
+  if (!rc && NV != 6) {
+    err = "the six-variant material card needs a library built for six variants (this one has " +
+          std::to_string(NV) + "); use mvpf_create_orbit";
+    rc = MVPF_EINVAL;
+  }
   if (rc) {
     g_create_err = err;
     return rc;
@@ -1985,6 +2232,53 @@ int mvpf_create(const mvpf_mesh* mesh, const mvpf_material* mat, const mvpf_load
   mvpf_problem* p = new mvpf_problem();
   p->mesh = *mesh;
   p->mat = *mat;
+  p->load = *load;
+  p->opts = *opts;
+  p->stream = (hipStream_t)stream;
+  rc = allocate(p);
+  if (rc) {
+    g_create_err = p->err;
+    destroy_all(p);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return 0;
+}
+
+int mvpf_create_orbit(const mvpf_mesh* mesh, const mvpf_orbit_material* om, const mvpf_loading* load,
+                      const mvpf_opts* opts, void* stream, mvpf_problem** out) {
+  if (!out) return MVPF_EINVAL;
+  *out = nullptr;
+  if (!om) {
+    g_create_err = "null argument";
+    return MVPF_EINVAL;
+  }
+  // the checks that do not depend on the kind of card
+  mvpf_material shape{};
+  shape.pade = om->pade;
+  shape.mixing = om->mixing;
+  std::string err;
+  int rc = validate(mesh, &shape, load, opts, err);
+  if (!rc) {
+    DevCard probe;
+    const int n = build_card_orbit(*om, probe);
+    if (n != NV) {
+      err = "the cubic orbit of U1 has " + std::to_string(n) + " variants; this library is built for " +
+            std::to_string(NV);
+      rc = MVPF_EINVAL;
+    }
+  }
+  if (rc) {
+    g_create_err = err;
+    return rc;
+  }
+  mvpf_problem* p = new mvpf_problem();
+  p->mesh = *mesh;
+  p->mat = shape;
+  p->mat.rho = om->rho;
+  p->omat = *om;
+  p->orbit = true;
   p->load = *load;
   p->opts = *opts;
   p->stream = (hipStream_t)stream;
@@ -2039,8 +2333,8 @@ int mvpf_set_state(mvpf_problem* p, const double* u, const double* eta, const do
   if (!p) return MVPF_EINVAL;
   const Grid& g = p->lev[0].g;
   if (u) launch_interleaved_to_soa(g, u, 3, 0, 3, p->lev[0].state, p->stream);
-  if (eta) launch_interleaved_to_soa(g, eta, 6, 3, 6, p->lev[0].state, p->stream);
-  if (eta_prev) launch_interleaved_to_soa(g, eta_prev, 6, 9, 6, p->lev[0].state, p->stream);
+  if (eta) launch_interleaved_to_soa(g, eta, NV, 3, NV, p->lev[0].state, p->stream);
+  if (eta_prev) launch_interleaved_to_soa(g, eta_prev, NV, 3 + NV, NV, p->lev[0].state, p->stream);
   p->depth = depth;
   p->have_system = p->have_solution = false;
   TRY(launch_check(p, "set_state"));
@@ -2052,8 +2346,8 @@ int mvpf_get_state(mvpf_problem* p, double* u, double* eta, double* eta_prev, do
   if (!p) return MVPF_EINVAL;
   const Grid& g = p->lev[0].g;
   if (u) launch_soa_to_interleaved(g, p->lev[0].state, 3, 0, 3, u, p->stream);
-  if (eta) launch_soa_to_interleaved(g, p->lev[0].state, 6, 3, 6, eta, p->stream);
-  if (eta_prev) launch_soa_to_interleaved(g, p->lev[0].state, 6, 9, 6, eta_prev, p->stream);
+  if (eta) launch_soa_to_interleaved(g, p->lev[0].state, NV, 3, NV, eta, p->stream);
+  if (eta_prev) launch_soa_to_interleaved(g, p->lev[0].state, NV, 3 + NV, NV, eta_prev, p->stream);
   if (depth) *depth = p->depth;
   TRY(launch_check(p, "get_state"));
   HIPCHK(hipStreamSynchronize(p->stream));
@@ -2073,7 +2367,7 @@ int mvpf_init_random(mvpf_problem* p, uint64_t seed) {
 int mvpf_residual(mvpf_problem* p, double* R, double* norm_free) {
   if (!p) return MVPF_EINVAL;
   TRY(compute_residual(p, p->have_system ? p->sys_depth : p->depth, norm_free));
-  if (R) launch_soa_to_interleaved(p->lev[0].g, p->R, 9, 0, 9, R, p->stream);
+  if (R) launch_soa_to_interleaved(p->lev[0].g, p->R, NDOF, 0, NDOF, R, p->stream);
   TRY(launch_check(p, "residual"));
   HIPCHK(hipStreamSynchronize(p->stream));
   return 0;
@@ -2092,7 +2386,7 @@ int mvpf_newton_system(mvpf_problem* p, double depth) {
 int mvpf_get_rhs(mvpf_problem* p, double* b) {
   if (!p || !b) return MVPF_EINVAL;
   if (!p->have_system) { p->err = "no Newton system"; return MVPF_ESTATE; }
-  launch_soa_to_interleaved(p->lev[0].g, p->rhs, 9, 0, 9, b, p->stream);
+  launch_soa_to_interleaved(p->lev[0].g, p->rhs, NDOF, 0, NDOF, b, p->stream);
   TRY(launch_check(p, "get_rhs"));
   HIPCHK(hipStreamSynchronize(p->stream));
   return 0;
@@ -2104,7 +2398,7 @@ int mvpf_jacobian_apply(mvpf_problem* p, int level, int precision, const double*
   Level& L = p->lev[level];
   const Grid& g = L.g;
   hipStream_t s = p->stream;
-  launch_interleaved_to_soa(g, x, 9, 0, 9, p->tmp, s);
+  launch_interleaved_to_soa(g, x, NDOF, 0, NDOF, p->tmp, s);
   const bool mf = level == 0 && use_mf(p);
   if (precision == MVPF_FP64) {
     if (mf) {
@@ -2129,7 +2423,7 @@ int mvpf_jacobian_apply(mvpf_problem* p, int level, int precision, const double*
   } else {
     return MVPF_EINVAL;
   }
-  launch_soa_to_interleaved(g, p->tmp2, 9, 0, 9, y, s);
+  launch_soa_to_interleaved(g, p->tmp2, NDOF, 0, NDOF, y, s);
   TRY(launch_check(p, "jacobian_apply"));
   HIPCHK(hipStreamSynchronize(s));
   return 0;
@@ -2139,12 +2433,12 @@ int mvpf_precondition(mvpf_problem* p, const double* v, double* z) {
   if (!p || !v || !z) return MVPF_EINVAL;
   if (!p->have_system) { p->err = "no Newton system"; return MVPF_ESTATE; }
   const Grid& g = p->lev[0].g;
-  launch_interleaved_to_soa(g, v, 9, 0, 9, p->tmp, p->stream);
+  launch_interleaved_to_soa(g, v, NDOF, 0, NDOF, p->tmp, p->stream);
   if (p->mixed)
     precondition<float, double>(p, p->tmp, p->tmp2);
   else
     precondition<double, double>(p, p->tmp, p->tmp2);
-  launch_soa_to_interleaved(g, p->tmp2, 9, 0, 9, z, p->stream);
+  launch_soa_to_interleaved(g, p->tmp2, NDOF, 0, NDOF, z, p->stream);
   TRY(launch_check(p, "precondition"));
   HIPCHK(hipStreamSynchronize(p->stream));
   return 0;
@@ -2158,13 +2452,13 @@ int mvpf_solve(mvpf_problem* p, const double* b, double* x, mvpf_solve_stats* st
   const Grid& g = p->lev[0].g;
   const double* bb = p->rhs;
   if (b) {
-    launch_interleaved_to_soa(g, b, 9, 0, 9, p->tmp2, p->stream);
+    launch_interleaved_to_soa(g, b, NDOF, 0, NDOF, p->tmp2, p->stream);
     bb = p->tmp2;
   }
   int rc = solve_internal(p, bb, p->dx, st);
   if (rc < 0) return rc;
   if (x) {
-    launch_soa_to_interleaved(g, p->dx, 9, 0, 9, x, p->stream);
+    launch_soa_to_interleaved(g, p->dx, NDOF, 0, NDOF, x, p->stream);
     TRY(launch_check(p, "solve output"));
     HIPCHK(hipStreamSynchronize(p->stream));
   }
@@ -2184,6 +2478,15 @@ int mvpf_newton_update(mvpf_problem* p) {
   p->have_solution = false;
   p->have_system = false;
   return 0;
+}
+
+int mvpf_newton_step(mvpf_problem* p, double depth, mvpf_solve_stats* stats) {
+  if (!p) return MVPF_EINVAL;
+  TRY(mvpf_newton_system(p, depth));
+  const int rc = mvpf_solve(p, nullptr, nullptr, stats);
+  if (rc < 0) return rc;
+  TRY(mvpf_newton_update(p));
+  return rc;
 }
 
 }  // extern "C"
@@ -2267,8 +2570,8 @@ int newton_attempt(mvpf_problem* p, double trial, mvpf_step_stats* st, int* its,
   HIPCHK(hipMemcpyAsync(p->save_state, L0.state, sbytes, hipMemcpyDeviceToDevice, p->stream));
   const int rc = newton_iterate(p, trial, st, its, ok, ev);
   if (rc == 0 && *ok) {
-    HIPCHK(hipMemcpyAsync(L0.state + (int64_t)9 * L0.g.Npad, L0.state + (int64_t)3 * L0.g.Npad,
-                          sizeof(double) * 6 * L0.g.Npad, hipMemcpyDeviceToDevice, p->stream));
+    HIPCHK(hipMemcpyAsync(L0.state + (int64_t)(3 + NV) * L0.g.Npad, L0.state + (int64_t)3 * L0.g.Npad,
+                          sizeof(double) * NV * L0.g.Npad, hipMemcpyDeviceToDevice, p->stream));
     p->depth = trial;
   } else {
     *ok = false;
@@ -2296,8 +2599,9 @@ int newton_attempt(mvpf_problem* p, double trial, mvpf_step_stats* st, int* its,
 // viscous coefficient rho of the material card (time-step dependent)
 int set_rho(mvpf_problem* p, double rho) {
   p->mat.rho = rho;
+  p->omat.rho = rho;
   DevCard hc;
-  build_card(p->mat, hc);
+  make_card(p, hc);
   HIPCHK(hipStreamSynchronize(p->stream));
   HIPCHK(hipMemcpy(p->card, &hc, sizeof(DevCard), hipMemcpyHostToDevice));
   return 0;
@@ -2381,7 +2685,7 @@ int mvpf_indent(mvpf_problem* p, const mvpf_indent_opts* o, mvpf_indent_callback
     p->err = "bad indentation options";
     return MVPF_EINVAL;
   }
-  const double rho0 = p->mat.rho;
+  const double rho0 = p->orbit ? p->omat.rho : p->mat.rho;
   double dd = o->dd_init;
   const double goals[2] = {o->depth_max, 0.0};
   int rc = 0, rejected = 0;
@@ -2454,6 +2758,9 @@ int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value) {
     p->small_nodes = value;
   } else if (!std::strcmp(key, "coarse_overlap")) {
     p->coarse_overlap = value;
+  } else if (!std::strcmp(key, "autotune_cache")) {
+    if (value > 1) { p->err = "autotune_cache is 0 or 1"; return MVPF_EINVAL; }
+    p->tune_cache_use = value;
   } else if (!std::strcmp(key, "mf_elements_per_block")) {
     if (value != 8 && value != 16 && value != 32) { p->err = "mf_elements_per_block is 8, 16 or 32"; return MVPF_EINVAL; }
     p->mf_epw = value;
@@ -2467,6 +2774,7 @@ int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value) {
     p->ne_use = value == 0 ? p->ne_cap : value;
   } else if (!std::strcmp(key, "matrix_free")) {
     if (value > 1 || (value && p->L < 2)) { p->err = "matrix_free is 0 or 1 (and needs two levels)"; return MVPF_EINVAL; }
+    if (value && !MF_AVAILABLE) { p->err = "the matrix-free finest level exists for six variants only"; return MVPF_EINVAL; }
     Level& L0 = p->lev[0];
     if (value && !p->Dmf64) {
       TRY(dalloc(p, &p->Dmf64, mf_hessian_values(L0.g)));
@@ -2500,6 +2808,8 @@ int mvpf_get_tuning(const mvpf_problem* p, const char* key, int level, int* valu
     *value = p->mf;
   } else if (!std::strcmp(key, "mf_elements_per_block")) {
     *value = p->mf_epw;
+  } else if (!std::strcmp(key, "autotune_cache")) {
+    *value = p->tune_cache_use;
   } else if (!std::strcmp(key, "coarse_overlap")) {
     const int nd = p->lev[p->L - 1].ndense;
     *value = p->coarse_overlap < 0 ? (nd <= COARSE_OVERLAP_MAX ? 1 : 0) : (p->coarse_overlap != 0);

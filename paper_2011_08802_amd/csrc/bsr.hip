@@ -48,30 +48,30 @@ inline int row_grid(const Grid& g, int G) {
 //    (u, m) has exactly one writer; lanes write consecutive m);
 //  pass 2 (row m): acc_m (-)= sum_u C[u-1][.][m] over the in-grid lower
 //    neighbours, then the kernel's epilogue (defect, Jacobi update, product).
-// C holds 13 * 9 * Npad values of the accumulation type.
+// C holds 13 * NDOF * Npad values of the accumulation type.
 // Stored blocks u0 .. u1 - 1 of row n (see upper_pass).
 template <bool SUB, typename TA, typename TX, typename TC>
 __device__ __forceinline__ void upper_range(const Grid& g, const TA* __restrict__ A, const TX* __restrict__ x, int n,
-                                            int u0, int u1, TC acc[9], TC* __restrict__ C) {
+                                            int u0, int u1, TC acc[NDOF], TC* __restrict__ C) {
   const int t = n >> 6, l = n & 63;
   const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
-  TC xn[9];
+  TC xn[NDOF];
 #pragma unroll
-  for (int c = 0; c < 9; ++c) xn[c] = (TC)x[(int64_t)c * g.Npad + n];
+  for (int c = 0; c < NDOF; ++c) xn[c] = (TC)x[(int64_t)c * g.Npad + n];
 #pragma unroll 1
   for (int u = u0; u < u1; ++u) {
     const int s = 13 + u;
     const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
     if (!((i + dx >= 0) && (i + dx < g.nnx) && (j + dy >= 0) && (j + dy < g.nny) && (k + dz < g.nnz))) continue;
     const int m = n + dx + g.nnx * (dy + g.nny * dz);
-    TC xv[9];
+    TC xv[NDOF];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) xv[c] = (TC)x[(int64_t)c * g.Npad + m];
+    for (int c = 0; c < NDOF; ++c) xv[c] = (TC)x[(int64_t)c * g.Npad + m];
     using VT = typename Vec16<TA>::type;
     constexpr int V = Lay<TA>::V;
     const VT* Ab = reinterpret_cast<const VT*>(A + ((int64_t)t * NUP + u) * Lay<TA>::SLICE) + l;
-    TC ct[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    TC sum[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    TC ct[NDOF] = {};
+    TC sum[NDOF] = {};
 #pragma unroll
     for (int q = 0; q < Lay<TA>::NQ; ++q) {
       const VT vq = Ab[q * TILE];
@@ -81,7 +81,7 @@ __device__ __forceinline__ void upper_range(const Grid& g, const TA* __restrict_
       for (int v = 0; v < V; ++v) {
         const int e = q * V + v;
         if (e < NBLK) {
-          const int r = e / 9, c = e % 9;
+          const int r = e / NDOF, c = e % NDOF;
           const TC a = (TC)av[v];
           sum[r] += a * xv[c];
           ct[c] += a * xn[r];
@@ -89,13 +89,13 @@ __device__ __forceinline__ void upper_range(const Grid& g, const TA* __restrict_
       }
     }
 #pragma unroll
-    for (int r = 0; r < 9; ++r) {
+    for (int r = 0; r < NDOF; ++r) {
       if (SUB) acc[r] -= sum[r]; else acc[r] += sum[r];
     }
     if (u > 0) {
-      TC* Cu = C + (int64_t)(u - 1) * 9 * g.Npad + m;
+      TC* Cu = C + (int64_t)(u - 1) * NDOF * g.Npad + m;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) Cu[(int64_t)c * g.Npad] = ct[c];
+      for (int c = 0; c < NDOF; ++c) Cu[(int64_t)c * g.Npad] = ct[c];
     }
   }
 }
@@ -108,27 +108,27 @@ constexpr int USPLIT = 7;
 
 template <bool SUB, typename TA, typename TX, typename TC>
 __device__ __forceinline__ void upper_pass(const Grid& g, const TA* __restrict__ A, const TX* __restrict__ x, int n,
-                                           TC acc[9], TC* __restrict__ C) {
+                                           TC acc[NDOF], TC* __restrict__ C) {
   upper_range<SUB>(g, A, x, n, 0, USPLIT, acc, C);
-  TC p1[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  TC p1[NDOF] = {};
   upper_range<false>(g, A, x, n, USPLIT, NUP, p1, C);
 #pragma unroll
-  for (int r = 0; r < 9; ++r) {
+  for (int r = 0; r < NDOF; ++r) {
     if (SUB) acc[r] -= p1[r]; else acc[r] += p1[r];
   }
 }
 
 template <bool SUB, typename TC>
-__device__ __forceinline__ void lower_pass(const Grid& g, int m, TC acc[9], const TC* __restrict__ C) {
+__device__ __forceinline__ void lower_pass(const Grid& g, int m, TC acc[NDOF], const TC* __restrict__ C) {
   const int i = m % g.nnx, j = (m / g.nnx) % g.nny, k = m / (g.nnx * g.nny);
 #pragma unroll
   for (int u = 1; u < NUP; ++u) {
     const int s = 13 + u;
     const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
     if (!((i - dx >= 0) && (i - dx < g.nnx) && (j - dy >= 0) && (j - dy < g.nny) && (k - dz >= 0))) continue;
-    const TC* Cu = C + (int64_t)(u - 1) * 9 * g.Npad + m;
+    const TC* Cu = C + (int64_t)(u - 1) * NDOF * g.Npad + m;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
+    for (int c = 0; c < NDOF; ++c) {
       if (SUB) acc[c] -= Cu[(int64_t)c * g.Npad]; else acc[c] += Cu[(int64_t)c * g.Npad];
     }
   }
@@ -140,10 +140,10 @@ __global__ void __launch_bounds__(256) spmv_upper_kernel(Grid g, const TA* __res
                                                          TY* __restrict__ y, TY* __restrict__ C) {
   ROW_LOOP(g) {
     if (n >= g.Npad) continue;
-    TY acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    TY acc[NDOF] = {};
     if (n < g.N) upper_pass<false>(g, A, x, n, acc, C);
 #pragma unroll
-    for (int r = 0; r < 9; ++r) y[(int64_t)r * g.Npad + n] = acc[r];
+    for (int r = 0; r < NDOF; ++r) y[(int64_t)r * g.Npad + n] = acc[r];
   }
 }
 
@@ -151,12 +151,12 @@ template <typename TY>
 __global__ void __launch_bounds__(256) spmv_lower_kernel(Grid g, TY* __restrict__ y, const TY* __restrict__ C) {
   ROW_LOOP(g) {
     if (n >= g.N) continue;
-    TY acc[9];
+    TY acc[NDOF];
 #pragma unroll
-    for (int r = 0; r < 9; ++r) acc[r] = y[(int64_t)r * g.Npad + n];
+    for (int r = 0; r < NDOF; ++r) acc[r] = y[(int64_t)r * g.Npad + n];
     lower_pass<false>(g, n, acc, C);
 #pragma unroll
-    for (int r = 0; r < 9; ++r) y[(int64_t)r * g.Npad + n] = acc[r];
+    for (int r = 0; r < NDOF; ++r) y[(int64_t)r * g.Npad + n] = acc[r];
   }
 }
 
@@ -174,21 +174,21 @@ template <typename TA, typename TX, typename TY>
 __global__ void __launch_bounds__(256) spmv_upper_split_kernel(Grid g, const TA* __restrict__ A,
                                                                const TX* __restrict__ x, TY* __restrict__ y,
                                                                TY* __restrict__ C) {
-  __shared__ TY sh[2][9][64];
+  __shared__ TY sh[2][NDOF][64];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, tl = w >> 1, half = w & 1;
   const int t = split_tile(blockIdx.x, gridDim.x) + tl;
   const int n = t * TILE + l;
   const bool valid = t < g.ntiles;
-  TY acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  TY acc[NDOF] = {};
   if (valid && n < g.N) upper_range<false>(g, A, x, n, half ? USPLIT : 0, half ? NUP : USPLIT, acc, C);
   if (half) {
 #pragma unroll
-    for (int r = 0; r < 9; ++r) sh[tl][r][l] = acc[r];
+    for (int r = 0; r < NDOF; ++r) sh[tl][r][l] = acc[r];
   }
   __syncthreads();
   if (!half && valid) {
 #pragma unroll
-    for (int r = 0; r < 9; ++r) y[(int64_t)r * g.Npad + n] = acc[r] + sh[tl][r][l];
+    for (int r = 0; r < NDOF; ++r) y[(int64_t)r * g.Npad + n] = acc[r] + sh[tl][r][l];
   }
 }
 
@@ -217,12 +217,12 @@ __global__ void __launch_bounds__(256) defect_upper_kernel(Grid g, const T* __re
                                                            T* __restrict__ C) {
   ROW_LOOP(g) {
     if (n >= g.Npad) continue;
-    T acc[9];
+    T acc[NDOF];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) acc[c] = b[(int64_t)c * g.Npad + n];
+    for (int c = 0; c < NDOF; ++c) acc[c] = b[(int64_t)c * g.Npad + n];
     if (n < g.N) upper_pass<true>(g, A, x, n, acc, C);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) r[(int64_t)c * g.Npad + n] = (n < g.N) ? acc[c] : (T)0;
+    for (int c = 0; c < NDOF; ++c) r[(int64_t)c * g.Npad + n] = (n < g.N) ? acc[c] : (T)0;
   }
 }
 
@@ -231,12 +231,12 @@ __device__ __forceinline__ void defect_lower_body(const Grid& g, T* __restrict__
                                                   int nblk) {
   ROW_LOOP_B(g, bid, nblk) {
     if (n >= g.N) continue;
-    T acc[9];
+    T acc[NDOF];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) acc[c] = r[(int64_t)c * g.Npad + n];
+    for (int c = 0; c < NDOF; ++c) acc[c] = r[(int64_t)c * g.Npad + n];
     lower_pass<true>(g, n, acc, C);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) r[(int64_t)c * g.Npad + n] = acc[c];
+    for (int c = 0; c < NDOF; ++c) r[(int64_t)c * g.Npad + n] = acc[c];
   }
 }
 template <typename T>
@@ -248,15 +248,15 @@ template <typename T>
 __device__ __forceinline__ void defect_upper_split_body(const Grid& g, const T* __restrict__ A,
                                                         const T* __restrict__ x, const T* __restrict__ b,
                                                         T* __restrict__ r, T* __restrict__ C, int bid, int nblk) {
-  __shared__ T sh[2][9][64];
+  __shared__ T sh[2][NDOF][64];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, tl = w >> 1, half = w & 1;
   const int t = split_tile(bid, nblk) + tl;
   const int n = t * TILE + l;
   const bool valid = t < g.ntiles;
-  T acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  T acc[NDOF] = {};
   if (valid && !half) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) acc[c] = b[(int64_t)c * g.Npad + n];
+    for (int c = 0; c < NDOF; ++c) acc[c] = b[(int64_t)c * g.Npad + n];
   }
   if (valid && n < g.N) {
     if (half)
@@ -266,12 +266,12 @@ __device__ __forceinline__ void defect_upper_split_body(const Grid& g, const T* 
   }
   if (half) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) sh[tl][c][l] = acc[c];
+    for (int c = 0; c < NDOF; ++c) sh[tl][c][l] = acc[c];
   }
   __syncthreads();
   if (!half && valid) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) r[(int64_t)c * g.Npad + n] = (n < g.N) ? acc[c] - sh[tl][c][l] : (T)0;
+    for (int c = 0; c < NDOF; ++c) r[(int64_t)c * g.Npad + n] = (n < g.N) ? acc[c] - sh[tl][c][l] : (T)0;
   }
 }
 template <typename T>
@@ -305,14 +305,14 @@ __device__ __forceinline__ void pbj_zero_body(const Grid& g, const T* __restrict
     if (n >= g.Npad) continue;
     const int t = n >> 6, l = n & 63;
     const T* Db = Dinv + (int64_t)t * Lay<T>::SLICE;
-    T bv[9];
+    T bv[NDOF];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) bv[c] = b[(int64_t)c * g.Npad + n];
+    for (int c = 0; c < NDOF; ++c) bv[c] = b[(int64_t)c * g.Npad + n];
 #pragma unroll
-    for (int r = 0; r < 9; ++r) {
+    for (int r = 0; r < NDOF; ++r) {
       T s = 0;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) s += Db[Lay<T>::off(r * 9 + c, l)] * bv[c];
+      for (int c = 0; c < NDOF; ++c) s += Db[Lay<T>::off(r * NDOF + c, l)] * bv[c];
       xo[(int64_t)r * g.Npad + n] = (n < g.N) ? omega * s : (T)0;
     }
   }
@@ -329,17 +329,17 @@ __device__ __forceinline__ void pbj_lower_body(const Grid& g, const T* __restric
                                                int nblk) {
   ROW_LOOP_B(g, bid, nblk) {
     if (n >= g.N) continue;
-    T res[9];
+    T res[NDOF];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) res[c] = xo[(int64_t)c * g.Npad + n];
+    for (int c = 0; c < NDOF; ++c) res[c] = xo[(int64_t)c * g.Npad + n];
     lower_pass<true>(g, n, res, C);
     const int t = n >> 6, l = n & 63;
     const T* Db = Dinv + (int64_t)t * Lay<T>::SLICE;
 #pragma unroll
-    for (int r = 0; r < 9; ++r) {
+    for (int r = 0; r < NDOF; ++r) {
       T s = 0;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) s += Db[Lay<T>::off(r * 9 + c, l)] * res[c];
+      for (int c = 0; c < NDOF; ++c) s += Db[Lay<T>::off(r * NDOF + c, l)] * res[c];
       xo[(int64_t)r * g.Npad + n] = x[(int64_t)r * g.Npad + n] + omega * s;
     }
   }
@@ -381,38 +381,38 @@ template <typename T, bool PBJ>
 __device__ __forceinline__ void row_small_body(const Grid& g, const T* __restrict__ A, const T* __restrict__ Dinv,
                                                const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ out,
                                                T omega, int bid) {
-  __shared__ T part[SMALL_ROWS][NSTEN][9];
-  __shared__ T res[SMALL_ROWS][9];
+  __shared__ T part[SMALL_ROWS][NSTEN][NDOF];
+  __shared__ T res[SMALL_ROWS][NDOF];
   const int tid = threadIdx.x;
   const int s = tid / SMALL_ROWS, ln = tid % SMALL_ROWS;
   const int n = bid * SMALL_ROWS + ln;
-  T pr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  T pr[NDOF] = {};
   if (tid < SMALL_ROWS * NSTEN && n < g.N) {
     const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
     const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
     if (i + dx >= 0 && i + dx < g.nnx && j + dy >= 0 && j + dy < g.nny && k + dz >= 0 && k + dz < g.nnz) {
       const int m = n + dx + g.nnx * (dy + g.nny * dz);
-      T xv[9];
+      T xv[NDOF];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) xv[c] = x[(int64_t)c * g.Npad + m];
+      for (int c = 0; c < NDOF; ++c) xv[c] = x[(int64_t)c * g.Npad + m];
       if (s >= 13) {
         const T* Ab = A + ((int64_t)(n >> 6) * NUP + (s - 13)) * Lay<T>::SLICE;
         const int ll = n & 63;
 #pragma unroll
-        for (int r = 0; r < 9; ++r) {
+        for (int r = 0; r < NDOF; ++r) {
           T acc = 0;
 #pragma unroll
-          for (int c = 0; c < 9; ++c) acc += Ab[Lay<T>::off(r * 9 + c, ll)] * xv[c];
+          for (int c = 0; c < NDOF; ++c) acc += Ab[Lay<T>::off(r * NDOF + c, ll)] * xv[c];
           pr[r] = acc;
         }
       } else {
         const T* Ab = A + ((int64_t)(m >> 6) * NUP + (13 - s)) * Lay<T>::SLICE;
         const int ll = m & 63;
 #pragma unroll
-        for (int r = 0; r < 9; ++r) {
+        for (int r = 0; r < NDOF; ++r) {
           T acc = 0;
 #pragma unroll
-          for (int c = 0; c < 9; ++c) acc += Ab[Lay<T>::off(c * 9 + r, ll)] * xv[c];
+          for (int c = 0; c < NDOF; ++c) acc += Ab[Lay<T>::off(c * NDOF + r, ll)] * xv[c];
           pr[r] = acc;
         }
       }
@@ -420,11 +420,11 @@ __device__ __forceinline__ void row_small_body(const Grid& g, const T* __restric
   }
   if (tid < SMALL_ROWS * NSTEN)
 #pragma unroll
-    for (int r = 0; r < 9; ++r) part[ln][s][r] = pr[r];
+    for (int r = 0; r < NDOF; ++r) part[ln][s][r] = pr[r];
   __syncthreads();
-  const int ln2 = tid / 9, r2 = tid % 9;
+  const int ln2 = tid / NDOF, r2 = tid % NDOF;
   const int n2 = bid * SMALL_ROWS + ln2;
-  const bool own = tid < SMALL_ROWS * 9 && n2 < g.N;
+  const bool own = tid < SMALL_ROWS * NDOF && n2 < g.N;
   if (own) {
     T acc = b[(int64_t)r2 * g.Npad + n2];
     for (int ss = 0; ss < NSTEN; ++ss) acc -= part[ln2][ss][r2];
@@ -438,7 +438,7 @@ __device__ __forceinline__ void row_small_body(const Grid& g, const T* __restric
       const T* Db = Dinv + (int64_t)(n2 >> 6) * Lay<T>::SLICE;
       T acc = 0;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) acc += Db[Lay<T>::off(r2 * 9 + c, n2 & 63)] * res[ln2][c];
+      for (int c = 0; c < NDOF; ++c) acc += Db[Lay<T>::off(r2 * NDOF + c, n2 & 63)] * res[ln2][c];
       out[(int64_t)r2 * g.Npad + n2] = x[(int64_t)r2 * g.Npad + n2] + omega * acc;
     }
   }

@@ -10,13 +10,13 @@
 
 namespace mvpf {
 
-// one thread per (node, stored block, block row): the 9 entries of that row
+// one thread per (node, stored block, block row): the NDOF entries of that row
 // and, for off-diagonal blocks, their transposes (the lower half)
 __global__ void __launch_bounds__(256) dense_from_bsr_kernel(Grid g, const double* __restrict__ A,
                                                              double* __restrict__ D) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= g.N * NUP * 9) return;
-  const int r = idx % 9, u = (idx / 9) % NUP, n = idx / (9 * NUP);
+  if (idx >= g.N * NUP * NDOF) return;
+  const int r = idx % NDOF, u = (idx / NDOF) % NUP, n = idx / (NDOF * NUP);
   const int64_t nd = (int64_t)NDOF * g.N;
   const int t = n >> 6, l = n & 63;
   const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
@@ -26,8 +26,8 @@ __global__ void __launch_bounds__(256) dense_from_bsr_kernel(Grid g, const doubl
   const int m = n + dx + g.nnx * (dy + g.nny * dz);
   const double* Ab = A + (int64_t)(t * NUP + u) * Lay<double>::SLICE;
 #pragma unroll
-  for (int c = 0; c < 9; ++c) {
-    const double v = Ab[Lay<double>::off(r * 9 + c, l)];
+  for (int c = 0; c < NDOF; ++c) {
+    const double v = Ab[Lay<double>::off(r * NDOF + c, l)];
     D[((int64_t)r * g.N + n) * nd + (int64_t)c * g.N + m] = v;
     if (u > 0) D[((int64_t)c * g.N + m) * nd + (int64_t)r * g.N + n] = v;  // lower half by symmetry
   }
@@ -41,7 +41,7 @@ __global__ void zero_kernel_d(int64_t n, double* p) {
 void launch_dense_from_bsr(const Grid& g, const double* A64, double* dense, hipStream_t s) {
   const int64_t nd = (int64_t)NDOF * g.N;
   zero_kernel_d<<<1024, 256, 0, s>>>(nd * nd, dense);
-  dense_from_bsr_kernel<<<(g.N * NUP * 9 + 255) / 256, 256, 0, s>>>(g, A64, dense);
+  dense_from_bsr_kernel<<<(g.N * NUP * NDOF + 255) / 256, 256, 0, s>>>(g, A64, dense);
 }
 
 // Two-level blocked Gauss-Jordan inversion with partial pivoting.

@@ -2,13 +2,14 @@
 //
 // Data layout in HBM:
 //  * vectors: structure-of-arrays, component-major: v[c * Npad + n] for the
-//    9 unknowns c of node n; Npad = N rounded up to 64; padding is kept 0.
-//  * state:   15 FP64 components [u_x,u_y,u_z, eta_1..6, eta_n_1..6] in the
+//    NDOF = 3 + N unknowns c of node n (N variants: 9 for N = 6, 15 for
+//    N = 12); Npad = N rounded up to 64; padding is kept 0.
+//  * state:   3 + 2N FP64 components [u_x,u_y,u_z, eta_1..N, eta_n_1..N] in the
 //    same SoA layout.
-//  * 9x9 block operators on the structured 27-point stencil, symmetric half
+//  * NDOF x NDOF block operators on the structured 27-point stencil, symmetric half
 //    storage, tiled: slice (t, u) = A + (t * 14 + u) * Lay<T>::SLICE holds the
 //    block coupling node n = 64 t + l with its neighbour n + off(13 + u); entry
-//    e = 9*row + col of lane l sits at Lay<T>::off(e, l), i.e. each lane's
+//    e = NDOF*row + col of lane l sits at Lay<T>::off(e, l), i.e. each lane's
 //    entries come in groups of V = 16 / sizeof(T) (one 16-byte load), and the
 //    64 lanes' groups are contiguous (one 1 KB coalesced wavefront load).
 //    s = (dz+1)*9 + (dy+1)*3 + (dx+1) numbers the 27
@@ -34,8 +35,8 @@
 
 namespace mvpf {
 
-constexpr int NDOF = 9;
-constexpr int NSTATE = 15;
+constexpr int NDOF = 3 + NV;         // unknowns per node: u (3), eta_hat (N)
+constexpr int NSTATE = 3 + 2 * NV;   // state per node: u, eta_hat, eta_hat_n
 constexpr int NSTEN = 27;
 constexpr int NUP = 14;              // stored stencil blocks per row (diagonal + 13 upper)
 
@@ -63,10 +64,15 @@ __device__ __forceinline__ double read_lane(double v, int lane) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 constexpr int NPAIR = 36;            // element node pairs a <= b
-constexpr int NBLK = 81;
+constexpr int NBLK = NDOF * NDOF;
 constexpr int TILE = 64;
-constexpr int QP_GRAD = 15;          // gradient components per Gauss point
-constexpr int QP_HESS = 15 + 120;    // gradient + packed Hessian
+constexpr int QP_GRAD = NQ;          // gradient components per Gauss point
+constexpr int QP_HESS = NQ + NHP;    // gradient + packed Hessian
+// packed Hessian entries rounded up to whole 8-component groups: the
+// element-matrix kernel stages them 8 at a time, so the Gauss-point buffer
+// holds NQ + NHP_PAD components (the padding is never used)
+constexpr int NHP_PAD = (NHP + 7) / 8 * 8;
+constexpr int QP_HESS_ALLOC = NQ + NHP_PAD;
 constexpr int MAX_LEVELS = 8;
 constexpr int MAX_RESTART = 64;
 constexpr int SMALL_GRID_NODES = 10000;  // default size limit of the small-grid kernels
@@ -112,9 +118,9 @@ __host__ __device__ constexpr int pair_index(int a, int b) { return a * 8 - (a *
 template <typename T>
 __host__ __device__ inline int64_t mf_index(int64_t NEpad, int k, int g, int64_t e) {
   constexpr int V = 16 / (int)sizeof(T);
-  return ((((e >> 3) * (120 / V) + k / V) * 64) + g * 8 + (e & 7)) * V + k % V;
+  return ((((e >> 3) * (NHP / V) + k / V) * 64) + g * 8 + (e & 7)) * V + k % V;
 }
-__host__ __device__ inline int64_t eo_index(int a, int c, int64_t n, int64_t Npad) { return (int64_t)(a * 9 + c) * Npad + n; }
+__host__ __device__ inline int64_t eo_index(int a, int c, int64_t n, int64_t Npad) { return (int64_t)(a * NDOF + c) * Npad + n; }
 
 // Rigid spherical indenter: centre (cx, cy, cz), radius R, contact penalty eps.
 struct Sphere {
@@ -140,12 +146,12 @@ struct Vec16<double> { typedef double2 type; };
 
 struct Level {
   Grid g;
-  double* state = nullptr;    // [15][Npad]
+  double* state = nullptr;    // [NSTATE][Npad]
   uint16_t* mask = nullptr;   // [Npad] constrained-dof bits (bit c = dof c)
   double* target = nullptr;   // [Npad] prescribed u_z on the top face (finest only)
   double* A64 = nullptr;      // FP64 operator (finest; every level in FP64 mode)
   float* A32 = nullptr;       // FP32 operator (mixed mode, all but coarsest)
-  double* diag64 = nullptr;   // FP64 diagonal blocks [ntiles][81][64]
+  double* diag64 = nullptr;   // FP64 diagonal blocks [ntiles][NBLK][64]
   double* Dinv64 = nullptr;   // FP64 block inverses (FP64 mode)
   float* Dinv32 = nullptr;    // FP32 block inverses (mixed mode)
   // work vectors of the V-cycle (type per precision mode), [9][Npad]
@@ -182,7 +188,9 @@ constexpr int64_t ASSEMBLY_SLAB_BYTES = (int64_t)40 << 30;
 
 struct mvpf_problem {
   mvpf_mesh mesh;
-  mvpf_material mat;
+  mvpf_material mat;                 // six-variant card (orbit == false)
+  mvpf_orbit_material omat;          // card from one stretch tensor's cubic orbit (orbit == true)
+  bool orbit = false;
   mvpf_loading load;
   mvpf_opts opts;
   int restart_cap = 0;
@@ -193,13 +201,14 @@ struct mvpf_problem {
   mvpf::Level lev[mvpf::MAX_LEVELS];
   mvpf::DevCard* card = nullptr;     // device copy
   int pade = 22;                     // Pade order of the Hencky strain (11, 22, 33)
+  int mixing = 0;                    // MVPF_MIX_LINEAR or MVPF_MIX_LOG
   double* qp = nullptr;              // per-Gauss-point scratch (finest size)
   double* elem = nullptr;            // element matrices, upper node pairs (finest size)
-  void* Cbuf = nullptr;              // lower-half contributions, 13 * 9 * Npad doubles (finest size)
+  void* Cbuf = nullptr;              // lower-half contributions, 13 * NDOF * Npad doubles (finest size)
   // matrix-free finest level (tuning key "matrix_free"): Gauss-point Hessians
   // in the matrix-free layout, FP64 (outer product, FP64 mode) and FP32
   // (mixed-mode smoother); element outputs go to Cbuf
-  int mf = 1;
+  int mf = mvpf::NV == 6 ? 1 : 0;    // the matrix-free finest level exists for six variants
   int mf_epw = 32;                   // elements per workgroup of the matrix-free element kernel (8, 16, 32)
   double* Dmf64 = nullptr;
   float* Dmf32 = nullptr;
@@ -226,6 +235,7 @@ struct mvpf_problem {
   int row_G[mvpf::MAX_LEVELS] = {0};  // launch shape of the smoother/defect kernels per level
   int outer_G = 0;                     // launch shape of the outer FP64 operator product
   int small_nodes = mvpf::SMALL_GRID_NODES;  // levels up to this size use the small-grid kernels
+  int tune_cache_use = 1;                    // mvpf_autotune reuses results for the same shapes
   mvpf::KernelTimer t_sweep, t_outer, t_resid, t_qp;
   // the coarsest-level inversion runs on a second stream (default priority),
   // overlapping the assembly of the finer levels
@@ -243,8 +253,8 @@ namespace mvpf {
 
 // ---- launchers (all asynchronous on `s`) ----------------------------------
 // quadrature / assembly
-void launch_qp(const Grid& g, const Chunk& ck, const double* state, const DevCard* cd, int pade, double* qp,
-               bool hess, hipStream_t s);
+void launch_qp(const Grid& g, const Chunk& ck, const double* state, const DevCard* cd, int pade, int mixing,
+               double* qp, bool hess, hipStream_t s);
 void launch_residual_gather(const Grid& g, const Chunk& ck, const double* state, const double* qp, const DevCard* cd,
                             double* R, hipStream_t s);
 // diag_only: only the 8 diagonal node pairs / the diagonal blocks (the
@@ -270,7 +280,8 @@ void launch_contact_load(const Grid& g, const Sphere& sp, const double* state, d
 template <typename T, typename TX>
 void launch_contact_apply(const Grid& g, const Sphere* sp, const double* state, const uint16_t* mask, const TX* x, T* E,
                           hipStream_t s);
-// matrix-free finest level (mf.hip)
+// matrix-free finest level (mf.hip): laid out for the six-variant card
+constexpr bool MF_AVAILABLE = NV == 6;
 size_t mf_hessian_values(const Grid& g);
 void launch_mf_pack(const Grid& g, const Chunk& ck, const double* qp, double* D64, float* D32, hipStream_t s);
 template <typename TD, typename TX, typename T>
@@ -456,8 +467,9 @@ struct AJob {
   int npair, nblocks, nup;   // pairs of the element matrices; gather blocks
   int block0, nblk;
 };
+constexpr int QP_LOG_MIX = 1000;  // added to the Pade order of a batched Hessian launch: logarithmic mixing
 enum AssemblyOp {
-  AOP_QP_HESS,        // Gauss-point gradients and Hessians (Pade order: the launch's template)
+  AOP_QP_HESS,        // Gauss-point gradients and Hessians (Pade order, + QP_LOG_MIX for log mixing)
   AOP_ELEMENT,        // element matrices (npair pairs)
   AOP_GATHER,         // stored blocks (nup per tile; A64 / A32 null: diagonal only)
   AOP_DIRICHLET,      // symmetric elimination on the stored blocks

@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(256) contact_element_kernel(Grid g, Chunk ck, 
 #pragma unroll
       for (int i3 = 0; i3 < 3; ++i3)
 #pragma unroll
-        for (int k3 = 0; k3 < 3; ++k3) Ep[(int64_t)(9 * i3 + k3) * ck.NEcpad] += K[SI(i3, k3)];
+        for (int k3 = 0; k3 < 3; ++k3) Ep[(int64_t)(NDOF * i3 + k3) * ck.NEcpad] += K[SI(i3, k3)];
     }
 }
 

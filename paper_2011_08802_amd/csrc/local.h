@@ -1,5 +1,5 @@
 // Local (quadrature-point) derivatives of the penalised incremental potential
-// density with respect to q = (F_00..F_22 row-major, eta_1..eta_6).
+// density with respect to q = (F_00..F_22 row-major, eta_1..eta_N).
 //
 // Density (Sec. 2.2-2.3, 3.1-3.2; gradient-energy part handled separately by
 // the element kernels since it is a constant quadratic form):
@@ -30,20 +30,34 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+// Number of martensite variants N: a compile-time constant of the library
+// (each build is one instantiation; 6 for CuAlNi, Sec. 4.1; 12 for a
+// NiTi-like card, the footnote of Sec. 4.4).
+#ifndef MVPF_NVAR
+#define MVPF_NVAR 6
+#endif
+
 namespace mvpf {
+
+constexpr int NV = MVPF_NVAR;           // variants N (order parameters per node)
+constexpr int NQ = 9 + NV;              // local variables of a Gauss point: F (9), eta_hat (N)
+constexpr int NHP = NQ * (NQ + 1) / 2;  // packed upper triangle of their Hessian
+static_assert(NV >= 1 && NV <= 13, "unknowns per node must fit the 16-bit constraint masks");
 
 // Material card on the device, in the sample frame.
 struct DevCard {
-  double dU[6][6];     // U_k - I (k = 1..6) as symmetric components
+  double dU[NV][6];    // U_k - I (k = 1..N) as symmetric components
   double L0[6][6];     // austenite stiffness, Voigt (engineering shear strain)
-  double dL[6][6][6];  // L_k - L_0
-  double dF0[6];       // F_k - F_0
-  double W[7][7];      // double-obstacle coefficients, zero diagonal
-  double Sw[6][6];     // condensed Hessian of 1/2 eta^T W eta w.r.t. eta_hat
-  double Mg[6][6];     // gradient-energy species matrix: psi_g = 1/2 Mg_kl grad eta_k . grad eta_l
+  double dL[NV][6][6];  // L_k - L_0
+  double dF0[NV];      // F_k - F_0
+  double W[NV + 1][NV + 1];   // double-obstacle coefficients, zero diagonal
+  double Sw[NV][NV];     // condensed Hessian of 1/2 eta^T W eta w.r.t. eta_hat
+  double Mg[NV][NV];     // gradient-energy species matrix: psi_g = 1/2 Mg_kl grad eta_k . grad eta_l
   double rho;
   double eps;
   int pade;
+  int mixing;          // MVPF_MIX_LINEAR (Eq. LinMix) or MVPF_MIX_LOG
+  double logU[NV][6];  // log U_k (logarithmic mixing rule, Sec. 2.1)
 };
 
 // symmetric index map (xx,yy,zz,yz,xz,xy)
@@ -142,8 +156,8 @@ __device__ __forceinline__ void basis(int v, double e[9]) {
   }
 }
 
-__host__ __device__ constexpr int hidx(int p, int q) {  // packed upper triangle, p <= q < 15
-  return p * 15 - (p * (p - 1)) / 2 + (q - p);
+__host__ __device__ constexpr int hidx(int p, int q) {  // packed upper triangle, p <= q < NQ
+  return p * NQ - (p * (p - 1)) / 2 + (q - p);
 }
 
 // Coefficients of H = A B^-1 with A = sum_p a_p C^p, B = sum_p b_p C^p.
@@ -182,7 +196,7 @@ struct LocalBase {
   double C[9];    // full symmetric
   double w;       // 1/2 H : L H
   double wC[6];   // dw/dC along E_v
-  double wEta[6]; // partial dw/deta_k at fixed C
+  double wEta[NV]; // partial dw/deta_k at fixed C
   double dh[6][6];  // engineering components of dH_v
   double h[6];      // engineering H
   double T[6];      // L H (tensor components)
@@ -190,18 +204,133 @@ struct LocalBase {
   double H[9];
 };
 
-// Hencky energy (Pade order PD) and its first C-derivatives.
-template <int PD>
-__device__ __forceinline__ void local_base(const double F[9], const double eh[6], const DevCard& cd,
-                                           LocalBase& b) {
-  using P = Pade<PD>;
-  double Ft[6];
+// With the logarithmic mixing rule F^t depends nonlinearly on eta: its
+// first derivatives dF^t/deta_k are kept per Gauss point.
+struct LocalBaseLog : LocalBase {
+  double dFt[NV][6];  // dF^t / deta_k (symmetric components)
+};
+template <int MIX> struct BaseOf { using type = LocalBase; };
+template <> struct BaseOf<1> { using type = LocalBaseLog; };
+
+// dF^t / deta_k: the constant U_k - I (Eq. LinMix) or the stored derivative
+__device__ __forceinline__ const double* dFt_of(const LocalBase& b, const DevCard& cd, int k) { return cd.dU[k]; }
+__device__ __forceinline__ const double* dFt_of(const LocalBaseLog& b, const DevCard& cd, int k) { return b.dFt[k]; }
+
+// Terms of the power series of exp: exact to rounding for ||M||_F <= 1
+// (the omitted tail is below 1/19! ~ 8e-18 there; the order parameters of
+// the workloads keep ||sum eta_k log U_k|| near 0.1).
+constexpr int EXP_TERMS = 18;
+
+__device__ __forceinline__ void log_mixing_matrix(const double eh[NV], const DevCard& cd, double M[9]) {
+  double Ms[6];
 #pragma unroll
   for (int v = 0; v < 6; ++v) {
-    double s = (v < 3) ? 1.0 : 0.0;
+    double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) s += eh[k] * cd.dU[k][v];
-    Ft[v] = s;
+    for (int k = 0; k < NV; ++k) s += eh[k] * cd.logU[k][v];
+    Ms[v] = s;
+  }
+  full_from_sym(Ms, M);
+}
+
+// F^t = exp(M), M = sum_k eta_k log U_k (logarithmic mixing, Sec. 2.1), and
+// dF^t/deta_k = sum_n 1/n! d(M^n)[log U_k], by the power series with the
+// recurrences M^n = M^(n-1) M and d(M^n)[A] = d(M^(n-1))[A] M + M^(n-1) A.
+__device__ __forceinline__ void log_mixing(const double eh[NV], const DevCard& cd, double Ft[6],
+                                           double dFt[NV][6]) {
+  double M[9], P[9], E[9];
+  log_mixing_matrix(eh, cd, M);
+  double D[NV][9], Sd[NV][9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) P[i] = E[i] = (i % 4 == 0) ? 1.0 : 0.0;
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) D[k][i] = Sd[k][i] = 0.0;
+  double c = 1.0;
+#pragma unroll 1
+  for (int n = 1; n <= EXP_TERMS; ++n) {
+    c /= n;
+    double T[9];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double A[9], DM[9], PA[9];
+      full_from_sym(cd.logU[k], A);
+      mm(D[k], M, DM);
+      mm(P, A, PA);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        D[k][i] = DM[i] + PA[i];
+        Sd[k][i] += c * D[k][i];
+      }
+    }
+    mm(P, M, T);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      P[i] = T[i];
+      E[i] += c * P[i];
+    }
+  }
+  sym_of(E, Ft);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) sym_of(Sd[k], dFt[k]);
+}
+
+// d^2 F^t / deta_k deta_l = sum_n 1/n! d^2(M^n)[A_k, A_l] (A = log U) with
+// d^2(M^n)[A_k, A_l] = d^2(M^(n-1))[A_k, A_l] M + d(M^(n-1))[A_l] A_k
+//                      + d(M^(n-1))[A_k] A_l.
+__device__ __forceinline__ void log_mixing_second(const double eh[NV], const DevCard& cd, int k, int l,
+                                                  double out[9]) {
+  double M[9], P[9], Dk[9], Dl[9], S[9], Ak[9], Al[9];
+  log_mixing_matrix(eh, cd, M);
+  full_from_sym(cd.logU[k], Ak);
+  full_from_sym(cd.logU[l], Al);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    P[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    Dk[i] = Dl[i] = S[i] = out[i] = 0.0;
+  }
+  double c = 1.0;
+#pragma unroll 1
+  for (int n = 1; n <= EXP_TERMS; ++n) {
+    c /= n;
+    double SM[9], DlA[9], DkA[9], DkM[9], DlM[9], PAk[9], PAl[9], T[9];
+    mm(S, M, SM);
+    mm(Dl, Ak, DlA);
+    mm(Dk, Al, DkA);
+    mm(Dk, M, DkM);
+    mm(Dl, M, DlM);
+    mm(P, Ak, PAk);
+    mm(P, Al, PAl);
+    mm(P, M, T);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      S[i] = SM[i] + DlA[i] + DkA[i];
+      Dk[i] = DkM[i] + PAk[i];
+      Dl[i] = DlM[i] + PAl[i];
+      P[i] = T[i];
+      out[i] += c * S[i];
+    }
+  }
+}
+
+// Hencky energy (Pade order PD) and its first C-derivatives; MIX: the
+// mixing rule of F^t (0: Eq. LinMix, 1: logarithmic).
+template <int PD, int MIX = 0>
+__device__ __forceinline__ void local_base(const double F[9], const double eh[NV], const DevCard& cd,
+                                           typename BaseOf<MIX>::type& b) {
+  using P = Pade<PD>;
+  double Ft[6];
+  if constexpr (MIX == 1) {
+    log_mixing(eh, cd, Ft, b.dFt);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 6; ++v) {
+      double s = (v < 3) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) s += eh[k] * cd.dU[k][v];
+      Ft[v] = s;
+    }
   }
   double Gs[6];
   b.Jt = sym_inv(Ft, Gs);
@@ -249,7 +378,7 @@ __device__ __forceinline__ void local_base(const double F[9], const double eh[6]
     for (int j = 0; j < 6; ++j) {
       double s = cd.L0[i][j];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) s += eh[k] * cd.dL[k][i][j];
+      for (int k = 0; k < NV; ++k) s += eh[k] * cd.dL[k][i][j];
       Lm[i][j] = s;
     }
   double w = 0.0;
@@ -264,7 +393,7 @@ __device__ __forceinline__ void local_base(const double F[9], const double eh[6]
   b.w = 0.5 * w;
   // partial derivative w.r.t. eta at fixed C: 1/2 h^T dL_k h
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < NV; ++k) {
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
@@ -319,9 +448,9 @@ __device__ __forceinline__ void local_base(const double F[9], const double eh[6]
   }
 }
 
-// Symmetric components of dC along variable q (0..8: F_ij row-major; 9..14: eta).
-__device__ __forceinline__ void dC_of(const LocalBase& b, const DevCard& cd, int q, double dc[6],
-                                      double dcf[9]) {
+// Symmetric components of dC along variable q (0..8: F_ij row-major; 9..: eta).
+template <class B>
+__device__ __forceinline__ void dC_of(const B& b, const DevCard& cd, int q, double dc[6], double dcf[9]) {
   if (q < 9) {
     const int i = q / 3, j = q % 3;
 #pragma unroll
@@ -332,7 +461,7 @@ __device__ __forceinline__ void dC_of(const LocalBase& b, const DevCard& cd, int
   } else {
     const int k = q - 9;
     double dU[9], Q[9], X[9];
-    full_from_sym(cd.dU[k], dU);
+    full_from_sym(dFt_of(b, cd, k), dU);
     mm(b.G, dU, Q);
     mm(Q, b.C, X);
 #pragma unroll
@@ -344,7 +473,8 @@ __device__ __forceinline__ void dC_of(const LocalBase& b, const DevCard& cd, int
   dc[3] = dcf[5]; dc[4] = dcf[2]; dc[5] = dcf[1];
 }
 
-// a[i] for a runtime i in 0..5 from six values (selection, no indexing)
+// a[i] for a runtime i in 0..N-1 (selection, no indexing: the array stays
+// in registers)
 __device__ __forceinline__ double pick6(int i, double a0, double a1, double a2, double a3, double a4, double a5) {
   double r = a0;
   r = (i == 1) ? a1 : r;
@@ -354,11 +484,47 @@ __device__ __forceinline__ double pick6(int i, double a0, double a1, double a2, 
   r = (i == 5) ? a5 : r;
   return r;
 }
+// a[i] of the N values at a (same selection chain)
+template <int N>
+__device__ __forceinline__ double pick_n(int i, const double* a) {
+  if constexpr (N == 6) {
+    return pick6(i, a[0], a[1], a[2], a[3], a[4], a[5]);
+  } else {
+    double r = a[0];
+#pragma unroll
+    for (int j = 1; j < N; ++j) r = (i == j) ? a[j] : r;
+    return r;
+  }
+}
+template <int N>
+__device__ __forceinline__ double pick(int i, const double (&a)[N]) {
+  if constexpr (N == 6) {
+    return pick6(i, a[0], a[1], a[2], a[3], a[4], a[5]);
+  } else {
+    double r = a[0];
+#pragma unroll
+    for (int j = 1; j < N; ++j) r = (i == j) ? a[j] : r;
+    return r;
+  }
+}
+// a[i][v] for a runtime i (selection, as pick)
+template <int N, int M>
+__device__ __forceinline__ double pick_row(int i, const double (&a)[N][M], int v) {
+  if constexpr (N == 6) {
+    return pick6(i, a[0][v], a[1][v], a[2][v], a[3][v], a[4][v], a[5][v]);
+  } else {
+    double r = a[0][v];
+#pragma unroll
+    for (int j = 1; j < N; ++j) r = (i == j) ? a[j][v] : r;
+    return r;
+  }
+}
 
-// Q_k = G dU_k (full)
-__device__ __forceinline__ void Q_of(const LocalBase& b, const DevCard& cd, int k, double Q[9]) {
+// Q_k = G dF^t/deta_k (full)
+template <class B>
+__device__ __forceinline__ void Q_of(const B& b, const DevCard& cd, int k, double Q[9]) {
   double dU[9];
-  full_from_sym(cd.dU[k], dU);
+  full_from_sym(dFt_of(b, cd, k), dU);
   mm(b.G, dU, Q);
 }
 
@@ -385,14 +551,14 @@ __device__ __forceinline__ void dC_F(const LocalBase& b, int q, double dc[6]) {
 
 __device__ __forceinline__ double neg_part(double x) { return x < 0.0 ? x : 0.0; }
 
-// Gradient of the local density: g[15].
-template <int PD>
-__device__ __forceinline__ void local_gradient(const double F[9], const double eh[6], const double ehn[6],
-                                               const DevCard& cd, double g[15]) {
-  LocalBase b;
-  local_base<PD>(F, eh, cd, b);
+// Gradient of the local density: g[NQ].
+template <int PD, int MIX = 0>
+__device__ __forceinline__ void local_gradient(const double F[9], const double eh[NV], const double ehn[NV],
+                                               const DevCard& cd, double g[NQ]) {
+  typename BaseOf<MIX>::type b;
+  local_base<PD, MIX>(F, eh, cd, b);
 #pragma unroll
-  for (int q = 0; q < 15; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     double dc[6], dcf[9];
     dC_of(b, cd, q, dc, dcf);
     double wq = 0.0;
@@ -403,31 +569,31 @@ __device__ __forceinline__ void local_gradient(const double F[9], const double e
     } else {
       const int k = q - 9;
       double dU[9], Q[9];
-      full_from_sym(cd.dU[k], dU);
+      full_from_sym(dFt_of(b, cd, k), dU);
       mm(b.G, dU, Q);
       const double trQ = Q[0] + Q[4] + Q[8];
       g[q] = b.Jt * (wq + b.wEta[k]) + b.Jt * trQ * b.w;
     }
   }
   // order-parameter terms: chemical, double obstacle, viscous, penalty
-  double eta[7], etan[7];
+  double eta[NV + 1], etan[NV + 1];
   double s = 0.0, sn = 0.0;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) { eta[k + 1] = eh[k]; etan[k + 1] = ehn[k]; s += eh[k]; sn += ehn[k]; }
+  for (int k = 0; k < NV; ++k) { eta[k + 1] = eh[k]; etan[k + 1] = ehn[k]; s += eh[k]; sn += ehn[k]; }
   eta[0] = 1.0 - s;
   etan[0] = 1.0 - sn;
-  double We[7];
+  double We[NV + 1];
 #pragma unroll
-  for (int i = 0; i < 7; ++i) {
+  for (int i = 0; i < NV + 1; ++i) {
     double t = 0.0;
 #pragma unroll
-    for (int j = 0; j < 7; ++j) t += cd.W[i][j] * eta[j];
+    for (int j = 0; j < NV + 1; ++j) t += cd.W[i][j] * eta[j];
     We[i] = t;
   }
   const double d0 = eta[0] - etan[0];
   const double n0 = neg_part(eta[0]);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < NV; ++k) {
     g[9 + k] += cd.dF0[k] + (We[k + 1] - We[0]) + cd.rho * ((eta[k + 1] - etan[k + 1]) - d0)
                 + cd.eps * (neg_part(eta[k + 1]) - n0);
   }
@@ -436,16 +602,16 @@ __device__ __forceinline__ void local_gradient(const double F[9], const double e
 // Gradient and packed upper-triangular Hessian of the local density; entry
 // hidx(p, q) of the Hessian is stored to D[hidx(p, q) * ds] as soon as it is
 // known (nothing of it is kept in registers).
-template <int PD>
-__device__ __forceinline__ void local_hessian(const double F[9], const double eh[6], const double ehn[6],
-                                              const DevCard& cd, double g[15], double* __restrict__ D,
+template <int PD, int MIX = 0>
+__device__ __forceinline__ void local_hessian(const double F[9], const double eh[NV], const double ehn[NV],
+                                              const DevCard& cd, double g[NQ], double* __restrict__ D,
                                               int64_t ds) {
   using P = Pade<PD>;
-  LocalBase b;
-  local_base<PD>(F, eh, cd, b);
+  typename BaseOf<MIX>::type b;
+  local_base<PD, MIX>(F, eh, cd, b);
   // ---- second derivatives in C-space -------------------------------------
   double wCC[6][6];
-  double wCeta[6][6];  // [v][k]
+  double wCeta[6][NV];  // [v][k]
   {
     double Lm[6][6];
 #pragma unroll
@@ -454,7 +620,7 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
       for (int j = 0; j < 6; ++j) {
         double s = cd.L0[i][j];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) s += eh[k] * cd.dL[k][i][j];
+        for (int k = 0; k < NV; ++k) s += eh[k] * cd.dL[k][i][j];
         Lm[i][j] = s;
       }
     // T : d2H_uv = Y : (d2A - H d2B) - V_u : dB_v - V_v : dB_u with Y = T B^-1,
@@ -549,7 +715,7 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
       }
     }
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < NV; ++k) {
       double dLh[6];
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
@@ -583,9 +749,9 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
     mm(GS, b.G, GSG);
   }
   // per eta_k: dC (dce), dw/deta_k (wqe), dJ_t (Jq)
-  double dce[6][6], wqe[6], Jq[6];
+  double dce[NV][6], wqe[NV], Jq[NV];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < NV; ++k) {
     double Q[9], dcf[9];
     Q_of(b, cd, k, Q);
     Jq[k] = b.Jt * (Q[0] + Q[4] + Q[8]);
@@ -597,11 +763,11 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
     g[9 + k] = b.Jt * wqe[k] + Jq[k] * b.w;
   }
   // eta-eta block
-  double eta[7], etan[7];
+  double eta[NV + 1], etan[NV + 1];
   {
     double s = 0.0, sn = 0.0;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) { eta[k + 1] = eh[k]; etan[k + 1] = ehn[k]; s += eh[k]; sn += ehn[k]; }
+    for (int k = 0; k < NV; ++k) { eta[k + 1] = eh[k]; etan[k + 1] = ehn[k]; s += eh[k]; sn += ehn[k]; }
     eta[0] = 1.0 - s;
     etan[0] = 1.0 - sn;
   }
@@ -610,7 +776,7 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
   // compiler keeps every Q_l product of all pairs live at once.  Values of
   // the per-eta register arrays are picked by static-index selection.
 #pragma unroll 1
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < NV; ++k) {
     double Qk[9], SQ[9], Rk[9], Uk[9], WCk[6], dk[6], wek[6];
     Q_of(b, cd, k, Qk);
     mm(Sf, Qk, SQ);
@@ -618,8 +784,8 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
     mm(SQ, b.C, Uk);  // S Q_k C
 #pragma unroll
     for (int v = 0; v < 6; ++v) {
-      dk[v] = pick6(k, dce[0][v], dce[1][v], dce[2][v], dce[3][v], dce[4][v], dce[5][v]);
-      wek[v] = pick6(k, wCeta[v][0], wCeta[v][1], wCeta[v][2], wCeta[v][3], wCeta[v][4], wCeta[v][5]);
+      dk[v] = pick_row(k, dce, v);
+      wek[v] = pick(k, wCeta[v]);
     }
 #pragma unroll
     for (int u = 0; u < 6; ++u) {
@@ -629,19 +795,19 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
       WCk[u] = s;
     }
     const double trk = Qk[0] + Qk[4] + Qk[8];
-    const double Jqk = pick6(k, Jq[0], Jq[1], Jq[2], Jq[3], Jq[4], Jq[5]);
-    const double wqk = pick6(k, wqe[0], wqe[1], wqe[2], wqe[3], wqe[4], wqe[5]);
-    const double etak = pick6(k, eta[1], eta[2], eta[3], eta[4], eta[5], eta[6]);
+    const double Jqk = pick(k, Jq);
+    const double wqk = pick(k, wqe);
+    const double etak = pick_n<NV>(k, eta + 1);
 #pragma unroll 1
-    for (int l = k; l < 6; ++l) {
+    for (int l = k; l < NV; ++l) {
       double Ql[9], SQl[9], Rl[9], dl[6], wel[6];
       Q_of(b, cd, l, Ql);
       mm(Sf, Ql, SQl);
       mm(b.C, SQl, Rl);  // C S Q_l
 #pragma unroll
       for (int v = 0; v < 6; ++v) {
-        dl[v] = pick6(l, dce[0][v], dce[1][v], dce[2][v], dce[3][v], dce[4][v], dce[5][v]);
-        wel[v] = pick6(l, wCeta[v][0], wCeta[v][1], wCeta[v][2], wCeta[v][3], wCeta[v][4], wCeta[v][5]);
+        dl[v] = pick_row(l, dce, v);
+        wel[v] = pick(l, wCeta[v]);
       }
       double s = 0.0;
 #pragma unroll
@@ -651,9 +817,22 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
       for (int v = 0; v < 6; ++v) s += wel[v] * dk[v] + wek[v] * dl[v];
       const double trl = Ql[0] + Ql[4] + Ql[8];
       const double Jkl = b.Jt * (trk * trl - trprod(Qk, Ql));
-      const double Jql = pick6(l, Jq[0], Jq[1], Jq[2], Jq[3], Jq[4], Jq[5]);
-      const double wql = pick6(l, wqe[0], wqe[1], wqe[2], wqe[3], wqe[4], wqe[5]);
+      const double Jql = pick(l, Jq);
+      const double wql = pick(l, wqe);
       double val = b.Jt * s + Jqk * wql + Jql * wqk + Jkl * b.w;
+      if constexpr (MIX == 1) {
+        // second derivative of F^t (nonzero under logarithmic mixing):
+        // d2C gains -(Q_kl C + C Q_kl^T) and d2J_t gains J_t tr Q_kl, with
+        // Q_kl = G d2F^t/deta_k deta_l
+        double S2[9], Qkl[9], dckl[6], dcfkl[9];
+        log_mixing_second(eh, cd, k, l, S2);
+        mm(b.G, S2, Qkl);
+        dC_eta(b, Qkl, dckl, dcfkl);
+        double wkl = 0.0;
+#pragma unroll
+        for (int v = 0; v < 6; ++v) wkl += b.wC[v] * dckl[v];
+        val += b.Jt * (wkl + (Qkl[0] + Qkl[4] + Qkl[8]) * b.w);
+      }
       // order-parameter terms
       val += cd.Sw[k][l] + cd.rho * ((k == l ? 1.0 : 0.0) + 1.0) + pen0;
       if (k == l && etak < 0.0) val += cd.eps;
@@ -664,7 +843,7 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
   // and wdk = wCC dC_k (wCC symmetric), entry (F_q, eta_k) is
   // J_t (wdk + ak) . dC_q + dJ_t/deta_k  dw/dF_q
 #pragma unroll 1
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < NV; ++k) {
     double Q[9], P[9], t[6];
     Q_of(b, cd, k, Q);
     mm(Sf, Q, P);  // S G dU_k
@@ -673,11 +852,11 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
       double wdk = 0.0;
 #pragma unroll
       for (int v = 0; v < 6; ++v)
-        wdk += wCC[u][v] * pick6(k, dce[0][v], dce[1][v], dce[2][v], dce[3][v], dce[4][v], dce[5][v]);
-      t[u] = wdk + pick6(k, wCeta[u][0], wCeta[u][1], wCeta[u][2], wCeta[u][3], wCeta[u][4], wCeta[u][5]) -
+        wdk += wCC[u][v] * pick_row(k, dce, v);
+      t[u] = wdk + pick(k, wCeta[u]) -
              2.0 * contract_basis(P, u);
     }
-    const double Jqk = pick6(k, Jq[0], Jq[1], Jq[2], Jq[3], Jq[4], Jq[5]);
+    const double Jqk = pick(k, Jq);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       double dcq[6];
@@ -722,18 +901,18 @@ __device__ __forceinline__ void local_hessian(const double F[9], const double eh
     }
   }
   // order-parameter gradient terms
-  double We[7];
+  double We[NV + 1];
 #pragma unroll
-  for (int i = 0; i < 7; ++i) {
+  for (int i = 0; i < NV + 1; ++i) {
     double t = 0.0;
 #pragma unroll
-    for (int j = 0; j < 7; ++j) t += cd.W[i][j] * eta[j];
+    for (int j = 0; j < NV + 1; ++j) t += cd.W[i][j] * eta[j];
     We[i] = t;
   }
   const double d0 = eta[0] - etan[0];
   const double n0 = neg_part(eta[0]);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < NV; ++k) {
     g[9 + k] += cd.dF0[k] + (We[k + 1] - We[0]) + cd.rho * ((eta[k + 1] - etan[k + 1]) - d0)
                 + cd.eps * (neg_part(eta[k + 1]) - n0);
   }

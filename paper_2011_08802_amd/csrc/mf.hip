@@ -23,6 +23,12 @@
 // buffer.  A node gather sums its <= 8 elements in a fixed order and applies
 // the epilogue (product, defect or damped point-block Jacobi update), so
 // results are reproducible bit for bit.
+//
+// The lane layout (9 unknowns per corner, 15 local variables, 120 Hessian
+// entries streamed as 30 16-byte vectors) is that of the six-variant card:
+// a library built for another number of variants never enables the
+// matrix-free level (its finest level is assembled like the others) and
+// launches none of these kernels.
 #include "common.h"
 
 namespace mvpf {
@@ -324,6 +330,7 @@ __global__ void __launch_bounds__(256) mf_pack_batch(const AJob* __restrict__ jo
   mf_pack_body(j.g, j.ck, j.qp, j.D64, j.D32, j.eb0, j.neb, bid);
 }
 void launch_mf_pack_batch(const AJob* jobs, int njobs, int blocks, hipStream_t s) {
+  if (!MF_AVAILABLE) return;
   mf_pack_batch<<<blocks, 256, 0, s>>>(jobs, njobs);
 }
 int mf_pack_job_blocks(AJob& j) {
@@ -332,9 +339,10 @@ int mf_pack_job_blocks(AJob& j) {
   return (int)((30 * j.neb * 64 + 255) / 256);
 }
 
-size_t mf_hessian_values(const Grid& g) { return (size_t)120 * 8 * g.NEpad; }
+size_t mf_hessian_values(const Grid& g) { return MF_AVAILABLE ? (size_t)120 * 8 * g.NEpad : 0; }
 
 void launch_mf_pack(const Grid& g, const Chunk& ck, const double* qp, double* D64, float* D32, hipStream_t s) {
+  if (!MF_AVAILABLE) return;
   const int64_t eb0 = ck.e0 / 8, eb1 = (ck.e0 + ck.NEc + 7) / 8;  // element groups of 8 touching the slab
   const int64_t n = 30 * (eb1 - eb0) * 64;
   mf_pack_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(g, ck, qp, D64, D32, eb0, eb1 - eb0);
@@ -347,6 +355,7 @@ constexpr int MF_PF32 = 20, MF_MINB32 = 3, MF_PF64 = 16, MF_MINB64 = 2;
 template <typename TD, typename TX, typename T>
 void launch_mf_element(const Grid& g, const TD* D, const TX* x, const uint16_t* mask, const DevCard* cd, T* E,
                        hipStream_t s, bool sparse_x, int elems_per_wg) {
+  if constexpr (!MF_AVAILABLE) return;
   const int64_t threads = (int64_t)g.NEpad * 8;  // NEpad is a multiple of 64: whole wavefronts
   constexpr bool f64 = sizeof(TD) == 8;
   constexpr int MINB = f64 ? MF_MINB64 : MF_MINB32, PF = f64 ? MF_PF64 : MF_PF32;
@@ -361,6 +370,7 @@ void launch_mf_element(const Grid& g, const TD* D, const TX* x, const uint16_t* 
 template <int MODE, typename T, typename TX, typename TY>
 void launch_mf_gather(const Grid& g, const T* E, const uint16_t* mask, const TX* x, const T* b, const T* Dinv, T omega,
                       TY* y, hipStream_t s) {
+  if constexpr (!MF_AVAILABLE) return;
   mf_gather_kernel<MODE, T, TX, TY><<<(g.Npad + 255) / 256, 256, 0, s>>>(g, E, mask, x, b, Dinv, omega, y);
 }
 
@@ -401,6 +411,7 @@ __global__ void __launch_bounds__(256) mf_gather_batch(const BJob* __restrict__ 
 }
 template <typename T>
 void launch_mf_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s, int threads) {
+  if constexpr (!MF_AVAILABLE) return;
   constexpr bool f64 = sizeof(T) == 8;
   if (op == BOP_MF_ELEMENT)
     mf_element_batch<T, f64 ? MF_MINB64 : MF_MINB32, f64 ? MF_PF64 : MF_PF32><<<blocks, threads, 0, s>>>(jobs, njobs);
@@ -435,6 +446,7 @@ __global__ void __launch_bounds__(256) mf_outer_gather_batch(const BJob* __restr
 }
 template <typename TZ>
 void launch_mf_outer_batch(int op, const BJob* jobs, int njobs, int blocks, hipStream_t s, int threads) {
+  if constexpr (!MF_AVAILABLE) return;
   if (op == BOP_MF_OUTER_ELEMENT)
     mf_outer_element_batch<TZ><<<blocks, threads, 0, s>>>(jobs, njobs);
   else if (op == BOP_MF_OUTER_GATHER)

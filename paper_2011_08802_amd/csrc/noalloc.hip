@@ -92,14 +92,14 @@ int mvpf_residual_noalloc(mvpf_problem* p, double* R, double* norm_free) {
   // read is written earlier in the same call, so nothing needs clearing
   launch_dirichlet_masks(g, p->load, depth, L0.mask, L0.target, s);
   for (const Chunk& ck : make_chunks(g, NE_CAP)) {
-    launch_qp(g, ck, L0.state, p->card, p->pade, qp, false, s);
+    launch_qp(g, ck, L0.state, p->card, p->pade, p->mixing, qp, false, s);
     launch_residual_gather(g, ck, L0.state, qp, p->card, p->R, s);
   }
   if (p->load.kind == MVPF_LOAD_SPHERE)
     launch_contact_residual(g, make_sphere(g, p->load, depth), L0.state, p->R, s);
   if ((rc = check(p, "residual_noalloc"))) return rc;
   if (norm_free) {
-    const int nb = red_blocks((int64_t)g.N * 9);
+    const int nb = red_blocks((int64_t)g.N * NDOF);
     launch_free_norm_partial(g, p->R, L0.mask, part, s);
     launch_reduce(1, nb, part, red, 0, s);
     if ((rc = check(p, "residual_noalloc norm"))) return rc;
@@ -111,7 +111,7 @@ int mvpf_residual_noalloc(mvpf_problem* p, double* R, double* norm_free) {
     }
     *norm_free = std::sqrt(p->hhost[0]);
   }
-  if (R) launch_soa_to_interleaved(g, p->R, 9, 0, 9, R, s);
+  if (R) launch_soa_to_interleaved(g, p->R, NDOF, 0, NDOF, R, s);
   if ((rc = check(p, "residual_noalloc"))) return rc;
   const hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) {

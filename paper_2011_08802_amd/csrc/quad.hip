@@ -51,7 +51,7 @@ __device__ __forceinline__ double lap_ref(int a, int b) {
   return 0.125 * s;
 }
 
-template <bool HESS, int PD>
+template <bool HESS, int PD, int MIX>
 __device__ __forceinline__ void qp_body(const Grid& g, const Chunk& ck, const double* __restrict__ state,
                                         const DevCard* __restrict__ cd, double* __restrict__ qp, int bid) {
   const int64_t tid = (int64_t)bid * 128 + threadIdx.x;
@@ -62,7 +62,9 @@ __device__ __forceinline__ void qp_body(const Grid& g, const Chunk& ck, const do
   const int ex = (int)(e % g.nx), ey = (int)((e / g.nx) % g.ny), ez = (int)(e / ((int64_t)g.nx * g.ny));
   const double ih = 1.0 / g.h;
   double F[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-  double eh[6] = {0, 0, 0, 0, 0, 0}, ehn[6] = {0, 0, 0, 0, 0, 0};
+  double eh[NV], ehn[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) eh[k] = ehn[k] = 0.0;
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
     const int node = (ex + (a & 1)) + g.nnx * ((ey + ((a >> 1) & 1)) + g.nny * (ez + ((a >> 2) & 1)));
@@ -74,47 +76,55 @@ __device__ __forceinline__ void qp_body(const Grid& g, const Chunk& ck, const do
       for (int j = 0; j < 3; ++j) F[3 * i + j] += u * s.dN[j] * ih;
     }
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < NV; ++k) {
       eh[k] += s.N * state[(int64_t)(3 + k) * g.Npad + node];
-      ehn[k] += s.N * state[(int64_t)(9 + k) * g.Npad + node];
+      ehn[k] += s.N * state[(int64_t)(3 + NV + k) * g.Npad + node];
     }
   }
   const int64_t stride = (int64_t)8 * ck.NEcpad;
   double* out = qp + (int64_t)gp * ck.NEcpad + el;
-  double gr[15];
+  double gr[NQ];
   if (HESS) {
-    local_hessian<PD>(F, eh, ehn, *cd, gr, out + (int64_t)15 * stride, stride);
+    local_hessian<PD, MIX>(F, eh, ehn, *cd, gr, out + (int64_t)NQ * stride, stride);
   } else {
-    local_gradient<PD>(F, eh, ehn, *cd, gr);
+    local_gradient<PD, MIX>(F, eh, ehn, *cd, gr);
   }
 #pragma unroll
-  for (int c = 0; c < 15; ++c) out[(int64_t)c * stride] = gr[c];
+  for (int c = 0; c < NQ; ++c) out[(int64_t)c * stride] = gr[c];
 }
-template <bool HESS, int PD>
+template <bool HESS, int PD, int MIX>
 __global__ void __launch_bounds__(128) qp_kernel(Grid g, Chunk ck, const double* __restrict__ state,
                                                  const DevCard* __restrict__ cd, double* __restrict__ qp) {
-  qp_body<HESS, PD>(g, ck, state, cd, qp, blockIdx.x);
+  qp_body<HESS, PD, MIX>(g, ck, state, cd, qp, blockIdx.x);
 }
 
-template <int PD>
+template <int PD, int MIX>
 void launch_qp_order(const Grid& g, const Chunk& ck, const double* state, const DevCard* cd, double* qp, bool hess,
                      hipStream_t s) {
   const int64_t n = (int64_t)8 * ck.NEcpad;
   const int bs = 128;
   const int nb = (int)((n + bs - 1) / bs);
   if (hess)
-    qp_kernel<true, PD><<<nb, bs, 0, s>>>(g, ck, state, cd, qp);
+    qp_kernel<true, PD, MIX><<<nb, bs, 0, s>>>(g, ck, state, cd, qp);
   else
-    qp_kernel<false, PD><<<nb, bs, 0, s>>>(g, ck, state, cd, qp);
+    qp_kernel<false, PD, MIX><<<nb, bs, 0, s>>>(g, ck, state, cd, qp);
 }
 
-// pade: 11, 22 or 33 (validated at creation)
-void launch_qp(const Grid& g, const Chunk& ck, const double* state, const DevCard* cd, int pade, double* qp,
-               bool hess, hipStream_t s) {
+// pade: 11, 22 or 33; mixing: MVPF_MIX_LINEAR or MVPF_MIX_LOG (validated at creation)
+void launch_qp(const Grid& g, const Chunk& ck, const double* state, const DevCard* cd, int pade, int mixing,
+               double* qp, bool hess, hipStream_t s) {
+  if (mixing == MVPF_MIX_LOG) {
+    switch (pade) {
+      case 11: launch_qp_order<11, 1>(g, ck, state, cd, qp, hess, s); break;
+      case 33: launch_qp_order<33, 1>(g, ck, state, cd, qp, hess, s); break;
+      default: launch_qp_order<22, 1>(g, ck, state, cd, qp, hess, s); break;
+    }
+    return;
+  }
   switch (pade) {
-    case 11: launch_qp_order<11>(g, ck, state, cd, qp, hess, s); break;
-    case 33: launch_qp_order<33>(g, ck, state, cd, qp, hess, s); break;
-    default: launch_qp_order<22>(g, ck, state, cd, qp, hess, s); break;
+    case 11: launch_qp_order<11, 0>(g, ck, state, cd, qp, hess, s); break;
+    case 33: launch_qp_order<33, 0>(g, ck, state, cd, qp, hess, s); break;
+    default: launch_qp_order<22, 0>(g, ck, state, cd, qp, hess, s); break;
   }
 }
 
@@ -123,7 +133,9 @@ __device__ __forceinline__ void residual_gather_body(const Grid& g, const Chunk&
                                                      double* __restrict__ R, int bid) {
   const int n = ck.n0 + bid * 256 + threadIdx.x;
   if (n >= ck.n1 || n >= g.Npad) return;
-  double r[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double r[NDOF];
+#pragma unroll
+  for (int c = 0; c < NDOF; ++c) r[c] = 0.0;
   if (n < g.N) {
     const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
     const double cu = g.h * g.h * 0.125, ce = g.h * g.h * g.h * 0.125;
@@ -142,27 +154,27 @@ __device__ __forceinline__ void residual_gather_body(const Grid& g, const Chunk&
           r[i3] += cu * (s.dN[0] * q[(3 * i3 + 0) * stride] + s.dN[1] * q[(3 * i3 + 1) * stride] +
                          s.dN[2] * q[(3 * i3 + 2) * stride]);
 #pragma unroll
-        for (int m = 0; m < 6; ++m) r[3 + m] += ce * s.N * q[(9 + m) * stride];
+        for (int m = 0; m < NV; ++m) r[3 + m] += ce * s.N * q[(9 + m) * stride];
       }
       // gradient energy 1/2 Mg_kl grad eta_k . grad eta_l: h * Lap_ab * Mg * eta_b
       for (int b = 0; b < 8; ++b) {
         const int nb = (ex + (b & 1)) + g.nnx * ((ey + ((b >> 1) & 1)) + g.nny * (ez + ((b >> 2) & 1)));
         const double lap = g.h * lap_ref(a, b);
-        double eb[6];
+        double eb[NV];
 #pragma unroll
-        for (int l = 0; l < 6; ++l) eb[l] = state[(int64_t)(3 + l) * g.Npad + nb];
+        for (int l = 0; l < NV; ++l) eb[l] = state[(int64_t)(3 + l) * g.Npad + nb];
 #pragma unroll
-        for (int m = 0; m < 6; ++m) {
+        for (int m = 0; m < NV; ++m) {
           double s2 = 0.0;
 #pragma unroll
-          for (int l = 0; l < 6; ++l) s2 += cd->Mg[m][l] * eb[l];
+          for (int l = 0; l < NV; ++l) s2 += cd->Mg[m][l] * eb[l];
           r[3 + m] += lap * s2;
         }
       }
     }
   }
 #pragma unroll
-  for (int c = 0; c < 9; ++c) R[(int64_t)c * g.Npad + n] = r[c];
+  for (int c = 0; c < NDOF; ++c) R[(int64_t)c * g.Npad + n] = r[c];
 }
 __global__ void __launch_bounds__(256) residual_gather_kernel(Grid g, Chunk ck, const double* __restrict__ state,
                                                               const double* __restrict__ qp,
@@ -190,15 +202,18 @@ __device__ __forceinline__ int xcd_logical(int b, int nb_pad) {
 // consecutive elements and EM_WAVES pairs; the Gauss-point Hessians of those
 // elements are staged once per Gauss point in LDS and shared by the
 // wavefronts (wave = pair, lane = element), so each Hessian is read from L2
-// 36 / EM_WAVES times in total.  Four waves leave room for the 81 FP64
-// accumulators in registers (no spills).
+// 36 / EM_WAVES times in total.  Four waves leave room for the NDOF^2 FP64
+// accumulators in registers (81 for N = 6: no spills).
 constexpr int EM_WAVES = 4;
+// workgroups per CU the registers are budgeted for (the staged Hessians of
+// 15 unknowns per node take 116 KB of LDS: one workgroup per CU)
+constexpr int EM_MINB = NHP_PAD * 64 * 8 <= 80 * 1024 ? 2 : 1;
 
 // npair = NPAIR: all 36 pairs; npair = 8: the diagonal pairs (a, a) only.
 __device__ __forceinline__ void element_matrix_body(const Grid& g, const Chunk& ck, const double* __restrict__ qp,
                                                     const DevCard* __restrict__ cd, double* __restrict__ E, int npair,
                                                     int bid, int nblk) {
-  __shared__ double Ds[120 * 64];
+  __shared__ double Ds[NHP_PAD * 64];
   // the NPAIR / EM_WAVES pair chunks of one element group are consecutive
   // logical blocks on one XCD, so the group's Hessians are read from HBM once
   // and then hit that XCD's L2
@@ -221,9 +236,9 @@ __device__ __forceinline__ void element_matrix_body(const Grid& g, const Chunk& 
   const int e = eg * 64 + l;
   const double cuu = g.h * 0.125, cue = g.h * g.h * 0.125, cee = g.h * g.h * g.h * 0.125;
   const int64_t stride = (int64_t)8 * ck.NEcpad;
-  double K[81];
+  double K[NBLK];
 #pragma unroll
-  for (int q = 0; q < 81; ++q) K[q] = 0.0;
+  for (int q = 0; q < NBLK; ++q) K[q] = 0.0;
   for (int gp = 0; gp < 8; ++gp) {
     __syncthreads();
     {
@@ -231,10 +246,10 @@ __device__ __forceinline__ void element_matrix_body(const Grid& g, const Chunk& 
       // instruction moves two Hessian components of the group's 64 elements,
       // lanes 0-31 component c and lanes 32-63 component c + 1, 16 B (two
       // elements) per lane, landing at LDS base + 16 * lane
-      const double* src = qp + (int64_t)(15 + 2 * w + (l >> 5)) * stride + (int64_t)gp * ck.NEcpad + eg * 64 +
+      const double* src = qp + (int64_t)(QP_GRAD + 2 * w + (l >> 5)) * stride + (int64_t)gp * ck.NEcpad + eg * 64 +
                           2 * (l & 31);
 #pragma unroll
-      for (int r = 0; r < 120 / (2 * EM_WAVES); ++r) {
+      for (int r = 0; r < NHP_PAD / (2 * EM_WAVES); ++r) {
         const int c = 2 * (w + EM_WAVES * r);
         __builtin_amdgcn_global_load_lds((const void*)(src + (int64_t)(2 * EM_WAVES * r) * stride),
                                          (__attribute__((address_space(3))) void*)(Ds + c * 64), 16, 0, 0);
@@ -258,40 +273,40 @@ __device__ __forceinline__ void element_matrix_body(const Grid& g, const Chunk& 
             const int pq = pp <= rr ? hidx(pp, rr) : hidx(rr, pp);
             sacc += sa.dN[jj] * sb.dN[ll] * DV(pq);
           }
-        K[9 * i3 + k3] += cuu * sacc;
+        K[NDOF * i3 + k3] += cuu * sacc;
       }
     // u-eta and eta-u
 #pragma unroll
-    for (int m = 0; m < 6; ++m)
+    for (int m = 0; m < NV; ++m)
 #pragma unroll
       for (int i3 = 0; i3 < 3; ++i3) {
         const double d0 = DV(hidx(3 * i3, 9 + m)), d1 = DV(hidx(3 * i3 + 1, 9 + m)), d2 = DV(hidx(3 * i3 + 2, 9 + m));
-        K[9 * i3 + 3 + m] += cue * sb.N * (sa.dN[0] * d0 + sa.dN[1] * d1 + sa.dN[2] * d2);
-        K[9 * (3 + m) + i3] += cue * sa.N * (sb.dN[0] * d0 + sb.dN[1] * d1 + sb.dN[2] * d2);
+        K[NDOF * i3 + 3 + m] += cue * sb.N * (sa.dN[0] * d0 + sa.dN[1] * d1 + sa.dN[2] * d2);
+        K[NDOF * (3 + m) + i3] += cue * sa.N * (sb.dN[0] * d0 + sb.dN[1] * d1 + sb.dN[2] * d2);
       }
     // eta-eta
     const double nn = cee * sa.N * sb.N;
 #pragma unroll
-    for (int m = 0; m < 6; ++m)
+    for (int m = 0; m < NV; ++m)
 #pragma unroll
-      for (int m2 = 0; m2 < 6; ++m2) {
+      for (int m2 = 0; m2 < NV; ++m2) {
         const int pq = m <= m2 ? hidx(9 + m, 9 + m2) : hidx(9 + m2, 9 + m);
-        K[9 * (3 + m) + 3 + m2] += nn * DV(pq);
+        K[NDOF * (3 + m) + 3 + m2] += nn * DV(pq);
       }
 #undef DV
   }
   // gradient energy: h * Lap_ab * Mg (exact under 2x2x2 Gauss)
   const double lap = g.h * lap_ref(a, b);
 #pragma unroll
-  for (int m = 0; m < 6; ++m)
+  for (int m = 0; m < NV; ++m)
 #pragma unroll
-    for (int m2 = 0; m2 < 6; ++m2) K[9 * (3 + m) + 3 + m2] += lap * cd->Mg[m][m2];
+    for (int m2 = 0; m2 < NV; ++m2) K[NDOF * (3 + m) + 3 + m2] += lap * cd->Mg[m][m2];
   if (e < ck.NEc) {
 #pragma unroll
-    for (int q = 0; q < 81; ++q) E[((int64_t)p * NBLK + q) * ck.NEcpad + e] = K[q];
+    for (int q = 0; q < NBLK; ++q) E[((int64_t)p * NBLK + q) * ck.NEcpad + e] = K[q];
   }
 }
-__global__ void __launch_bounds__(EM_WAVES * 64, 2) element_matrix_kernel(Grid g, Chunk ck,
+__global__ void __launch_bounds__(EM_WAVES * 64, EM_MINB) element_matrix_kernel(Grid g, Chunk ck,
                                                                           const double* __restrict__ qp,
                                                                           const DevCard* __restrict__ cd,
                                                                           double* __restrict__ E, int npair) {
@@ -328,11 +343,11 @@ __device__ __forceinline__ void jacobian_gather_body(const Grid& g, const Chunk&
   const int64_t base64 = (int64_t)(t * NUP + u) * Lay<double>::SLICE;
   const int64_t base32 = (int64_t)(t * NUP + u) * Lay<float>::SLICE;
   const int64_t db = (int64_t)t * Lay<double>::SLICE;
-  // three chunks of three block rows keep 27 accumulators live
-  for (int r0 = 0; r0 < 9; r0 += 3) {
-    double K[27];
+  // chunks of three block rows keep 3 NDOF accumulators live
+  for (int r0 = 0; r0 < NDOF; r0 += 3) {
+    double K[3 * NDOF];
 #pragma unroll
-    for (int q = 0; q < 27; ++q) K[q] = 0.0;
+    for (int q = 0; q < 3 * NDOF; ++q) K[q] = 0.0;
     if (inside) {
       for (int a = 0; a < 8; ++a) {
         const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
@@ -346,27 +361,27 @@ __device__ __forceinline__ void jacobian_gather_body(const Grid& g, const Chunk&
         if (a <= b) {
           const double* src = E + (int64_t)pair_index(a, b) * NBLK * es + e;
 #pragma unroll
-          for (int q = 0; q < 27; ++q) K[q] += src[(int64_t)(9 * r0 + q) * es];
+          for (int q = 0; q < 3 * NDOF; ++q) K[q] += src[(int64_t)(NDOF * r0 + q) * es];
         } else {
           const double* src = E + (int64_t)pair_index(b, a) * NBLK * es + e;
 #pragma unroll
           for (int rr = 0; rr < 3; ++rr)
 #pragma unroll
-            for (int c = 0; c < 9; ++c) K[9 * rr + c] += src[(int64_t)(9 * c + r0 + rr) * es];
+            for (int c = 0; c < NDOF; ++c) K[NDOF * rr + c] += src[(int64_t)(NDOF * c + r0 + rr) * es];
         }
       }
     }
     if (A64) {
 #pragma unroll
-      for (int q = 0; q < 27; ++q) A64[base64 + Lay<double>::off(9 * r0 + q, l)] = K[q];
+      for (int q = 0; q < 3 * NDOF; ++q) A64[base64 + Lay<double>::off(NDOF * r0 + q, l)] = K[q];
     }
     if (A32) {
 #pragma unroll
-      for (int q = 0; q < 27; ++q) A32[base32 + Lay<float>::off(9 * r0 + q, l)] = (float)K[q];
+      for (int q = 0; q < 3 * NDOF; ++q) A32[base32 + Lay<float>::off(NDOF * r0 + q, l)] = (float)K[q];
     }
     if (u == 0 && diag64) {
 #pragma unroll
-      for (int q = 0; q < 27; ++q) diag64[db + Lay<double>::off(9 * r0 + q, l)] = K[q];
+      for (int q = 0; q < 3 * NDOF; ++q) diag64[db + Lay<double>::off(NDOF * r0 + q, l)] = K[q];
     }
   }
 }
@@ -408,8 +423,8 @@ __device__ __forceinline__ void apply_dirichlet_body(const Grid& g, const uint16
   const int64_t base64 = (int64_t)(t * NUP + u) * Lay<double>::SLICE;
   const int64_t base32 = (int64_t)(t * NUP + u) * Lay<float>::SLICE;
   const int64_t db = (int64_t)t * Lay<double>::SLICE;
-  for (int e = 0; e < 81; ++e) {
-    const int r = e / 9, c = e % 9;
+  for (int e = 0; e < NBLK; ++e) {
+    const int r = e / NDOF, c = e % NDOF;
     if (((mr >> r) & 1) || ((mc >> c) & 1)) {
       const double v = (u == 0 && r == c) ? 1.0 : 0.0;
       if (A64) A64[base64 + Lay<double>::off(e, l)] = v;
@@ -431,55 +446,55 @@ void launch_apply_dirichlet(const Grid& g, const uint16_t* mask, double* A64, fl
   apply_dirichlet_kernel<<<nb_pad, TILE, 0, s>>>(g, mask, A64, A32, diag64, nblocks);
 }
 
-// 9x9 inverse by Gauss-Jordan elimination with partial pivoting (the paper's
-// point-block Jacobi inverts each block by LU with partial pivoting).  Each
-// thread keeps its augmented [A | I] in LDS, lane-interleaved.
-constexpr int BI_THREADS = 32;  // 32 x 9 x 18 doubles = 41 KB of LDS per block
+// NDOF x NDOF inverse by Gauss-Jordan elimination with partial pivoting (the
+// paper's point-block Jacobi inverts each block by LU with partial
+// pivoting).  Each thread keeps its augmented [A | I] in LDS, lane-interleaved.
+constexpr int BI_THREADS = NDOF <= 9 ? 32 : 16;  // 32 x 9 x 18 doubles = 41 KB of LDS per block (N = 6)
 
 __device__ __forceinline__ void block_inverse_body(const Grid& g, const double* __restrict__ diag64,
                                                    double* __restrict__ Dinv64, float* __restrict__ Dinv32,
                                                    int* status, int bid) {
-  __shared__ double M[9 * 18 * BI_THREADS];
+  __shared__ double M[NDOF * 2 * NDOF * BI_THREADS];
   const int n = bid * BI_THREADS + threadIdx.x;
   const int t = n / TILE, l = n % TILE, lt = threadIdx.x;
   if (n >= g.Npad) return;
   const int64_t db = (int64_t)t * Lay<double>::SLICE;
   const int64_t db32 = (int64_t)t * Lay<float>::SLICE;
-#define MM(r, c) M[((r) * 18 + (c)) * BI_THREADS + lt]
+#define MM(r, c) M[((r) * 2 * NDOF + (c)) * BI_THREADS + lt]
   bool ok = n < g.N;
   if (ok) {
-    for (int r = 0; r < 9; ++r)
-      for (int c = 0; c < 9; ++c) {
-        MM(r, c) = diag64[db + Lay<double>::off(9 * r + c, l)];
-        MM(r, 9 + c) = (r == c) ? 1.0 : 0.0;
+    for (int r = 0; r < NDOF; ++r)
+      for (int c = 0; c < NDOF; ++c) {
+        MM(r, c) = diag64[db + Lay<double>::off(NDOF * r + c, l)];
+        MM(r, NDOF + c) = (r == c) ? 1.0 : 0.0;
       }
-    for (int c = 0; c < 9; ++c) {
+    for (int c = 0; c < NDOF; ++c) {
       int p = c;
       double best = fabs(MM(c, c));
-      for (int r = c + 1; r < 9; ++r) {
+      for (int r = c + 1; r < NDOF; ++r) {
         const double v = fabs(MM(r, c));
         if (v > best) { best = v; p = r; }
       }
       if (!(best > 0.0)) { ok = false; break; }
       if (p != c)
-        for (int cc = 0; cc < 18; ++cc) {
+        for (int cc = 0; cc < 2 * NDOF; ++cc) {
           const double tmp = MM(c, cc);
           MM(c, cc) = MM(p, cc);
           MM(p, cc) = tmp;
         }
       const double ip = 1.0 / MM(c, c);
-      for (int cc = 0; cc < 18; ++cc) MM(c, cc) *= ip;
-      for (int r = 0; r < 9; ++r) {
+      for (int cc = 0; cc < 2 * NDOF; ++cc) MM(c, cc) *= ip;
+      for (int r = 0; r < NDOF; ++r) {
         if (r == c) continue;
         const double f = MM(r, c);
         if (f != 0.0)
-          for (int cc = 0; cc < 18; ++cc) MM(r, cc) -= f * MM(c, cc);
+          for (int cc = 0; cc < 2 * NDOF; ++cc) MM(r, cc) -= f * MM(c, cc);
       }
     }
     if (!ok) atomicOr(status, 1);
   }
-  for (int e = 0; e < 81; ++e) {
-    const double v = ok ? MM(e / 9, 9 + e % 9) : 0.0;
+  for (int e = 0; e < NBLK; ++e) {
+    const double v = ok ? MM(e / NDOF, NDOF + e % NDOF) : 0.0;
     if (Dinv64) Dinv64[db + Lay<double>::off(e, l)] = v;
     if (Dinv32) Dinv32[db32 + Lay<float>::off(e, l)] = (float)v;
   }
@@ -498,13 +513,13 @@ void launch_block_inverse(const Grid& g, const double* diag64, double* Dinv64, f
 }
 
 // ---- batched assembly (jobs of many problems in one launch) --------------------
-template <int PD>
+template <int PD, int MIX>
 __global__ void __launch_bounds__(128) qp_hess_batch(const AJob* __restrict__ jobs, int njobs) {
   int bid;
   const AJob& j = find_job(jobs, njobs, bid);
-  qp_body<true, PD>(j.g, j.ck, j.state, j.cd, j.qp, bid);
+  qp_body<true, PD, MIX>(j.g, j.ck, j.state, j.cd, j.qp, bid);
 }
-__global__ void __launch_bounds__(EM_WAVES * 64, 2) element_matrix_batch(const AJob* __restrict__ jobs, int njobs) {
+__global__ void __launch_bounds__(EM_WAVES * 64, EM_MINB) element_matrix_batch(const AJob* __restrict__ jobs, int njobs) {
   int bid;
   const AJob& j = find_job(jobs, njobs, bid);
   element_matrix_body(j.g, j.ck, j.qp, j.cd, j.elem, j.npair, bid, j.nblk);
@@ -560,14 +575,24 @@ int assembly_job_blocks(int op, AJob& j, bool diag_only) {
 void launch_assembly_batch(int op, int pade, const AJob* jobs, int njobs, int blocks, hipStream_t s) {
   if (njobs <= 0 || blocks <= 0) return;
   switch (op) {
-    case AOP_QP_HESS:
-      if (pade == 11)
-        qp_hess_batch<11><<<blocks, 128, 0, s>>>(jobs, njobs);
-      else if (pade == 33)
-        qp_hess_batch<33><<<blocks, 128, 0, s>>>(jobs, njobs);
-      else
-        qp_hess_batch<22><<<blocks, 128, 0, s>>>(jobs, njobs);
+    case AOP_QP_HESS: {  // pade = Pade order + QP_LOG_MIX for logarithmic mixing
+      const int pd = pade % QP_LOG_MIX;
+      if (pade >= QP_LOG_MIX) {
+        if (pd == 11)
+          qp_hess_batch<11, 1><<<blocks, 128, 0, s>>>(jobs, njobs);
+        else if (pd == 33)
+          qp_hess_batch<33, 1><<<blocks, 128, 0, s>>>(jobs, njobs);
+        else
+          qp_hess_batch<22, 1><<<blocks, 128, 0, s>>>(jobs, njobs);
+      } else if (pd == 11) {
+        qp_hess_batch<11, 0><<<blocks, 128, 0, s>>>(jobs, njobs);
+      } else if (pd == 33) {
+        qp_hess_batch<33, 0><<<blocks, 128, 0, s>>>(jobs, njobs);
+      } else {
+        qp_hess_batch<22, 0><<<blocks, 128, 0, s>>>(jobs, njobs);
+      }
       break;
+    }
     case AOP_ELEMENT: element_matrix_batch<<<blocks, EM_WAVES * 64, 0, s>>>(jobs, njobs); break;
     case AOP_GATHER: jacobian_gather_batch<<<blocks, TILE, 0, s>>>(jobs, njobs); break;
     case AOP_DIRICHLET: apply_dirichlet_batch<<<blocks, TILE, 0, s>>>(jobs, njobs); break;

@@ -16,7 +16,7 @@ __device__ __forceinline__ void restrict_body(const Grid& f, const Grid& c, cons
                                               const uint16_t* __restrict__ cmask, T* __restrict__ bc, int bid) {
   const int I = bid * 256 + threadIdx.x;
   if (I >= c.Npad) return;
-  T acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  T acc[NDOF] = {};
   unsigned msk = 0x1ff;
   if (I < c.N) {
     msk = cmask[I];
@@ -34,13 +34,13 @@ __device__ __forceinline__ void restrict_body(const Grid& f, const Grid& c, cons
           const T w = (T)((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
           const int m = x + f.nnx * (y + f.nny * z);
 #pragma unroll
-          for (int q = 0; q < 9; ++q) acc[q] += w * rf[(int64_t)q * f.Npad + m];
+          for (int q = 0; q < NDOF; ++q) acc[q] += w * rf[(int64_t)q * f.Npad + m];
         }
       }
     }
   }
 #pragma unroll
-  for (int q = 0; q < 9; ++q) bc[(int64_t)q * c.Npad + I] = ((msk >> q) & 1) ? (T)0 : acc[q];
+  for (int q = 0; q < NDOF; ++q) bc[(int64_t)q * c.Npad + I] = ((msk >> q) & 1) ? (T)0 : acc[q];
 }
 template <typename T>
 __global__ void __launch_bounds__(256) restrict_kernel(Grid f, Grid c, const T* __restrict__ rf,
@@ -72,16 +72,16 @@ __device__ __forceinline__ void prolong_add_body(const Grid& f, const Grid& c, c
   if (j & 1) { py[0] = j >> 1; py[1] = (j >> 1) + 1; nyp = 2; wy = (T)0.5; } else { py[0] = j >> 1; nyp = 1; wy = (T)1; }
   if (k & 1) { pz[0] = k >> 1; pz[1] = (k >> 1) + 1; nzp = 2; wz = (T)0.5; } else { pz[0] = k >> 1; nzp = 1; wz = (T)1; }
   const T w = wx * wy * wz;
-  T acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  T acc[NDOF] = {};
   for (int a = 0; a < nzp; ++a)
     for (int b = 0; b < nyp; ++b)
       for (int d = 0; d < nxp; ++d) {
         const int m = px[d] + c.nnx * (py[b] + c.nny * pz[a]);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) acc[q] += ec[(int64_t)q * c.Npad + m];
+        for (int q = 0; q < NDOF; ++q) acc[q] += ec[(int64_t)q * c.Npad + m];
       }
 #pragma unroll
-  for (int q = 0; q < 9; ++q)
+  for (int q = 0; q < NDOF; ++q)
     if (!((msk >> q) & 1)) xf[(int64_t)q * f.Npad + n] += w * acc[q];
 }
 template <typename T>

@@ -229,9 +229,9 @@ __device__ __forceinline__ void convert_masked_body(const Grid& g, const TI* __r
                                                     const uint16_t* __restrict__ mask, TO* __restrict__ out, int bid) {
   const int n = bid * RB + threadIdx.x;
   if (n >= g.Npad) return;
-  const unsigned m = (n < g.N) ? mask[n] : 0x1ff;
+  const unsigned m = (n < g.N) ? mask[n] : (1u << NDOF) - 1u;
 #pragma unroll
-  for (int c = 0; c < 9; ++c)
+  for (int c = 0; c < NDOF; ++c)
     out[(int64_t)c * g.Npad + n] = ((m >> c) & 1) ? (TO)0 : (TO)in[(int64_t)c * g.Npad + n];
 }
 template <typename TI, typename TO>
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(RB) set_constrained_kernel(Grid g, const uint1
   const unsigned m = mask[n];
   if (!m) return;
 #pragma unroll
-  for (int c = 0; c < 9; ++c)
+  for (int c = 0; c < NDOF; ++c)
     if ((m >> c) & 1) dst[(int64_t)c * g.Npad + n] = src[(int64_t)c * g.Npad + n];
 }
 
@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(RB) increment_kernel(Grid g, const uint16_t* _
   if (n >= g.Npad) return;
   const unsigned m = (n < g.N) ? mask[n] : 0;
 #pragma unroll
-  for (int c = 0; c < 9; ++c) {
+  for (int c = 0; c < NDOF; ++c) {
     double v = 0.0;
     if ((m >> c) & 1) v = (c == 2 ? target[n] : 0.0) - state[(int64_t)c * g.Npad + n];
     gv[(int64_t)c * g.Npad + n] = v;
@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(RB) newton_rhs_kernel(Grid g, const uint16_t* 
   if (n >= g.Npad) return;
   const unsigned m = (n < g.N) ? mask[n] : 0;
 #pragma unroll
-  for (int c = 0; c < 9; ++c) {
+  for (int c = 0; c < NDOF; ++c) {
     const int64_t q = (int64_t)c * g.Npad + n;
     rhs[q] = (n >= g.N) ? 0.0 : (((m >> c) & 1) ? gv[q] : -R[q] - Kg[q]);
   }
@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(RB) state_update_kernel(Grid g, const uint16_t
   if (n >= g.N) return;
   const unsigned m = mask[n];
 #pragma unroll
-  for (int c = 0; c < 9; ++c) {
+  for (int c = 0; c < NDOF; ++c) {
     const int64_t q = (int64_t)c * g.Npad + n;
     st[q] = ((m >> c) & 1) ? (c == 2 ? target[n] : 0.0) : st[q] + dx[q];
   }
@@ -372,14 +372,14 @@ __global__ void __launch_bounds__(RB) init_random_kernel(Grid g, uint64_t seed, 
   const int n = blockIdx.x * RB + threadIdx.x;
   if (n >= g.Npad) return;
   for (int c = 0; c < 3; ++c) st[(int64_t)c * g.Npad + n] = 0.0;
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < NV; ++i) {
     double v = 0.0;
     if (n < g.N) {
-      const uint64_t r = splitmix64(seed ^ (uint64_t)(9ull * (uint64_t)n + 3ull + (uint64_t)i));
+      const uint64_t r = splitmix64(seed ^ (uint64_t)((uint64_t)NDOF * (uint64_t)n + 3ull + (uint64_t)i));
       v = 0.05 * ((double)(r >> 11) * 0x1.0p-53);
     }
     st[(int64_t)(3 + i) * g.Npad + n] = v;
-    st[(int64_t)(9 + i) * g.Npad + n] = v;
+    st[(int64_t)(3 + NV + i) * g.Npad + n] = v;
   }
 }
 
@@ -394,7 +394,7 @@ __global__ void __launch_bounds__(RB) free_norm_kernel(Grid g, const double* __r
   for (int n = blockIdx.x * RB + threadIdx.x; n < g.N; n += gridDim.x * RB) {
     const unsigned m = mask[n];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
+    for (int c = 0; c < NDOF; ++c) {
       const double x = v[(int64_t)c * g.Npad + n];
       if (!((m >> c) & 1)) s += x * x;
     }
@@ -404,7 +404,7 @@ __global__ void __launch_bounds__(RB) free_norm_kernel(Grid g, const double* __r
 }
 
 void launch_free_norm_partial(const Grid& g, const double* v, const uint16_t* mask, double* part, hipStream_t s) {
-  free_norm_kernel<<<red_blocks((int64_t)g.N * 9), RB, 0, s>>>(g, v, mask, part);
+  free_norm_kernel<<<red_blocks((int64_t)g.N * NDOF), RB, 0, s>>>(g, v, mask, part);
 }
 
 // flat type conversion out[i] = (TO) in[i]
@@ -430,7 +430,7 @@ __device__ __forceinline__ void precond_finish_body(const Grid& g, const T* __re
   if (n >= g.Npad) return;
   const unsigned m = (n < g.N) ? mask[n] : 0;
 #pragma unroll
-  for (int c = 0; c < 9; ++c) {
+  for (int c = 0; c < NDOF; ++c) {
     const int64_t q = (int64_t)c * g.Npad + n;
     z[q] = ((m >> c) & 1) ? (TZ)v[q] : (TZ)x[q];
   }

@@ -17,7 +17,14 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmvpf.so")
 
+
+def lib_path(nvar: int = 6) -> str:
+    """The library built for nvar martensite variants (a compile-time
+    constant of its kernels): libmvpf.so for 6, libmvpf_n<N>.so otherwise."""
+    return LIB_PATH if nvar == 6 else os.path.join(HERE, f"libmvpf_n{nvar}.so")
+
 FP64, MIXED = 0, 1
+MIX_LINEAR, MIX_LOG = 0, 1
 LOAD_PATCH, LOAD_CAP, LOAD_SPHERE = 0, 1, 2
 _LOAD_KINDS = {"patch": LOAD_PATCH, "cap": LOAD_CAP, "sphere": LOAD_SPHERE}
 OK, ENOTCONV = 0, 1
@@ -40,7 +47,14 @@ class Material(C.Structure):
     _fields_ = [("cubic", C.c_double * 3), ("ortho", C.c_double * 9), ("alpha", C.c_double),
                 ("beta", C.c_double), ("gamma", C.c_double), ("Q", C.c_double * 9), ("F0", C.c_double * 7),
                 ("w_am", C.c_double), ("w_mm", C.c_double), ("ell", C.c_double), ("rho", C.c_double),
-                ("eps_eta", C.c_double), ("pade", C.c_int)]
+                ("eps_eta", C.c_double), ("pade", C.c_int), ("mixing", C.c_int)]
+
+
+class OrbitMaterial(C.Structure):
+    _fields_ = [("U1", C.c_double * 9), ("L1", C.c_double * 36), ("cubic", C.c_double * 3), ("Q", C.c_double * 9),
+                ("F0_a", C.c_double), ("F0_m", C.c_double), ("w_am", C.c_double), ("w_mm", C.c_double),
+                ("ell", C.c_double), ("rho", C.c_double), ("eps_eta", C.c_double), ("pade", C.c_int),
+                ("mixing", C.c_int)]
 
 
 class Loading(C.Structure):
@@ -91,6 +105,9 @@ SIGNATURES = {
     "mvpf_default_opts": (None, [C.POINTER(Opts)]),
     "mvpf_create": (C.c_int, [C.POINTER(Mesh), C.POINTER(Material), C.POINTER(Loading), C.POINTER(Opts), _P,
                               C.POINTER(_P)]),
+    "mvpf_create_orbit": (C.c_int, [C.POINTER(Mesh), C.POINTER(OrbitMaterial), C.POINTER(Loading), C.POINTER(Opts),
+                                    _P, C.POINTER(_P)]),
+    "mvpf_nvar": (C.c_int, []),
     "mvpf_destroy": (None, [_P]),
     "mvpf_last_error": (C.c_char_p, [_P]),
     "mvpf_get_info": (C.c_int, [_P, C.POINTER(Info)]),
@@ -107,6 +124,7 @@ SIGNATURES = {
     "mvpf_precondition": (C.c_int, [_P, _P, _P]),
     "mvpf_solve": (C.c_int, [_P, _P, _P, C.POINTER(SolveStats)]),
     "mvpf_newton_update": (C.c_int, [_P]),
+    "mvpf_newton_step": (C.c_int, [_P, C.c_double, C.POINTER(SolveStats)]),
     "mvpf_time_step": (C.c_int, [_P, C.c_double, C.POINTER(StepStats)]),
     "mvpf_contact_load": (C.c_int, [_P, _D]),
     "mvpf_default_indent_opts": (None, [C.POINTER(IndentOpts)]),
@@ -127,14 +145,14 @@ SIGNATURES = {
     "mvpf_batch_newton_update": (C.c_int, [_P]),
 }
 
-_lib = None
+_libs = {}
 
 
-def load(path: str = LIB_PATH) -> C.CDLL:
-    """Load libmvpf.so (raises if it has not been built)."""
-    global _lib
-    if _lib is not None:
-        return _lib
+def load(nvar: int = 6) -> C.CDLL:
+    """Load the library for nvar variants (raises if it has not been built)."""
+    if nvar in _libs:
+        return _libs[nvar]
+    path = lib_path(nvar)
     if not os.path.exists(path):
         raise MvpfError(-3, f"{path} not found: build it with __graft_entry__.build()")
     lib = C.CDLL(path)
@@ -142,7 +160,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
-    _lib = lib
+    if lib.mvpf_nvar() != nvar:
+        raise MvpfError(-1, f"{path} is built for {lib.mvpf_nvar()} variants, not {nvar}")
+    _libs[nvar] = lib
     return lib
 
 
@@ -154,6 +174,20 @@ def _ptr(t: Optional[torch.Tensor]):
     return C.c_void_p(t.data_ptr())
 
 
+MIXING = {"linear": MIX_LINEAR, "log": MIX_LOG}
+
+
+def orbit_struct(om) -> OrbitMaterial:
+    m = OrbitMaterial()
+    m.U1[:] = list(om.U1)
+    m.L1[:] = list(om.L1)
+    m.cubic[:] = list(om.cubic)
+    m.Q[:] = list(om.Q)
+    m.F0_a, m.F0_m, m.w_am, m.w_mm = om.F0_a, om.F0_m, om.w_am, om.w_mm
+    m.ell, m.rho, m.eps_eta, m.pade, m.mixing = om.ell, om.rho, om.eps_eta, om.pade, MIXING[om.mixing]
+    return m
+
+
 def material_struct(mp) -> Material:
     m = Material()
     m.cubic[:] = list(mp.cubic)
@@ -162,6 +196,7 @@ def material_struct(mp) -> Material:
     m.Q[:] = list(mp.Q)
     m.F0[:] = list(mp.F0)
     m.w_am, m.w_mm, m.ell, m.rho, m.eps_eta, m.pade = mp.w_am, mp.w_mm, mp.ell, mp.rho, mp.eps_eta, mp.pade
+    m.mixing = MIXING[getattr(mp, "mixing", "linear")]
     return m
 
 
@@ -199,12 +234,14 @@ class Problem:
     """One indentation problem on the GPU (handle of mvpf_create)."""
 
     def __init__(self, prob, precision: str = "fp64", device: int = 0, _handle=None, _opts=None, **opts):
-        lib = load()
+        self.nvar = getattr(prob, "n_var", 6)
+        lib = load(self.nvar)
         self.lib = lib
         self.prob = prob
         self.device = torch.device("cuda", device)
         self.stream = torch.cuda.current_stream(self.device)
         self.n_nodes = prob.n_nodes
+        self.ndof = 3 + self.nvar
         self.owned = _handle is None
         if _handle is not None:  # a problem owned by a Batch
             self.h = _handle
@@ -212,10 +249,15 @@ class Problem:
             return
         o = opts_struct(precision, **opts)
         self.opts = o
-        self.mat = material_struct(prob.material)
         h = C.c_void_p()
-        rc = lib.mvpf_create(C.byref(mesh_struct(prob)), C.byref(self.mat), C.byref(loading_struct(prob)), C.byref(o),
-                             C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if hasattr(prob.material, "U1"):  # card generated from one stretch tensor
+            self.mat = orbit_struct(prob.material)
+            rc = lib.mvpf_create_orbit(C.byref(mesh_struct(prob)), C.byref(self.mat), C.byref(loading_struct(prob)),
+                                       C.byref(o), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        else:
+            self.mat = material_struct(prob.material)
+            rc = lib.mvpf_create(C.byref(mesh_struct(prob)), C.byref(self.mat), C.byref(loading_struct(prob)),
+                                 C.byref(o), C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if rc != 0:
             raise MvpfError(rc, lib.mvpf_last_error(None).decode())
         self.h = h
@@ -237,7 +279,8 @@ class Problem:
         except Exception:
             pass
 
-    def _vec(self, n_nodes=None, comps=9):
+    def _vec(self, n_nodes=None, comps=None):
+        comps = self.ndof if comps is None else comps
         return torch.zeros((n_nodes or self.n_nodes) * comps, dtype=torch.float64, device=self.device)
 
     def info(self) -> Info:
@@ -259,10 +302,11 @@ class Problem:
         self._check(self.lib.mvpf_set_state(self.h, _ptr(u), _ptr(eta), _ptr(eta_prev), depth))
 
     def get_state(self):
-        u, e, en = self._vec(comps=3), self._vec(comps=6), self._vec(comps=6)
+        n = self.nvar
+        u, e, en = self._vec(comps=3), self._vec(comps=n), self._vec(comps=n)
         d = C.c_double()
         self._check(self.lib.mvpf_get_state(self.h, _ptr(u), _ptr(e), _ptr(en), C.byref(d)))
-        return u.view(-1, 3), e.view(-1, 6), en.view(-1, 6), d.value
+        return u.view(-1, 3), e.view(-1, n), en.view(-1, n), d.value
 
     def init_random(self, seed: int):
         self._check(self.lib.mvpf_init_random(self.h, C.c_uint64(seed)))
@@ -308,6 +352,12 @@ class Problem:
 
     def newton_update(self):
         self._check(self.lib.mvpf_newton_update(self.h))
+
+    def newton_step(self, depth: float):
+        """mvpf_newton_step: system at `depth`, solve, update; the solve's stats."""
+        st = SolveStats()
+        self._check(self.lib.mvpf_newton_step(self.h, depth, C.byref(st)), allow=(OK, ENOTCONV))
+        return st
 
     def time_step(self, depth: float):
         st = StepStats()

@@ -18,10 +18,11 @@ def say(msg):
 
 
 def seeded_state(p, u_amp=0.0, seed=7):
-    """(U (n,9), Eta_n (n,6)): eta_hat from the problem seed (splitmix64),
-    optional small random displacement field (numpy PCG64 with ``seed``)."""
+    """(U (n, 3 + N), Eta_n (n, N)): eta_hat from the problem seed
+    (splitmix64), optional small random displacement field (numpy PCG64 with
+    ``seed``)."""
     m = Mesh.from_problem(p)
-    U = np.zeros((m.n_nodes, NDOF))
+    U = np.zeros((m.n_nodes, 3 + p.n_var))
     U[:, 3:] = p.eta0()
     if u_amp:
         U[:, :3] = u_amp * np.random.default_rng(seed).standard_normal((m.n_nodes, 3))
@@ -34,10 +35,11 @@ def residual_abs(disc, U, En, elems=None):
     contributions cancel at equilibrium, so |R| alone understates it)."""
     if elems is None:
         elems = np.arange(disc.mesh.n_elem)
-    out = np.zeros(disc.mesh.n_nodes * NDOF)
+    nd = disc.ndof
+    out = np.zeros(disc.mesh.n_nodes * nd)
     for s in range(0, len(elems), 4096):
         en, Re = disc.element_residuals(np.ravel(U), np.ravel(En), elems[s:s + 4096])
-        dofs = (en[:, :, None] * NDOF + np.arange(NDOF)).reshape(len(en), 8 * NDOF)
+        dofs = (en[:, :, None] * nd + np.arange(nd)).reshape(len(en), 8 * nd)
         np.add.at(out, dofs.ravel(), np.abs(Re).ravel())
     return out
 
@@ -50,7 +52,7 @@ class OracleCase:
         self.card = Card(p.material)
         self.mesh = Mesh.from_problem(p)
         self.U, self.En = U, En
-        self.mask, self.target = S.dirichlet(self.mesh, p.kind, p.patch, p.radius, depth=depth)
+        self.mask, self.target = S.dirichlet(self.mesh, p.kind, p.patch, p.radius, depth=depth, ndof=3 + p.n_var)
         self.g = S.increment(self.mask, self.target, U)
         self.sys = S.NewtonSystem(p, self.card, U.ravel(), En.ravel(), self.mask, self.g, depth)
         self.mg = S.Multigrid(p, self.card, U.ravel(), En.ravel(), self.mask, K_fine=self.sys.K,
@@ -89,14 +91,14 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def rel_blocks(a, b):
+def rel_blocks(a, b, ndof=NDOF):
     """Relative errors of the displacement and order-parameter parts."""
-    a = np.asarray(a).reshape(-1, NDOF)
-    b = np.asarray(b).reshape(-1, NDOF)
+    a = np.asarray(a).reshape(-1, ndof)
+    b = np.asarray(b).reshape(-1, ndof)
     return rel(a[:, :3], b[:, :3]), rel(a[:, 3:], b[:, 3:])
 
 
-def entry_errors(a, b, scale=None):
+def entry_errors(a, b, scale=None, ndof=NDOF):
     """Per-entry error ratios |a_i - b_i| / (|b_i| + s_i (+ c_i)), where s_i is
     the largest |b| among the 9 unknowns of entry i's node and c (optional)
     the entry's rounding scale: the sum of the absolute values of the terms
@@ -107,26 +109,26 @@ def entry_errors(a, b, scale=None):
     two correct evaluations in different orders agree to that scale."""
     a = np.asarray(a, dtype=float).ravel()
     b = np.asarray(b, dtype=float).ravel()
-    s = np.repeat(np.abs(b).reshape(-1, NDOF).max(axis=1), NDOF)
+    s = np.repeat(np.abs(b).reshape(-1, ndof).max(axis=1), ndof)
     den = np.abs(b) + s
     if scale is not None:
         den = den + np.abs(np.asarray(scale, dtype=float).ravel())
     return np.abs(a - b) / np.maximum(den, 1e-300)
 
 
-def check_entries(a, b, tol, what, scale=None):
+def check_entries(a, b, tol, what, scale=None, ndof=NDOF):
     """Element-wise parity gate (see entry_errors): every entry within tol of
     the oracle's, relative to its node's scale.  On failure the worst entry
     (node, unknown, both values) is reported; the norm-wise relative errors of
     the displacement and order-parameter parts are printed as diagnostics."""
-    e = entry_errors(a, b, scale)
+    e = entry_errors(a, b, scale, ndof)
     i = int(np.argmax(e))
     a = np.asarray(a, dtype=float).ravel()
     b = np.asarray(b, dtype=float).ravel()
-    ru, re = rel_blocks(a, b)
-    say(f"    {what}: worst entry ratio {e[i]:.2e} (node {i // NDOF}, unknown {i % NDOF}); "
+    ru, re = rel_blocks(a, b, ndof)
+    say(f"    {what}: worst entry ratio {e[i]:.2e} (node {i // ndof}, unknown {i % ndof}); "
         f"norm-wise u {ru:.2e}, eta {re:.2e}")
-    assert e[i] <= tol, (f"{what}: entry {i} (node {i // NDOF}, unknown {i % NDOF}) "
+    assert e[i] <= tol, (f"{what}: entry {i} (node {i // ndof}, unknown {i % ndof}) "
                          f"gpu {a[i]!r} oracle {b[i]!r}, ratio {e[i]:.3e} > {tol:g}")
     return float(e[i])
 

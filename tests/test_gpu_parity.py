@@ -381,6 +381,34 @@ def test_time_step_singular_setup_restores_state():
     gp.close()
 
 
+def test_newton_step_and_tuning_cache():
+    """mvpf_newton_step is mvpf_newton_system + mvpf_solve + mvpf_newton_update
+    (bitwise the same state afterwards); a second problem of the same shape
+    takes its launch shapes from the tuning cache (the same values)."""
+    p = synth.Problem(16, 16, 16, n_levels=3, patch=4, depth_increment=0.01)
+    U, En = seeded_state(p, 1e-3)
+    say("[newton_step] 16^3 mixed")
+    a = gpu_problem(p, U, En, "mixed")
+    b = gpu_problem(p, U, En, "mixed")
+    try:
+        a.newton_system(p.depth_increment)
+        shapes_a = a.autotune()
+        _, sa = a.solve(want_x=False)
+        a.newton_update()
+        b.newton_system(p.depth_increment)
+        assert b.get_tuning("autotune_cache") == 1
+        shapes_b = b.autotune()
+        assert list(shapes_a) == list(shapes_b)
+        b.set_state(U[:, :3], U[:, 3:], En, 0.0)
+        sb = b.newton_step(p.depth_increment)
+        assert sa.iterations == sb.iterations and sa.converged and sb.converged
+        for x, y in zip(a.get_state()[:3], b.get_state()[:3]):
+            assert torch.equal(x, y)
+    finally:
+        a.close()
+        b.close()
+
+
 @pytest.mark.parametrize("order", [11, 22, 33])
 def test_pade_orders_match_oracle(order):
     """Hencky strain by the (1,1), (2,2) or (3,3) Pade approximant (Eqs.
