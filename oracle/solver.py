@@ -18,6 +18,13 @@ Readings where the paper is silent:
   Newton system by lifting: b_free = -R_free - (K g)_free, b_con = g.
 * Coarse-level state is the injection (coincident-node values) of the fine
   state; a coarse dof is constrained iff its coincident fine dof is.
+* Besides the paper's reassembly, coarse operators can be the Galerkin
+  products A_c = P~^T A P~ (P~ = P with the rows of constrained fine dofs
+  zeroed, matching the transfers below).  For nested Q1 spaces and a state
+  that is uniform over each coarse element the two coincide (the 2x2x2
+  Gauss rule integrates both exactly); they differ where the penalty of
+  Eq. IntEnergy is active on a pattern finer than the coarse mesh, which the
+  injected coarse state cannot represent.
 * Prolongation P = trilinear interpolation, restriction = P^T; restricted
   residuals are zeroed at constrained coarse dofs, prolongated corrections are
   not added at constrained fine dofs; the preconditioner is the identity on
@@ -191,13 +198,28 @@ class MGOptions:
     omega: float = 0.55
 
 
+def galerkin_coarse(A: sp.csr_matrix, fine_mask: np.ndarray, P: sp.csr_matrix,
+                    coarse_mask_: np.ndarray) -> sp.csr_matrix:
+    """Galerkin coarse operator of an eliminated fine operator A: with P~ = P
+    whose rows of constrained fine dofs are zero (a correction never touches
+    them), A_c = P~^T A P~, then the constrained coarse dofs eliminated."""
+    keep = sp.diags((~fine_mask.ravel()).astype(float))
+    Pt = (keep @ P).tocsr()
+    return eliminate((Pt.T @ A @ Pt).tocsr(), coarse_mask_)
+
+
 class Multigrid:
-    """Geometric multigrid hierarchy rebuilt by reassembly at injected states."""
+    """Geometric multigrid hierarchy.  coarse = 'reassemble': every coarse
+    operator is the discretisation on its own mesh at the injected state
+    (Sec. 3.4); coarse = 'galerkin': A_l = P~^T A_{l-1} P~ (galerkin_coarse)
+    from the finest operator down."""
 
     def __init__(self, problem, card: Card, U: np.ndarray, Eta_n: np.ndarray,
                  fine_mask: np.ndarray, n_levels: Optional[int] = None,
                  opts: MGOptions = MGOptions(), K_fine: Optional[sp.csr_matrix] = None,
-                 depth: float = 0.0):
+                 depth: float = 0.0, coarse: str = "reassemble"):
+        if coarse not in ("reassemble", "galerkin"):
+            raise ValueError(f"coarse operators: 'reassemble' or 'galerkin', not {coarse!r}")
         self.opts = opts
         self.bs = 3 + card.n_var
         L = problem.n_levels if n_levels is None else n_levels
@@ -209,9 +231,14 @@ class Multigrid:
                 cm = Mesh.from_problem(problem, l)
                 Ul = inject(mesh, Ul, cm)
                 En = inject(mesh, En, cm)
+                fmask = mask
                 mask = coarse_mask(mesh, mask, cm)
-                self.levels[-1].P = prolongation(cm, mesh, self.bs)
+                prev = self.levels[-1]
+                prev.P = prolongation(cm, mesh, self.bs)
                 mesh = cm
+                if coarse == "galerkin":
+                    self.levels.append(Level(mesh=mesh, mask=mask, A=galerkin_coarse(prev.A, fmask, prev.P, mask)))
+                    continue
             disc = Discretisation(mesh, card)
             K = K_fine if (l == 0 and K_fine is not None) else \
                 assemble(disc, Ul.ravel(), En.ravel(), contact_of(problem, mesh), depth)

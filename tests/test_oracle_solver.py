@@ -200,3 +200,64 @@ def test_point_block_jacobi_exact_on_block_diagonal():
     for k in (1, 2, 3):
         x = mg.smooth(lev, np.zeros_like(b), b, k)
         assert np.allclose(x, (1.0 - (1.0 - omega) ** k) * xs, rtol=1e-12, atol=1e-13)
+
+
+def _uniform_state_problem():
+    """8 x 8 x 4 box (3 levels), no top constraint (cap at depth 0: only the
+    bottom face, which every level resolves), a homogeneous deformation
+    u = G X and uniform eta: the Gauss-point Hessians are the same at every
+    point of every level (injection of a linear field is exact)."""
+    p = synth.Problem(8, 8, 4, lz=0.5, n_levels=3, kind="cap", radius=0.2, depth_increment=0.0)
+    card = Card(p.material)
+    m = Mesh.from_problem(p)
+    i, j, k = m.node_ijk(np.arange(m.n_nodes))
+    X = np.stack([i, j, k], 1) * m.h
+    G = np.array([[0.010, 0.004, -0.002], [0.003, -0.006, 0.001], [-0.001, 0.002, 0.008]])
+    U = np.zeros((m.n_nodes, NDOF))
+    U[:, :3] = X @ G.T
+    U[:, 3:] = np.array([0.02, 0.05, 0.01, 0.03, 0.04, 0.02])
+    mask, _ = S.dirichlet(m, "cap", radius=0.2, depth=0.0)
+    return p, card, m, U.ravel(), U[:, 3:].ravel().copy(), mask
+
+
+def test_galerkin_equals_reassembly_on_uniform_state():
+    """For nested Q1 spaces the coarse discretisation integrates exactly what
+    P^T A P integrates when the Hessian is constant: both constructions give
+    the same coarse operators (up to rounding) at a homogeneous state, with a
+    Dirichlet set every level resolves."""
+    p, card, m, U, En, mask = _uniform_state_problem()
+    sys0 = S.NewtonSystem(p, card, U, En, mask, np.zeros(mask.shape))
+    re = S.Multigrid(p, card, U, En, mask, K_fine=sys0.K, coarse="reassemble")
+    ga = S.Multigrid(p, card, U, En, mask, K_fine=sys0.K, coarse="galerkin")
+    for l in range(1, p.n_levels):
+        Ar, Ag = re.levels[l].A, ga.levels[l].A
+        scale = abs(Ar).max()
+        assert abs(Ar - Ag).max() <= 1e-12 * scale, (l, abs(Ar - Ag).max() / scale)
+        assert np.array_equal(re.levels[l].mask, ga.levels[l].mask)
+
+
+def test_galerkin_coarse_correction_is_orthogonal():
+    """Two-level correction with the Galerkin operator, using the V-cycle's
+    transfers (restriction zeroed on constrained coarse dofs, prolongation
+    not added on constrained fine dofs): the corrected error is A-orthogonal
+    to every admissible coarse function, at a non-uniform state where the
+    penalty is active on part of the nodes."""
+    p, card, m, U, En, mask, g = _tiny(n=8, levels=2, eta_offset=-0.02)
+    sysk = S.NewtonSystem(p, card, U, En, mask, g)
+    mg = S.Multigrid(p, card, U, En, mask, K_fine=sysk.K, coarse="galerkin")
+    f, c = mg.levels
+    e = np.random.default_rng(5).standard_normal(f.A.shape[0])
+    e[f.mask.ravel()] = 0.0
+    r = f.A @ e
+    bc = f.P.T @ r
+    bc[c.mask.ravel()] = 0.0
+    corr = f.P @ np.linalg.solve(c.A.toarray(), bc)
+    corr[f.mask.ravel()] = 0.0
+    e2 = e - corr
+    free_c = ~c.mask.ravel()
+    keep = np.where(f.mask.ravel(), 0.0, 1.0)
+    before = (f.P.T @ (keep * (f.A @ e)))[free_c]
+    after = (f.P.T @ (keep * (f.A @ e2)))[free_c]
+    assert np.linalg.norm(after) <= 1e-11 * np.linalg.norm(before)
+    # the penalty is active at some Gauss points (the state is not uniform)
+    assert (U.reshape(-1, NDOF)[:, 3:] < 0).any()
