@@ -63,13 +63,16 @@ class NewtonRun:
     C ABI, with the library's own step rule (Sec. 3.4, as mvpf_time_step):
     iterate newton_system / solve / newton_update until the free-dof
     residual is <= newton_rtol times the attempt's first right-hand side
-    norm.  An attempt fails after newton_max solves without convergence, on a
+    norm (a linear solve stopped at max_it still gives its update).  An
+    attempt fails after newton_max solves without convergence, on a
     non-finite residual or on a singular 9x9 block / coarse operator; then
     the state of the attempt's start is restored and the depth increment
-    halved (at most 8 times per load step).  An accepted attempt sets
-    eta_n <- eta and, if it stopped short of the load step's depth, the next
-    attempt goes on to it.  One call of iteration() is one Newton iteration
-    (a failed attempt's restore is part of the iteration that ended it)."""
+    halved (at most 8 times per load step).  The material's rho belongs to the whole load step; an
+    attempt over a fraction f of it runs with rho / f (the time step is
+    proportional to the increment).  An accepted attempt sets eta_n <- eta
+    and, if it stopped short of the load step's depth, the next attempt goes
+    on to it.  One call of iteration() is one Newton iteration (a failed
+    attempt's restore is part of the iteration that ended it)."""
 
     def __init__(self, gp, prob, newton_rtol=1e-9, newton_max=12, tag=None):
         self.gp, self.prob, self.tag = gp, prob, tag
@@ -80,9 +83,17 @@ class NewtonRun:
         self.trial = prob.depth_increment   # depth of the current attempt
         self.halvings = 0
         self.saved = None
+        self.rho0 = prob.material.rho
+        self.rho = self.rho0
 
     def _save(self):
         self.saved = [t.clone() for t in self.gp.get_state()[:3]]
+        dd = abs(self.trial - self.depth)
+        f = dd / self.prob.depth_increment
+        rho = self.rho0 / f if 0 < f < 1 else self.rho0
+        if rho != self.rho:
+            self.gp.set_viscosity(rho)
+            self.rho = rho
 
     def _fail(self):
         u, e, en = self.saved

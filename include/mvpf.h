@@ -320,14 +320,26 @@ int mvpf_newton_step(mvpf_problem* p, double depth, mvpf_solve_stats* stats);
 
 /* One implicit time step to total depth `depth` (Sec. 3.4): Newton
  * iterations (newton_system, solve, update) until the free-dof residual is
- * <= newton_rtol * ||b_0||; if not within newton_max iterations, or if a 9x9
- * diagonal block or the coarsest operator is singular, or the residual is not
- * finite, the attempt fails: the state and depth are restored to their values
- * before the attempt and the depth increment is halved (at most 8 times, then
- * MVPF_ENOTCONV).  Any error returned (negative) also leaves the state and
- * depth as they were before the failing attempt.  On success eta_hat_n <-
- * eta_hat and the depth is advanced. */
+ * <= newton_rtol * ||b_0|| (a linear solve stopped at max_it still gives its
+ * update: an inexact Newton step); if not within newton_max iterations, or if
+ * a 9x9 diagonal block or the coarsest operator is singular, or the residual
+ * is not finite, the attempt fails: the state and depth are restored to their
+ * values before the attempt and the depth increment is halved (at most 8
+ * times, then MVPF_ENOTCONV).  The
+ * material's rho = 1/(m tau) belongs to the whole increment (depth minus the
+ * current depth); an attempt over a fraction f of it runs with rho / f (the
+ * time step tau is proportional to the increment), and the material's rho is
+ * in place again when the call returns.  Any error returned (negative) also
+ * leaves the state and depth as they were before the failing attempt.  On
+ * success eta_hat_n <- eta_hat and the depth is advanced. */
 int mvpf_time_step(mvpf_problem* p, double depth, mvpf_step_stats* stats);
+
+/* Set the viscous coefficient rho = 1/(m tau) of the material (Sec. 2.3: the
+ * time-discrete dissipation (rho / 2) |eta_hat - eta_hat_n|^2; it depends on
+ * the time step tau, so a caller that chooses its own steps sets it per
+ * step).  rho finite and >= 0, else MVPF_EINVAL.  Takes effect with the next
+ * residual or system. */
+int mvpf_set_viscosity(mvpf_problem* p, double rho);
 
 /* Indentation load of the sphere-contact loading at the current state and
  * depth: P = d/dd of the contact energy at fixed displacements,

@@ -2508,10 +2508,12 @@ struct EventPair {
 // Newton iterations of one implicit step to indenter depth `trial` from the
 // current state (Sec. 3.4): system, solve, update until the free-dof residual
 // is <= newton_rtol ||b_0|| (b_0 = the first right-hand side), checked before
-// each of at most newton_max solves and after the last.  A non-finite
-// residual or a singular 9x9 block / coarse operator ends the iterations
-// without success (*ok false, return 0); other errors are returned.  Timings
-// and iteration counts accumulate into st; *its = the solves made.
+// each of at most newton_max solves and after the last (a linear solve that
+// stops at max_it still gives the update: an inexact Newton step).  A
+// non-finite residual or a singular 9x9 block / coarse operator ends the
+// iterations without success (*ok false, return 0); other errors are
+// returned.  Timings and iteration counts accumulate into st; *its = the
+// solves made.
 int newton_iterate(mvpf_problem* p, double trial, mvpf_step_stats* st, int* its, bool* ok, EventPair& ev) {
   Level& L0 = p->lev[0];
   double b0 = 0.0;
@@ -2626,26 +2628,49 @@ int mvpf_time_step(mvpf_problem* p, double depth, mvpf_step_stats* stats) {
   mvpf_step_stats* st = stats ? stats : &local;
   std::memset(st, 0, sizeof(*st));
   const double goal = depth;
+  const double rho0 = p->orbit ? p->omat.rho : p->mat.rho;
+  const double dd0 = std::fabs(goal - p->depth);  // the increment the material's rho belongs to
   double trial = depth;
+  int rc = 0;
   while (true) {
     const double cur = p->depth;
+    // rho = 1/(m tau) and tau is proportional to the increment: a halved
+    // increment doubles rho (the last attempt to the goal uses rho0 again)
+    const double dd = std::fabs(trial - cur);
+    const double rho = (dd > 0 && dd < dd0) ? rho0 * (dd0 / dd) : rho0;
+    if ((rc = set_rho(p, rho)) != 0) break;
     bool ok = false;
     int its = 0;
-    TRY(newton_attempt(p, trial, st, &its, &ok));
+    if ((rc = newton_attempt(p, trial, st, &its, &ok)) != 0) break;
     if (ok) {
       if (trial == goal) {
         st->converged = 1;
-        return 0;
+        break;
       }
       trial = goal;
       continue;
     }
     if (++st->halvings > 8) {
       p->err = "Newton failed after 8 halvings";
-      return MVPF_ENOTCONV;
+      rc = MVPF_ENOTCONV;
+      break;
     }
     trial = cur + 0.5 * (trial - cur);
   }
+  if ((p->orbit ? p->omat.rho : p->mat.rho) != rho0) {
+    const int rr = set_rho(p, rho0);
+    if (rc == 0) rc = rr;
+  }
+  return rc;
+}
+
+int mvpf_set_viscosity(mvpf_problem* p, double rho) {
+  if (!p) return MVPF_EINVAL;
+  if (!std::isfinite(rho) || rho < 0) {
+    p->err = "viscosity: rho must be finite and >= 0";
+    return MVPF_EINVAL;
+  }
+  return set_rho(p, rho);
 }
 
 int mvpf_contact_load(mvpf_problem* p, double* load) {

@@ -126,6 +126,7 @@ SIGNATURES = {
     "mvpf_newton_update": (C.c_int, [_P]),
     "mvpf_newton_step": (C.c_int, [_P, C.c_double, C.POINTER(SolveStats)]),
     "mvpf_time_step": (C.c_int, [_P, C.c_double, C.POINTER(StepStats)]),
+    "mvpf_set_viscosity": (C.c_int, [_P, C.c_double]),
     "mvpf_contact_load": (C.c_int, [_P, _D]),
     "mvpf_default_indent_opts": (None, [C.POINTER(IndentOpts)]),
     "mvpf_indent": (C.c_int, [_P, C.POINTER(IndentOpts), C.c_void_p, _P, C.POINTER(IndentRecord), C.c_int,
@@ -363,6 +364,9 @@ class Problem:
         st = StepStats()
         self._check(self.lib.mvpf_time_step(self.h, depth, C.byref(st)), allow=(OK, ENOTCONV))
         return st
+
+    def set_viscosity(self, rho: float):
+        self._check(self.lib.mvpf_set_viscosity(self.h, rho))
 
     def contact_load(self) -> float:
         P = C.c_double()

@@ -353,6 +353,46 @@ def test_time_step_failure_restores_state():
     gp.close()
 
 
+def test_set_viscosity_and_time_step_restores_it():
+    """mvpf_set_viscosity: the residual with another rho = 1/(m tau) (Sec. 2.3)
+    matches the oracle's with that rho entry by entry, and setting the
+    material's rho back reproduces the first residual bitwise.  A time step
+    whose attempts all fail (forced from the host: one Newton iteration,
+    unreachable tolerance) runs its halved attempts with 2^k rho and returns
+    with the state, the depth and the material's rho exactly as before."""
+    from dataclasses import replace
+    p = synth.tiny()
+    U, En = seeded_state(p, 1e-3)
+    En = 0.5 * En  # eta_hat != eta_hat_n: the viscous term is not zero
+    say("[viscosity] tiny, rho 3.7 vs the oracle")
+    gp = gpu_problem(p, U, En, "mixed")
+    R0, nf0 = gp.residual()
+    R0 = R0.cpu().numpy()
+    gp.set_viscosity(3.7)
+    R1, _ = gp.residual()
+    p1 = replace(p, material=replace(p.material, rho=3.7))
+    oc = OracleCase(p1, U, En, 0.0, build_mg=False, direct=False)
+    check_entries(R1.cpu().numpy(), oc.sys.R, 1e-12, "residual at rho 3.7", oc.abs_scales()[0])
+    assert not np.array_equal(R1.cpu().numpy(), R0)
+    gp.set_viscosity(p.material.rho)
+    R2, nf2 = gp.residual()
+    assert np.array_equal(R2.cpu().numpy(), R0) and nf2 == nf0
+    with pytest.raises(RuntimeError, match="rho must be finite"):
+        gp.set_viscosity(float("nan"))
+    say("[viscosity] failing time step")
+    gp.set_opts(newton_max=1, newton_rtol=1e-30)
+    before = gp.get_state()
+    st = gp.time_step(p.depth_increment)
+    after = gp.get_state()
+    assert not st.converged and st.halvings == 9 and st.newton_iterations == 9
+    for a, b in zip(before[:3], after[:3]):
+        assert torch.equal(a, b)
+    assert after[3] == before[3] == 0.0
+    R3, nf3 = gp.residual()
+    assert np.array_equal(R3.cpu().numpy(), R0) and nf3 == nf0
+    gp.close()
+
+
 def test_time_step_singular_setup_restores_state():
     """A singular 9x9 diagonal block ends a Newton attempt like a failed one
     (Sec. 3.4: the increment is halved), and the state is restored.  The
