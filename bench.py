@@ -160,14 +160,15 @@ class NewtonRun:
         return rec
 
 
-def run_sequence(prob, precision, warmup, steps, timing, tune=True, matrix_free=-1, snapshot_at=None, tag=None):
+def run_sequence(prob, precision, warmup, steps, timing, tune=True, matrix_free=-1, snapshot_at=None, tag=None,
+                 coarse="galerkin", **solver):
     """W untimed + K timed Newton iterations of the workload's load-step
     sequence from the seeded initial state.  Before it (untimed): launch
     shapes autotuned on the first Newton system and that system's solution
     kept for the error statement.  snapshot_at = n <= W keeps (u, eta) after
     the first n iterations (taken in the warm-up, outside the timed region)."""
     from paper_2011_08802_amd import mvpf
-    gp = mvpf.Problem(prob, precision, rtol=1e-8)
+    gp = mvpf.Problem(prob, precision, rtol=1e-8, coarse=coarse, **solver)
     try:
         if matrix_free >= 0:
             gp.set_tuning("matrix_free", 0, matrix_free)
@@ -212,12 +213,12 @@ def run_sequence(prob, precision, warmup, steps, timing, tune=True, matrix_free=
                 matrix_free=mf, snapshot=snap)
 
 
-def multistep(prob, precision, budget_s=120.0):
+def multistep(prob, precision, budget_s=120.0, coarse="galerkin"):
     """The workload's whole run: every load step to convergence, every Newton
     solve listed (untimed as a whole; each solve's own time is recorded).
     Stops after budget_s seconds of wall time (then 'completed' is false)."""
     from paper_2011_08802_amd import mvpf
-    gp = mvpf.Problem(prob, precision, rtol=1e-8)
+    gp = mvpf.Problem(prob, precision, rtol=1e-8, coarse=coarse)
     try:
         gp.init_random(prob.seed)
         gp.newton_system(prob.depth_increment)
@@ -402,11 +403,11 @@ def indent_main(a):
     # once martensite forms the systems are much harder than the patch workload's: V(4,4) with
     # damping 0.4 and FGMRES(60) take the whole run from 125 s (V(3,3), 0.5, FGMRES(30)) to 80 s
     nu = a.sweeps if a.sweeps > 0 else 4
-    sweeps = dict(nu_pre=nu, nu_post=nu, omega=0.4, restart=60)
+    sweeps = dict(nu_pre=nu, nu_post=nu, omega=0.4, restart=a.restart if a.restart > 0 else 60)
     log(f"[bench] indentation workload: {prob.nx}x{prob.ny}x{prob.nz}, {ndof} dof, run {run}, smoother {sweeps}")
     res = {}
     for prec in ("mixed",) + (() if a.no_fp64 else ("fp64",)):
-        gp = mvpf.Problem(prob, prec, rtol=1e-8, **sweeps)
+        gp = mvpf.Problem(prob, prec, rtol=1e-8, coarse=a.coarse, **sweeps)
         gp.init_random(prob.seed)
         u0, e0, en0, _ = gp.get_state()
         u0, e0, en0 = u0.clone(), e0.clone(), en0.clone()
@@ -466,7 +467,7 @@ def indent_main(a):
                                f"steps (7 desired / 12 max Newton iterations), {prob.n_levels}-level GMG "
                                f"V({nu},{nu}) damping 0.4, FGMRES(60) rtol 1e-8; a step = one whole "
                                f"run; value = dof x Newton iterations per second", "precision": "mixed",
-                   "levels": prob.n_levels, **run},
+                   "levels": prob.n_levels, "coarse": a.coarse, **run},
         "mixed": ms,
     }
     if ms["sweep"]:
@@ -531,7 +532,7 @@ def cpu_model():
     return "unknown"
 
 
-def oracle_newton(p, threads, reference):
+def oracle_newton(p, threads, reference, coarse="galerkin"):
     """The oracle (test infrastructure) on one Newton iteration of problem p
     from its seeded initial state: autodiff assembly of the residual and
     tangent on every level + multigrid setup, then FGMRES+GMG to 1e-8 (timed).
@@ -549,7 +550,8 @@ def oracle_newton(p, threads, reference):
     t0 = time.perf_counter()
     sysk = S.NewtonSystem(p, card, U.ravel(), U[:, 3:].ravel().copy(), mask, S.increment(mask, target, U),
                           p.depth_increment)
-    mg = S.Multigrid(p, card, U.ravel(), U[:, 3:].ravel().copy(), mask, K_fine=sysk.K, depth=p.depth_increment)
+    mg = S.Multigrid(p, card, U.ravel(), U[:, 3:].ravel().copy(), mask, K_fine=sysk.K, depth=p.depth_increment,
+                     coarse="galerkin" if coarse == "galerkin" else "reassemble")
     t1 = time.perf_counter()
     x, st = S.fgmres(sysk.A, sysk.b, mg.precondition, rtol=1e-8)
     t2 = time.perf_counter()
@@ -560,13 +562,13 @@ def oracle_newton(p, threads, reference):
     return dict(assembly_s=t1 - t0, solve_s=t2 - t1, iterations=st.iterations, x=x, xref=xref)
 
 
-def gpu_errors(p, xref):
+def gpu_errors(p, xref, coarse="galerkin"):
     """GPU solves (mixed and FP64 multigrid, rtol 1e-8) of the same first
     Newton system; relative error of each against the oracle's reference."""
     from paper_2011_08802_amd import mvpf
     out = {}
     for prec in ("mixed", "fp64"):
-        gp = mvpf.Problem(p, prec, rtol=1e-8)
+        gp = mvpf.Problem(p, prec, rtol=1e-8, coarse=coarse)
         try:
             gp.init_random(p.seed)
             gp.newton_system(p.depth_increment)
@@ -579,20 +581,20 @@ def gpu_errors(p, xref):
     return out
 
 
-def cpu_baseline(sample):
+def cpu_baseline(sample, coarse="galerkin"):
     """The oracle on the host cores: the whole 8^3 workload (all threads and
     one thread) and a bounded sample of the benchmarked workload; value = the
     sample's DOF per second of one Newton iteration (assembly + solve)."""
     threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or (os.cpu_count() or 1)
     tiny = synth.tiny()
     log(f"[bench] oracle: whole 8^3 workload, {threads} threads")
-    a = oracle_newton(tiny, threads, "direct")
+    a = oracle_newton(tiny, threads, "direct", coarse)
     log("[bench] oracle: whole 8^3 workload, 1 thread")
-    a1 = oracle_newton(tiny, 1, "direct")
-    err_tiny = gpu_errors(tiny, a["xref"])
+    a1 = oracle_newton(tiny, 1, "direct", coarse)
+    err_tiny = gpu_errors(tiny, a["xref"], coarse)
     log(f"[bench] oracle: sample {sample.nx}x{sample.ny}x{sample.nz}, {threads} threads")
-    b = oracle_newton(sample, threads, "fgmres")
-    err_sample = gpu_errors(sample, b["xref"])
+    b = oracle_newton(sample, threads, "fgmres", coarse)
+    err_sample = gpu_errors(sample, b["xref"], coarse)
     torch.set_num_threads(threads)
     step_s = b["assembly_s"] + b["solve_s"]
     return dict(
@@ -629,9 +631,14 @@ def main():
     ap.add_argument("--matrix-free", type=int, default=-1,
                     help="finest level applied from its Gauss-point Hessians (1) or assembled (0); -1: the default")
     ap.add_argument("--sweeps", type=int, default=0,
-                    help="indentation workload: pre- and post-smoothing sweeps (default 3)")
+                    help="pre- and post-smoothing sweeps (default: 2; indentation workload 4)")
+    ap.add_argument("--restart", type=int, default=0,
+                    help="FGMRES restart length (default: 30; indentation workload 60)")
     ap.add_argument("--indent-depth", type=float, default=0.0,
                     help="indentation workload: maximum depth (default: the workload's 0.03)")
+    ap.add_argument("--coarse", default="galerkin", choices=["galerkin", "rediscretise"],
+                    help="coarse multigrid operators: Galerkin products of the finest tangent (default) or the "
+                         "paper's rediscretisation at the injected state")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run an elementwise copy of this many MiB (counter calibration)")
     a = ap.parse_args()
@@ -672,8 +679,14 @@ def single_main(a):
     log(f"[bench] workload {a.workload}: {prob.nx}x{prob.ny}x{prob.nz}, {ndof} dof, {prob.n_levels} levels; "
         f"{W} + {K} Newton iterations of the load-step sequence")
     log("[bench] mixed (FP32 multigrid) ...")
+    solver = {}
+    if a.sweeps > 0:
+        solver.update(nu_pre=a.sweeps, nu_post=a.sweeps)
+    if a.restart > 0:
+        solver.update(restart=a.restart)
+    nu, restart = solver.get("nu_pre", 2), solver.get("restart", 30)
     mixed = run_sequence(prob, "mixed", W, K, not a.no_timing, not a.no_tune, a.matrix_free, snapshot_at=W,
-                         tag="mixed")
+                         tag="mixed", coarse=a.coarse, **solver)
     x1m = mixed.pop("x1")
     log(f"[bench] mixed: {ndof * K / mixed['total_s']:.4g} DOF/s, {1e3 * mixed['total_s'] / K:.1f} ms per Newton "
         f"iteration; sweep {mixed['kernels'].get('pbj_sweep')}")
@@ -681,7 +694,8 @@ def single_main(a):
     if not a.no_fp64:
         kf = min(K, a.fp64_steps)
         log(f"[bench] fp64 multigrid: {W} + {kf} Newton iterations of the same sequence ...")
-        fp64 = run_sequence(prob, "fp64", W, kf, False, not a.no_tune, a.matrix_free, snapshot_at=W, tag="fp64")
+        fp64 = run_sequence(prob, "fp64", W, kf, False, not a.no_tune, a.matrix_free, snapshot_at=W, tag="fp64",
+                            coarse=a.coarse, **solver)
         x1f = fp64.pop("x1")
 
     def summary(r):
@@ -715,13 +729,14 @@ def single_main(a):
         "data": "synthetic",
         "config": {"workload": f"{'patch' if prob.kind == 'patch' else 'spherical-cap'} indentation "
                                f"{prob.nx}x{prob.ny}x{prob.nz} Q1 hex ({prob.lx:g}x{prob.ly:g}x{prob.lz:g}), "
-                               f"{ndof} dof, {prob.n_levels}-level GMG V(2,2), FGMRES(30) rtol 1e-8; "
+                               f"{ndof} dof, {prob.n_levels}-level GMG V({nu},{nu}) ({a.coarse} coarse operators), "
+                               f"FGMRES({restart}) rtol 1e-8; "
                                f"{prob.steps} load steps of {prob.depth_increment}; a step = one Newton "
                                f"iteration of the running load-step sequence (Newton rtol 1e-9), iterations "
                                f"{W}..{W + K - 1} timed",
                    "nx": prob.nx, "ny": prob.ny, "nz": prob.nz, "levels": prob.n_levels,
                    "load": prob.kind, "depth_increment": prob.depth_increment, "load_steps": prob.steps,
-                   "seed": prob.seed, "precision": "mixed"},
+                   "seed": prob.seed, "precision": "mixed", "coarse": a.coarse},
         "mixed": ms,
         "newton_iterations": [{k: (round(r[k], 4) if isinstance(r[k], float) and k.endswith("ms") else r[k])
                                for k in keep} for r in mixed["recs"]],
@@ -772,7 +787,7 @@ def single_main(a):
         for prec in ("fp64", "mixed"):
             log(f"[bench] whole 64^3 run ({med.steps} load steps of {med.depth_increment}), {prec} ...")
             try:
-                out["multistep_64cubed"][prec] = multistep(med, prec)
+                out["multistep_64cubed"][prec] = multistep(med, prec, coarse=a.coarse)
             except Exception as err:  # reported, not fatal for the headline
                 out["multistep_64cubed"][prec] = {"error": str(err)}
     if not a.no_pade and a.workload in ("tiny", "medium"):
@@ -780,7 +795,7 @@ def single_main(a):
         out["pade_assembly"] = pade_assembly(prob)
     if not a.no_cpu_baseline:
         log("[bench] oracle cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(SAMPLES[a.workload](prob))
+        out["cpu_baseline"] = cpu_baseline(SAMPLES[a.workload](prob), a.coarse)
     print(json.dumps(out), flush=True)
 
 

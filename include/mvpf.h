@@ -56,6 +56,7 @@ enum {
 enum { MVPF_FP64 = 0, MVPF_MIXED = 1 };          /* mvpf_opts.precision */
 enum { MVPF_MIX_LINEAR = 0, MVPF_MIX_LOG = 1 };  /* mixing rule of the transformation stretch */
 enum { MVPF_LOAD_PATCH = 0, MVPF_LOAD_CAP = 1, MVPF_LOAD_SPHERE = 2 };  /* mvpf_loading.kind */
+enum { MVPF_COARSE_REDISCRETISE = 0, MVPF_COARSE_GALERKIN = 1 };  /* mvpf_opts.coarse */
 
 typedef struct mvpf_problem mvpf_problem;
 typedef struct mvpf_batch mvpf_batch;
@@ -170,7 +171,21 @@ typedef struct {
  * size m (<= 64).  max_it: total FGMRES iterations.  nu_pre, nu_post, omega:
  * damped point-block Jacobi sweeps and damping.  newton_max, newton_rtol:
  * Newton iterations of a time step (Sec. 3.4: 12) and its tolerance on the
- * free-dof residual relative to the first right-hand side. */
+ * free-dof residual relative to the first right-hand side.  coarse: how the
+ * multigrid levels below the finest get their operators --
+ * MVPF_COARSE_REDISCRETISE (the paper's choice, Sec. 3.4): the tangent
+ * reassembled on each level's own mesh at the injected state (contact
+ * included); MVPF_COARSE_GALERKIN: A_(l+1) = P~^T A_l P~ from the finest
+ * tangent down, P~ the trilinear prolongation with the rows of constrained
+ * level-l unknowns zeroed, then the constrained level-(l+1) unknowns
+ * eliminated.  The two agree where the state is uniform over each coarse
+ * element; where the order parameters' penalty (Eq. PenPot) is active on a
+ * pattern finer than the coarse mesh, the Galerkin levels keep the coarse
+ * correction consistent with the fine operator.  It needs device memory for
+ * the element matrices of every coarse level (the first level below the
+ * finest: 36 * 81 doubles per element of that level, ~1/8 of the finest
+ * element count), allocated on first use; batches (mvpf_create_batch) use
+ * MVPF_COARSE_REDISCRETISE only. */
 typedef struct {
   int precision;
   double rtol;
@@ -180,6 +195,7 @@ typedef struct {
   double omega;
   int newton_max;
   double newton_rtol;
+  int coarse;
 } mvpf_opts;
 
 typedef struct {
@@ -210,7 +226,8 @@ typedef struct {
 } mvpf_info;
 
 /* Fill opts with the defaults (FP64, rtol 1e-8, restart 30, max_it 500,
- * V(2,2), omega 0.55, newton_max 12, newton_rtol 1e-9). */
+ * V(2,2), omega 0.55, newton_max 12, newton_rtol 1e-9, rediscretised coarse
+ * levels). */
 void mvpf_default_opts(mvpf_opts* opts);
 
 /* Create a problem (the setup of the paper's problem statement, Sec. 2 and
@@ -277,8 +294,10 @@ int mvpf_residual_noalloc(mvpf_problem* p, double* R, double* norm_free);
 int mvpf_residual_noalloc_max_layer(void);
 
 /* Build the Newton system of Eq. linAlgEq at the current state for the
- * loading at total depth `depth`: tangent K = d^2 Pi / dU^2 reassembled on
- * every level at the injected state (Sec. 3.4), Dirichlet rows/columns
+ * loading at total depth `depth`: tangent K = d^2 Pi / dU^2 on the finest
+ * level, and on every coarser level either reassembled at the injected state
+ * (Sec. 3.4) or the Galerkin product of the level above (opts.coarse),
+ * Dirichlet rows/columns
  * replaced by the identity, right-hand side b_free = -R_free - (K g)_free,
  * b_con = g with g = target - current on constrained dofs (lifting); inverts
  * the 9x9 diagonal blocks (LU, partial pivoting) and factors the coarsest

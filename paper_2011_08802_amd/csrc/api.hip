@@ -826,6 +826,10 @@ int validate(const mvpf_mesh* mesh, const mvpf_material* mat, const mvpf_loading
     err = "bad smoother/Newton options";
     return MVPF_EINVAL;
   }
+  if (o->coarse != MVPF_COARSE_REDISCRETISE && o->coarse != MVPF_COARSE_GALERKIN) {
+    err = "coarse must be MVPF_COARSE_REDISCRETISE or MVPF_COARSE_GALERKIN";
+    return MVPF_EINVAL;
+  }
   return 0;
 }
 
@@ -837,6 +841,7 @@ void destroy_all(mvpf_problem* p) {
     dfree(L.state); dfree(L.mask); dfree(L.target); dfree(L.A64); dfree(L.A32); dfree(L.diag64);
     dfree(L.Dinv64); dfree(L.Dinv32); dfree(L.x); dfree(L.x2); dfree(L.b); dfree(L.r); dfree(L.Ainv);
   }
+  for (int l = 0; l < MAX_LEVELS; ++l) dfree(p->gal[l]);
   dfree(p->Dmf64); dfree(p->Dmf32); dfree(p->sphere);
   dfree(p->card); dfree(p->qp); dfree(p->elem); dfree(p->Cbuf); dfree(p->R); dfree(p->rhs); dfree(p->gvec); dfree(p->dx); dfree(p->tmp);
   dfree(p->tmp2); dfree(p->V); dfree(p->Z); dfree(p->red); dfree(p->hcol); dfree(p->save_state);
@@ -1039,7 +1044,109 @@ int system_rhs(mvpf_problem* p, double depth) {
   return 0;
 }
 
+double* coarse_dense(mvpf_problem* p) { return p->coarse_work ? p->coarse_work : p->V; }
+
+// the coarsest level's eliminated operator -> dense matrix; marks it ready
+int coarse_fork(mvpf_problem* p, bool coarse_inline) {
+  Level& C = p->lev[p->L - 1];
+  launch_dense_from_bsr(C.g, C.A64, coarse_dense(p), p->stream);
+  HIPCHK(hipEventRecord(p->ev_fork, p->stream));
+  if (!coarse_inline) p->coarse_pending = true;
+  return 0;
+}
+
+// the smoother's block inverses, enqueued before the coarse inversion's long
+// chain of launches (the host can block while it enqueues that chain), then
+// the inversion (on the side stream when it overlaps)
+int finish_system(mvpf_problem* p, bool coarse_inline) {
+  hipStream_t s = p->stream;
+  for (int l = 0; l < p->L - 1; ++l) {
+    Level& L = p->lev[l];
+    launch_block_inverse(L.g, L.diag64, L.Dinv64, L.Dinv32, setup_status(p), s);
+  }
+  TRY(launch_check(p, "assembly"));
+  if (coarse_inline) {
+    Level& C = p->lev[p->L - 1];
+    const int nd = C.ndense;
+    double* work = coarse_dense(p);
+    const bool overlap = p->coarse_overlap < 0 ? nd <= COARSE_OVERLAP_MAX : p->coarse_overlap != 0;
+    hipStream_t cs = overlap ? p->side : s;
+    if (overlap) HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+    if (dense_invert(nd, work, C.Ainv, work + (int64_t)nd * nd, setup_status(p), cs) != 0) {
+      p->err = "coarse inversion launch failed";
+      return MVPF_EDEVICE;
+    }
+    if (overlap) {
+      HIPCHK(hipEventRecord(p->ev_join, p->side));
+      p->coarse_pending = true;
+    }
+    TRY(launch_check(p, "coarse inversion"));
+  }
+  return 0;
+}
+
+// Galerkin hierarchy (opts.coarse = MVPF_COARSE_GALERKIN, galerkin.hip): the
+// finest tangent's element matrices (all 36 node pairs, contact included)
+// are coarsened slab by slab into level 1's, each level's into the next's;
+// every coarse level's stored blocks are gathered from its element matrices.
+// The coarsest level is finished first so that its inversion overlaps the
+// intermediate levels' gathers and the block inverses.
+int build_system_galerkin(mvpf_problem* p, double depth, bool coarse_inline) {
+  hipStream_t s = p->stream;
+  Level& L0 = p->lev[0];
+  const int Lc = p->L - 1;
+  for (int l = 1; l < p->L; ++l)
+    if (!p->gal[l]) TRY(dalloc(p, &p->gal[l], (size_t)NPAIR * NBLK * p->lev[l].g.NEpad));
+  TRY(system_prelude(p, depth));
+  const bool mf = use_mf(p);
+  const Grid& g1 = p->lev[1].g;
+  const int64_t nxy = (int64_t)L0.g.nx * L0.g.ny;
+  int zdone = 0;  // level-1 element layers coarsened so far
+  for (const Chunk& ck : make_chunks(L0.g, p->ne_use)) {
+    timer_begin(p, p->t_qp);
+    launch_qp(L0.g, ck, L0.state, p->card, p->pade, p->mixing, p->qp, true, s);
+    timer_end(p, p->t_qp, 8.0 * 8 * QP_HESS * (double)ck.NEc);
+    if (mf) launch_mf_pack(L0.g, ck, p->qp, p->Dmf64, p->Dmf32, s);
+    launch_residual_gather(L0.g, ck, L0.state, p->qp, p->card, p->R, s);
+    launch_element_matrices(L0.g, ck, p->qp, p->card, p->elem, s, false);
+    if (contact(p)) launch_contact_element(L0.g, ck, make_sphere(L0.g, p->load, depth), L0.state, p->elem, s, false);
+    launch_jacobian_gather(L0.g, ck, p->elem, L0.A64, L0.A32, L0.diag64, s, mf);
+    // level-1 layers Z whose child layers 2Z and 2Z + 1 this slab holds (slabs
+    // overlap by one element layer, so each layer is met in one of them)
+    const int ez0 = (int)(ck.e0 / nxy), ez1 = (int)((ck.e0 + ck.NEc) / nxy);
+    const int z1 = ez1 / 2;
+    if (zdone < z1) {
+      if (2 * zdone < ez0) {
+        p->err = "internal: an assembly slab does not hold the child layers of a coarse layer";
+        return MVPF_EDEVICE;
+      }
+      launch_galerkin_coarsen(L0.g, ck, p->elem, L0.mask, g1, zdone, z1, p->gal[1], s);
+      zdone = z1;
+    }
+  }
+  if (zdone != g1.nz) {
+    p->err = "internal: coarse layers left out of the Galerkin product";
+    return MVPF_EDEVICE;
+  }
+  TRY(system_rhs(p, depth));
+  launch_apply_dirichlet(L0.g, L0.mask, L0.A64, L0.A32, L0.diag64, s);
+  auto whole = [](const Grid& g) { return Chunk{0, g.NE, g.NEpad, 0, g.Npad}; };
+  for (int l = 1; l < Lc; ++l) {
+    const Grid& g = p->lev[l].g;
+    launch_galerkin_coarsen(g, whole(g), p->gal[l], p->lev[l].mask, p->lev[l + 1].g, 0, p->lev[l + 1].g.nz,
+                            p->gal[l + 1], s);
+  }
+  for (int l = Lc; l >= 1; --l) {
+    Level& C = p->lev[l];
+    launch_jacobian_gather(C.g, whole(C.g), p->gal[l], C.A64, C.A32, C.diag64, s);
+    launch_apply_dirichlet(C.g, C.mask, C.A64, C.A32, C.diag64, s);
+    if (l == Lc) TRY(coarse_fork(p, coarse_inline));
+  }
+  return finish_system(p, coarse_inline);
+}
+
 int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
+  if (p->opts.coarse == MVPF_COARSE_GALERKIN) return build_system_galerkin(p, depth, coarse_inline);
   hipStream_t s = p->stream;
   Level& L0 = p->lev[0];
   const int Lc = p->L - 1;
@@ -1050,12 +1157,7 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
   // then runs beside it
   assemble_coarse_level(p, Lc, depth);
   TRY(launch_check(p, "coarse assembly"));
-  Level& C = p->lev[Lc];
-  const int nd = C.ndense;
-  double* work = p->coarse_work ? p->coarse_work : p->V;
-  launch_dense_from_bsr(C.g, C.A64, work, s);
-  HIPCHK(hipEventRecord(p->ev_fork, s));
-  if (!coarse_inline) p->coarse_pending = true;
+  TRY(coarse_fork(p, coarse_inline));
   for (int l = Lc - 1; l >= 1; --l) assemble_coarse_level(p, l, depth);
   // finest: residual and unconstrained tangent
   for (const Chunk& ck : make_chunks(L0.g, p->ne_use)) {
@@ -1073,28 +1175,7 @@ int build_system(mvpf_problem* p, double depth, bool coarse_inline = true) {
   // lifting of the prescribed increment, then symmetric elimination
   TRY(system_rhs(p, depth));
   launch_apply_dirichlet(L0.g, L0.mask, L0.A64, L0.A32, L0.diag64, s);
-  // the smoother's block inverses, enqueued before the coarse inversion's
-  // long chain of launches (the host can block while it enqueues that chain)
-  for (int l = 0; l < p->L - 1; ++l) {
-    Level& L = p->lev[l];
-    launch_block_inverse(L.g, L.diag64, L.Dinv64, L.Dinv32, setup_status(p), s);
-  }
-  TRY(launch_check(p, "assembly"));
-  if (coarse_inline) {
-    const bool overlap = p->coarse_overlap < 0 ? nd <= COARSE_OVERLAP_MAX : p->coarse_overlap != 0;
-    hipStream_t cs = overlap ? p->side : s;
-    if (overlap) HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
-    if (dense_invert(nd, work, C.Ainv, work + (int64_t)nd * nd, setup_status(p), cs) != 0) {
-      p->err = "coarse inversion launch failed";
-      return MVPF_EDEVICE;
-    }
-    if (overlap) {
-      HIPCHK(hipEventRecord(p->ev_join, p->side));
-      p->coarse_pending = true;
-    }
-    TRY(launch_check(p, "coarse inversion"));
-  }
-  return 0;
+  return finish_system(p, coarse_inline);
 }
 
 // pinned host slot of the setup status
@@ -2210,6 +2291,7 @@ void mvpf_default_opts(mvpf_opts* o) {
   o->omega = 0.55;
   o->newton_max = 12;
   o->newton_rtol = 1e-9;
+  o->coarse = MVPF_COARSE_REDISCRETISE;
 }
 
 int mvpf_nvar(void) { return NV; }
@@ -2898,6 +2980,10 @@ int mvpf_create_batch(int n, const mvpf_mesh* meshes, const mvpf_material* mats,
     g_create_err = "bad batch arguments";
     return MVPF_EINVAL;
   }
+  if (opts->coarse != MVPF_COARSE_REDISCRETISE) {
+    g_create_err = "batches use rediscretised coarse levels (opts.coarse = MVPF_COARSE_REDISCRETISE)";
+    return MVPF_EINVAL;
+  }
   mvpf_batch* b = new mvpf_batch();
   b->n = n;
   b->mixed = opts->precision == MVPF_MIXED;
@@ -2984,6 +3070,11 @@ mvpf_problem* mvpf_batch_problem(mvpf_batch* b, int i) {
 // the coarsest-level inversions of all problems run as one batched chain.
 int mvpf_batch_newton_system(mvpf_batch* b, const double* depths) {
   if (!b || !depths) return MVPF_EINVAL;
+  for (mvpf_problem* p : b->probs)
+    if (p->opts.coarse != MVPF_COARSE_REDISCRETISE) {
+      b->err = "batches use rediscretised coarse levels (opts.coarse = MVPF_COARSE_REDISCRETISE)";
+      return MVPF_EINVAL;
+    }
   BCHK(hipEventRecord(b->enter, b->stream));
   int rc = 0, bad = -1;
   if (batch_single_slabs(b)) {

@@ -103,6 +103,14 @@ struct Chunk {
 // Slabs of at most ne_cap padded elements each (one slab if the level fits).
 std::vector<Chunk> make_chunks(const Grid& g, int64_t ne_cap);
 
+// Logical block index with the 8 XCDs of the chip in mind: hardware places
+// workgroup b on XCD b % 8; consecutive logical ids are kept on one XCD so
+// that neighbouring tiles share its L2 (nb_pad: the grid, a multiple of 8).
+__device__ __forceinline__ int xcd_logical(int b, int nb_pad) {
+  const int per = nb_pad >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
 // element node pair a <= b < 8 -> 0..35
 __host__ __device__ constexpr int pair_index(int a, int b) { return a * 8 - (a * (a - 1)) / 2 + (b - a); }
 
@@ -244,6 +252,9 @@ struct mvpf_problem {
   double* coarse_work = nullptr;     // dense scratch when V is too small
   bool coarse_pending = false;
   int coarse_overlap = -1;           // 1: side stream, 0: problem stream, -1: by size
+  // Galerkin coarse levels (opts.coarse): element matrices of level l >= 1,
+  // [(p * NBLK + q) * NEpad_l + E], allocated on first use
+  double* gal[mvpf::MAX_LEVELS] = {nullptr};
   int64_t ne_cap = 0;                // element capacity of qp / elem (assembly slab size)
   int64_t ne_use = 0;                // slab size in use (<= ne_cap)
   int config_version = 0;            // bumped by set_opts / set_tuning / autotune (captured graphs)
@@ -265,6 +276,12 @@ void launch_jacobian_gather(const Grid& g, const Chunk& ck, const double* elem, 
                             hipStream_t s, bool diag_only = false);
 void launch_apply_dirichlet(const Grid& g, const uint16_t* mask, double* A64, float* A32, double* diag64,
                             hipStream_t s);
+// Galerkin coarsening (galerkin.hip): element matrices of the parent layers
+// Z0 .. Z1 - 1 of level gp from the child element matrices Ec of chunk ckc of
+// level gc (which must hold both child layers of each) and the child level's
+// constrained-dof masks; parents go to Ep (whole level, stride gp.NEpad)
+void launch_galerkin_coarsen(const Grid& gc, const Chunk& ckc, const double* Ec, const uint16_t* maskc,
+                             const Grid& gp, int Z0, int Z1, double* Ep, hipStream_t s);
 void launch_block_inverse(const Grid& g, const double* diag64, double* Dinv64, float* Dinv32, int* status,
                           hipStream_t s);
 // penalty contact with a rigid sphere (MVPF_LOAD_SPHERE)

@@ -188,14 +188,6 @@ void launch_residual_gather(const Grid& g, const Chunk& ck, const double* state,
   residual_gather_kernel<<<(ck.n1 - ck.n0 + 255) / 256, 256, 0, s>>>(g, ck, state, qp, cd, R);
 }
 
-// Logical block index with the 8 XCDs of the chip in mind: hardware places
-// workgroup b on XCD b % 8; consecutive logical ids are kept on one XCD so
-// that neighbouring tiles share its L2.
-__device__ __forceinline__ int xcd_logical(int b, int nb_pad) {
-  const int per = nb_pad >> 3;
-  return (b & 7) * per + (b >> 3);
-}
-
 
 // Element matrices K_e = sum_g w_g B_g^T D_g B_g + h Lap (x) Mg for the 36
 // node pairs a <= b.  A workgroup of EM_WAVES wavefronts covers 64

@@ -26,6 +26,8 @@ def lib_path(nvar: int = 6) -> str:
 FP64, MIXED = 0, 1
 MIX_LINEAR, MIX_LOG = 0, 1
 LOAD_PATCH, LOAD_CAP, LOAD_SPHERE = 0, 1, 2
+COARSE_REDISCRETISE, COARSE_GALERKIN = 0, 1
+COARSE = {"rediscretise": COARSE_REDISCRETISE, "galerkin": COARSE_GALERKIN}
 _LOAD_KINDS = {"patch": LOAD_PATCH, "cap": LOAD_CAP, "sphere": LOAD_SPHERE}
 OK, ENOTCONV = 0, 1
 MAX_COARSE_DOF = 8192
@@ -64,7 +66,7 @@ class Loading(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("rtol", C.c_double), ("restart", C.c_int), ("max_it", C.c_int),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("omega", C.c_double), ("newton_max", C.c_int),
-                ("newton_rtol", C.c_double)]
+                ("newton_rtol", C.c_double), ("coarse", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -224,9 +226,13 @@ def indent_opts(**kw) -> IndentOpts:
 
 
 def opts_struct(precision: str, **opts) -> Opts:
+    """Default options with precision ('fp64' or 'mixed') and overrides;
+    coarse may be given by name ('rediscretise' or 'galerkin')."""
     o = default_opts()
     o.precision = MIXED if precision == "mixed" else FP64
     for k, v in opts.items():
+        if k == "coarse" and isinstance(v, str):
+            v = COARSE[v]
         setattr(o, k, v)
     return o
 
@@ -291,6 +297,8 @@ class Problem:
 
     def set_opts(self, **kw):
         for k, v in kw.items():
+            if k == "coarse" and isinstance(v, str):
+                v = COARSE[v]
             setattr(self.opts, k, v)
         self._check(self.lib.mvpf_set_opts(self.h, C.byref(self.opts)))
 

@@ -47,7 +47,7 @@ def residual_abs(disc, U, En, elems=None):
 class OracleCase:
     """Oracle Newton system + multigrid for one problem/state/depth."""
 
-    def __init__(self, p, U, En, depth, build_mg=True, direct=True):
+    def __init__(self, p, U, En, depth, build_mg=True, direct=True, coarse="reassemble"):
         self.p = p
         self.card = Card(p.material)
         self.mesh = Mesh.from_problem(p)
@@ -56,7 +56,7 @@ class OracleCase:
         self.g = S.increment(self.mask, self.target, U)
         self.sys = S.NewtonSystem(p, self.card, U.ravel(), En.ravel(), self.mask, self.g, depth)
         self.mg = S.Multigrid(p, self.card, U.ravel(), En.ravel(), self.mask, K_fine=self.sys.K,
-                              depth=depth) if build_mg else None
+                              depth=depth, coarse=coarse) if build_mg else None
         self.x = S.direct_solve(self.sys.A, self.sys.b) if direct else None
         self.depth = depth
         self._scales = None
