@@ -24,6 +24,7 @@ error against the oracle's.
 Prints one JSON line (see the README/DESIGN for the fields).
 """
 import argparse
+import dataclasses
 import json
 import os
 import statistics
@@ -632,6 +633,7 @@ def main():
                     help="finest level applied from its Gauss-point Hessians (1) or assembled (0); -1: the default")
     ap.add_argument("--sweeps", type=int, default=0,
                     help="pre- and post-smoothing sweeps (default: 2; indentation workload 4)")
+    ap.add_argument("--levels", type=int, default=0, help="multigrid levels (default: the workload's)")
     ap.add_argument("--restart", type=int, default=0,
                     help="FGMRES restart length (default: 30; indentation workload 60)")
     ap.add_argument("--indent-depth", type=float, default=0.0,
@@ -674,6 +676,8 @@ SAMPLES = {  # bounded samples of each workload for the oracle (about 10-20 s of
 
 def single_main(a):
     prob = WORKLOADS[a.workload]()
+    if a.levels > 0:
+        prob = dataclasses.replace(prob, n_levels=a.levels)
     ndof = prob.n_dof
     W, K = a.warmup, a.steps
     log(f"[bench] workload {a.workload}: {prob.nx}x{prob.ny}x{prob.nz}, {ndof} dof, {prob.n_levels} levels; "

@@ -266,7 +266,10 @@ void fill_card(const CubicCard& cc, const double Qm[9], const double F0[NV + 1],
   // gradient energy -sum_{i<j} w_ij l^2 grad eta_i . grad eta_j in eta_hat
   const double l2 = ell * ell;
   for (int k = 0; k < NV; ++k)
-    for (int l = 0; l < NV; ++l) cd.Mg[k][l] = -l2 * cd.Sw[k][l];
+    for (int l = 0; l < NV; ++l) {
+      cd.Mg[k][l] = -l2 * cd.Sw[k][l];
+      cd.Mg32[k][l] = (float)cd.Mg[k][l];
+    }
   cd.rho = rho;
   cd.eps = eps;
   cd.pade = pade;

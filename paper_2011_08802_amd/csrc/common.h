@@ -42,9 +42,12 @@ constexpr int NUP = 14;              // stored stencil blocks per row (diagonal 
 
 // Lane exchange by a DPP control word (quad permutations, row mirrors): the
 // value of the lane the control selects, moved through the VALU (no LDS).
+// Every lane of these permutations has a source lane, so the bound control
+// changes nothing; it lets the compiler fold the move into the VALU
+// instruction that consumes it (a DPP source operand).
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp_t(float v) {

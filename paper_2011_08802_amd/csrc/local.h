@@ -53,6 +53,7 @@ struct DevCard {
   double W[NV + 1][NV + 1];   // double-obstacle coefficients, zero diagonal
   double Sw[NV][NV];     // condensed Hessian of 1/2 eta^T W eta w.r.t. eta_hat
   double Mg[NV][NV];     // gradient-energy species matrix: psi_g = 1/2 Mg_kl grad eta_k . grad eta_l
+  float Mg32[NV][NV];    // Mg rounded to FP32 (the FP32 matrix-free operator)
   double rho;
   double eps;
   int pade;

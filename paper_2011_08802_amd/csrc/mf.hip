@@ -48,34 +48,47 @@ __device__ __forceinline__ T lane_xor(T v) {
 
 // One direction of the trilinear interpolation at the Gauss points, by lane
 // pairs (sum factorisation).  Each lane holds n values belonging to its node
-// index bit b along this direction; afterwards it holds, at its Gauss
-// coordinate q (the same bit selects q), the interpolated values (s) and,
-// for the first nd of them, the difference across the pair (the derivative
-// along this direction on the unit reference cube).
-template <int X, typename T, int n>
-__device__ __forceinline__ void interp_pair(const T (&in)[n], bool bit, T q, T (&s)[n], T (&d)[n]) {
+// index bit b along this direction; with t = (partner's value) - (own value)
+// it gets, at its Gauss coordinate q (the same bit selects q), the
+// interpolated value s = own + qq t (qq = q for b = 0, 1 - q for b = 1) and,
+// for the first nd values, the difference across the pair, d = sg t (sg = +1
+// for b = 0, -1 for b = 1): the derivative along this direction on the unit
+// reference cube.  The partner's value enters only through the subtraction,
+// so the lane exchange folds into it (a DPP operand), and no lane selects
+// are needed.
+template <int X, typename T, int n, int nd>
+__device__ __forceinline__ void interp_pair(const T (&in)[n], T qq, T sg, T (&s)[n], T (&d)[nd]) {
 #pragma unroll
   for (int k = 0; k < n; ++k) {
-    const T other = lane_xor<X>(in[k]);
-    const T lo = bit ? other : in[k], hi = bit ? in[k] : other;
-    d[k] = hi - lo;
-    s[k] = lo + q * d[k];
+    const T t = lane_xor<X>(in[k]) - in[k];
+    s[k] = in[k] + qq * t;
+    if (k < nd) d[k] = sg * t;
   }
 }
 
 // Transpose of interp_pair: a lane at Gauss coordinate q along this
-// direction holds coefficients a (of the values) and b (of the derivatives);
-// afterwards it holds, for its node bit, the sum over both Gauss points of
-// a * phi(q) + b * phi', phi = 1 - q or q, phi' = -1 or +1.
+// direction holds coefficients a (of the values) and bs = sb * b (of the
+// derivatives, sb = -1 for node bit 0, +1 for bit 1: the sign is applied by
+// the caller where b is formed); afterwards it holds, for its node bit, the
+// sum over both Gauss points of a * phi(q) + b * phi', phi = 1 - q or q,
+// phi' = -1 or +1.  Own part a mq + bs, partner's part a tq - bs (mq = 1 - q,
+// tq = q for bit 0; mq = q, tq = 1 - q for bit 1); the exchange folds into the
+// final addition.
 template <int X, typename T, int n>
-__device__ __forceinline__ void interp_pair_t(const T (&a)[n], const T (&b)[n], bool bit, T q, T (&out)[n]) {
+__device__ __forceinline__ void interp_pair_t(const T (&a)[n], const T (&bs)[n], T mq, T tq, T (&out)[n]) {
 #pragma unroll
   for (int k = 0; k < n; ++k) {
-    const T to0 = a[k] * ((T)1 - q) - b[k];  // contribution to node bit 0
-    const T to1 = a[k] * q + b[k];           // contribution to node bit 1
-    const T mine = bit ? to1 : to0, theirs = bit ? to0 : to1;
+    const T mine = a[k] * mq + bs[k];
+    const T theirs = a[k] * tq - bs[k];
     out[k] = mine + lane_xor<X>(theirs);
   }
+}
+
+// gradient-energy coefficient Mg[m][m2] in the arithmetic type
+template <typename T>
+__device__ __forceinline__ T mg_coef(const DevCard* __restrict__ cd, int m, int m2) {
+  if constexpr (sizeof(T) == 4) return cd->Mg32[m][m2];
+  else return cd->Mg[m][m2];
 }
 
 // E = element parts of K x_e (x masked on constrained dofs when mask != null).
@@ -105,7 +118,14 @@ __device__ __forceinline__ void mf_element_body(const Grid& g, const TD* __restr
   const int64_t e = (t >> 6) * 8 + (lane >> 3);
   const bool active = e < g.NE;  // inactive lanes hold zeros and still take part in the exchanges
   const bool b0 = gp & 1, b1 = (gp >> 1) & 1, b2 = (gp >> 2) & 1;
-  const T q0 = (T)(b0 ? MGQ1 : MGQ0), q1 = (T)(b1 ? MGQ1 : MGQ0), q2 = (T)(b2 ? MGQ1 : MGQ0);
+  // per direction: qq (interpolation weight of the partner's difference) and
+  // sg (sign of the derivative) of the forward stages; mq / tq (own and
+  // partner's weight) and sb (derivative sign) of the transposed stages
+  const T one = (T)1, lo = (T)MGQ0, hi = (T)MGQ1;
+  const T qq0 = b0 ? one - hi : lo, qq1 = b1 ? one - hi : lo, qq2 = b2 ? one - hi : lo;
+  const T sg0 = b0 ? -one : one, sg1 = b1 ? -one : one, sg2 = b2 ? -one : one;
+  const T mq0 = b0 ? hi : one - lo, mq1 = b1 ? hi : one - lo, mq2 = b2 ? hi : one - lo;
+  const T tq0 = b0 ? one - hi : lo, tq1 = b1 ? one - hi : lo, tq2 = b2 ? one - hi : lo;
   const T h = (T)g.h, c1 = (T)(0.125 * g.h);
   // the unknowns of corner gp
   T xa[9];
@@ -137,17 +157,17 @@ __device__ __forceinline__ void mf_element_body(const Grid& g, const TD* __restr
   }
   // interpolation to Gauss point gp: x, then y, then z
   T s1[9], d1[9];
-  interp_pair<1>(xa, b0, q0, s1, d1);
-  T sd1[18], s2[18], d2[18];
+  interp_pair<1>(xa, qq0, sg0, s1, d1);
+  T sd1[18], s2[18], d2[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) sd1[c] = s1[c], sd1[9 + c] = d1[c];
-  interp_pair<2>(sd1, b1, q1, s2, d2);  // s2 = (value, d/dx) at (q0, q1); d2[0..8] = d/dy
-  T sd2[27], s3[27], d3[27];
+  interp_pair<2>(sd1, qq1, sg1, s2, d2);  // s2 = (value, d/dx) at (q0, q1); d2 = d/dy
+  T sd2[27], s3[27], d3[9];
 #pragma unroll
   for (int c = 0; c < 18; ++c) sd2[c] = s2[c];
 #pragma unroll
   for (int c = 0; c < 9; ++c) sd2[18 + c] = d2[c];
-  interp_pair<4>(sd2, b2, q2, s3, d3);  // s3 = (value, d/dx, d/dy); d3[0..8] = d/dz
+  interp_pair<4>(sd2, qq2, sg2, s3, d3);  // s3 = (value, d/dx, d/dy); d3 = d/dz
   // v: reference gradients of u (3 x 3), h * eta (6); ge: reference gradients of eta
   T v[15], ge[18];
 #pragma unroll
@@ -192,37 +212,41 @@ __device__ __forceinline__ void mf_element_body(const Grid& g, const TD* __restr
     for (int j = 0; j < 3; ++j) {
       T sum = 0;
 #pragma unroll
-      for (int m2 = 0; m2 < 6; ++m2) sum += (T)cd->Mg[m][m2] * ge[3 * m2 + j];
+      for (int m2 = 0; m2 < 6; ++m2) sum += mg_coef<T>(cd, m, m2) * ge[3 * m2 + j];
       z[3 * m + j] = sum;
     }
   // coefficients of point gp: a = of the shape-function values, (bx, by, bz)
-  // = of their reference derivatives, per component
+  // = of their reference derivatives, per component, each derivative
+  // coefficient carrying the transposed stage's sign of its direction (the
+  // x and y coefficients keep it through the z and y stages, whose lane
+  // partners share the lane's x and y bits)
+  const T cx = b0 ? c1 : -c1, cy = b1 ? c1 : -c1, cz = b2 ? c1 : -c1;
   T a3[27], bz[27];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    a3[c] = 0, a3[9 + c] = c1 * w[3 * c], a3[18 + c] = c1 * w[3 * c + 1];
-    bz[c] = c1 * w[3 * c + 2];
+    a3[c] = 0, a3[9 + c] = cx * w[3 * c], a3[18 + c] = cy * w[3 * c + 1];
+    bz[c] = cz * w[3 * c + 2];
   }
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
-    a3[3 + m] = c1 * h * w[9 + m], a3[12 + m] = c1 * z[3 * m], a3[21 + m] = c1 * z[3 * m + 1];
-    bz[3 + m] = c1 * z[3 * m + 2];
+    a3[3 + m] = c1 * h * w[9 + m], a3[12 + m] = cx * z[3 * m], a3[21 + m] = cy * z[3 * m + 1];
+    bz[3 + m] = cz * z[3 * m + 2];
   }
 #pragma unroll
   for (int c = 0; c < 9; ++c) bz[9 + c] = 0, bz[18 + c] = 0;
   // back to the corners: z (27 sums: value, x, y coefficients), then y, then x
   T r3[27];
-  interp_pair_t<4>(a3, bz, b2, q2, r3);
+  interp_pair_t<4>(a3, bz, mq2, tq2, r3);
   T a2[18], by[18], r2[18];
 #pragma unroll
   for (int c = 0; c < 18; ++c) a2[c] = r3[c], by[c] = 0;
 #pragma unroll
   for (int c = 0; c < 9; ++c) by[c] = r3[18 + c];
-  interp_pair_t<2>(a2, by, b1, q1, r2);
+  interp_pair_t<2>(a2, by, mq1, tq1, r2);
   T a1[9], bx[9], out[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) a1[c] = r2[c], bx[c] = r2[9 + c];
-  interp_pair_t<1>(a1, bx, b0, q0, out);
+  interp_pair_t<1>(a1, bx, mq0, tq0, out);
   if (active) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) E[eo_index(gp, c, node, g.Npad)] = out[c];
