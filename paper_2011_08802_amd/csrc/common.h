@@ -114,8 +114,10 @@ __device__ __forceinline__ int xcd_logical(int b, int nb_pad) {
   return (b & 7) * per + (b >> 3);
 }
 
-// element node pair a <= b < 8 -> 0..35
+// element node pair a <= b < 8 -> 0..35, and back
 __host__ __device__ constexpr int pair_index(int a, int b) { return a * 8 - (a * (a - 1)) / 2 + (b - a); }
+__host__ __device__ constexpr int pair_a(int p) { return p < 8 ? 0 : p < 15 ? 1 : p < 21 ? 2 : p < 26 ? 3 : p < 30 ? 4 : p < 33 ? 5 : p < 35 ? 6 : 7; }
+__host__ __device__ constexpr int pair_b(int p) { return pair_a(p) + p - pair_index(pair_a(p), pair_a(p)); }
 
 // Matrix-free finest level: Gauss-point Hessian entry k (packed upper
 // triangle, 0..119) of point g of element e in storage type T, and the
@@ -123,15 +125,16 @@ __host__ __device__ constexpr int pair_index(int a, int b) { return a * 8 - (a *
 // groups of V = 16 / sizeof(T) per lane (one 16-byte load) and 64 lanes
 // (8 elements x 8 points) per group, so a wavefront reads 1 KB contiguous
 // (and, wave-contiguous, the 8 elements' 120 x 64 entries in one span).
-// Element outputs are stored per corner a and indexed by the corner's node n
-// (each (a, n) names one element), so a gather over consecutive nodes reads
-// consecutive addresses.
+// Element outputs are stored per corner a and unknown c, indexed by the
+// element: a workgroup of consecutive elements writes whole aligned lines of
+// each stream, and a gather over consecutive nodes reads consecutive
+// elements of each stream (one gap per node row).
 template <typename T>
 __host__ __device__ inline int64_t mf_index(int64_t NEpad, int k, int g, int64_t e) {
   constexpr int V = 16 / (int)sizeof(T);
   return ((((e >> 3) * (NHP / V) + k / V) * 64) + g * 8 + (e & 7)) * V + k % V;
 }
-__host__ __device__ inline int64_t eo_index(int a, int c, int64_t n, int64_t Npad) { return (int64_t)(a * NDOF + c) * Npad + n; }
+__host__ __device__ inline int64_t eo_index(int a, int c, int64_t e, int64_t NEpad) { return (int64_t)(a * NDOF + c) * NEpad + e; }
 
 // Rigid spherical indenter: centre (cx, cy, cz), radius R, contact penalty eps.
 struct Sphere {

@@ -145,11 +145,9 @@ __global__ void __launch_bounds__(256) contact_apply_kernel(Grid g, const Sphere
   const int64_t e = (int64_t)(g.nz - 1) * g.nx * g.ny + t;
   const double w = 0.25 * g.h * g.h * s.eps;
   double xb[4][3];
-  int nodes[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int node = (fi + (a & 1)) + g.nnx * ((fj + (a >> 1)) + g.nny * g.nz);
-    nodes[a] = node;
     const unsigned mb = mask ? mask[node] : 0u;
 #pragma unroll
     for (int c = 0; c < 3; ++c) xb[a][c] = ((mb >> c) & 1) ? 0.0 : (double)x[(int64_t)c * g.Npad + node];
@@ -182,7 +180,7 @@ __global__ void __launch_bounds__(256) contact_apply_kernel(Grid g, const Sphere
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) E[eo_index(4 + a, c, nodes[a], g.Npad)] += (T)out[a][c];
+    for (int c = 0; c < 3; ++c) E[eo_index(4 + a, c, e, g.NEpad)] += (T)out[a][c];
 }
 
 // P = sum over active face points of w eps g n_z (one workgroup, fixed order)

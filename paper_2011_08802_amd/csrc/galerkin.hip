@@ -55,69 +55,111 @@ template <int S, int a, int b, int... I>
 __device__ __forceinline__ void gal_terms(double k, double (&acc)[NPAIR], std::integer_sequence<int, I...>) {
   (gal_term<S, a, b, I>(k, acc), ...);
 }
-// ordered child corner pair J = 8 a + b: entry (c, c2) of the child's block
-// K_ab (the stored pair (a, b), or the transpose of (b, a)), zero where
-// dof c of corner a or dof c2 of corner b is constrained
-template <int S, int J>
-__device__ __forceinline__ void gal_child_pair(const double* __restrict__ Ee, int64_t es, int q, int qt, uint32_t fa,
-                                               uint32_t fb, double (&acc)[NPAIR]) {
-  constexpr int a = J >> 3, b = J & 7;
-  const double k = a <= b ? Ee[((int64_t)pair_index(a, b) * NBLK + q) * es]
-                          : Ee[((int64_t)pair_index(b, a) * NBLK + qt) * es];
+// the ordered child corner pair (a, b) contributes entry (c, c2) of K_ab to
+// entry (c, c2) of the parent blocks, zero where dof c of corner a or dof c2
+// of corner b is constrained (fa, fb: free bits of dofs c and c2)
+template <int S, int a, int b>
+__device__ __forceinline__ void gal_add(double k, uint32_t fa, uint32_t fb, double (&acc)[NPAIR]) {
   const bool keep = ((fa >> gal_node(S, a)) & (fb >> gal_node(S, b)) & 1u) != 0u;
   gal_terms<S, a, b>(keep ? k : 0.0, acc, std::make_integer_sequence<int, 64>{});
 }
-template <int S, int... J>
-__device__ __forceinline__ void gal_child(const double* __restrict__ Ee, int64_t es, int q, int qt, uint32_t fa,
-                                          uint32_t fb, double (&acc)[NPAIR], std::integer_sequence<int, J...>) {
-  (gal_child_pair<S, J>(Ee, es, q, qt, fa, fb, acc), ...);
+// stored child pair P (a <= b): its entries q = (c, c2) and qt = (c2, c),
+// i.e. K_ab[c][c2] and K_ab[c2][c], are also K_ba[c2][c] and K_ba[c][c2];
+// the lane accumulates entry q (accq) and, off the diagonal of the blocks,
+// entry qt (acct) of the parent pairs, so each child entry is read once
+template <int S, bool DIAG, int P>
+__device__ __forceinline__ void gal_child_pair(const double* __restrict__ Ee, int64_t es, int q, int qt, uint32_t fc,
+                                               uint32_t fc2, double (&accq)[NPAIR], double (&acct)[NPAIR]) {
+  constexpr int a = pair_a(P), b = pair_b(P);
+  const double kq = Ee[((int64_t)P * NBLK + q) * es];
+  if constexpr (DIAG) {  // c == c2: K_ab[c][c] = K_ba[c][c]
+    gal_add<S, a, b>(kq, fc, fc, accq);
+    if constexpr (a != b) gal_add<S, b, a>(kq, fc, fc, accq);
+  } else {
+    const double kt = Ee[((int64_t)P * NBLK + qt) * es];
+    gal_add<S, a, b>(kq, fc, fc2, accq);   // K_ab[c][c2]
+    gal_add<S, a, b>(kt, fc2, fc, acct);   // K_ab[c2][c]
+    if constexpr (a != b) {
+      gal_add<S, b, a>(kt, fc, fc2, accq);  // K_ba[c][c2] = K_ab[c2][c]
+      gal_add<S, b, a>(kq, fc2, fc, acct);  // K_ba[c2][c] = K_ab[c][c2]
+    }
+  }
+}
+template <int S, bool DIAG, int... P>
+__device__ __forceinline__ void gal_child(const double* __restrict__ Ee, int64_t es, int q, int qt, uint32_t fc,
+                                          uint32_t fc2, double (&accq)[NPAIR], double (&acct)[NPAIR],
+                                          std::integer_sequence<int, P...>) {
+  (gal_child_pair<S, DIAG, P>(Ee, es, q, qt, fc, fc2, accq, acct), ...);
 }
 
-// One wavefront per 64 consecutive parents and one entry q = NDOF c + c2 of
-// the NDOF x NDOF blocks: each lane accumulates entry q of the 36 stored node
-// pairs of its parent over the 8 children and their 64 ordered corner pairs,
-// in a fixed order (bitwise reproducible).  The NBLK wavefronts of one parent
-// group are consecutive logical workgroups on one XCD, so the child entries
-// that entries q and its transpose both read meet in that XCD's L2.
-// Child element matrices: chunk-local, Ec[(p NBLK + q) es + e - e0];
+// Block entries handled together: the diagonal ones (c, c) alone, the others
+// as the pairs (c, c2), (c2, c) with c < c2: NDOF (NDOF + 1) / 2 tasks.
+constexpr int GAL_TASKS = NDOF * (NDOF + 1) / 2;
+__device__ __forceinline__ void gal_task(int task, int& c, int& c2) {
+  c = 0;
+  while (task >= NDOF - c) { task -= NDOF - c; ++c; }
+  c2 = c + task;
+}
+
+template <bool DIAG>
+__device__ __forceinline__ void gal_parent(const Grid& gc, const Chunk& ckc, const double* __restrict__ Ec,
+                                           const Grid& gp, int64_t E, int c, int c2, uint32_t fc, uint32_t fc2,
+                                           double* __restrict__ Ep) {
+  const int q = NDOF * c + c2, qt = NDOF * c2 + c;
+  const int X = (int)(E % gp.nx), Y = (int)((E / gp.nx) % gp.ny), Z = (int)(E / ((int64_t)gp.nx * gp.ny));
+  double accq[NPAIR], acct[NPAIR];
+#pragma unroll
+  for (int p = 0; p < NPAIR; ++p) accq[p] = acct[p] = 0.0;
+  const int64_t es = ckc.NEcpad;
+  const int64_t nxc = gc.nx, nxyc = (int64_t)gc.nx * gc.ny;
+  const int64_t e00 = 2 * X + nxc * 2 * Y + nxyc * 2 * Z - ckc.e0;  // child 0, chunk-local
+  const std::make_integer_sequence<int, NPAIR> pairs{};
+  gal_child<0, DIAG>(Ec + e00, es, q, qt, fc, fc2, accq, acct, pairs);
+  gal_child<1, DIAG>(Ec + e00 + 1, es, q, qt, fc, fc2, accq, acct, pairs);
+  gal_child<2, DIAG>(Ec + e00 + nxc, es, q, qt, fc, fc2, accq, acct, pairs);
+  gal_child<3, DIAG>(Ec + e00 + nxc + 1, es, q, qt, fc, fc2, accq, acct, pairs);
+  gal_child<4, DIAG>(Ec + e00 + nxyc, es, q, qt, fc, fc2, accq, acct, pairs);
+  gal_child<5, DIAG>(Ec + e00 + nxyc + 1, es, q, qt, fc, fc2, accq, acct, pairs);
+  gal_child<6, DIAG>(Ec + e00 + nxyc + nxc, es, q, qt, fc, fc2, accq, acct, pairs);
+  gal_child<7, DIAG>(Ec + e00 + nxyc + nxc + 1, es, q, qt, fc, fc2, accq, acct, pairs);
+#pragma unroll
+  for (int p = 0; p < NPAIR; ++p) Ep[((int64_t)p * NBLK + q) * gp.NEpad + E] = accq[p];
+  if constexpr (!DIAG) {
+#pragma unroll
+    for (int p = 0; p < NPAIR; ++p) Ep[((int64_t)p * NBLK + qt) * gp.NEpad + E] = acct[p];
+  }
+}
+
+// One wavefront per 64 consecutive parents and one task: block entry (c, c)
+// or the entry pair (c, c2), (c2, c).  Each lane accumulates those entries of
+// its parent's 36 node pairs over the 8 children and their corner pairs, in
+// a fixed order (bitwise reproducible), reading each child entry it needs
+// once.  The tasks of one parent group are consecutive logical workgroups on
+// one XCD.  Child element matrices: chunk-local, Ec[(p NBLK + q) es + e - e0];
 // parents: whole level, Ep[(P NBLK + q) NEpad + E], E in [E0, E1).
 __global__ void __launch_bounds__(64) galerkin_coarsen_kernel(Grid gc, Chunk ckc, const double* __restrict__ Ec,
                                                              const uint16_t* __restrict__ maskc, Grid gp,
                                                              int64_t E0, int64_t E1, int nwork, double* __restrict__ Ep) {
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= nwork) return;
-  const int q = L % NBLK;
-  const int c = q / NDOF, c2 = q % NDOF;
-  const int qt = c2 * NDOF + c;
-  const int64_t E = E0 + (int64_t)(L / NBLK) * 64 + threadIdx.x;
+  int c, c2;
+  gal_task(L % GAL_TASKS, c, c2);
+  const int64_t E = E0 + (int64_t)(L / GAL_TASKS) * 64 + threadIdx.x;
   if (E >= E1) return;
   const int X = (int)(E % gp.nx), Y = (int)((E / gp.nx) % gp.ny), Z = (int)(E / ((int64_t)gp.nx * gp.ny));
-  // free bits of dof c (fa) and dof c2 (fb) of the parent's 27 child-level nodes
-  uint32_t fa = 0, fb = 0;
+  // free bits of dofs c (fc) and c2 (fc2) of the parent's 27 child-level nodes
+  uint32_t fc = 0, fc2 = 0;
 #pragma unroll
   for (int k = 0; k < 27; ++k) {
     const int64_t node = (2 * X + k % 3) + (int64_t)gc.nnx * ((2 * Y + (k / 3) % 3) + (int64_t)gc.nny * (2 * Z + k / 9));
     const uint32_t m = maskc[node];
-    fa |= ((~m >> c) & 1u) << k;
-    fb |= ((~m >> c2) & 1u) << k;
+    fc |= ((~m >> c) & 1u) << k;
+    fc2 |= ((~m >> c2) & 1u) << k;
   }
-  double acc[NPAIR];
-#pragma unroll
-  for (int p = 0; p < NPAIR; ++p) acc[p] = 0.0;
-  const int64_t es = ckc.NEcpad;
-  const int64_t nxc = gc.nx, nxyc = (int64_t)gc.nx * gc.ny;
-  const int64_t e00 = 2 * X + nxc * 2 * Y + nxyc * 2 * Z - ckc.e0;  // child 0, chunk-local
-  const std::make_integer_sequence<int, 64> corner_pairs{};
-  gal_child<0>(Ec + e00, es, q, qt, fa, fb, acc, corner_pairs);
-  gal_child<1>(Ec + e00 + 1, es, q, qt, fa, fb, acc, corner_pairs);
-  gal_child<2>(Ec + e00 + nxc, es, q, qt, fa, fb, acc, corner_pairs);
-  gal_child<3>(Ec + e00 + nxc + 1, es, q, qt, fa, fb, acc, corner_pairs);
-  gal_child<4>(Ec + e00 + nxyc, es, q, qt, fa, fb, acc, corner_pairs);
-  gal_child<5>(Ec + e00 + nxyc + 1, es, q, qt, fa, fb, acc, corner_pairs);
-  gal_child<6>(Ec + e00 + nxyc + nxc, es, q, qt, fa, fb, acc, corner_pairs);
-  gal_child<7>(Ec + e00 + nxyc + nxc + 1, es, q, qt, fa, fb, acc, corner_pairs);
-#pragma unroll
-  for (int p = 0; p < NPAIR; ++p) Ep[((int64_t)p * NBLK + q) * gp.NEpad + E] = acc[p];
+  if (c == c2)
+    gal_parent<true>(gc, ckc, Ec, gp, E, c, c2, fc, fc2, Ep);
+  else
+    gal_parent<false>(gc, ckc, Ec, gp, E, c, c2, fc, fc2, Ep);
 }
 
 void launch_galerkin_coarsen(const Grid& gc, const Chunk& ckc, const double* Ec, const uint16_t* maskc,
@@ -125,7 +167,7 @@ void launch_galerkin_coarsen(const Grid& gc, const Chunk& ckc, const double* Ec,
   const int64_t nxy = (int64_t)gp.nx * gp.ny;
   const int64_t E0 = Z0 * nxy, E1 = Z1 * nxy;
   if (E1 <= E0) return;
-  const int64_t nwork = (E1 - E0 + 63) / 64 * NBLK;
+  const int64_t nwork = (E1 - E0 + 63) / 64 * GAL_TASKS;
   const int blocks = (int)((nwork + 7) / 8 * 8);
   galerkin_coarsen_kernel<<<blocks, 64, 0, s>>>(gc, ckc, Ec, maskc, gp, E0, E1, (int)nwork, Ep);
 }

@@ -84,6 +84,9 @@ __device__ __forceinline__ void interp_pair_t(const T (&a)[n], const T (&bs)[n],
   }
 }
 
+// elements per workgroup of the element kernels: 8, 16 or 32
+constexpr int MF_MAX_EPW = 32;
+
 // gradient-energy coefficient Mg[m][m2] in the arithmetic type
 template <typename T>
 __device__ __forceinline__ T mg_coef(const DevCard* __restrict__ cd, int m, int m2) {
@@ -247,9 +250,22 @@ __device__ __forceinline__ void mf_element_body(const Grid& g, const TD* __restr
 #pragma unroll
   for (int c = 0; c < 9; ++c) a1[c] = r2[c], bx[c] = r2[9 + c];
   interp_pair_t<1>(a1, bx, mq0, tq0, out);
-  if (active) {
+  // Element outputs through LDS: a lane holds corner gp's 9 values, which in
+  // its wavefront would make 8-element (32-byte) pieces of each stream
+  // (gp, c); staged per stream, the workgroup's epw consecutive elements go
+  // out as one contiguous, aligned run of each stream per store (whole
+  // 128-byte lines at 32 elements in FP32).  Every lane of the workgroup
+  // reaches the barrier.
+  __shared__ T eo[72 * (MF_MAX_EPW + 1)];
+  const int epw = blockDim.x >> 3;
+  const int jw = threadIdx.x >> 3;  // element within the workgroup
 #pragma unroll
-    for (int c = 0; c < 9; ++c) E[eo_index(gp, c, node, g.Npad)] = out[c];
+  for (int c = 0; c < 9; ++c) eo[(gp * 9 + c) * (epw + 1) + jw] = out[c];
+  __syncthreads();
+  const int64_t ew = (int64_t)bid * epw;  // the workgroup's first element
+  for (int idx = threadIdx.x; idx < 72 * epw; idx += blockDim.x) {
+    const int s = idx / epw, jj = idx - s * epw;  // stream s = 9 a + c
+    if (ew + jj < g.NE) E[(int64_t)s * g.NEpad + ew + jj] = eo[s * (epw + 1) + jj];
   }
 }
 template <typename TD, typename TX, typename T, int MINB, int PF, bool SPARSE>
@@ -279,8 +295,9 @@ __device__ __forceinline__ void mf_gather_body(const Grid& g, const T* __restric
   for (int a = 7; a >= 0; --a) {  // element (i - ax, j - ay, k - az) has this node as corner a
     const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - ((a >> 2) & 1);
     if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || ez < 0 || ez >= g.nz) continue;
+    const int64_t e = ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) s[c] += E[eo_index(a, c, n, g.Npad)];
+    for (int c = 0; c < 9; ++c) s[c] += E[eo_index(a, c, e, g.NEpad)];
   }
   const unsigned mb = mask ? mask[n] : 0u;
   T r[9];

@@ -440,16 +440,92 @@ void launch_apply_dirichlet(const Grid& g, const uint16_t* mask, double* A64, fl
 
 // NDOF x NDOF inverse by Gauss-Jordan elimination with partial pivoting (the
 // paper's point-block Jacobi inverts each block by LU with partial
-// pivoting).  Each thread keeps its augmented [A | I] in LDS, lane-interleaved.
-constexpr int BI_THREADS = NDOF <= 9 ? 32 : 16;  // 32 x 9 x 18 doubles = 41 KB of LDS per block (N = 6)
+// pivoting).  Pivot: the largest magnitude in the column among the rows not
+// yet pivoted, ties to the lowest row.
+//  * NDOF <= 9: one thread per block, the matrix in registers and inverted in
+//    place (Gauss-Jordan on A itself: the pivot row is scaled with the
+//    reciprocal on the diagonal, the other rows eliminated with the negated
+//    multiples in the pivot column); the row interchanges are selects over
+//    the rows below, and are undone as column interchanges in reverse order
+//    (the steps invert P A, and A^-1 = (P A)^-1 P), applied as the columns'
+//    store positions.
+//  * larger blocks: each thread keeps its augmented [A | I] in LDS,
+//    lane-interleaved (registers would not hold it).
+constexpr bool BI_REGS = NDOF <= 9;
+constexpr int BI_THREADS = BI_REGS ? 64 : 16;
 
-__device__ __forceinline__ void block_inverse_body(const Grid& g, const double* __restrict__ diag64,
+__device__ __forceinline__ void block_inverse_regs(const Grid& g, const double* __restrict__ diag64,
                                                    double* __restrict__ Dinv64, float* __restrict__ Dinv32,
-                                                   int* status, int bid) {
+                                                   int* status, int n) {
+  const int t = n / TILE, l = n % TILE;
+  const int64_t db = (int64_t)t * Lay<double>::SLICE;
+  const int64_t db32 = (int64_t)t * Lay<float>::SLICE;
+  bool ok = n < g.N;
+  double A[NDOF][NDOF];
+#pragma unroll
+  for (int r = 0; r < NDOF; ++r)
+#pragma unroll
+    for (int c = 0; c < NDOF; ++c) A[r][c] = ok ? diag64[db + Lay<double>::off(NDOF * r + c, l)] : 0.0;
+  int piv[NDOF];
+#pragma unroll
+  for (int k = 0; k < NDOF; ++k) {
+    int p = k;
+    double best = fabs(A[k][k]);
+#pragma unroll
+    for (int r = k + 1; r < NDOF; ++r) {
+      const double v = fabs(A[r][k]);
+      if (v > best) { best = v; p = r; }
+    }
+    piv[k] = p;
+    ok = ok && best > 0.0;
+#pragma unroll
+    for (int r = k + 1; r < NDOF; ++r) {
+      const bool sw = p == r;
+#pragma unroll
+      for (int c = 0; c < NDOF; ++c) {
+        const double a = A[k][c], b = A[r][c];
+        A[k][c] = sw ? b : a;
+        A[r][c] = sw ? a : b;
+      }
+    }
+    const double ip = 1.0 / (ok ? A[k][k] : 1.0);
+#pragma unroll
+    for (int c = 0; c < NDOF; ++c) A[k][c] = (c == k) ? ip : A[k][c] * ip;
+#pragma unroll
+    for (int r = 0; r < NDOF; ++r) {
+      if (r == k) continue;
+      const double f = A[r][k];
+#pragma unroll
+      for (int c = 0; c < NDOF; ++c) A[r][c] = (c == k) ? -f * ip : A[r][c] - f * A[k][c];
+    }
+  }
+  // column interchanges k <-> piv[k] in reverse order, applied through the
+  // store: column m of the registers goes to column dst[m] of the inverse
+  int dst[NDOF];
+#pragma unroll
+  for (int m = 0; m < NDOF; ++m) dst[m] = m;
+#pragma unroll
+  for (int k = NDOF - 1; k >= 0; --k) {
+    const int p = piv[k];
+#pragma unroll
+    for (int m = 0; m < NDOF; ++m) dst[m] = dst[m] == k ? p : (dst[m] == p ? k : dst[m]);
+  }
+  if (n < g.N && !ok) atomicOr(status, 1);
+#pragma unroll
+  for (int r = 0; r < NDOF; ++r)
+#pragma unroll
+    for (int m = 0; m < NDOF; ++m) {
+      const double v = ok ? A[r][m] : 0.0;
+      if (Dinv64) Dinv64[db + Lay<double>::off(NDOF * r + dst[m], l)] = v;
+      if (Dinv32) Dinv32[db32 + Lay<float>::off(NDOF * r + dst[m], l)] = (float)v;
+    }
+}
+
+__device__ __forceinline__ void block_inverse_lds(const Grid& g, const double* __restrict__ diag64,
+                                                  double* __restrict__ Dinv64, float* __restrict__ Dinv32,
+                                                  int* status, int n) {
   __shared__ double M[NDOF * 2 * NDOF * BI_THREADS];
-  const int n = bid * BI_THREADS + threadIdx.x;
   const int t = n / TILE, l = n % TILE, lt = threadIdx.x;
-  if (n >= g.Npad) return;
   const int64_t db = (int64_t)t * Lay<double>::SLICE;
   const int64_t db32 = (int64_t)t * Lay<float>::SLICE;
 #define MM(r, c) M[((r) * 2 * NDOF + (c)) * BI_THREADS + lt]
@@ -491,6 +567,17 @@ __device__ __forceinline__ void block_inverse_body(const Grid& g, const double* 
     if (Dinv32) Dinv32[db32 + Lay<float>::off(e, l)] = (float)v;
   }
 #undef MM
+}
+
+__device__ __forceinline__ void block_inverse_body(const Grid& g, const double* __restrict__ diag64,
+                                                   double* __restrict__ Dinv64, float* __restrict__ Dinv32,
+                                                   int* status, int bid) {
+  const int n = bid * BI_THREADS + threadIdx.x;
+  if (n >= g.Npad) return;
+  if constexpr (BI_REGS)
+    block_inverse_regs(g, diag64, Dinv64, Dinv32, status, n);
+  else
+    block_inverse_lds(g, diag64, Dinv64, Dinv32, status, n);
 }
 __global__ void __launch_bounds__(BI_THREADS) block_inverse_kernel(Grid g, const double* __restrict__ diag64,
                                                                    double* __restrict__ Dinv64,
