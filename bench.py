@@ -634,6 +634,9 @@ def main():
     ap.add_argument("--sweeps", type=int, default=0,
                     help="pre- and post-smoothing sweeps (default: 2; indentation workload 4)")
     ap.add_argument("--levels", type=int, default=0, help="multigrid levels (default: the workload's)")
+    ap.add_argument("--pre", type=int, default=-1, help="pre-smoothing sweeps (overrides --sweeps)")
+    ap.add_argument("--post", type=int, default=-1, help="post-smoothing sweeps (overrides --sweeps)")
+    ap.add_argument("--omega", type=float, default=0.0, help="smoother damping (default 0.55)")
     ap.add_argument("--restart", type=int, default=0,
                     help="FGMRES restart length (default: 30; indentation workload 60)")
     ap.add_argument("--indent-depth", type=float, default=0.0,
@@ -688,7 +691,13 @@ def single_main(a):
         solver.update(nu_pre=a.sweeps, nu_post=a.sweeps)
     if a.restart > 0:
         solver.update(restart=a.restart)
-    nu, restart = solver.get("nu_pre", 2), solver.get("restart", 30)
+    if a.pre >= 0:
+        solver.update(nu_pre=a.pre)
+    if a.post >= 0:
+        solver.update(nu_post=a.post)
+    if a.omega > 0:
+        solver.update(omega=a.omega)
+    nu, nu2, restart = solver.get("nu_pre", 2), solver.get("nu_post", 2), solver.get("restart", 30)
     mixed = run_sequence(prob, "mixed", W, K, not a.no_timing, not a.no_tune, a.matrix_free, snapshot_at=W,
                          tag="mixed", coarse=a.coarse, **solver)
     x1m = mixed.pop("x1")
@@ -733,7 +742,8 @@ def single_main(a):
         "data": "synthetic",
         "config": {"workload": f"{'patch' if prob.kind == 'patch' else 'spherical-cap'} indentation "
                                f"{prob.nx}x{prob.ny}x{prob.nz} Q1 hex ({prob.lx:g}x{prob.ly:g}x{prob.lz:g}), "
-                               f"{ndof} dof, {prob.n_levels}-level GMG V({nu},{nu}) ({a.coarse} coarse operators), "
+                               f"{ndof} dof, {prob.n_levels}-level GMG V({nu},{nu2}) damping {solver.get('omega', 0.55)} "
+                               f"({a.coarse} coarse operators), "
                                f"FGMRES({restart}) rtol 1e-8; "
                                f"{prob.steps} load steps of {prob.depth_increment}; a step = one Newton "
                                f"iteration of the running load-step sequence (Newton rtol 1e-9), iterations "
