@@ -404,7 +404,8 @@ def indent_main(a):
     # once martensite forms the systems are much harder than the patch workload's: V(4,4) with
     # damping 0.4 and FGMRES(60) take the whole run from 125 s (V(3,3), 0.5, FGMRES(30)) to 80 s
     nu = a.sweeps if a.sweeps > 0 else 4
-    sweeps = dict(nu_pre=nu, nu_post=nu, omega=0.4, restart=a.restart if a.restart > 0 else 60)
+    sweeps = dict(nu_pre=nu, nu_post=nu, omega=a.omega if a.omega > 0 else 0.4,
+                  restart=a.restart if a.restart > 0 else 60)
     log(f"[bench] indentation workload: {prob.nx}x{prob.ny}x{prob.nz}, {ndof} dof, run {run}, smoother {sweeps}")
     res = {}
     for prec in ("mixed",) + (() if a.no_fp64 else ("fp64",)):
@@ -466,7 +467,8 @@ def indent_main(a):
                                f"{ndof} dof, rigid sphere R={prob.radius} in penalty contact "
                                f"(eps_N={prob.eps_n:g}), load to {run['depth_max']} and unload, adaptive "
                                f"steps (7 desired / 12 max Newton iterations), {prob.n_levels}-level GMG "
-                               f"V({nu},{nu}) damping 0.4, FGMRES(60) rtol 1e-8; a step = one whole "
+                               f"V({nu},{nu}) damping {sweeps['omega']}, FGMRES({sweeps['restart']}) rtol 1e-8; "
+                               f"a step = one whole "
                                f"run; value = dof x Newton iterations per second", "precision": "mixed",
                    "levels": prob.n_levels, "coarse": a.coarse, **run},
         "mixed": ms,

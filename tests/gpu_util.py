@@ -136,3 +136,65 @@ def check_entries(a, b, tol, what, scale=None, ndof=NDOF):
 def abs_product(A, x):
     """(|A| |x|): the per-entry rounding scale of the product A x."""
     return abs(A) @ np.abs(np.asarray(x, dtype=float).ravel())
+
+
+def prolong_nodal(xc, shape_c):
+    """Trilinear prolongation of node-interleaved values (n_nodes_c, ndof) on
+    a structured grid of shape_c = (nzc, nyc, nxc) elements to the grid twice
+    as fine (the V-cycle's P; coarse node (I, J, K) = fine node (2I, 2J, 2K))."""
+    nzc, nyc, nxc = shape_c
+    c = np.asarray(xc, dtype=float).reshape(nzc + 1, nyc + 1, nxc + 1, -1)
+    for ax in range(3):
+        n = c.shape[ax]
+        f = np.empty(c.shape[:ax] + (2 * n - 1,) + c.shape[ax + 1:])
+        sl = [slice(None)] * 4
+        sl[ax] = slice(0, None, 2)
+        f[tuple(sl)] = c
+        lo = [slice(None)] * 4
+        hi = [slice(None)] * 4
+        lo[ax], hi[ax] = slice(0, n - 1), slice(1, n)
+        sl[ax] = slice(1, None, 2)
+        f[tuple(sl)] = 0.5 * (c[tuple(lo)] + c[tuple(hi)])
+        c = f
+    return c.reshape(-1, c.shape[-1])
+
+
+def restrict_nodal(yf, shape_c):
+    """The transpose of prolong_nodal (fine grid of 2 shape_c elements)."""
+    nzc, nyc, nxc = shape_c
+    f = np.asarray(yf, dtype=float).reshape(2 * nzc + 1, 2 * nyc + 1, 2 * nxc + 1, -1)
+    for ax in range(3):
+        sl = [slice(None)] * 4
+        sl[ax] = slice(0, None, 2)
+        c = f[tuple(sl)].copy()
+        sl[ax] = slice(1, None, 2)
+        odd = 0.5 * f[tuple(sl)]
+        lo = [slice(None)] * 4
+        hi = [slice(None)] * 4
+        lo[ax], hi[ax] = slice(0, -1), slice(1, None)
+        c[tuple(lo)] += odd
+        c[tuple(hi)] += odd
+        f = c
+    return f.reshape(-1, f.shape[-1])
+
+
+def galerkin_apply(apply_fine, xc, shape_c, mask_f, mask_c):
+    """A_c x_c of the eliminated Galerkin operator A_c = P~^T A_f P~ (P~ = P
+    with the rows of constrained fine dofs zeroed) from a product with the
+    eliminated fine operator (apply_fine: flat fine vector -> flat product):
+    free coarse rows (P~^T A_f P~ x~)_free with x~ = x_c zeroed on the
+    constrained coarse dofs; constrained rows x_c."""
+    ndof = mask_c.shape[1]
+    x = np.where(mask_c, 0.0, np.asarray(xc, dtype=float).reshape(-1, ndof))
+    xf = np.where(mask_f, 0.0, prolong_nodal(x, shape_c))
+    yf = np.asarray(apply_fine(xf.ravel()), dtype=float).reshape(-1, ndof)
+    yc = restrict_nodal(np.where(mask_f, 0.0, yf), shape_c)
+    return np.where(mask_c, np.asarray(xc, dtype=float).reshape(-1, ndof), yc).ravel()
+
+
+def coarse_masks(mask0, shape0, n_levels):
+    """Constrained-dof masks of every level: a coarse dof is constrained iff
+    its coincident finest dof is."""
+    nz, ny, nx = shape0
+    m3 = np.asarray(mask0).reshape(nz + 1, ny + 1, nx + 1, -1)
+    return [m3[::2 ** l, ::2 ** l, ::2 ** l].reshape(-1, m3.shape[-1]) for l in range(n_levels)]

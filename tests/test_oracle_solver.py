@@ -261,3 +261,41 @@ def test_galerkin_coarse_correction_is_orthogonal():
     assert np.linalg.norm(after) <= 1e-11 * np.linalg.norm(before)
     # the penalty is active at some Gauss points (the state is not uniform)
     assert (U.reshape(-1, NDOF)[:, 3:] < 0).any()
+
+
+def test_nodal_transfers_used_by_the_full_size_galerkin_check():
+    """The numpy transfers of the GPU tests' full-size Galerkin check are the
+    oracle's prolongation and its transpose (same matrix, compared on random
+    vectors), on a non-cubic grid with several unknowns per node."""
+    from gpu_util import prolong_nodal, restrict_nodal
+    fine, coarse = Mesh(6, 4, 8, 0.1), Mesh(3, 2, 4, 0.2)
+    P = S.prolongation(coarse, fine, bs=1)
+    rng = np.random.default_rng(11)
+    xc = rng.standard_normal((coarse.n_nodes, 3))
+    yf = rng.standard_normal((fine.n_nodes, 3))
+    assert np.allclose(prolong_nodal(xc, (4, 2, 3)), P @ xc, rtol=0, atol=1e-14)
+    assert np.allclose(restrict_nodal(yf, (4, 2, 3)), P.T @ yf, rtol=0, atol=1e-13)
+
+
+def test_full_size_galerkin_rows_from_local_elements():
+    """The full-size GPU tests' sampled Galerkin rows (finest elements around
+    the support of each sampled coarse node's column of the composite
+    prolongation) reproduce the rows of the oracle's assembled Galerkin
+    hierarchy on levels 1 and 2, and their rounding scale bounds |A_l| |x|."""
+    from oracle.fem import NDOF
+    from gpu_util import OracleCase
+    from test_gpu_fullsize import GalerkinRows, sample_nodes
+    p = synth.Problem(16, 16, 8, lz=0.5, n_levels=3, kind="cap", radius=0.2, depth_increment=0.02)
+    m = Mesh.from_problem(p)
+    U = np.zeros((m.n_nodes, NDOF))
+    U[:, 3:] = p.eta0()
+    oc = OracleCase(p, U, U[:, 3:], p.depth_increment, coarse="galerkin", direct=False)
+    rng = np.random.default_rng(1)
+    for l in (1, 2):
+        cm = Mesh.from_problem(p, l)
+        x = rng.standard_normal(cm.n_nodes * NDOF)
+        gr = GalerkinRows(p, U, U[:, 3:], p.depth_increment, l, sample_nodes(cm, 1, seed=3, n_random=5), x)
+        A = oc.mg.levels[l].A
+        ref = (A @ x)[gr.dofs]
+        assert np.abs(gr.y - ref).max() <= 1e-13 * np.abs(ref).max()
+        assert np.all(gr.y_abs >= (abs(A) @ np.abs(x))[gr.dofs] * (1 - 1e-12))
