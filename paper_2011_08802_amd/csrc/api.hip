@@ -411,6 +411,10 @@ template <> const float* opA<float>(const Level& L) { return L.A32; }
 template <> const double* opA<double>(const Level& L) { return L.A64; }
 template <typename T> const T* opD(const Level& L);
 template <> const float* opD<float>(const Level& L) { return L.Dinv32; }
+// block inverses read by the matrix-free finest level's Jacobi gather
+template <typename T> const T* mfDinv(const Level& L);
+template <> const double* mfDinv<double>(const Level& L) { return L.Dinv64; }
+template <> const float* mfDinv<float>(const Level& L) { return L.DinvS32; }
 template <> const double* opD<double>(const Level& L) { return L.Dinv64; }
 
 int64_t nvec(const Grid& g) { return (int64_t)NDOF * g.Npad; }
@@ -461,7 +465,8 @@ double stored_blocks(const Grid& g) { return 0.5 * (stencil_blocks(g) + g.N); }
 template <typename T>
 double sweep_bytes(const Grid& g, bool mf) {
   const double op = mf ? 960.0 * g.NE : stored_blocks(g) * NBLK;
-  return sizeof(T) * (op + (double)g.N * (NBLK + 3 * NDOF));
+  const double dinv = (mf && sizeof(T) == 4) ? NSYM : NBLK;  // packed symmetric FP32 inverses
+  return sizeof(T) * (op + (double)g.N * (dinv + 3 * NDOF));
 }
 
 // ---- matrix-free finest level --------------------------------------------------
@@ -491,8 +496,8 @@ void sweep(mvpf_problem* p, int l, bool zero) {
   if (timed) timer_begin(p, p->t_sweep);
   if (!zero && l == 0 && use_mf(p)) {
     mf_elements<T, T>(p, (const T*)L.x, true);
-    launch_mf_gather<2, T, T, T>(L.g, (const T*)p->Cbuf, L.mask, (const T*)L.x, (const T*)L.b, opD<T>(L), om,
-                                 (T*)L.x2, p->stream);
+    launch_mf_gather<2, T, T, T>(L.g, (const T*)p->Cbuf, contact(p), p->mf_epw, L.mask, (const T*)L.x, (const T*)L.b,
+                                 mfDinv<T>(L), om, (T*)L.x2, p->stream);
   } else if (!zero && L.g.N <= p->small_nodes)
     launch_row_small<T>(L.g, opA<T>(L), opD<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.x2, om, true, p->stream);
   else
@@ -519,8 +524,8 @@ void vcycle(mvpf_problem* p, int l) {
   if (l == 0 && p->timing) timer_begin(p, p->t_resid);
   if (l == 0 && use_mf(p)) {
     mf_elements<T, T>(p, (const T*)L.x, true);
-    launch_mf_gather<1, T, T, T>(L.g, (const T*)p->Cbuf, L.mask, (const T*)L.x, (const T*)L.b, nullptr, (T)0,
-                                 (T*)L.r, s);
+    launch_mf_gather<1, T, T, T>(L.g, (const T*)p->Cbuf, contact(p), p->mf_epw, L.mask, (const T*)L.x, (const T*)L.b,
+                                 nullptr, (T)0, (T*)L.r, s);
   } else if (L.g.N <= p->small_nodes)
     launch_row_small<T>(L.g, opA<T>(L), opD<T>(L), (const T*)L.x, (const T*)L.b, (T*)L.r, (T)0, false, s);
   else
@@ -656,8 +661,8 @@ struct Krylov {
     if (p->timing) timer_begin(p, p->t_outer);
     if (use_mf(p)) {
       mf_elements<double, TZ>(p, zj(), true);
-      launch_mf_gather<0, double, TZ, double>(g, (const double*)p->Cbuf, p->lev[0].mask, zj(), nullptr, nullptr, 0.0,
-                                              w, s);
+      launch_mf_gather<0, double, TZ, double>(g, (const double*)p->Cbuf, contact(p), p->mf_epw, p->lev[0].mask, zj(),
+                                              nullptr, nullptr, 0.0, w, s);
     } else {
       launch_spmv<double, TZ, double>(g, p->lev[0].A64, zj(), w, p->Cbuf, s, p->outer_G);
     }
@@ -726,8 +731,8 @@ struct Krylov {
     launch_combine<TZ>(n, (const TZ*)p->Z, n, k, h1(), x, s);
     if (use_mf(p)) {
       mf_elements<double, double>(p, x, true);
-      launch_mf_gather<0, double, double, double>(g, (const double*)p->Cbuf, p->lev[0].mask, x, nullptr, nullptr,
-                                                  0.0, p->tmp, s);
+      launch_mf_gather<0, double, double, double>(g, (const double*)p->Cbuf, contact(p), p->mf_epw, p->lev[0].mask, x,
+                                                  nullptr, nullptr, 0.0, p->tmp, s);
     } else {
       launch_spmv<double, double, double>(g, p->lev[0].A64, x, p->tmp, p->Cbuf, s, p->outer_G);
     }
@@ -842,7 +847,8 @@ void destroy_all(mvpf_problem* p) {
   for (int l = 0; l < MAX_LEVELS; ++l) {
     Level& L = p->lev[l];
     dfree(L.state); dfree(L.mask); dfree(L.target); dfree(L.A64); dfree(L.A32); dfree(L.diag64);
-    dfree(L.Dinv64); dfree(L.Dinv32); dfree(L.x); dfree(L.x2); dfree(L.b); dfree(L.r); dfree(L.Ainv);
+    dfree(L.Dinv64); dfree(L.Dinv32); dfree(L.DinvS32);
+    dfree(L.x); dfree(L.x2); dfree(L.b); dfree(L.r); dfree(L.Ainv);
   }
   for (int l = 0; l < MAX_LEVELS; ++l) dfree(p->gal[l]);
   dfree(p->Dmf64); dfree(p->Dmf32); dfree(p->sphere);
@@ -892,6 +898,7 @@ int allocate(mvpf_problem* p) {
         TRY(dalloc(p, &L.Dinv32, (size_t)nD32));
       else
         TRY(dalloc(p, &L.Dinv64, (size_t)nD64));
+      if (mf0 && p->mixed) TRY(dalloc(p, &L.DinvS32, (size_t)L.g.ntiles * LaySym<float>::SLICE));
     }
     const size_t es = p->mixed ? sizeof(float) : sizeof(double);
     for (void** v : {&L.x, &L.x2, &L.b, &L.r}) {
@@ -923,8 +930,9 @@ int allocate(mvpf_problem* p) {
     TRY(dalloc(p, &p->elem, (size_t)NPAIR * NBLK * p->ne_cap));
   }
   {
+    // transposed half-stencil contributions, or the matrix-free element outputs
     double* cb = nullptr;
-    TRY(dalloc(p, &cb, (size_t)(NUP - 1) * NDOF * g0.Npad));
+    TRY(dalloc(p, &cb, (size_t)std::max<int64_t>((int64_t)(NUP - 1) * NDOF * g0.Npad, mf_out_values(g0))));
     p->Cbuf = cb;
   }
   for (double** v : {&p->R, &p->rhs, &p->gvec, &p->dx, &p->tmp, &p->tmp2}) TRY(dalloc(p, v, (size_t)n));
@@ -1038,8 +1046,8 @@ int system_rhs(mvpf_problem* p, double depth) {
   launch_increment(L0.g, L0.mask, L0.target, L0.state, p->gvec, s);
   if (use_mf(p)) {
     mf_elements<double, double>(p, p->gvec, false, true);
-    launch_mf_gather<0, double, double, double>(L0.g, (const double*)p->Cbuf, nullptr, p->gvec, nullptr, nullptr,
-                                                0.0, p->tmp, s);
+    launch_mf_gather<0, double, double, double>(L0.g, (const double*)p->Cbuf, contact(p), p->mf_epw, nullptr, p->gvec,
+                                                nullptr, nullptr, 0.0, p->tmp, s);
   } else {
     launch_spmv<double, double, double>(L0.g, L0.A64, p->gvec, p->tmp, p->Cbuf, s);
   }
@@ -1065,7 +1073,7 @@ int finish_system(mvpf_problem* p, bool coarse_inline) {
   hipStream_t s = p->stream;
   for (int l = 0; l < p->L - 1; ++l) {
     Level& L = p->lev[l];
-    launch_block_inverse(L.g, L.diag64, L.Dinv64, L.Dinv32, setup_status(p), s);
+    launch_block_inverse(L.g, L.diag64, L.Dinv64, L.Dinv32, L.DinvS32, setup_status(p), s);
   }
   TRY(launch_check(p, "assembly"));
   if (coarse_inline) {
@@ -1329,8 +1337,8 @@ void autotune_levels(mvpf_problem* p, int* tuned) {
       p->mf_epw = epw;
       const double ms = time_launches(p, 5, [&] {
         mf_elements<T, T>(p, (const T*)L.x, true);
-        launch_mf_gather<2, T, T, T>(L.g, (const T*)p->Cbuf, L.mask, (const T*)L.x, (const T*)L.b, opD<T>(L),
-                                     (T)p->opts.omega, (T*)L.x2, p->stream);
+        launch_mf_gather<2, T, T, T>(L.g, (const T*)p->Cbuf, contact(p), p->mf_epw, L.mask, (const T*)L.x,
+                                     (const T*)L.b, mfDinv<T>(L), (T)p->opts.omega, (T*)L.x2, p->stream);
       });
       if (ms < best * 0.98) { best = ms; bestE = epw; }
     }
@@ -1501,7 +1509,16 @@ int batch_mf_epw(const std::vector<mvpf_problem*>& ps) {
       most = p->lev[0].g.NE;
       epw = p->mf_epw;
     }
-  return epw;
+  return mf_epw_of(epw);
+}
+// the gathers of a batched matrix-free product read what the element launch
+// of batch_mf_epw(mf) wrote, contact face outputs included
+void set_mf_gathers(std::vector<BJob>& gather, const std::vector<mvpf_problem*>& mf) {
+  const int epw = batch_mf_epw(mf);
+  for (size_t i = 0; i < gather.size(); ++i) {
+    gather[i].epw = epw;
+    gather[i].contact = contact(mf[i]);
+  }
 }
 
 template <typename T>
@@ -1546,6 +1563,7 @@ void plan_sweep(Planner& pl, const std::vector<mvpf_problem*>& ps, int l, bool z
     } else if (l == 0 && use_mf(p)) {
       mf.push_back(p);
       j.C = p->Cbuf;
+      j.D = mfDinv<T>(L);
       gather.push_back(j);
     } else if (L.g.N <= p->small_nodes) {
       j.A = opA<T>(L);
@@ -1558,6 +1576,7 @@ void plan_sweep(Planner& pl, const std::vector<mvpf_problem*>& ps, int l, bool z
     }
   }
   plan_mf_elements<T>(pl, mf);
+  set_mf_gathers(gather, mf);
   pl.add(BOP_PBJ_ZERO, std::move(z));
   pl.add(BOP_DEFECT_SPLIT, std::move(split));
   pl.add(BOP_ROW_SMALL_PBJ, std::move(small));
@@ -1593,6 +1612,7 @@ void plan_defect(Planner& pl, const std::vector<mvpf_problem*>& ps, int l) {
     }
   }
   plan_mf_elements<T>(pl, mf);
+  set_mf_gathers(gather, mf);
   pl.add(BOP_DEFECT_SPLIT, std::move(split));
   pl.add(BOP_ROW_SMALL_DEFECT, std::move(small));
   pl.add(BOP_MF_GATHER_DEFECT, std::move(gather));
@@ -1918,6 +1938,7 @@ int batch_fgmres(mvpf_batch* b, mvpf_solve_stats* st) {
           });
         }
       }
+      set_mf_gathers(og, omf);
       outer.add(BOP_MF_OUTER_ELEMENT, oe, bblocks, 8 * batch_mf_epw(omf));
       outer.add(BOP_MF_OUTER_GATHER, og, bblocks);
       // classical Gram-Schmidt twice, norm, Hessenberg columns
@@ -2180,6 +2201,7 @@ int batch_assemble(mvpf_batch* b, const double* depths, hipStream_t s) {
         j.diag64 = L.diag64;
         j.Dinv64 = L.Dinv64;
         j.Dinv32 = L.Dinv32;
+        j.DinvS32 = L.DinvS32;
         j.status = setup_status(p);
         bi.push_back(j);
       }
@@ -2488,8 +2510,8 @@ int mvpf_jacobian_apply(mvpf_problem* p, int level, int precision, const double*
   if (precision == MVPF_FP64) {
     if (mf) {
       mf_elements<double, double>(p, p->tmp, true);
-      launch_mf_gather<0, double, double, double>(g, (const double*)p->Cbuf, L.mask, p->tmp, nullptr, nullptr, 0.0,
-                                                  p->tmp2, s);
+      launch_mf_gather<0, double, double, double>(g, (const double*)p->Cbuf, contact(p), p->mf_epw, L.mask, p->tmp,
+                                                  nullptr, nullptr, 0.0, p->tmp2, s);
     } else {
       if (!L.A64) { p->err = "no FP64 operator on this level"; return MVPF_EINVAL; }
       launch_spmv<double, double, double>(g, L.A64, p->tmp, p->tmp2, p->Cbuf, s);
@@ -2499,8 +2521,8 @@ int mvpf_jacobian_apply(mvpf_problem* p, int level, int precision, const double*
     launch_convert<double, float>(nvec(g), p->tmp, (float*)L.x, s);
     if (mf) {
       mf_elements<float, float>(p, (const float*)L.x, true);
-      launch_mf_gather<0, float, float, float>(g, (const float*)p->Cbuf, L.mask, (const float*)L.x, nullptr, nullptr,
-                                               0.0f, (float*)L.r, s);
+      launch_mf_gather<0, float, float, float>(g, (const float*)p->Cbuf, contact(p), p->mf_epw, L.mask,
+                                               (const float*)L.x, nullptr, nullptr, 0.0f, (float*)L.r, s);
     } else {
       launch_spmv<float, float, float>(g, L.A32, (const float*)L.x, (float*)L.r, p->Cbuf, s);
     }
@@ -2890,6 +2912,7 @@ int mvpf_set_tuning(mvpf_problem* p, const char* key, int level, int value) {
       TRY(dalloc(p, &p->Dmf64, mf_hessian_values(L0.g)));
       if (p->mixed) TRY(dalloc(p, &p->Dmf32, mf_hessian_values(L0.g)));
     }
+    if (value && p->mixed && !L0.DinvS32) TRY(dalloc(p, &L0.DinvS32, (size_t)L0.g.ntiles * LaySym<float>::SLICE));
     if (!value && !L0.A64) {  // the stored finest operator, on first use
       TRY(dalloc(p, &L0.A64, (size_t)L0.g.ntiles * NUP * Lay<double>::SLICE));
       if (p->mixed) TRY(dalloc(p, &L0.A32, (size_t)L0.g.ntiles * NUP * Lay<float>::SLICE));

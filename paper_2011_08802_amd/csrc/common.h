@@ -120,21 +120,43 @@ __host__ __device__ constexpr int pair_a(int p) { return p < 8 ? 0 : p < 15 ? 1 
 __host__ __device__ constexpr int pair_b(int p) { return pair_a(p) + p - pair_index(pair_a(p), pair_a(p)); }
 
 // Matrix-free finest level: Gauss-point Hessian entry k (packed upper
-// triangle, 0..119) of point g of element e in storage type T, and the
-// element-output value c of node a of element e.  Hessian entries come in
-// groups of V = 16 / sizeof(T) per lane (one 16-byte load) and 64 lanes
-// (8 elements x 8 points) per group, so a wavefront reads 1 KB contiguous
-// (and, wave-contiguous, the 8 elements' 120 x 64 entries in one span).
-// Element outputs are stored per corner a and unknown c, indexed by the
-// element: a workgroup of consecutive elements writes whole aligned lines of
-// each stream, and a gather over consecutive nodes reads consecutive
-// elements of each stream (one gap per node row).
+// triangle, 0..119) of point g of element e in storage type T.  Hessian
+// entries come in groups of V = 16 / sizeof(T) per lane (one 16-byte load)
+// and 64 lanes (8 elements x 8 points) per group, so a wavefront reads 1 KB
+// contiguous (and, wave-contiguous, the 8 elements' 120 x 64 entries in one
+// span).
 template <typename T>
 __host__ __device__ inline int64_t mf_index(int64_t NEpad, int k, int g, int64_t e) {
   constexpr int V = 16 / (int)sizeof(T);
   return ((((e >> 3) * (NHP / V) + k / V) * 64) + g * 8 + (e & 7)) * V + k % V;
 }
-__host__ __device__ inline int64_t eo_index(int a, int c, int64_t e, int64_t NEpad) { return (int64_t)(a * NDOF + c) * NEpad + e; }
+
+// Element outputs of the matrix-free product, merged along x.  A node with
+// offset (by, bz) in the element row r = ey + ny ez (node row j = ey + by,
+// k = ez + bz) receives, from that row, the left-corner part of element
+// (i, r) and the right-corner part of element (i - 1, r).  The element kernel
+// adds the two when both elements belong to its workgroup (epw consecutive
+// elements, epw = 8, 16 or 32) and stores per element e, q = by + 2 bz and
+// unknown c:
+//   L[(9q + c) NEpad + e]   left part of e (+ right part of e - 1 if merged)
+//   W[(9q + c) NW + w]      right part of workgroup w's last element, unless
+//                           it ends its row (the next workgroup's first
+//                           element then reads it)
+//   Rr[(9q + c) NR + r]     right part of row r's last element
+// and the face outputs of penalty contact (3 values per face corner a =
+// bx + 2 by, per top face f = fi + nx fj):
+//   Cf[(3a + c) NF + f]
+// Half the element-indexed values of a store per corner; the two parts of a
+// node meet in one addition, in the kernel or in the gather, so the sums do
+// not depend on epw.
+__host__ __device__ inline int mf_epw_of(int epw) { return (epw == 8 || epw == 16) ? epw : 32; }
+__host__ __device__ inline int64_t mf_nw(const Grid& g) { return (int64_t)g.NEpad / 8; }
+__host__ __device__ inline int64_t mf_nr(const Grid& g) { return ((int64_t)g.ny * g.nz + 63) / 64 * 64; }
+__host__ __device__ inline int64_t mf_nf(const Grid& g) { return ((int64_t)g.nx * g.ny + 63) / 64 * 64; }
+__host__ __device__ inline int64_t mf_w_offset(const Grid& g) { return (int64_t)36 * g.NEpad; }
+__host__ __device__ inline int64_t mf_r_offset(const Grid& g) { return mf_w_offset(g) + 36 * mf_nw(g); }
+__host__ __device__ inline int64_t mf_cf_offset(const Grid& g) { return mf_r_offset(g) + 36 * mf_nr(g); }
+__host__ __device__ inline int64_t mf_out_values(const Grid& g) { return mf_cf_offset(g) + 12 * mf_nf(g); }
 
 // Rigid spherical indenter: centre (cx, cy, cz), radius R, contact penalty eps.
 struct Sphere {
@@ -147,6 +169,20 @@ struct Lay {
   static constexpr int V = 16 / (int)sizeof(T);                 // entries per 16-byte load
   static constexpr int NE = (NBLK + V - 1) / V * V;             // padded entries per lane
   static constexpr int NQ = NE / V;                             // 16-byte loads per block
+  static constexpr int64_t SLICE = (int64_t)NE * TILE;
+  __host__ __device__ static constexpr int64_t off(int e, int l) { return ((int64_t)(e / V) * TILE + l) * V + e % V; }
+};
+
+// Packed symmetric block (upper triangle, row-major, r <= c) in the same
+// slice layout: the FP32 block inverses of a matrix-free finest level.
+constexpr int NSYM = NDOF * (NDOF + 1) / 2;
+__host__ __device__ constexpr int sym_index(int r, int c) {
+  return r <= c ? r * NDOF - r * (r - 1) / 2 + (c - r) : c * NDOF - c * (c - 1) / 2 + (r - c);
+}
+template <typename T>
+struct LaySym {
+  static constexpr int V = 16 / (int)sizeof(T);
+  static constexpr int NE = (NSYM + V - 1) / V * V;
   static constexpr int64_t SLICE = (int64_t)NE * TILE;
   __host__ __device__ static constexpr int64_t off(int e, int l) { return ((int64_t)(e / V) * TILE + l) * V + e % V; }
 };
@@ -168,6 +204,7 @@ struct Level {
   double* diag64 = nullptr;   // FP64 diagonal blocks [ntiles][NBLK][64]
   double* Dinv64 = nullptr;   // FP64 block inverses (FP64 mode)
   float* Dinv32 = nullptr;    // FP32 block inverses (mixed mode)
+  float* DinvS32 = nullptr;   // their upper triangles, packed (matrix-free finest level, mixed mode)
   // work vectors of the V-cycle (type per precision mode), [9][Npad]
   void* x = nullptr;
   void* x2 = nullptr;
@@ -288,8 +325,10 @@ void launch_apply_dirichlet(const Grid& g, const uint16_t* mask, double* A64, fl
 // constrained-dof masks; parents go to Ep (whole level, stride gp.NEpad)
 void launch_galerkin_coarsen(const Grid& gc, const Chunk& ckc, const double* Ec, const uint16_t* maskc,
                              const Grid& gp, int Z0, int Z1, double* Ep, hipStream_t s);
-void launch_block_inverse(const Grid& g, const double* diag64, double* Dinv64, float* Dinv32, int* status,
-                          hipStream_t s);
+// block inverses of the diagonal blocks (outputs may be null; DinvS32: packed
+// upper triangles in FP32)
+void launch_block_inverse(const Grid& g, const double* diag64, double* Dinv64, float* Dinv32, float* DinvS32,
+                          int* status, hipStream_t s);
 // penalty contact with a rigid sphere (MVPF_LOAD_SPHERE)
 Sphere make_sphere(const Grid& g, const mvpf_loading& ld, double depth);
 void launch_contact_residual(const Grid& g, const Sphere& sp, const double* state, double* R, hipStream_t s);
@@ -298,8 +337,9 @@ void launch_contact_residual(const Grid& g, const Sphere& sp, const double* stat
 void launch_contact_element(const Grid& g, const Chunk& ck, const Sphere& sp, const double* state, double* elem,
                             hipStream_t s, bool diag_only = false);
 void launch_contact_load(const Grid& g, const Sphere& sp, const double* state, double* out, hipStream_t s);
-// matrix-free contact stiffness: E (element outputs of the top layer) += K_c x;
-// sp: the indenter in device memory
+// matrix-free contact stiffness: the face outputs K_c x of every top face
+// (zero without contact) into the contact part of the element-output buffer
+// E; sp: the indenter in device memory
 template <typename T, typename TX>
 void launch_contact_apply(const Grid& g, const Sphere* sp, const double* state, const uint16_t* mask, const TX* x, T* E,
                           hipStream_t s);
@@ -311,10 +351,12 @@ template <typename TD, typename TX, typename T>
 // elems_per_wg: elements per workgroup (8, 16 or 32 = 64, 128 or 256 threads)
 void launch_mf_element(const Grid& g, const TD* D, const TX* x, const uint16_t* mask, const DevCard* cd, T* E,
                        hipStream_t s, bool sparse_x = false, int elems_per_wg = 32);
-// MODE 0: y = K x; 1: y = b - K x; 2: y = x + omega Dinv (b - K x); constrained rows act as the identity
+// MODE 0: y = K x; 1: y = b - K x; 2: y = x + omega Dinv (b - K x); constrained rows act as the identity.
+// E: outputs of launch_mf_element with the same elems_per_wg (and of
+// launch_contact_apply when contact)
 template <int MODE, typename T, typename TX, typename TY>
-void launch_mf_gather(const Grid& g, const T* E, const uint16_t* mask, const TX* x, const T* b, const T* Dinv, T omega,
-                      TY* y, hipStream_t s);
+void launch_mf_gather(const Grid& g, const T* E, bool contact, int elems_per_wg, const uint16_t* mask, const TX* x,
+                      const T* b, const T* Dinv, T omega, TY* y, hipStream_t s);
 // BSR products (TA = operator type, TX = vector type)
 // G: number of workgroups (0 = one per 256 rows; smaller = persistent rounds).
 // C: scratch for the transposed lower-half contributions, >= 13 * 9 * Npad
@@ -418,6 +460,8 @@ struct BJob {
   const DevCard* cd;       // material card (matrix-free element kernel)
   double omega;            // damping of the Jacobi sweeps
   int block0, nblk;
+  int epw;                 // matrix-free gathers: elements per workgroup of the element launch
+  int contact;             // matrix-free gathers: add the contact face outputs
 };
 // job of this workgroup in a batched launch; bid = its workgroup index within the job
 template <typename J>
@@ -483,7 +527,7 @@ struct AJob {
   double* qp;                // Gauss-point scratch
   double* elem;              // element matrices
   double *A64, *diag64, *Dinv64, *R, *D64;
-  float *A32, *Dinv32, *D32;
+  float *A32, *Dinv32, *D32, *DinvS32;
   const uint16_t* mask;
   int* status;
   int64_t eb0, neb;          // element groups of the Hessian pack

@@ -129,10 +129,11 @@ __global__ void __launch_bounds__(256) contact_element_kernel(Grid g, Chunk ck, 
     }
 }
 
-// E += face stiffness times x for the top element layer (matrix-free
-// finest level): one thread per top element, face nodes 0..3 = element
-// corners 4..7, x masked on constrained dofs.  The indenter is read from
-// device memory, so a captured graph follows its depth.
+// Face stiffness times x for the top faces (matrix-free finest level), into
+// the contact part of the element-output buffer: one thread per top face,
+// face corner a = bx + 2 by, x masked on constrained dofs; zeros where no
+// face point is in contact.  The indenter is read from device memory, so a
+// captured graph follows its depth.
 template <typename T, typename TX>
 __global__ void __launch_bounds__(256) contact_apply_kernel(Grid g, const Sphere* __restrict__ sp,
                                                             const double* __restrict__ state,
@@ -142,7 +143,6 @@ __global__ void __launch_bounds__(256) contact_apply_kernel(Grid g, const Sphere
   if (t >= g.nx * g.ny) return;
   const Sphere s = *sp;
   const int fi = t % g.nx, fj = t / g.nx;
-  const int64_t e = (int64_t)(g.nz - 1) * g.nx * g.ny + t;
   const double w = 0.25 * g.h * g.h * s.eps;
   double xb[4][3];
 #pragma unroll
@@ -153,12 +153,10 @@ __global__ void __launch_bounds__(256) contact_apply_kernel(Grid g, const Sphere
     for (int c = 0; c < 3; ++c) xb[a][c] = ((mb >> c) & 1) ? 0.0 : (double)x[(int64_t)c * g.Npad + node];
   }
   double out[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  bool any = false;
   for (int q = 0; q < 4; ++q) {
     FacePoint fp;
     face_point(g, s, state, fi, fj, q, fp);
     if (!(fp.gap < 0.0)) continue;
-    any = true;
     const double ir = 1.0 / fp.r;
     const double n[3] = {fp.d[0] * ir, fp.d[1] * ir, fp.d[2] * ir};
     const double gr = fp.gap * ir;
@@ -176,11 +174,12 @@ __global__ void __launch_bounds__(256) contact_apply_kernel(Grid g, const Sphere
       for (int a = 0; a < 4; ++a) out[a][c] += fp.N[a] * at;
     }
   }
-  if (!any) return;
+  T* __restrict__ Cf = E + mf_cf_offset(g);
+  const int64_t nf = mf_nf(g);
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) E[eo_index(4 + a, c, e, g.NEpad)] += (T)out[a][c];
+    for (int c = 0; c < 3; ++c) Cf[(3 * a + c) * nf + t] = (T)out[a][c];
 }
 
 // P = sum over active face points of w eps g n_z (one workgroup, fixed order)

@@ -250,12 +250,13 @@ __device__ __forceinline__ void mf_element_body(const Grid& g, const TD* __restr
 #pragma unroll
   for (int c = 0; c < 9; ++c) a1[c] = r2[c], bx[c] = r2[9 + c];
   interp_pair_t<1>(a1, bx, mq0, tq0, out);
-  // Element outputs through LDS: a lane holds corner gp's 9 values, which in
-  // its wavefront would make 8-element (32-byte) pieces of each stream
-  // (gp, c); staged per stream, the workgroup's epw consecutive elements go
-  // out as one contiguous, aligned run of each stream per store (whole
-  // 128-byte lines at 32 elements in FP32).  Every lane of the workgroup
-  // reaches the barrier.
+  // Element outputs through LDS: a lane holds corner gp's 9 values; staged
+  // per stream (gp, c), the workgroup merges each element's left corners
+  // with the right corners of its predecessor in the same row and stores
+  // one contiguous, aligned run of each merged stream (whole 128-byte lines
+  // at 32 elements in FP32), plus the right corners that no element of the
+  // workgroup takes (its last element's, row ends).  Every lane of the
+  // workgroup reaches the barrier.
   __shared__ T eo[72 * (MF_MAX_EPW + 1)];
   const int epw = blockDim.x >> 3;
   const int jw = threadIdx.x >> 3;  // element within the workgroup
@@ -263,9 +264,23 @@ __device__ __forceinline__ void mf_element_body(const Grid& g, const TD* __restr
   for (int c = 0; c < 9; ++c) eo[(gp * 9 + c) * (epw + 1) + jw] = out[c];
   __syncthreads();
   const int64_t ew = (int64_t)bid * epw;  // the workgroup's first element
-  for (int idx = threadIdx.x; idx < 72 * epw; idx += blockDim.x) {
-    const int s = idx / epw, jj = idx - s * epw;  // stream s = 9 a + c
-    if (ew + jj < g.NE) E[(int64_t)s * g.NEpad + ew + jj] = eo[s * (epw + 1) + jj];
+  const int ex0 = (int)(ew % g.nx);
+  T* __restrict__ W = E + mf_w_offset(g);
+  T* __restrict__ Rr = E + mf_r_offset(g);
+  for (int idx = threadIdx.x; idx < 36 * epw; idx += blockDim.x) {
+    const int s = idx / epw, jj = idx - s * epw;  // merged stream s = 9 q + c
+    const int64_t e = ew + jj;
+    if (e >= g.NE) continue;
+    const int q = s / 9, c = s - 9 * q;
+    int ex = ex0 + jj;
+    while (ex >= g.nx) ex -= g.nx;
+    const T* left = eo + (18 * q + c) * (epw + 1);      // corner 2q
+    const T* right = eo + (18 * q + 9 + c) * (epw + 1);  // corner 2q + 1
+    T v = left[jj];
+    if (jj > 0 && ex > 0) v = v + right[jj - 1];
+    E[(int64_t)s * g.NEpad + e] = v;
+    if (ex == g.nx - 1) Rr[(int64_t)s * mf_nr(g) + e / g.nx] = right[jj];
+    else if (jj == epw - 1) W[(int64_t)s * mf_nw(g) + bid] = right[jj];
   }
 }
 template <typename TD, typename TX, typename T, int MINB, int PF, bool SPARSE>
@@ -276,10 +291,13 @@ __global__ void __launch_bounds__(256, MINB) mf_element_kernel(Grid g, const TD*
 }
 
 // Node gather with epilogue.  MODE 0: y = K x; 1: r = b - K x;
-// 2: xo = x + omega Dinv (b - K x).  Constrained rows (mask) act as the
-// identity, as in the eliminated assembled operator.
+// 2: xo = x + omega Dinv (b - K x), Dinv packed symmetric (LaySym) in FP32,
+// full (Lay) in FP64.  Constrained rows (mask) act as the identity, as in the
+// eliminated assembled operator.  E: the element outputs of a launch with
+// epw elements per workgroup; Cf: the contact face outputs, or null.
 template <int MODE, typename T, typename TX, typename TY>
-__device__ __forceinline__ void mf_gather_body(const Grid& g, const T* __restrict__ E, const uint16_t* __restrict__ mask,
+__device__ __forceinline__ void mf_gather_body(const Grid& g, const T* __restrict__ E, const T* __restrict__ Cf,
+                                               int epw, const uint16_t* __restrict__ mask,
                                                const TX* __restrict__ x, const T* __restrict__ b,
                                                const T* __restrict__ Dinv, T omega, TY* __restrict__ y, int bid) {
   const int n = bid * 256 + threadIdx.x;
@@ -291,13 +309,40 @@ __device__ __forceinline__ void mf_gather_body(const Grid& g, const T* __restric
   }
   const int i = n % g.nnx, j = (n / g.nnx) % g.nny, k = n / (g.nnx * g.nny);
   T s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const T* __restrict__ W = E + mf_w_offset(g);
+  const T* __restrict__ Rr = E + mf_r_offset(g);
 #pragma unroll
-  for (int a = 7; a >= 0; --a) {  // element (i - ax, j - ay, k - az) has this node as corner a
-    const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - ((a >> 2) & 1);
-    if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || ez < 0 || ez >= g.nz) continue;
-    const int64_t e = ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez);
+  for (int q = 3; q >= 0; --q) {  // element row r = (j - by) + ny (k - bz) holds this node at (by, bz)
+    const int ey = j - (q & 1), ez = k - (q >> 1);
+    if (ey < 0 || ey >= g.ny || ez < 0 || ez >= g.nz) continue;
+    const int64_t r = ey + (int64_t)g.ny * ez;
+    T t[9];
+    if (i < g.nx) {
+      const int64_t e = i + g.nx * r;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) s[c] += E[eo_index(a, c, e, g.NEpad)];
+      for (int c = 0; c < 9; ++c) t[c] = E[(int64_t)(9 * q + c) * g.NEpad + e];
+      if (i > 0 && (e & (epw - 1)) == 0) {  // element e - 1 ended the previous workgroup
+        const int64_t w = e / epw - 1;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) t[c] = t[c] + W[(int64_t)(9 * q + c) * mf_nw(g) + w];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) t[c] = Rr[(int64_t)(9 * q + c) * mf_nr(g) + r];
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) s[c] += t[c];
+  }
+  if (Cf && k == g.nz) {  // penalty contact: the top faces around the node
+    const int64_t nf = mf_nf(g);
+#pragma unroll
+    for (int a = 3; a >= 0; --a) {
+      const int fi = i - (a & 1), fj = j - (a >> 1);
+      if (fi < 0 || fi >= g.nx || fj < 0 || fj >= g.ny) continue;
+      const int64_t f = fi + (int64_t)g.nx * fj;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s[c] += Cf[(3 * a + c) * nf + f];
+    }
   }
   const unsigned mb = mask ? mask[n] : 0u;
   T r[9];
@@ -307,7 +352,20 @@ __device__ __forceinline__ void mf_gather_body(const Grid& g, const T* __restric
     const T kx = ((mb >> c) & 1) ? xv : s[c];
     r[c] = (MODE == 0) ? kx : b[(int64_t)c * g.Npad + n] - kx;
   }
-  if (MODE == 2) {
+  if (MODE == 2 && sizeof(T) == 4) {  // FP32: the packed upper triangles of the symmetric block inverses
+    const int t = n >> 6, l = n & 63;
+    const T* Db = Dinv + (int64_t)t * LaySym<T>::SLICE;
+    T dv[NSYM];
+#pragma unroll
+    for (int e = 0; e < NSYM; ++e) dv[e] = Db[LaySym<T>::off(e, l)];
+#pragma unroll
+    for (int rr = 0; rr < 9; ++rr) {
+      T acc = 0;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc += dv[sym_index(rr, c)] * r[c];
+      y[(int64_t)rr * g.Npad + n] = (TY)((T)x[(int64_t)rr * g.Npad + n] + omega * acc);
+    }
+  } else if (MODE == 2) {
     const int t = n >> 6, l = n & 63;
     const T* Db = Dinv + (int64_t)t * Lay<T>::SLICE;
 #pragma unroll
@@ -323,10 +381,11 @@ __device__ __forceinline__ void mf_gather_body(const Grid& g, const T* __restric
   }
 }
 template <int MODE, typename T, typename TX, typename TY>
-__global__ void __launch_bounds__(256) mf_gather_kernel(Grid g, const T* __restrict__ E, const uint16_t* __restrict__ mask,
+__global__ void __launch_bounds__(256) mf_gather_kernel(Grid g, const T* __restrict__ E, const T* __restrict__ Cf,
+                                                        int epw, const uint16_t* __restrict__ mask,
                                                         const TX* __restrict__ x, const T* __restrict__ b,
                                                         const T* __restrict__ Dinv, T omega, TY* __restrict__ y) {
-  mf_gather_body<MODE, T, TX, TY>(g, E, mask, x, b, Dinv, omega, y, blockIdx.x);
+  mf_gather_body<MODE, T, TX, TY>(g, E, Cf, epw, mask, x, b, Dinv, omega, y, blockIdx.x);
 }
 
 // Gauss-point Hessians of a slab (standard Gauss-point layout, entries
@@ -400,7 +459,7 @@ void launch_mf_element(const Grid& g, const TD* D, const TX* x, const uint16_t* 
   const int64_t threads = (int64_t)g.NEpad * 8;  // NEpad is a multiple of 64: whole wavefronts
   constexpr bool f64 = sizeof(TD) == 8;
   constexpr int MINB = f64 ? MF_MINB64 : MF_MINB32, PF = f64 ? MF_PF64 : MF_PF32;
-  const int wg = (elems_per_wg == 8 || elems_per_wg == 16) ? 8 * elems_per_wg : 256;  // divides threads
+  const int wg = 8 * mf_epw_of(elems_per_wg);  // divides threads
   const int blocks = (int)(threads / wg);
   if (sparse_x)
     mf_element_kernel<TD, TX, T, MINB, PF, true><<<blocks, wg, 0, s>>>(g, D, x, mask, cd, E);
@@ -409,10 +468,11 @@ void launch_mf_element(const Grid& g, const TD* D, const TX* x, const uint16_t* 
 }
 
 template <int MODE, typename T, typename TX, typename TY>
-void launch_mf_gather(const Grid& g, const T* E, const uint16_t* mask, const TX* x, const T* b, const T* Dinv, T omega,
-                      TY* y, hipStream_t s) {
+void launch_mf_gather(const Grid& g, const T* E, bool contact, int elems_per_wg, const uint16_t* mask, const TX* x,
+                      const T* b, const T* Dinv, T omega, TY* y, hipStream_t s) {
   if constexpr (!MF_AVAILABLE) return;
-  mf_gather_kernel<MODE, T, TX, TY><<<(g.Npad + 255) / 256, 256, 0, s>>>(g, E, mask, x, b, Dinv, omega, y);
+  mf_gather_kernel<MODE, T, TX, TY><<<(g.Npad + 255) / 256, 256, 0, s>>>(
+      g, E, contact ? E + mf_cf_offset(g) : nullptr, mf_epw_of(elems_per_wg), mask, x, b, Dinv, omega, y);
 }
 
 template void launch_mf_element<float, float, float>(const Grid&, const float*, const float*, const uint16_t*,
@@ -421,20 +481,27 @@ template void launch_mf_element<double, float, double>(const Grid&, const double
                                                        const DevCard*, double*, hipStream_t, bool, int);
 template void launch_mf_element<double, double, double>(const Grid&, const double*, const double*, const uint16_t*,
                                                         const DevCard*, double*, hipStream_t, bool, int);
-template void launch_mf_gather<0, float, float, float>(const Grid&, const float*, const uint16_t*, const float*,
-                                                       const float*, const float*, float, float*, hipStream_t);
-template void launch_mf_gather<1, float, float, float>(const Grid&, const float*, const uint16_t*, const float*,
-                                                       const float*, const float*, float, float*, hipStream_t);
-template void launch_mf_gather<2, float, float, float>(const Grid&, const float*, const uint16_t*, const float*,
-                                                       const float*, const float*, float, float*, hipStream_t);
-template void launch_mf_gather<0, double, float, double>(const Grid&, const double*, const uint16_t*, const float*,
-                                                         const double*, const double*, double, double*, hipStream_t);
-template void launch_mf_gather<0, double, double, double>(const Grid&, const double*, const uint16_t*, const double*,
-                                                          const double*, const double*, double, double*, hipStream_t);
-template void launch_mf_gather<1, double, double, double>(const Grid&, const double*, const uint16_t*, const double*,
-                                                          const double*, const double*, double, double*, hipStream_t);
-template void launch_mf_gather<2, double, double, double>(const Grid&, const double*, const uint16_t*, const double*,
-                                                          const double*, const double*, double, double*, hipStream_t);
+template void launch_mf_gather<0, float, float, float>(const Grid&, const float*, bool, int, const uint16_t*,
+                                                       const float*, const float*, const float*, float, float*,
+                                                       hipStream_t);
+template void launch_mf_gather<1, float, float, float>(const Grid&, const float*, bool, int, const uint16_t*,
+                                                       const float*, const float*, const float*, float, float*,
+                                                       hipStream_t);
+template void launch_mf_gather<2, float, float, float>(const Grid&, const float*, bool, int, const uint16_t*,
+                                                       const float*, const float*, const float*, float, float*,
+                                                       hipStream_t);
+template void launch_mf_gather<0, double, float, double>(const Grid&, const double*, bool, int, const uint16_t*,
+                                                         const float*, const double*, const double*, double, double*,
+                                                         hipStream_t);
+template void launch_mf_gather<0, double, double, double>(const Grid&, const double*, bool, int, const uint16_t*,
+                                                          const double*, const double*, const double*, double,
+                                                          double*, hipStream_t);
+template void launch_mf_gather<1, double, double, double>(const Grid&, const double*, bool, int, const uint16_t*,
+                                                          const double*, const double*, const double*, double,
+                                                          double*, hipStream_t);
+template void launch_mf_gather<2, double, double, double>(const Grid&, const double*, bool, int, const uint16_t*,
+                                                          const double*, const double*, const double*, double,
+                                                          double*, hipStream_t);
 
 // ---- batched launches (FP32 or FP64 smoothing on matrix-free finest levels) ----
 template <typename T, int MINB, int PF>
@@ -447,7 +514,8 @@ template <int MODE, typename T>
 __global__ void __launch_bounds__(256) mf_gather_batch(const BJob* __restrict__ jobs, int njobs) {
   int bid;
   const BJob& j = find_job(jobs, njobs, bid);
-  mf_gather_body<MODE, T, T, T>(j.g, (const T*)j.C, j.mask, (const T*)j.x, (const T*)j.b, (const T*)j.D, (T)j.omega,
+  mf_gather_body<MODE, T, T, T>(j.g, (const T*)j.C, j.contact ? (const T*)j.C + mf_cf_offset(j.g) : nullptr, j.epw,
+                                j.mask, (const T*)j.x, (const T*)j.b, (const T*)j.D, (T)j.omega,
                                 (T*)j.y, bid);
 }
 template <typename T>
@@ -482,7 +550,9 @@ template <typename TZ>
 __global__ void __launch_bounds__(256) mf_outer_gather_batch(const BJob* __restrict__ jobs, int njobs) {
   int bid;
   const BJob& j = find_job(jobs, njobs, bid);
-  mf_gather_body<0, double, TZ, double>(j.g, (const double*)j.C, j.mask, (const TZ*)j.x, nullptr, nullptr, 0.0,
+  mf_gather_body<0, double, TZ, double>(j.g, (const double*)j.C,
+                                        j.contact ? (const double*)j.C + mf_cf_offset(j.g) : nullptr, j.epw, j.mask,
+                                        (const TZ*)j.x, nullptr, nullptr, 0.0,
                                         (double*)j.y, bid);
 }
 template <typename TZ>

@@ -451,15 +451,19 @@ void launch_apply_dirichlet(const Grid& g, const uint16_t* mask, double* A64, fl
 //    store positions.
 //  * larger blocks: each thread keeps its augmented [A | I] in LDS,
 //    lane-interleaved (registers would not hold it).
+// DinvS32 (NDOF <= 9; null otherwise): the upper triangle of the FP32
+// inverse, packed.  The blocks are symmetric (diagonal blocks of the Hessian
+// of the potential, Sec. 3.4), so are their inverses up to rounding.
 constexpr bool BI_REGS = NDOF <= 9;
 constexpr int BI_THREADS = BI_REGS ? 64 : 16;
 
 __device__ __forceinline__ void block_inverse_regs(const Grid& g, const double* __restrict__ diag64,
                                                    double* __restrict__ Dinv64, float* __restrict__ Dinv32,
-                                                   int* status, int n) {
+                                                   float* __restrict__ DinvS32, int* status, int n) {
   const int t = n / TILE, l = n % TILE;
   const int64_t db = (int64_t)t * Lay<double>::SLICE;
   const int64_t db32 = (int64_t)t * Lay<float>::SLICE;
+  const int64_t dbs = (int64_t)t * LaySym<float>::SLICE;
   bool ok = n < g.N;
   double A[NDOF][NDOF];
 #pragma unroll
@@ -518,6 +522,7 @@ __device__ __forceinline__ void block_inverse_regs(const Grid& g, const double* 
       const double v = ok ? A[r][m] : 0.0;
       if (Dinv64) Dinv64[db + Lay<double>::off(NDOF * r + dst[m], l)] = v;
       if (Dinv32) Dinv32[db32 + Lay<float>::off(NDOF * r + dst[m], l)] = (float)v;
+      if (DinvS32 && r <= dst[m]) DinvS32[dbs + LaySym<float>::off(sym_index(r, dst[m]), l)] = (float)v;
     }
 }
 
@@ -571,24 +576,25 @@ __device__ __forceinline__ void block_inverse_lds(const Grid& g, const double* _
 
 __device__ __forceinline__ void block_inverse_body(const Grid& g, const double* __restrict__ diag64,
                                                    double* __restrict__ Dinv64, float* __restrict__ Dinv32,
-                                                   int* status, int bid) {
+                                                   float* __restrict__ DinvS32, int* status, int bid) {
   const int n = bid * BI_THREADS + threadIdx.x;
   if (n >= g.Npad) return;
   if constexpr (BI_REGS)
-    block_inverse_regs(g, diag64, Dinv64, Dinv32, status, n);
+    block_inverse_regs(g, diag64, Dinv64, Dinv32, DinvS32, status, n);
   else
     block_inverse_lds(g, diag64, Dinv64, Dinv32, status, n);
 }
 __global__ void __launch_bounds__(BI_THREADS) block_inverse_kernel(Grid g, const double* __restrict__ diag64,
                                                                    double* __restrict__ Dinv64,
-                                                                   float* __restrict__ Dinv32, int* status) {
-  block_inverse_body(g, diag64, Dinv64, Dinv32, status, blockIdx.x);
+                                                                   float* __restrict__ Dinv32,
+                                                                   float* __restrict__ DinvS32, int* status) {
+  block_inverse_body(g, diag64, Dinv64, Dinv32, DinvS32, status, blockIdx.x);
 }
 
-void launch_block_inverse(const Grid& g, const double* diag64, double* Dinv64, float* Dinv32, int* status,
-                          hipStream_t s) {
-  block_inverse_kernel<<<(g.Npad + BI_THREADS - 1) / BI_THREADS, BI_THREADS, 0, s>>>(g, diag64, Dinv64, Dinv32,
-                                                                                      status);
+void launch_block_inverse(const Grid& g, const double* diag64, double* Dinv64, float* Dinv32, float* DinvS32,
+                          int* status, hipStream_t s) {
+  block_inverse_kernel<<<(g.Npad + BI_THREADS - 1) / BI_THREADS, BI_THREADS, 0, s>>>(
+      g, diag64, Dinv64, Dinv32, BI_REGS ? DinvS32 : nullptr, status);
 }
 
 // ---- batched assembly (jobs of many problems in one launch) --------------------
@@ -616,7 +622,7 @@ __global__ void __launch_bounds__(64) apply_dirichlet_batch(const AJob* __restri
 __global__ void __launch_bounds__(BI_THREADS) block_inverse_batch(const AJob* __restrict__ jobs, int njobs) {
   int bid;
   const AJob& j = find_job(jobs, njobs, bid);
-  block_inverse_body(j.g, j.diag64, j.Dinv64, j.Dinv32, j.status, bid);
+  block_inverse_body(j.g, j.diag64, j.Dinv64, j.Dinv32, BI_REGS ? j.DinvS32 : nullptr, j.status, bid);
 }
 __global__ void __launch_bounds__(256) residual_gather_batch(const AJob* __restrict__ jobs, int njobs) {
   int bid;

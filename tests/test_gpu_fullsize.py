@@ -171,7 +171,8 @@ def _check(p, depth, radius_nodes, tag, precision="mixed", coarse="galerkin", co
     rediscretised coarse levels and coarse_levels, the sampled rows of every
     coarser level's operator; with Galerkin coarse levels, the sampled rows of
     levels 1 and 2 (galerkin_samples: the number of seeded random nodes among
-    each level's samples, None = the default sample) and the identity
+    each level's samples, None = the default sample; level 2 keeps every other
+    sampled node) and the identity
     A_l = P~^T A_{l-1} P~ on the deeper ones; then the solve's true FP64
     residual."""
     from paper_2011_08802_amd import mvpf
@@ -181,13 +182,13 @@ def _check(p, depth, radius_nodes, tag, precision="mixed", coarse="galerkin", co
     nodes = sample_nodes(m, radius_nodes)
     say(f"[{tag}] oracle rows of {len(nodes)} sampled nodes")
     lr = LocalRows(p, U, U[:, 3:], depth, nodes)
-    coarse = []
+    coarse_rows = []
     if coarse_levels:
         for l in range(1, p.n_levels):
             cm = Mesh.from_problem(p, l)
             cn = sample_nodes(cm, max(1, radius_nodes >> l), seed=17 + l)
             say(f"[{tag}] oracle rows of {len(cn)} sampled nodes on level {l}")
-            coarse.append((l, LocalRows(p, U, U[:, 3:], depth, cn, level=l)))
+            coarse_rows.append((l, LocalRows(p, U, U[:, 3:], depth, cn, level=l)))
     galerkin = []
     if coarse == "galerkin":
         rng = np.random.default_rng(23)
@@ -196,14 +197,14 @@ def _check(p, depth, radius_nodes, tag, precision="mixed", coarse="galerkin", co
                 break
             cm = Mesh.from_problem(p, l)
             cn = sample_nodes(cm, max(1, radius_nodes >> l), seed=31 + l,
-                              **({} if nr is None else {"n_random": nr}))
+                              **({} if nr is None else {"n_random": nr}))[::l]  # level 2: every other one
             say(f"[{tag}] oracle Galerkin rows of {len(cn)} sampled nodes on level {l}")
             xc = rng.standard_normal(cm.n_nodes * NDOF)
             galerkin.append((xc, GalerkinRows(p, U, U[:, 3:], depth, l, cn, xc)))
     say(f"[{tag}] GPU system {p.nx}x{p.ny}x{p.nz} {precision}, {coarse} coarse operators")
     gp = mvpf.Problem(p, precision, rtol=1e-8, coarse=coarse)
     try:
-        return _check_gpu(gp, p, depth, tag, precision, lr, coarse, m, galerkin)
+        return _check_gpu(gp, p, depth, tag, precision, lr, coarse, coarse_rows, m, galerkin)
     finally:
         gp.close()
 
@@ -240,7 +241,7 @@ def _galerkin_identity(gp, p, depth, precision, first, tag):
         assert np.allclose(y[~free], x[~free], rtol=1e-7, atol=0), (tag, l)
 
 
-def _check_gpu(gp, p, depth, tag, precision, lr, coarse, m, galerkin):
+def _check_gpu(gp, p, depth, tag, precision, lr, coarse, coarse_rows, m, galerkin):
     from paper_2011_08802_amd import mvpf
     assert gp.get_tuning("matrix_free") == 1
     gp.init_random(p.seed)
@@ -256,7 +257,7 @@ def _check_gpu(gp, p, depth, tag, precision, lr, coarse, m, galerkin):
     check_entries(gp.jacobian_apply(0, xd, mvpf.FP64).cpu().numpy()[lr.dofs], yo, 1e-12, "FP64 K x", ya)
     if precision == "mixed":
         check_entries(gp.jacobian_apply(0, xd, mvpf.MIXED).cpu().numpy()[lr.dofs], yo, 2e-6, "FP32 K x", ya)
-    for l, cr in coarse:
+    for l, cr in coarse_rows:
         xc = rng.standard_normal(cr.m.n_nodes * NDOF)
         yc = gp.jacobian_apply(l, torch.as_tensor(xc).cuda(), mvpf.FP64).cpu().numpy()[cr.dofs]
         check_entries(yc, cr.apply(xc), 1e-12, f"FP64 K x level {l}", cr.apply(xc, absolute=True))
