@@ -671,8 +671,7 @@ struct Krylov {
                                    (double)g.N * NDOF * (sizeof(TZ) + sizeof(double)));
     launch_multidot(n, p->V, n, j + 1, w, p->red, s);
     launch_reduce(j + 1, nb, p->red, h1(), 0, s);
-    launch_multiaxpy(n, p->V, n, j + 1, h1(), w, nullptr, s);
-    launch_multidot(n, p->V, n, j + 1, w, p->red, s);
+    launch_multiaxpy_dot(n, p->V, n, j + 1, h1(), w, p->red, s);
     launch_reduce(j + 1, nb, p->red, h2(), 0, s);
     launch_multiaxpy(n, p->V, n, j + 1, h2(), w, p->red, s);
     launch_reduce(1, nb, p->red, hn(), 0, s);

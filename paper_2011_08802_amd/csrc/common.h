@@ -431,6 +431,11 @@ void launch_multidot(int64_t n, const double* V, int64_t ldv, int k, const doubl
 void launch_reduce(int k, int nblk, const double* part, double* out, int accumulate, hipStream_t s);
 void launch_multiaxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w,
                       double* part_norm, hipStream_t s);
+// w -= sum_j h_j V_j, then part = the block partial sums of V_j . w (the
+// updated w), j < k: multiaxpy followed by multidot, bitwise, in one sweep
+// over the basis when k <= 32
+void launch_multiaxpy_dot(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w, double* part,
+                          hipStream_t s);
 void launch_scale(int64_t n, const double* w, const double* beta, double* v, hipStream_t s);
 template <typename TZ>
 void launch_combine(int64_t n, const TZ* Z, int64_t ldz, int k, const double* y, double* x, hipStream_t s);

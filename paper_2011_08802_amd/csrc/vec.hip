@@ -137,9 +137,115 @@ __global__ void __launch_bounds__(RB) multiaxpy_kernel(int64_t n, const double* 
   multiaxpy_body(n, V, ldv, k, h, w, part_norm, blockIdx.x, gridDim.x);
 }
 
+// The same update with a row's k basis entries loaded together (k <= KB:
+// up to 8 loads in flight instead of one); with KD > 0, also the projections
+// of the updated w on the first min(k, KD) basis vectors, part[j * nblk + blk]
+// = the chunk's sum of V_j . w (classical Gram-Schmidt: the first pass's
+// update and the second pass's projections in one sweep over the basis);
+// with KD = 0 and part, the chunk's sum of w^2.  Every thread takes the rows,
+// and every sum its terms, in the order of multiaxpy_body and multidot_body,
+// so the results are bitwise theirs.
+template <int KB, int KD>
+__global__ void __launch_bounds__(RB) multiaxpy_reg_kernel(int64_t n, const double* __restrict__ V, int64_t ldv,
+                                                           int k, const double* __restrict__ h,
+                                                           double* __restrict__ w, double* __restrict__ part) {
+  constexpr int NA = KD > 0 ? KD : 1;
+  __shared__ double sh[NA][RB / 64];
+  __shared__ double hs[KB];
+  for (int j = threadIdx.x; j < k; j += RB) hs[j] = h[j];
+  __syncthreads();
+  const int bid = blockIdx.x, nblk = gridDim.x;
+  const int64_t chunk = (n + nblk - 1) / nblk;
+  const int64_t lo = (int64_t)bid * chunk;
+  const int64_t hi = std::min<int64_t>(n, lo + chunk);
+  double acc[NA];
+#pragma unroll
+  for (int g = 0; g < NA; ++g) acc[g] = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += RB) {
+    double s = w[i];
+#pragma unroll
+    for (int g0 = 0; g0 < KB; g0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = g0 + u < k ? V[(int64_t)(g0 + u) * ldv + i] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (g0 + u < k) s -= hs[g0 + u] * v[u];
+    }
+    w[i] = s;
+    if constexpr (KD > 0) {
+      // the row's basis entries again (cache hits): holding them from the
+      // update would double the registers
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int g0 = 0; g0 < KD; g0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = g0 + u < k ? V[(int64_t)(g0 + u) * ldv + i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (g0 + u < k) acc[g0 + u] += v[u] * s;
+      }
+    } else {
+      acc[0] += s * s;
+    }
+  }
+  if (!part) return;  // uniform
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if constexpr (KD > 0) {
+    const int kd = std::min(k, KD);
+#pragma unroll
+    for (int g = 0; g < KD; ++g) {
+      if (g < kd) {
+        double v = acc[g];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) sh[g][wid] = v;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < kd) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < RB / 64; ++q) t += sh[threadIdx.x][q];
+      part[(int64_t)threadIdx.x * nblk + bid] = t;
+    }
+  } else {
+    const double nrm = block_sum(acc[0], &sh[0][0]);
+    if (threadIdx.x == 0) part[bid] = nrm;
+  }
+}
+
+// register tiers k <= 8, 16, 24, 32 (false above); with dots, those of
+// vectors 16 and up (k > 16) by multidot afterwards
+template <bool DOT>
+bool launch_multiaxpy_reg(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w, double* part,
+                          hipStream_t s) {
+  const int nb = red_blocks(n);
+  if (k <= 8)
+    multiaxpy_reg_kernel<8, DOT ? 8 : 0><<<nb, RB, 0, s>>>(n, V, ldv, k, h, w, part);
+  else if (k <= 16)
+    multiaxpy_reg_kernel<16, DOT ? 16 : 0><<<nb, RB, 0, s>>>(n, V, ldv, k, h, w, part);
+  else if (k <= 24)
+    multiaxpy_reg_kernel<24, DOT ? 16 : 0><<<nb, RB, 0, s>>>(n, V, ldv, k, h, w, part);
+  else if (k <= 32)
+    multiaxpy_reg_kernel<32, DOT ? 16 : 0><<<nb, RB, 0, s>>>(n, V, ldv, k, h, w, part);
+  else
+    return false;
+  if (DOT && k > 16) launch_multidot(n, V + 16 * ldv, ldv, k - 16, w, part + (int64_t)16 * nb, s);
+  return true;
+}
+
 void launch_multiaxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w, double* part_norm,
                       hipStream_t s) {
+  if (launch_multiaxpy_reg<false>(n, V, ldv, k, h, w, part_norm, s)) return;
   multiaxpy_kernel<<<red_blocks(n), RB, 0, s>>>(n, V, ldv, k, h, w, part_norm);
+}
+
+void launch_multiaxpy_dot(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w, double* part,
+                          hipStream_t s) {
+  if (launch_multiaxpy_reg<true>(n, V, ldv, k, h, w, part, s)) return;
+  launch_multiaxpy(n, V, ldv, k, h, w, nullptr, s);
+  multidot_kernel<<<red_blocks(n), RB, 0, s>>>(n, V, ldv, k, w, part);
 }
 
 __global__ void __launch_bounds__(RB) scale_kernel(int64_t n, const double* __restrict__ w, const double* beta,
