@@ -163,6 +163,7 @@ __global__ void __launch_bounds__(RB) multiaxpy_reg_kernel(int64_t n, const doub
   for (int g = 0; g < NA; ++g) acc[g] = 0.0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += RB) {
     double s = w[i];
+    double keep[NA];  // the entries of the first KD vectors, for the projections
 #pragma unroll
     for (int g0 = 0; g0 < KB; g0 += 8) {
       double v[8];
@@ -171,21 +172,17 @@ __global__ void __launch_bounds__(RB) multiaxpy_reg_kernel(int64_t n, const doub
 #pragma unroll
       for (int u = 0; u < 8; ++u)
         if (g0 + u < k) s -= hs[g0 + u] * v[u];
+      if constexpr (KD > 0) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (g0 + u < KD) keep[g0 + u] = v[u];
+      }
     }
     w[i] = s;
     if constexpr (KD > 0) {
-      // the row's basis entries again (cache hits): holding them from the
-      // update would double the registers
-      asm volatile("" ::: "memory");
 #pragma unroll
-      for (int g0 = 0; g0 < KD; g0 += 8) {
-        double v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = g0 + u < k ? V[(int64_t)(g0 + u) * ldv + i] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (g0 + u < k) acc[g0 + u] += v[u] * s;
-      }
+      for (int g = 0; g < KD; ++g)
+        if (g < k) acc[g] += keep[g] * s;
     } else {
       acc[0] += s * s;
     }
