@@ -97,3 +97,50 @@ def test_mf_iterations_match_assembled():
     assert abs(its[0][0] - its[1][0]) <= 1 and its[1][0] == its[2][0]
     assert np.array_equal(its[1][1], its[2][1])
     assert rel(its[1][1], its[0][1]) < 1e-6
+
+
+MERGE_CASES = {
+    # 20 elements per row: workgroups of 8, 16 and 32 elements end inside rows
+    # and take several row ends; the sphere case adds the contact face outputs
+    "rows20": synth.Problem(20, 6, 4, ly=0.3, lz=0.2, n_levels=2, patch=2, depth_increment=0.01),
+    "rows20_sphere": synth.Problem(20, 6, 4, ly=0.3, lz=0.2, n_levels=2, kind="sphere", radius=0.5,
+                                   depth_increment=0.03),
+}
+
+
+@pytest.mark.parametrize("name", list(MERGE_CASES))
+def test_mf_merged_outputs_independent_of_workgroup_size(name):
+    """Element outputs merged along x inside a workgroup (its last element's
+    right corners and row ends through separate streams): for 8, 16 and 32
+    elements per workgroup the FP32 and FP64 products and the V-cycle are
+    bitwise the same (a node's two parts always meet in one addition), and
+    the products match the oracle's tangent entry by entry."""
+    from paper_2011_08802_amd import mvpf
+    p = MERGE_CASES[name]
+    U, En = seeded_state(p, 1e-3)
+    d = p.depth_increment
+    say(f"[mf merge {name}] oracle")
+    oc = OracleCase(p, U, En, d, build_mg=False, direct=False)
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal(oc.sys.b.shape[0])
+    v = rng.standard_normal(oc.sys.b.shape[0])
+    ya = abs_product(oc.sys.A, x)
+    outs = []
+    for epw in (8, 16, 32):
+        say(f"[mf merge {name}] {epw} elements per workgroup")
+        gp = gpu_problem(p, U, En, "mixed", depth=d)
+        try:
+            gp.set_tuning("matrix_free", 0, 1)
+            gp.set_tuning("mf_elements_per_block", 0, epw)
+            gp.newton_system(d)
+            y64 = gp.jacobian_apply(0, _dev(x), mvpf.FP64).cpu().numpy()
+            y32 = gp.jacobian_apply(0, _dev(x), mvpf.MIXED).cpu().numpy()
+            z = gp.precondition(_dev(v)).cpu().numpy()
+        finally:
+            gp.close()
+        check_entries(y64, oc.sys.A @ x, 1e-12, f"FP64 K x ({epw})", ya)
+        check_entries(y32, oc.sys.A @ x, 2e-6, f"FP32 K x ({epw})", ya)
+        outs.append((y64, y32, z))
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
