@@ -19,10 +19,12 @@
 // interpolation stages over lane pairs (sum factorisation; lanes exchange
 // values by DPP moves, xor 1, 2, 4), and the contributions B^T [w; z] go
 // back to the corners through the transposed stages, so that lane j ends
-// with the element's part for corner j, written to the element-output
-// buffer.  A node gather sums its <= 8 elements in a fixed order and applies
-// the epilogue (product, defect or damped point-block Jacobi update), so
-// results are reproducible bit for bit.
+// with the element's part for corner j.  The workgroup merges the parts of
+// neighbouring elements along x that meet at a node and writes them to the
+// element-output buffer (layout in common.h); a node gather sums its <= 4
+// merged element rows in a fixed order and applies the epilogue (product,
+// defect or damped point-block Jacobi update), so results are reproducible
+// bit for bit.
 //
 // The lane layout (9 unknowns per corner, 15 local variables, 120 Hessian
 // entries streamed as 30 16-byte vectors) is that of the six-variant card:
