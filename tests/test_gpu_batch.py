@@ -35,6 +35,42 @@ def _state(gp):
     return np.concatenate([u.cpu().numpy(), e.cpu().numpy()], 1)
 
 
+def test_batch_bitwise_long_arnoldi_cycles():
+    """A weak smoother (V(1,1), damping 0.3) and rtol 1e-11 make every
+    problem take many FGMRES iterations (at least one more than 30), so the Arnoldi steps reach
+    all register tiers of the single-problem Gram-Schmidt kernels (basis sizes
+    up to 31, the first pass's update fused with the second pass's
+    projections) and a restart: the batched solve, which keeps the separate
+    passes, gives bitwise the same states and iteration counts."""
+    from paper_2011_08802_amd import mvpf
+    probs = small_batch()
+    states = [seeded_state(p, 1e-3) for p in probs]
+    opts = dict(nu_pre=1, nu_post=1, omega=0.3, rtol=1e-11)
+    B = mvpf.Batch(probs, "mixed", **opts)
+    say("[batch long cycles] single-problem references")
+    ref = []
+    for i, (p, (U, En)) in enumerate(zip(probs, states)):
+        gp = mvpf.Problem(p, "mixed", **opts)
+        gp.set_tuning("small_grid_nodes", 0, B.problem(i).get_tuning("small_grid_nodes"))
+        gp.set_state(U[:, :3], U[:, 3:], En, 0.0)
+        gp.newton_system(p.depth_increment)
+        _, st = gp.solve(want_x=False)
+        gp.newton_update()
+        say(f"    problem {i}: {st.iterations} FGMRES iterations, {st.restarts} restarts")
+        ref.append((_state(gp), st.iterations))
+        gp.close()
+    assert max(r[1] for r in ref) > 30
+    for i, (U, En) in enumerate(states):
+        B.problem(i).set_state(U[:, :3], U[:, 3:], En, 0.0)
+    B.newton_system([p.depth_increment for p in probs])
+    stats = B.solve()
+    B.newton_update()
+    for i in range(len(probs)):
+        assert stats[i].converged and stats[i].iterations == ref[i][1], (i, stats[i].iterations, ref[i][1])
+        assert np.array_equal(_state(B.problem(i)), ref[i][0]), i
+    B.close()
+
+
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_batch_bitwise_equals_single_solves(precision):
     from paper_2011_08802_amd import mvpf
